@@ -1,0 +1,859 @@
+// api.hip -- C ABI of libcsg: workspace layout, operator construction, the
+// V-cycle sequence (section 3.1) and the flexible GMRES driver (section 5).
+#include <algorithm>
+#include <cfloat>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "kernels.h"
+
+using namespace csg;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(x)                                                                               \
+    do {                                                                                        \
+        hipError_t e_ = (x);                                                                    \
+        if (e_ != hipSuccess) return fail(CSG_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Bump allocator over the caller's workspace (base == nullptr: size only).
+struct Carver {
+    char *base;
+    size_t off = 0;
+    explicit Carver(void *b) : base((char *)b) {}
+    void *take(size_t bytes)
+    {
+        off = (off + 255) & ~(size_t)255;
+        void *p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    }
+};
+
+// Blocks and points per block of a pass over n points.
+void geometry(unsigned n, int &nb, unsigned &chunk)
+{
+    long want = ((long)n + BLK - 1) / BLK;
+    if (want < 1) want = 1;
+    nb = (int)std::min<long>(NBMAX, want);
+    if (nb >= 8) nb &= ~7;
+    long per = ((long)n + nb - 1) / nb;
+    chunk = (unsigned)(((per + BLK - 1) / BLK) * BLK);
+}
+
+// The layout of every buffer in the workspace; `op` may be a dry-run object.
+void carve(csg_operator &op, const int nint[CSG_MAX_LEVELS][3], Carver &cv)
+{
+    const csg_params &p = op.p;
+    const int R = p.max_rhs;
+    const size_t cz = op.csize, cr = cz / 2;
+    for (int l = 0; l < op.L; ++l) {
+        DevLevel &lv = op.lev[l];
+        lv.N = 1;
+        for (int a = 0; a < 3; ++a) {
+            lv.nu[a] = a < p.dim ? (unsigned)(nint[l][a] - 1) : 1u;
+            lv.N *= lv.nu[a];
+        }
+        lv.ld = lv.N;
+        geometry(lv.N, lv.nb, lv.chunk);
+        for (int a = 0; a < p.dim; ++a) lv.tab[a] = cv.take(3 * (size_t)lv.nu[a] * cz);
+        for (int a = p.dim; a < 3; ++a) lv.tab[a] = nullptr;
+        lv.phi = cv.take(lv.N * cr);
+        const size_t vb = (size_t)R * lv.N * cz;
+        lv.b = cv.take(vb);
+        lv.xa = cv.take(vb);
+        lv.xb = cv.take(vb);
+        lv.r = cv.take(vb);
+        lv.u[0] = nullptr;
+        for (int i = 1; i <= CSG_MAX_S; ++i) lv.u[i] = i <= p.s ? cv.take(vb) : nullptr;
+        for (int k = 0; k < 2; ++k) lv.part[k] = (zc *)cv.take((size_t)R * NVAL * NBMAX * sizeof(zc));
+        lv.gs = (GState *)cv.take((size_t)R * sizeof(GState));
+    }
+    const DevLevel &f = op.lev[0];
+    for (int a = 0; a < p.dim; ++a) op.tabH[a] = cv.take(3 * (size_t)f.nu[a] * sizeof(zc));
+    for (int a = p.dim; a < 3; ++a) op.tabH[a] = nullptr;
+    op.phiH = (const double *)cv.take(f.N * sizeof(double));
+    const DevLevel &c = op.lev[op.L - 1];
+    op.nc = (int)c.N;
+    op.minvT = cv.take((size_t)op.nc * op.nc * cz);
+    const size_t n0 = (size_t)R * f.N;
+    op.V = (zc *)cv.take((size_t)(p.restart + 1) * n0 * sizeof(zc));
+    op.Z = cv.take((size_t)p.restart * n0 * cz);
+    op.w = (zc *)cv.take(n0 * sizeof(zc));
+    op.b0 = p.cycle_prec ? cv.take(n0 * cz) : nullptr;
+    op.opart = (zc *)cv.take((size_t)R * OVAL * NBMAX * sizeof(zc));
+    op.fs = (FState *)cv.take((size_t)R * sizeof(FState));
+    op.rep = (Report *)cv.take((size_t)R * sizeof(Report));
+    op.active = (int *)cv.take((size_t)3 * R * sizeof(int));
+    op.ones = op.active + 2 * R;
+}
+
+int cyc_mask_offset(const csg_operator *op) { return op->p.max_rhs; }
+
+template <typename T>
+LvlK<T> lvl(const csg_operator *op, int l)
+{
+    const DevLevel &d = op->lev[l];
+    LvlK<T> L;
+    for (int a = 0; a < 3; ++a) L.tab[a] = (const Cx<T> *)d.tab[a];
+    L.phi = (const T *)d.phi;
+    L.nx = d.nu[0];
+    L.ny = d.nu[1];
+    L.nz = d.nu[2];
+    L.N = d.N;
+    return L;
+}
+
+LvlK<double> lvlH(const csg_operator *op)
+{
+    const DevLevel &d = op->lev[0];
+    LvlK<double> L;
+    for (int a = 0; a < 3; ++a) L.tab[a] = (const zc *)op->tabH[a];
+    L.phi = op->phiH;
+    L.nx = d.nu[0];
+    L.ny = d.nu[1];
+    L.nz = d.nu[2];
+    L.N = d.N;
+    return L;
+}
+
+Launch lch(const csg_operator *op, int l, int nrhs, hipStream_t st)
+{
+    Launch g;
+    g.nb = op->lev[l].nb;
+    g.chunk = op->lev[l].chunk;
+    g.nrhs = nrhs;
+    g.st = st;
+    return g;
+}
+
+template <typename T>
+double tiny_of() { return 10.0 * (sizeof(T) == 8 ? DBL_EPSILON : (double)FLT_EPSILON); }
+
+// One GMRES(s) sweep on level l: Arnoldi steps on u_0 (= b when x == 0, else
+// the residual in lv.r), then the closing pass.  `close` selects the plain
+// update (x (+)= V y) or the update fused with the restriction of the
+// Arnoldi residual to level l+1.
+template <typename T, int DIM>
+void sweep(const csg_operator *op, int l, const Cx<T> *b, Cx<T> *x, bool from_zero, bool restrict_after, int nrhs,
+           hipStream_t st, const int *active)
+{
+    const DevLevel &lv = op->lev[l];
+    const int s = op->p.s;
+    const LvlK<T> L = lvl<T>(op, l);
+    const Launch g = lch(op, l, nrhs, st);
+    const double tiny = tiny_of<T>();
+    Basis<T> B;
+    for (int i = 0; i <= CSG_MAX_S; ++i) B.u[i] = (Cx<T> *)lv.u[i];
+    if (from_zero) {
+        B.u[0] = const_cast<Cx<T> *>(b);
+    } else {
+        launch_resid<T, DIM>(L, x, b, (Cx<T> *)lv.r, lv.ld, g, active);
+        B.u[0] = (Cx<T> *)lv.r;
+    }
+    for (int j = 0; j < s; ++j) {
+        launch_st<T, DIM>(L, B, j, lv.ld, lv.part[1], lv.nb, lv.part[0], lv.gs, tiny, g, active);
+        launch_orth<T>(B, j, s, lv.N, lv.ld, lv.part[0], lv.nb, lv.part[1], lv.gs, g, active);
+    }
+    if (restrict_after) {
+        const DevLevel &cl = op->lev[l + 1];
+        launch_upd_res<T, DIM>(x, from_zero ? 0 : 1, B, s, L, lvl<T>(op, l + 1), (Cx<T> *)cl.b, lv.ld, cl.ld,
+                               lv.part[1], lv.nb, lv.gs, tiny, lch(op, l + 1, nrhs, st), active);
+    } else {
+        launch_upd<T>(x, from_zero ? 0 : 1, B, s, lv.N, lv.ld, lv.part[1], lv.nb, lv.gs, tiny, g, active);
+    }
+}
+
+// x = V_{nu1,nu2}(0; b) on level l downwards (section 3.1).
+template <typename T, int DIM>
+void vcycle_impl(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, hipStream_t st, const int *active)
+{
+    const int L = op->L;
+    const int nu1 = op->p.nu1, nu2 = op->p.nu2;
+    if (L == 1) {
+        launch_coarse<T>((const Cx<T> *)op->minvT, op->nc, b0, x0, op->lev[0].ld, nrhs, st, active);
+        return;
+    }
+    for (int l = 0; l < L - 1; ++l) {
+        const DevLevel &lv = op->lev[l];
+        const DevLevel &cl = op->lev[l + 1];
+        const Cx<T> *b = l == 0 ? b0 : (const Cx<T> *)lv.b;
+        Cx<T> *xa = (Cx<T> *)lv.xa;
+        if (nu1 == 0) {
+            launch_restrict<T, DIM>(lvl<T>(op, l), lvl<T>(op, l + 1), nullptr, b, (Cx<T> *)cl.b, lv.ld, cl.ld,
+                                    lch(op, l + 1, nrhs, st), active);
+        } else {
+            for (int k = 0; k < nu1; ++k) sweep<T, DIM>(op, l, b, xa, k == 0, k == nu1 - 1, nrhs, st, active);
+        }
+    }
+    {
+        const DevLevel &c = op->lev[L - 1];
+        launch_coarse<T>((const Cx<T> *)op->minvT, op->nc, (const Cx<T> *)c.b, (Cx<T> *)c.xb, c.ld, nrhs, st, active);
+    }
+    for (int l = L - 2; l >= 0; --l) {
+        const DevLevel &lv = op->lev[l];
+        const DevLevel &cl = op->lev[l + 1];
+        const Cx<T> *b = l == 0 ? b0 : (const Cx<T> *)lv.b;
+        Cx<T> *xo = l == 0 ? x0 : (Cx<T> *)lv.xb;
+        const Cx<T> *xi = nu1 > 0 ? (const Cx<T> *)lv.xa : nullptr;
+        const Launch g = lch(op, l, nrhs, st);
+        if (nu2 == 0) {
+            launch_prolong<T, DIM>(lvl<T>(op, l), lvl<T>(op, l + 1), (const Cx<T> *)cl.xb, xi, xo, lv.ld, cl.ld, g,
+                                   active);
+        } else {
+            launch_prc<T, DIM>(lvl<T>(op, l), lvl<T>(op, l + 1), (const Cx<T> *)cl.xb, xi, xo, b, (Cx<T> *)lv.r,
+                               lv.ld, cl.ld, g, active);
+            for (int k = 0; k < nu2; ++k) {
+                // the first post-sweep starts from the residual already in lv.r
+                const DevLevel &d = op->lev[l];
+                const int s = op->p.s;
+                const LvlK<T> Lk = lvl<T>(op, l);
+                const double tiny = tiny_of<T>();
+                Basis<T> B;
+                for (int i = 0; i <= CSG_MAX_S; ++i) B.u[i] = (Cx<T> *)d.u[i];
+                if (k > 0) launch_resid<T, DIM>(Lk, xo, b, (Cx<T> *)d.r, d.ld, g, active);
+                B.u[0] = (Cx<T> *)d.r;
+                for (int j = 0; j < s; ++j) {
+                    launch_st<T, DIM>(Lk, B, j, d.ld, d.part[1], d.nb, d.part[0], d.gs, tiny, g, active);
+                    launch_orth<T>(B, j, s, d.N, d.ld, d.part[0], d.nb, d.part[1], d.gs, g, active);
+                }
+                launch_upd<T>(xo, 1, B, s, d.N, d.ld, d.part[1], d.nb, d.gs, tiny, g, active);
+            }
+        }
+    }
+}
+
+template <typename T>
+void vcycle_dispatch(const csg_operator *op, const void *b, void *x, int nrhs, hipStream_t st, const int *active)
+{
+    if (op->p.dim == 2)
+        vcycle_impl<T, 2>(op, (const Cx<T> *)b, (Cx<T> *)x, nrhs, st, active);
+    else
+        vcycle_impl<T, 3>(op, (const Cx<T> *)b, (Cx<T> *)x, nrhs, st, active);
+}
+
+void run_vcycle(const csg_operator *op, const void *b, void *x, int nrhs, hipStream_t st, const int *active)
+{
+    if (op->p.cycle_prec)
+        vcycle_dispatch<float>(op, b, x, nrhs, st, active);
+    else
+        vcycle_dispatch<double>(op, b, x, nrhs, st, active);
+}
+
+int check_op(const csg_operator *op, int nrhs)
+{
+    if (!op) return fail(CSG_EINVAL, "null operator");
+    if (nrhs < 0 || nrhs > op->p.max_rhs) return fail(CSG_EINVAL, "nrhs out of range 0..max_rhs");
+    return CSG_OK;
+}
+
+int last_launch_error()
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(CSG_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    return CSG_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// FGMRES driver (section 5): a small host state machine over device passes.
+// ===========================================================================
+
+struct csg_solve {
+    csg_operator *op;
+    const zc *chi;
+    zc *u;
+    int nrhs, m, maxit, use_x0;
+    double tol;
+    hipStream_t st;
+    enum { INIT, WAIT_BEGIN, CYCLE, WAIT_ITER, CYCLE_END, WAIT_END, FINISHED } phase;
+    int j;
+    int rc;
+    int it[CSG_MAX_RHS_HOST];
+    int done[CSG_MAX_RHS_HOST], conv[CSG_MAX_RHS_HOST], act[CSG_MAX_RHS_HOST], restarts[CSG_MAX_RHS_HOST];
+    double est[CSG_MAX_RHS_HOST], truer[CSG_MAX_RHS_HOST];
+    int *mask_host;   // pinned: [active | cyc]
+    std::chrono::steady_clock::time_point t0;
+    double seconds;
+};
+
+namespace {
+
+template <int DIM>
+void enqueue_begin(csg_solve *sv, bool with_chi_norm)
+{
+    csg_operator *op = sv->op;
+    const DevLevel &f = op->lev[0];
+    const Launch g = lch(op, 0, sv->nrhs, sv->st);
+    const int *mask = op->active + cyc_mask_offset(op);
+    launch_tres<DIM>(lvlH(op), sv->chi, sv->u, op->V, f.ld, with_chi_norm ? 1 : 0, op->opart, g, mask);
+    launch_fin(with_chi_norm ? FIN_BEGIN : FIN_BETA, op->opart, f.nb, 0, op->fs, op->rep, sv->nrhs, sv->st, mask);
+    if (op->p.cycle_prec)
+        launch_vnorm<float>(op->V, op->V, (cf *)op->b0, f.N, f.ld, op->fs, g, mask);
+    else
+        launch_vnorm<double>(op->V, op->V, (zc *)nullptr, f.N, f.ld, op->fs, g, mask);
+}
+
+template <typename TZ, int DIM>
+void enqueue_iter(csg_solve *sv)
+{
+    csg_operator *op = sv->op;
+    const DevLevel &f = op->lev[0];
+    const int j = sv->j;
+    const size_t vstride = (size_t)op->p.max_rhs * f.N;
+    const Launch g = lch(op, 0, sv->nrhs, sv->st);
+    const int *mask = op->active;
+    const void *b = op->p.cycle_prec ? op->b0 : (const void *)(op->V + j * vstride);
+    Cx<TZ> *z = (Cx<TZ> *)op->Z + j * vstride;
+    run_vcycle(op, b, z, sv->nrhs, sv->st, mask);
+    launch_hst<TZ, DIM>(lvlH(op), z, op->w, op->V, vstride, j, f.ld, op->opart, g, mask);
+    launch_fin(FIN_H, op->opart, f.nb, j, op->fs, op->rep, sv->nrhs, sv->st, mask);
+    launch_cgs1(op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->opart, g, mask);
+    launch_fin(FIN_C, op->opart, f.nb, j, op->fs, op->rep, sv->nrhs, sv->st, mask);
+    launch_cgs2(op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->opart, g, mask);
+    launch_fin(FIN_N, op->opart, f.nb, j, op->fs, op->rep, sv->nrhs, sv->st, mask);
+    launch_vnorm<TZ>(op->w, op->V + (j + 1) * vstride, op->p.cycle_prec ? (Cx<TZ> *)op->b0 : nullptr, f.N, f.ld,
+                     op->fs, g, mask);
+}
+
+template <typename TZ, int DIM>
+void enqueue_end(csg_solve *sv)
+{
+    csg_operator *op = sv->op;
+    const DevLevel &f = op->lev[0];
+    const size_t vstride = (size_t)op->p.max_rhs * f.N;
+    const Launch g = lch(op, 0, sv->nrhs, sv->st);
+    const int *mask = op->active + cyc_mask_offset(op);
+    launch_fin(FIN_LS, op->opart, f.nb, 0, op->fs, op->rep, sv->nrhs, sv->st, mask);
+    launch_uupd<TZ>(sv->u, (const Cx<TZ> *)op->Z, vstride, f.N, f.ld, op->fs, g, mask);
+    enqueue_begin<DIM>(sv, false);
+}
+
+void upload_masks(csg_solve *sv)
+{
+    csg_operator *op = sv->op;
+    const int R = op->p.max_rhs;
+    for (int r = 0; r < R; ++r) {
+        const bool in = r < sv->nrhs && !sv->done[r];
+        sv->mask_host[r] = in && sv->act[r];
+        sv->mask_host[R + r] = in;
+    }
+    hipMemcpyAsync(op->active, sv->mask_host, 2 * R * sizeof(int), hipMemcpyHostToDevice, sv->st);
+}
+
+void enqueue_report(csg_solve *sv)
+{
+    csg_operator *op = sv->op;
+    hipMemcpyAsync(op->rep_host, op->rep, sv->nrhs * sizeof(Report), hipMemcpyDeviceToHost, sv->st);
+    hipEventRecord(op->ev, sv->st);
+}
+
+int solve_step(csg_solve *sv)
+{
+    csg_operator *op = sv->op;
+    const bool mixed = op->p.cycle_prec != 0;
+    const bool d3 = op->p.dim == 3;
+    switch (sv->phase) {
+    case csg_solve::INIT:
+        upload_masks(sv);
+        if (d3) enqueue_begin<3>(sv, true); else enqueue_begin<2>(sv, true);
+        enqueue_report(sv);
+        sv->phase = csg_solve::WAIT_BEGIN;
+        break;
+    case csg_solve::CYCLE:
+        upload_masks(sv);
+        if (mixed) { if (d3) enqueue_iter<float, 3>(sv); else enqueue_iter<float, 2>(sv); }
+        else { if (d3) enqueue_iter<double, 3>(sv); else enqueue_iter<double, 2>(sv); }
+        enqueue_report(sv);
+        sv->phase = csg_solve::WAIT_ITER;
+        break;
+    case csg_solve::CYCLE_END:
+        upload_masks(sv);
+        if (mixed) { if (d3) enqueue_end<float, 3>(sv); else enqueue_end<float, 2>(sv); }
+        else { if (d3) enqueue_end<double, 3>(sv); else enqueue_end<double, 2>(sv); }
+        enqueue_report(sv);
+        sv->phase = csg_solve::WAIT_END;
+        break;
+    default:
+        return CSG_OK;   // waiting or finished: nothing to enqueue
+    }
+    return last_launch_error();
+}
+
+// Host decisions after a report has landed.
+void solve_advance(csg_solve *sv)
+{
+    csg_operator *op = sv->op;
+    const Report *rp = op->rep_host;
+    bool any = false;
+    switch (sv->phase) {
+    case csg_solve::WAIT_BEGIN:
+    case csg_solve::WAIT_END:
+        for (int r = 0; r < sv->nrhs; ++r) {
+            if (sv->done[r]) continue;
+            if (sv->phase == csg_solve::WAIT_END) sv->restarts[r]++;
+            const double nchi = (sv->phase == csg_solve::WAIT_BEGIN) ? rp[r].hn : 1.0;
+            if (!rp[r].finite) { sv->done[r] = 1; sv->rc = CSG_ENUMERIC; continue; }
+            if (sv->phase == csg_solve::WAIT_BEGIN && nchi == 0.0) {
+                // zero source: the solution is zero
+                hipMemsetAsync(sv->u + (size_t)r * op->lev[0].ld, 0, op->lev[0].N * sizeof(zc), sv->st);
+                sv->done[r] = sv->conv[r] = 1;
+                sv->truer[r] = sv->est[r] = 0.0;
+                continue;
+            }
+            sv->truer[r] = rp[r].est;
+            if (sv->phase == csg_solve::WAIT_BEGIN) sv->est[r] = rp[r].est;
+            if (rp[r].est <= sv->tol) { sv->done[r] = sv->conv[r] = 1; continue; }
+            if (sv->it[r] >= sv->maxit) { sv->done[r] = 1; continue; }
+            sv->act[r] = 1;
+            any = true;
+        }
+        sv->j = 0;
+        sv->phase = any ? csg_solve::CYCLE : csg_solve::FINISHED;
+        break;
+    case csg_solve::WAIT_ITER: {
+        bool still = false;
+        for (int r = 0; r < sv->nrhs; ++r) {
+            if (sv->done[r] || !sv->act[r]) continue;
+            sv->it[r]++;
+            sv->est[r] = rp[r].est;
+            if (!rp[r].finite) { sv->act[r] = 0; sv->rc = CSG_ENUMERIC; sv->done[r] = 1; continue; }
+            if (rp[r].est <= sv->tol || rp[r].hn == 0.0 || sv->it[r] >= sv->maxit) { sv->act[r] = 0; continue; }
+            still = true;
+        }
+        sv->j++;
+        sv->phase = (still && sv->j < sv->m) ? csg_solve::CYCLE : csg_solve::CYCLE_END;
+        break;
+    }
+    default:
+        break;
+    }
+}
+
+}  // namespace
+
+// ===========================================================================
+// exported entry points
+// ===========================================================================
+
+extern "C" {
+
+const char *csg_last_error(void) { return g_err.c_str(); }
+
+int csg_plan_levels(const csg_params *p, int *levels, int dims[][3])
+{
+    if (!p) return fail(CSG_EINVAL, "null params");
+    int nint[CSG_MAX_LEVELS][3];
+    int L = 0;
+    std::string err;
+    int st = plan_levels(*p, L, nint, err);
+    if (st) return fail(st, err);
+    if (levels) *levels = L;
+    if (dims)
+        for (int l = 0; l < L; ++l)
+            for (int a = 0; a < 3; ++a) dims[l][a] = a < p->dim ? nint[l][a] - 1 : 1;
+    return CSG_OK;
+}
+
+int csg_workspace_bytes(const csg_params *p, size_t *bytes)
+{
+    if (!p || !bytes) return fail(CSG_EINVAL, "null argument");
+    int nint[CSG_MAX_LEVELS][3];
+    int L = 0;
+    std::string err;
+    int st = plan_levels(*p, L, nint, err);
+    if (st) return fail(st, err);
+    csg_operator dry;
+    memset(&dry, 0, sizeof(dry));
+    dry.p = *p;
+    dry.L = L;
+    dry.csize = p->cycle_prec ? 8 : 16;
+    Carver cv(nullptr);
+    carve(dry, nint, cv);
+    *bytes = (cv.off + 255) & ~(size_t)255;
+    return CSG_OK;
+}
+
+int csg_operator_create(const csg_params *p, const double *phi_host, void *ws_dev, size_t ws_bytes, void *stream,
+                        csg_operator **out)
+{
+    if (!p || !phi_host || !out) return fail(CSG_EINVAL, "null argument");
+    *out = nullptr;
+    if (((uintptr_t)ws_dev & 255) != 0) return fail(CSG_EINVAL, "workspace must be 256-byte aligned");
+    size_t need = 0;
+    int st = csg_workspace_bytes(p, &need);
+    if (st) return st;
+    if (p->max_rhs > CSG_MAX_RHS_HOST) return fail(CSG_EINVAL, "max_rhs too large");
+    if (!ws_dev || ws_bytes < need) return fail(CSG_ENOMEM, "workspace too small");
+    HostHier hh;
+    std::string err;
+    st = build_hierarchy(*p, phi_host, hh, err);
+    if (st) return fail(st, err);
+
+    csg_operator *op = new csg_operator;
+    memset(op, 0, sizeof(*op));
+    op->p = *p;
+    op->L = hh.L;
+    op->csize = p->cycle_prec ? 8 : 16;
+    int nint[CSG_MAX_LEVELS][3];
+    for (int l = 0; l < hh.L; ++l)
+        for (int a = 0; a < 3; ++a) nint[l][a] = hh.lev[l].nint[a];
+    Carver cv(ws_dev);
+    carve(*op, nint, cv);
+    op->ws_used = cv.off;
+    hipStream_t s = (hipStream_t)stream;
+    const bool mixed = p->cycle_prec != 0;
+
+    // tables with zeroed boundary weights (west of the first, east of the last unknown)
+    std::vector<char> buf;
+    auto put_tab = [&](const std::vector<cd> &t, int nu, const void *dst, bool dbl) -> hipError_t {
+        const size_t esz = dbl ? 16 : 8;
+        buf.assign(3 * (size_t)nu * esz, 0);
+        for (int q = 0; q < 3 * nu; ++q) {
+            cd v = t[q];
+            if (q == 0 || q == 3 * nu - 1) v = 0.0;   // west[0], east[nu-1]
+            if (dbl) {
+                double *d = (double *)buf.data() + 2 * q;
+                d[0] = v.real();
+                d[1] = v.imag();
+            } else {
+                float *d = (float *)buf.data() + 2 * q;
+                d[0] = (float)v.real();
+                d[1] = (float)v.imag();
+            }
+        }
+        return hipMemcpyAsync((void *)dst, buf.data(), buf.size(), hipMemcpyHostToDevice, s);
+    };
+    int rc = CSG_OK;
+    std::vector<std::vector<char>> keep;   // host staging kept alive until the sync below
+    for (int l = 0; l < hh.L && rc == CSG_OK; ++l) {
+        const HostLevel &hl = hh.lev[l];
+        for (int a = 0; a < p->dim; ++a) {
+            if (put_tab(hl.tab[a], hl.nu[a], op->lev[l].tab[a], !mixed) != hipSuccess) rc = CSG_EDEVICE;
+            hipStreamSynchronize(s);
+        }
+        std::vector<char> ph(hl.N * (mixed ? 4 : 8));
+        for (long q = 0; q < hl.N; ++q) {
+            if (mixed) ((float *)ph.data())[q] = (float)hl.phi[q];
+            else ((double *)ph.data())[q] = hl.phi[q];
+        }
+        if (hipMemcpyAsync((void *)op->lev[l].phi, ph.data(), ph.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+            rc = CSG_EDEVICE;
+        keep.push_back(std::move(ph));
+        if (hipMemsetAsync(op->lev[l].gs, 0, p->max_rhs * sizeof(GState), s) != hipSuccess) rc = CSG_EDEVICE;
+        for (int k = 0; k < 2; ++k)
+            if (hipMemsetAsync(op->lev[l].part[k], 0, (size_t)p->max_rhs * NVAL * NBMAX * sizeof(zc), s) != hipSuccess)
+                rc = CSG_EDEVICE;
+    }
+    for (int a = 0; a < p->dim && rc == CSG_OK; ++a) {
+        if (put_tab(hh.tabH[a], hh.lev[0].nu[a], op->tabH[a], true) != hipSuccess) rc = CSG_EDEVICE;
+        hipStreamSynchronize(s);
+    }
+    if (rc == CSG_OK) {
+        if (hipMemcpyAsync((void *)op->phiH, hh.lev[0].phi.data(), hh.lev[0].N * sizeof(double),
+                           hipMemcpyHostToDevice, s) != hipSuccess)
+            rc = CSG_EDEVICE;
+        std::vector<char> mi((size_t)op->nc * op->nc * op->csize);
+        for (size_t q = 0; q < (size_t)op->nc * op->nc; ++q) {
+            if (mixed) {
+                ((float *)mi.data())[2 * q] = (float)hh.minvT[q].real();
+                ((float *)mi.data())[2 * q + 1] = (float)hh.minvT[q].imag();
+            } else {
+                ((double *)mi.data())[2 * q] = hh.minvT[q].real();
+                ((double *)mi.data())[2 * q + 1] = hh.minvT[q].imag();
+            }
+        }
+        if (hipMemcpyAsync((void *)op->minvT, mi.data(), mi.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+            rc = CSG_EDEVICE;
+        keep.push_back(std::move(mi));
+        std::vector<int> ones(3 * (size_t)p->max_rhs, 1);
+        if (hipMemcpyAsync(op->active, ones.data(), ones.size() * sizeof(int), hipMemcpyHostToDevice, s) !=
+            hipSuccess)
+            rc = CSG_EDEVICE;
+        if (hipMemsetAsync(op->fs, 0, p->max_rhs * sizeof(FState), s) != hipSuccess) rc = CSG_EDEVICE;
+        if (hipStreamSynchronize(s) != hipSuccess) rc = CSG_EDEVICE;
+    }
+    if (rc == CSG_OK) {
+        if (hipHostMalloc((void **)&op->rep_host, p->max_rhs * sizeof(Report), hipHostMallocDefault) != hipSuccess)
+            rc = CSG_EDEVICE;
+        if (hipEventCreateWithFlags(&op->ev, hipEventDisableTiming) != hipSuccess) rc = CSG_EDEVICE;
+    }
+    if (rc != CSG_OK) {
+        hipError_t e = hipGetLastError();
+        if (op->rep_host) hipHostFree(op->rep_host);
+        delete op;
+        return fail(rc, std::string("device setup failed: ") + hipGetErrorString(e));
+    }
+    *out = op;
+    return CSG_OK;
+}
+
+int csg_operator_destroy(csg_operator *op)
+{
+    if (!op) return CSG_OK;
+    if (op->ev) hipEventDestroy(op->ev);
+    if (op->rep_host) hipHostFree(op->rep_host);
+    delete op;
+    return CSG_OK;
+}
+
+int csg_operator_info(const csg_operator *op, int *levels, int dims[][3])
+{
+    if (!op) return fail(CSG_EINVAL, "null operator");
+    if (levels) *levels = op->L;
+    if (dims)
+        for (int l = 0; l < op->L; ++l)
+            for (int a = 0; a < 3; ++a) dims[l][a] = (int)op->lev[l].nu[a];
+    return CSG_OK;
+}
+
+int csg_stencil_apply(const csg_operator *op, int which, int level, const void *x, void *y, int nrhs, void *stream)
+{
+    int st = check_op(op, nrhs);
+    if (st) return st;
+    if (which != 0 && which != 1) return fail(CSG_EINVAL, "which must be 0 (H) or 1 (M)");
+    if (level < 0 || level >= op->L || (which == 0 && level != 0)) return fail(CSG_EINVAL, "bad level");
+    if (nrhs == 0) return CSG_OK;
+    if (!x || !y) return fail(CSG_EINVAL, "null vector");
+    const Launch g = lch(op, level, nrhs, (hipStream_t)stream);
+    const size_t ld = op->lev[level].ld;
+    const bool d3 = op->p.dim == 3;
+    if (which == 0) {
+        if (d3) launch_apply<double, 3>(lvlH(op), x, y, ld, g, op->ones);
+        else launch_apply<double, 2>(lvlH(op), x, y, ld, g, op->ones);
+    } else if (op->p.cycle_prec) {
+        if (d3) launch_apply<float, 3>(lvl<float>(op, level), x, y, ld, g, op->ones);
+        else launch_apply<float, 2>(lvl<float>(op, level), x, y, ld, g, op->ones);
+    } else {
+        if (d3) launch_apply<double, 3>(lvl<double>(op, level), x, y, ld, g, op->ones);
+        else launch_apply<double, 2>(lvl<double>(op, level), x, y, ld, g, op->ones);
+    }
+    return last_launch_error();
+}
+
+int csg_vcycle(const csg_operator *op, const void *b, void *x, int nrhs, void *stream)
+{
+    int st = check_op(op, nrhs);
+    if (st) return st;
+    if (nrhs == 0) return CSG_OK;
+    if (!b || !x) return fail(CSG_EINVAL, "null vector");
+    run_vcycle(op, b, x, nrhs, (hipStream_t)stream, op->ones);
+    return last_launch_error();
+}
+
+int csg_smooth(const csg_operator *op, int level, const void *b, void *x, int nrhs, void *stream)
+{
+    int st = check_op(op, nrhs);
+    if (st) return st;
+    if (level < 0 || level >= op->L) return fail(CSG_EINVAL, "bad level");
+    if (nrhs == 0) return CSG_OK;
+    if (!b || !x) return fail(CSG_EINVAL, "null vector");
+    hipStream_t s = (hipStream_t)stream;
+    if (op->p.cycle_prec) {
+        if (op->p.dim == 3) sweep<float, 3>(op, level, (const cf *)b, (cf *)x, false, false, nrhs, s, op->ones);
+        else sweep<float, 2>(op, level, (const cf *)b, (cf *)x, false, false, nrhs, s, op->ones);
+    } else {
+        if (op->p.dim == 3) sweep<double, 3>(op, level, (const zc *)b, (zc *)x, false, false, nrhs, s, op->ones);
+        else sweep<double, 2>(op, level, (const zc *)b, (zc *)x, false, false, nrhs, s, op->ones);
+    }
+    return last_launch_error();
+}
+
+int csg_residual_restrict(const csg_operator *op, int level, const void *b, const void *x, void *bc, int nrhs,
+                          void *stream)
+{
+    int st = check_op(op, nrhs);
+    if (st) return st;
+    if (level < 0 || level >= op->L - 1) return fail(CSG_EINVAL, "bad level (needs a coarser level)");
+    if (nrhs == 0) return CSG_OK;
+    if (!b || !bc) return fail(CSG_EINVAL, "null vector");
+    const Launch g = lch(op, level + 1, nrhs, (hipStream_t)stream);
+    const size_t ldf = op->lev[level].ld, ldc = op->lev[level + 1].ld;
+    if (op->p.cycle_prec) {
+        if (op->p.dim == 3)
+            launch_restrict<float, 3>(lvl<float>(op, level), lvl<float>(op, level + 1), (const cf *)x, (const cf *)b,
+                                      (cf *)bc, ldf, ldc, g, op->ones);
+        else
+            launch_restrict<float, 2>(lvl<float>(op, level), lvl<float>(op, level + 1), (const cf *)x, (const cf *)b,
+                                      (cf *)bc, ldf, ldc, g, op->ones);
+    } else {
+        if (op->p.dim == 3)
+            launch_restrict<double, 3>(lvl<double>(op, level), lvl<double>(op, level + 1), (const zc *)x,
+                                       (const zc *)b, (zc *)bc, ldf, ldc, g, op->ones);
+        else
+            launch_restrict<double, 2>(lvl<double>(op, level), lvl<double>(op, level + 1), (const zc *)x,
+                                       (const zc *)b, (zc *)bc, ldf, ldc, g, op->ones);
+    }
+    return last_launch_error();
+}
+
+int csg_prolong_correct(const csg_operator *op, int level, const void *ec, void *x, int nrhs, void *stream)
+{
+    int st = check_op(op, nrhs);
+    if (st) return st;
+    if (level < 0 || level >= op->L - 1) return fail(CSG_EINVAL, "bad level (needs a coarser level)");
+    if (nrhs == 0) return CSG_OK;
+    if (!ec || !x) return fail(CSG_EINVAL, "null vector");
+    const Launch g = lch(op, level, nrhs, (hipStream_t)stream);
+    const size_t ldf = op->lev[level].ld, ldc = op->lev[level + 1].ld;
+    if (op->p.cycle_prec) {
+        if (op->p.dim == 3)
+            launch_prolong<float, 3>(lvl<float>(op, level), lvl<float>(op, level + 1), (const cf *)ec, (const cf *)x,
+                                     (cf *)x, ldf, ldc, g, op->ones);
+        else
+            launch_prolong<float, 2>(lvl<float>(op, level), lvl<float>(op, level + 1), (const cf *)ec, (const cf *)x,
+                                     (cf *)x, ldf, ldc, g, op->ones);
+    } else {
+        if (op->p.dim == 3)
+            launch_prolong<double, 3>(lvl<double>(op, level), lvl<double>(op, level + 1), (const zc *)ec,
+                                      (const zc *)x, (zc *)x, ldf, ldc, g, op->ones);
+        else
+            launch_prolong<double, 2>(lvl<double>(op, level), lvl<double>(op, level + 1), (const zc *)ec,
+                                      (const zc *)x, (zc *)x, ldf, ldc, g, op->ones);
+    }
+    return last_launch_error();
+}
+
+int csg_coarse_solve(const csg_operator *op, const void *b, void *x, int nrhs, void *stream)
+{
+    int st = check_op(op, nrhs);
+    if (st) return st;
+    if (nrhs == 0) return CSG_OK;
+    if (!b || !x) return fail(CSG_EINVAL, "null vector");
+    const size_t ld = op->lev[op->L - 1].ld;
+    if (op->p.cycle_prec)
+        launch_coarse<float>((const cf *)op->minvT, op->nc, (const cf *)b, (cf *)x, ld, nrhs, (hipStream_t)stream,
+                             op->ones);
+    else
+        launch_coarse<double>((const zc *)op->minvT, op->nc, (const zc *)b, (zc *)x, ld, nrhs, (hipStream_t)stream,
+                              op->ones);
+    return last_launch_error();
+}
+
+int csg_solve_begin(const csg_operator *opc, const void *chi, void *u, int nrhs, double tol, int restart, int maxit,
+                    int use_initial_guess, void *stream, csg_solve **out)
+{
+    csg_operator *op = const_cast<csg_operator *>(opc);
+    if (!out) return fail(CSG_EINVAL, "null output");
+    *out = nullptr;
+    int st = check_op(op, nrhs);
+    if (st) return st;
+    if (nrhs < 1) return fail(CSG_EINVAL, "nrhs must be >= 1");
+    if (!chi || !u) return fail(CSG_EINVAL, "null vector");
+    if (restart < 1 || restart > op->p.restart) return fail(CSG_EINVAL, "restart exceeds the workspace's restart");
+    if (maxit < 0) return fail(CSG_EINVAL, "maxit must be >= 0");
+    if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(CSG_EINVAL, "tol must be finite and >= 0");
+    if (op->busy) return fail(CSG_EINVAL, "a solve is already in flight on this operator");
+    csg_solve *sv = new csg_solve();
+    sv->op = op;
+    sv->chi = (const zc *)chi;
+    sv->u = (zc *)u;
+    sv->nrhs = nrhs;
+    sv->m = restart;
+    sv->maxit = maxit;
+    sv->use_x0 = use_initial_guess;
+    sv->tol = tol;
+    sv->st = (hipStream_t)stream;
+    sv->phase = csg_solve::INIT;
+    sv->rc = CSG_OK;
+    if (hipHostMalloc((void **)&sv->mask_host, 2 * op->p.max_rhs * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+        delete sv;
+        return fail(CSG_EDEVICE, "pinned host allocation failed");
+    }
+    sv->t0 = std::chrono::steady_clock::now();
+    if (!use_initial_guess) {
+        if (hipMemsetAsync(sv->u, 0, (size_t)nrhs * op->lev[0].ld * sizeof(zc), sv->st) != hipSuccess) {
+            hipHostFree(sv->mask_host);
+            delete sv;
+            return fail(CSG_EDEVICE, "memset of the initial guess failed");
+        }
+    }
+    op->busy = 1;
+    *out = sv;
+    return solve_step(sv);
+}
+
+int csg_solve_step(csg_solve *sv)
+{
+    if (!sv) return fail(CSG_EINVAL, "null solve");
+    return solve_step(sv);
+}
+
+int csg_solve_poll(csg_solve *sv, int *done)
+{
+    if (!sv) return fail(CSG_EINVAL, "null solve");
+    if (done) *done = sv->phase == csg_solve::FINISHED;
+    if (sv->phase == csg_solve::FINISHED) return 1;
+    if (sv->phase != csg_solve::WAIT_BEGIN && sv->phase != csg_solve::WAIT_ITER && sv->phase != csg_solve::WAIT_END)
+        return 1;   // nothing in flight: the caller should step
+    hipError_t e = hipEventQuery(sv->op->ev);
+    if (e == hipErrorNotReady) return 0;
+    if (e != hipSuccess) return fail(CSG_EDEVICE, std::string("solve: ") + hipGetErrorString(e));
+    solve_advance(sv);
+    if (done) *done = sv->phase == csg_solve::FINISHED;
+    return 1;
+}
+
+int csg_solve_end(csg_solve *sv, csg_solve_info *info)
+{
+    if (!sv) return fail(CSG_EINVAL, "null solve");
+    hipError_t e = hipStreamSynchronize(sv->st);
+    sv->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - sv->t0).count();
+    int rc = sv->rc;
+    if (e != hipSuccess) rc = fail(CSG_EDEVICE, std::string("solve: ") + hipGetErrorString(e));
+    bool all = true;
+    for (int r = 0; r < sv->nrhs; ++r) {
+        all = all && sv->conv[r];
+        if (info) {
+            info[r].iterations = sv->it[r];
+            info[r].restarts = sv->restarts[r];
+            info[r].vcycles = sv->it[r];
+            info[r].converged = sv->conv[r];
+            info[r].relres_true = sv->truer[r];
+            info[r].relres_est = sv->est[r];
+            info[r].seconds = sv->seconds;
+        }
+    }
+    if (rc == CSG_OK && !all) rc = fail(CSG_ENOCONV, "maxit reached before the tolerance");
+    if (rc == CSG_ENUMERIC) fail(CSG_ENUMERIC, "non-finite residual norm");
+    sv->op->busy = 0;
+    hipHostFree(sv->mask_host);
+    delete sv;
+    return rc;
+}
+
+int helm_solve(const csg_operator *op, const void *chi, void *u, int nrhs, double tol, int restart, int maxit,
+               int use_initial_guess, csg_solve_info *info, void *stream)
+{
+    int st = check_op(op, nrhs);
+    if (st) return st;
+    if (nrhs == 0) return CSG_OK;
+    csg_solve *sv = nullptr;
+    st = csg_solve_begin(op, chi, u, nrhs, tol, restart, maxit, use_initial_guess, stream, &sv);
+    if (!sv) return st;
+    while (st == CSG_OK && sv->phase != csg_solve::FINISHED) {
+        if (hipEventSynchronize(op->ev) != hipSuccess) { st = fail(CSG_EDEVICE, "event wait failed"); break; }
+        int done = 0;
+        int pr = csg_solve_poll(sv, &done);
+        if (pr < 0) { st = pr; break; }
+        if (done) break;
+        st = csg_solve_step(sv);
+    }
+    int rc = csg_solve_end(sv, info);
+    return st != CSG_OK ? st : rc;
+}
+
+}  // extern "C"

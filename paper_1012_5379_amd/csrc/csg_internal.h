@@ -1,0 +1,135 @@
+// csg_internal.h -- internal structures of libcsg (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstddef>
+#include <string>
+#include <vector>
+
+#include "csg.h"
+#include "cx.h"
+
+namespace csg {
+
+using cd = std::complex<double>;
+
+constexpr int BLK = 256;                    // threads per block of every level pass
+constexpr int NBMAX = 512;                  // max blocks of a reducing pass (partials per value)
+constexpr int NVAL = CSG_MAX_S + 2;         // partial values per smoother pass
+constexpr int OVAL = CSG_MAX_RESTART + 1;   // partial values per outer pass
+constexpr int MAXC = 4096;                  // max coarsest unknowns
+#define CSG_MAX_RHS_HOST CSG_MAX_RHS
+
+// ---------------------------------------------------------------------------
+// Device-resident small state
+// ---------------------------------------------------------------------------
+
+// GMRES(s) smoother state of one (level, right-hand side).  The Krylov basis is
+// stored unnormalised (u_i) with v_i = sig[i] * u_i; H holds the Arnoldi
+// coefficients h_ij of the normalised basis, row-major (s+1) x s.
+struct GState {
+    double sig[CSG_MAX_S + 2];
+    zc H[(CSG_MAX_S + 1) * CSG_MAX_S];
+    zc y[CSG_MAX_S];
+    double beta0;
+    int k;
+    int pad;
+};
+
+// Flexible GMRES state of one right-hand side.
+struct FState {
+    zc R[(CSG_MAX_RESTART + 1) * CSG_MAX_RESTART];  // rotated Hessenberg, row-major ld = MAXR
+    double cs[CSG_MAX_RESTART];
+    zc sn[CSG_MAX_RESTART];
+    zc g[CSG_MAX_RESTART + 1];
+    zc hcol[CSG_MAX_RESTART + 1];   // current column (first + second CGS round)
+    zc corr[CSG_MAX_RESTART + 1];   // second-round coefficients of the current column
+    zc y[CSG_MAX_RESTART];
+    double beta;       // norm of the current restart residual
+    double nchi;       // ||chi||
+    double hn;         // h_{j+1,j} of the current column
+    double inv_hn;     // scale applied to form v_{j+1}
+    int kcols;         // columns of the current restart cycle used by the update
+    int pad[3];
+};
+
+// Host-visible per-RHS report (copied back after every outer iteration).
+struct Report {
+    double est;        // |g_{j+1}| / ||chi||  (or true relres after a restart)
+    double hn;
+    int finite;
+    int pad;
+};
+
+// ---------------------------------------------------------------------------
+// Host hierarchy (FP64), built by setup.cpp
+// ---------------------------------------------------------------------------
+
+struct HostLevel {
+    int nint[3] = {0, 0, 0};   // intervals per axis
+    int nu[3] = {1, 1, 1};     // unknowns per axis (1 on unused axes)
+    long N = 0;
+    std::vector<cd> z[3];      // nested complex node coordinates of M's grid
+    std::vector<cd> tab[3];    // Shortley-Weller rows of M: [west | centre | east]
+    std::vector<double> phi;
+};
+
+struct HostHier {
+    int dim = 2, L = 0;
+    HostLevel lev[CSG_MAX_LEVELS];
+    std::vector<cd> tabH[3];   // finest-level Shortley-Weller rows of H (theta = 0)
+    std::vector<cd> minvT;     // coarsest M^{-1}, transposed (column j contiguous)
+    int nc = 0;
+};
+
+int plan_levels(const csg_params &p, int &L, int nint[CSG_MAX_LEVELS][3], std::string &err);
+int build_hierarchy(const csg_params &p, const double *phi, HostHier &hh, std::string &err);
+
+// ---------------------------------------------------------------------------
+// Device hierarchy carved from the caller's workspace
+// ---------------------------------------------------------------------------
+
+struct DevLevel {
+    unsigned nu[3];
+    unsigned N;
+    size_t ld;                 // elements between consecutive RHS vectors
+    const void *tab[3];        // cycle-precision complex tables (boundary weights zeroed)
+    const void *phi;           // cycle-precision real phi
+    void *b, *xa, *xb, *r;     // cycle-precision vectors [max_rhs][ld]
+    void *u[CSG_MAX_S + 1];    // u[1..s]; u[0] aliases b or r
+    zc *part[2];               // reduction partials [max_rhs][NVAL][NBMAX]
+    GState *gs;                // [max_rhs]
+    int nb;                    // blocks of a reducing pass
+    unsigned chunk;            // points per block of a reducing pass
+};
+
+struct SolveCache;
+
+}  // namespace csg
+
+struct csg_operator {
+    csg_params p;
+    int L;
+    int csize;                        // bytes of one cycle complex (8 or 16)
+    csg::DevLevel lev[CSG_MAX_LEVELS];
+    const void *tabH[3];              // FP64 H tables
+    const double *phiH;               // FP64 phi on the finest level
+    const void *minvT;                // coarsest inverse (cycle precision), transposed
+    int nc;
+    // outer FGMRES storage
+    csg::zc *V;                       // (m+1) x max_rhs x ld0
+    void *Z;                          // m x max_rhs x ld0, cycle precision
+    csg::zc *w;                       // max_rhs x ld0
+    void *b0;                         // cycle-precision copy of v_j (mixed mode)
+    csg::zc *opart;                   // [max_rhs][OVAL][NBMAX]
+    csg::FState *fs;                  // [max_rhs]
+    csg::Report *rep;                 // [max_rhs] device
+    int *active;                      // [max_rhs] device mask of RHS still iterating
+    int *ones;                        // [max_rhs] device all-ones mask
+    csg::Report *rep_host;            // pinned host mirror
+    hipEvent_t ev;
+    size_t ws_used;
+    int busy;                         // a csg_solve is in flight
+};

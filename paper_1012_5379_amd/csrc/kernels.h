@@ -1,0 +1,104 @@
+// kernels.h -- host-side launchers of the gfx950 kernels of libcsg.
+#pragma once
+
+#include "csg_internal.h"
+
+namespace csg {
+
+// Geometry of one level as seen by a kernel (tables and phi in precision T).
+template <typename T>
+struct LvlK {
+    const Cx<T> *tab[3];   // per axis [west | centre | east], boundary weights zeroed
+    const T *phi;
+    unsigned nx, ny, nz, N;
+};
+
+// Up to CSG_MAX_S+1 basis vector pointers (u_0..u_s) of one level.
+template <typename T>
+struct Basis {
+    Cx<T> *u[CSG_MAX_S + 1];
+};
+
+// Up to OVAL pointers are too many for kernel arguments; the outer basis is
+// addressed as base + i * vstride instead.
+
+struct Launch {
+    int nb;            // blocks along x (reducing passes: <= NBMAX)
+    unsigned chunk;    // points per block
+    int nrhs;
+    hipStream_t st;
+};
+
+// ---- smoother / cycle passes (T = float or double, DIM = 2 or 3) ----------
+template <typename T, int DIM>
+void launch_apply(const LvlK<T> &L, const void *x, void *y, size_t ld, const Launch &g, const int *active);
+
+template <typename T, int DIM>
+void launch_st(const LvlK<T> &L, const Basis<T> &B, int j, size_t ld, const zc *pin, int nbin, zc *pout,
+               GState *gs, double tiny, const Launch &g, const int *active);
+
+template <typename T>
+void launch_orth(const Basis<T> &B, int j, int s, unsigned N, size_t ld, const zc *pin, int nbin, zc *pout,
+                 GState *gs, const Launch &g, const int *active);
+
+template <typename T>
+void launch_upd(Cx<T> *x, int accumulate, const Basis<T> &B, int s, unsigned N, size_t ld, const zc *pin,
+                int nbin, GState *gs, double tiny, const Launch &g, const int *active);
+
+template <typename T, int DIM>
+void launch_upd_res(Cx<T> *x, int accumulate, const Basis<T> &B, int s, const LvlK<T> &F, const LvlK<T> &C,
+                    Cx<T> *bc, size_t ldf, size_t ldc, const zc *pin, int nbin, GState *gs, double tiny,
+                    const Launch &gc, const int *active);
+
+template <typename T, int DIM>
+void launch_resid(const LvlK<T> &L, const Cx<T> *x, const Cx<T> *b, Cx<T> *r, size_t ld, const Launch &g,
+                  const int *active);
+
+template <typename T, int DIM>
+void launch_restrict(const LvlK<T> &F, const LvlK<T> &C, const Cx<T> *x, const Cx<T> *b, Cx<T> *bc,
+                     size_t ldf, size_t ldc, const Launch &gc, const int *active);
+
+template <typename T, int DIM>
+void launch_prolong(const LvlK<T> &F, const LvlK<T> &C, const Cx<T> *ec, const Cx<T> *xin, Cx<T> *xout,
+                    size_t ldf, size_t ldc, const Launch &g, const int *active);
+
+template <typename T, int DIM>
+void launch_prc(const LvlK<T> &F, const LvlK<T> &C, const Cx<T> *ec, const Cx<T> *xin, Cx<T> *xout,
+                const Cx<T> *b, Cx<T> *r, size_t ldf, size_t ldc, const Launch &g, const int *active);
+
+template <typename T>
+void launch_coarse(const Cx<T> *minvT, int n, const Cx<T> *b, Cx<T> *x, size_t ld, int nrhs, hipStream_t st,
+                   const int *active);
+
+// ---- outer FGMRES passes (FP64 arithmetic; TZ = cycle precision) ----------
+template <typename TZ, int DIM>
+void launch_hst(const LvlK<double> &H, const Cx<TZ> *z, zc *w, const zc *V, size_t vstride, int j, size_t ld,
+                zc *pout, const Launch &g, const int *active);
+
+void launch_cgs1(zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, const FState *fs, zc *pout,
+                 const Launch &g, const int *active);
+
+void launch_cgs2(zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, const FState *fs, zc *pout,
+                 const Launch &g, const int *active);
+
+// v = w * scale (scale = fs->inv_hn), optional cycle-precision copy (cast).
+template <typename TB>
+void launch_vnorm(const zc *w, zc *v, Cx<TB> *bcast, unsigned N, size_t ld, const FState *fs, const Launch &g,
+                  const int *active);
+
+template <int DIM>
+void launch_tres(const LvlK<double> &H, const zc *chi, const zc *u, zc *r, size_t ld, int with_chi, zc *pout,
+                 const Launch &g, const int *active);
+
+template <typename TZ>
+void launch_uupd(zc *u, const Cx<TZ> *Z, size_t zstride, unsigned N, size_t ld, const FState *fs, const Launch &g,
+                 const int *active);
+
+// finish kernels: one block per RHS
+enum FinMode { FIN_H = 0, FIN_C = 1, FIN_N = 2, FIN_BEGIN = 3, FIN_BETA = 4, FIN_LS = 5 };
+void launch_fin(int mode, const zc *pin, int nbin, int j, FState *fs, Report *rep, int nrhs, hipStream_t st,
+                const int *active);
+
+void launch_copy_mask(const int *src, int *dst, int n, hipStream_t st);
+
+}  // namespace csg

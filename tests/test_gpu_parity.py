@@ -1,0 +1,200 @@
+"""GPU parity: every operation of the hot path through the C ABI against the
+FP64 CPU oracle on identical seeded inputs.
+
+Bars: complex128 path, norm-wise relative error <= 1e-12 per operation; end to
+end, the outer iteration count equals the oracle's +-1 and the solution agrees
+to 1e-10.  complex64 cycle: per-operation errors are stated by the tolerances
+below (single-precision rounding of the cycle)."""
+import numpy as np
+import pytest
+
+from synth import workloads as W
+from tests.gpu_common import dev, host, note, pair, rel, rvec, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+# C1 plus grids with odd interval counts, unequal layers and several blocks
+# with a ragged tail, in 2-D and 3-D.
+CASES = {
+    "c1": lambda: W.c1(),
+    "2d_ragged": lambda: W.small(dim=2, n=101, mlo=7, mhi=4, beta=0.35, kh=0.45, item=1),
+    "2d_wide": lambda: W.small(dim=2, n=300, m=21, beta=0.4, kh=0.5, item=2),
+    "3d_ragged": lambda: W.small(dim=3, n=27, mlo=3, mhi=4, beta=0.4, kh=0.4, item=3),
+}
+TOL64 = 1e-12
+TOL32 = {"apply": 1e-5, "restrict": 1e-5, "prolong": 1e-6, "coarse": 1e-4, "smooth": 1e-4, "vcycle": 1e-3}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    torch_cuda()
+    w = CASES[request.param]()
+    return request.param, w
+
+
+def _ops(case, cycle_prec):
+    name, w = case
+    return pair(w, max_rhs=2, cycle_prec=cycle_prec)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_stencil_every_level(case, prec):
+    import torch
+    op, orc = _ops(case, prec)
+    tol = TOL64 if prec == 0 else TOL32["apply"]
+    for l in range(op.levels):
+        x = np.stack([rvec(orc.shape(l), 10 + l), rvec(orc.shape(l), 20 + l)])
+        y = host(op.apply(dev(x, op.cdtype), which=1, level=l))
+        for r in range(2):
+            e = rel(y[r], orc.apply(x[r], which=1, l=l))
+            note(f"  M level {l} rhs {r}: {e:.2e}")
+            assert e <= tol
+    x = np.stack([rvec(orc.shape(0), 30), rvec(orc.shape(0), 31)])
+    y = host(op.apply(dev(x, torch.complex128), which=0, level=0))
+    for r in range(2):
+        e = rel(y[r], orc.apply(x[r], which=0, l=0))
+        note(f"  H rhs {r}: {e:.2e}")
+        assert e <= TOL64
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_transfers_every_level(case, prec):
+    op, orc = _ops(case, prec)
+    for l in range(op.levels - 1):
+        b = np.stack([rvec(orc.shape(l), 40 + l), rvec(orc.shape(l), 50 + l)])
+        x = np.stack([rvec(orc.shape(l), 60 + l), rvec(orc.shape(l), 70 + l)]) * 1e-3
+        bc = host(op.residual_restrict(dev(b, op.cdtype), dev(x, op.cdtype), level=l))
+        ec = np.stack([rvec(orc.shape(l + 1), 80 + l), rvec(orc.shape(l + 1), 90 + l)])
+        xp = host(op.prolong_correct(dev(ec, op.cdtype), dev(x, op.cdtype), level=l))
+        for r in range(2):
+            er = rel(bc[r], orc.restrict(b[r] - orc.apply(x[r], 1, l), l))
+            ep = rel(xp[r], orc.prolong_add(ec[r], x[r], l))
+            note(f"  level {l} rhs {r}: restrict {er:.2e} prolong {ep:.2e}")
+            assert er <= (TOL64 if prec == 0 else TOL32["restrict"])
+            assert ep <= (TOL64 if prec == 0 else TOL32["prolong"])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_coarse_solve(case, prec):
+    op, orc = _ops(case, prec)
+    L = op.levels - 1
+    b = np.stack([rvec(orc.shape(L), 100), rvec(orc.shape(L), 101)])
+    x = host(op.coarse_solve(dev(b, op.cdtype)))
+    for r in range(2):
+        e = rel(x[r], orc.coarse_solve(b[r]))
+        note(f"  coarse rhs {r}: {e:.2e}")
+        assert e <= (TOL64 if prec == 0 else TOL32["coarse"])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_gmres_sweep_every_level(case, prec):
+    op, orc = _ops(case, prec)
+    for l in range(op.levels):
+        b = np.stack([rvec(orc.shape(l), 110 + l), rvec(orc.shape(l), 120 + l)])
+        x0 = np.stack([rvec(orc.shape(l), 130 + l), rvec(orc.shape(l), 140 + l)]) * 1e-4
+        xd = dev(x0, op.cdtype)
+        x = host(op.smooth(dev(b, op.cdtype), xd, level=l))
+        for r in range(2):
+            xo, k = orc.gmres_sweep(b[r], x0[r], l=l)
+            e = rel(x[r], xo)
+            note(f"  sweep level {l} rhs {r}: {e:.2e} (oracle steps {k})")
+            assert e <= (TOL64 * 10 if prec == 0 else TOL32["smooth"])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_vcycle(case, prec):
+    op, orc = _ops(case, prec)
+    b = np.stack([rvec(orc.shape(0), 150), rvec(orc.shape(0), 151)])
+    x = host(op.vcycle(dev(b, op.cdtype)))
+    for r in range(2):
+        e = rel(x[r], orc.vcycle(b[r]))
+        note(f"  vcycle rhs {r}: {e:.2e}")
+        assert e <= (TOL64 if prec == 0 else TOL32["vcycle"])
+
+
+def test_vcycle_repeatable_bitwise(case):
+    """Deterministic reductions: the same cycle twice gives identical bits."""
+    op, orc = _ops(case, 0)
+    b = dev(np.stack([rvec(orc.shape(0), 160)] * 2), op.cdtype)
+    x1 = host(op.vcycle(b))
+    x2 = host(op.vcycle(b))
+    assert np.array_equal(x1, x2)
+    assert np.array_equal(x1[0], x1[1])   # batch position does not change the result
+
+
+def test_fgmres_fp64_matches_oracle():
+    """End to end on the 64^2 + 8 workload (k = 20, beta = 0.4): outer
+    iterations +-1 and solution within 1e-10 of the oracle at tol 1e-6."""
+    import torch
+    w = W.c1()
+    op, orc = pair(w, max_rhs=1, cycle_prec=0)
+    u_o, info_o = orc.fgmres(w.chi[0], tol=1e-6, restart=30, maxit=500)
+    u, rc, infos = op.solve(dev(w.chi, torch.complex128), tol=1e-6, restart=30, maxit=500)
+    u = host(u)[0]
+    note(f"  oracle its {info_o.iterations} gpu its {infos[0]['iterations']} relres {infos[0]['relres_true']:.3e}")
+    assert rc == 0 and infos[0]["converged"]
+    assert abs(infos[0]["iterations"] - info_o.iterations) <= 1
+    e = rel(u, u_o)
+    note(f"  solution vs oracle: {e:.2e}")
+    assert e <= 1e-10
+    # the true residual, recomputed independently by the oracle's H
+    r = w.chi[0] - orc.apply(u, which=0, l=0)
+    assert np.linalg.norm(r) / np.linalg.norm(w.chi[0]) <= 1e-6
+
+
+@pytest.mark.parametrize("name", ["2d_ragged", "3d_ragged"])
+def test_fgmres_fp64_multi_rhs(name):
+    """Two right-hand sides solved together, each matching its own oracle solve."""
+    import torch
+    w = CASES[name]()
+    chi = np.stack([w.chi[0], rvec(w.chi.shape[1:], 170)])
+    op, orc = pair(w, max_rhs=2, cycle_prec=0)
+    u, rc, infos = op.solve(dev(chi, torch.complex128), tol=1e-8, restart=20, maxit=400)
+    u = host(u)
+    assert rc == 0
+    for r in range(2):
+        uo, io = orc.fgmres(chi[r], tol=1e-8, restart=20, maxit=400)
+        e = rel(u[r], uo)
+        note(f"  rhs {r}: its gpu {infos[r]['iterations']} oracle {io.iterations} sol err {e:.2e}")
+        assert abs(infos[r]["iterations"] - io.iterations) <= 1
+        assert e <= 1e-10
+
+
+def test_fgmres_mixed_precision_reaches_tolerance():
+    """complex64 cycle, complex128 outer: true FP64 relres <= 1e-6 and the
+    solution error against the tightly converged FP64 oracle is stated."""
+    import torch
+    w = W.c1()
+    op, orc = pair(w, max_rhs=1, cycle_prec=1)
+    u, rc, infos = op.solve(dev(w.chi, torch.complex128), tol=1e-6, restart=30, maxit=500)
+    u = host(u)[0]
+    assert rc == 0 and infos[0]["converged"]
+    r = w.chi[0] - orc.apply(u, which=0, l=0)
+    rr = np.linalg.norm(r) / np.linalg.norm(w.chi[0])
+    u_ref, _ = orc.fgmres(w.chi[0], tol=1e-12, restart=30, maxit=2000)
+    u6, i6 = orc.fgmres(w.chi[0], tol=1e-6, restart=30, maxit=2000)
+    floor = rel(u6, u_ref)
+    e = rel(u, u_ref)
+    note(f"  mixed: its {infos[0]['iterations']} (fp64 oracle {i6.iterations}) relres {rr:.2e} "
+         f"sol err {e:.2e} (floor of a 1e-6 solve: {floor:.2e})")
+    assert rr <= 1e-6
+    assert e <= max(1e-5, 10 * floor)
+
+
+def test_solve_edge_cases():
+    """Zero source -> zero solution in 0 iterations; maxit -> ENOCONV with the
+    last iterate; a converged initial guess takes no iteration."""
+    import torch
+    from paper_1012_5379_amd import binding as B
+    w = W.small(dim=2, n=24, m=4, item=9)
+    op, orc = pair(w, max_rhs=2, cycle_prec=0)
+    chi = np.stack([np.zeros(w.grid_shape, complex), w.chi[0]])
+    u, rc, infos = op.solve(dev(chi, torch.complex128), tol=1e-8, restart=10, maxit=300)
+    u = host(u)
+    assert rc == 0
+    assert infos[0]["iterations"] == 0 and not np.any(u[0])
+    u2, rc2, inf2 = op.solve(dev(chi[1:], torch.complex128), tol=1e-14, restart=10, maxit=3)
+    assert rc2 == B.CSG_ENOCONV and inf2[0]["iterations"] == 3 and not inf2[0]["converged"]
+    u3, rc3, inf3 = op.solve(dev(chi[1:], torch.complex128), tol=1e-8, restart=10, maxit=300,
+                             u0=dev(u[1:], torch.complex128))
+    assert rc3 == 0 and inf3[0]["iterations"] == 0
