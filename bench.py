@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Benchmark of the GMRES-smoothed CSG multigrid / FGMRES Helmholtz solve on one
+MI355X.
+
+One step = one complete solve of the 2-D 1024^2-interior problem with 32-cell
+ECS layers (phi = k0^2 (1 - 0.5 exp(-|x-c|^2/0.02)), kh = 0.5, Gaussian source
+of width 2h, beta = 0.4, 8 levels, V(1,1) with GMRES(3), FGMRES(30) to true
+relative residual 1e-6, all in complex128): every pass of the hot path (setup
+excluded, inputs resident in HBM) runs inside each step.
+
+Printed JSON (one line): solves/s as `value`, p50/p99 solve latency, V-cycle
+GB/s, the roofline of the dominant pass (its algorithmic bytes per launch over
+its average launch time, both measured with HIP events on the solve's stream
+inside the timed region), and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "solves/s & p99 latency at relres 1e-6; V-cycle GB/s vs HBM peak"
+
+
+def _workload(name):
+    from synth import workloads as W
+    if name == "c2":
+        return W.c2(), "2d_1024sq_ecs32_kh0.5_gauss_beta0.4_8lev_fp64"
+    if name == "c3":
+        return W.c3(), "2d_2048sq_ecs32_3layer_kh0.5_beta0.3_9lev_c64cycle"
+    if name == "c3_fp64":
+        return W.c3(cycle_prec=0), "2d_2048sq_ecs32_3layer_kh0.5_beta0.3_9lev_fp64"
+    if name == "c1":
+        return W.c1(), "2d_64sq_ecs8_k20_beta0.4_5lev_fp64"
+    if name == "c4":
+        return W.c4(), "3d_128cube_ecs16_16rhs_beta0.4_6lev_c64cycle"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(w, its_per_solve, sample_its):
+    """Oracle (as it stands) on the same workload: time `sample_its` FGMRES
+    iterations and scale to solves/s with the solve's iteration count."""
+    from oracle import oracle as O
+    O.lib()
+    p = O.Params(**w.params())
+    t0 = time.perf_counter()
+    o = O.Oracle(p, w.phi)
+    t_setup = time.perf_counter() - t0
+    chi = w.chi[0]
+    t0 = time.perf_counter()
+    _, info = o.fgmres(chi, tol=w.tol, restart=30, maxit=sample_its)
+    dt = time.perf_counter() - t0
+    per_it = dt / max(1, info.iterations)
+    return {
+        "value": 1.0 / (per_it * its_per_solve * w.nrhs),
+        "unit": "solves/s",
+        "cores": O.threads(),
+        "kind": "oracle",
+        "sample": (f"first {info.iterations} FGMRES iterations of the same solve on the CPU oracle "
+                   f"({dt:.1f} s, {per_it * 1e3:.1f} ms/iteration; setup {t_setup:.2f} s excluded), "
+                   f"scaled to the {its_per_solve} iterations of a full solve"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--cpu-sample-its", type=int, default=40)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-survey", action="store_true", help="skip the per-pass time survey")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this solver build runs every solve on a single MI355X "
+              "(requests and right-hand sides would shard across GPUs without exchange); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1012_5379_amd import Operator
+    from paper_1012_5379_amd import binding as B
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(2)
+
+    w, wname = _workload(args.workload)
+    params = dict(w.params(), cycle_prec=w.cycle_prec, max_rhs=w.nrhs, restart=w.restart)
+    t0 = time.perf_counter()
+    op = Operator(params, w.phi)
+    t_setup = time.perf_counter() - t0
+    chi = torch.from_numpy(w.chi).to("cuda")
+    u = torch.empty_like(chi)
+    stream = torch.cuda.current_stream().cuda_stream
+    nrhs = w.nrhs
+
+    def solve():
+        rc, infos = B.helm_solve(op.op, chi.data_ptr(), u.data_ptr(), nrhs, w.tol, w.restart, w.maxit, 0, stream)
+        if rc != 0:
+            raise RuntimeError(f"solve did not converge: {B.STATUS.get(rc, rc)} {infos}")
+        return infos
+
+    print(f"[bench] workload {wname}: levels {op.levels} dims {op.dims[0]}; setup {t_setup:.2f}s", file=sys.stderr,
+          flush=True)
+    for i in range(args.warmup):
+        infos = solve()
+        print(f"[bench] warmup {i}: {infos[0]['iterations']} its, relres {infos[0]['relres_true']:.2e}, "
+              f"{infos[0]['seconds'] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+
+    # untimed survey: kernel time per pass kind over one solve each
+    survey = {}
+    its = infos[0]["iterations"] if args.warmup else None
+    if not args.no_survey:
+        for name, kind in B.PROF_KINDS.items():
+            B.csg_profile(op.op, kind, 1 << 16)
+            infos = solve()
+            ms, n, by = B.csg_profile_read(op.op)
+            B.csg_profile(op.op, 0, 0)
+            survey[name] = {"ms_per_solve": ms, "launches": n, "GBps": (by / (ms * 1e-3) / 1e9) if ms > 0 else 0.0}
+            its = infos[0]["iterations"]
+            print(f"[bench] survey {name}: {ms:.2f} ms over {n} launches, "
+                  f"{survey[name]['GBps']:.0f} GB/s", file=sys.stderr, flush=True)
+    passes = {k: v for k, v in survey.items() if k != "vcycle"}
+    dominant = max(passes, key=lambda k: passes[k]["ms_per_solve"]) if passes else "outer_cgs1"
+
+    # timed region: K solves; the dominant pass is timed with events on its stream
+    B.csg_profile(op.op, B.PROF_KINDS[dominant], 1 << 20)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        infos = solve()
+        lat.append(time.perf_counter() - s0)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kms, kn, kbytes = B.csg_profile_read(op.op)
+    B.csg_profile(op.op, 0, 0)
+    its = infos[0]["iterations"]
+
+    value = args.steps * nrhs / elapsed
+    achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
+    lat_ms = np.array(lat) * 1e3
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if w.cycle_prec else "f64",
+        "data": "synthetic",
+        "config": {"workload": wname, "unknowns": int(w.unknowns), "nrhs": nrhs, "levels": op.levels,
+                   "tol": w.tol, "restart": w.restart, "cycle": "V(1,1) GMRES(3)",
+                   "outer_dtype": "f64", "parallelism": "single-gpu"},
+        "iterations_per_solve": its,
+        "relres_true": infos[0]["relres_true"],
+        "p50_latency_ms": float(np.percentile(lat_ms, 50)),
+        "p99_latency_ms": float(np.percentile(lat_ms, 99)),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dominant,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": None,
+            "launches": kn,
+            "avg_launch_us": kms * 1e3 / max(1, kn),
+            "alg_bytes_per_launch": kbytes / max(1, kn),
+        },
+    }
+    if "vcycle" in survey:
+        v = survey["vcycle"]
+        out["vcycle_GBps"] = v["GBps"]
+        out["vcycle_ms"] = v["ms_per_solve"] / max(1, v["launches"])
+        out["vcycle_frac_of_hbm_peak"] = v["GBps"] / HBM_PEAK_GBPS
+        out["pass_survey_ms_per_solve"] = {k: round(v["ms_per_solve"], 3) for k, v in survey.items()}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, its, args.cpu_sample_its)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

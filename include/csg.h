@@ -178,6 +178,31 @@ int csg_solve_step(csg_solve *sv);
 int csg_solve_poll(csg_solve *sv, int *done);
 int csg_solve_end(csg_solve *sv, csg_solve_info *info);
 
+/* Benchmark instrumentation (not needed to solve).  csg_profile(op, kind, cap)
+ * makes the library record a pair of HIP events around every launch of one
+ * pass kind, on the stream that launch uses, for up to `cap` launches, and sum
+ * the algorithmic bytes those launches move (the minimal traffic of the pass:
+ * each input vector read once, each output written once).  kind 0 disables it.
+ * csg_profile_read waits for the last recorded event and returns the summed
+ * kernel time (ms), the number of launches timed and the summed algorithmic
+ * bytes.  Kinds: */
+enum {
+    CSG_PROF_OFF = 0,
+    CSG_PROF_VCYCLE = 1,        /* one whole V-cycle (every level)            */
+    CSG_PROF_STENCIL_DOTS = 2,  /* finest-level Arnoldi stencil + dot pass    */
+    CSG_PROF_ORTH = 3,          /* finest-level Gram-Schmidt + norm pass      */
+    CSG_PROF_UPD_RESTRICT = 4,  /* finest-level update + restriction pass     */
+    CSG_PROF_PROLONG_RESID = 5, /* finest-level correction + residual pass    */
+    CSG_PROF_UPDATE = 6,        /* finest-level post-smoother update pass     */
+    CSG_PROF_OUTER_H = 7,       /* FGMRES: w = H z + first-round dots         */
+    CSG_PROF_OUTER_CGS1 = 8,    /* FGMRES: first projection + second-round dots */
+    CSG_PROF_OUTER_CGS2 = 9,    /* FGMRES: second projection + norm           */
+    CSG_PROF_OUTER_NORM = 10,   /* FGMRES: normalisation (and cast)           */
+    CSG_PROF_KINDS = 11
+};
+int csg_profile(csg_operator *op, int kind, int cap);
+int csg_profile_read(csg_operator *op, double *ms, long *launches, double *bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -10,6 +10,9 @@
 
 #include <float.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -57,6 +60,15 @@ cplx ora_dot(long n, const cplx *x, const cplx *y)
     for (long c = 0; c < nchunks; ++c) s += part[c];
     free(part);
     return s;
+}
+
+int ora_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 static double nrm2(long n, const cplx *x) { return sqrt(creal(ora_dot(n, x, x))); }

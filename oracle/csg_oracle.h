@@ -96,6 +96,9 @@ int ora_fgmres(const ora_hier *hh, const double complex *chi, double complex *u,
  * chunks, summed in chunk order (independent of the thread count). */
 double complex ora_dot(long n, const double complex *x, const double complex *y);
 
+/* OpenMP threads the oracle's parallel loops use (1 without OpenMP). */
+int ora_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -77,6 +77,8 @@ def lib():
         L.ora_vcycle_level.argtypes = [vp, ip, vp, vp]
         L.ora_vcycle.argtypes = [vp, vp, vp]
         L.ora_fgmres.argtypes = [vp, vp, vp, dp, ip, ip, ip, C.POINTER(_Info), vp, ip]
+        L.ora_threads.restype = C.c_int
+        L.ora_threads.argtypes = []
         L.ora_dot.restype = _Cplx
         L.ora_dot.argtypes = [C.c_long, vp, vp]
         _lib = L
@@ -250,3 +252,7 @@ def dot(x: np.ndarray, y: np.ndarray) -> complex:
     y, py = _c(y.ravel(), np.complex128)
     r = lib().ora_dot(x.size, px, py)
     return complex(r.re, r.im)
+
+
+def threads() -> int:
+    return int(lib().ora_threads())

@@ -66,7 +66,12 @@ _SIGS = {
     "csg_solve_step": (ip, [vp]),
     "csg_solve_poll": (ip, [vp, C.POINTER(C.c_int)]),
     "csg_solve_end": (ip, [vp, C.POINTER(csg_solve_info)]),
+    "csg_profile": (ip, [vp, ip, ip]),
+    "csg_profile_read": (ip, [vp, C.POINTER(C.c_double), C.POINTER(C.c_long), C.POINTER(C.c_double)]),
 }
+
+PROF_KINDS = {"vcycle": 1, "stencil_dots": 2, "orth": 3, "upd_restrict": 4, "prolong_resid": 5,
+              "update": 6, "outer_h": 7, "outer_cgs1": 8, "outer_cgs2": 9, "outer_norm": 10}
 
 
 def lib() -> C.CDLL:
@@ -204,3 +209,14 @@ def csg_solve_end(sv, nrhs):
     if rc < 0 and rc != CSG_ENOCONV:
         check(rc)
     return rc, [infos[r].as_dict() for r in range(nrhs)]
+
+
+def csg_profile(op, kind: int, cap: int) -> None:
+    check(lib().csg_profile(op, kind, cap))
+
+
+def csg_profile_read(op):
+    """Returns (kernel ms summed, launches, algorithmic bytes summed)."""
+    ms, n, by = C.c_double(0), C.c_long(0), C.c_double(0)
+    check(lib().csg_profile_read(op, C.byref(ms), C.byref(n), C.byref(by)))
+    return ms.value, n.value, by.value

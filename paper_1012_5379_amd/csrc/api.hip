@@ -142,6 +142,84 @@ Launch lch(const csg_operator *op, int l, int nrhs, hipStream_t st)
 template <typename T>
 double tiny_of() { return 10.0 * (sizeof(T) == 8 ? DBL_EPSILON : (double)FLT_EPSILON); }
 
+// ---------------------------------------------------------------------------
+// benchmark instrumentation: event pairs around the launches of one pass kind
+// ---------------------------------------------------------------------------
+struct ProfScope {
+    Prof *pr = nullptr;
+    hipStream_t st = nullptr;
+    bool on = false;
+    ProfScope(const csg_operator *op, int kind, hipStream_t s, double bytes)
+    {
+        pr = op->prof;
+        on = pr && pr->kind == kind && pr->n < pr->cap;
+        if (on) {
+            st = s;
+            hipEventRecord(pr->ev[2 * pr->n], s);
+            pr->bytes += bytes;
+        }
+    }
+    ~ProfScope()
+    {
+        if (on) {
+            hipEventRecord(pr->ev[2 * pr->n + 1], st);
+            pr->n++;
+        }
+    }
+};
+
+// Algorithmic bytes of the passes (each input vector read once, each output
+// written once; phi and tables counted once per launch).
+struct Bytes {
+    double z, p;   // bytes of one cycle complex / real
+    int R;         // right-hand sides
+    double st(int j, double N) const { return R * (j + 2) * z * N + p * N; }
+    double orth(int j, double N) const { return R * (j + 3) * z * N; }
+    double upd(int k, bool acc, double N) const { return R * (k + 1 + (acc ? 1 : 0)) * z * N; }
+    double upd_res(int s, bool acc, double N, double Nc) const
+    {
+        return R * ((s + 2 + (acc ? 1 : 0)) * z * N + z * Nc);
+    }
+    double resid(double N) const { return R * 3 * z * N + p * N; }
+    double restrict_b(double N, double Nc) const { return R * z * (N + Nc); }
+    double prc(bool xin, double N, double Nc) const { return R * z * ((xin ? N : 0) + Nc + 3 * N) + p * N; }
+    double prolong(bool xin, double N, double Nc) const { return R * z * ((xin ? N : 0) + Nc + N); }
+    double coarse(double n) const { return n * n * z + R * 2 * n * z; }
+};
+
+Bytes bytes_of(const csg_operator *op, int nrhs)
+{
+    Bytes b;
+    b.z = op->csize;
+    b.p = op->csize / 2;
+    b.R = nrhs;
+    return b;
+}
+
+double vcycle_bytes(const csg_operator *op, int nrhs)
+{
+    const Bytes b = bytes_of(op, nrhs);
+    const int s = op->p.s, nu1 = op->p.nu1, nu2 = op->p.nu2;
+    double tot = b.coarse(op->nc);
+    for (int l = 0; l + 1 < op->L; ++l) {
+        const double N = op->lev[l].N, Nc = op->lev[l + 1].N;
+        double steps = 0;
+        for (int j = 0; j < s; ++j) steps += b.st(j, N) + b.orth(j, N);
+        if (nu1 == 0) tot += b.restrict_b(N, Nc);
+        for (int k = 0; k < nu1; ++k) {
+            tot += (k ? b.resid(N) : 0) + steps;
+            tot += (k == nu1 - 1) ? b.upd_res(s, k > 0, N, Nc) : b.upd(s, k > 0, N);
+        }
+        if (nu2 == 0) {
+            tot += b.prolong(nu1 > 0, N, Nc);
+        } else {
+            tot += b.prc(nu1 > 0, N, Nc);
+            for (int k = 0; k < nu2; ++k) tot += (k ? b.resid(N) : 0) + steps + b.upd(s, true, N);
+        }
+    }
+    return tot;
+}
+
 // One GMRES(s) sweep on level l: Arnoldi steps on u_0 (= b when x == 0, else
 // the residual in lv.r), then the closing pass.  `close` selects the plain
 // update (x (+)= V y) or the update fused with the restriction of the
@@ -163,15 +241,23 @@ void sweep(const csg_operator *op, int l, const Cx<T> *b, Cx<T> *x, bool from_ze
         launch_resid<T, DIM>(L, x, b, (Cx<T> *)lv.r, lv.ld, g, active);
         B.u[0] = (Cx<T> *)lv.r;
     }
+    const Bytes by = bytes_of(op, nrhs);
+    const int k0 = l == 0 ? 0 : -1;   // instrumented kinds exist for the finest level only
     for (int j = 0; j < s; ++j) {
-        launch_st<T, DIM>(L, B, j, lv.ld, lv.part[1], lv.nb, lv.part[0], lv.gs, tiny, g, active);
+        {
+            ProfScope ps(op, k0 ? -1 : CSG_PROF_STENCIL_DOTS, st, by.st(j, lv.N));
+            launch_st<T, DIM>(L, B, j, lv.ld, lv.part[1], lv.nb, lv.part[0], lv.gs, tiny, g, active);
+        }
+        ProfScope ps(op, k0 ? -1 : CSG_PROF_ORTH, st, by.orth(j, lv.N));
         launch_orth<T>(B, j, s, lv.N, lv.ld, lv.part[0], lv.nb, lv.part[1], lv.gs, g, active);
     }
     if (restrict_after) {
         const DevLevel &cl = op->lev[l + 1];
+        ProfScope ps(op, k0 ? -1 : CSG_PROF_UPD_RESTRICT, st, by.upd_res(s, !from_zero, lv.N, cl.N));
         launch_upd_res<T, DIM>(x, from_zero ? 0 : 1, B, s, L, lvl<T>(op, l + 1), (Cx<T> *)cl.b, lv.ld, cl.ld,
                                lv.part[1], lv.nb, lv.gs, tiny, lch(op, l + 1, nrhs, st), active);
     } else {
+        ProfScope ps(op, k0 ? -1 : CSG_PROF_UPDATE, st, by.upd(s, !from_zero, lv.N));
         launch_upd<T>(x, from_zero ? 0 : 1, B, s, lv.N, lv.ld, lv.part[1], lv.nb, lv.gs, tiny, g, active);
     }
 }
@@ -213,8 +299,12 @@ void vcycle_impl(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, h
             launch_prolong<T, DIM>(lvl<T>(op, l), lvl<T>(op, l + 1), (const Cx<T> *)cl.xb, xi, xo, lv.ld, cl.ld, g,
                                    active);
         } else {
-            launch_prc<T, DIM>(lvl<T>(op, l), lvl<T>(op, l + 1), (const Cx<T> *)cl.xb, xi, xo, b, (Cx<T> *)lv.r,
-                               lv.ld, cl.ld, g, active);
+            {
+                ProfScope ps(op, l == 0 ? CSG_PROF_PROLONG_RESID : -1, st,
+                             bytes_of(op, nrhs).prc(xi != nullptr, lv.N, cl.N));
+                launch_prc<T, DIM>(lvl<T>(op, l), lvl<T>(op, l + 1), (const Cx<T> *)cl.xb, xi, xo, b,
+                                   (Cx<T> *)lv.r, lv.ld, cl.ld, g, active);
+            }
             for (int k = 0; k < nu2; ++k) {
                 // the first post-sweep starts from the residual already in lv.r
                 const DevLevel &d = op->lev[l];
@@ -225,10 +315,16 @@ void vcycle_impl(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, h
                 for (int i = 0; i <= CSG_MAX_S; ++i) B.u[i] = (Cx<T> *)d.u[i];
                 if (k > 0) launch_resid<T, DIM>(Lk, xo, b, (Cx<T> *)d.r, d.ld, g, active);
                 B.u[0] = (Cx<T> *)d.r;
+                const Bytes by = bytes_of(op, nrhs);
                 for (int j = 0; j < s; ++j) {
-                    launch_st<T, DIM>(Lk, B, j, d.ld, d.part[1], d.nb, d.part[0], d.gs, tiny, g, active);
+                    {
+                        ProfScope ps(op, l == 0 ? CSG_PROF_STENCIL_DOTS : -1, st, by.st(j, d.N));
+                        launch_st<T, DIM>(Lk, B, j, d.ld, d.part[1], d.nb, d.part[0], d.gs, tiny, g, active);
+                    }
+                    ProfScope ps(op, l == 0 ? CSG_PROF_ORTH : -1, st, by.orth(j, d.N));
                     launch_orth<T>(B, j, s, d.N, d.ld, d.part[0], d.nb, d.part[1], d.gs, g, active);
                 }
+                ProfScope ps(op, l == 0 ? CSG_PROF_UPDATE : -1, st, by.upd(s, true, d.N));
                 launch_upd<T>(xo, 1, B, s, d.N, d.ld, d.part[1], d.nb, d.gs, tiny, g, active);
             }
         }
@@ -246,6 +342,7 @@ void vcycle_dispatch(const csg_operator *op, const void *b, void *x, int nrhs, h
 
 void run_vcycle(const csg_operator *op, const void *b, void *x, int nrhs, hipStream_t st, const int *active)
 {
+    ProfScope ps(op, CSG_PROF_VCYCLE, st, vcycle_bytes(op, nrhs));
     if (op->p.cycle_prec)
         vcycle_dispatch<float>(op, b, x, nrhs, st, active);
     else
@@ -319,12 +416,23 @@ void enqueue_iter(csg_solve *sv)
     const void *b = op->p.cycle_prec ? op->b0 : (const void *)(op->V + j * vstride);
     Cx<TZ> *z = (Cx<TZ> *)op->Z + j * vstride;
     run_vcycle(op, b, z, sv->nrhs, sv->st, mask);
-    launch_hst<TZ, DIM>(lvlH(op), z, op->w, op->V, vstride, j, f.ld, op->opart, g, mask);
+    const double N = f.N, R = sv->nrhs;
+    {
+        ProfScope ps(op, CSG_PROF_OUTER_H, sv->st, R * N * (sizeof(Cx<TZ>) + 16.0 * (j + 2)) + 8.0 * N);
+        launch_hst<TZ, DIM>(lvlH(op), z, op->w, op->V, vstride, j, f.ld, op->opart, g, mask);
+    }
     launch_fin(FIN_H, op->opart, f.nb, j, op->fs, op->rep, sv->nrhs, sv->st, mask);
-    launch_cgs1(op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->opart, g, mask);
+    {
+        ProfScope ps(op, CSG_PROF_OUTER_CGS1, sv->st, R * N * 16.0 * (j + 3));
+        launch_cgs1(op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->opart, g, mask);
+    }
     launch_fin(FIN_C, op->opart, f.nb, j, op->fs, op->rep, sv->nrhs, sv->st, mask);
-    launch_cgs2(op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->opart, g, mask);
+    {
+        ProfScope ps(op, CSG_PROF_OUTER_CGS2, sv->st, R * N * 16.0 * (j + 3));
+        launch_cgs2(op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->opart, g, mask);
+    }
     launch_fin(FIN_N, op->opart, f.nb, j, op->fs, op->rep, sv->nrhs, sv->st, mask);
+    ProfScope ps(op, CSG_PROF_OUTER_NORM, sv->st, R * N * (32.0 + (op->p.cycle_prec ? 8.0 : 0.0)));
     launch_vnorm<TZ>(op->w, op->V + (j + 1) * vstride, op->p.cycle_prec ? (Cx<TZ> *)op->b0 : nullptr, f.N, f.ld,
                      op->fs, g, mask);
 }
@@ -601,9 +709,58 @@ int csg_operator_create(const csg_params *p, const double *phi_host, void *ws_de
     return CSG_OK;
 }
 
+int csg_profile(csg_operator *op, int kind, int cap)
+{
+    if (!op) return fail(CSG_EINVAL, "null operator");
+    if (kind < 0 || kind >= CSG_PROF_KINDS || cap < 0 || cap > (1 << 20)) return fail(CSG_EINVAL, "bad profile kind/cap");
+    if (op->prof) {
+        hipDeviceSynchronize();
+        for (hipEvent_t e : op->prof->ev) hipEventDestroy(e);
+        delete op->prof;
+        op->prof = nullptr;
+    }
+    if (kind == CSG_PROF_OFF || cap == 0) return CSG_OK;
+    Prof *pr = new Prof;
+    pr->kind = kind;
+    pr->cap = cap;
+    pr->ev.resize(2 * (size_t)cap);
+    for (auto &e : pr->ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            delete pr;
+            return fail(CSG_EDEVICE, "event creation failed");
+        }
+    op->prof = pr;
+    return CSG_OK;
+}
+
+int csg_profile_read(csg_operator *op, double *ms, long *launches, double *bytes)
+{
+    if (!op) return fail(CSG_EINVAL, "null operator");
+    double tot = 0.0;
+    long n = 0;
+    double by = 0.0;
+    if (op->prof && op->prof->n > 0) {
+        Prof *pr = op->prof;
+        if (hipEventSynchronize(pr->ev[2 * (pr->n - 1) + 1]) != hipSuccess) return fail(CSG_EDEVICE, "event wait");
+        for (int i = 0; i < pr->n; ++i) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, pr->ev[2 * i], pr->ev[2 * i + 1]) != hipSuccess)
+                return fail(CSG_EDEVICE, "event elapsed time");
+            tot += t;
+        }
+        n = pr->n;
+        by = pr->bytes;
+    }
+    if (ms) *ms = tot;
+    if (launches) *launches = n;
+    if (bytes) *bytes = by;
+    return CSG_OK;
+}
+
 int csg_operator_destroy(csg_operator *op)
 {
     if (!op) return CSG_OK;
+    if (op->prof) csg_profile(op, CSG_PROF_OFF, 0);
     if (op->ev) hipEventDestroy(op->ev);
     if (op->rep_host) hipHostFree(op->rep_host);
     delete op;

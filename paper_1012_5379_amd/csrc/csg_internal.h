@@ -105,7 +105,14 @@ struct DevLevel {
     unsigned chunk;            // points per block of a reducing pass
 };
 
-struct SolveCache;
+// Event-pair instrumentation of one pass kind (benchmarks only).
+struct Prof {
+    int kind = 0;
+    int cap = 0;
+    int n = 0;
+    double bytes = 0.0;
+    std::vector<hipEvent_t> ev;   // 2 * cap events: start, stop
+};
 
 }  // namespace csg
 
@@ -132,4 +139,5 @@ struct csg_operator {
     hipEvent_t ev;
     size_t ws_used;
     int busy;                         // a csg_solve is in flight
+    csg::Prof *prof;                  // instrumentation, or null
 };
