@@ -73,6 +73,16 @@ typedef struct csg_params {
     int cycle_prec;     /* 0 = complex128 V-cycle, 1 = complex64 V-cycle (mixed) */
     int max_rhs;        /* right-hand sides solved together, 1..CSG_MAX_RHS */
     int restart;        /* FGMRES restart length m the workspace is sized for, 1..CSG_MAX_RESTART */
+    /* execution tuning (0 = library default; results are unaffected beyond rounding):
+     *   tail_max  levels with at most this many unknowns run in the one-workgroup
+     *             coarse-tail kernel (-1: only the coarsest level)
+     *   fuse_max  levels with at most this many unknowns use the fused
+     *             Gram-Schmidt + stencil Arnoldi passes (-1: never)
+     *   graphs    1 (default) replay FGMRES iterations from captured HIP graphs,
+     *             -1 launch eagerly */
+    int tail_max;
+    int fuse_max;
+    int graphs;
 } csg_params;
 
 typedef struct csg_operator csg_operator;
@@ -195,10 +205,11 @@ enum {
     CSG_PROF_PROLONG_RESID = 5, /* finest-level correction + residual pass    */
     CSG_PROF_UPDATE = 6,        /* finest-level post-smoother update pass     */
     CSG_PROF_OUTER_H = 7,       /* FGMRES: w = H z + first-round dots         */
-    CSG_PROF_OUTER_CGS1 = 8,    /* FGMRES: first projection + second-round dots */
-    CSG_PROF_OUTER_CGS2 = 9,    /* FGMRES: second projection + norm           */
+    CSG_PROF_OUTER_CGS1 = 8,    /* FGMRES: first projection                   */
+    CSG_PROF_OUTER_CGS2 = 9,    /* FGMRES: second-round dots                  */
     CSG_PROF_OUTER_NORM = 10,   /* FGMRES: normalisation (and cast)           */
-    CSG_PROF_KINDS = 11
+    CSG_PROF_OUTER_PROJ2 = 11,  /* FGMRES: second projection + norm           */
+    CSG_PROF_KINDS = 12
 };
 int csg_profile(csg_operator *op, int kind, int cap);
 int csg_profile_read(csg_operator *op, double *ms, long *launches, double *bytes);

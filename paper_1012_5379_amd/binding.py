@@ -26,7 +26,8 @@ class csg_params(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("h", C.c_double),
                 ("layer_lo", C.c_int * 3), ("layer_hi", C.c_int * 3), ("gamma", C.c_double),
                 ("beta", C.c_double), ("levels", C.c_int), ("s", C.c_int), ("nu1", C.c_int),
-                ("nu2", C.c_int), ("cycle_prec", C.c_int), ("max_rhs", C.c_int), ("restart", C.c_int)]
+                ("nu2", C.c_int), ("cycle_prec", C.c_int), ("max_rhs", C.c_int), ("restart", C.c_int),
+                ("tail_max", C.c_int), ("fuse_max", C.c_int), ("graphs", C.c_int)]
 
 
 class csg_solve_info(C.Structure):
@@ -71,7 +72,8 @@ _SIGS = {
 }
 
 PROF_KINDS = {"vcycle": 1, "stencil_dots": 2, "orth": 3, "upd_restrict": 4, "prolong_resid": 5,
-              "update": 6, "outer_h": 7, "outer_cgs1": 8, "outer_cgs2": 9, "outer_norm": 10}
+              "update": 6, "outer_h": 7, "outer_cgs1": 8, "outer_cgs2": 9, "outer_norm": 10,
+              "outer_proj2": 11}
 
 
 def lib() -> C.CDLL:
@@ -104,7 +106,7 @@ def check(code: int) -> int:
 
 def make_params(dim=2, n=(64, 64, 0), h=1 / 64, layer_lo=(8, 8, 0), layer_hi=(8, 8, 0),
                 gamma=0.5235987755982988, beta=0.4, levels=0, s=3, nu1=1, nu2=1, cycle_prec=0,
-                max_rhs=1, restart=30) -> csg_params:
+                max_rhs=1, restart=30, tail_max=0, fuse_max=0, graphs=0) -> csg_params:
     p = csg_params()
     p.dim = int(dim)
     for a in range(3):
@@ -114,6 +116,7 @@ def make_params(dim=2, n=(64, 64, 0), h=1 / 64, layer_lo=(8, 8, 0), layer_hi=(8,
     p.h, p.gamma, p.beta = float(h), float(gamma), float(beta)
     p.levels, p.s, p.nu1, p.nu2 = int(levels), int(s), int(nu1), int(nu2)
     p.cycle_prec, p.max_rhs, p.restart = int(cycle_prec), int(max_rhs), int(restart)
+    p.tail_max, p.fuse_max, p.graphs = int(tail_max), int(fuse_max), int(graphs)
     return p
 
 

@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -78,6 +79,8 @@ void carve(csg_operator &op, const int nint[CSG_MAX_LEVELS][3], Carver &cv)
         lv.r = cv.take(vb);
         lv.u[0] = nullptr;
         for (int i = 1; i <= CSG_MAX_S; ++i) lv.u[i] = i <= p.s ? cv.take(vb) : nullptr;
+        lv.w[0] = cv.take(vb);
+        lv.w[1] = cv.take(vb);
         for (int k = 0; k < 2; ++k) lv.part[k] = (zc *)cv.take((size_t)R * NVAL * NBMAX * sizeof(zc));
         lv.gs = (GState *)cv.take((size_t)R * sizeof(GState));
     }
@@ -88,6 +91,7 @@ void carve(csg_operator &op, const int nint[CSG_MAX_LEVELS][3], Carver &cv)
     const DevLevel &c = op.lev[op.L - 1];
     op.nc = (int)c.N;
     op.minvT = cv.take((size_t)op.nc * op.nc * cz);
+    op.tlev = cv.take((size_t)op.L * sizeof(TLev<double>));
     const size_t n0 = (size_t)R * f.N;
     op.V = (zc *)cv.take((size_t)(p.restart + 1) * n0 * sizeof(zc));
     op.Z = cv.take((size_t)p.restart * n0 * cz);
@@ -175,7 +179,10 @@ struct Bytes {
     int R;         // right-hand sides
     double st(int j, double N) const { return R * (j + 2) * z * N + p * N; }
     double orth(int j, double N) const { return R * (j + 3) * z * N; }
+    // fused pass j+1: reads w_j, u_0..u_j, phi; writes u_{j+1}, w_{j+1}
+    double os(int j, double N) const { return R * (j + 4) * z * N + p * N; }
     double upd(int k, bool acc, double N) const { return R * (k + 1 + (acc ? 1 : 0)) * z * N; }
+    double upd_r(int s, bool acc, double N) const { return R * (s + 1 + (acc ? 1 : 0) + 2) * z * N; }
     double upd_res(int s, bool acc, double N, double Nc) const
     {
         return R * ((s + 2 + (acc ? 1 : 0)) * z * N + z * Nc);
@@ -203,8 +210,9 @@ double vcycle_bytes(const csg_operator *op, int nrhs)
     double tot = b.coarse(op->nc);
     for (int l = 0; l + 1 < op->L; ++l) {
         const double N = op->lev[l].N, Nc = op->lev[l + 1].N;
-        double steps = 0;
-        for (int j = 0; j < s; ++j) steps += b.st(j, N) + b.orth(j, N);
+        // Arnoldi passes of one sweep: pass 0, fused passes, last Gram-Schmidt pass
+        double steps = b.st(0, N) + b.orth(s - 1, N);
+        for (int j = 0; j + 1 < s; ++j) steps += b.os(j, N);
         if (nu1 == 0) tot += b.restrict_b(N, Nc);
         for (int k = 0; k < nu1; ++k) {
             tot += (k ? b.resid(N) : 0) + steps;
@@ -220,10 +228,55 @@ double vcycle_bytes(const csg_operator *op, int nrhs)
     return tot;
 }
 
-// One GMRES(s) sweep on level l: Arnoldi steps on u_0 (= b when x == 0, else
-// the residual in lv.r), then the closing pass.  `close` selects the plain
-// update (x (+)= V y) or the update fused with the restriction of the
-// Arnoldi residual to level l+1.
+// Arnoldi passes of one GMRES(s) sweep on level l with u_0 = B.u[0]: pass 0,
+// s-1 fused Gram-Schmidt + stencil passes, the last Gram-Schmidt pass.  The
+// partials of pass k go to part[k % 2]; the closing pass reads part[s % 2].
+template <typename T, int DIM>
+void arnoldi_passes(const csg_operator *op, int l, const Basis<T> &B, int nrhs, hipStream_t st, const int *active)
+{
+    const DevLevel &lv = op->lev[l];
+    const int s = op->p.s;
+    const LvlK<T> L = lvl<T>(op, l);
+    const Launch g = lch(op, l, nrhs, st);
+    const double tiny = tiny_of<T>();
+    const Bytes by = bytes_of(op, nrhs);
+    Cx<T> *W[2] = {(Cx<T> *)lv.w[0], (Cx<T> *)lv.w[1]};
+    if (lv.N > op->fuse_max) {
+        // large level: stencil pass then Gram-Schmidt pass per step (fewer loads per point)
+        for (int j = 0; j < s; ++j) {
+            {
+                ProfScope ps(op, l == 0 ? CSG_PROF_STENCIL_DOTS : -1, st, by.st(j, lv.N));
+                launch_stj<T, DIM>(L, B, W[j & 1], j, s, lv.ld, lv.part[0], g, active);
+            }
+            ProfScope ps(op, l == 0 ? CSG_PROF_ORTH : -1, st, by.orth(j, lv.N));
+            launch_orthl<T>(B, W[j & 1], j, s, lv.N, lv.ld, lv.part[0], lv.nb, lv.part[1], lv.gs, tiny, g, active);
+        }
+        return;
+    }
+    {
+        ProfScope ps(op, l == 0 ? CSG_PROF_STENCIL_DOTS : -1, st, by.st(0, lv.N));
+        launch_st0<T, DIM>(L, B.u[0], W[0], lv.ld, lv.part[0], g, active);
+    }
+    for (int j = 0; j + 1 < s; ++j) {
+        ProfScope ps(op, l == 0 ? CSG_PROF_STENCIL_DOTS : -1, st, by.os(j, lv.N));
+        launch_os<T, DIM>(L, B, W[j & 1], W[(j + 1) & 1], j, s, lv.ld, lv.part[j & 1], lv.nb, lv.part[(j + 1) & 1],
+                          lv.gs, tiny, g, active);
+    }
+    ProfScope ps(op, l == 0 ? CSG_PROF_ORTH : -1, st, by.orth(s - 1, lv.N));
+    launch_orthl<T>(B, W[(s - 1) & 1], s - 1, s, lv.N, lv.ld, lv.part[(s - 1) & 1], lv.nb, lv.part[s & 1], lv.gs,
+                    tiny, g, active);
+}
+
+// Partials buffer the closing pass of a sweep on level l reads.
+zc *close_part(const csg_operator *op, int l)
+{
+    const DevLevel &lv = op->lev[l];
+    return lv.N > op->fuse_max ? lv.part[1] : lv.part[op->p.s & 1];
+}
+
+// One GMRES(s) sweep on level l: Arnoldi passes on u_0 (= b when x == 0, else
+// the residual in lv.r), then the closing pass: the plain update
+// (x (+)= V y) or, before the restriction, the update plus the Arnoldi residual.
 template <typename T, int DIM>
 void sweep(const csg_operator *op, int l, const Cx<T> *b, Cx<T> *x, bool from_zero, bool restrict_after, int nrhs,
            hipStream_t st, const int *active)
@@ -241,24 +294,22 @@ void sweep(const csg_operator *op, int l, const Cx<T> *b, Cx<T> *x, bool from_ze
         launch_resid<T, DIM>(L, x, b, (Cx<T> *)lv.r, lv.ld, g, active);
         B.u[0] = (Cx<T> *)lv.r;
     }
+    arnoldi_passes<T, DIM>(op, l, B, nrhs, st, active);
     const Bytes by = bytes_of(op, nrhs);
     const int k0 = l == 0 ? 0 : -1;   // instrumented kinds exist for the finest level only
-    for (int j = 0; j < s; ++j) {
-        {
-            ProfScope ps(op, k0 ? -1 : CSG_PROF_STENCIL_DOTS, st, by.st(j, lv.N));
-            launch_st<T, DIM>(L, B, j, lv.ld, lv.part[1], lv.nb, lv.part[0], lv.gs, tiny, g, active);
-        }
-        ProfScope ps(op, k0 ? -1 : CSG_PROF_ORTH, st, by.orth(j, lv.N));
-        launch_orth<T>(B, j, s, lv.N, lv.ld, lv.part[0], lv.nb, lv.part[1], lv.gs, g, active);
-    }
+    zc *pclose = close_part(op, l);
     if (restrict_after) {
+        // closing update writes x and the Arnoldi residual r; full weighting of r
         const DevLevel &cl = op->lev[l + 1];
-        ProfScope ps(op, k0 ? -1 : CSG_PROF_UPD_RESTRICT, st, by.upd_res(s, !from_zero, lv.N, cl.N));
-        launch_upd_res<T, DIM>(x, from_zero ? 0 : 1, B, s, L, lvl<T>(op, l + 1), (Cx<T> *)cl.b, lv.ld, cl.ld,
-                               lv.part[1], lv.nb, lv.gs, tiny, lch(op, l + 1, nrhs, st), active);
+        ProfScope ps(op, k0 ? -1 : CSG_PROF_UPD_RESTRICT, st,
+                     by.upd_r(s, !from_zero, lv.N) + by.restrict_b(lv.N, cl.N));
+        launch_upd_r<T>(x, from_zero ? 0 : 1, (Cx<T> *)lv.r, B, s, lv.N, lv.ld, pclose, lv.nb, lv.gs, tiny, g,
+                        active);
+        launch_restrict<T, DIM>(L, lvl<T>(op, l + 1), nullptr, (const Cx<T> *)lv.r, (Cx<T> *)cl.b, lv.ld, cl.ld,
+                                lch(op, l + 1, nrhs, st), active);
     } else {
         ProfScope ps(op, k0 ? -1 : CSG_PROF_UPDATE, st, by.upd(s, !from_zero, lv.N));
-        launch_upd<T>(x, from_zero ? 0 : 1, B, s, lv.N, lv.ld, lv.part[1], lv.nb, lv.gs, tiny, g, active);
+        launch_upd<T>(x, from_zero ? 0 : 1, B, s, lv.N, lv.ld, pclose, lv.nb, lv.gs, tiny, g, active);
     }
 }
 
@@ -267,12 +318,9 @@ template <typename T, int DIM>
 void vcycle_impl(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, hipStream_t st, const int *active)
 {
     const int L = op->L;
+    const int lt = op->lt;
     const int nu1 = op->p.nu1, nu2 = op->p.nu2;
-    if (L == 1) {
-        launch_coarse<T>((const Cx<T> *)op->minvT, op->nc, b0, x0, op->lev[0].ld, nrhs, st, active);
-        return;
-    }
-    for (int l = 0; l < L - 1; ++l) {
+    for (int l = 0; l < lt; ++l) {
         const DevLevel &lv = op->lev[l];
         const DevLevel &cl = op->lev[l + 1];
         const Cx<T> *b = l == 0 ? b0 : (const Cx<T> *)lv.b;
@@ -285,10 +333,13 @@ void vcycle_impl(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, h
         }
     }
     {
-        const DevLevel &c = op->lev[L - 1];
-        launch_coarse<T>((const Cx<T> *)op->minvT, op->nc, (const Cx<T> *)c.b, (Cx<T> *)c.xb, c.ld, nrhs, st, active);
+        // levels lt..L-1 (coarsest solve included) in one workgroup per RHS
+        const Cx<T> *bt = lt == 0 ? b0 : (const Cx<T> *)op->lev[lt].b;
+        Cx<T> *xt = lt == 0 ? x0 : (Cx<T> *)op->lev[lt].xb;
+        launch_tail<T, DIM>((const TLev<T> *)op->tlev, lt, L, bt, xt, (const Cx<T> *)op->minvT, op->nc, op->p.s, nu1,
+                            nu2, tiny_of<T>(), nrhs, st, active);
     }
-    for (int l = L - 2; l >= 0; --l) {
+    for (int l = lt - 1; l >= 0; --l) {
         const DevLevel &lv = op->lev[l];
         const DevLevel &cl = op->lev[l + 1];
         const Cx<T> *b = l == 0 ? b0 : (const Cx<T> *)lv.b;
@@ -300,10 +351,13 @@ void vcycle_impl(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, h
                                    active);
         } else {
             {
+                // interpolated correction, then the residual that opens the post-sweep
+                const Bytes by = bytes_of(op, nrhs);
                 ProfScope ps(op, l == 0 ? CSG_PROF_PROLONG_RESID : -1, st,
-                             bytes_of(op, nrhs).prc(xi != nullptr, lv.N, cl.N));
-                launch_prc<T, DIM>(lvl<T>(op, l), lvl<T>(op, l + 1), (const Cx<T> *)cl.xb, xi, xo, b,
-                                   (Cx<T> *)lv.r, lv.ld, cl.ld, g, active);
+                             by.prolong(xi != nullptr, lv.N, cl.N) + by.resid(lv.N));
+                launch_prolong<T, DIM>(lvl<T>(op, l), lvl<T>(op, l + 1), (const Cx<T> *)cl.xb, xi, xo, lv.ld, cl.ld,
+                                       g, active);
+                launch_resid<T, DIM>(lvl<T>(op, l), xo, b, (Cx<T> *)lv.r, lv.ld, g, active);
             }
             for (int k = 0; k < nu2; ++k) {
                 // the first post-sweep starts from the residual already in lv.r
@@ -315,17 +369,9 @@ void vcycle_impl(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, h
                 for (int i = 0; i <= CSG_MAX_S; ++i) B.u[i] = (Cx<T> *)d.u[i];
                 if (k > 0) launch_resid<T, DIM>(Lk, xo, b, (Cx<T> *)d.r, d.ld, g, active);
                 B.u[0] = (Cx<T> *)d.r;
-                const Bytes by = bytes_of(op, nrhs);
-                for (int j = 0; j < s; ++j) {
-                    {
-                        ProfScope ps(op, l == 0 ? CSG_PROF_STENCIL_DOTS : -1, st, by.st(j, d.N));
-                        launch_st<T, DIM>(Lk, B, j, d.ld, d.part[1], d.nb, d.part[0], d.gs, tiny, g, active);
-                    }
-                    ProfScope ps(op, l == 0 ? CSG_PROF_ORTH : -1, st, by.orth(j, d.N));
-                    launch_orth<T>(B, j, s, d.N, d.ld, d.part[0], d.nb, d.part[1], d.gs, g, active);
-                }
-                ProfScope ps(op, l == 0 ? CSG_PROF_UPDATE : -1, st, by.upd(s, true, d.N));
-                launch_upd<T>(xo, 1, B, s, d.N, d.ld, d.part[1], d.nb, d.gs, tiny, g, active);
+                arnoldi_passes<T, DIM>(op, l, B, nrhs, st, active);
+                ProfScope ps(op, l == 0 ? CSG_PROF_UPDATE : -1, st, bytes_of(op, nrhs).upd(s, true, d.N));
+                launch_upd<T>(xo, 1, B, s, d.N, d.ld, close_part(op, l), d.nb, d.gs, tiny, g, active);
             }
         }
     }
@@ -404,37 +450,77 @@ void enqueue_begin(csg_solve *sv, bool with_chi_norm)
         launch_vnorm<double>(op->V, op->V, (zc *)nullptr, f.N, f.ld, op->fs, g, mask);
 }
 
+// One FGMRES iteration (section 5): z_j = V(v_j), w = H z_j, Gram-Schmidt
+// against v_0..v_j (second round on demand), Givens update, v_{j+1} = w / h.
+template <typename TZ, int DIM>
+void iter_body(csg_solve *sv, int j, hipStream_t st)
+{
+    csg_operator *op = sv->op;
+    const DevLevel &f = op->lev[0];
+    const size_t vstride = (size_t)op->p.max_rhs * f.N;
+    const Launch g = lch(op, 0, sv->nrhs, st);
+    const int *mask = op->active;
+    const void *b = op->p.cycle_prec ? op->b0 : (const void *)(op->V + j * vstride);
+    Cx<TZ> *z = (Cx<TZ> *)op->Z + j * vstride;
+    run_vcycle(op, b, z, sv->nrhs, st, mask);
+    const double N = f.N, R = sv->nrhs;
+    {
+        ProfScope ps(op, CSG_PROF_OUTER_H, st, R * N * (sizeof(Cx<TZ>) + 16.0 * (j + 2)) + 8.0 * N);
+        launch_hdot<TZ, DIM>(lvlH(op), z, op->w, op->V, vstride, j, f.ld, op->opart, g, mask);
+    }
+    launch_fin(FIN_H, op->opart, f.nb, j, op->fs, op->rep, sv->nrhs, st, mask);
+    {
+        ProfScope ps(op, CSG_PROF_OUTER_CGS1, st, R * N * 16.0 * (j + 3));
+        launch_proj(0, op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->opart, g, mask);
+    }
+    {
+        ProfScope ps(op, CSG_PROF_OUTER_CGS2, st, R * N * 16.0 * (j + 2));
+        launch_mdot(op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->opart, g, mask);
+    }
+    launch_fin(FIN_C, op->opart, f.nb, j, op->fs, op->rep, sv->nrhs, st, mask);
+    {
+        ProfScope ps(op, CSG_PROF_OUTER_PROJ2, st, R * N * 16.0 * (j + 3));
+        launch_proj(1, op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->opart, g, mask);
+    }
+    launch_fin(FIN_N, op->opart, f.nb, j, op->fs, op->rep, sv->nrhs, st, mask);
+    ProfScope ps(op, CSG_PROF_OUTER_NORM, st, R * N * (32.0 + (op->p.cycle_prec ? 8.0 : 0.0)));
+    launch_vnorm<TZ>(op->w, op->V + (j + 1) * vstride, op->p.cycle_prec ? (Cx<TZ> *)op->b0 : nullptr, f.N, f.ld,
+                     op->fs, g, mask);
+}
+
+// Replays the captured graph of column j (capturing it on first use); eager
+// launches when graphs are disabled or a pass is being instrumented.
 template <typename TZ, int DIM>
 void enqueue_iter(csg_solve *sv)
 {
     csg_operator *op = sv->op;
-    const DevLevel &f = op->lev[0];
+    GraphCache *gc = op->gc;
     const int j = sv->j;
-    const size_t vstride = (size_t)op->p.max_rhs * f.N;
-    const Launch g = lch(op, 0, sv->nrhs, sv->st);
-    const int *mask = op->active;
-    const void *b = op->p.cycle_prec ? op->b0 : (const void *)(op->V + j * vstride);
-    Cx<TZ> *z = (Cx<TZ> *)op->Z + j * vstride;
-    run_vcycle(op, b, z, sv->nrhs, sv->st, mask);
-    const double N = f.N, R = sv->nrhs;
-    {
-        ProfScope ps(op, CSG_PROF_OUTER_H, sv->st, R * N * (sizeof(Cx<TZ>) + 16.0 * (j + 2)) + 8.0 * N);
-        launch_hst<TZ, DIM>(lvlH(op), z, op->w, op->V, vstride, j, f.ld, op->opart, g, mask);
+    if (!gc || !gc->enabled || op->prof) {
+        iter_body<TZ, DIM>(sv, j, sv->st);
+        return;
     }
-    launch_fin(FIN_H, op->opart, f.nb, j, op->fs, op->rep, sv->nrhs, sv->st, mask);
-    {
-        ProfScope ps(op, CSG_PROF_OUTER_CGS1, sv->st, R * N * 16.0 * (j + 3));
-        launch_cgs1(op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->opart, g, mask);
+    std::vector<hipGraphExec_t> &v = gc->it[sv->nrhs];
+    if ((int)v.size() < op->p.restart) v.resize(op->p.restart, nullptr);
+    if (!v[j]) {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        bool ok = hipStreamBeginCapture(gc->cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            iter_body<TZ, DIM>(sv, j, gc->cap);
+            ok = hipStreamEndCapture(gc->cap, &graph) == hipSuccess && graph;
+        }
+        ok = ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+        if (graph) hipGraphDestroy(graph);
+        if (!ok) {
+            hipGetLastError();
+            gc->enabled = false;   // capture unsupported here: stay eager
+            iter_body<TZ, DIM>(sv, j, sv->st);
+            return;
+        }
+        v[j] = exec;
     }
-    launch_fin(FIN_C, op->opart, f.nb, j, op->fs, op->rep, sv->nrhs, sv->st, mask);
-    {
-        ProfScope ps(op, CSG_PROF_OUTER_CGS2, sv->st, R * N * 16.0 * (j + 3));
-        launch_cgs2(op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->opart, g, mask);
-    }
-    launch_fin(FIN_N, op->opart, f.nb, j, op->fs, op->rep, sv->nrhs, sv->st, mask);
-    ProfScope ps(op, CSG_PROF_OUTER_NORM, sv->st, R * N * (32.0 + (op->p.cycle_prec ? 8.0 : 0.0)));
-    launch_vnorm<TZ>(op->w, op->V + (j + 1) * vstride, op->p.cycle_prec ? (Cx<TZ> *)op->b0 : nullptr, f.N, f.ld,
-                     op->fs, g, mask);
+    hipGraphLaunch(v[j], sv->st);
 }
 
 template <typename TZ, int DIM>
@@ -670,6 +756,43 @@ int csg_operator_create(const csg_params *p, const double *phi_host, void *ws_de
         if (put_tab(hh.tabH[a], hh.lev[0].nu[a], op->tabH[a], true) != hipSuccess) rc = CSG_EDEVICE;
         hipStreamSynchronize(s);
     }
+    {
+        // the coarse tail starts at the first level small enough for one workgroup
+        // execution tuning: parameter, else environment (experiments), else default
+        long tail_max = 1200;
+        if (const char *e = getenv("CSG_TAIL_MAX")) tail_max = atol(e);
+        if (p->tail_max) tail_max = p->tail_max < 0 ? 0 : p->tail_max;
+        op->fuse_max = 100000;
+        if (const char *e = getenv("CSG_FUSE_MAX")) op->fuse_max = atol(e);
+        if (p->fuse_max) op->fuse_max = p->fuse_max < 0 ? 0 : p->fuse_max;
+        op->lt = op->L - 1;
+        for (int l = 0; l < op->L; ++l)
+            if ((long)op->lev[l].N <= tail_max) { op->lt = l; break; }
+        std::vector<TLev<double>> tl(op->L);
+        for (int l = 0; l < op->L; ++l) {
+            const DevLevel &d = op->lev[l];
+            TLev<double> &t = tl[l];
+            for (int a = 0; a < 3; ++a) t.tab[a] = (const zc *)d.tab[a];
+            t.phi = (const double *)d.phi;
+            t.b = (zc *)d.b;
+            t.xa = (zc *)d.xa;
+            t.xb = (zc *)d.xb;
+            t.r = (zc *)d.r;
+            for (int q = 0; q <= CSG_MAX_S; ++q) t.u[q] = (zc *)d.u[q];
+            t.w[0] = (zc *)d.w[0];
+            t.w[1] = (zc *)d.w[1];
+            t.nx = d.nu[0];
+            t.ny = d.nu[1];
+            t.nz = d.nu[2];
+            t.N = d.N;
+            t.ld = d.ld;
+        }
+        // the descriptor holds only pointers and sizes: identical layout for both precisions
+        if (rc == CSG_OK && hipMemcpyAsync(op->tlev, tl.data(), tl.size() * sizeof(TLev<double>),
+                                           hipMemcpyHostToDevice, s) != hipSuccess)
+            rc = CSG_EDEVICE;
+        hipStreamSynchronize(s);
+    }
     if (rc == CSG_OK) {
         if (hipMemcpyAsync((void *)op->phiH, hh.lev[0].phi.data(), hh.lev[0].N * sizeof(double),
                            hipMemcpyHostToDevice, s) != hipSuccess)
@@ -698,10 +821,18 @@ int csg_operator_create(const csg_params *p, const double *phi_host, void *ws_de
         if (hipHostMalloc((void **)&op->rep_host, p->max_rhs * sizeof(Report), hipHostMallocDefault) != hipSuccess)
             rc = CSG_EDEVICE;
         if (hipEventCreateWithFlags(&op->ev, hipEventDisableTiming) != hipSuccess) rc = CSG_EDEVICE;
+        op->gc = new GraphCache;
+        if (const char *e = getenv("CSG_GRAPHS")) op->gc->enabled = atoi(e) != 0;
+        if (p->graphs) op->gc->enabled = p->graphs > 0;
+        if (hipStreamCreateWithFlags(&op->gc->cap, hipStreamNonBlocking) != hipSuccess) rc = CSG_EDEVICE;
     }
     if (rc != CSG_OK) {
         hipError_t e = hipGetLastError();
         if (op->rep_host) hipHostFree(op->rep_host);
+        if (op->gc) {
+            if (op->gc->cap) hipStreamDestroy(op->gc->cap);
+            delete op->gc;
+        }
         delete op;
         return fail(rc, std::string("device setup failed: ") + hipGetErrorString(e));
     }
@@ -761,6 +892,14 @@ int csg_operator_destroy(csg_operator *op)
 {
     if (!op) return CSG_OK;
     if (op->prof) csg_profile(op, CSG_PROF_OFF, 0);
+    if (op->gc) {
+        hipDeviceSynchronize();
+        for (auto &kv : op->gc->it)
+            for (hipGraphExec_t g : kv.second)
+                if (g) hipGraphExecDestroy(g);
+        if (op->gc->cap) hipStreamDestroy(op->gc->cap);
+        delete op->gc;
+    }
     if (op->ev) hipEventDestroy(op->ev);
     if (op->rep_host) hipHostFree(op->rep_host);
     delete op;

@@ -5,6 +5,7 @@
 
 #include <complex>
 #include <cstddef>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -15,8 +16,8 @@ namespace csg {
 
 using cd = std::complex<double>;
 
-constexpr int BLK = 256;                    // threads per block of every level pass
-constexpr int NBMAX = 512;                  // max blocks of a reducing pass (partials per value)
+constexpr int BLK = 512;                    // threads per block of every level pass
+constexpr int NBMAX = 256;                  // max blocks of a reducing pass (partials per value)
 constexpr int NVAL = CSG_MAX_S + 2;         // partial values per smoother pass
 constexpr int OVAL = CSG_MAX_RESTART + 1;   // partial values per outer pass
 constexpr int MAXC = 4096;                  // max coarsest unknowns
@@ -99,10 +100,19 @@ struct DevLevel {
     const void *phi;           // cycle-precision real phi
     void *b, *xa, *xb, *r;     // cycle-precision vectors [max_rhs][ld]
     void *u[CSG_MAX_S + 1];    // u[1..s]; u[0] aliases b or r
+    void *w[2];                // stencil outputs of the Arnoldi passes (ping-pong)
     zc *part[2];               // reduction partials [max_rhs][NVAL][NBMAX]
     GState *gs;                // [max_rhs]
     int nb;                    // blocks of a reducing pass
     unsigned chunk;            // points per block of a reducing pass
+};
+
+// Instantiated graphs of one FGMRES iteration (V-cycle + outer passes), per
+// right-hand-side count and Arnoldi column, captured on a private stream.
+struct GraphCache {
+    std::map<int, std::vector<hipGraphExec_t>> it;
+    hipStream_t cap = nullptr;
+    bool enabled = true;
 };
 
 // Event-pair instrumentation of one pass kind (benchmarks only).
@@ -125,6 +135,9 @@ struct csg_operator {
     const double *phiH;               // FP64 phi on the finest level
     const void *minvT;                // coarsest inverse (cycle precision), transposed
     int nc;
+    void *tlev;                       // device level descriptors of the coarse tail
+    int lt;                           // first level handled by the coarse-tail kernel
+    long fuse_max;                    // levels up to this size use the fused Arnoldi passes
     // outer FGMRES storage
     csg::zc *V;                       // (m+1) x max_rhs x ld0
     void *Z;                          // m x max_rhs x ld0, cycle precision
@@ -140,4 +153,5 @@ struct csg_operator {
     size_t ws_used;
     int busy;                         // a csg_solve is in flight
     csg::Prof *prof;                  // instrumentation, or null
+    csg::GraphCache *gc;              // captured FGMRES iterations
 };

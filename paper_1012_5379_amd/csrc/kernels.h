@@ -19,8 +19,17 @@ struct Basis {
     Cx<T> *u[CSG_MAX_S + 1];
 };
 
-// Up to OVAL pointers are too many for kernel arguments; the outer basis is
-// addressed as base + i * vstride instead.
+// Device-resident description of one level for the coarse-tail kernel.
+template <typename T>
+struct TLev {
+    const Cx<T> *tab[3];
+    const T *phi;
+    Cx<T> *b, *xa, *xb, *r;
+    Cx<T> *u[CSG_MAX_S + 1];
+    Cx<T> *w[2];
+    unsigned nx, ny, nz, N;
+    size_t ld;
+};
 
 struct Launch {
     int nb;            // blocks along x (reducing passes: <= NBMAX)
@@ -33,17 +42,32 @@ struct Launch {
 template <typename T, int DIM>
 void launch_apply(const LvlK<T> &L, const void *x, void *y, size_t ld, const Launch &g, const int *active);
 
+// GMRES(s) Arnoldi passes on the raw basis (see kernels.hip): pass 0, fused
+// Gram-Schmidt + stencil passes j = 0..s-2, and the last Gram-Schmidt pass.
 template <typename T, int DIM>
-void launch_st(const LvlK<T> &L, const Basis<T> &B, int j, size_t ld, const zc *pin, int nbin, zc *pout,
-               GState *gs, double tiny, const Launch &g, const int *active);
+void launch_st0(const LvlK<T> &L, const Cx<T> *u0, Cx<T> *w, size_t ld, zc *pout, const Launch &g, const int *active);
+
+// unfused pass: w = A u_j, <u_i, w> (i <= j) and ||u_j||^2
+template <typename T, int DIM>
+void launch_stj(const LvlK<T> &L, const Basis<T> &B, Cx<T> *w, int j, int s, size_t ld, zc *pout, const Launch &g,
+                const int *active);
+
+template <typename T, int DIM>
+void launch_os(const LvlK<T> &L, const Basis<T> &B, const Cx<T> *win, Cx<T> *wout, int j, int s, size_t ld,
+               const zc *pin, int nbin, zc *pout, GState *gs, double tiny, const Launch &g, const int *active);
 
 template <typename T>
-void launch_orth(const Basis<T> &B, int j, int s, unsigned N, size_t ld, const zc *pin, int nbin, zc *pout,
-                 GState *gs, const Launch &g, const int *active);
+void launch_orthl(const Basis<T> &B, const Cx<T> *win, int j, int s, unsigned N, size_t ld, const zc *pin, int nbin,
+                  zc *pout, GState *gs, double tiny, const Launch &g, const int *active);
 
 template <typename T>
 void launch_upd(Cx<T> *x, int accumulate, const Basis<T> &B, int s, unsigned N, size_t ld, const zc *pin,
                 int nbin, GState *gs, double tiny, const Launch &g, const int *active);
+
+// x (+)= V y and r = V (beta e1 - Hbar y) on the fine grid (closing pass of a sweep)
+template <typename T>
+void launch_upd_r(Cx<T> *x, int accumulate, Cx<T> *r, const Basis<T> &B, int s, unsigned N, size_t ld, const zc *pin,
+                  int nbin, GState *gs, double tiny, const Launch &g, const int *active);
 
 template <typename T, int DIM>
 void launch_upd_res(Cx<T> *x, int accumulate, const Basis<T> &B, int s, const LvlK<T> &F, const LvlK<T> &C,
@@ -70,15 +94,24 @@ template <typename T>
 void launch_coarse(const Cx<T> *minvT, int n, const Cx<T> *b, Cx<T> *x, size_t ld, int nrhs, hipStream_t st,
                    const int *active);
 
+// One workgroup per RHS runs levels lt..L-1 of the V-cycle (input b at level lt,
+// output x at level lt).
+template <typename T, int DIM>
+void launch_tail(const TLev<T> *lev, int lt, int L, const Cx<T> *b_in, Cx<T> *x_out, const Cx<T> *minvT, int nc,
+                 int s, int nu1, int nu2, double tiny, int nrhs, hipStream_t st, const int *active);
+
 // ---- outer FGMRES passes (FP64 arithmetic; TZ = cycle precision) ----------
+// w = H z and <v_i, w> (i <= j)
 template <typename TZ, int DIM>
-void launch_hst(const LvlK<double> &H, const Cx<TZ> *z, zc *w, const zc *V, size_t vstride, int j, size_t ld,
-                zc *pout, const Launch &g, const int *active);
+void launch_hdot(const LvlK<double> &H, const Cx<TZ> *z, zc *w, const zc *V, size_t vstride, int j, size_t ld,
+                 zc *pout, const Launch &g, const int *active);
 
-void launch_cgs1(zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, const FState *fs, zc *pout,
-                 const Launch &g, const int *active);
+// w -= V a (a = hcol for round 0, corr for round 1; round 1 also ||w||^2)
+void launch_proj(int round, zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, const FState *fs,
+                 zc *pout, const Launch &g, const int *active);
 
-void launch_cgs2(zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, const FState *fs, zc *pout,
+// second-round <v_i, w>
+void launch_mdot(const zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, const FState *fs, zc *pout,
                  const Launch &g, const int *active);
 
 // v = w * scale (scale = fs->inv_hn), optional cycle-precision copy (cast).

@@ -70,11 +70,12 @@ __device__ __forceinline__ Cx<T> apply_pt(const LvlK<T> &L, const Cx<TI> *__rest
     return acc;
 }
 
-// Wavefront (64 lanes) butterfly, then the 4 wavefronts in order.  Every lane
-// ends with bit-identical sums (pairwise additions are commutative).
+// Wavefront (64 lanes) butterfly, then the BLK/64 wavefronts in order.  Every
+// lane ends with bit-identical sums (pairwise additions are commutative).
 template <int NV>
 __device__ __forceinline__ void block_sum(zc (&v)[NV], int nv, zc *sh, zc *res)
 {
+    constexpr int NW = BLK / 64;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
@@ -95,9 +96,8 @@ __device__ __forceinline__ void block_sum(zc (&v)[NV], int nv, zc *sh, zc *res)
     if (threadIdx.x < nv) {
         const int q = threadIdx.x;
         zc a = sh[q];
-        a = a + sh[NV + q];
-        a = a + sh[2 * NV + q];
-        a = a + sh[3 * NV + q];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) a = a + sh[w * NV + q];
         res[q] = a;
     }
     __syncthreads();
@@ -179,197 +179,258 @@ __device__ int gmres_ls(const GState *gs, int s, double hn_last, zc *R, zc *y, z
 }
 
 // ---------------------------------------------------------------------------
-// operator application
+// pass bodies: one loop over a range of points, shared by the multi-block
+// passes (range = one block's chunk) and the single-workgroup coarse tail
+// (range = the whole level)
 // ---------------------------------------------------------------------------
 
-template <typename T, int DIM>
-__global__ __launch_bounds__(BLK) void k_apply(LvlK<T> L, const Cx<T> *__restrict__ x, Cx<T> *__restrict__ y,
-                                               size_t ld, unsigned chunk, int nb, const int *active)
+template <typename T>
+__device__ __forceinline__ Cx<T> *pick(const Basis<T> &B, int j)
 {
-    const int rhs = blockIdx.y;
-    if (!active[rhs]) return;
-    x += rhs * ld;
-    y += rhs * ld;
-    const unsigned c = chunk_id(nb);
-    const unsigned p0 = c * chunk, p1 = min(L.N, p0 + chunk);
-    for (unsigned p = p0 + threadIdx.x; p < p1; p += BLK) {
+    Cx<T> *r = B.u[0];
+#pragma unroll
+    for (int q = 1; q <= CSG_MAX_S; ++q)
+        if (q == j) r = B.u[q];
+    return r;
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ void body_apply(const LvlK<T> &L, const Cx<T> *x, Cx<T> *y, unsigned p0, unsigned p1,
+                                           unsigned st)
+{
+    for (unsigned p = p0; p < p1; p += st) {
         unsigned i, j, k;
         decomp<DIM>(p, L.nx, L.ny, i, j, k);
         y[p] = apply_pt<T, DIM>(L, x, i, j, k, p);
     }
 }
 
-// ---------------------------------------------------------------------------
-// GMRES(s) sweep passes
-// ---------------------------------------------------------------------------
+// Points a thread handles per iteration: their loads are issued together
+// (indices clamped to the last point of the range, stores masked), so each
+// iteration pays one memory latency for U points.
+template <typename T>
+struct Ubatch {
+    static constexpr int U = sizeof(T) == 8 ? 2 : 4;
+};
 
-// Arnoldi step j, first half: w = A u_j (raw basis vector) and the inner
-// products <u_i, w>, i <= j (plus <u_0, u_0> when j = 0).  Block 0 first
-// finishes the previous step's norm: h_{j,j-1} and the scale of u_j.
+// Arnoldi bookkeeping on the raw (unnormalised) basis u_0..u_s of one sweep,
+// v_i = sig_i u_i: pass 0 forms w_0 = A u_0; pass j+1 (j < s-1) forms
+// u_{j+1} = sig_j w_j - sum_{i<=j} sig_i h_ij u_i (classical Gram-Schmidt) and,
+// in the same sweep over the grid, w_{j+1} = A u_{j+1} with u_{j+1} recomputed at
+// the stencil neighbours; the last pass forms u_s only.  Every pass emits the
+// partial sums <u_i, w> (i up to its newest vector) and ||newest u||^2.
+
+// pass 0: w = A u_0, acc[0] += <u_0, w>, acc[1] += ||u_0||^2
 template <typename T, int DIM>
-__global__ __launch_bounds__(BLK) void k_st(LvlK<T> L, Basis<T> B, int j, size_t ld, const zc *__restrict__ pin,
-                                            int nbin, zc *__restrict__ pout, GState *gsb, double tiny,
-                                            unsigned chunk, int nb, const int *active)
+__device__ __forceinline__ void body_st0(const LvlK<T> &L, const Cx<T> *u0, Cx<T> *w, unsigned p0, unsigned p1,
+                                         unsigned st, zc (&acc)[2])
 {
-    __shared__ zc sh[4 * NVAL];
-    __shared__ zc res[NVAL];
-    const int rhs = blockIdx.y;
-    if (!active[rhs]) return;
-    GState *gs = gsb + rhs;
-    if (j >= 1 && blockIdx.x == 0) {
-        reduce_parts<1>(pin + (size_t)rhs * NVAL * NBMAX, nbin, 1, sh, res);
-        if (threadIdx.x == 0) {
-            const double hn = sqrt(res[0].re);
-            const bool brk = !(hn > tiny * gs->beta0);
-            gs->H[j * CSG_MAX_S + (j - 1)] = mkc(hn, 0.0);
-            gs->sig[j] = brk ? 0.0 : 1.0 / hn;
-            if (brk && gs->k > j) gs->k = j;
+    constexpr int U = Ubatch<T>::U;
+    if (p0 >= p1) return;
+    const unsigned last = p1 - 1;
+    for (unsigned p = p0; p < p1; p += U * st) {
+        Cx<T> wv[U], uc[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const unsigned pk = min(p + k * st, last);
+            unsigned i, jj, kk;
+            decomp<DIM>(pk, L.nx, L.ny, i, jj, kk);
+            wv[k] = apply_pt<T, DIM>(L, u0, i, jj, kk, pk);
+            uc[k] = u0[pk];
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            if (p + k * st >= p1) break;
+            w[p + k * st] = wv[k];
+            const zc wd = cvt<double>(wv[k]), ud = cvt<double>(uc[k]);
+            acc[0] = cjfma(ud, wd, acc[0]);
+            acc[1].re += cabs2(ud);
         }
     }
-    const size_t off = rhs * ld;
-    const Cx<T> *uj = B.u[j] + off;
-    Cx<T> *w = B.u[j + 1] + off;
-    const int nv = j + 1 + (j == 0);
-    zc acc[NVAL];
+}
+
+// unfused pass 2j: w_j = A u_j, acc[i] += <u_i, w_j> (i <= j), acc[j+1] += ||u_j||^2
+template <typename T, int DIM, int SB>
+__device__ __forceinline__ void body_stj(const LvlK<T> &L, const Basis<T> &B, Cx<T> *w, int j, size_t off,
+                                         unsigned p0, unsigned p1, unsigned st, zc (&acc)[SB])
+{
+    constexpr int U = Ubatch<T>::U;
+    const Cx<T> *uj = pick(B, j) + off;
+    Cx<T> *wo = w + off;
+    if (p0 >= p1) return;
+    const unsigned last = p1 - 1;
+    for (unsigned p = p0; p < p1; p += U * st) {
+        Cx<T> wv[U], uq[U][SB - 1];
 #pragma unroll
-    for (int q = 0; q < NVAL; ++q) acc[q] = mkc(0.0, 0.0);
-    const unsigned c = chunk_id(nb);
-    const unsigned p0 = c * chunk, p1 = min(L.N, p0 + chunk);
-    for (unsigned p = p0 + threadIdx.x; p < p1; p += BLK) {
+        for (int k = 0; k < U; ++k) {
+            const unsigned pk = min(p + k * st, last);
+            unsigned i, jj, kk;
+            decomp<DIM>(pk, L.nx, L.ny, i, jj, kk);
+            wv[k] = apply_pt<T, DIM>(L, uj, i, jj, kk, pk);
+#pragma unroll
+            for (int q = 0; q < SB - 1; ++q)
+                if (q <= j) uq[k][q] = B.u[q][off + pk];
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            if (p + k * st >= p1) break;
+            wo[p + k * st] = wv[k];
+            const zc wd = cvt<double>(wv[k]);
+#pragma unroll
+            for (int q = 0; q < SB - 1; ++q) {
+                if (q <= j) acc[q] = cjfma(cvt<double>(uq[k][q]), wd, acc[q]);
+                if (q == j) acc[q + 1].re += cabs2(cvt<double>(uq[k][q]));
+            }
+        }
+    }
+}
+
+// u_{j+1}(q) = sj w_j(q) - sum_{i<=j} cu_i u_i(q)
+template <typename T, int SB>
+__device__ __forceinline__ Cx<T> next_u(const Basis<T> &B, const Cx<T> *win, int j, T sj, const Cx<T> (&cu)[SB],
+                                        size_t off, unsigned q)
+{
+    Cx<T> v = sj * win[q];
+#pragma unroll
+    for (int i = 0; i < SB - 1; ++i)
+        if (i <= j) v = v - cu[i] * B.u[i][off + q];
+    return v;
+}
+
+// pass j+1: u_{j+1} (written to B.u[j+1]), w_{j+1} = A u_{j+1} (written to wout),
+// acc[i] += <u_i, w_{j+1}> for i <= j+1, acc[j+2] += ||u_{j+1}||^2
+template <typename T, int DIM, int SB>
+__device__ __forceinline__ void body_os(const LvlK<T> &L, const Basis<T> &B, const Cx<T> *win, Cx<T> *wout, int j,
+                                        T sj, const Cx<T> (&cu)[SB], size_t off, unsigned p0, unsigned p1,
+                                        unsigned st, zc (&acc)[SB])
+{
+    Cx<T> *un = pick(B, j + 1) + off;
+    const Cx<T> *wi = win + off;
+    Cx<T> *wo = wout + off;
+    for (unsigned p = p0; p < p1; p += st) {
         unsigned i, jj, k;
         decomp<DIM>(p, L.nx, L.ny, i, jj, k);
-        const Cx<T> wv = apply_pt<T, DIM>(L, uj, i, jj, k, p);
-        w[p] = wv;
-        const zc wd = cvt<double>(wv);
+        Cx<T> uq[SB - 1];
+        Cx<T> uc = sj * wi[p];
 #pragma unroll
-        for (int q = 0; q < NVAL - 1; ++q)
-            if (q <= j) acc[q] = cjfma(cvt<double>(B.u[q][off + p]), wd, acc[q]);
-        if (j == 0) acc[1].re += cabs2(cvt<double>(uj[p]));
-    }
-    block_sum<NVAL>(acc, nv, sh, res);
-    if (threadIdx.x < nv) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + c] = res[threadIdx.x];
-}
-
-// Arnoldi step j, second half: h_ij = sig_i sig_j <u_i, w>, then
-// u_{j+1} = sig_j w - sum_i h_ij sig_i u_i (classical Gram-Schmidt) and the
-// partial ||u_{j+1}||^2.
-template <typename T>
-__global__ __launch_bounds__(BLK) void k_orth(Basis<T> B, int j, unsigned N, size_t ld, const zc *__restrict__ pin,
-                                              int nbin, zc *__restrict__ pout, GState *gsb, unsigned chunk, int nb,
-                                              int s, const int *active)
-{
-    __shared__ zc sh[4 * NVAL];
-    __shared__ zc res[NVAL];
-    const int rhs = blockIdx.y;
-    if (!active[rhs]) return;
-    GState *gs = gsb + rhs;
-    const int nv = j + 1 + (j == 0);
-    reduce_parts<NVAL>(pin + (size_t)rhs * NVAL * NBMAX, nbin, nv, sh, res);
-    double sig[NVAL];
-    double beta0;
-    if (j == 0) {
-        beta0 = sqrt(res[1].re);
-        sig[0] = beta0 > 0.0 ? 1.0 / beta0 : 0.0;
-    } else {
-        beta0 = gs->beta0;
+        for (int q = 0; q < SB - 1; ++q)
+            if (q <= j) {
+                uq[q] = B.u[q][off + p];
+                uc = uc - cu[q] * uq[q];
+            }
+        const Cx<T> *tx = L.tab[0];
+        Cx<T> d = tx[L.nx + i];
+        if (DIM >= 2) d = d + L.tab[1][L.ny + jj];
+        if (DIM == 3) d = d + L.tab[2][L.nz + k];
+        d.re -= L.phi[p];
+        Cx<T> a = d * uc;
+        if (i) a = cfma(tx[i], next_u<T, SB>(B, wi, j, sj, cu, off, p - 1), a);
+        if (i + 1 < L.nx) a = cfma(tx[2 * L.nx + i], next_u<T, SB>(B, wi, j, sj, cu, off, p + 1), a);
+        if (DIM >= 2) {
+            const Cx<T> *ty = L.tab[1];
+            if (jj) a = cfma(ty[jj], next_u<T, SB>(B, wi, j, sj, cu, off, p - L.nx), a);
+            if (jj + 1 < L.ny) a = cfma(ty[2 * L.ny + jj], next_u<T, SB>(B, wi, j, sj, cu, off, p + L.nx), a);
+        }
+        if (DIM == 3) {
+            const Cx<T> *tz = L.tab[2];
+            const unsigned sz = L.nx * L.ny;
+            if (k) a = cfma(tz[k], next_u<T, SB>(B, wi, j, sj, cu, off, p - sz), a);
+            if (k + 1 < L.nz) a = cfma(tz[2 * L.nz + k], next_u<T, SB>(B, wi, j, sj, cu, off, p + sz), a);
+        }
+        un[p] = uc;
+        wo[p] = a;
+        const zc wd = cvt<double>(a), ud = cvt<double>(uc);
 #pragma unroll
-        for (int q = 0; q < NVAL; ++q)
-            if (q <= j) sig[q] = gs->sig[q];
-    }
-    double sj = 0.0;
+        for (int q = 0; q < SB - 1; ++q)
+            if (q <= j) acc[q] = cjfma(cvt<double>(uq[q]), wd, acc[q]);
 #pragma unroll
-    for (int q = 0; q < NVAL; ++q)
-        if (q == j) sj = sig[q];
-    zc h[NVAL];
-    Cx<T> cu[NVAL];
-#pragma unroll
-    for (int q = 0; q < NVAL; ++q) {
-        if (q <= j) {
-            h[q] = (sig[q] * sj) * res[q];
-            cu[q] = cvt<T>(sig[q] * h[q]);
+        for (int q = 1; q < SB; ++q) {
+            if (q == j + 1) acc[q] = cjfma(ud, wd, acc[q]);
+            if (q == j + 2) acc[q].re += cabs2(ud);
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        if (j == 0) {
-            gs->beta0 = beta0;
-            gs->sig[0] = sig[0];
-            gs->k = s;
-        }
-#pragma unroll
-        for (int q = 0; q < NVAL; ++q)
-            if (q <= j) gs->H[q * CSG_MAX_S + j] = h[q];
-    }
-    const size_t off = rhs * ld;
-    Cx<T> *w = B.u[j + 1] + off;
-    const T aw = (T)sj;
-    zc acc[1] = {mkc(0.0, 0.0)};
-    const unsigned c = chunk_id(nb);
-    const unsigned p0 = c * chunk, p1 = min(N, p0 + chunk);
-    for (unsigned p = p0 + threadIdx.x; p < p1; p += BLK) {
-        Cx<T> v = aw * w[p];
-#pragma unroll
-        for (int q = 0; q < NVAL - 1; ++q)
-            if (q <= j) v = v - cu[q] * B.u[q][off + p];
-        w[p] = v;
-        acc[0].re += cabs2(cvt<double>(v));
-    }
-    block_sum<1>(acc, 1, sh, res);
-    if (threadIdx.x == 0) pout[((size_t)rhs * NVAL) * NBMAX + c] = res[0];
 }
 
-// Shared prologue of the sweep's closing passes: finish h_{s,s-1}, solve the
-// small least-squares problem and publish coefficients in shared memory:
-// ax[i] = y_i sig_i (update), ar[i] = cres_i sig_i (Arnoldi residual).
-__device__ int close_sweep(const zc *pin, int nbin, GState *gs, int s, double tiny, zc *sh, zc *res, zc *ax, zc *ar)
+// last pass: u_s = sj w - sum_i cu_i u_i into B.u[j+1], nrm += ||u_s||^2
+template <typename T, int SB>
+__device__ __forceinline__ void body_orthl(const Basis<T> &B, const Cx<T> *win, int j, T sj, const Cx<T> (&cu)[SB],
+                                           size_t off, unsigned p0, unsigned p1, unsigned st, double &nrm)
 {
-    reduce_parts<1>(pin, nbin, 1, sh, res);
-    __shared__ int ks;
-    __shared__ zc Rs[(CSG_MAX_S + 1) * CSG_MAX_S], ys[CSG_MAX_S], crs[CSG_MAX_S + 1];
-    if (threadIdx.x == 0) {
-        const double hn = sqrt(res[0].re);
-        const bool brk = !(hn > tiny * gs->beta0);
-        const double sig_s = brk ? 0.0 : 1.0 / hn;
-        zc *y = ys, *cr = crs;
-        const int k = gmres_ls(gs, s, hn, Rs, y, cr);
-        for (int i = 0; i < k; ++i) ax[i] = gs->sig[i] * y[i];
-        for (int i = 0; i <= k; ++i) ar[i] = ((i == s) ? sig_s : gs->sig[i]) * cr[i];
-        ks = k;
-        if (blockIdx.x == 0) {
-            gs->H[s * CSG_MAX_S + (s - 1)] = mkc(hn, 0.0);
-            gs->sig[s] = sig_s;
-            for (int i = 0; i < k; ++i) gs->y[i] = y[i];
+    constexpr int U = Ubatch<T>::U;
+    Cx<T> *un = pick(B, j + 1) + off;
+    if (p0 >= p1) return;
+    const unsigned last = p1 - 1;
+    for (unsigned p = p0; p < p1; p += U * st) {
+        Cx<T> v[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) v[k] = next_u<T, SB>(B, win, j, sj, cu, off, min(p + k * st, last));
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            if (p + k * st >= p1) break;
+            un[p + k * st] = v[k];
+            nrm += cabs2(cvt<double>(v[k]));
         }
     }
-    __syncthreads();
-    return ks;
 }
 
-// x (+)= sum_i y_i sig_i u_i
-template <typename T>
-__global__ __launch_bounds__(BLK) void k_upd(Cx<T> *x, int accumulate, Basis<T> B, int s, unsigned N, size_t ld,
-                                             const zc *__restrict__ pin, int nbin, GState *gsb, double tiny,
-                                             unsigned chunk, int nb, const int *active)
+// x (+)= sum_{i<k} cx_i u_i
+template <typename T, int SB>
+__device__ __forceinline__ void body_upd(Cx<T> *x, int accumulate, const Basis<T> &B, int k,
+                                         const Cx<T> (&cx)[SB], size_t off, unsigned p0, unsigned p1,
+                                         unsigned st)
 {
-    __shared__ zc sh[4];
-    __shared__ zc res[1];
-    __shared__ zc ax[CSG_MAX_S], ar[CSG_MAX_S + 1];
-    const int rhs = blockIdx.y;
-    if (!active[rhs]) return;
-    const int k = close_sweep(pin + (size_t)rhs * NVAL * NBMAX, nbin, gsb + rhs, s, tiny, sh, res, ax, ar);
-    Cx<T> cx[CSG_MAX_S];
+    constexpr int U = Ubatch<T>::U;
+    if (p0 >= p1) return;
+    const unsigned last = p1 - 1;
+    for (unsigned p = p0; p < p1; p += U * st) {
+        Cx<T> v[U];
 #pragma unroll
-    for (int q = 0; q < CSG_MAX_S; ++q)
-        if (q < k) cx[q] = cvt<T>(ax[q]);
-    const size_t off = rhs * ld;
-    Cx<T> *xx = x + off;
-    const unsigned c = chunk_id(nb);
-    const unsigned p0 = c * chunk, p1 = min(N, p0 + chunk);
-    for (unsigned p = p0 + threadIdx.x; p < p1; p += BLK) {
-        Cx<T> v = accumulate ? xx[p] : mkc<T>(0, 0);
+        for (int kk = 0; kk < U; ++kk) {
+            const unsigned pk = min(p + kk * st, last);
+            v[kk] = accumulate ? x[pk] : mkc<T>(0, 0);
 #pragma unroll
-        for (int q = 0; q < CSG_MAX_S; ++q)
-            if (q < k) v = cfma(cx[q], B.u[q][off + p], v);
-        xx[p] = v;
+            for (int q = 0; q < SB - 1; ++q)
+                if (q < k) v[kk] = cfma(cx[q], B.u[q][off + pk], v[kk]);
+        }
+#pragma unroll
+        for (int kk = 0; kk < U; ++kk) {
+            if (p + kk * st >= p1) break;
+            x[p + kk * st] = v[kk];
+        }
+    }
+}
+
+// x (+)= sum_{i<k} cx_i u_i and r = sum_{i<=k} cr_i u_i (the Arnoldi residual
+// of the sweep), pointwise on the fine grid
+template <typename T, int SB>
+__device__ __forceinline__ void body_upd_r(Cx<T> *x, int accumulate, Cx<T> *r, const Basis<T> &B, int k,
+                                           const Cx<T> (&cx)[SB], const Cx<T> (&cr)[SB], size_t off, unsigned p0,
+                                           unsigned p1, unsigned st)
+{
+    constexpr int U = Ubatch<T>::U;
+    if (p0 >= p1) return;
+    const unsigned last = p1 - 1;
+    for (unsigned p = p0; p < p1; p += U * st) {
+        Cx<T> v[U], rr[U];
+#pragma unroll
+        for (int kk = 0; kk < U; ++kk) {
+            const unsigned pk = min(p + kk * st, last);
+            v[kk] = accumulate ? x[pk] : mkc<T>(0, 0);
+            rr[kk] = mkc<T>(0, 0);
+#pragma unroll
+            for (int q = 0; q < SB; ++q)
+                if (q <= k) {
+                    const Cx<T> u = B.u[q][off + pk];
+                    rr[kk] = cfma(cr[q], u, rr[kk]);
+                    if (q < k) v[kk] = cfma(cx[q], u, v[kk]);
+                }
+        }
+#pragma unroll
+        for (int kk = 0; kk < U; ++kk) {
+            if (p + kk * st >= p1) break;
+            x[p + kk * st] = v[kk];
+            r[p + kk * st] = rr[kk];
+        }
     }
 }
 
@@ -448,34 +509,17 @@ __device__ __forceinline__ RAx raxis(unsigned I, unsigned nuc, unsigned nuf)
 }
 __device__ __forceinline__ float rw(int q) { return q == 1 ? 1.f : 0.5f; }
 
-// Closing pass of the last pre-smoothing sweep fused with the restriction:
-// x (+)= sum y_i sig_i u_i on the fine grid, and
-// bc = 2^-d P^T r with the Arnoldi residual r = sum_i cres_i sig_i u_i.
-template <typename T, int DIM>
-__global__ __launch_bounds__(BLK) void k_upd_res(Cx<T> *x, int accumulate, Basis<T> B, int s, LvlK<T> F, LvlK<T> C,
-                                                 Cx<T> *bc, size_t ldf, size_t ldc, const zc *__restrict__ pin,
-                                                 int nbin, GState *gsb, double tiny, unsigned chunk, int nb,
-                                                 const int *active)
+// Closing pass of the last pre-smoothing sweep fused with the restriction, per
+// coarse point: x (+)= sum cx_i u_i on the fine points it owns, and
+// bc = 2^-d P^T r with the Arnoldi residual r = sum_i cr_i u_i.
+template <typename T, int DIM, int SB>
+__device__ __forceinline__ void body_upd_res(Cx<T> *xx, int accumulate, const Basis<T> &B, int k,
+                                             const Cx<T> (&cx)[SB], const Cx<T> (&cr)[SB],
+                                             const LvlK<T> &F, const LvlK<T> &C, Cx<T> *bb, size_t offf,
+                                             unsigned p0, unsigned p1, unsigned st)
 {
-    __shared__ zc sh[4];
-    __shared__ zc res[1];
-    __shared__ zc ax[CSG_MAX_S], ar[CSG_MAX_S + 1];
-    const int rhs = blockIdx.y;
-    if (!active[rhs]) return;
-    const int k = close_sweep(pin + (size_t)rhs * NVAL * NBMAX, nbin, gsb + rhs, s, tiny, sh, res, ax, ar);
-    Cx<T> cx[CSG_MAX_S], cr[CSG_MAX_S + 1];
-#pragma unroll
-    for (int q = 0; q <= CSG_MAX_S; ++q) {
-        if (q < k) cx[q] = cvt<T>(ax[q]);
-        if (q <= k) cr[q] = cvt<T>(ar[q]);
-    }
-    const size_t offf = rhs * ldf;
-    Cx<T> *xx = x + offf;
-    Cx<T> *bb = bc + rhs * ldc;
     const T scale = (DIM == 2) ? (T)0.25 : (T)0.125;
-    const unsigned c = chunk_id(nb);
-    const unsigned p0 = c * chunk, p1 = min(C.N, p0 + chunk);
-    for (unsigned pc = p0 + threadIdx.x; pc < p1; pc += BLK) {
+    for (unsigned pc = p0; pc < p1; pc += st) {
         unsigned I, J, K;
         decomp<DIM>(pc, C.nx, C.ny, I, J, K);
         const RAx rx = raxis(I, C.nx, F.nx);
@@ -486,13 +530,13 @@ __global__ __launch_bounds__(BLK) void k_upd_res(Cx<T> *x, int accumulate, Basis
             for (int qy = 0; qy < ry.n; ++qy)
                 for (int qx = 0; qx < rx.n; ++qx) {
                     const unsigned fp = ((rz.lo + qz) * F.ny + (ry.lo + qy)) * F.nx + (rx.lo + qx);
-                    Cx<T> uv[CSG_MAX_S + 1];
+                    Cx<T> uv[SB];
 #pragma unroll
-                    for (int q = 0; q <= CSG_MAX_S; ++q)
+                    for (int q = 0; q < SB; ++q)
                         if (q <= k) uv[q] = B.u[q][offf + fp];
                     Cx<T> r = mkc<T>(0, 0);
 #pragma unroll
-                    for (int q = 0; q <= CSG_MAX_S; ++q)
+                    for (int q = 0; q < SB; ++q)
                         if (q <= k) r = cfma(cr[q], uv[q], r);
                     T wgt = (T)(rw(qx) * rw(qy));
                     if (DIM == 3) wgt *= (T)rw(qz);
@@ -501,7 +545,7 @@ __global__ __launch_bounds__(BLK) void k_upd_res(Cx<T> *x, int accumulate, Basis
                     if (own) {
                         Cx<T> v = accumulate ? xx[fp] : mkc<T>(0, 0);
 #pragma unroll
-                        for (int q = 0; q < CSG_MAX_S; ++q)
+                        for (int q = 0; q < SB - 1; ++q)
                             if (q < k) v = cfma(cx[q], uv[q], v);
                         xx[fp] = v;
                     }
@@ -512,36 +556,23 @@ __global__ __launch_bounds__(BLK) void k_upd_res(Cx<T> *x, int accumulate, Basis
 
 // r = b - A x
 template <typename T, int DIM>
-__global__ __launch_bounds__(BLK) void k_resid(LvlK<T> L, const Cx<T> *__restrict__ x, const Cx<T> *__restrict__ b,
-                                               Cx<T> *__restrict__ r, size_t ld, unsigned chunk, int nb,
-                                               const int *active)
+__device__ __forceinline__ void body_resid(const LvlK<T> &L, const Cx<T> *x, const Cx<T> *b, Cx<T> *r, unsigned p0,
+                                           unsigned p1, unsigned st)
 {
-    const int rhs = blockIdx.y;
-    if (!active[rhs]) return;
-    const size_t off = rhs * ld;
-    const unsigned c = chunk_id(nb);
-    const unsigned p0 = c * chunk, p1 = min(L.N, p0 + chunk);
-    for (unsigned p = p0 + threadIdx.x; p < p1; p += BLK) {
+    for (unsigned p = p0; p < p1; p += st) {
         unsigned i, j, k;
         decomp<DIM>(p, L.nx, L.ny, i, j, k);
-        r[off + p] = b[off + p] - apply_pt<T, DIM>(L, x + off, i, j, k, p);
+        r[p] = b[p] - apply_pt<T, DIM>(L, x, i, j, k, p);
     }
 }
 
 // bc = 2^-d P^T (b - A x)   (x may be null: bc = 2^-d P^T b)
 template <typename T, int DIM>
-__global__ __launch_bounds__(BLK) void k_restrict(LvlK<T> F, LvlK<T> C, const Cx<T> *__restrict__ x,
-                                                  const Cx<T> *__restrict__ b, Cx<T> *__restrict__ bc, size_t ldf,
-                                                  size_t ldc, unsigned chunk, int nb, const int *active)
+__device__ __forceinline__ void body_restrict(const LvlK<T> &F, const LvlK<T> &C, const Cx<T> *xx, const Cx<T> *b,
+                                              Cx<T> *bc, unsigned p0, unsigned p1, unsigned st)
 {
-    const int rhs = blockIdx.y;
-    if (!active[rhs]) return;
-    const size_t offf = rhs * ldf;
-    const Cx<T> *xx = x ? x + offf : nullptr;
     const T scale = (DIM == 2) ? (T)0.25 : (T)0.125;
-    const unsigned c = chunk_id(nb);
-    const unsigned p0 = c * chunk, p1 = min(C.N, p0 + chunk);
-    for (unsigned pc = p0 + threadIdx.x; pc < p1; pc += BLK) {
+    for (unsigned pc = p0; pc < p1; pc += st) {
         unsigned I, J, K;
         decomp<DIM>(pc, C.nx, C.ny, I, J, K);
         const RAx rx = raxis(I, C.nx, F.nx);
@@ -553,17 +584,392 @@ __global__ __launch_bounds__(BLK) void k_restrict(LvlK<T> F, LvlK<T> C, const Cx
                 for (int qx = 0; qx < rx.n; ++qx) {
                     const unsigned fi = rx.lo + qx, fj = ry.lo + qy, fk = rz.lo + qz;
                     const unsigned fp = (fk * F.ny + fj) * F.nx + fi;
-                    Cx<T> r = b[offf + fp];
+                    Cx<T> r = b[fp];
                     if (xx) r = r - apply_pt<T, DIM>(F, xx, fi, fj, fk, fp);
                     T wgt = (T)(rw(qx) * rw(qy));
                     if (DIM == 3) wgt *= (T)rw(qz);
                     acc = acc + wgt * r;
                 }
-        bc[rhs * ldc + pc] = scale * acc;
+        bc[pc] = scale * acc;
     }
 }
 
 // xout = xin + P ec   (xin may be null; xin == xout allowed)
+template <typename T, int DIM>
+__device__ __forceinline__ void body_prolong(const LvlK<T> &F, const LvlK<T> &C, const Cx<T> *e, const Cx<T> *xin,
+                                             Cx<T> *xout, unsigned p0, unsigned p1, unsigned st)
+{
+    for (unsigned p = p0; p < p1; p += st) {
+        unsigned i, j, k;
+        decomp<DIM>(p, F.nx, F.ny, i, j, k);
+        Cx<T> v = prolong_pt<T, DIM>(e, i, j, k, C.nx, C.ny, C.nz);
+        if (xin) v = v + xin[p];
+        xout[p] = v;
+    }
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ Cx<T> corrected(const Cx<T> *xin, const Cx<T> *e, unsigned i, unsigned j, unsigned k,
+                                           unsigned p, const LvlK<T> &C)
+{
+    Cx<T> v = prolong_pt<T, DIM>(e, i, j, k, C.nx, C.ny, C.nz);
+    if (xin) v = v + xin[p];
+    return v;
+}
+
+// Interpolated correction fused with the residual that opens the next sweep:
+// xout = xin + P ec and r = b - A xout (xout at the neighbours recomputed).
+template <typename T, int DIM>
+__device__ __forceinline__ void prc_pt(const LvlK<T> &F, const LvlK<T> &C, const Cx<T> *e, const Cx<T> *xi,
+                                       const Cx<T> *b, unsigned p, Cx<T> &xc, Cx<T> &rr)
+{
+    unsigned i, j, k;
+    decomp<DIM>(p, F.nx, F.ny, i, j, k);
+    const Cx<T> *tx = F.tab[0];
+    Cx<T> d = tx[F.nx + i];
+    if (DIM >= 2) d = d + F.tab[1][F.ny + j];
+    if (DIM == 3) d = d + F.tab[2][F.nz + k];
+    d.re -= F.phi[p];
+    xc = corrected<T, DIM>(xi, e, i, j, k, p, C);
+    Cx<T> acc = d * xc;
+    if (i) acc = cfma(tx[i], corrected<T, DIM>(xi, e, i - 1, j, k, p - 1, C), acc);
+    if (i + 1 < F.nx) acc = cfma(tx[2 * F.nx + i], corrected<T, DIM>(xi, e, i + 1, j, k, p + 1, C), acc);
+    if (DIM >= 2) {
+        const Cx<T> *ty = F.tab[1];
+        if (j) acc = cfma(ty[j], corrected<T, DIM>(xi, e, i, j - 1, k, p - F.nx, C), acc);
+        if (j + 1 < F.ny) acc = cfma(ty[2 * F.ny + j], corrected<T, DIM>(xi, e, i, j + 1, k, p + F.nx, C), acc);
+    }
+    if (DIM == 3) {
+        const Cx<T> *tz = F.tab[2];
+        const unsigned sz = F.nx * F.ny;
+        if (k) acc = cfma(tz[k], corrected<T, DIM>(xi, e, i, j, k - 1, p - sz, C), acc);
+        if (k + 1 < F.nz) acc = cfma(tz[2 * F.nz + k], corrected<T, DIM>(xi, e, i, j, k + 1, p + sz, C), acc);
+    }
+    rr = b[p] - acc;
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ void body_prc(const LvlK<T> &F, const LvlK<T> &C, const Cx<T> *e, const Cx<T> *xi,
+                                         Cx<T> *xout, const Cx<T> *b, Cx<T> *r, unsigned p0, unsigned p1,
+                                         unsigned st)
+{
+    constexpr int U = Ubatch<T>::U;
+    if (p0 >= p1) return;
+    const unsigned last = p1 - 1;
+    for (unsigned p = p0; p < p1; p += U * st) {
+        Cx<T> xc[U], rr[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) prc_pt<T, DIM>(F, C, e, xi, b, min(p + k * st, last), xc[k], rr[k]);
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            if (p + k * st >= p1) break;
+            xout[p + k * st] = xc[k];
+            r[p + k * st] = rr[k];
+        }
+    }
+}
+
+// x = M^{-1} b with the transposed dense inverse (column c contiguous), by NT
+// threads: rows in blocks of R = min(n, NT), NT/R column groups per row,
+// group sums combined in a fixed order through shared memory `part`.
+template <typename T, int NT>
+__device__ __forceinline__ void body_coarse(const Cx<T> *minvT, int n, const Cx<T> *b, Cx<T> *x, Cx<T> *part)
+{
+    const int R = n < NT ? n : NT;
+    const int G = NT / R;
+    const int t = threadIdx.x;
+    for (int r0 = 0; r0 < n; r0 += R) {
+        const int row = r0 + t % R, g = t / R;
+        Cx<T> acc = mkc<T>(0, 0);
+        if (g < G && row < n)
+            for (int c = g; c < n; c += G) acc = cfma(minvT[(size_t)c * n + row], b[c], acc);
+        if (g < G) part[g * R + t % R] = acc;
+        __syncthreads();
+        if (t < R && r0 + t < n) {
+            Cx<T> s = part[t];
+            for (int q = 1; q < G; ++q) s = s + part[q * R + t];
+            x[r0 + t] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// scalar logic of a GMRES(s) sweep (Arnoldi coefficients, breakdown, small
+// least squares), identical for the multi-block passes and the tail
+// ---------------------------------------------------------------------------
+
+// Consumer of the partials of pass j (res[i] = <u_i, w_j> for i <= j,
+// res[j+1] = ||u_j||^2): the scale sig_j of u_j (j = 0: beta0 = ||u_0||;
+// j > 0: h_{j,j-1} = ||u_j||, with the breakdown test against tiny * beta0),
+// h_ij = sig_i sig_j <u_i, w_j>, and the Gram-Schmidt coefficients
+// cu_i = sig_i h_ij of u_{j+1}.  Returns sig_j.  `store` publishes the state
+// (sig_i for i < j come from the state written by earlier passes).
+template <typename T, int SB>
+__device__ __forceinline__ double coef_step(const zc *res, int j, int s, double tiny, GState *gs, bool store,
+                                            Cx<T> (&cu)[SB])
+{
+    double sig[SB];
+    double nrm2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < SB; ++q)
+        if (q == j + 1) nrm2 = res[q].re;
+    const double hn = sqrt(nrm2);
+    double beta0, sj;
+    bool brk = false;
+    if (j == 0) {
+        beta0 = hn;
+        sj = beta0 > 0.0 ? 1.0 / beta0 : 0.0;
+    } else {
+        beta0 = gs->beta0;
+        brk = !(hn > tiny * beta0);
+        sj = brk ? 0.0 : 1.0 / hn;
+    }
+#pragma unroll
+    for (int q = 0; q < SB; ++q) {
+        if (q < j) sig[q] = gs->sig[q];
+        if (q == j) sig[q] = sj;
+    }
+    zc h[SB];
+#pragma unroll
+    for (int q = 0; q < SB; ++q) {
+        if (q <= j) {
+            h[q] = (sig[q] * sj) * res[q];
+            cu[q] = cvt<T>(sig[q] * h[q]);
+        }
+    }
+    if (store) {
+        if (j == 0) {
+            gs->beta0 = beta0;
+            gs->k = s;
+        } else {
+            gs->H[j * CSG_MAX_S + (j - 1)] = mkc(hn, 0.0);
+            if (brk && gs->k > j) gs->k = j;
+        }
+        gs->sig[j] = sj;
+#pragma unroll
+        for (int q = 0; q < SB; ++q)
+            if (q <= j) gs->H[q * CSG_MAX_S + j] = h[q];
+    }
+    return sj;
+}
+
+// ---------------------------------------------------------------------------
+// multi-block passes
+// ---------------------------------------------------------------------------
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(BLK) void k_apply(LvlK<T> L, const Cx<T> *__restrict__ x, Cx<T> *__restrict__ y,
+                                               size_t ld, unsigned chunk, int nb, const int *active)
+{
+    const int rhs = blockIdx.y;
+    if (!active[rhs]) return;
+    const unsigned c = chunk_id(nb);
+    const unsigned p0 = c * chunk, p1 = min(L.N, p0 + chunk);
+    body_apply<T, DIM>(L, x + rhs * ld, y + rhs * ld, p0 + threadIdx.x, p1, BLK);
+}
+
+// pass 0 of a sweep: w_0 = A u_0 with <u_0, w_0> and ||u_0||^2
+template <typename T, int DIM>
+__global__ __launch_bounds__(BLK) void k_st0(LvlK<T> L, const Cx<T> *u0, Cx<T> *w, size_t ld, zc *__restrict__ pout,
+                                             unsigned chunk, int nb, const int *active)
+{
+    __shared__ zc sh[(BLK / 64) * 2];
+    __shared__ zc res[2];
+    const int rhs = blockIdx.y;
+    if (!active[rhs]) return;
+    zc acc[2] = {mkc(0.0, 0.0), mkc(0.0, 0.0)};
+    const unsigned c = chunk_id(nb);
+    const unsigned p0 = c * chunk, p1 = min(L.N, p0 + chunk);
+    body_st0<T, DIM>(L, u0 + rhs * ld, w + rhs * ld, p0 + threadIdx.x, p1, BLK, acc);
+    block_sum<2>(acc, 2, sh, res);
+    if (threadIdx.x < 2) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + c] = res[threadIdx.x];
+}
+
+// unfused pass 2j: w_j = A u_j with <u_i, w_j> (i <= j) and ||u_j||^2
+template <typename T, int DIM, int SB>
+__global__ __launch_bounds__(BLK) void k_stj(LvlK<T> L, Basis<T> B, Cx<T> *w, int j, size_t ld, zc *__restrict__ pout,
+                                             unsigned chunk, int nb, const int *active)
+{
+    __shared__ zc sh[(BLK / 64) * NVAL];
+    __shared__ zc res[NVAL];
+    const int rhs = blockIdx.y;
+    if (!active[rhs]) return;
+    zc acc[SB];
+#pragma unroll
+    for (int q = 0; q < SB; ++q) acc[q] = mkc(0.0, 0.0);
+    const unsigned c = chunk_id(nb);
+    const unsigned p0 = c * chunk, p1 = min(L.N, p0 + chunk);
+    body_stj<T, DIM, SB>(L, B, w, j, rhs * ld, p0 + threadIdx.x, p1, BLK, acc);
+    block_sum<SB>(acc, j + 2, sh, res);
+    if (threadIdx.x < j + 2) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + c] = res[threadIdx.x];
+}
+
+// pass j+1 (j < s-1): u_{j+1} and w_{j+1} = A u_{j+1} in one sweep of the grid
+template <typename T, int DIM, int SB>
+__global__ __launch_bounds__(BLK) void k_os(LvlK<T> L, Basis<T> B, const Cx<T> *win, Cx<T> *wout, int j, int s,
+                                            size_t ld, const zc *__restrict__ pin, int nbin, zc *__restrict__ pout,
+                                            GState *gsb, double tiny, unsigned chunk, int nb, const int *active)
+{
+    __shared__ zc sh[(BLK / 64) * NVAL];
+    __shared__ zc res[NVAL];
+    const int rhs = blockIdx.y;
+    if (!active[rhs]) return;
+    GState *gs = gsb + rhs;
+    reduce_parts<SB>(pin + (size_t)rhs * NVAL * NBMAX, nbin, j + 2, sh, res);
+    Cx<T> cu[SB];
+    const double sj = coef_step<T, SB>(res, j, s, tiny, gs, blockIdx.x == 0 && threadIdx.x == 0, cu);
+    zc acc[SB];
+#pragma unroll
+    for (int q = 0; q < SB; ++q) acc[q] = mkc(0.0, 0.0);
+    const unsigned c = chunk_id(nb);
+    const unsigned p0 = c * chunk, p1 = min(L.N, p0 + chunk);
+    body_os<T, DIM, SB>(L, B, win, wout, j, (T)sj, cu, rhs * ld, p0 + threadIdx.x, p1, BLK, acc);
+    block_sum<SB>(acc, j + 3, sh, res);
+    if (threadIdx.x < j + 3) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + c] = res[threadIdx.x];
+}
+
+// last pass: u_s and ||u_s||^2
+template <typename T, int SB>
+__global__ __launch_bounds__(BLK) void k_orthl(Basis<T> B, const Cx<T> *win, int j, int s, unsigned N, size_t ld,
+                                               const zc *__restrict__ pin, int nbin, zc *__restrict__ pout,
+                                               GState *gsb, double tiny, unsigned chunk, int nb, const int *active)
+{
+    __shared__ zc sh[(BLK / 64) * NVAL];
+    __shared__ zc res[NVAL];
+    const int rhs = blockIdx.y;
+    if (!active[rhs]) return;
+    GState *gs = gsb + rhs;
+    reduce_parts<SB>(pin + (size_t)rhs * NVAL * NBMAX, nbin, j + 2, sh, res);
+    Cx<T> cu[SB];
+    const double sj = coef_step<T, SB>(res, j, s, tiny, gs, blockIdx.x == 0 && threadIdx.x == 0, cu);
+    zc acc[1] = {mkc(0.0, 0.0)};
+    const unsigned c = chunk_id(nb);
+    const unsigned p0 = c * chunk, p1 = min(N, p0 + chunk);
+    body_orthl<T, SB>(B, win + rhs * ld, j, (T)sj, cu, rhs * ld, p0 + threadIdx.x, p1, BLK, acc[0].re);
+    block_sum<1>(acc, 1, sh, res);
+    if (threadIdx.x == 0) pout[((size_t)rhs * NVAL) * NBMAX + c] = res[0];
+}
+
+// Shared prologue of the sweep's closing passes: finish h_{s,s-1}, solve the
+// small least-squares problem and publish coefficients in shared memory:
+// ax[i] = y_i sig_i (update), ar[i] = cres_i sig_i (Arnoldi residual).
+__device__ int close_sweep(const zc *pin, int nbin, GState *gs, int s, double tiny, zc *sh, zc *res, zc *ax, zc *ar)
+{
+    reduce_parts<1>(pin, nbin, 1, sh, res);
+    __shared__ int ks;
+    __shared__ zc Rs[(CSG_MAX_S + 1) * CSG_MAX_S], ys[CSG_MAX_S], crs[CSG_MAX_S + 1];
+    if (threadIdx.x == 0) {
+        const double hn = sqrt(res[0].re);
+        const bool brk = !(hn > tiny * gs->beta0);
+        const double sig_s = brk ? 0.0 : 1.0 / hn;
+        const int k = gmres_ls(gs, s, hn, Rs, ys, crs);
+        for (int i = 0; i < k; ++i) ax[i] = gs->sig[i] * ys[i];
+        for (int i = 0; i <= k; ++i) ar[i] = ((i == s) ? sig_s : gs->sig[i]) * crs[i];
+        ks = k;
+        if (blockIdx.x == 0) {
+            gs->H[s * CSG_MAX_S + (s - 1)] = mkc(hn, 0.0);
+            gs->sig[s] = sig_s;
+            for (int i = 0; i < k; ++i) gs->y[i] = ys[i];
+        }
+    }
+    __syncthreads();
+    return ks;
+}
+
+template <typename T, int SB>
+__device__ __forceinline__ void coefs_to_T(int k, const zc *ax, const zc *ar, Cx<T> (&cx)[SB], Cx<T> (&cr)[SB])
+{
+#pragma unroll
+    for (int q = 0; q < SB; ++q) {
+        if (q < k) cx[q] = cvt<T>(ax[q]);
+        if (q <= k) cr[q] = cvt<T>(ar[q]);
+    }
+}
+
+// x (+)= sum_i y_i sig_i u_i
+template <typename T, int SB>
+__global__ __launch_bounds__(BLK) void k_upd(Cx<T> *x, int accumulate, Basis<T> B, int s, unsigned N, size_t ld,
+                                             const zc *__restrict__ pin, int nbin, GState *gsb, double tiny,
+                                             unsigned chunk, int nb, const int *active)
+{
+    __shared__ zc sh[BLK / 64];
+    __shared__ zc res[1];
+    __shared__ zc ax[CSG_MAX_S], ar[CSG_MAX_S + 1];
+    const int rhs = blockIdx.y;
+    if (!active[rhs]) return;
+    const int k = close_sweep(pin + (size_t)rhs * NVAL * NBMAX, nbin, gsb + rhs, s, tiny, sh, res, ax, ar);
+    Cx<T> cx[SB], cr[SB];
+    coefs_to_T<T, SB>(k, ax, ar, cx, cr);
+    const unsigned c = chunk_id(nb);
+    const unsigned p0 = c * chunk, p1 = min(N, p0 + chunk);
+    body_upd<T, SB>(x + rhs * ld, accumulate, B, k, cx, rhs * ld, p0 + threadIdx.x, p1, BLK);
+}
+
+template <typename T, int DIM, int SB>
+__global__ __launch_bounds__(BLK) void k_upd_res(Cx<T> *x, int accumulate, Basis<T> B, int s, LvlK<T> F, LvlK<T> C,
+                                                 Cx<T> *bc, size_t ldf, size_t ldc, const zc *__restrict__ pin,
+                                                 int nbin, GState *gsb, double tiny, unsigned chunk, int nb,
+                                                 const int *active)
+{
+    __shared__ zc sh[BLK / 64];
+    __shared__ zc res[1];
+    __shared__ zc ax[CSG_MAX_S], ar[CSG_MAX_S + 1];
+    const int rhs = blockIdx.y;
+    if (!active[rhs]) return;
+    const int k = close_sweep(pin + (size_t)rhs * NVAL * NBMAX, nbin, gsb + rhs, s, tiny, sh, res, ax, ar);
+    Cx<T> cx[SB], cr[SB];
+    coefs_to_T<T, SB>(k, ax, ar, cx, cr);
+    const unsigned c = chunk_id(nb);
+    const unsigned p0 = c * chunk, p1 = min(C.N, p0 + chunk);
+    body_upd_res<T, DIM, SB>(x + rhs * ldf, accumulate, B, k, cx, cr, F, C, bc + rhs * ldc, rhs * ldf, p0 + threadIdx.x,
+                         p1, BLK);
+}
+
+template <typename T, int SB>
+__global__ __launch_bounds__(BLK) void k_upd_r(Cx<T> *x, int accumulate, Cx<T> *r, Basis<T> B, int s, unsigned N,
+                                               size_t ld, const zc *__restrict__ pin, int nbin, GState *gsb,
+                                               double tiny, unsigned chunk, int nb, const int *active)
+{
+    __shared__ zc sh[BLK / 64];
+    __shared__ zc res[1];
+    __shared__ zc ax[CSG_MAX_S], ar[CSG_MAX_S + 1];
+    const int rhs = blockIdx.y;
+    if (!active[rhs]) return;
+    const int k = close_sweep(pin + (size_t)rhs * NVAL * NBMAX, nbin, gsb + rhs, s, tiny, sh, res, ax, ar);
+    Cx<T> cx[SB], cr[SB];
+    coefs_to_T<T, SB>(k, ax, ar, cx, cr);
+    const unsigned c = chunk_id(nb);
+    const unsigned p0 = c * chunk, p1 = min(N, p0 + chunk);
+    body_upd_r<T, SB>(x + rhs * ld, accumulate, r + rhs * ld, B, k, cx, cr, rhs * ld, p0 + threadIdx.x, p1, BLK);
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(BLK) void k_resid(LvlK<T> L, const Cx<T> *__restrict__ x, const Cx<T> *__restrict__ b,
+                                               Cx<T> *__restrict__ r, size_t ld, unsigned chunk, int nb,
+                                               const int *active)
+{
+    const int rhs = blockIdx.y;
+    if (!active[rhs]) return;
+    const size_t off = rhs * ld;
+    const unsigned c = chunk_id(nb);
+    const unsigned p0 = c * chunk, p1 = min(L.N, p0 + chunk);
+    body_resid<T, DIM>(L, x + off, b + off, r + off, p0 + threadIdx.x, p1, BLK);
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(BLK) void k_restrict(LvlK<T> F, LvlK<T> C, const Cx<T> *__restrict__ x,
+                                                  const Cx<T> *__restrict__ b, Cx<T> *__restrict__ bc, size_t ldf,
+                                                  size_t ldc, unsigned chunk, int nb, const int *active)
+{
+    const int rhs = blockIdx.y;
+    if (!active[rhs]) return;
+    const size_t offf = rhs * ldf;
+    const unsigned c = chunk_id(nb);
+    const unsigned p0 = c * chunk, p1 = min(C.N, p0 + chunk);
+    body_restrict<T, DIM>(F, C, x ? x + offf : nullptr, b + offf, bc + rhs * ldc, p0 + threadIdx.x, p1, BLK);
+}
+
 template <typename T, int DIM>
 __global__ __launch_bounds__(BLK) void k_prolong(LvlK<T> F, LvlK<T> C, const Cx<T> *ec, const Cx<T> *xin,
                                                  Cx<T> *xout, size_t ldf, size_t ldc, unsigned chunk, int nb,
@@ -572,27 +978,9 @@ __global__ __launch_bounds__(BLK) void k_prolong(LvlK<T> F, LvlK<T> C, const Cx<
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
     const size_t off = rhs * ldf;
-    const Cx<T> *e = ec + rhs * ldc;
     const unsigned c = chunk_id(nb);
     const unsigned p0 = c * chunk, p1 = min(F.N, p0 + chunk);
-    for (unsigned p = p0 + threadIdx.x; p < p1; p += BLK) {
-        unsigned i, j, k;
-        decomp<DIM>(p, F.nx, F.ny, i, j, k);
-        Cx<T> v = prolong_pt<T, DIM>(e, i, j, k, C.nx, C.ny, C.nz);
-        if (xin) v = v + xin[off + p];
-        xout[off + p] = v;
-    }
-}
-
-// Interpolated correction fused with the residual that opens the next sweep:
-// xout = xin + P ec and r = b - A xout (xout at the neighbours recomputed).
-template <typename T, int DIM>
-__device__ __forceinline__ Cx<T> corrected(const Cx<T> *xin, const Cx<T> *e, unsigned i, unsigned j, unsigned k,
-                                           unsigned p, const LvlK<T> &C)
-{
-    Cx<T> v = prolong_pt<T, DIM>(e, i, j, k, C.nx, C.ny, C.nz);
-    if (xin) v = v + xin[p];
-    return v;
+    body_prolong<T, DIM>(F, C, ec + rhs * ldc, xin ? xin + off : nullptr, xout + off, p0 + threadIdx.x, p1, BLK);
 }
 
 template <typename T, int DIM>
@@ -603,139 +991,289 @@ __global__ __launch_bounds__(BLK) void k_prc(LvlK<T> F, LvlK<T> C, const Cx<T> *
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
     const size_t off = rhs * ldf;
-    const Cx<T> *e = ec + rhs * ldc;
-    const Cx<T> *xi = xin ? xin + off : nullptr;
     const unsigned c = chunk_id(nb);
     const unsigned p0 = c * chunk, p1 = min(F.N, p0 + chunk);
-    for (unsigned p = p0 + threadIdx.x; p < p1; p += BLK) {
-        unsigned i, j, k;
-        decomp<DIM>(p, F.nx, F.ny, i, j, k);
-        const Cx<T> *tx = F.tab[0];
-        Cx<T> d = tx[F.nx + i];
-        if (DIM >= 2) d = d + F.tab[1][F.ny + j];
-        if (DIM == 3) d = d + F.tab[2][F.nz + k];
-        d.re -= F.phi[p];
-        const Cx<T> xc = corrected<T, DIM>(xi, e, i, j, k, p, C);
-        Cx<T> acc = d * xc;
-        if (i) acc = cfma(tx[i], corrected<T, DIM>(xi, e, i - 1, j, k, p - 1, C), acc);
-        if (i + 1 < F.nx) acc = cfma(tx[2 * F.nx + i], corrected<T, DIM>(xi, e, i + 1, j, k, p + 1, C), acc);
-        if (DIM >= 2) {
-            const Cx<T> *ty = F.tab[1];
-            if (j) acc = cfma(ty[j], corrected<T, DIM>(xi, e, i, j - 1, k, p - F.nx, C), acc);
-            if (j + 1 < F.ny) acc = cfma(ty[2 * F.ny + j], corrected<T, DIM>(xi, e, i, j + 1, k, p + F.nx, C), acc);
-        }
-        if (DIM == 3) {
-            const Cx<T> *tz = F.tab[2];
-            const unsigned sz = F.nx * F.ny;
-            if (k) acc = cfma(tz[k], corrected<T, DIM>(xi, e, i, j, k - 1, p - sz, C), acc);
-            if (k + 1 < F.nz) acc = cfma(tz[2 * F.nz + k], corrected<T, DIM>(xi, e, i, j, k + 1, p + sz, C), acc);
-        }
-        xout[off + p] = xc;
-        r[off + p] = b[off + p] - acc;
-    }
+    body_prc<T, DIM>(F, C, ec + rhs * ldc, xin ? xin + off : nullptr, xout + off, b + off, r + off, p0 + threadIdx.x,
+                     p1, BLK);
 }
 
-// x = M_L^{-1} b with the transposed dense inverse (column c contiguous).
 template <typename T>
 __global__ __launch_bounds__(BLK) void k_coarse(const Cx<T> *__restrict__ minvT, int n, const Cx<T> *__restrict__ b,
                                                 Cx<T> *__restrict__ x, size_t ld, const int *active)
 {
+    __shared__ Cx<T> part[BLK];
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
-    const Cx<T> *bb = b + rhs * ld;
-    for (int i = blockIdx.x * BLK + threadIdx.x; i < n; i += gridDim.x * BLK) {
-        Cx<T> acc = mkc<T>(0, 0);
-        for (int c = 0; c < n; ++c) acc = cfma(minvT[(size_t)c * n + i], bb[c], acc);
-        x[rhs * ld + i] = acc;
+    body_coarse<T, BLK>(minvT, n, b + rhs * ld, x + rhs * ld, part);
+}
+
+// ---------------------------------------------------------------------------
+// coarse tail: one workgroup per right-hand side runs every level from lt down
+// to the coarsest and back (section 3.1 V-cycle), with __syncthreads between
+// passes instead of kernel boundaries.  Same bodies and scalar logic as the
+// multi-block passes; block-wide sums replace the partials.
+// ---------------------------------------------------------------------------
+
+constexpr int TB = 512;
+constexpr int TW = TB / 64;
+
+// sum of v[0..nv-1] over the workgroup, result in res (all threads see it)
+template <int NV>
+__device__ __forceinline__ void tail_sum(zc (&v)[NV], int nv, zc *sh, zc *res)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        if (q < nv) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                v[q].re += __shfl_xor(v[q].re, off, 64);
+                v[q].im += __shfl_xor(v[q].im, off, 64);
+            }
+        }
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q)
+            if (q < nv) sh[wv * NV + q] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < nv) {
+        const int q = threadIdx.x;
+        zc a = sh[q];
+        for (int w = 1; w < TW; ++w) a = a + sh[w * NV + q];
+        res[q] = a;
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ LvlK<T> tlvl(const TLev<T> &d)
+{
+    LvlK<T> L;
+    for (int a = 0; a < 3; ++a) L.tab[a] = d.tab[a];
+    L.phi = d.phi;
+    L.nx = d.nx;
+    L.ny = d.ny;
+    L.nz = d.nz;
+    L.N = d.N;
+    return L;
+}
+
+// Arnoldi passes of one sweep on the raw basis B (u_0 given), whole level;
+// w0, w1 hold the stencil outputs (ping-pong).
+template <typename T, int DIM, int SB>
+__device__ void tail_steps(const LvlK<T> &L, const Basis<T> &B, Cx<T> *w0, Cx<T> *w1, size_t off, int s,
+                           double tiny, GState *gs, zc *sh, zc *res)
+{
+    {
+        zc acc[2] = {mkc(0.0, 0.0), mkc(0.0, 0.0)};
+        body_st0<T, DIM>(L, B.u[0] + off, w0 + off, threadIdx.x, L.N, TB, acc);
+        tail_sum<2>(acc, 2, sh, res);
+    }
+    for (int j = 0; j < s; ++j) {
+        Cx<T> cu[SB];
+        const double sj = coef_step<T, SB>(res, j, s, tiny, gs, threadIdx.x == 0, cu);
+        Cx<T> *win = (j & 1) ? w1 : w0;
+        Cx<T> *wout = (j & 1) ? w0 : w1;
+        if (j + 1 < s) {
+            zc acc[SB];
+#pragma unroll
+            for (int q = 0; q < SB; ++q) acc[q] = mkc(0.0, 0.0);
+            body_os<T, DIM, SB>(L, B, win, wout, j, (T)sj, cu, off, threadIdx.x, L.N, TB, acc);
+            tail_sum<SB>(acc, j + 3, sh, res);
+        } else {
+            zc nr[1] = {mkc(0.0, 0.0)};
+            body_orthl<T, SB>(B, win + off, j, (T)sj, cu, off, threadIdx.x, L.N, TB, nr[0].re);
+            tail_sum<1>(nr, 1, sh, res);
+            if (threadIdx.x == 0) {
+                // h_{s,s-1}, the scale of u_s and the breakdown test
+                const double hn = sqrt(res[0].re);
+                const bool brk = !(hn > tiny * gs->beta0);
+                gs->H[s * CSG_MAX_S + (s - 1)] = mkc(hn, 0.0);
+                gs->sig[s] = brk ? 0.0 : 1.0 / hn;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Least squares of the sweep (thread 0) -> coefficients for every thread.
+template <typename T, int SB>
+__device__ int tail_close(const GState *gs, int s, zc *Rs, zc *ys, zc *crs, zc *ax, zc *ar, int *ks,
+                          Cx<T> (&cx)[SB], Cx<T> (&cr)[SB])
+{
+    if (threadIdx.x == 0) {
+        const double hn = gs->H[s * CSG_MAX_S + (s - 1)].re;
+        const int k = gmres_ls(gs, s, hn, Rs, ys, crs);
+        for (int i = 0; i < k; ++i) ax[i] = gs->sig[i] * ys[i];
+        for (int i = 0; i <= k; ++i) ar[i] = gs->sig[i] * crs[i];
+        *ks = k;
+    }
+    __syncthreads();
+    const int k = *ks;
+    coefs_to_T<T, SB>(k, ax, ar, cx, cr);
+    return k;
+}
+
+template <typename T, int DIM, int SB>
+__global__ __launch_bounds__(TB) void k_tail(const TLev<T> *__restrict__ lev, int lt, int L, const Cx<T> *b_in,
+                                             Cx<T> *x_out, const Cx<T> *__restrict__ minvT, int nc, int s, int nu1,
+                                             int nu2, double tiny, const int *active)
+{
+    __shared__ GState gs;
+    __shared__ zc sh[TW * NVAL];
+    __shared__ zc res[NVAL];
+    __shared__ zc Rs[(CSG_MAX_S + 1) * CSG_MAX_S], ys[CSG_MAX_S], crs[CSG_MAX_S + 1], ax[CSG_MAX_S],
+        ar[CSG_MAX_S + 1];
+    __shared__ int ks;
+    __shared__ Cx<T> cpart[TB];
+    const int rhs = blockIdx.x;
+    if (!active[rhs]) return;
+    const int t = threadIdx.x;
+
+    // down: pre-smoothing and restriction
+    for (int l = lt; l < L - 1; ++l) {
+        const TLev<T> &Fd = lev[l];
+        const TLev<T> &Cd = lev[l + 1];
+        const LvlK<T> F = tlvl(Fd), C = tlvl(Cd);
+        const size_t offf = rhs * Fd.ld, offc = rhs * Cd.ld;
+        const Cx<T> *b = (l == lt ? b_in : Fd.b) + offf;
+        if (nu1 == 0) {
+            body_restrict<T, DIM>(F, C, nullptr, b, Cd.b + offc, t, C.N, TB);
+            __syncthreads();
+            continue;
+        }
+        Basis<T> B;
+        for (int q = 0; q <= CSG_MAX_S; ++q) B.u[q] = Fd.u[q];
+        for (int k = 0; k < nu1; ++k) {
+            if (k == 0) {
+                B.u[0] = const_cast<Cx<T> *>(b) - offf;
+            } else {
+                body_resid<T, DIM>(F, Fd.xa + offf, b, Fd.r + offf, t, F.N, TB);
+                __syncthreads();
+                B.u[0] = Fd.r;
+            }
+            tail_steps<T, DIM, SB>(F, B, Fd.w[0], Fd.w[1], offf, s, tiny, &gs, sh, res);
+            Cx<T> cx[SB], cr[SB];
+            const int kk = tail_close<T, SB>(&gs, s, Rs, ys, crs, ax, ar, &ks, cx, cr);
+            if (k == nu1 - 1)
+                body_upd_res<T, DIM, SB>(Fd.xa + offf, k > 0, B, kk, cx, cr, F, C, Cd.b + offc, offf, t, C.N, TB);
+            else
+                body_upd<T, SB>(Fd.xa + offf, k > 0, B, kk, cx, offf, t, F.N, TB);
+            __syncthreads();
+        }
+    }
+    // coarsest level: exact solve
+    {
+        const TLev<T> &Cd = lev[L - 1];
+        const size_t off = rhs * Cd.ld;
+        const Cx<T> *b = (lt == L - 1 ? b_in : Cd.b) + off;
+        Cx<T> *x = (lt == L - 1 ? x_out : Cd.xb) + off;
+        body_coarse<T, TB>(minvT, nc, b, x, cpart);
+        __syncthreads();
+    }
+    // up: interpolated correction and post-smoothing
+    for (int l = L - 2; l >= lt; --l) {
+        const TLev<T> &Fd = lev[l];
+        const TLev<T> &Cd = lev[l + 1];
+        const LvlK<T> F = tlvl(Fd), C = tlvl(Cd);
+        const size_t offf = rhs * Fd.ld, offc = rhs * Cd.ld;
+        const Cx<T> *b = (l == lt ? b_in : Fd.b) + offf;
+        Cx<T> *x = (l == lt ? x_out : Fd.xb) + offf;
+        const Cx<T> *xi = nu1 > 0 ? Fd.xa + offf : nullptr;
+        const Cx<T> *ec = Cd.xb + offc;
+        if (nu2 == 0) {
+            body_prolong<T, DIM>(F, C, ec, xi, x, t, F.N, TB);
+            __syncthreads();
+            continue;
+        }
+        body_prc<T, DIM>(F, C, ec, xi, x, b, Fd.r + offf, t, F.N, TB);
+        __syncthreads();
+        Basis<T> B;
+        for (int q = 0; q <= CSG_MAX_S; ++q) B.u[q] = Fd.u[q];
+        B.u[0] = Fd.r;
+        for (int k = 0; k < nu2; ++k) {
+            if (k > 0) {
+                body_resid<T, DIM>(F, x, b, Fd.r + offf, t, F.N, TB);
+                __syncthreads();
+            }
+            tail_steps<T, DIM, SB>(F, B, Fd.w[0], Fd.w[1], offf, s, tiny, &gs, sh, res);
+            Cx<T> cx[SB], cr[SB];
+            const int kk = tail_close<T, SB>(&gs, s, Rs, ys, crs, ax, ar, &ks, cx, cr);
+            body_upd<T, SB>(x, 1, B, kk, cx, offf, t, F.N, TB);
+            __syncthreads();
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
 // outer flexible GMRES passes (FP64)
+//
+// Orthogonalisation is classical Gram-Schmidt applied twice (CGS2): with a good
+// preconditioner H z_j is close to v_j, the first projection cancels most of
+// w, and a second round restores orthogonality to working precision.
+// Inner products over many basis vectors are taken in groups of 8 so a thread
+// holds 8 accumulators, re-reading its chunk of w from cache per group.
 // ---------------------------------------------------------------------------
 
-template <int JB>
-__device__ __forceinline__ void store_parts(zc (&acc)[JB], int nv, zc *pout, int rhs, unsigned c, zc *sh, zc *res)
+// partial <v_i, w> of this block's points for i <= j, by groups of 8
+__device__ __forceinline__ void grouped_dots(const zc *w, const zc *V, size_t vstride, int j, size_t off, unsigned p0,
+                                             unsigned p1, zc *pout, unsigned c, zc *sh, zc *res)
 {
-    block_sum<JB>(acc, nv, sh, res);
-    for (int q = threadIdx.x; q < nv; q += BLK) pout[((size_t)rhs * OVAL + q) * NBMAX + c] = res[q];
+    for (int g = 0; 8 * g <= j; ++g) {
+        zc acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = mkc(0.0, 0.0);
+        for (unsigned p = p0; p < p1; p += BLK) {
+            const zc wv = w[off + p];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int i = min(8 * g + q, j);
+                const zc v = V[i * vstride + off + p];
+                if (8 * g + q <= j) acc[q] = cjfma(v, wv, acc[q]);
+            }
+        }
+        block_sum<8>(acc, 8, sh, res);
+        if (threadIdx.x < 8 && 8 * g + (int)threadIdx.x <= j) pout[(8 * g + threadIdx.x) * NBMAX + c] = res[threadIdx.x];
+    }
 }
 
 // w = H z and the first-round inner products <v_i, w>, i <= j.
-template <typename TZ, int DIM, int JB>
-__global__ __launch_bounds__(BLK) void k_hst(LvlK<double> H, const Cx<TZ> *__restrict__ z, zc *__restrict__ w,
-                                             const zc *__restrict__ V, size_t vstride, int j, size_t ld,
-                                             zc *__restrict__ pout, unsigned chunk, int nb, const int *active)
+template <typename TZ, int DIM>
+__global__ __launch_bounds__(BLK) void k_hdot(LvlK<double> H, const Cx<TZ> *__restrict__ z, zc *__restrict__ w,
+                                              const zc *__restrict__ V, size_t vstride, int j, size_t ld,
+                                              zc *__restrict__ pout, unsigned chunk, int nb, const int *active)
 {
-    __shared__ zc sh[4 * JB];
-    __shared__ zc res[JB];
+    __shared__ zc sh[(BLK / 64) * 8];
+    __shared__ zc res[8];
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
     const size_t off = rhs * ld;
-    zc acc[JB];
-#pragma unroll
-    for (int q = 0; q < JB; ++q) acc[q] = mkc(0.0, 0.0);
+    zc *po = pout + (size_t)rhs * OVAL * NBMAX;
     const unsigned c = chunk_id(nb);
-    const unsigned p0 = c * chunk, p1 = min(H.N, p0 + chunk);
-    for (unsigned p = p0 + threadIdx.x; p < p1; p += BLK) {
+    const unsigned p0 = c * chunk + threadIdx.x, p1 = min(H.N, c * chunk + chunk);
+    for (unsigned p = p0; p < p1; p += BLK) {
         unsigned i, jj, k;
         decomp<DIM>(p, H.nx, H.ny, i, jj, k);
-        const zc wv = apply_pt<double, DIM>(H, z + off, i, jj, k, p);
-        w[off + p] = wv;
-#pragma unroll
-        for (int q = 0; q < JB; ++q)
-            if (q <= j) acc[q] = cjfma(V[q * vstride + off + p], wv, acc[q]);
+        w[off + p] = apply_pt<double, DIM>(H, z + off, i, jj, k, p);
     }
-    store_parts<JB>(acc, j + 1, pout, rhs, c, sh, res);
+    grouped_dots(w, V, vstride, j, off, p0, p1, po, c, sh, res);
 }
 
-// w -= sum_i h_i v_i, then the second-round inner products <v_i, w>.
-template <int JB>
-__global__ __launch_bounds__(BLK) void k_cgs1(zc *__restrict__ w, const zc *__restrict__ V, size_t vstride, int j,
-                                              unsigned N, size_t ld, const FState *fsb, zc *__restrict__ pout,
+// w -= sum_i a_i v_i with a = hcol (first round) or corr (second round); the
+// second round also produces the partial ||w||^2.
+__global__ __launch_bounds__(BLK) void k_proj(int round, zc *__restrict__ w, const zc *__restrict__ V, size_t vstride,
+                                              int j, unsigned N, size_t ld, const FState *fsb, zc *__restrict__ pout,
                                               unsigned chunk, int nb, const int *active)
 {
-    __shared__ zc sh[4 * JB];
-    __shared__ zc res[JB];
-    __shared__ zc hh[JB];
-    const int rhs = blockIdx.y;
-    if (!active[rhs]) return;
-    if (threadIdx.x <= j) hh[threadIdx.x] = fsb[rhs].hcol[threadIdx.x];
-    __syncthreads();
-    const size_t off = rhs * ld;
-    zc acc[JB];
-#pragma unroll
-    for (int q = 0; q < JB; ++q) acc[q] = mkc(0.0, 0.0);
-    const unsigned c = chunk_id(nb);
-    const unsigned p0 = c * chunk, p1 = min(N, p0 + chunk);
-    for (unsigned p = p0 + threadIdx.x; p < p1; p += BLK) {
-        zc vv[JB];
-        zc x = w[off + p];
-#pragma unroll
-        for (int q = 0; q < JB; ++q)
-            if (q <= j) {
-                vv[q] = V[q * vstride + off + p];
-                x = x - hh[q] * vv[q];
-            }
-        w[off + p] = x;
-#pragma unroll
-        for (int q = 0; q < JB; ++q)
-            if (q <= j) acc[q] = cjfma(vv[q], x, acc[q]);
-    }
-    store_parts<JB>(acc, j + 1, pout, rhs, c, sh, res);
-}
-
-// w -= sum_i c_i v_i (second round) and the partial ||w||^2.
-__global__ __launch_bounds__(BLK) void k_cgs2(zc *__restrict__ w, const zc *__restrict__ V, size_t vstride, int j,
-                                              unsigned N, size_t ld, const FState *fsb, zc *__restrict__ pout,
-                                              unsigned chunk, int nb, const int *active)
-{
-    __shared__ zc sh[4];
+    __shared__ zc sh[BLK / 64];
     __shared__ zc res[1];
     __shared__ zc cc[OVAL];
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
-    if (threadIdx.x <= j) cc[threadIdx.x] = fsb[rhs].corr[threadIdx.x];
+    const FState *fs = fsb + rhs;
+    if (threadIdx.x <= j) cc[threadIdx.x] = round == 0 ? fs->hcol[threadIdx.x] : fs->corr[threadIdx.x];
     __syncthreads();
     const size_t off = rhs * ld;
     zc acc[1] = {mkc(0.0, 0.0)};
@@ -743,19 +1281,35 @@ __global__ __launch_bounds__(BLK) void k_cgs2(zc *__restrict__ w, const zc *__re
     const unsigned p0 = c * chunk, p1 = min(N, p0 + chunk);
     for (unsigned p = p0 + threadIdx.x; p < p1; p += BLK) {
         zc x = w[off + p];
+#pragma unroll 4
         for (int q = 0; q <= j; ++q) x = x - cc[q] * V[q * vstride + off + p];
         w[off + p] = x;
         acc[0].re += cabs2(x);
     }
+    if (round == 0) return;
     block_sum<1>(acc, 1, sh, res);
     if (threadIdx.x == 0) pout[((size_t)rhs * OVAL) * NBMAX + c] = res[0];
 }
 
+// second-round inner products c_i = <v_i, w1>
+__global__ __launch_bounds__(BLK) void k_mdot(const zc *__restrict__ w, const zc *__restrict__ V, size_t vstride, int j,
+                                              unsigned N, size_t ld, const FState *fsb, zc *__restrict__ pout,
+                                              unsigned chunk, int nb, const int *active)
+{
+    __shared__ zc sh[(BLK / 64) * 8];
+    __shared__ zc res[8];
+    const int rhs = blockIdx.y;
+    if (!active[rhs]) return;
+    const size_t off = rhs * ld;
+    const unsigned c = chunk_id(nb);
+    grouped_dots(w, V, vstride, j, off, c * chunk + threadIdx.x, min(N, c * chunk + chunk),
+                 pout + (size_t)rhs * OVAL * NBMAX, c, sh, res);
+}
+
 // v = w / h (scale from the FGMRES state), optional cycle-precision copy.
 template <typename TB>
-__global__ __launch_bounds__(BLK) void k_vnorm(const zc *w, zc *v, Cx<TB> *__restrict__ bc,
-                                               unsigned N, size_t ld, const FState *fsb, unsigned chunk, int nb,
-                                               const int *active)
+__global__ __launch_bounds__(BLK) void k_vnorm(const zc *w, zc *v, Cx<TB> *__restrict__ bc, unsigned N, size_t ld,
+                                               const FState *fsb, unsigned chunk, int nb, const int *active)
 {
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
@@ -776,7 +1330,7 @@ __global__ __launch_bounds__(BLK) void k_tres(LvlK<double> H, const zc *__restri
                                               zc *__restrict__ r, size_t ld, int with_chi, zc *__restrict__ pout,
                                               unsigned chunk, int nb, const int *active)
 {
-    __shared__ zc sh[8];
+    __shared__ zc sh[(BLK / 64) * 2];
     __shared__ zc res[2];
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
@@ -820,31 +1374,67 @@ __global__ __launch_bounds__(BLK) void k_uupd(zc *__restrict__ u, const Cx<TZ> *
     }
 }
 
+constexpr int FT = 1024;   // threads of the finish kernel
+constexpr int FG = 32;     // lanes that reduce one value
+
+// Sum of the partials of value q by FG consecutive lanes (independent loads,
+// then a butterfly inside the lane group): deterministic, no block barrier.
+__device__ __forceinline__ zc group_parts(const zc *pp, int nbin)
+{
+    const int lane = threadIdx.x % FG;
+    zc v = mkc(0.0, 0.0);
+#pragma unroll 4
+    for (int b = lane; b < nbin; b += FG) v = v + pp[b];
+#pragma unroll
+    for (int off = FG / 2; off > 0; off >>= 1) {
+        v.re += __shfl_xor(v.re, off, FG);
+        v.im += __shfl_xor(v.im, off, FG);
+    }
+    return v;
+}
+
+// Column j of the Hessenberg matrix is complete (hcol, h_{j+1,j} = hn): apply
+// the previous rotations, form the new one, update g and the estimate.
+__device__ void givens_column(FState *fs, Report *rp, int j, double hn)
+{
+    const int m = CSG_MAX_RESTART;
+    for (int q = 0; q <= j; ++q) fs->R[q * m + j] = fs->hcol[q];
+    fs->R[(j + 1) * m + j] = mkc(hn, 0.0);
+    for (int q = 0; q < j; ++q) {
+        const zc t1 = fs->R[q * m + j], t2 = fs->R[(q + 1) * m + j];
+        fs->R[q * m + j] = fs->cs[q] * t1 + fs->sn[q] * t2;
+        fs->R[(q + 1) * m + j] = fs->cs[q] * t2 - mkc(fs->sn[q].re, -fs->sn[q].im) * t1;
+    }
+    double cs;
+    zc sn;
+    rot(fs->R[j * m + j], fs->R[(j + 1) * m + j], cs, sn);
+    fs->cs[j] = cs;
+    fs->sn[j] = sn;
+    const zc t1 = fs->R[j * m + j], t2 = fs->R[(j + 1) * m + j];
+    fs->R[j * m + j] = cs * t1 + sn * t2;
+    fs->R[(j + 1) * m + j] = mkc(0.0, 0.0);
+    const zc gj = fs->g[j];
+    fs->g[j + 1] = mkc(0.0, 0.0) - mkc(sn.re, -sn.im) * gj;
+    fs->g[j] = cs * gj;
+    fs->hn = hn;
+    fs->inv_hn = hn > 0.0 ? 1.0 / hn : 0.0;
+    fs->kcols = j + 1;
+    const double est = sqrt(cabs2(fs->g[j + 1])) / fs->nchi;
+    rp->est = est;
+    rp->hn = hn;
+    rp->finite = isfinite(est) && isfinite(hn);
+}
+
 // One block per RHS: finish an outer reduction and advance the small FGMRES
 // state (Hessenberg column, Givens rotations, residual estimate, LS solve).
-__global__ __launch_bounds__(BLK) void k_fin(int mode, const zc *__restrict__ pin, int nbin, int j, FState *fsb,
-                                             Report *rep, const int *active)
+__global__ __launch_bounds__(FT) void k_fin(int mode, const zc *__restrict__ pin, int nbin, int j, FState *fsb,
+                                            Report *rep, const int *active)
 {
-    __shared__ zc sh[4];
-    __shared__ zc res[1];
+    __shared__ zc val[OVAL];
     const int rhs = blockIdx.x;
     if (!active[rhs]) return;
     FState *fs = fsb + rhs;
     const zc *pp = pin + (size_t)rhs * OVAL * NBMAX;
-    if (mode == FIN_H || mode == FIN_C) {
-        for (int q = 0; q <= j; ++q) {
-            reduce_parts<1>(pp + q * NBMAX, nbin, 1, sh, res);
-            if (threadIdx.x == 0) {
-                if (mode == FIN_H) {
-                    fs->hcol[q] = res[0];
-                } else {
-                    fs->corr[q] = res[0];
-                    fs->hcol[q] = fs->hcol[q] + res[0];
-                }
-            }
-        }
-        return;
-    }
     if (mode == FIN_LS) {
         if (threadIdx.x == 0) {
             const int k = fs->kcols;
@@ -857,55 +1447,43 @@ __global__ __launch_bounds__(BLK) void k_fin(int mode, const zc *__restrict__ pi
         }
         return;
     }
-    double nchi2 = 0.0;
-    if (mode == FIN_BEGIN) {
-        reduce_parts<1>(pp + NBMAX, nbin, 1, sh, res);
-        nchi2 = res[0].re;
+    // values: FIN_H / FIN_C: 0..j; FIN_BEGIN: 0, 1; others: 0
+    const int nv = (mode == FIN_H || mode == FIN_C) ? j + 1 : (mode == FIN_BEGIN ? 2 : 1);
+    const int grp = threadIdx.x / FG;
+    for (int q = grp; q < nv; q += FT / FG) {
+        const zc v = group_parts(pp + q * NBMAX, nbin);
+        if (threadIdx.x % FG == 0) val[q] = v;
     }
-    reduce_parts<1>(pp, nbin, 1, sh, res);
+    __syncthreads();
     if (threadIdx.x != 0) return;
-    if (mode == FIN_N) {
-        const double hn = sqrt(res[0].re);
-        const int m = CSG_MAX_RESTART;
-        for (int q = 0; q <= j; ++q) fs->R[q * m + j] = fs->hcol[q];
-        fs->R[(j + 1) * m + j] = mkc(hn, 0.0);
-        for (int q = 0; q < j; ++q) {
-            const zc t1 = fs->R[q * m + j], t2 = fs->R[(q + 1) * m + j];
-            fs->R[q * m + j] = fs->cs[q] * t1 + fs->sn[q] * t2;
-            fs->R[(q + 1) * m + j] = fs->cs[q] * t2 - mkc(fs->sn[q].re, -fs->sn[q].im) * t1;
-        }
-        double cs;
-        zc sn;
-        rot(fs->R[j * m + j], fs->R[(j + 1) * m + j], cs, sn);
-        fs->cs[j] = cs;
-        fs->sn[j] = sn;
-        const zc t1 = fs->R[j * m + j], t2 = fs->R[(j + 1) * m + j];
-        fs->R[j * m + j] = cs * t1 + sn * t2;
-        fs->R[(j + 1) * m + j] = mkc(0.0, 0.0);
-        const zc gj = fs->g[j];
-        fs->g[j + 1] = mkc(0.0, 0.0) - mkc(sn.re, -sn.im) * gj;
-        fs->g[j] = cs * gj;
-        fs->hn = hn;
-        fs->inv_hn = hn > 0.0 ? 1.0 / hn : 0.0;
-        fs->kcols = j + 1;
-        const double est = sqrt(cabs2(fs->g[j + 1])) / fs->nchi;
-        rep[rhs].est = est;
-        rep[rhs].hn = hn;
-        rep[rhs].finite = isfinite(est) && isfinite(hn);
+    switch (mode) {
+    case FIN_H:
+        for (int q = 0; q <= j; ++q) fs->hcol[q] = val[q];
         return;
+    case FIN_C:
+        for (int q = 0; q <= j; ++q) {
+            fs->corr[q] = val[q];
+            fs->hcol[q] = fs->hcol[q] + val[q];
+        }
+        return;
+    case FIN_N:
+        givens_column(fs, rep + rhs, j, sqrt(val[0].re));
+        return;
+    default: {
+        // FIN_BEGIN / FIN_BETA: start of a restart cycle
+        const double beta = sqrt(val[0].re);
+        if (mode == FIN_BEGIN) fs->nchi = sqrt(val[1].re);
+        fs->beta = beta;
+        for (int q = 0; q <= CSG_MAX_RESTART; ++q) fs->g[q] = mkc(0.0, 0.0);
+        fs->g[0] = mkc(beta, 0.0);
+        fs->inv_hn = beta > 0.0 ? 1.0 / beta : 0.0;
+        fs->kcols = 0;
+        const double est = fs->nchi > 0.0 ? beta / fs->nchi : 0.0;
+        rep[rhs].est = est;
+        rep[rhs].hn = fs->nchi;
+        rep[rhs].finite = isfinite(est) && isfinite(fs->nchi);
     }
-    // FIN_BEGIN / FIN_BETA: start of a restart cycle
-    const double beta = sqrt(res[0].re);
-    if (mode == FIN_BEGIN) fs->nchi = sqrt(nchi2);
-    fs->beta = beta;
-    for (int q = 0; q <= CSG_MAX_RESTART; ++q) fs->g[q] = mkc(0.0, 0.0);
-    fs->g[0] = mkc(beta, 0.0);
-    fs->inv_hn = beta > 0.0 ? 1.0 / beta : 0.0;
-    fs->kcols = 0;
-    const double est = fs->nchi > 0.0 ? beta / fs->nchi : 0.0;
-    rep[rhs].est = est;
-    rep[rhs].hn = fs->nchi;
-    rep[rhs].finite = isfinite(est) && isfinite(fs->nchi);
+    }
 }
 
 __global__ void k_copy_mask(const int *src, int *dst, int n)
@@ -928,27 +1506,56 @@ void launch_apply(const LvlK<T> &L, const void *x, void *y, size_t ld, const Lau
 }
 
 template <typename T, int DIM>
-void launch_st(const LvlK<T> &L, const Basis<T> &B, int j, size_t ld, const zc *pin, int nbin, zc *pout, GState *gs,
-               double tiny, const Launch &g, const int *active)
+void launch_st0(const LvlK<T> &L, const Cx<T> *u0, Cx<T> *w, size_t ld, zc *pout, const Launch &g, const int *active)
 {
-    hipLaunchKernelGGL((k_st<T, DIM>), grid(g), dim3(BLK), 0, g.st, L, B, j, ld, pin, nbin, pout, gs, tiny, g.chunk,
-                       g.nb, active);
+    hipLaunchKernelGGL((k_st0<T, DIM>), grid(g), dim3(BLK), 0, g.st, L, u0, w, ld, pout, g.chunk, g.nb, active);
+}
+
+template <typename T, int DIM>
+void launch_stj(const LvlK<T> &L, const Basis<T> &B, Cx<T> *w, int j, int s, size_t ld, zc *pout, const Launch &g,
+                const int *active)
+{
+    if (s <= 3)
+        hipLaunchKernelGGL((k_stj<T, DIM, 4>), grid(g), dim3(BLK), 0, g.st, L, B, w, j, ld, pout, g.chunk, g.nb, active);
+    else
+        hipLaunchKernelGGL((k_stj<T, DIM, NVAL - 1>), grid(g), dim3(BLK), 0, g.st, L, B, w, j, ld, pout, g.chunk, g.nb,
+                           active);
+}
+
+template <typename T, int DIM>
+void launch_os(const LvlK<T> &L, const Basis<T> &B, const Cx<T> *win, Cx<T> *wout, int j, int s, size_t ld,
+               const zc *pin, int nbin, zc *pout, GState *gs, double tiny, const Launch &g, const int *active)
+{
+    if (s <= 3)
+        hipLaunchKernelGGL((k_os<T, DIM, 4>), grid(g), dim3(BLK), 0, g.st, L, B, win, wout, j, s, ld, pin, nbin, pout,
+                           gs, tiny, g.chunk, g.nb, active);
+    else
+        hipLaunchKernelGGL((k_os<T, DIM, NVAL - 1>), grid(g), dim3(BLK), 0, g.st, L, B, win, wout, j, s, ld, pin, nbin,
+                           pout, gs, tiny, g.chunk, g.nb, active);
 }
 
 template <typename T>
-void launch_orth(const Basis<T> &B, int j, int s, unsigned N, size_t ld, const zc *pin, int nbin, zc *pout,
-                 GState *gs, const Launch &g, const int *active)
+void launch_orthl(const Basis<T> &B, const Cx<T> *win, int j, int s, unsigned N, size_t ld, const zc *pin, int nbin,
+                  zc *pout, GState *gs, double tiny, const Launch &g, const int *active)
 {
-    hipLaunchKernelGGL((k_orth<T>), grid(g), dim3(BLK), 0, g.st, B, j, N, ld, pin, nbin, pout, gs, g.chunk, g.nb, s,
-                       active);
+    if (s <= 3)
+        hipLaunchKernelGGL((k_orthl<T, 4>), grid(g), dim3(BLK), 0, g.st, B, win, j, s, N, ld, pin, nbin, pout, gs, tiny,
+                           g.chunk, g.nb, active);
+    else
+        hipLaunchKernelGGL((k_orthl<T, NVAL - 1>), grid(g), dim3(BLK), 0, g.st, B, win, j, s, N, ld, pin, nbin, pout, gs,
+                           tiny, g.chunk, g.nb, active);
 }
 
 template <typename T>
 void launch_upd(Cx<T> *x, int accumulate, const Basis<T> &B, int s, unsigned N, size_t ld, const zc *pin, int nbin,
                 GState *gs, double tiny, const Launch &g, const int *active)
 {
-    hipLaunchKernelGGL((k_upd<T>), grid(g), dim3(BLK), 0, g.st, x, accumulate, B, s, N, ld, pin, nbin, gs, tiny,
-                       g.chunk, g.nb, active);
+    if (s <= 3)
+        hipLaunchKernelGGL((k_upd<T, 4>), grid(g), dim3(BLK), 0, g.st, x, accumulate, B, s, N, ld, pin, nbin, gs, tiny,
+                           g.chunk, g.nb, active);
+    else
+        hipLaunchKernelGGL((k_upd<T, NVAL - 1>), grid(g), dim3(BLK), 0, g.st, x, accumulate, B, s, N, ld, pin, nbin,
+                           gs, tiny, g.chunk, g.nb, active);
 }
 
 template <typename T, int DIM>
@@ -956,8 +1563,24 @@ void launch_upd_res(Cx<T> *x, int accumulate, const Basis<T> &B, int s, const Lv
                     Cx<T> *bc, size_t ldf, size_t ldc, const zc *pin, int nbin, GState *gs, double tiny,
                     const Launch &gc, const int *active)
 {
-    hipLaunchKernelGGL((k_upd_res<T, DIM>), grid(gc), dim3(BLK), 0, gc.st, x, accumulate, B, s, F, C, bc, ldf, ldc,
-                       pin, nbin, gs, tiny, gc.chunk, gc.nb, active);
+    if (s <= 3)
+        hipLaunchKernelGGL((k_upd_res<T, DIM, 4>), grid(gc), dim3(BLK), 0, gc.st, x, accumulate, B, s, F, C, bc, ldf,
+                           ldc, pin, nbin, gs, tiny, gc.chunk, gc.nb, active);
+    else
+        hipLaunchKernelGGL((k_upd_res<T, DIM, NVAL - 1>), grid(gc), dim3(BLK), 0, gc.st, x, accumulate, B, s, F, C, bc,
+                           ldf, ldc, pin, nbin, gs, tiny, gc.chunk, gc.nb, active);
+}
+
+template <typename T>
+void launch_upd_r(Cx<T> *x, int accumulate, Cx<T> *r, const Basis<T> &B, int s, unsigned N, size_t ld, const zc *pin,
+                  int nbin, GState *gs, double tiny, const Launch &g, const int *active)
+{
+    if (s <= 3)
+        hipLaunchKernelGGL((k_upd_r<T, 4>), grid(g), dim3(BLK), 0, g.st, x, accumulate, r, B, s, N, ld, pin, nbin, gs,
+                           tiny, g.chunk, g.nb, active);
+    else
+        hipLaunchKernelGGL((k_upd_r<T, NVAL - 1>), grid(g), dim3(BLK), 0, g.st, x, accumulate, r, B, s, N, ld, pin,
+                           nbin, gs, tiny, g.chunk, g.nb, active);
 }
 
 template <typename T, int DIM>
@@ -995,49 +1618,28 @@ template <typename T>
 void launch_coarse(const Cx<T> *minvT, int n, const Cx<T> *b, Cx<T> *x, size_t ld, int nrhs, hipStream_t st,
                    const int *active)
 {
-    const int nbx = (n + BLK - 1) / BLK;
-    hipLaunchKernelGGL((k_coarse<T>), dim3(nbx, nrhs), dim3(BLK), 0, st, minvT, n, b, x, ld, active);
+    hipLaunchKernelGGL((k_coarse<T>), dim3(1, nrhs), dim3(BLK), 0, st, minvT, n, b, x, ld, active);
 }
 
 template <typename TZ, int DIM>
-void launch_hst(const LvlK<double> &H, const Cx<TZ> *z, zc *w, const zc *V, size_t vstride, int j, size_t ld,
-                zc *pout, const Launch &g, const int *active)
+void launch_hdot(const LvlK<double> &H, const Cx<TZ> *z, zc *w, const zc *V, size_t vstride, int j, size_t ld,
+                 zc *pout, const Launch &g, const int *active)
 {
-    if (j < 8)
-        hipLaunchKernelGGL((k_hst<TZ, DIM, 8>), grid(g), dim3(BLK), 0, g.st, H, z, w, V, vstride, j, ld, pout, g.chunk,
-                           g.nb, active);
-    else if (j < 16)
-        hipLaunchKernelGGL((k_hst<TZ, DIM, 16>), grid(g), dim3(BLK), 0, g.st, H, z, w, V, vstride, j, ld, pout,
-                           g.chunk, g.nb, active);
-    else if (j < 32)
-        hipLaunchKernelGGL((k_hst<TZ, DIM, 32>), grid(g), dim3(BLK), 0, g.st, H, z, w, V, vstride, j, ld, pout,
-                           g.chunk, g.nb, active);
-    else
-        hipLaunchKernelGGL((k_hst<TZ, DIM, 64>), grid(g), dim3(BLK), 0, g.st, H, z, w, V, vstride, j, ld, pout,
-                           g.chunk, g.nb, active);
+    hipLaunchKernelGGL((k_hdot<TZ, DIM>), grid(g), dim3(BLK), 0, g.st, H, z, w, V, vstride, j, ld, pout, g.chunk,
+                       g.nb, active);
 }
 
-void launch_cgs1(zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, const FState *fs, zc *pout,
-                 const Launch &g, const int *active)
+void launch_proj(int round, zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, const FState *fs,
+                 zc *pout, const Launch &g, const int *active)
 {
-    if (j < 8)
-        hipLaunchKernelGGL((k_cgs1<8>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, pout, g.chunk, g.nb,
-                           active);
-    else if (j < 16)
-        hipLaunchKernelGGL((k_cgs1<16>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, pout, g.chunk,
-                           g.nb, active);
-    else if (j < 32)
-        hipLaunchKernelGGL((k_cgs1<32>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, pout, g.chunk,
-                           g.nb, active);
-    else
-        hipLaunchKernelGGL((k_cgs1<64>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, pout, g.chunk,
-                           g.nb, active);
+    hipLaunchKernelGGL(k_proj, grid(g), dim3(BLK), 0, g.st, round, w, V, vstride, j, N, ld, fs, pout, g.chunk, g.nb,
+                       active);
 }
 
-void launch_cgs2(zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, const FState *fs, zc *pout,
+void launch_mdot(const zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, const FState *fs, zc *pout,
                  const Launch &g, const int *active)
 {
-    hipLaunchKernelGGL(k_cgs2, grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, pout, g.chunk, g.nb, active);
+    hipLaunchKernelGGL(k_mdot, grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, pout, g.chunk, g.nb, active);
 }
 
 template <typename TB>
@@ -1065,7 +1667,19 @@ void launch_uupd(zc *u, const Cx<TZ> *Z, size_t zstride, unsigned N, size_t ld, 
 void launch_fin(int mode, const zc *pin, int nbin, int j, FState *fs, Report *rep, int nrhs, hipStream_t st,
                 const int *active)
 {
-    hipLaunchKernelGGL(k_fin, dim3(nrhs), dim3(BLK), 0, st, mode, pin, nbin, j, fs, rep, active);
+    hipLaunchKernelGGL(k_fin, dim3(nrhs), dim3(FT), 0, st, mode, pin, nbin, j, fs, rep, active);
+}
+
+template <typename T, int DIM>
+void launch_tail(const TLev<T> *lev, int lt, int L, const Cx<T> *b_in, Cx<T> *x_out, const Cx<T> *minvT, int nc,
+                 int s, int nu1, int nu2, double tiny, int nrhs, hipStream_t st, const int *active)
+{
+    if (s <= 3)
+        hipLaunchKernelGGL((k_tail<T, DIM, 4>), dim3(nrhs), dim3(TB), 0, st, lev, lt, L, b_in, x_out, minvT, nc, s, nu1,
+                           nu2, tiny, active);
+    else
+        hipLaunchKernelGGL((k_tail<T, DIM, NVAL - 1>), dim3(nrhs), dim3(TB), 0, st, lev, lt, L, b_in, x_out, minvT, nc,
+                           s, nu1, nu2, tiny, active);
 }
 
 void launch_copy_mask(const int *src, int *dst, int n, hipStream_t st)
@@ -1079,8 +1693,12 @@ void launch_copy_mask(const int *src, int *dst, int n, hipStream_t st)
 
 #define INST_TD(T, D)                                                                                               \
     template void launch_apply<T, D>(const LvlK<T> &, const void *, void *, size_t, const Launch &, const int *);  \
-    template void launch_st<T, D>(const LvlK<T> &, const Basis<T> &, int, size_t, const zc *, int, zc *, GState *, \
-                                  double, const Launch &, const int *);                                            \
+    template void launch_st0<T, D>(const LvlK<T> &, const Cx<T> *, Cx<T> *, size_t, zc *, const Launch &,          \
+                                   const int *);                                                                   \
+    template void launch_stj<T, D>(const LvlK<T> &, const Basis<T> &, Cx<T> *, int, int, size_t, zc *,             \
+                                   const Launch &, const int *);                                                   \
+    template void launch_os<T, D>(const LvlK<T> &, const Basis<T> &, const Cx<T> *, Cx<T> *, int, int, size_t,     \
+                                  const zc *, int, zc *, GState *, double, const Launch &, const int *);           \
     template void launch_upd_res<T, D>(Cx<T> *, int, const Basis<T> &, int, const LvlK<T> &, const LvlK<T> &,      \
                                        Cx<T> *, size_t, size_t, const zc *, int, GState *, double, const Launch &, \
                                        const int *);                                                               \
@@ -1092,8 +1710,10 @@ void launch_copy_mask(const int *src, int *dst, int n, hipStream_t st)
                                        size_t, size_t, const Launch &, const int *);                               \
     template void launch_prc<T, D>(const LvlK<T> &, const LvlK<T> &, const Cx<T> *, const Cx<T> *, Cx<T> *,        \
                                    const Cx<T> *, Cx<T> *, size_t, size_t, const Launch &, const int *);           \
-    template void launch_hst<T, D>(const LvlK<double> &, const Cx<T> *, zc *, const zc *, size_t, int, size_t,     \
-                                   zc *, const Launch &, const int *);
+    template void launch_hdot<T, D>(const LvlK<double> &, const Cx<T> *, zc *, const zc *, size_t, int, size_t,    \
+                                    zc *, const Launch &, const int *);                                            \
+    template void launch_tail<T, D>(const TLev<T> *, int, int, const Cx<T> *, Cx<T> *, const Cx<T> *, int, int,     \
+                                    int, int, double, int, hipStream_t, const int *);
 
 INST_TD(double, 2)
 INST_TD(double, 3)
@@ -1101,10 +1721,12 @@ INST_TD(float, 2)
 INST_TD(float, 3)
 
 #define INST_T(T)                                                                                                  \
-    template void launch_orth<T>(const Basis<T> &, int, int, unsigned, size_t, const zc *, int, zc *, GState *,    \
-                                 const Launch &, const int *);                                                     \
+    template void launch_orthl<T>(const Basis<T> &, const Cx<T> *, int, int, unsigned, size_t, const zc *, int,    \
+                                  zc *, GState *, double, const Launch &, const int *);                            \
     template void launch_upd<T>(Cx<T> *, int, const Basis<T> &, int, unsigned, size_t, const zc *, int, GState *, \
                                 double, const Launch &, const int *);                                              \
+    template void launch_upd_r<T>(Cx<T> *, int, Cx<T> *, const Basis<T> &, int, unsigned, size_t, const zc *, int, \
+                                  GState *, double, const Launch &, const int *);                                  \
     template void launch_coarse<T>(const Cx<T> *, int, const Cx<T> *, Cx<T> *, size_t, int, hipStream_t,          \
                                    const int *);                                                                   \
     template void launch_vnorm<T>(const zc *, zc *, Cx<T> *, unsigned, size_t, const FState *, const Launch &,     \

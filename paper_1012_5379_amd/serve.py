@@ -1,0 +1,209 @@
+"""Continuous-batching serving loop over libcsg.
+
+Requests (a problem: grid, phi, beta, ...; 1..max RHS) arrive over time.  The
+engine admits a request as soon as its exact workspace (csg_workspace_bytes)
+fits the HBM budget and a stream slot is free; the hierarchy is built on a
+worker thread (ctypes releases the GIL) and stays resident until the solve
+retires.  Admitted solves advance one FGMRES iteration at a time through the
+non-blocking csg_solve_step / csg_solve_poll pair, each on its own HIP stream,
+so the iterations of different requests overlap on the device; the right-hand
+sides of one request run batched in the same launches.  Latency is arrival ->
+last RHS done (queueing and setup included); setup is also reported apart.
+
+Every arithmetic step runs in libcsg's kernels; this module only schedules.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import time
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+from . import binding as B
+
+
+@dataclass
+class Request:
+    rid: int
+    params: dict             # csg_params fields (dim, n, h, layers, gamma, beta, levels, s, nu1, nu2, cycle_prec)
+    phi: np.ndarray          # real FP64 on the finest unknowns
+    chi: np.ndarray          # complex128 (nrhs, *grid)
+    tol: float = 1e-6
+    restart: int = 30
+    maxit: int = 3000
+    arrival: float = 0.0     # seconds after the start of the run
+    # filled by the engine
+    t_admit: float = float("nan")
+    t_ready: float = float("nan")
+    t_done: float = float("nan")
+    status: Optional[int] = None
+    infos: list = field(default_factory=list)
+    u: Optional[np.ndarray] = None
+
+    @property
+    def nrhs(self) -> int:
+        return int(self.chi.shape[0])
+
+    def csg_params(self):
+        return B.make_params(**dict(self.params, max_rhs=self.nrhs, restart=self.restart, graphs=-1))
+
+    def workspace_bytes(self) -> int:
+        return B.csg_workspace_bytes(self.csg_params())
+
+
+class _Active:
+    def __init__(self, req, slot, ws, op, chi, u, stream):
+        self.req, self.slot, self.ws, self.op, self.chi, self.u, self.stream = req, slot, ws, op, chi, u, stream
+        self.sv = None
+
+
+class Engine:
+    """Admit by HBM budget, overlap solves on `streams` HIP streams."""
+
+    def __init__(self, hbm_budget: Optional[int] = None, streams: int = 4, device: str = "cuda",
+                 keep_solutions: bool = True):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        if hbm_budget is None:
+            free, _ = torch.cuda.mem_get_info(self.device)
+            hbm_budget = int(0.8 * free)
+        self.budget = int(hbm_budget)
+        self.used = 0
+        self.high_water = 0
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
+        self.free_slots = list(range(streams))
+        self.queue: list = []
+        self.active: list = []
+        self.pending: list = []        # (future, request, slot, bytes)
+        self.done: list = []
+        self.keep = keep_solutions
+        self.pool = cf.ThreadPoolExecutor(max_workers=1)
+        self.t0 = time.perf_counter()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def submit(self, req: Request) -> None:
+        nb = req.workspace_bytes()
+        if nb > self.budget:
+            raise ValueError(f"request {req.rid} needs {nb} bytes, more than the HBM budget {self.budget}")
+        self.queue.append(req)
+
+    # -- admission -------------------------------------------------------------
+    def _setup(self, req: Request, slot: int):
+        torch = self.torch
+        stream = self.streams[slot]
+        p = req.csg_params()
+        nb = B.csg_workspace_bytes(p)
+        with torch.cuda.stream(stream):
+            ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+            chi = torch.from_numpy(np.ascontiguousarray(req.chi)).to(self.device, non_blocking=False)
+            u = torch.empty_like(chi)
+        phi = np.ascontiguousarray(req.phi, dtype=np.float64)
+        op = B.csg_operator_create(p, phi.ctypes.data, ws.data_ptr(), nb, stream.cuda_stream)
+        return _Active(req, slot, ws, op, chi, u, stream)
+
+    def _admit(self) -> None:
+        while self.queue and self.free_slots:
+            req = self.queue[0]
+            nb = req.workspace_bytes()
+            if self.used + nb > self.budget:
+                break
+            self.queue.pop(0)
+            slot = self.free_slots.pop(0)
+            self.used += nb
+            self.high_water = max(self.high_water, self.used)
+            req.t_admit = self.now()
+            self.pending.append((self.pool.submit(self._setup, req, slot), req, slot, nb))
+
+    def _start_ready(self) -> None:
+        still = []
+        for fut, req, slot, nb in self.pending:
+            if not fut.done():
+                still.append((fut, req, slot, nb))
+                continue
+            a = fut.result()
+            a.nbytes = nb
+            req.t_ready = self.now()
+            a.sv = B.csg_solve_begin(a.op, a.chi.data_ptr(), a.u.data_ptr(), req.nrhs, req.tol, req.restart,
+                                     req.maxit, 0, a.stream.cuda_stream)
+            self.active.append(a)
+        self.pending = still
+
+    # -- stepping --------------------------------------------------------------
+    def _retire(self, a: _Active) -> None:
+        rc, infos = B.csg_solve_end(a.sv, a.req.nrhs)
+        a.req.status, a.req.infos = rc, infos
+        a.req.t_done = self.now()
+        if self.keep:
+            a.req.u = a.u.cpu().numpy()
+        B.csg_operator_destroy(a.op)
+        a.op = None
+        self.used -= a.nbytes
+        a.ws = None
+        self.free_slots.append(a.slot)
+        self.done.append(a.req)
+
+    def step(self) -> bool:
+        """Admit what fits, advance every solve whose last iteration landed.
+        Returns True while work remains."""
+        self._admit()
+        self._start_ready()
+        keep = []
+        for a in self.active:
+            r, done = B.csg_solve_poll(a.sv)
+            if done:
+                self._retire(a)
+                continue
+            if r == 1:
+                B.csg_solve_step(a.sv)
+            keep.append(a)
+        self.active = keep
+        return bool(self.queue or self.pending or self.active)
+
+    def run(self, requests, realtime: bool = True) -> list:
+        """Serve `requests` (arrival times in seconds from now when realtime)."""
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        self.t0 = time.perf_counter()
+        i = 0
+        while i < len(reqs) or self.step():
+            t = self.now()
+            while i < len(reqs) and (not realtime or reqs[i].arrival <= t):
+                if not realtime:
+                    reqs[i].arrival = t
+                self.submit(reqs[i])
+                i += 1
+            if i >= len(reqs) and not (self.queue or self.pending or self.active):
+                break
+        return self.done
+
+    def close(self) -> None:
+        self.pool.shutdown(wait=True)
+
+
+def report(done: list, t_total: float) -> dict:
+    lat = np.array([r.t_done - r.arrival for r in done]) * 1e3
+    setup = np.array([r.t_ready - r.t_admit for r in done]) * 1e3
+    solves = sum(r.nrhs for r in done)
+    ok = all(r.status == 0 for r in done)
+    return {
+        "requests": len(done),
+        "solves": solves,
+        "seconds": t_total,
+        "requests_per_s": len(done) / t_total if t_total > 0 else 0.0,
+        "solves_per_s": solves / t_total if t_total > 0 else 0.0,
+        "p50_latency_ms": float(np.percentile(lat, 50)) if len(lat) else None,
+        "p99_latency_ms": float(np.percentile(lat, 99)) if len(lat) else None,
+        "p50_setup_ms": float(np.percentile(setup, 50)) if len(setup) else None,
+        "all_converged": ok,
+    }
+
+
+def request_from_workload(w, rid: int, arrival: float = 0.0) -> Request:
+    """Wrap a seeded workload (synth.workloads.Workload) as a request."""
+    params = dict(w.params(), cycle_prec=w.cycle_prec)
+    return Request(rid=rid, params=params, phi=w.phi, chi=w.chi, tol=w.tol, restart=w.restart,
+                   maxit=w.maxit, arrival=arrival)

@@ -198,3 +198,36 @@ def test_solve_edge_cases():
     u3, rc3, inf3 = op.solve(dev(chi[1:], torch.complex128), tol=1e-8, restart=10, maxit=300,
                              u0=dev(u[1:], torch.complex128))
     assert rc3 == 0 and inf3[0]["iterations"] == 0
+
+
+@pytest.mark.parametrize("tail_max", ["0", "1200", "10000", "1000000000"])
+def test_vcycle_any_tail_split(tail_max, monkeypatch):
+    """The coarse-tail kernel (one workgroup per RHS for the small levels) and
+    the multi-block passes compute the same cycle: every split point matches
+    the oracle to 1e-12."""
+    monkeypatch.setenv("CSG_TAIL_MAX", tail_max)
+    w = CASES["2d_wide"]()
+    op, orc = pair(w, max_rhs=2, cycle_prec=0)
+    b = np.stack([rvec(orc.shape(0), 180), rvec(orc.shape(0), 181)])
+    x = host(op.vcycle(dev(b, op.cdtype)))
+    for r in range(2):
+        e = rel(x[r], orc.vcycle(b[r]))
+        note(f"  tail_max {tail_max} rhs {r}: {e:.2e}")
+        assert e <= TOL64
+
+
+def test_graph_replay_matches_eager(monkeypatch):
+    """FGMRES iterations replayed from captured graphs (with eager restart and
+    report work in between) give bit-identical results to eager launches."""
+    import torch
+    w = CASES["2d_ragged"]()
+    chi = dev(np.stack([w.chi[0], rvec(w.chi.shape[1:], 190)]), torch.complex128)
+    outs = []
+    for graphs in ("1", "0", "1"):
+        monkeypatch.setenv("CSG_GRAPHS", graphs)
+        op, orc = pair(w, max_rhs=2, cycle_prec=0, restart=12)
+        u, rc, infos = op.solve(chi, tol=1e-9, restart=12, maxit=400)
+        assert rc == 0
+        outs.append((host(u), [i["iterations"] for i in infos]))
+    assert outs[0][1] == outs[1][1] == outs[2][1]
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][0], outs[2][0])
