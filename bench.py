@@ -67,6 +67,79 @@ def cpu_baseline(w, its_per_solve, sample_its):
     }
 
 
+def serve_bench(args):
+    """Serving stream: seeded C5 requests (2-D 256^2..2048^2 and 3-D 64^3..192^3,
+    1-8 point sources, complex64 cycle).  A closed-loop pass (every request
+    queued at once) measures the saturated rate; an open-loop pass then replays
+    Poisson arrivals at `--load` times that rate.  Latency = arrival -> last RHS
+    done, setup included."""
+    import torch
+    from synth import workloads as W
+    from paper_1012_5379_amd.serve import Engine, report, request_from_workload
+
+    count = args.requests
+    items = list(range(count))
+    t0 = time.perf_counter()
+    base = [W.c5_request(i) for i in items]
+    print(f"[bench] c5: {count} requests generated in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+
+    def reqs(arrivals):
+        return [request_from_workload(w, rid=i, arrival=float(a)) for i, (w, a) in enumerate(zip(base, arrivals))]
+
+    # warm-up (kernels loaded, allocator primed): two small requests
+    eng = Engine(streams=args.streams, keep_solutions=False, cache=False)
+    eng.run([request_from_workload(W.c5_request(10 ** 5 + i, dim=2, n=256), rid=i) for i in range(2)],
+            realtime=False)
+    eng.close()
+
+    eng = Engine(streams=args.streams, keep_solutions=False, cache=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = eng.run(reqs([0.0] * count), realtime=False)
+    torch.cuda.synchronize()
+    closed = report(done, time.perf_counter() - t0)
+    closed["hbm_high_water_GB"] = eng.high_water / 1e9
+    eng.close()
+    print(f"[bench] c5 closed loop: {json.dumps(closed)}", file=sys.stderr, flush=True)
+
+    rate = args.load * closed["requests_per_s"]
+    arr, _ = W.c5_stream(count, rate)
+    eng = Engine(streams=args.streams, keep_solutions=False, cache=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = eng.run(reqs(arr), realtime=True)
+    torch.cuda.synchronize()
+    opened = report(done, time.perf_counter() - t0)
+    opened["hbm_high_water_GB"] = eng.high_water / 1e9
+    eng.close()
+    classes = {}
+    for w in base:
+        k = f"{w.dim}d_{w.n[0]}"
+        classes[k] = classes.get(k, 0) + 1
+    out = {
+        "metric": METRIC,
+        "value": closed["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": count,
+        "warmup": 2,
+        "ms_per_step": closed["seconds"] / count * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "c5_serving_stream_2d256-2048_3d64-192_1-8rhs_c64cycle", "requests": count,
+                   "classes": classes, "streams": args.streams, "tol": 1e-6, "outer_dtype": "f64",
+                   "parallelism": "single-gpu"},
+        "closed_loop": closed,
+        "open_loop": dict(opened, offered_rate_rps=rate, load=args.load),
+        "p50_latency_ms": opened["p50_latency_ms"],
+        "p99_latency_ms": opened["p99_latency_ms"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +149,9 @@ def main():
     ap.add_argument("--cpu-sample-its", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-survey", action="store_true", help="skip the per-pass time survey")
+    ap.add_argument("--requests", type=int, default=24, help="c5: requests per pass")
+    ap.add_argument("--streams", type=int, default=4, help="c5: concurrent solves")
+    ap.add_argument("--load", type=float, default=0.75, help="c5: offered rate / saturated rate")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -92,6 +168,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "c5":
+        serve_bench(args)
+        return
 
     w, wname = _workload(args.workload)
     params = dict(w.params(), cycle_prec=w.cycle_prec, max_rhs=w.nrhs, restart=w.restart)

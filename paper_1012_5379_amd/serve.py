@@ -9,13 +9,18 @@ non-blocking csg_solve_step / csg_solve_poll pair, each on its own HIP stream,
 so the iterations of different requests overlap on the device; the right-hand
 sides of one request run batched in the same launches.  Latency is arrival ->
 last RHS done (queueing and setup included); setup is also reported apart.
+A retired request's hierarchy is kept in an LRU cache keyed by a hash of its
+parameters and phi, so a repeated problem skips setup; cached hierarchies are
+evicted, oldest first, when an admission needs their memory.
 
 Every arithmetic step runs in libcsg's kernels; this module only schedules.
 """
 from __future__ import annotations
 
 import concurrent.futures as cf
+import hashlib
 import time
+from collections import OrderedDict
 from dataclasses import dataclass, field
 from typing import Optional
 
@@ -52,18 +57,26 @@ class Request:
     def workspace_bytes(self) -> int:
         return B.csg_workspace_bytes(self.csg_params())
 
+    def key(self) -> str:
+        h = hashlib.sha1(repr(sorted(self.params.items())).encode())
+        h.update(repr((self.nrhs, self.restart)).encode())
+        h.update(np.ascontiguousarray(self.phi, dtype=np.float64).tobytes())
+        return h.hexdigest()
+
 
 class _Active:
     def __init__(self, req, slot, ws, op, chi, u, stream):
         self.req, self.slot, self.ws, self.op, self.chi, self.u, self.stream = req, slot, ws, op, chi, u, stream
         self.sv = None
+        self.nbytes = 0
+        self.key = None
 
 
 class Engine:
     """Admit by HBM budget, overlap solves on `streams` HIP streams."""
 
     def __init__(self, hbm_budget: Optional[int] = None, streams: int = 4, device: str = "cuda",
-                 keep_solutions: bool = True):
+                 keep_solutions: bool = True, cache: bool = True):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -81,6 +94,9 @@ class Engine:
         self.done: list = []
         self.keep = keep_solutions
         self.pool = cf.ThreadPoolExecutor(max_workers=1)
+        self.use_cache = cache
+        self.cache: "OrderedDict[str, tuple]" = OrderedDict()   # key -> (ws tensor, op, bytes)
+        self.cache_hits = 0
         self.t0 = time.perf_counter()
 
     def now(self) -> float:
@@ -93,40 +109,60 @@ class Engine:
         self.queue.append(req)
 
     # -- admission -------------------------------------------------------------
-    def _setup(self, req: Request, slot: int):
+    def _setup(self, req: Request, slot: int, cached=None):
         torch = self.torch
         stream = self.streams[slot]
+        with torch.cuda.stream(stream):
+            chi = torch.from_numpy(np.ascontiguousarray(req.chi)).to(self.device, non_blocking=False)
+            u = torch.empty_like(chi)
+        if cached is not None:
+            ws, op, _ = cached
+            return _Active(req, slot, ws, op, chi, u, stream)
         p = req.csg_params()
         nb = B.csg_workspace_bytes(p)
         with torch.cuda.stream(stream):
             ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
-            chi = torch.from_numpy(np.ascontiguousarray(req.chi)).to(self.device, non_blocking=False)
-            u = torch.empty_like(chi)
         phi = np.ascontiguousarray(req.phi, dtype=np.float64)
         op = B.csg_operator_create(p, phi.ctypes.data, ws.data_ptr(), nb, stream.cuda_stream)
         return _Active(req, slot, ws, op, chi, u, stream)
 
+    def _evict_one(self) -> bool:
+        if not self.cache:
+            return False
+        _, (ws, op, nb) = self.cache.popitem(last=False)
+        B.csg_operator_destroy(op)
+        self.used -= nb
+        return True
+
     def _admit(self) -> None:
         while self.queue and self.free_slots:
             req = self.queue[0]
-            nb = req.workspace_bytes()
-            if self.used + nb > self.budget:
-                break
+            key = req.key() if self.use_cache else None
+            cached = self.cache.pop(key, None) if key is not None else None
+            if cached is not None:
+                nb = cached[2]
+                self.cache_hits += 1
+            else:
+                nb = req.workspace_bytes()
+                while self.used + nb > self.budget and self._evict_one():
+                    pass
+                if self.used + nb > self.budget:
+                    break
+                self.used += nb
+                self.high_water = max(self.high_water, self.used)
             self.queue.pop(0)
             slot = self.free_slots.pop(0)
-            self.used += nb
-            self.high_water = max(self.high_water, self.used)
             req.t_admit = self.now()
-            self.pending.append((self.pool.submit(self._setup, req, slot), req, slot, nb))
+            self.pending.append((self.pool.submit(self._setup, req, slot, cached), req, slot, nb, key))
 
     def _start_ready(self) -> None:
         still = []
-        for fut, req, slot, nb in self.pending:
+        for fut, req, slot, nb, key in self.pending:
             if not fut.done():
-                still.append((fut, req, slot, nb))
+                still.append((fut, req, slot, nb, key))
                 continue
             a = fut.result()
-            a.nbytes = nb
+            a.nbytes, a.key = nb, key
             req.t_ready = self.now()
             a.sv = B.csg_solve_begin(a.op, a.chi.data_ptr(), a.u.data_ptr(), req.nrhs, req.tol, req.restart,
                                      req.maxit, 0, a.stream.cuda_stream)
@@ -140,9 +176,12 @@ class Engine:
         a.req.t_done = self.now()
         if self.keep:
             a.req.u = a.u.cpu().numpy()
-        B.csg_operator_destroy(a.op)
+        if a.key is not None:
+            self.cache[a.key] = (a.ws, a.op, a.nbytes)
+        else:
+            B.csg_operator_destroy(a.op)
+            self.used -= a.nbytes
         a.op = None
-        self.used -= a.nbytes
         a.ws = None
         self.free_slots.append(a.slot)
         self.done.append(a.req)
@@ -169,19 +208,22 @@ class Engine:
         reqs = sorted(requests, key=lambda r: r.arrival)
         self.t0 = time.perf_counter()
         i = 0
-        while i < len(reqs) or self.step():
+        while True:
             t = self.now()
             while i < len(reqs) and (not realtime or reqs[i].arrival <= t):
                 if not realtime:
                     reqs[i].arrival = t
                 self.submit(reqs[i])
                 i += 1
-            if i >= len(reqs) and not (self.queue or self.pending or self.active):
+            busy = self.step()
+            if i >= len(reqs) and not busy:
                 break
         return self.done
 
     def close(self) -> None:
         self.pool.shutdown(wait=True)
+        while self._evict_one():
+            pass
 
 
 def report(done: list, t_total: float) -> dict:

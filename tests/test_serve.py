@@ -1,0 +1,74 @@
+"""Serving loop: continuous admission by HBM budget, overlapping solves on
+several streams; every request's answer is the same alone and in the mix."""
+import numpy as np
+import pytest
+
+from synth import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests(n=10):
+    from paper_1012_5379_amd.serve import request_from_workload
+    reqs = []
+    for i in range(n):
+        if i % 3 == 2:
+            w = W.small(dim=3, n=12 + 4 * (i % 2), m=2, beta=0.4, kh=0.4, item=i, nrhs=1 + i % 3, cycle_prec=1)
+        else:
+            w = W.small(dim=2, n=48 + 16 * (i % 4), m=6, beta=0.3 + 0.05 * (i % 3), kh=0.5, item=i,
+                        nrhs=1 + i % 4, cycle_prec=i % 2)
+        reqs.append(request_from_workload(w.with_(tol=1e-7), rid=i, arrival=0.002 * i))
+    return reqs
+
+
+def _serve(reqs, streams, budget=None):
+    from paper_1012_5379_amd.serve import Engine
+    eng = Engine(hbm_budget=budget, streams=streams)
+    done = eng.run(reqs, realtime=True)
+    eng.close()
+    return {r.rid: r for r in done}, eng
+
+
+def test_alone_equals_mix():
+    """Each request solved alone (one stream, one at a time) and in the mix
+    (four streams, overlapping) gives bit-identical solutions and counts."""
+    alone, _ = _serve(_requests(), streams=1)
+    mixed, eng = _serve(_requests(), streams=4)
+    assert set(alone) == set(mixed) and len(alone) == 10
+    for rid in alone:
+        a, m = alone[rid], mixed[rid]
+        assert a.status == 0 and m.status == 0
+        assert [i["iterations"] for i in a.infos] == [i["iterations"] for i in m.infos]
+        assert np.array_equal(a.u, m.u)
+        assert all(i["relres_true"] <= 1e-7 for i in m.infos)
+
+
+def test_admission_respects_budget():
+    """A budget that holds only the largest request at a time still serves
+    every request, never exceeding the budget."""
+    reqs = _requests(6)
+    need = max(r.workspace_bytes() for r in reqs)
+    done, eng = _serve(reqs, streams=4, budget=need)
+    assert len(done) == 6 and all(r.status == 0 for r in done.values())
+    assert eng.high_water <= need
+
+
+def test_oversized_request_rejected():
+    from paper_1012_5379_amd.serve import Engine
+    reqs = _requests(1)
+    eng = Engine(hbm_budget=reqs[0].workspace_bytes() - 1, streams=1)
+    with pytest.raises(ValueError):
+        eng.submit(reqs[0])
+    eng.close()
+
+
+def test_repeated_problem_reuses_hierarchy():
+    """The same problem submitted twice is built once (LRU cache hit) and gives
+    the same answer bit for bit."""
+    from paper_1012_5379_amd.serve import request_from_workload
+    w = W.small(dim=2, n=64, m=6, beta=0.35, kh=0.5, item=42, nrhs=2, cycle_prec=1).with_(tol=1e-7)
+    reqs = [request_from_workload(w, rid=i, arrival=0.0) for i in range(2)]
+    done, eng = _serve(reqs, streams=1)
+    assert eng.cache_hits == 1
+    assert done[0].status == 0 and done[1].status == 0
+    assert np.array_equal(done[0].u, done[1].u)
