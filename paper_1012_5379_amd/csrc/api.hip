@@ -298,7 +298,14 @@ void sweep(const csg_operator *op, int l, const Cx<T> *b, Cx<T> *x, bool from_ze
     const Bytes by = bytes_of(op, nrhs);
     const int k0 = l == 0 ? 0 : -1;   // instrumented kinds exist for the finest level only
     zc *pclose = close_part(op, l);
-    if (restrict_after) {
+    if (restrict_after && lv.N <= op->fuse_max) {
+        // small level: one pass per coarse point forms the Arnoldi residual on
+        // its fine stencil, restricts it and updates the fine points it owns
+        const DevLevel &cl = op->lev[l + 1];
+        ProfScope ps(op, k0 ? -1 : CSG_PROF_UPD_RESTRICT, st, by.upd_res(s, !from_zero, lv.N, cl.N));
+        launch_upd_res<T, DIM>(x, from_zero ? 0 : 1, B, s, L, lvl<T>(op, l + 1), (Cx<T> *)cl.b, lv.ld, cl.ld, pclose,
+                               lv.nb, lv.gs, tiny, lch(op, l + 1, nrhs, st), active);
+    } else if (restrict_after) {
         // closing update writes x and the Arnoldi residual r; full weighting of r
         const DevLevel &cl = op->lev[l + 1];
         ProfScope ps(op, k0 ? -1 : CSG_PROF_UPD_RESTRICT, st,
@@ -350,7 +357,14 @@ void vcycle_impl(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, h
             launch_prolong<T, DIM>(lvl<T>(op, l), lvl<T>(op, l + 1), (const Cx<T> *)cl.xb, xi, xo, lv.ld, cl.ld, g,
                                    active);
         } else {
-            {
+            if (lv.N <= op->fuse_max) {
+                // small level: correction and residual in one pass (the
+                // corrected x recomputed at the stencil neighbours)
+                ProfScope ps(op, l == 0 ? CSG_PROF_PROLONG_RESID : -1, st,
+                             bytes_of(op, nrhs).prc(xi != nullptr, lv.N, cl.N));
+                launch_prc<T, DIM>(lvl<T>(op, l), lvl<T>(op, l + 1), (const Cx<T> *)cl.xb, xi, xo, b, (Cx<T> *)lv.r,
+                                   lv.ld, cl.ld, g, active);
+            } else {
                 // interpolated correction, then the residual that opens the post-sweep
                 const Bytes by = bytes_of(op, nrhs);
                 ProfScope ps(op, l == 0 ? CSG_PROF_PROLONG_RESID : -1, st,
@@ -444,14 +458,17 @@ void enqueue_begin(csg_solve *sv, bool with_chi_norm)
     const int *mask = op->active + cyc_mask_offset(op);
     launch_tres<DIM>(lvlH(op), sv->chi, sv->u, op->V, f.ld, with_chi_norm ? 1 : 0, op->opart, g, mask);
     launch_fin(with_chi_norm ? FIN_BEGIN : FIN_BETA, op->opart, f.nb, 0, op->fs, op->rep, sv->nrhs, sv->st, mask);
+    ProfScope ps(op, CSG_PROF_OUTER_NORM, sv->st, sv->nrhs * f.N * (32.0 + (op->p.cycle_prec ? 8.0 : 0.0)));
     if (op->p.cycle_prec)
         launch_vnorm<float>(op->V, op->V, (cf *)op->b0, f.N, f.ld, op->fs, g, mask);
     else
         launch_vnorm<double>(op->V, op->V, (zc *)nullptr, f.N, f.ld, op->fs, g, mask);
 }
 
-// One FGMRES iteration (section 5): z_j = V(v_j), w = H z_j, Gram-Schmidt
-// against v_0..v_j (second round on demand), Givens update, v_{j+1} = w / h.
+// One FGMRES iteration (section 5): z_j = V(v_j), w = H z_j, classical
+// Gram-Schmidt against v_0..v_j twice (the first projection also yields
+// ||w1||^2, so h_{j+1,j} follows from the second-round coefficients), Givens
+// update, and v_{j+1} written normalised by the second projection.
 template <typename TZ, int DIM>
 void iter_body(csg_solve *sv, int j, hipStream_t st)
 {
@@ -471,21 +488,16 @@ void iter_body(csg_solve *sv, int j, hipStream_t st)
     launch_fin(FIN_H, op->opart, f.nb, j, op->fs, op->rep, sv->nrhs, st, mask);
     {
         ProfScope ps(op, CSG_PROF_OUTER_CGS1, st, R * N * 16.0 * (j + 3));
-        launch_proj(0, op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->opart, g, mask);
+        launch_proj0(op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->opart, g, mask);
     }
     {
         ProfScope ps(op, CSG_PROF_OUTER_CGS2, st, R * N * 16.0 * (j + 2));
         launch_mdot(op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->opart, g, mask);
     }
-    launch_fin(FIN_C, op->opart, f.nb, j, op->fs, op->rep, sv->nrhs, st, mask);
-    {
-        ProfScope ps(op, CSG_PROF_OUTER_PROJ2, st, R * N * 16.0 * (j + 3));
-        launch_proj(1, op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->opart, g, mask);
-    }
-    launch_fin(FIN_N, op->opart, f.nb, j, op->fs, op->rep, sv->nrhs, st, mask);
-    ProfScope ps(op, CSG_PROF_OUTER_NORM, st, R * N * (32.0 + (op->p.cycle_prec ? 8.0 : 0.0)));
-    launch_vnorm<TZ>(op->w, op->V + (j + 1) * vstride, op->p.cycle_prec ? (Cx<TZ> *)op->b0 : nullptr, f.N, f.ld,
-                     op->fs, g, mask);
+    launch_fin(FIN_CN, op->opart, f.nb, j, op->fs, op->rep, sv->nrhs, st, mask);
+    ProfScope ps(op, CSG_PROF_OUTER_PROJ2, st, R * N * (16.0 * (j + 3) + (op->p.cycle_prec ? 8.0 : 0.0)));
+    launch_proj1<TZ>(op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->V + (j + 1) * vstride,
+                     op->p.cycle_prec ? (Cx<TZ> *)op->b0 : nullptr, g, mask);
 }
 
 // Replays the captured graph of column j (capturing it on first use); eager

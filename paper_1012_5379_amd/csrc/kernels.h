@@ -106,9 +106,14 @@ template <typename TZ, int DIM>
 void launch_hdot(const LvlK<double> &H, const Cx<TZ> *z, zc *w, const zc *V, size_t vstride, int j, size_t ld,
                  zc *pout, const Launch &g, const int *active);
 
-// w -= V a (a = hcol for round 0, corr for round 1; round 1 also ||w||^2)
-void launch_proj(int round, zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, const FState *fs,
-                 zc *pout, const Launch &g, const int *active);
+// first projection w -= V hcol in place; partial ||w||^2 as value j+1
+void launch_proj0(zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, const FState *fs, zc *pout,
+                  const Launch &g, const int *active);
+
+// v_{j+1} = (w - V corr) * inv_hn, optional cycle-precision copy
+template <typename TB>
+void launch_proj1(const zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, const FState *fs, zc *vout,
+                  Cx<TB> *bcast, const Launch &g, const int *active);
 
 // second-round <v_i, w>
 void launch_mdot(const zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, const FState *fs, zc *pout,
@@ -128,7 +133,7 @@ void launch_uupd(zc *u, const Cx<TZ> *Z, size_t zstride, unsigned N, size_t ld, 
                  const int *active);
 
 // finish kernels: one block per RHS
-enum FinMode { FIN_H = 0, FIN_C = 1, FIN_N = 2, FIN_BEGIN = 3, FIN_BETA = 4, FIN_LS = 5 };
+enum FinMode { FIN_H = 0, FIN_CN = 1, FIN_BEGIN = 3, FIN_BETA = 4, FIN_LS = 5 };
 void launch_fin(int mode, const zc *pin, int nbin, int j, FState *fs, Report *rep, int nrhs, hipStream_t st,
                 const int *active);
 

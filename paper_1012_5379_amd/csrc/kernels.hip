@@ -1217,34 +1217,52 @@ __global__ __launch_bounds__(TB) void k_tail(const TLev<T> *__restrict__ lev, in
 // holds 8 accumulators, re-reading its chunk of w from cache per group.
 // ---------------------------------------------------------------------------
 
-// partial <v_i, w> of this block's points for i <= j, by groups of 8
-__device__ __forceinline__ void grouped_dots(const zc *w, const zc *V, size_t vstride, int j, size_t off, unsigned p0,
-                                             unsigned p1, zc *pout, unsigned c, zc *sh, zc *res)
+// Points a thread handles per iteration in the outer passes (loads of all of
+// them issued before any use; indices clamped, stores masked).  Per-thread
+// accumulation still visits points in increasing order.
+constexpr int UO = 4;
+
+// acc[q] += <v_{8g+q}, w> over points p0, p0+BLK, ... < p1 (q with 8g+q <= j)
+__device__ __forceinline__ void dots8(const zc *w, const zc *V, size_t vstride, int g, int j, size_t off, unsigned p0,
+                                      unsigned p1, zc (&acc)[8])
 {
-    for (int g = 0; 8 * g <= j; ++g) {
-        zc acc[8];
+    if (p0 >= p1) return;
+    const unsigned last = p1 - 1;
+    for (unsigned p = p0; p < p1; p += UO * BLK) {
+        zc wv[UO], vv[UO][8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] = mkc(0.0, 0.0);
-        for (unsigned p = p0; p < p1; p += BLK) {
-            const zc wv = w[off + p];
+        for (int k = 0; k < UO; ++k) {
+            const unsigned pk = min(p + k * BLK, last);
+            wv[k] = w[off + pk];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int i = min(8 * g + q, j);
-                const zc v = V[i * vstride + off + p];
-                if (8 * g + q <= j) acc[q] = cjfma(v, wv, acc[q]);
-            }
+            for (int q = 0; q < 8; ++q)
+                if (8 * g + q <= j) vv[k][q] = V[(8 * g + q) * vstride + off + pk];
         }
-        block_sum<8>(acc, 8, sh, res);
-        if (threadIdx.x < 8 && 8 * g + (int)threadIdx.x <= j) pout[(8 * g + threadIdx.x) * NBMAX + c] = res[threadIdx.x];
+#pragma unroll
+        for (int k = 0; k < UO; ++k) {
+            if (p + k * BLK >= p1) break;
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (8 * g + q <= j) acc[q] = cjfma(vv[k][q], wv[k], acc[q]);
+        }
     }
 }
 
-// w = H z and the first-round inner products <v_i, w>, i <= j.
+// block total of group g's accumulators into the partials of values 8g..8g+7
+__device__ __forceinline__ void store_group(zc (&acc)[8], int g, int j, zc *pout, unsigned c, zc *sh, zc *res)
+{
+    block_sum<8>(acc, 8, sh, res);
+    if (threadIdx.x < 8 && 8 * g + (int)threadIdx.x <= j) pout[(8 * g + threadIdx.x) * NBMAX + c] = res[threadIdx.x];
+}
+
+// w = H z and the first-round inner products <v_i, w>, i <= j: the first group
+// of 8 is accumulated while w is formed, later groups re-read w.
 template <typename TZ, int DIM>
 __global__ __launch_bounds__(BLK) void k_hdot(LvlK<double> H, const Cx<TZ> *__restrict__ z, zc *__restrict__ w,
                                               const zc *__restrict__ V, size_t vstride, int j, size_t ld,
                                               zc *__restrict__ pout, unsigned chunk, int nb, const int *active)
 {
+    constexpr int UH = 2;
     __shared__ zc sh[(BLK / 64) * 8];
     __shared__ zc res[8];
     const int rhs = blockIdx.y;
@@ -1253,19 +1271,65 @@ __global__ __launch_bounds__(BLK) void k_hdot(LvlK<double> H, const Cx<TZ> *__re
     zc *po = pout + (size_t)rhs * OVAL * NBMAX;
     const unsigned c = chunk_id(nb);
     const unsigned p0 = c * chunk + threadIdx.x, p1 = min(H.N, c * chunk + chunk);
-    for (unsigned p = p0; p < p1; p += BLK) {
-        unsigned i, jj, k;
-        decomp<DIM>(p, H.nx, H.ny, i, jj, k);
-        w[off + p] = apply_pt<double, DIM>(H, z + off, i, jj, k, p);
+    zc acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = mkc(0.0, 0.0);
+    if (p0 < p1) {
+        const unsigned last = p1 - 1;
+        for (unsigned p = p0; p < p1; p += UH * BLK) {
+            zc wv[UH], vv[UH][8];
+#pragma unroll
+            for (int k = 0; k < UH; ++k) {
+                const unsigned pk = min(p + k * BLK, last);
+                unsigned i, jj, kk;
+                decomp<DIM>(pk, H.nx, H.ny, i, jj, kk);
+                wv[k] = apply_pt<double, DIM>(H, z + off, i, jj, kk, pk);
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (q <= j) vv[k][q] = V[q * vstride + off + pk];
+            }
+#pragma unroll
+            for (int k = 0; k < UH; ++k) {
+                if (p + k * BLK >= p1) break;
+                w[off + p + k * BLK] = wv[k];
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (q <= j) acc[q] = cjfma(vv[k][q], wv[k], acc[q]);
+            }
+        }
     }
-    grouped_dots(w, V, vstride, j, off, p0, p1, po, c, sh, res);
+    store_group(acc, 0, j, po, c, sh, res);
+    for (int g = 1; 8 * g <= j; ++g) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = mkc(0.0, 0.0);
+        dots8(w, V, vstride, g, j, off, p0, p1, acc);
+        store_group(acc, g, j, po, c, sh, res);
+    }
 }
 
-// w -= sum_i a_i v_i with a = hcol (first round) or corr (second round); the
-// second round also produces the partial ||w||^2.
-__global__ __launch_bounds__(BLK) void k_proj(int round, zc *__restrict__ w, const zc *__restrict__ V, size_t vstride,
-                                              int j, unsigned N, size_t ld, const FState *fsb, zc *__restrict__ pout,
-                                              unsigned chunk, int nb, const int *active)
+// x(p) = w(p) - sum_{q <= j} a_q v_q(p) for the U points of one batch
+__device__ __forceinline__ void proj_batch(const zc *w, const zc *V, size_t vstride, int j, size_t off, unsigned p,
+                                           unsigned last, const zc *cc, zc (&x)[UO])
+{
+#pragma unroll
+    for (int k = 0; k < UO; ++k) x[k] = w[off + min(p + k * BLK, last)];
+#pragma unroll 2
+    for (int q = 0; q <= j; ++q) {
+        zc vq[UO];
+        const zc a = cc[q];
+#pragma unroll
+        for (int k = 0; k < UO; ++k) vq[k] = V[q * vstride + off + min(p + k * BLK, last)];
+#pragma unroll
+        for (int k = 0; k < UO; ++k) x[k] = x[k] - a * vq[k];
+    }
+}
+
+// First projection w <- w - sum_i h_i v_i (h = hcol), in place, with the
+// partial ||w||^2 of the result as value j+1 (values 0..j are left to the
+// second-round inner products).
+__global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__restrict__ V, size_t vstride, int j,
+                                               unsigned N, size_t ld, const FState *fsb, zc *__restrict__ pout,
+                                               unsigned chunk, int nb, const int *active)
 {
     __shared__ zc sh[BLK / 64];
     __shared__ zc res[1];
@@ -1273,22 +1337,60 @@ __global__ __launch_bounds__(BLK) void k_proj(int round, zc *__restrict__ w, con
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
     const FState *fs = fsb + rhs;
-    if (threadIdx.x <= j) cc[threadIdx.x] = round == 0 ? fs->hcol[threadIdx.x] : fs->corr[threadIdx.x];
+    if (threadIdx.x <= j) cc[threadIdx.x] = fs->hcol[threadIdx.x];
     __syncthreads();
     const size_t off = rhs * ld;
     zc acc[1] = {mkc(0.0, 0.0)};
     const unsigned c = chunk_id(nb);
-    const unsigned p0 = c * chunk, p1 = min(N, p0 + chunk);
-    for (unsigned p = p0 + threadIdx.x; p < p1; p += BLK) {
-        zc x = w[off + p];
-#pragma unroll 4
-        for (int q = 0; q <= j; ++q) x = x - cc[q] * V[q * vstride + off + p];
-        w[off + p] = x;
-        acc[0].re += cabs2(x);
+    const unsigned p0 = c * chunk + threadIdx.x, p1 = min(N, c * chunk + chunk);
+    if (p0 < p1) {
+        const unsigned last = p1 - 1;
+        for (unsigned p = p0; p < p1; p += UO * BLK) {
+            zc x[UO];
+            proj_batch(w, V, vstride, j, off, p, last, cc, x);
+#pragma unroll
+            for (int k = 0; k < UO; ++k) {
+                if (p + k * BLK >= p1) break;
+                w[off + p + k * BLK] = x[k];
+                acc[0].re += cabs2(x[k]);
+            }
+        }
     }
-    if (round == 0) return;
     block_sum<1>(acc, 1, sh, res);
-    if (threadIdx.x == 0) pout[((size_t)rhs * OVAL) * NBMAX + c] = res[0];
+    if (threadIdx.x == 0) pout[((size_t)rhs * OVAL + j + 1) * NBMAX + c] = res[0];
+}
+
+// Second projection and normalisation: v_{j+1} = (w - sum_i c_i v_i) / h_{j+1,j}
+// (c = corr, 1/h = inv_hn from the finish of the second round), with the
+// optional cycle-precision copy of v_{j+1} (the next V-cycle's input).
+template <typename TB>
+__global__ __launch_bounds__(BLK) void k_proj1(const zc *__restrict__ w, const zc *__restrict__ V, size_t vstride,
+                                               int j, unsigned N, size_t ld, const FState *fsb, zc *__restrict__ vout,
+                                               Cx<TB> *__restrict__ bc, unsigned chunk, int nb, const int *active)
+{
+    __shared__ zc cc[OVAL];
+    const int rhs = blockIdx.y;
+    if (!active[rhs]) return;
+    const FState *fs = fsb + rhs;
+    if (threadIdx.x <= j) cc[threadIdx.x] = fs->corr[threadIdx.x];
+    __syncthreads();
+    const double sc = fs->inv_hn;
+    const size_t off = rhs * ld;
+    const unsigned c = chunk_id(nb);
+    const unsigned p0 = c * chunk + threadIdx.x, p1 = min(N, c * chunk + chunk);
+    if (p0 >= p1) return;
+    const unsigned last = p1 - 1;
+    for (unsigned p = p0; p < p1; p += UO * BLK) {
+        zc x[UO];
+        proj_batch(w, V, vstride, j, off, p, last, cc, x);
+#pragma unroll
+        for (int k = 0; k < UO; ++k) {
+            if (p + k * BLK >= p1) break;
+            const zc v = sc * x[k];
+            vout[off + p + k * BLK] = v;
+            if (bc) bc[off + p + k * BLK] = cvt<TB>(v);
+        }
+    }
 }
 
 // second-round inner products c_i = <v_i, w1>
@@ -1302,8 +1404,15 @@ __global__ __launch_bounds__(BLK) void k_mdot(const zc *__restrict__ w, const zc
     if (!active[rhs]) return;
     const size_t off = rhs * ld;
     const unsigned c = chunk_id(nb);
-    grouped_dots(w, V, vstride, j, off, c * chunk + threadIdx.x, min(N, c * chunk + chunk),
-                 pout + (size_t)rhs * OVAL * NBMAX, c, sh, res);
+    const unsigned p0 = c * chunk + threadIdx.x, p1 = min(N, c * chunk + chunk);
+    zc *po = pout + (size_t)rhs * OVAL * NBMAX;
+    for (int g = 0; 8 * g <= j; ++g) {
+        zc acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = mkc(0.0, 0.0);
+        dots8(w, V, vstride, g, j, off, p0, p1, acc);
+        store_group(acc, g, j, po, c, sh, res);
+    }
 }
 
 // v = w / h (scale from the FGMRES state), optional cycle-precision copy.
@@ -1316,11 +1425,19 @@ __global__ __launch_bounds__(BLK) void k_vnorm(const zc *w, zc *v, Cx<TB> *__res
     const double sc = fsb[rhs].inv_hn;
     const size_t off = rhs * ld;
     const unsigned c = chunk_id(nb);
-    const unsigned p0 = c * chunk, p1 = min(N, p0 + chunk);
-    for (unsigned p = p0 + threadIdx.x; p < p1; p += BLK) {
-        const zc x = sc * w[off + p];
-        v[off + p] = x;
-        if (bc) bc[off + p] = cvt<TB>(x);
+    const unsigned p0 = c * chunk + threadIdx.x, p1 = min(N, c * chunk + chunk);
+    if (p0 >= p1) return;
+    const unsigned last = p1 - 1;
+    for (unsigned p = p0; p < p1; p += UO * BLK) {
+        zc x[UO];
+#pragma unroll
+        for (int k = 0; k < UO; ++k) x[k] = sc * w[off + min(p + k * BLK, last)];
+#pragma unroll
+        for (int k = 0; k < UO; ++k) {
+            if (p + k * BLK >= p1) break;
+            v[off + p + k * BLK] = x[k];
+            if (bc) bc[off + p + k * BLK] = cvt<TB>(x[k]);
+        }
     }
 }
 
@@ -1366,11 +1483,25 @@ __global__ __launch_bounds__(BLK) void k_uupd(zc *__restrict__ u, const Cx<TZ> *
     __syncthreads();
     const size_t off = rhs * ld;
     const unsigned c = chunk_id(nb);
-    const unsigned p0 = c * chunk, p1 = min(N, p0 + chunk);
-    for (unsigned p = p0 + threadIdx.x; p < p1; p += BLK) {
-        zc x = u[off + p];
-        for (int q = 0; q < kc; ++q) x = cfma(yy[q], cvt<double>(Z[q * zstride + off + p]), x);
-        u[off + p] = x;
+    const unsigned p0 = c * chunk + threadIdx.x, p1 = min(N, c * chunk + chunk);
+    if (p0 >= p1) return;
+    const unsigned last = p1 - 1;
+    for (unsigned p = p0; p < p1; p += UO * BLK) {
+        zc x[UO];
+#pragma unroll
+        for (int k = 0; k < UO; ++k) x[k] = u[off + min(p + k * BLK, last)];
+        for (int q = 0; q < kc; ++q) {
+            Cx<TZ> zq[UO];
+#pragma unroll
+            for (int k = 0; k < UO; ++k) zq[k] = Z[q * zstride + off + min(p + k * BLK, last)];
+#pragma unroll
+            for (int k = 0; k < UO; ++k) x[k] = cfma(yy[q], cvt<double>(zq[k]), x[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < UO; ++k) {
+            if (p + k * BLK >= p1) break;
+            u[off + p + k * BLK] = x[k];
+        }
     }
 }
 
@@ -1447,8 +1578,8 @@ __global__ __launch_bounds__(FT) void k_fin(int mode, const zc *__restrict__ pin
         }
         return;
     }
-    // values: FIN_H / FIN_C: 0..j; FIN_BEGIN: 0, 1; others: 0
-    const int nv = (mode == FIN_H || mode == FIN_C) ? j + 1 : (mode == FIN_BEGIN ? 2 : 1);
+    // values: FIN_H: 0..j; FIN_CN: 0..j+1; FIN_BEGIN: 0, 1; others: 0
+    const int nv = mode == FIN_H ? j + 1 : (mode == FIN_CN ? j + 2 : (mode == FIN_BEGIN ? 2 : 1));
     const int grp = threadIdx.x / FG;
     for (int q = grp; q < nv; q += FT / FG) {
         const zc v = group_parts(pp + q * NBMAX, nbin);
@@ -1460,15 +1591,21 @@ __global__ __launch_bounds__(FT) void k_fin(int mode, const zc *__restrict__ pin
     case FIN_H:
         for (int q = 0; q <= j; ++q) fs->hcol[q] = val[q];
         return;
-    case FIN_C:
+    case FIN_CN: {
+        // second-round coefficients c (values 0..j) and ||w1||^2 of the first
+        // projection (value j+1): h_{j+1,j}^2 = ||w1||^2 - ||c||^2, the norm of
+        // w1 - V c for orthonormal V.  A difference at rounding level of
+        // ||w1||^2 means w1 lies in span(V): breakdown, h = 0.
+        double c2 = 0.0;
         for (int q = 0; q <= j; ++q) {
             fs->corr[q] = val[q];
             fs->hcol[q] = fs->hcol[q] + val[q];
+            c2 += cabs2(val[q]);
         }
+        const double w2 = val[j + 1].re, h2 = w2 - c2;
+        givens_column(fs, rep + rhs, j, h2 > 1e-13 * w2 ? sqrt(h2) : 0.0);
         return;
-    case FIN_N:
-        givens_column(fs, rep + rhs, j, sqrt(val[0].re));
-        return;
+    }
     default: {
         // FIN_BEGIN / FIN_BETA: start of a restart cycle
         const double beta = sqrt(val[0].re);
@@ -1629,11 +1766,18 @@ void launch_hdot(const LvlK<double> &H, const Cx<TZ> *z, zc *w, const zc *V, siz
                        g.nb, active);
 }
 
-void launch_proj(int round, zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, const FState *fs,
-                 zc *pout, const Launch &g, const int *active)
+void launch_proj0(zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, const FState *fs, zc *pout,
+                  const Launch &g, const int *active)
 {
-    hipLaunchKernelGGL(k_proj, grid(g), dim3(BLK), 0, g.st, round, w, V, vstride, j, N, ld, fs, pout, g.chunk, g.nb,
-                       active);
+    hipLaunchKernelGGL(k_proj0, grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, pout, g.chunk, g.nb, active);
+}
+
+template <typename TB>
+void launch_proj1(const zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, const FState *fs, zc *vout,
+                  Cx<TB> *bcast, const Launch &g, const int *active)
+{
+    hipLaunchKernelGGL((k_proj1<TB>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, vout, bcast, g.chunk,
+                       g.nb, active);
 }
 
 void launch_mdot(const zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, const FState *fs, zc *pout,
@@ -1731,6 +1875,8 @@ INST_TD(float, 3)
                                    const int *);                                                                   \
     template void launch_vnorm<T>(const zc *, zc *, Cx<T> *, unsigned, size_t, const FState *, const Launch &,     \
                                   const int *);                                                                    \
+    template void launch_proj1<T>(const zc *, const zc *, size_t, int, unsigned, size_t, const FState *, zc *,     \
+                                  Cx<T> *, const Launch &, const int *);                                           \
     template void launch_uupd<T>(zc *, const Cx<T> *, size_t, unsigned, size_t, const FState *, const Launch &,    \
                                  const int *);
 
