@@ -210,8 +210,9 @@ double vcycle_bytes(const csg_operator *op, int nrhs)
     double tot = b.coarse(op->nc);
     for (int l = 0; l + 1 < op->L; ++l) {
         const double N = op->lev[l].N, Nc = op->lev[l + 1].N;
-        // Arnoldi passes of one sweep: pass 0, fused passes, last Gram-Schmidt pass
-        double steps = b.st(0, N) + b.orth(s - 1, N);
+        // Arnoldi passes of one sweep: pass 0 and the fused passes (h_{s,s-1} from
+        // the last pass's sums; the closing pass combines w_{s-1} in place of u_s)
+        double steps = b.st(0, N);
         for (int j = 0; j + 1 < s; ++j) steps += b.os(j, N);
         if (nu1 == 0) tot += b.restrict_b(N, Nc);
         for (int k = 0; k < nu1; ++k) {
@@ -228,9 +229,12 @@ double vcycle_bytes(const csg_operator *op, int nrhs)
     return tot;
 }
 
-// Arnoldi passes of one GMRES(s) sweep on level l with u_0 = B.u[0]: pass 0,
-// s-1 fused Gram-Schmidt + stencil passes, the last Gram-Schmidt pass.  The
-// partials of pass k go to part[k % 2]; the closing pass reads part[s % 2].
+// Arnoldi passes of one GMRES(s) sweep on level l with u_0 = B.u[0]: pass 0 and
+// s-1 fused Gram-Schmidt + stencil passes (large levels: a stencil pass and a
+// Gram-Schmidt pass per step).  The last pass also sums ||w_{s-1}||^2, from
+// which the closing pass takes h_{s,s-1}; w_{s-1} stays in lv.w[(s-1) % 2].
+// The fused passes write partials to part[k % 2] for pass k; the closing pass
+// reads close_part().
 template <typename T, int DIM>
 void arnoldi_passes(const csg_operator *op, int l, const Basis<T> &B, int nrhs, hipStream_t st, const int *active)
 {
@@ -248,6 +252,7 @@ void arnoldi_passes(const csg_operator *op, int l, const Basis<T> &B, int nrhs, 
                 ProfScope ps(op, l == 0 ? CSG_PROF_STENCIL_DOTS : -1, st, by.st(j, lv.N));
                 launch_stj<T, DIM>(L, B, W[j & 1], j, s, lv.ld, lv.part[0], g, active);
             }
+            if (j + 1 == s) break;
             ProfScope ps(op, l == 0 ? CSG_PROF_ORTH : -1, st, by.orth(j, lv.N));
             launch_orthl<T>(B, W[j & 1], j, s, lv.N, lv.ld, lv.part[0], lv.nb, lv.part[1], lv.gs, tiny, g, active);
         }
@@ -255,23 +260,29 @@ void arnoldi_passes(const csg_operator *op, int l, const Basis<T> &B, int nrhs, 
     }
     {
         ProfScope ps(op, l == 0 ? CSG_PROF_STENCIL_DOTS : -1, st, by.st(0, lv.N));
-        launch_st0<T, DIM>(L, B.u[0], W[0], lv.ld, lv.part[0], g, active);
+        launch_st0<T, DIM>(L, B.u[0], W[0], s == 1, lv.ld, lv.part[0], g, active);
     }
     for (int j = 0; j + 1 < s; ++j) {
         ProfScope ps(op, l == 0 ? CSG_PROF_STENCIL_DOTS : -1, st, by.os(j, lv.N));
         launch_os<T, DIM>(L, B, W[j & 1], W[(j + 1) & 1], j, s, lv.ld, lv.part[j & 1], lv.nb, lv.part[(j + 1) & 1],
                           lv.gs, tiny, g, active);
     }
-    ProfScope ps(op, l == 0 ? CSG_PROF_ORTH : -1, st, by.orth(s - 1, lv.N));
-    launch_orthl<T>(B, W[(s - 1) & 1], s - 1, s, lv.N, lv.ld, lv.part[(s - 1) & 1], lv.nb, lv.part[s & 1], lv.gs,
-                    tiny, g, active);
 }
 
-// Partials buffer the closing pass of a sweep on level l reads.
+// Partials buffer the closing pass of a sweep on level l reads (written by the
+// last Arnoldi pass).
 zc *close_part(const csg_operator *op, int l)
 {
     const DevLevel &lv = op->lev[l];
-    return lv.N > op->fuse_max ? lv.part[1] : lv.part[op->p.s & 1];
+    return lv.N > op->fuse_max ? lv.part[0] : lv.part[(op->p.s - 1) & 1];
+}
+
+// Basis the closing pass combines: u_0..u_{s-1} and, in place of u_s, w_{s-1}.
+template <typename T>
+Basis<T> closing_basis(const csg_operator *op, int l, Basis<T> B)
+{
+    B.u[op->p.s] = (Cx<T> *)op->lev[l].w[(op->p.s - 1) & 1];
+    return B;
 }
 
 // One GMRES(s) sweep on level l: Arnoldi passes on u_0 (= b when x == 0, else
@@ -295,17 +306,11 @@ void sweep(const csg_operator *op, int l, const Cx<T> *b, Cx<T> *x, bool from_ze
         B.u[0] = (Cx<T> *)lv.r;
     }
     arnoldi_passes<T, DIM>(op, l, B, nrhs, st, active);
+    B = closing_basis<T>(op, l, B);
     const Bytes by = bytes_of(op, nrhs);
     const int k0 = l == 0 ? 0 : -1;   // instrumented kinds exist for the finest level only
     zc *pclose = close_part(op, l);
-    if (restrict_after && lv.N <= op->fuse_max) {
-        // small level: one pass per coarse point forms the Arnoldi residual on
-        // its fine stencil, restricts it and updates the fine points it owns
-        const DevLevel &cl = op->lev[l + 1];
-        ProfScope ps(op, k0 ? -1 : CSG_PROF_UPD_RESTRICT, st, by.upd_res(s, !from_zero, lv.N, cl.N));
-        launch_upd_res<T, DIM>(x, from_zero ? 0 : 1, B, s, L, lvl<T>(op, l + 1), (Cx<T> *)cl.b, lv.ld, cl.ld, pclose,
-                               lv.nb, lv.gs, tiny, lch(op, l + 1, nrhs, st), active);
-    } else if (restrict_after) {
+    if (restrict_after) {
         // closing update writes x and the Arnoldi residual r; full weighting of r
         const DevLevel &cl = op->lev[l + 1];
         ProfScope ps(op, k0 ? -1 : CSG_PROF_UPD_RESTRICT, st,
@@ -357,14 +362,7 @@ void vcycle_impl(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, h
             launch_prolong<T, DIM>(lvl<T>(op, l), lvl<T>(op, l + 1), (const Cx<T> *)cl.xb, xi, xo, lv.ld, cl.ld, g,
                                    active);
         } else {
-            if (lv.N <= op->fuse_max) {
-                // small level: correction and residual in one pass (the
-                // corrected x recomputed at the stencil neighbours)
-                ProfScope ps(op, l == 0 ? CSG_PROF_PROLONG_RESID : -1, st,
-                             bytes_of(op, nrhs).prc(xi != nullptr, lv.N, cl.N));
-                launch_prc<T, DIM>(lvl<T>(op, l), lvl<T>(op, l + 1), (const Cx<T> *)cl.xb, xi, xo, b, (Cx<T> *)lv.r,
-                                   lv.ld, cl.ld, g, active);
-            } else {
+            {
                 // interpolated correction, then the residual that opens the post-sweep
                 const Bytes by = bytes_of(op, nrhs);
                 ProfScope ps(op, l == 0 ? CSG_PROF_PROLONG_RESID : -1, st,
@@ -384,6 +382,7 @@ void vcycle_impl(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, h
                 if (k > 0) launch_resid<T, DIM>(Lk, xo, b, (Cx<T> *)d.r, d.ld, g, active);
                 B.u[0] = (Cx<T> *)d.r;
                 arnoldi_passes<T, DIM>(op, l, B, nrhs, st, active);
+                B = closing_basis<T>(op, l, B);
                 ProfScope ps(op, l == 0 ? CSG_PROF_UPDATE : -1, st, bytes_of(op, nrhs).upd(s, true, d.N));
                 launch_upd<T>(xo, 1, B, s, d.N, d.ld, close_part(op, l), d.nb, d.gs, tiny, g, active);
             }

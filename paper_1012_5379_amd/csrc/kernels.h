@@ -43,11 +43,13 @@ template <typename T, int DIM>
 void launch_apply(const LvlK<T> &L, const void *x, void *y, size_t ld, const Launch &g, const int *active);
 
 // GMRES(s) Arnoldi passes on the raw basis (see kernels.hip): pass 0, fused
-// Gram-Schmidt + stencil passes j = 0..s-2, and the last Gram-Schmidt pass.
+// Gram-Schmidt + stencil passes j = 0..s-2; the last of them also sums
+// ||w_{s-1}||^2 (wn) so the closing pass needs no further Gram-Schmidt pass.
 template <typename T, int DIM>
-void launch_st0(const LvlK<T> &L, const Cx<T> *u0, Cx<T> *w, size_t ld, zc *pout, const Launch &g, const int *active);
+void launch_st0(const LvlK<T> &L, const Cx<T> *u0, Cx<T> *w, int wn, size_t ld, zc *pout, const Launch &g,
+                const int *active);
 
-// unfused pass: w = A u_j, <u_i, w> (i <= j) and ||u_j||^2
+// unfused pass: w = A u_j, <u_i, w> (i <= j) and ||u_j||^2 (and ||w||^2 when j = s-1)
 template <typename T, int DIM>
 void launch_stj(const LvlK<T> &L, const Basis<T> &B, Cx<T> *w, int j, int s, size_t ld, zc *pout, const Launch &g,
                 const int *active);

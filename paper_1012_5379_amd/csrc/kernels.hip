@@ -132,9 +132,12 @@ __device__ __forceinline__ void rot(zc a, zc b, double &c, zc &s)
 // Least squares of one GMRES(s) sweep: y = argmin || beta0 e1 - Hbar y || over
 // the first k Arnoldi columns, and the residual coefficients
 // cres = beta0 e1 - Hbar y (so that r = sum_i cres_i v_i).  R is caller
-// scratch of (CSG_MAX_S+1) * CSG_MAX_S values.  Returns k.
+// scratch of (CSG_MAX_S+1) * CSG_MAX_S values.  Returns k.  SB - 1 bounds s:
+// the loops are unrolled to it so the rotations, g and y stay in registers.
+template <int SB>
 __device__ int gmres_ls(const GState *gs, int s, double hn_last, zc *R, zc *y, zc *cres)
 {
+    constexpr int K = SB - 1;
     const double beta0 = gs->beta0;
     int k = gs->k;
     if (k > s) k = s;
@@ -145,12 +148,16 @@ __device__ int gmres_ls(const GState *gs, int s, double hn_last, zc *R, zc *y, z
     };
     for (int i = 0; i <= k; ++i)
         for (int c = 0; c < k; ++c) R[i * CSG_MAX_S + c] = hget(i, c);
-    zc g[CSG_MAX_S + 1];
-    for (int i = 0; i <= CSG_MAX_S; ++i) g[i] = mkc(0.0, 0.0);
+    zc g[K + 1], yl[K];
+    double cs[K];
+    zc sn[K];
+#pragma unroll
+    for (int i = 0; i <= K; ++i) g[i] = mkc(0.0, 0.0);
     g[0] = mkc(beta0, 0.0);
-    double cs[CSG_MAX_S];
-    zc sn[CSG_MAX_S];
-    for (int c = 0; c < k; ++c) {
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        if (c >= k) break;
+#pragma unroll
         for (int i = 0; i < c; ++i) {
             const zc t1 = R[i * CSG_MAX_S + c], t2 = R[(i + 1) * CSG_MAX_S + c];
             R[i * CSG_MAX_S + c] = cs[i] * t1 + sn[i] * t2;
@@ -164,15 +171,27 @@ __device__ int gmres_ls(const GState *gs, int s, double hn_last, zc *R, zc *y, z
         g[c + 1] = mkc(0.0, 0.0) - mkc(sn[c].re, -sn[c].im) * gc;
         g[c] = cs[c] * gc;
     }
-    for (int i = k - 1; i >= 0; --i) {
-        zc acc = g[i];
-        for (int c = i + 1; c < k; ++c) acc = acc - R[i * CSG_MAX_S + c] * y[c];
-        const zc d = R[i * CSG_MAX_S + i];
-        y[i] = (1.0 / cabs2(d)) * (acc * mkc(d.re, -d.im));
+#pragma unroll
+    for (int i = K - 1; i >= 0; --i) {
+        if (i < k) {
+            zc acc = g[i];
+#pragma unroll
+            for (int c = i + 1; c < K; ++c)
+                if (c < k) acc = acc - R[i * CSG_MAX_S + c] * yl[c];
+            const zc d = R[i * CSG_MAX_S + i];
+            yl[i] = (1.0 / cabs2(d)) * (acc * mkc(d.re, -d.im));
+        }
     }
-    for (int i = 0; i <= k; ++i) {
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+        if (i < k) y[i] = yl[i];
+#pragma unroll
+    for (int i = 0; i <= K; ++i) {
+        if (i > k) break;
         zc acc = (i == 0) ? mkc(beta0, 0.0) : mkc(0.0, 0.0);
-        for (int c = 0; c < k; ++c) acc = acc - hget(i, c) * y[c];
+#pragma unroll
+        for (int c = 0; c < K; ++c)
+            if (c < k) acc = acc - hget(i, c) * yl[c];
         cres[i] = acc;
     }
     return k;
@@ -220,10 +239,11 @@ struct Ubatch {
 // the stencil neighbours; the last pass forms u_s only.  Every pass emits the
 // partial sums <u_i, w> (i up to its newest vector) and ||newest u||^2.
 
-// pass 0: w = A u_0, acc[0] += <u_0, w>, acc[1] += ||u_0||^2
-template <typename T, int DIM>
+// pass 0: w = A u_0, acc[0] += <u_0, w>, acc[1] += ||u_0||^2 (and, with NA = 3,
+// acc[2] += ||w||^2 for a sweep of one step)
+template <typename T, int DIM, int NA = 2>
 __device__ __forceinline__ void body_st0(const LvlK<T> &L, const Cx<T> *u0, Cx<T> *w, unsigned p0, unsigned p1,
-                                         unsigned st, zc (&acc)[2])
+                                         unsigned st, zc (&acc)[NA])
 {
     constexpr int U = Ubatch<T>::U;
     if (p0 >= p1) return;
@@ -245,14 +265,16 @@ __device__ __forceinline__ void body_st0(const LvlK<T> &L, const Cx<T> *u0, Cx<T
             const zc wd = cvt<double>(wv[k]), ud = cvt<double>(uc[k]);
             acc[0] = cjfma(ud, wd, acc[0]);
             acc[1].re += cabs2(ud);
+            if (NA > 2) acc[NA - 1].re += cabs2(wd);
         }
     }
 }
 
-// unfused pass 2j: w_j = A u_j, acc[i] += <u_i, w_j> (i <= j), acc[j+1] += ||u_j||^2
+// unfused pass 2j: w_j = A u_j, acc[i] += <u_i, w_j> (i <= j), acc[j+1] += ||u_j||^2,
+// and with wn (the last step of a sweep) acc[j+2] += ||w_j||^2
 template <typename T, int DIM, int SB>
 __device__ __forceinline__ void body_stj(const LvlK<T> &L, const Basis<T> &B, Cx<T> *w, int j, size_t off,
-                                         unsigned p0, unsigned p1, unsigned st, zc (&acc)[SB])
+                                         unsigned p0, unsigned p1, unsigned st, zc (&acc)[SB + 1], bool wn)
 {
     constexpr int U = Ubatch<T>::U;
     const Cx<T> *uj = pick(B, j) + off;
@@ -280,6 +302,7 @@ __device__ __forceinline__ void body_stj(const LvlK<T> &L, const Basis<T> &B, Cx
             for (int q = 0; q < SB - 1; ++q) {
                 if (q <= j) acc[q] = cjfma(cvt<double>(uq[k][q]), wd, acc[q]);
                 if (q == j) acc[q + 1].re += cabs2(cvt<double>(uq[k][q]));
+                if (q == j && wn) acc[q + 2].re += cabs2(wd);
             }
         }
     }
@@ -299,10 +322,11 @@ __device__ __forceinline__ Cx<T> next_u(const Basis<T> &B, const Cx<T> *win, int
 
 // pass j+1: u_{j+1} (written to B.u[j+1]), w_{j+1} = A u_{j+1} (written to wout),
 // acc[i] += <u_i, w_{j+1}> for i <= j+1, acc[j+2] += ||u_{j+1}||^2
-template <typename T, int DIM, int SB>
+// (with wn, the last step of a sweep: acc[j+3] += ||w_{j+1}||^2; NA >= SB + 1)
+template <typename T, int DIM, int SB, int NA>
 __device__ __forceinline__ void body_os(const LvlK<T> &L, const Basis<T> &B, const Cx<T> *win, Cx<T> *wout, int j,
                                         T sj, const Cx<T> (&cu)[SB], size_t off, unsigned p0, unsigned p1,
-                                        unsigned st, zc (&acc)[SB])
+                                        unsigned st, zc (&acc)[NA], bool wn)
 {
     Cx<T> *un = pick(B, j + 1) + off;
     const Cx<T> *wi = win + off;
@@ -347,6 +371,11 @@ __device__ __forceinline__ void body_os(const LvlK<T> &L, const Basis<T> &B, con
         for (int q = 1; q < SB; ++q) {
             if (q == j + 1) acc[q] = cjfma(ud, wd, acc[q]);
             if (q == j + 2) acc[q].re += cabs2(ud);
+        }
+        if (wn) {
+#pragma unroll
+            for (int q = 3; q < NA; ++q)
+                if (q == j + 3) acc[q].re += cabs2(wd);
         }
     }
 }
@@ -769,40 +798,44 @@ __global__ __launch_bounds__(BLK) void k_apply(LvlK<T> L, const Cx<T> *__restric
     body_apply<T, DIM>(L, x + rhs * ld, y + rhs * ld, p0 + threadIdx.x, p1, BLK);
 }
 
-// pass 0 of a sweep: w_0 = A u_0 with <u_0, w_0> and ||u_0||^2
-template <typename T, int DIM>
+// pass 0 of a sweep: w_0 = A u_0 with <u_0, w_0> and ||u_0||^2 (NA = 3: and
+// ||w_0||^2, when the sweep has one step)
+template <typename T, int DIM, int NA>
 __global__ __launch_bounds__(BLK) void k_st0(LvlK<T> L, const Cx<T> *u0, Cx<T> *w, size_t ld, zc *__restrict__ pout,
                                              unsigned chunk, int nb, const int *active)
 {
-    __shared__ zc sh[(BLK / 64) * 2];
-    __shared__ zc res[2];
+    __shared__ zc sh[(BLK / 64) * NA];
+    __shared__ zc res[NA];
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
-    zc acc[2] = {mkc(0.0, 0.0), mkc(0.0, 0.0)};
+    zc acc[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) acc[q] = mkc(0.0, 0.0);
     const unsigned c = chunk_id(nb);
     const unsigned p0 = c * chunk, p1 = min(L.N, p0 + chunk);
-    body_st0<T, DIM>(L, u0 + rhs * ld, w + rhs * ld, p0 + threadIdx.x, p1, BLK, acc);
-    block_sum<2>(acc, 2, sh, res);
-    if (threadIdx.x < 2) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + c] = res[threadIdx.x];
+    body_st0<T, DIM, NA>(L, u0 + rhs * ld, w + rhs * ld, p0 + threadIdx.x, p1, BLK, acc);
+    block_sum<NA>(acc, NA, sh, res);
+    if (threadIdx.x < NA) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + c] = res[threadIdx.x];
 }
 
 // unfused pass 2j: w_j = A u_j with <u_i, w_j> (i <= j) and ||u_j||^2
 template <typename T, int DIM, int SB>
-__global__ __launch_bounds__(BLK) void k_stj(LvlK<T> L, Basis<T> B, Cx<T> *w, int j, size_t ld, zc *__restrict__ pout,
-                                             unsigned chunk, int nb, const int *active)
+__global__ __launch_bounds__(BLK) void k_stj(LvlK<T> L, Basis<T> B, Cx<T> *w, int j, int wn, size_t ld,
+                                             zc *__restrict__ pout, unsigned chunk, int nb, const int *active)
 {
-    __shared__ zc sh[(BLK / 64) * NVAL];
-    __shared__ zc res[NVAL];
+    __shared__ zc sh[(BLK / 64) * (SB + 1)];
+    __shared__ zc res[SB + 1];
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
-    zc acc[SB];
+    zc acc[SB + 1];
 #pragma unroll
-    for (int q = 0; q < SB; ++q) acc[q] = mkc(0.0, 0.0);
+    for (int q = 0; q <= SB; ++q) acc[q] = mkc(0.0, 0.0);
     const unsigned c = chunk_id(nb);
     const unsigned p0 = c * chunk, p1 = min(L.N, p0 + chunk);
-    body_stj<T, DIM, SB>(L, B, w, j, rhs * ld, p0 + threadIdx.x, p1, BLK, acc);
-    block_sum<SB>(acc, j + 2, sh, res);
-    if (threadIdx.x < j + 2) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + c] = res[threadIdx.x];
+    body_stj<T, DIM, SB>(L, B, w, j, rhs * ld, p0 + threadIdx.x, p1, BLK, acc, wn != 0);
+    const int nv = j + 2 + (wn ? 1 : 0);
+    block_sum<SB + 1>(acc, nv, sh, res);
+    if (threadIdx.x < nv) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + c] = res[threadIdx.x];
 }
 
 // pass j+1 (j < s-1): u_{j+1} and w_{j+1} = A u_{j+1} in one sweep of the grid
@@ -811,22 +844,24 @@ __global__ __launch_bounds__(BLK) void k_os(LvlK<T> L, Basis<T> B, const Cx<T> *
                                             size_t ld, const zc *__restrict__ pin, int nbin, zc *__restrict__ pout,
                                             GState *gsb, double tiny, unsigned chunk, int nb, const int *active)
 {
-    __shared__ zc sh[(BLK / 64) * NVAL];
-    __shared__ zc res[NVAL];
+    __shared__ zc sh[(BLK / 64) * (SB + 1)];
+    __shared__ zc res[SB + 1];
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
     GState *gs = gsb + rhs;
-    reduce_parts<SB>(pin + (size_t)rhs * NVAL * NBMAX, nbin, j + 2, sh, res);
+    reduce_parts<SB + 1>(pin + (size_t)rhs * NVAL * NBMAX, nbin, j + 2, sh, res);
     Cx<T> cu[SB];
     const double sj = coef_step<T, SB>(res, j, s, tiny, gs, blockIdx.x == 0 && threadIdx.x == 0, cu);
-    zc acc[SB];
+    zc acc[SB + 1];
 #pragma unroll
-    for (int q = 0; q < SB; ++q) acc[q] = mkc(0.0, 0.0);
+    for (int q = 0; q <= SB; ++q) acc[q] = mkc(0.0, 0.0);
     const unsigned c = chunk_id(nb);
     const unsigned p0 = c * chunk, p1 = min(L.N, p0 + chunk);
-    body_os<T, DIM, SB>(L, B, win, wout, j, (T)sj, cu, rhs * ld, p0 + threadIdx.x, p1, BLK, acc);
-    block_sum<SB>(acc, j + 3, sh, res);
-    if (threadIdx.x < j + 3) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + c] = res[threadIdx.x];
+    const bool wn = j + 2 == s;   // last step of the sweep
+    body_os<T, DIM, SB, SB + 1>(L, B, win, wout, j, (T)sj, cu, rhs * ld, p0 + threadIdx.x, p1, BLK, acc, wn);
+    const int nv = j + 3 + (wn ? 1 : 0);
+    block_sum<SB + 1>(acc, nv, sh, res);
+    if (threadIdx.x < nv) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + c] = res[threadIdx.x];
 }
 
 // last pass: u_s and ||u_s||^2
@@ -851,26 +886,50 @@ __global__ __launch_bounds__(BLK) void k_orthl(Basis<T> B, const Cx<T> *win, int
     if (threadIdx.x == 0) pout[((size_t)rhs * NVAL) * NBMAX + c] = res[0];
 }
 
-// Shared prologue of the sweep's closing passes: finish h_{s,s-1}, solve the
-// small least-squares problem and publish coefficients in shared memory:
-// ax[i] = y_i sig_i (update), ar[i] = cres_i sig_i (Arnoldi residual).
+// Shared prologue of the sweep's closing passes.  The last Arnoldi pass left
+// <u_i, w_{s-1}> (i < s), ||u_{s-1}||^2 and ||w_{s-1}||^2 with w_{s-1} = A u_{s-1}:
+// finish column s-1 of the Hessenberg matrix (coef_step), take h_{s,s-1} from
+// ||A v_{s-1}||^2 = sum_i |h_{i,s-1}|^2 + h_{s,s-1}^2 (v_i orthonormal), so u_s
+// itself is never formed, solve the small least-squares problem and publish
+// ax[i] = y_i sig_i (update) and the Arnoldi residual on {u_0..u_{s-1}, w_{s-1}}:
+// r = sum_{i<s} ar_i u_i + ar_s w_{s-1} (u_s = sig_{s-1} w_{s-1} - sum_i cu_i u_i
+// folded in).  Every block finishes the column in its own shared copy of the
+// state; block 0 publishes it.
+template <typename T, int SB>
 __device__ int close_sweep(const zc *pin, int nbin, GState *gs, int s, double tiny, zc *sh, zc *res, zc *ax, zc *ar)
 {
-    reduce_parts<1>(pin, nbin, 1, sh, res);
+    __shared__ GState lg;
     __shared__ int ks;
     __shared__ zc Rs[(CSG_MAX_S + 1) * CSG_MAX_S], ys[CSG_MAX_S], crs[CSG_MAX_S + 1];
+    {
+        const double *src = (const double *)gs;
+        double *dst = (double *)&lg;
+        for (int i = threadIdx.x; i < (int)(sizeof(GState) / sizeof(double)); i += blockDim.x) dst[i] = src[i];
+    }
+    reduce_parts<SB + 1>(pin, nbin, s + 2, sh, res);
     if (threadIdx.x == 0) {
-        const double hn = sqrt(res[0].re);
-        const bool brk = !(hn > tiny * gs->beta0);
+        Cx<T> cu[SB];
+        const double sj = coef_step<T, SB>(res, s - 1, s, tiny, &lg, true, cu);
+        double h2 = sj * sj * res[s + 1].re;
+        for (int i = 0; i < s; ++i) h2 -= cabs2(lg.H[i * CSG_MAX_S + (s - 1)]);
+        // a difference at rounding level of ||A v_{s-1}||^2: A v_{s-1} lies in the basis span
+        const double hn = h2 > 1e-13 * (sj * sj * res[s + 1].re) ? sqrt(h2) : 0.0;
+        const bool brk = !(hn > tiny * lg.beta0);
         const double sig_s = brk ? 0.0 : 1.0 / hn;
-        const int k = gmres_ls(gs, s, hn, Rs, ys, crs);
-        for (int i = 0; i < k; ++i) ax[i] = gs->sig[i] * ys[i];
-        for (int i = 0; i <= k; ++i) ar[i] = ((i == s) ? sig_s : gs->sig[i]) * crs[i];
+        const int k = gmres_ls<SB>(&lg, s, hn, Rs, ys, crs);
+        for (int i = 0; i < k; ++i) ax[i] = lg.sig[i] * ys[i];
+        for (int i = 0; i <= k; ++i) ar[i] = ((i == s) ? sig_s : lg.sig[i]) * crs[i];
+        if (k == s) {
+            const zc as = ar[s];
+            for (int i = 0; i < s; ++i) ar[i] = ar[i] - as * cvt<double>(cu[i]);
+            ar[s] = sj * as;
+        }
         ks = k;
         if (blockIdx.x == 0) {
-            gs->H[s * CSG_MAX_S + (s - 1)] = mkc(hn, 0.0);
-            gs->sig[s] = sig_s;
-            for (int i = 0; i < k; ++i) gs->y[i] = ys[i];
+            lg.H[s * CSG_MAX_S + (s - 1)] = mkc(hn, 0.0);
+            lg.sig[s] = sig_s;
+            for (int i = 0; i < k; ++i) lg.y[i] = ys[i];
+            *gs = lg;
         }
     }
     __syncthreads();
@@ -893,12 +952,12 @@ __global__ __launch_bounds__(BLK) void k_upd(Cx<T> *x, int accumulate, Basis<T> 
                                              const zc *__restrict__ pin, int nbin, GState *gsb, double tiny,
                                              unsigned chunk, int nb, const int *active)
 {
-    __shared__ zc sh[BLK / 64];
-    __shared__ zc res[1];
+    __shared__ zc sh[(BLK / 64) * (SB + 1)];
+    __shared__ zc res[SB + 1];
     __shared__ zc ax[CSG_MAX_S], ar[CSG_MAX_S + 1];
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
-    const int k = close_sweep(pin + (size_t)rhs * NVAL * NBMAX, nbin, gsb + rhs, s, tiny, sh, res, ax, ar);
+    const int k = close_sweep<T, SB>(pin + (size_t)rhs * NVAL * NBMAX, nbin, gsb + rhs, s, tiny, sh, res, ax, ar);
     Cx<T> cx[SB], cr[SB];
     coefs_to_T<T, SB>(k, ax, ar, cx, cr);
     const unsigned c = chunk_id(nb);
@@ -912,12 +971,12 @@ __global__ __launch_bounds__(BLK) void k_upd_res(Cx<T> *x, int accumulate, Basis
                                                  int nbin, GState *gsb, double tiny, unsigned chunk, int nb,
                                                  const int *active)
 {
-    __shared__ zc sh[BLK / 64];
-    __shared__ zc res[1];
+    __shared__ zc sh[(BLK / 64) * (SB + 1)];
+    __shared__ zc res[SB + 1];
     __shared__ zc ax[CSG_MAX_S], ar[CSG_MAX_S + 1];
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
-    const int k = close_sweep(pin + (size_t)rhs * NVAL * NBMAX, nbin, gsb + rhs, s, tiny, sh, res, ax, ar);
+    const int k = close_sweep<T, SB>(pin + (size_t)rhs * NVAL * NBMAX, nbin, gsb + rhs, s, tiny, sh, res, ax, ar);
     Cx<T> cx[SB], cr[SB];
     coefs_to_T<T, SB>(k, ax, ar, cx, cr);
     const unsigned c = chunk_id(nb);
@@ -931,12 +990,12 @@ __global__ __launch_bounds__(BLK) void k_upd_r(Cx<T> *x, int accumulate, Cx<T> *
                                                size_t ld, const zc *__restrict__ pin, int nbin, GState *gsb,
                                                double tiny, unsigned chunk, int nb, const int *active)
 {
-    __shared__ zc sh[BLK / 64];
-    __shared__ zc res[1];
+    __shared__ zc sh[(BLK / 64) * (SB + 1)];
+    __shared__ zc res[SB + 1];
     __shared__ zc ax[CSG_MAX_S], ar[CSG_MAX_S + 1];
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
-    const int k = close_sweep(pin + (size_t)rhs * NVAL * NBMAX, nbin, gsb + rhs, s, tiny, sh, res, ax, ar);
+    const int k = close_sweep<T, SB>(pin + (size_t)rhs * NVAL * NBMAX, nbin, gsb + rhs, s, tiny, sh, res, ax, ar);
     Cx<T> cx[SB], cr[SB];
     coefs_to_T<T, SB>(k, ax, ar, cx, cr);
     const unsigned c = chunk_id(nb);
@@ -1080,7 +1139,7 @@ __device__ void tail_steps(const LvlK<T> &L, const Basis<T> &B, Cx<T> *w0, Cx<T>
             zc acc[SB];
 #pragma unroll
             for (int q = 0; q < SB; ++q) acc[q] = mkc(0.0, 0.0);
-            body_os<T, DIM, SB>(L, B, win, wout, j, (T)sj, cu, off, threadIdx.x, L.N, TB, acc);
+            body_os<T, DIM, SB, SB>(L, B, win, wout, j, (T)sj, cu, off, threadIdx.x, L.N, TB, acc, false);
             tail_sum<SB>(acc, j + 3, sh, res);
         } else {
             zc nr[1] = {mkc(0.0, 0.0)};
@@ -1105,7 +1164,7 @@ __device__ int tail_close(const GState *gs, int s, zc *Rs, zc *ys, zc *crs, zc *
 {
     if (threadIdx.x == 0) {
         const double hn = gs->H[s * CSG_MAX_S + (s - 1)].re;
-        const int k = gmres_ls(gs, s, hn, Rs, ys, crs);
+        const int k = gmres_ls<SB>(gs, s, hn, Rs, ys, crs);
         for (int i = 0; i < k; ++i) ax[i] = gs->sig[i] * ys[i];
         for (int i = 0; i <= k; ++i) ar[i] = gs->sig[i] * crs[i];
         *ks = k;
@@ -1643,20 +1702,26 @@ void launch_apply(const LvlK<T> &L, const void *x, void *y, size_t ld, const Lau
 }
 
 template <typename T, int DIM>
-void launch_st0(const LvlK<T> &L, const Cx<T> *u0, Cx<T> *w, size_t ld, zc *pout, const Launch &g, const int *active)
+void launch_st0(const LvlK<T> &L, const Cx<T> *u0, Cx<T> *w, int wn, size_t ld, zc *pout, const Launch &g,
+                const int *active)
 {
-    hipLaunchKernelGGL((k_st0<T, DIM>), grid(g), dim3(BLK), 0, g.st, L, u0, w, ld, pout, g.chunk, g.nb, active);
+    if (wn)
+        hipLaunchKernelGGL((k_st0<T, DIM, 3>), grid(g), dim3(BLK), 0, g.st, L, u0, w, ld, pout, g.chunk, g.nb, active);
+    else
+        hipLaunchKernelGGL((k_st0<T, DIM, 2>), grid(g), dim3(BLK), 0, g.st, L, u0, w, ld, pout, g.chunk, g.nb, active);
 }
 
 template <typename T, int DIM>
 void launch_stj(const LvlK<T> &L, const Basis<T> &B, Cx<T> *w, int j, int s, size_t ld, zc *pout, const Launch &g,
                 const int *active)
 {
+    const int wn = j + 1 == s;
     if (s <= 3)
-        hipLaunchKernelGGL((k_stj<T, DIM, 4>), grid(g), dim3(BLK), 0, g.st, L, B, w, j, ld, pout, g.chunk, g.nb, active);
-    else
-        hipLaunchKernelGGL((k_stj<T, DIM, NVAL - 1>), grid(g), dim3(BLK), 0, g.st, L, B, w, j, ld, pout, g.chunk, g.nb,
+        hipLaunchKernelGGL((k_stj<T, DIM, 4>), grid(g), dim3(BLK), 0, g.st, L, B, w, j, wn, ld, pout, g.chunk, g.nb,
                            active);
+    else
+        hipLaunchKernelGGL((k_stj<T, DIM, NVAL - 1>), grid(g), dim3(BLK), 0, g.st, L, B, w, j, wn, ld, pout, g.chunk,
+                           g.nb, active);
 }
 
 template <typename T, int DIM>
@@ -1837,7 +1902,7 @@ void launch_copy_mask(const int *src, int *dst, int n, hipStream_t st)
 
 #define INST_TD(T, D)                                                                                               \
     template void launch_apply<T, D>(const LvlK<T> &, const void *, void *, size_t, const Launch &, const int *);  \
-    template void launch_st0<T, D>(const LvlK<T> &, const Cx<T> *, Cx<T> *, size_t, zc *, const Launch &,          \
+    template void launch_st0<T, D>(const LvlK<T> &, const Cx<T> *, Cx<T> *, int, size_t, zc *, const Launch &,     \
                                    const int *);                                                                   \
     template void launch_stj<T, D>(const LvlK<T> &, const Basis<T> &, Cx<T> *, int, int, size_t, zc *,             \
                                    const Launch &, const int *);                                                   \
