@@ -734,9 +734,26 @@ __device__ __forceinline__ void body_coarse(const Cx<T> *minvT, int n, const Cx<
 // h_ij = sig_i sig_j <u_i, w_j>, and the Gram-Schmidt coefficients
 // cu_i = sig_i h_ij of u_{j+1}.  Returns sig_j.  `store` publishes the state
 // (sig_i for i < j come from the state written by earlier passes).
+// State of the earlier passes of a sweep that coef_step reads (beta0, sig_i),
+// loaded at kernel entry so the loads overlap the partial-sum reduction.
+template <int SB>
+struct GPrev {
+    double beta0;
+    double sig[SB];
+};
+template <int SB>
+__device__ __forceinline__ GPrev<SB> load_prev(const GState *gs, int j)
+{
+    GPrev<SB> g;
+    g.beta0 = gs->beta0;
+#pragma unroll
+    for (int q = 0; q < SB; ++q) g.sig[q] = q < j ? gs->sig[q] : 0.0;
+    return g;
+}
+
 template <typename T, int SB>
-__device__ __forceinline__ double coef_step(const zc *res, int j, int s, double tiny, GState *gs, bool store,
-                                            Cx<T> (&cu)[SB])
+__device__ __forceinline__ double coef_step(const zc *res, int j, int s, double tiny, const GPrev<SB> &pv, GState *gs,
+                                            bool store, Cx<T> (&cu)[SB])
 {
     double sig[SB];
     double nrm2 = 0.0;
@@ -750,13 +767,13 @@ __device__ __forceinline__ double coef_step(const zc *res, int j, int s, double 
         beta0 = hn;
         sj = beta0 > 0.0 ? 1.0 / beta0 : 0.0;
     } else {
-        beta0 = gs->beta0;
+        beta0 = pv.beta0;
         brk = !(hn > tiny * beta0);
         sj = brk ? 0.0 : 1.0 / hn;
     }
 #pragma unroll
     for (int q = 0; q < SB; ++q) {
-        if (q < j) sig[q] = gs->sig[q];
+        if (q < j) sig[q] = pv.sig[q];
         if (q == j) sig[q] = sj;
     }
     zc h[SB];
@@ -849,9 +866,10 @@ __global__ __launch_bounds__(BLK) void k_os(LvlK<T> L, Basis<T> B, const Cx<T> *
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
     GState *gs = gsb + rhs;
+    const GPrev<SB> pv = load_prev<SB>(gs, j);
     reduce_parts<SB + 1>(pin + (size_t)rhs * NVAL * NBMAX, nbin, j + 2, sh, res);
     Cx<T> cu[SB];
-    const double sj = coef_step<T, SB>(res, j, s, tiny, gs, blockIdx.x == 0 && threadIdx.x == 0, cu);
+    const double sj = coef_step<T, SB>(res, j, s, tiny, pv, gs, blockIdx.x == 0 && threadIdx.x == 0, cu);
     zc acc[SB + 1];
 #pragma unroll
     for (int q = 0; q <= SB; ++q) acc[q] = mkc(0.0, 0.0);
@@ -875,9 +893,10 @@ __global__ __launch_bounds__(BLK) void k_orthl(Basis<T> B, const Cx<T> *win, int
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
     GState *gs = gsb + rhs;
+    const GPrev<SB> pv = load_prev<SB>(gs, j);
     reduce_parts<SB>(pin + (size_t)rhs * NVAL * NBMAX, nbin, j + 2, sh, res);
     Cx<T> cu[SB];
-    const double sj = coef_step<T, SB>(res, j, s, tiny, gs, blockIdx.x == 0 && threadIdx.x == 0, cu);
+    const double sj = coef_step<T, SB>(res, j, s, tiny, pv, gs, blockIdx.x == 0 && threadIdx.x == 0, cu);
     zc acc[1] = {mkc(0.0, 0.0)};
     const unsigned c = chunk_id(nb);
     const unsigned p0 = c * chunk, p1 = min(N, p0 + chunk);
@@ -895,11 +914,202 @@ __global__ __launch_bounds__(BLK) void k_orthl(Basis<T> B, const Cx<T> *win, int
 // r = sum_{i<s} ar_i u_i + ar_s w_{s-1} (u_s = sig_{s-1} w_{s-1} - sum_i cu_i u_i
 // folded in).  Every block finishes the column in its own shared copy of the
 // state; block 0 publishes it.
+// Register-resident form of the closing least squares for s <= SB - 1 <= 3,
+// run by one thread: gathers columns 0..s-2 of the sweep's state, finishes
+// column s-1 and h_{s,s-1} as described above, and writes ax, ar (shared) and
+// k.  With `publish` the finished state goes back to gs.  The arithmetic is the
+// same, operation for operation, as coef_step followed by gmres_ls.
+template <int SB>
+struct CloseIn {
+    zc H[SB][SB - 1];
+    double sig[SB];
+    double beta0;
+    int k;
+};
+
+// columns 0..s-2 of the sweep's state (loaded before the partial-sum reduction)
+template <int SB>
+__device__ __forceinline__ void close_gather(const GState *gs, int s, CloseIn<SB> &in)
+{
+    constexpr int K = SB - 1;
+    const int j = s - 1;
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+#pragma unroll
+        for (int r = 0; r < SB; ++r) in.H[r][c] = mkc(0.0, 0.0);
+        in.sig[c] = 0.0;
+        if (c < j) {
+            in.sig[c] = gs->sig[c];
+#pragma unroll
+            for (int r = 0; r < SB; ++r)
+                if (r <= c + 1 && !(c + 1 == j && r == j)) in.H[r][c] = gs->H[r * CSG_MAX_S + c];
+        }
+    }
+    in.sig[K] = 0.0;
+    in.k = gs->k;
+    in.beta0 = gs->beta0;
+}
+
+template <typename T, int SB>
+__device__ void close_regs(const CloseIn<SB> &in, GState *gs, const zc *res, int s, double tiny, bool publish, zc *ax,
+                           zc *ar, int *ks)
+{
+    constexpr int K = SB - 1;
+    const int j = s - 1;
+    zc H[SB][K];
+    double sig[SB];
+#pragma unroll
+    for (int r = 0; r < SB; ++r) {
+        sig[r] = in.sig[r];
+#pragma unroll
+        for (int c = 0; c < K; ++c) H[r][c] = in.H[r][c];
+    }
+    int k = in.k;
+    double beta0 = in.beta0;
+    // column j (coef_step)
+    const double hnj = sqrt(res[j + 1].re);
+    double sj;
+    if (j == 0) {
+        beta0 = hnj;
+        sj = beta0 > 0.0 ? 1.0 / beta0 : 0.0;
+        k = s;
+    } else {
+        const bool brk = !(hnj > tiny * beta0);
+        sj = brk ? 0.0 : 1.0 / hnj;
+        if (brk && k > j) k = j;
+    }
+    zc cu[SB];
+    double w2 = sj * sj * res[j + 2].re, c2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < SB; ++q) {
+        if (q == j) sig[q] = sj;
+#pragma unroll
+        for (int c = 0; c < K; ++c)
+            if (c == j && q <= j) {
+                const zc h = (sig[q] * sj) * res[q];
+                H[q][c] = h;
+                cu[q] = cvt<double>(cvt<T>(sig[q] * h));
+                c2 += cabs2(h);
+            }
+#pragma unroll
+        for (int c = 1; c < K; ++c)
+            if (c == j && q == j) H[q][c - 1] = mkc(hnj, 0.0);
+    }
+    // h_{s,s-1}: a difference at rounding level of ||A v_{s-1}||^2 means A v_{s-1}
+    // lies in the basis span
+    const double h2 = w2 - c2;
+    const double hn = h2 > 1e-13 * w2 ? sqrt(h2) : 0.0;
+    const double sig_s = !(hn > tiny * beta0) ? 0.0 : 1.0 / hn;
+#pragma unroll
+    for (int c = 0; c < K; ++c)
+#pragma unroll
+        for (int r = 1; r < SB; ++r)
+            if (c == j && r == s) H[r][c] = mkc(hn, 0.0);
+    if (k > s) k = s;
+    if (!(beta0 > 0.0)) k = 0;
+    // least squares (gmres_ls) on the register copy
+    zc R[SB][K], g[SB], yl[K];
+    double cs[K];
+    zc sn[K];
+#pragma unroll
+    for (int r = 0; r < SB; ++r) {
+        g[r] = mkc(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < K; ++c) R[r][c] = H[r][c];
+    }
+    g[0] = mkc(beta0, 0.0);
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        if (c >= k) break;
+#pragma unroll
+        for (int i = 0; i < c; ++i) {
+            const zc t1 = R[i][c], t2 = R[i + 1][c];
+            R[i][c] = cs[i] * t1 + sn[i] * t2;
+            R[i + 1][c] = cs[i] * t2 - mkc(sn[i].re, -sn[i].im) * t1;
+        }
+        rot(R[c][c], R[c + 1][c], cs[c], sn[c]);
+        const zc t1 = R[c][c], t2 = R[c + 1][c];
+        R[c][c] = cs[c] * t1 + sn[c] * t2;
+        R[c + 1][c] = mkc(0.0, 0.0);
+        const zc gc = g[c];
+        g[c + 1] = mkc(0.0, 0.0) - mkc(sn[c].re, -sn[c].im) * gc;
+        g[c] = cs[c] * gc;
+    }
+#pragma unroll
+    for (int i = K - 1; i >= 0; --i) {
+        yl[i] = mkc(0.0, 0.0);
+        if (i < k) {
+            zc acc = g[i];
+#pragma unroll
+            for (int c = i + 1; c < K; ++c)
+                if (c < k) acc = acc - R[i][c] * yl[c];
+            const zc d = R[i][i];
+            yl[i] = (1.0 / cabs2(d)) * (acc * mkc(d.re, -d.im));
+        }
+    }
+    zc arl[SB];
+#pragma unroll
+    for (int i = 0; i < SB; ++i) {
+        zc acc = (i == 0) ? mkc(beta0, 0.0) : mkc(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < K; ++c)
+            if (c < k && i <= c + 1) acc = acc - H[i][c] * yl[c];
+        arl[i] = ((i == s) ? sig_s : sig[i]) * acc;
+    }
+    if (k == s) {
+        zc as = mkc(0.0, 0.0);
+#pragma unroll
+        for (int i = 0; i < SB; ++i)
+            if (i == s) as = arl[i];
+#pragma unroll
+        for (int i = 0; i < SB - 1; ++i)
+            if (i < s) arl[i] = arl[i] - as * cu[i];
+#pragma unroll
+        for (int i = 0; i < SB; ++i)
+            if (i == s) arl[i] = sj * as;
+    }
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+        if (i < k) ax[i] = sig[i] * yl[i];
+#pragma unroll
+    for (int i = 0; i < SB; ++i)
+        if (i <= k) ar[i] = arl[i];
+    *ks = k;
+    if (publish) {
+        gs->beta0 = beta0;
+        gs->k = k;
+#pragma unroll
+        for (int c = 0; c < K; ++c)
+            if (c == j) {
+#pragma unroll
+                for (int r = 0; r < SB; ++r)
+                    if (r <= s) gs->H[r * CSG_MAX_S + c] = H[r][c];
+                if (j > 0) gs->H[j * CSG_MAX_S + (j - 1)] = mkc(hnj, 0.0);
+            }
+#pragma unroll
+        for (int i = 0; i < SB; ++i) {
+            if (i == j) gs->sig[i] = sj;
+            if (i == s) gs->sig[i] = sig_s;
+        }
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if (i < k) gs->y[i] = yl[i];
+    }
+}
+
 template <typename T, int SB>
 __device__ int close_sweep(const zc *pin, int nbin, GState *gs, int s, double tiny, zc *sh, zc *res, zc *ax, zc *ar)
 {
-    __shared__ GState lg;
     __shared__ int ks;
+    if constexpr (SB <= 4) {
+        CloseIn<SB> in;
+        if (threadIdx.x == 0) close_gather<SB>(gs, s, in);
+        reduce_parts<SB + 1>(pin, nbin, s + 2, sh, res);
+        if (threadIdx.x == 0) close_regs<T, SB>(in, gs, res, s, tiny, blockIdx.x == 0, ax, ar, &ks);
+        __syncthreads();
+        return ks;
+    }
+    __shared__ GState lg;
     __shared__ zc Rs[(CSG_MAX_S + 1) * CSG_MAX_S], ys[CSG_MAX_S], crs[CSG_MAX_S + 1];
     {
         const double *src = (const double *)gs;
@@ -909,7 +1119,7 @@ __device__ int close_sweep(const zc *pin, int nbin, GState *gs, int s, double ti
     reduce_parts<SB + 1>(pin, nbin, s + 2, sh, res);
     if (threadIdx.x == 0) {
         Cx<T> cu[SB];
-        const double sj = coef_step<T, SB>(res, s - 1, s, tiny, &lg, true, cu);
+        const double sj = coef_step<T, SB>(res, s - 1, s, tiny, load_prev<SB>(&lg, s - 1), &lg, true, cu);
         double h2 = sj * sj * res[s + 1].re;
         for (int i = 0; i < s; ++i) h2 -= cabs2(lg.H[i * CSG_MAX_S + (s - 1)]);
         // a difference at rounding level of ||A v_{s-1}||^2: A v_{s-1} lies in the basis span
@@ -1132,7 +1342,7 @@ __device__ void tail_steps(const LvlK<T> &L, const Basis<T> &B, Cx<T> *w0, Cx<T>
     }
     for (int j = 0; j < s; ++j) {
         Cx<T> cu[SB];
-        const double sj = coef_step<T, SB>(res, j, s, tiny, gs, threadIdx.x == 0, cu);
+        const double sj = coef_step<T, SB>(res, j, s, tiny, load_prev<SB>(gs, j), gs, threadIdx.x == 0, cu);
         Cx<T> *win = (j & 1) ? w1 : w0;
         Cx<T> *wout = (j & 1) ? w0 : w1;
         if (j + 1 < s) {
