@@ -210,9 +210,10 @@ double vcycle_bytes(const csg_operator *op, int nrhs)
     double tot = b.coarse(op->nc);
     for (int l = 0; l + 1 < op->L; ++l) {
         const double N = op->lev[l].N, Nc = op->lev[l + 1].N;
-        // Arnoldi passes of one sweep: pass 0 and the fused passes (h_{s,s-1} from
-        // the last pass's sums; the closing pass combines w_{s-1} in place of u_s)
-        double steps = b.st(0, N);
+        // Arnoldi passes of one sweep: pass 0 and the fused passes (FP64: h_{s,s-1}
+        // from the last pass's sums, the closing pass combines w_{s-1} in place of
+        // u_s; complex64: a last Gram-Schmidt pass forms u_s)
+        double steps = b.st(0, N) + (op->p.cycle_prec ? b.orth(s - 1, N) : 0.0);
         for (int j = 0; j + 1 < s; ++j) steps += b.os(j, N);
         if (nu1 == 0) tot += b.restrict_b(N, Nc);
         for (int k = 0; k < nu1; ++k) {
@@ -245,6 +246,7 @@ void arnoldi_passes(const csg_operator *op, int l, const Basis<T> &B, int nrhs, 
     const double tiny = tiny_of<T>();
     const Bytes by = bytes_of(op, nrhs);
     Cx<T> *W[2] = {(Cx<T> *)lv.w[0], (Cx<T> *)lv.w[1]};
+    const bool sums = sizeof(T) == 8;   // FP64: h_{s,s-1} from the last pass's sums
     if (lv.N > op->fuse_max) {
         // large level: stencil pass then Gram-Schmidt pass per step (fewer loads per point)
         for (int j = 0; j < s; ++j) {
@@ -252,7 +254,7 @@ void arnoldi_passes(const csg_operator *op, int l, const Basis<T> &B, int nrhs, 
                 ProfScope ps(op, l == 0 ? CSG_PROF_STENCIL_DOTS : -1, st, by.st(j, lv.N));
                 launch_stj<T, DIM>(L, B, W[j & 1], j, s, lv.ld, lv.part[0], g, active);
             }
-            if (j + 1 == s) break;
+            if (sums && j + 1 == s) break;
             ProfScope ps(op, l == 0 ? CSG_PROF_ORTH : -1, st, by.orth(j, lv.N));
             launch_orthl<T>(B, W[j & 1], j, s, lv.N, lv.ld, lv.part[0], lv.nb, lv.part[1], lv.gs, tiny, g, active);
         }
@@ -260,28 +262,38 @@ void arnoldi_passes(const csg_operator *op, int l, const Basis<T> &B, int nrhs, 
     }
     {
         ProfScope ps(op, l == 0 ? CSG_PROF_STENCIL_DOTS : -1, st, by.st(0, lv.N));
-        launch_st0<T, DIM>(L, B.u[0], W[0], s == 1, lv.ld, lv.part[0], g, active);
+        launch_st0<T, DIM>(L, B.u[0], W[0], sums && s == 1, lv.ld, lv.part[0], g, active);
     }
     for (int j = 0; j + 1 < s; ++j) {
         ProfScope ps(op, l == 0 ? CSG_PROF_STENCIL_DOTS : -1, st, by.os(j, lv.N));
         launch_os<T, DIM>(L, B, W[j & 1], W[(j + 1) & 1], j, s, lv.ld, lv.part[j & 1], lv.nb, lv.part[(j + 1) & 1],
                           lv.gs, tiny, g, active);
     }
+    if (!sums) {
+        // complex64: the last Gram-Schmidt pass forms u_s and its norm
+        ProfScope ps(op, l == 0 ? CSG_PROF_ORTH : -1, st, by.orth(s - 1, lv.N));
+        launch_orthl<T>(B, W[(s - 1) & 1], s - 1, s, lv.N, lv.ld, lv.part[(s - 1) & 1], lv.nb, lv.part[s & 1], lv.gs,
+                        tiny, g, active);
+    }
 }
 
 // Partials buffer the closing pass of a sweep on level l reads (written by the
 // last Arnoldi pass).
+template <typename T>
 zc *close_part(const csg_operator *op, int l)
 {
     const DevLevel &lv = op->lev[l];
-    return lv.N > op->fuse_max ? lv.part[0] : lv.part[(op->p.s - 1) & 1];
+    const int s = op->p.s;
+    if (sizeof(T) == 8) return lv.N > op->fuse_max ? lv.part[0] : lv.part[(s - 1) & 1];
+    return lv.N > op->fuse_max ? lv.part[1] : lv.part[s & 1];
 }
 
-// Basis the closing pass combines: u_0..u_{s-1} and, in place of u_s, w_{s-1}.
+// Basis the closing pass combines: u_0..u_{s-1} and, in place of u_s, w_{s-1}
+// (FP64; complex64 sweeps form u_s).
 template <typename T>
 Basis<T> closing_basis(const csg_operator *op, int l, Basis<T> B)
 {
-    B.u[op->p.s] = (Cx<T> *)op->lev[l].w[(op->p.s - 1) & 1];
+    if (sizeof(T) == 8) B.u[op->p.s] = (Cx<T> *)op->lev[l].w[(op->p.s - 1) & 1];
     return B;
 }
 
@@ -309,7 +321,7 @@ void sweep(const csg_operator *op, int l, const Cx<T> *b, Cx<T> *x, bool from_ze
     B = closing_basis<T>(op, l, B);
     const Bytes by = bytes_of(op, nrhs);
     const int k0 = l == 0 ? 0 : -1;   // instrumented kinds exist for the finest level only
-    zc *pclose = close_part(op, l);
+    zc *pclose = close_part<T>(op, l);
     if (restrict_after) {
         // closing update writes x and the Arnoldi residual r; full weighting of r
         const DevLevel &cl = op->lev[l + 1];
@@ -384,7 +396,7 @@ void vcycle_impl(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, h
                 arnoldi_passes<T, DIM>(op, l, B, nrhs, st, active);
                 B = closing_basis<T>(op, l, B);
                 ProfScope ps(op, l == 0 ? CSG_PROF_UPDATE : -1, st, bytes_of(op, nrhs).upd(s, true, d.N));
-                launch_upd<T>(xo, 1, B, s, d.N, d.ld, close_part(op, l), d.nb, d.gs, tiny, g, active);
+                launch_upd<T>(xo, 1, B, s, d.N, d.ld, close_part<T>(op, l), d.nb, d.gs, tiny, g, active);
             }
         }
     }

@@ -232,6 +232,15 @@ struct Ubatch {
     static constexpr int U = sizeof(T) == 8 ? 2 : 4;
 };
 
+// h_{s,s-1} of a sweep, two ways.  FP64 cycles take it from the sums of the
+// last Arnoldi pass (below) and never form u_s.  complex64 cycles form u_s in
+// an explicit last Gram-Schmidt pass and take its norm: with single-pass
+// classical Gram-Schmidt on float vectors the basis is orthonormal only to
+// float accuracy, too little for the identity when A v_{s-1} nearly lies in the
+// basis span (under-resolved coarse levels).
+template <typename T>
+constexpr bool norm_from_sums() { return sizeof(T) == 8; }
+
 // Arnoldi bookkeeping on the raw (unnormalised) basis u_0..u_s of one sweep,
 // v_i = sig_i u_i: pass 0 forms w_0 = A u_0; pass j+1 (j < s-1) forms
 // u_{j+1} = sig_j w_j - sum_{i<=j} sig_i h_ij u_i (classical Gram-Schmidt) and,
@@ -468,23 +477,21 @@ __device__ __forceinline__ void body_upd_r(Cx<T> *x, int accumulate, Cx<T> *r, c
 // weight 1) or nodes (f-1)/2 and (f+1)/2 (f odd, weight 1/2); coarse node c is
 // an unknown (index c-1) when 1 <= c <= nuc.
 struct PAx {
-    int n;
     unsigned idx[2];
     float w[2];
 };
+// Both candidate coarse nodes always present (indices clamped into range,
+// weight 0 for a node that is absent or a Dirichlet end), so the loads of a
+// point issue without branches.
 __device__ __forceinline__ PAx paxis(unsigned i, unsigned nuc)
 {
     PAx a;
-    a.n = 0;
-    const unsigned f = i + 1;
-    if ((f & 1u) == 0) {
-        const unsigned c = f >> 1;
-        if (c >= 1 && c <= nuc) { a.idx[0] = c - 1; a.w[0] = 1.f; a.n = 1; }
-    } else {
-        const unsigned c0 = (f - 1) >> 1, c1 = (f + 1) >> 1;
-        if (c0 >= 1) { a.idx[a.n] = c0 - 1; a.w[a.n] = 0.5f; a.n++; }
-        if (c1 <= nuc) { a.idx[a.n] = c1 - 1; a.w[a.n] = 0.5f; a.n++; }
-    }
+    const unsigned f = i + 1, c0 = f >> 1;
+    const bool odd = (f & 1u) != 0;
+    a.w[0] = (c0 >= 1 && c0 <= nuc) ? (odd ? 0.5f : 1.f) : 0.f;
+    a.w[1] = (odd && c0 + 1 <= nuc) ? 0.5f : 0.f;
+    a.idx[0] = min(max(c0, 1u), nuc) - 1;
+    a.idx[1] = min(c0 + 1, nuc) - 1;
     return a;
 }
 
@@ -499,9 +506,7 @@ __device__ __forceinline__ Cx<T> prolong_pt(const Cx<T> *__restrict__ ec, unsign
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
-                if (b < ay.n && a < ax.n)
-                    acc = acc + (T)(ax.w[a] * ay.w[b]) * ec[ay.idx[b] * ncx + ax.idx[a]];
+            for (int a = 0; a < 2; ++a) acc = acc + (T)(ax.w[a] * ay.w[b]) * ec[ay.idx[b] * ncx + ax.idx[a]];
     } else {
         const PAx ay = paxis(j, ncy), az = paxis(k, ncz);
 #pragma unroll
@@ -510,9 +515,7 @@ __device__ __forceinline__ Cx<T> prolong_pt(const Cx<T> *__restrict__ ec, unsign
             for (int b = 0; b < 2; ++b)
 #pragma unroll
                 for (int a = 0; a < 2; ++a)
-                    if (cz < az.n && b < ay.n && a < ax.n)
-                        acc = acc + (T)(ax.w[a] * ay.w[b] * az.w[cz]) *
-                                        ec[(az.idx[cz] * ncy + ay.idx[b]) * ncx + ax.idx[a]];
+                    acc = acc + (T)(ax.w[a] * ay.w[b] * az.w[cz]) * ec[(az.idx[cz] * ncy + ay.idx[b]) * ncx + ax.idx[a]];
     }
     return acc;
 }
@@ -588,10 +591,23 @@ template <typename T, int DIM>
 __device__ __forceinline__ void body_resid(const LvlK<T> &L, const Cx<T> *x, const Cx<T> *b, Cx<T> *r, unsigned p0,
                                            unsigned p1, unsigned st)
 {
-    for (unsigned p = p0; p < p1; p += st) {
-        unsigned i, j, k;
-        decomp<DIM>(p, L.nx, L.ny, i, j, k);
-        r[p] = b[p] - apply_pt<T, DIM>(L, x, i, j, k, p);
+    constexpr int U = Ubatch<T>::U;
+    if (p0 >= p1) return;
+    const unsigned last = p1 - 1;
+    for (unsigned p = p0; p < p1; p += U * st) {
+        Cx<T> v[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const unsigned pk = min(p + k * st, last);
+            unsigned i, j, kk;
+            decomp<DIM>(pk, L.nx, L.ny, i, j, kk);
+            v[k] = b[pk] - apply_pt<T, DIM>(L, x, i, j, kk, pk);
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            if (p + k * st >= p1) break;
+            r[p + k * st] = v[k];
+        }
     }
 }
 
@@ -628,12 +644,24 @@ template <typename T, int DIM>
 __device__ __forceinline__ void body_prolong(const LvlK<T> &F, const LvlK<T> &C, const Cx<T> *e, const Cx<T> *xin,
                                              Cx<T> *xout, unsigned p0, unsigned p1, unsigned st)
 {
-    for (unsigned p = p0; p < p1; p += st) {
-        unsigned i, j, k;
-        decomp<DIM>(p, F.nx, F.ny, i, j, k);
-        Cx<T> v = prolong_pt<T, DIM>(e, i, j, k, C.nx, C.ny, C.nz);
-        if (xin) v = v + xin[p];
-        xout[p] = v;
+    constexpr int U = Ubatch<T>::U;
+    if (p0 >= p1) return;
+    const unsigned last = p1 - 1;
+    for (unsigned p = p0; p < p1; p += U * st) {
+        Cx<T> v[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const unsigned pk = min(p + k * st, last);
+            unsigned i, j, kk;
+            decomp<DIM>(pk, F.nx, F.ny, i, j, kk);
+            v[k] = prolong_pt<T, DIM>(e, i, j, kk, C.nx, C.ny, C.nz);
+            if (xin) v[k] = v[k] + xin[pk];
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            if (p + k * st >= p1) break;
+            xout[p + k * st] = v[k];
+        }
     }
 }
 
@@ -875,7 +903,7 @@ __global__ __launch_bounds__(BLK) void k_os(LvlK<T> L, Basis<T> B, const Cx<T> *
     for (int q = 0; q <= SB; ++q) acc[q] = mkc(0.0, 0.0);
     const unsigned c = chunk_id(nb);
     const unsigned p0 = c * chunk, p1 = min(L.N, p0 + chunk);
-    const bool wn = j + 2 == s;   // last step of the sweep
+    const bool wn = norm_from_sums<T>() && j + 2 == s;   // last step of the sweep
     body_os<T, DIM, SB, SB + 1>(L, B, win, wout, j, (T)sj, cu, rhs * ld, p0 + threadIdx.x, p1, BLK, acc, wn);
     const int nv = j + 3 + (wn ? 1 : 0);
     block_sum<SB + 1>(acc, nv, sh, res);
@@ -927,27 +955,78 @@ struct CloseIn {
     int k;
 };
 
-// columns 0..s-2 of the sweep's state (loaded before the partial-sum reduction)
+// The sweep's state as far as earlier passes finished it (loaded before the
+// partial-sum reduction): columns 0..s-2 (sums form) or 0..s-1 (explicit form,
+// all but h_{s,s-1}).
 template <int SB>
-__device__ __forceinline__ void close_gather(const GState *gs, int s, CloseIn<SB> &in)
+__device__ __forceinline__ void close_gather(const GState *gs, int s, bool sums, CloseIn<SB> &in)
 {
     constexpr int K = SB - 1;
     const int j = s - 1;
+    const int ncol = sums ? s - 1 : s;
 #pragma unroll
     for (int c = 0; c < K; ++c) {
 #pragma unroll
         for (int r = 0; r < SB; ++r) in.H[r][c] = mkc(0.0, 0.0);
         in.sig[c] = 0.0;
-        if (c < j) {
+        if (c < ncol) {
             in.sig[c] = gs->sig[c];
 #pragma unroll
             for (int r = 0; r < SB; ++r)
-                if (r <= c + 1 && !(c + 1 == j && r == j)) in.H[r][c] = gs->H[r * CSG_MAX_S + c];
+                if (r <= c + 1 && !(sums && c + 1 == j && r == j) && !(!sums && r == s))
+                    in.H[r][c] = gs->H[r * CSG_MAX_S + c];
         }
     }
     in.sig[K] = 0.0;
     in.k = gs->k;
     in.beta0 = gs->beta0;
+}
+
+// y = argmin || beta0 e1 - Hbar y || over the first k columns (gmres_ls on a
+// register copy of Hbar)
+template <int SB>
+__device__ __forceinline__ void ls_regs(const zc (&H)[SB][SB - 1], double beta0, int k, zc (&yl)[SB - 1])
+{
+    constexpr int K = SB - 1;
+    zc R[SB][K], g[SB];
+    double cs[K];
+    zc sn[K];
+#pragma unroll
+    for (int r = 0; r < SB; ++r) {
+        g[r] = mkc(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < K; ++c) R[r][c] = H[r][c];
+    }
+    g[0] = mkc(beta0, 0.0);
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        if (c >= k) break;
+#pragma unroll
+        for (int i = 0; i < c; ++i) {
+            const zc t1 = R[i][c], t2 = R[i + 1][c];
+            R[i][c] = cs[i] * t1 + sn[i] * t2;
+            R[i + 1][c] = cs[i] * t2 - mkc(sn[i].re, -sn[i].im) * t1;
+        }
+        rot(R[c][c], R[c + 1][c], cs[c], sn[c]);
+        const zc t1 = R[c][c], t2 = R[c + 1][c];
+        R[c][c] = cs[c] * t1 + sn[c] * t2;
+        R[c + 1][c] = mkc(0.0, 0.0);
+        const zc gc = g[c];
+        g[c + 1] = mkc(0.0, 0.0) - mkc(sn[c].re, -sn[c].im) * gc;
+        g[c] = cs[c] * gc;
+    }
+#pragma unroll
+    for (int i = K - 1; i >= 0; --i) {
+        yl[i] = mkc(0.0, 0.0);
+        if (i < k) {
+            zc acc = g[i];
+#pragma unroll
+            for (int c = i + 1; c < K; ++c)
+                if (c < k) acc = acc - R[i][c] * yl[c];
+            const zc d = R[i][i];
+            yl[i] = (1.0 / cabs2(d)) * (acc * mkc(d.re, -d.im));
+        }
+    }
 }
 
 template <typename T, int SB>
@@ -966,6 +1045,43 @@ __device__ void close_regs(const CloseIn<SB> &in, GState *gs, const zc *res, int
     }
     int k = in.k;
     double beta0 = in.beta0;
+    if constexpr (!norm_from_sums<T>()) {
+        // explicit form: column s-1 is complete, res[0] = ||u_s||^2
+        const double hn = sqrt(res[0].re);
+        const double sig_s = !(hn > tiny * beta0) ? 0.0 : 1.0 / hn;
+#pragma unroll
+        for (int c = 0; c < K; ++c)
+#pragma unroll
+            for (int r = 1; r < SB; ++r)
+                if (c == j && r == s) H[r][c] = mkc(hn, 0.0);
+#pragma unroll
+        for (int i = 0; i < SB; ++i)
+            if (i == s) sig[i] = sig_s;
+        if (k > s) k = s;
+        if (!(beta0 > 0.0)) k = 0;
+        zc yl[K];
+        ls_regs<SB>(H, beta0, k, yl);
+#pragma unroll
+        for (int i = 0; i < SB; ++i) {
+            zc acc = (i == 0) ? mkc(beta0, 0.0) : mkc(0.0, 0.0);
+#pragma unroll
+            for (int c = 0; c < K; ++c)
+                if (c < k && i <= c + 1) acc = acc - H[i][c] * yl[c];
+            if (i <= k) ar[i] = sig[i] * acc;
+        }
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if (i < k) ax[i] = sig[i] * yl[i];
+        *ks = k;
+        if (publish) {
+            gs->H[s * CSG_MAX_S + (s - 1)] = mkc(hn, 0.0);
+            gs->sig[s] = sig_s;
+#pragma unroll
+            for (int i = 0; i < K; ++i)
+                if (i < k) gs->y[i] = yl[i];
+        }
+        return;
+    }
     // column j (coef_step)
     const double hnj = sqrt(res[j + 1].re);
     double sj;
@@ -1007,46 +1123,8 @@ __device__ void close_regs(const CloseIn<SB> &in, GState *gs, const zc *res, int
             if (c == j && r == s) H[r][c] = mkc(hn, 0.0);
     if (k > s) k = s;
     if (!(beta0 > 0.0)) k = 0;
-    // least squares (gmres_ls) on the register copy
-    zc R[SB][K], g[SB], yl[K];
-    double cs[K];
-    zc sn[K];
-#pragma unroll
-    for (int r = 0; r < SB; ++r) {
-        g[r] = mkc(0.0, 0.0);
-#pragma unroll
-        for (int c = 0; c < K; ++c) R[r][c] = H[r][c];
-    }
-    g[0] = mkc(beta0, 0.0);
-#pragma unroll
-    for (int c = 0; c < K; ++c) {
-        if (c >= k) break;
-#pragma unroll
-        for (int i = 0; i < c; ++i) {
-            const zc t1 = R[i][c], t2 = R[i + 1][c];
-            R[i][c] = cs[i] * t1 + sn[i] * t2;
-            R[i + 1][c] = cs[i] * t2 - mkc(sn[i].re, -sn[i].im) * t1;
-        }
-        rot(R[c][c], R[c + 1][c], cs[c], sn[c]);
-        const zc t1 = R[c][c], t2 = R[c + 1][c];
-        R[c][c] = cs[c] * t1 + sn[c] * t2;
-        R[c + 1][c] = mkc(0.0, 0.0);
-        const zc gc = g[c];
-        g[c + 1] = mkc(0.0, 0.0) - mkc(sn[c].re, -sn[c].im) * gc;
-        g[c] = cs[c] * gc;
-    }
-#pragma unroll
-    for (int i = K - 1; i >= 0; --i) {
-        yl[i] = mkc(0.0, 0.0);
-        if (i < k) {
-            zc acc = g[i];
-#pragma unroll
-            for (int c = i + 1; c < K; ++c)
-                if (c < k) acc = acc - R[i][c] * yl[c];
-            const zc d = R[i][i];
-            yl[i] = (1.0 / cabs2(d)) * (acc * mkc(d.re, -d.im));
-        }
-    }
+    zc yl[K];
+    ls_regs<SB>(H, beta0, k, yl);
     zc arl[SB];
 #pragma unroll
     for (int i = 0; i < SB; ++i) {
@@ -1101,11 +1179,32 @@ template <typename T, int SB>
 __device__ int close_sweep(const zc *pin, int nbin, GState *gs, int s, double tiny, zc *sh, zc *res, zc *ax, zc *ar)
 {
     __shared__ int ks;
+    constexpr bool sums = norm_from_sums<T>();
     if constexpr (SB <= 4) {
         CloseIn<SB> in;
-        if (threadIdx.x == 0) close_gather<SB>(gs, s, in);
-        reduce_parts<SB + 1>(pin, nbin, s + 2, sh, res);
+        if (threadIdx.x == 0) close_gather<SB>(gs, s, sums, in);
+        reduce_parts<SB + 1>(pin, nbin, sums ? s + 2 : 1, sh, res);
         if (threadIdx.x == 0) close_regs<T, SB>(in, gs, res, s, tiny, blockIdx.x == 0, ax, ar, &ks);
+        __syncthreads();
+        return ks;
+    }
+    if constexpr (!sums) {
+        __shared__ zc Rs[(CSG_MAX_S + 1) * CSG_MAX_S], ys[CSG_MAX_S], crs[CSG_MAX_S + 1];
+        reduce_parts<1>(pin, nbin, 1, sh, res);
+        if (threadIdx.x == 0) {
+            const double hn = sqrt(res[0].re);
+            const bool brk = !(hn > tiny * gs->beta0);
+            const double sig_s = brk ? 0.0 : 1.0 / hn;
+            const int k = gmres_ls<SB>(gs, s, hn, Rs, ys, crs);
+            for (int i = 0; i < k; ++i) ax[i] = gs->sig[i] * ys[i];
+            for (int i = 0; i <= k; ++i) ar[i] = ((i == s) ? sig_s : gs->sig[i]) * crs[i];
+            ks = k;
+            if (blockIdx.x == 0) {
+                gs->H[s * CSG_MAX_S + (s - 1)] = mkc(hn, 0.0);
+                gs->sig[s] = sig_s;
+                for (int i = 0; i < k; ++i) gs->y[i] = ys[i];
+            }
+        }
         __syncthreads();
         return ks;
     }
@@ -1330,12 +1429,20 @@ __device__ __forceinline__ LvlK<T> tlvl(const TLev<T> &d)
 }
 
 // Arnoldi passes of one sweep on the raw basis B (u_0 given), whole level;
-// w0, w1 hold the stencil outputs (ping-pong).
+// w0, w1 hold the stencil outputs (ping-pong), w_{s-1} ends in w[(s-1) % 2].
+// As on the multi-block levels the last pass also sums ||w_{s-1}||^2 and
+// h_{s,s-1} follows from ||A v_{s-1}||^2 = sum_i |h_{i,s-1}|^2 + h_{s,s-1}^2;
+// fold[0..s-1] = cu_i and fold[s] = sig_{s-1} (u_s = fold[s] w_{s-1} -
+// sum_i fold[i] u_i) are left for the closing pass.
 template <typename T, int DIM, int SB>
 __device__ void tail_steps(const LvlK<T> &L, const Basis<T> &B, Cx<T> *w0, Cx<T> *w1, size_t off, int s,
-                           double tiny, GState *gs, zc *sh, zc *res)
+                           double tiny, GState *gs, zc *sh, zc *res, zc *fold)
 {
-    {
+    if (norm_from_sums<T>() && s == 1) {
+        zc acc[3] = {mkc(0.0, 0.0), mkc(0.0, 0.0), mkc(0.0, 0.0)};
+        body_st0<T, DIM, 3>(L, B.u[0] + off, w0 + off, threadIdx.x, L.N, TB, acc);
+        tail_sum<3>(acc, 3, sh, res);
+    } else {
         zc acc[2] = {mkc(0.0, 0.0), mkc(0.0, 0.0)};
         body_st0<T, DIM>(L, B.u[0] + off, w0 + off, threadIdx.x, L.N, TB, acc);
         tail_sum<2>(acc, 2, sh, res);
@@ -1346,30 +1453,49 @@ __device__ void tail_steps(const LvlK<T> &L, const Basis<T> &B, Cx<T> *w0, Cx<T>
         Cx<T> *win = (j & 1) ? w1 : w0;
         Cx<T> *wout = (j & 1) ? w0 : w1;
         if (j + 1 < s) {
-            zc acc[SB];
+            zc acc[SB + 1];
 #pragma unroll
-            for (int q = 0; q < SB; ++q) acc[q] = mkc(0.0, 0.0);
-            body_os<T, DIM, SB, SB>(L, B, win, wout, j, (T)sj, cu, off, threadIdx.x, L.N, TB, acc, false);
-            tail_sum<SB>(acc, j + 3, sh, res);
-        } else {
+            for (int q = 0; q <= SB; ++q) acc[q] = mkc(0.0, 0.0);
+            const bool wn = norm_from_sums<T>() && j + 2 == s;
+            body_os<T, DIM, SB, SB + 1>(L, B, win, wout, j, (T)sj, cu, off, threadIdx.x, L.N, TB, acc, wn);
+            tail_sum<SB + 1>(acc, j + 3 + (wn ? 1 : 0), sh, res);
+        } else if constexpr (!norm_from_sums<T>()) {
+            // explicit form: u_s and its norm
             zc nr[1] = {mkc(0.0, 0.0)};
             body_orthl<T, SB>(B, win + off, j, (T)sj, cu, off, threadIdx.x, L.N, TB, nr[0].re);
             tail_sum<1>(nr, 1, sh, res);
             if (threadIdx.x == 0) {
-                // h_{s,s-1}, the scale of u_s and the breakdown test
                 const double hn = sqrt(res[0].re);
                 const bool brk = !(hn > tiny * gs->beta0);
                 gs->H[s * CSG_MAX_S + (s - 1)] = mkc(hn, 0.0);
                 gs->sig[s] = brk ? 0.0 : 1.0 / hn;
             }
             __syncthreads();
+        } else {
+            if (threadIdx.x == 0) {
+                // h_{s,s-1} (a difference at rounding level of ||A v_{s-1}||^2:
+                // A v_{s-1} lies in the basis span), the scale of u_s, the breakdown test
+                const double w2 = sj * sj * res[s + 1].re;
+                double h2 = w2;
+                for (int i = 0; i < s; ++i) h2 -= cabs2(gs->H[i * CSG_MAX_S + (s - 1)]);
+                const double hn = h2 > 1e-13 * w2 ? sqrt(h2) : 0.0;
+                const bool brk = !(hn > tiny * gs->beta0);
+                gs->H[s * CSG_MAX_S + (s - 1)] = mkc(hn, 0.0);
+                gs->sig[s] = brk ? 0.0 : 1.0 / hn;
+#pragma unroll
+                for (int i = 0; i < SB; ++i)
+                    if (i < s) fold[i] = cvt<double>(cu[i]);
+                fold[s] = mkc(sj, 0.0);
+            }
+            __syncthreads();
         }
     }
 }
 
-// Least squares of the sweep (thread 0) -> coefficients for every thread.
+// Least squares of the sweep (thread 0) -> coefficients for every thread; the
+// residual coefficients are those on {u_0..u_{s-1}, w_{s-1}} (u_s folded in).
 template <typename T, int SB>
-__device__ int tail_close(const GState *gs, int s, zc *Rs, zc *ys, zc *crs, zc *ax, zc *ar, int *ks,
+__device__ int tail_close(const GState *gs, int s, zc *Rs, zc *ys, zc *crs, zc *ax, zc *ar, int *ks, const zc *fold,
                           Cx<T> (&cx)[SB], Cx<T> (&cr)[SB])
 {
     if (threadIdx.x == 0) {
@@ -1377,6 +1503,11 @@ __device__ int tail_close(const GState *gs, int s, zc *Rs, zc *ys, zc *crs, zc *
         const int k = gmres_ls<SB>(gs, s, hn, Rs, ys, crs);
         for (int i = 0; i < k; ++i) ax[i] = gs->sig[i] * ys[i];
         for (int i = 0; i <= k; ++i) ar[i] = gs->sig[i] * crs[i];
+        if (norm_from_sums<T>() && k == s) {
+            const zc as = ar[s];
+            for (int i = 0; i < s; ++i) ar[i] = ar[i] - as * fold[i];
+            ar[s] = fold[s].re * as;
+        }
         *ks = k;
     }
     __syncthreads();
@@ -1396,6 +1527,7 @@ __global__ __launch_bounds__(TB) void k_tail(const TLev<T> *__restrict__ lev, in
     __shared__ zc Rs[(CSG_MAX_S + 1) * CSG_MAX_S], ys[CSG_MAX_S], crs[CSG_MAX_S + 1], ax[CSG_MAX_S],
         ar[CSG_MAX_S + 1];
     __shared__ int ks;
+    __shared__ zc fold[CSG_MAX_S + 1];
     __shared__ Cx<T> cpart[TB];
     const int rhs = blockIdx.x;
     if (!active[rhs]) return;
@@ -1415,6 +1547,7 @@ __global__ __launch_bounds__(TB) void k_tail(const TLev<T> *__restrict__ lev, in
         }
         Basis<T> B;
         for (int q = 0; q <= CSG_MAX_S; ++q) B.u[q] = Fd.u[q];
+        if (norm_from_sums<T>()) B.u[s] = Fd.w[(s - 1) & 1];   // closing combines w_{s-1} in place of u_s
         for (int k = 0; k < nu1; ++k) {
             if (k == 0) {
                 B.u[0] = const_cast<Cx<T> *>(b) - offf;
@@ -1423,9 +1556,9 @@ __global__ __launch_bounds__(TB) void k_tail(const TLev<T> *__restrict__ lev, in
                 __syncthreads();
                 B.u[0] = Fd.r;
             }
-            tail_steps<T, DIM, SB>(F, B, Fd.w[0], Fd.w[1], offf, s, tiny, &gs, sh, res);
+            tail_steps<T, DIM, SB>(F, B, Fd.w[0], Fd.w[1], offf, s, tiny, &gs, sh, res, fold);
             Cx<T> cx[SB], cr[SB];
-            const int kk = tail_close<T, SB>(&gs, s, Rs, ys, crs, ax, ar, &ks, cx, cr);
+            const int kk = tail_close<T, SB>(&gs, s, Rs, ys, crs, ax, ar, &ks, fold, cx, cr);
             if (k == nu1 - 1)
                 body_upd_res<T, DIM, SB>(Fd.xa + offf, k > 0, B, kk, cx, cr, F, C, Cd.b + offc, offf, t, C.N, TB);
             else
@@ -1462,14 +1595,15 @@ __global__ __launch_bounds__(TB) void k_tail(const TLev<T> *__restrict__ lev, in
         Basis<T> B;
         for (int q = 0; q <= CSG_MAX_S; ++q) B.u[q] = Fd.u[q];
         B.u[0] = Fd.r;
+        if (norm_from_sums<T>()) B.u[s] = Fd.w[(s - 1) & 1];
         for (int k = 0; k < nu2; ++k) {
             if (k > 0) {
                 body_resid<T, DIM>(F, x, b, Fd.r + offf, t, F.N, TB);
                 __syncthreads();
             }
-            tail_steps<T, DIM, SB>(F, B, Fd.w[0], Fd.w[1], offf, s, tiny, &gs, sh, res);
+            tail_steps<T, DIM, SB>(F, B, Fd.w[0], Fd.w[1], offf, s, tiny, &gs, sh, res, fold);
             Cx<T> cx[SB], cr[SB];
-            const int kk = tail_close<T, SB>(&gs, s, Rs, ys, crs, ax, ar, &ks, cx, cr);
+            const int kk = tail_close<T, SB>(&gs, s, Rs, ys, crs, ax, ar, &ks, fold, cx, cr);
             body_upd<T, SB>(x, 1, B, kk, cx, offf, t, F.N, TB);
             __syncthreads();
         }
@@ -1793,33 +1927,34 @@ __device__ __forceinline__ zc group_parts(const zc *pp, int nbin)
     return v;
 }
 
-// Column j of the Hessenberg matrix is complete (hcol, h_{j+1,j} = hn): apply
-// the previous rotations, form the new one, update g and the estimate.
-__device__ void givens_column(FState *fs, Report *rp, int j, double hn)
+// Column j of the Hessenberg matrix is complete (col[0..j] in shared memory,
+// h_{j+1,j} = hn): apply the previous rotations (cs, sn staged in shared
+// memory), form the new one, update g and the estimate.  One thread; the
+// rotated column is left in col for the block to store.
+__device__ void givens_column(FState *fs, Report *rp, int j, double hn, zc *col, const double *cs_s, const zc *sn_s)
 {
-    const int m = CSG_MAX_RESTART;
-    for (int q = 0; q <= j; ++q) fs->R[q * m + j] = fs->hcol[q];
-    fs->R[(j + 1) * m + j] = mkc(hn, 0.0);
+    col[j + 1] = mkc(hn, 0.0);
     for (int q = 0; q < j; ++q) {
-        const zc t1 = fs->R[q * m + j], t2 = fs->R[(q + 1) * m + j];
-        fs->R[q * m + j] = fs->cs[q] * t1 + fs->sn[q] * t2;
-        fs->R[(q + 1) * m + j] = fs->cs[q] * t2 - mkc(fs->sn[q].re, -fs->sn[q].im) * t1;
+        const zc t1 = col[q], t2 = col[q + 1];
+        col[q] = cs_s[q] * t1 + sn_s[q] * t2;
+        col[q + 1] = cs_s[q] * t2 - mkc(sn_s[q].re, -sn_s[q].im) * t1;
     }
     double cs;
     zc sn;
-    rot(fs->R[j * m + j], fs->R[(j + 1) * m + j], cs, sn);
+    rot(col[j], col[j + 1], cs, sn);
     fs->cs[j] = cs;
     fs->sn[j] = sn;
-    const zc t1 = fs->R[j * m + j], t2 = fs->R[(j + 1) * m + j];
-    fs->R[j * m + j] = cs * t1 + sn * t2;
-    fs->R[(j + 1) * m + j] = mkc(0.0, 0.0);
+    const zc t1 = col[j], t2 = col[j + 1];
+    col[j] = cs * t1 + sn * t2;
+    col[j + 1] = mkc(0.0, 0.0);
     const zc gj = fs->g[j];
-    fs->g[j + 1] = mkc(0.0, 0.0) - mkc(sn.re, -sn.im) * gj;
+    const zc g1 = mkc(0.0, 0.0) - mkc(sn.re, -sn.im) * gj;
+    fs->g[j + 1] = g1;
     fs->g[j] = cs * gj;
     fs->hn = hn;
     fs->inv_hn = hn > 0.0 ? 1.0 / hn : 0.0;
     fs->kcols = j + 1;
-    const double est = sqrt(cabs2(fs->g[j + 1])) / fs->nchi;
+    const double est = sqrt(cabs2(g1)) / fs->nchi;
     rp->est = est;
     rp->hn = hn;
     rp->finite = isfinite(est) && isfinite(hn);
@@ -1827,24 +1962,40 @@ __device__ void givens_column(FState *fs, Report *rp, int j, double hn)
 
 // One block per RHS: finish an outer reduction and advance the small FGMRES
 // state (Hessenberg column, Givens rotations, residual estimate, LS solve).
+// The serial parts run on one thread over shared-memory copies of the state.
 __global__ __launch_bounds__(FT) void k_fin(int mode, const zc *__restrict__ pin, int nbin, int j, FState *fsb,
                                             Report *rep, const int *active)
 {
+    constexpr int M = CSG_MAX_RESTART;
     __shared__ zc val[OVAL];
+    __shared__ zc col[OVAL];
+    __shared__ double cs_s[M];
+    __shared__ zc sn_s[M];
     const int rhs = blockIdx.x;
     if (!active[rhs]) return;
     FState *fs = fsb + rhs;
     const zc *pp = pin + (size_t)rhs * OVAL * NBMAX;
     if (mode == FIN_LS) {
+        // back substitution R y = g on the k x k upper triangle (staged)
+        __shared__ zc Rt[M * M];
+        __shared__ zc gy[M];
+        const int k = fs->kcols;
+        for (int e = threadIdx.x; e < k * k; e += FT) {
+            const int i = e / k, c = e % k;
+            if (c >= i) Rt[i * M + c] = fs->R[i * M + c];
+        }
+        for (int i = threadIdx.x; i < k; i += FT) gy[i] = fs->g[i];
+        __syncthreads();
         if (threadIdx.x == 0) {
-            const int k = fs->kcols;
             for (int i = k - 1; i >= 0; --i) {
-                zc acc = fs->g[i];
-                for (int c = i + 1; c < k; ++c) acc = acc - fs->R[i * CSG_MAX_RESTART + c] * fs->y[c];
-                const zc d = fs->R[i * CSG_MAX_RESTART + i];
-                fs->y[i] = (1.0 / cabs2(d)) * (acc * mkc(d.re, -d.im));
+                zc acc = gy[i];
+                for (int c = i + 1; c < k; ++c) acc = acc - Rt[i * M + c] * gy[c];
+                const zc d = Rt[i * M + i];
+                gy[i] = (1.0 / cabs2(d)) * (acc * mkc(d.re, -d.im));
             }
         }
+        __syncthreads();
+        for (int i = threadIdx.x; i < k; i += FT) fs->y[i] = gy[i];
         return;
     }
     // values: FIN_H: 0..j; FIN_CN: 0..j+1; FIN_BEGIN: 0, 1; others: 0
@@ -1854,27 +2005,43 @@ __global__ __launch_bounds__(FT) void k_fin(int mode, const zc *__restrict__ pin
         const zc v = group_parts(pp + q * NBMAX, nbin);
         if (threadIdx.x % FG == 0) val[q] = v;
     }
+    if (mode == FIN_CN) {
+        for (int q = threadIdx.x; q < j; q += FT) {
+            cs_s[q] = fs->cs[q];
+            sn_s[q] = fs->sn[q];
+        }
+        for (int q = threadIdx.x; q <= j; q += FT) col[q] = fs->hcol[q];
+    }
     __syncthreads();
+    if (mode == FIN_CN) {
+        // second-round coefficients c (values 0..j) and ||w1||^2 of the first
+        // projection (value j+1): h_{j+1,j}^2 = ||w1||^2 - ||c||^2, the norm of
+        // w1 - V c for orthonormal V.  A difference at rounding level of
+        // ||w1||^2 means w1 lies in span(V): breakdown, h = 0.
+        for (int q = threadIdx.x; q <= j; q += FT) {
+            const zc h = col[q] + val[q];
+            fs->corr[q] = val[q];
+            fs->hcol[q] = h;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double c2 = 0.0;
+            for (int q = 0; q <= j; ++q) {
+                col[q] = col[q] + val[q];
+                c2 += cabs2(val[q]);
+            }
+            const double w2 = val[j + 1].re, h2 = w2 - c2;
+            givens_column(fs, rep + rhs, j, h2 > 1e-13 * w2 ? sqrt(h2) : 0.0, col, cs_s, sn_s);
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q <= j + 1; q += FT) fs->R[q * M + j] = col[q];
+        return;
+    }
     if (threadIdx.x != 0) return;
     switch (mode) {
     case FIN_H:
         for (int q = 0; q <= j; ++q) fs->hcol[q] = val[q];
         return;
-    case FIN_CN: {
-        // second-round coefficients c (values 0..j) and ||w1||^2 of the first
-        // projection (value j+1): h_{j+1,j}^2 = ||w1||^2 - ||c||^2, the norm of
-        // w1 - V c for orthonormal V.  A difference at rounding level of
-        // ||w1||^2 means w1 lies in span(V): breakdown, h = 0.
-        double c2 = 0.0;
-        for (int q = 0; q <= j; ++q) {
-            fs->corr[q] = val[q];
-            fs->hcol[q] = fs->hcol[q] + val[q];
-            c2 += cabs2(val[q]);
-        }
-        const double w2 = val[j + 1].re, h2 = w2 - c2;
-        givens_column(fs, rep + rhs, j, h2 > 1e-13 * w2 ? sqrt(h2) : 0.0);
-        return;
-    }
     default: {
         // FIN_BEGIN / FIN_BETA: start of a restart cycle
         const double beta = sqrt(val[0].re);
@@ -1925,7 +2092,7 @@ template <typename T, int DIM>
 void launch_stj(const LvlK<T> &L, const Basis<T> &B, Cx<T> *w, int j, int s, size_t ld, zc *pout, const Launch &g,
                 const int *active)
 {
-    const int wn = j + 1 == s;
+    const int wn = norm_from_sums<T>() && j + 1 == s;
     if (s <= 3)
         hipLaunchKernelGGL((k_stj<T, DIM, 4>), grid(g), dim3(BLK), 0, g.st, L, B, w, j, wn, ld, pout, g.chunk, g.nb,
                            active);
