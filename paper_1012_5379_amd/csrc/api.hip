@@ -785,7 +785,7 @@ int csg_operator_create(const csg_params *p, const double *phi_host, void *ws_de
         long tail_max = 1200;
         if (const char *e = getenv("CSG_TAIL_MAX")) tail_max = atol(e);
         if (p->tail_max) tail_max = p->tail_max < 0 ? 0 : p->tail_max;
-        op->fuse_max = 100000;
+        op->fuse_max = 300000;
         if (const char *e = getenv("CSG_FUSE_MAX")) op->fuse_max = atol(e);
         if (p->fuse_max) op->fuse_max = p->fuse_max < 0 ? 0 : p->fuse_max;
         op->lt = op->L - 1;
