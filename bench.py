@@ -152,6 +152,9 @@ def main():
     ap.add_argument("--requests", type=int, default=24, help="c5: requests per pass")
     ap.add_argument("--streams", type=int, default=4, help="c5: concurrent solves")
     ap.add_argument("--load", type=float, default=0.75, help="c5: offered rate / saturated rate")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="one device-to-device copy of MIB MiB before the solves (a plain copy of known size "
+                         "for scaling hardware byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -179,6 +182,14 @@ def main():
     t_setup = time.perf_counter() - t0
     chi = torch.from_numpy(w.chi).to("cuda")
     u = torch.empty_like(chi)
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy: {n} bytes read, {n} bytes written", file=sys.stderr, flush=True)
+        del src, dst
     stream = torch.cuda.current_stream().cuda_stream
     nrhs = w.nrhs
 

@@ -54,6 +54,31 @@ void geometry(unsigned n, int &nb, unsigned &chunk)
     chunk = (unsigned)(((per + BLK - 1) / BLK) * BLK);
 }
 
+// Tiles of a 2-D level for the LDS-staged fused pass: as many as the chunked
+// passes have blocks (nb), tile rows in multiples of 8 when nb is, so the
+// XCD-aware block order hands each XCD a band of rows as in the chunked passes.
+TileGeo tiling(unsigned nx, unsigned ny, int nb)
+{
+    TileGeo t{0, 0, 0, 0};
+    if (nb < 1) return t;
+    unsigned nty;
+    if (nb >= 64 && nb % 8 == 0) {
+        const unsigned k = std::max(1u, (unsigned)std::lround(std::sqrt((double)nb) / 8.0));
+        nty = 8 * k;
+    } else {
+        nty = std::max(1u, (unsigned)std::lround(std::sqrt((double)nb)));
+    }
+    nty = std::min(nty, ny);
+    unsigned ntx = std::max(1u, std::min((unsigned)nb / nty, nx));
+    t.tx = (nx + ntx - 1) / ntx;
+    t.ty = (ny + nty - 1) / nty;
+    // no empty tile rows or columns
+    t.ntx = (nx + t.tx - 1) / t.tx;
+    t.nty = (ny + t.ty - 1) / t.ty;
+    if (!tile_fits(t) || (int)(t.ntx * t.nty) > NBMAX) t.ntx = 0;
+    return t;
+}
+
 // The layout of every buffer in the workspace; `op` may be a dry-run object.
 void carve(csg_operator &op, const int nint[CSG_MAX_LEVELS][3], Carver &cv)
 {
@@ -69,6 +94,7 @@ void carve(csg_operator &op, const int nint[CSG_MAX_LEVELS][3], Carver &cv)
         }
         lv.ld = lv.N;
         geometry(lv.N, lv.nb, lv.chunk);
+        lv.tile = p.dim == 2 ? tiling(lv.nu[0], lv.nu[1], lv.nb) : TileGeo{0, 0, 0, 0};
         for (int a = 0; a < p.dim; ++a) lv.tab[a] = cv.take(3 * (size_t)lv.nu[a] * cz);
         for (int a = p.dim; a < 3; ++a) lv.tab[a] = nullptr;
         lv.phi = cv.take(lv.N * cr);
@@ -237,7 +263,13 @@ double vcycle_bytes(const csg_operator *op, int nrhs)
 // The fused passes write partials to part[k % 2] for pass k; the closing pass
 // reads close_part().
 template <typename T, int DIM>
-void arnoldi_passes(const csg_operator *op, int l, const Basis<T> &B, int nrhs, hipStream_t st, const int *active)
+bool tiled(const csg_operator *op, int l)
+{
+    return DIM == 2 && op->tiles && op->p.s <= 3 && tile_fits(op->lev[l].tile);
+}
+
+template <typename T, int DIM>
+int arnoldi_passes(const csg_operator *op, int l, const Basis<T> &B, int nrhs, hipStream_t st, const int *active)
 {
     const DevLevel &lv = op->lev[l];
     const int s = op->p.s;
@@ -247,7 +279,8 @@ void arnoldi_passes(const csg_operator *op, int l, const Basis<T> &B, int nrhs, 
     const Bytes by = bytes_of(op, nrhs);
     Cx<T> *W[2] = {(Cx<T> *)lv.w[0], (Cx<T> *)lv.w[1]};
     const bool sums = sizeof(T) == 8;   // FP64: h_{s,s-1} from the last pass's sums
-    if (lv.N > op->fuse_max) {
+    const bool tl = tiled<T, DIM>(op, l);
+    if (!tl && lv.N > op->fuse_max) {
         // large level: stencil pass then Gram-Schmidt pass per step (fewer loads per point)
         for (int j = 0; j < s; ++j) {
             {
@@ -258,34 +291,45 @@ void arnoldi_passes(const csg_operator *op, int l, const Basis<T> &B, int nrhs, 
             ProfScope ps(op, l == 0 ? CSG_PROF_ORTH : -1, st, by.orth(j, lv.N));
             launch_orthl<T>(B, W[j & 1], j, s, lv.N, lv.ld, lv.part[0], lv.nb, lv.part[1], lv.gs, tiny, g, active);
         }
-        return;
+        return lv.nb;
     }
+    const int ntile = tl ? (int)(lv.tile.ntx * lv.tile.nty) : lv.nb;
     {
         ProfScope ps(op, l == 0 ? CSG_PROF_STENCIL_DOTS : -1, st, by.st(0, lv.N));
         launch_st0<T, DIM>(L, B.u[0], W[0], sums && s == 1, lv.ld, lv.part[0], g, active);
     }
+    int nlast = lv.nb;   // partials written by the last pass
     for (int j = 0; j + 1 < s; ++j) {
         ProfScope ps(op, l == 0 ? CSG_PROF_STENCIL_DOTS : -1, st, by.os(j, lv.N));
-        launch_os<T, DIM>(L, B, W[j & 1], W[(j + 1) & 1], j, s, lv.ld, lv.part[j & 1], lv.nb, lv.part[(j + 1) & 1],
-                          lv.gs, tiny, g, active);
+        if (tl) {
+            launch_os_tile<T>(L, B, W[j & 1], W[(j + 1) & 1], j, s, lv.ld, lv.part[j & 1], nlast,
+                              lv.part[(j + 1) & 1], lv.gs, tiny, lv.tile, nrhs, st, active);
+            nlast = ntile;
+        } else {
+            launch_os<T, DIM>(L, B, W[j & 1], W[(j + 1) & 1], j, s, lv.ld, lv.part[j & 1], lv.nb,
+                              lv.part[(j + 1) & 1], lv.gs, tiny, g, active);
+        }
     }
     if (!sums) {
         // complex64: the last Gram-Schmidt pass forms u_s and its norm
         ProfScope ps(op, l == 0 ? CSG_PROF_ORTH : -1, st, by.orth(s - 1, lv.N));
-        launch_orthl<T>(B, W[(s - 1) & 1], s - 1, s, lv.N, lv.ld, lv.part[(s - 1) & 1], lv.nb, lv.part[s & 1], lv.gs,
+        launch_orthl<T>(B, W[(s - 1) & 1], s - 1, s, lv.N, lv.ld, lv.part[(s - 1) & 1], nlast, lv.part[s & 1], lv.gs,
                         tiny, g, active);
+        nlast = lv.nb;
     }
+    return nlast;
 }
 
 // Partials buffer the closing pass of a sweep on level l reads (written by the
 // last Arnoldi pass).
-template <typename T>
+template <typename T, int DIM>
 zc *close_part(const csg_operator *op, int l)
 {
     const DevLevel &lv = op->lev[l];
     const int s = op->p.s;
-    if (sizeof(T) == 8) return lv.N > op->fuse_max ? lv.part[0] : lv.part[(s - 1) & 1];
-    return lv.N > op->fuse_max ? lv.part[1] : lv.part[s & 1];
+    const bool unfused = !tiled<T, DIM>(op, l) && lv.N > op->fuse_max;
+    if (sizeof(T) == 8) return unfused ? lv.part[0] : lv.part[(s - 1) & 1];
+    return unfused ? lv.part[1] : lv.part[s & 1];
 }
 
 // Basis the closing pass combines: u_0..u_{s-1} and, in place of u_s, w_{s-1}
@@ -317,23 +361,23 @@ void sweep(const csg_operator *op, int l, const Cx<T> *b, Cx<T> *x, bool from_ze
         launch_resid<T, DIM>(L, x, b, (Cx<T> *)lv.r, lv.ld, g, active);
         B.u[0] = (Cx<T> *)lv.r;
     }
-    arnoldi_passes<T, DIM>(op, l, B, nrhs, st, active);
+    const int nclose = arnoldi_passes<T, DIM>(op, l, B, nrhs, st, active);
     B = closing_basis<T>(op, l, B);
     const Bytes by = bytes_of(op, nrhs);
     const int k0 = l == 0 ? 0 : -1;   // instrumented kinds exist for the finest level only
-    zc *pclose = close_part<T>(op, l);
+    zc *pclose = close_part<T, DIM>(op, l);
     if (restrict_after) {
         // closing update writes x and the Arnoldi residual r; full weighting of r
         const DevLevel &cl = op->lev[l + 1];
         ProfScope ps(op, k0 ? -1 : CSG_PROF_UPD_RESTRICT, st,
                      by.upd_r(s, !from_zero, lv.N) + by.restrict_b(lv.N, cl.N));
-        launch_upd_r<T>(x, from_zero ? 0 : 1, (Cx<T> *)lv.r, B, s, lv.N, lv.ld, pclose, lv.nb, lv.gs, tiny, g,
+        launch_upd_r<T>(x, from_zero ? 0 : 1, (Cx<T> *)lv.r, B, s, lv.N, lv.ld, pclose, nclose, lv.gs, tiny, g,
                         active);
         launch_restrict<T, DIM>(L, lvl<T>(op, l + 1), nullptr, (const Cx<T> *)lv.r, (Cx<T> *)cl.b, lv.ld, cl.ld,
                                 lch(op, l + 1, nrhs, st), active);
     } else {
         ProfScope ps(op, k0 ? -1 : CSG_PROF_UPDATE, st, by.upd(s, !from_zero, lv.N));
-        launch_upd<T>(x, from_zero ? 0 : 1, B, s, lv.N, lv.ld, pclose, lv.nb, lv.gs, tiny, g, active);
+        launch_upd<T>(x, from_zero ? 0 : 1, B, s, lv.N, lv.ld, pclose, nclose, lv.gs, tiny, g, active);
     }
 }
 
@@ -393,10 +437,10 @@ void vcycle_impl(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, h
                 for (int i = 0; i <= CSG_MAX_S; ++i) B.u[i] = (Cx<T> *)d.u[i];
                 if (k > 0) launch_resid<T, DIM>(Lk, xo, b, (Cx<T> *)d.r, d.ld, g, active);
                 B.u[0] = (Cx<T> *)d.r;
-                arnoldi_passes<T, DIM>(op, l, B, nrhs, st, active);
+                const int nclose = arnoldi_passes<T, DIM>(op, l, B, nrhs, st, active);
                 B = closing_basis<T>(op, l, B);
                 ProfScope ps(op, l == 0 ? CSG_PROF_UPDATE : -1, st, bytes_of(op, nrhs).upd(s, true, d.N));
-                launch_upd<T>(xo, 1, B, s, d.N, d.ld, close_part<T>(op, l), d.nb, d.gs, tiny, g, active);
+                launch_upd<T>(xo, 1, B, s, d.N, d.ld, close_part<T, DIM>(op, l), nclose, d.gs, tiny, g, active);
             }
         }
     }
@@ -788,6 +832,8 @@ int csg_operator_create(const csg_params *p, const double *phi_host, void *ws_de
         op->fuse_max = 300000;
         if (const char *e = getenv("CSG_FUSE_MAX")) op->fuse_max = atol(e);
         if (p->fuse_max) op->fuse_max = p->fuse_max < 0 ? 0 : p->fuse_max;
+        op->tiles = true;
+        if (const char *e = getenv("CSG_TILES")) op->tiles = atoi(e) != 0;
         op->lt = op->L - 1;
         for (int l = 0; l < op->L; ++l)
             if ((long)op->lev[l].N <= tail_max) { op->lt = l; break; }

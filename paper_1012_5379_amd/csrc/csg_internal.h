@@ -92,6 +92,16 @@ int build_hierarchy(const csg_params &p, const double *phi, HostHier &hh, std::s
 // Device hierarchy carved from the caller's workspace
 // ---------------------------------------------------------------------------
 
+// 2-D tiling of a level for the LDS-staged fused pass: ntx x nty tiles of
+// tx x ty points (the last ones ragged); partial sums indexed by tile.
+struct TileGeo {
+    unsigned ntx, nty, tx, ty;
+};
+constexpr int TILE_MAXE = 10;                 // halo-tile points per thread
+constexpr int TILE_MAXN = TILE_MAXE * BLK;    // halo-tile points per block
+// Whether a tiling exists and its halo tile fits the shared-memory buffer.
+inline bool tile_fits(const TileGeo &t) { return t.ntx > 0 && (t.tx + 2) * (t.ty + 2) <= (unsigned)TILE_MAXN; }
+
 struct DevLevel {
     unsigned nu[3];
     unsigned N;
@@ -105,6 +115,7 @@ struct DevLevel {
     GState *gs;                // [max_rhs]
     int nb;                    // blocks of a reducing pass
     unsigned chunk;            // points per block of a reducing pass
+    TileGeo tile;              // 2-D tiling of the LDS-staged fused pass (ntx = 0: none)
 };
 
 // Instantiated graphs of one FGMRES iteration (V-cycle + outer passes), per
@@ -138,6 +149,7 @@ struct csg_operator {
     void *tlev;                       // device level descriptors of the coarse tail
     int lt;                           // first level handled by the coarse-tail kernel
     long fuse_max;                    // levels up to this size use the fused Arnoldi passes
+    bool tiles;                       // 2-D levels whose tiles fit use the LDS-staged fused pass
     // outer FGMRES storage
     csg::zc *V;                       // (m+1) x max_rhs x ld0
     void *Z;                          // m x max_rhs x ld0, cycle precision

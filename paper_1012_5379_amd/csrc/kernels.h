@@ -58,6 +58,14 @@ template <typename T, int DIM>
 void launch_os(const LvlK<T> &L, const Basis<T> &B, const Cx<T> *win, Cx<T> *wout, int j, int s, size_t ld,
                const zc *pin, int nbin, zc *pout, GState *gs, double tiny, const Launch &g, const int *active);
 
+// Fused pass j+1 on 2-D tiles (s <= 3): u_{j+1} is formed once per point of
+// the tile and its one-point halo into shared memory, then w_{j+1} = A u_{j+1}
+// is taken from there; same outputs as launch_os, partials by tile.
+template <typename T>
+void launch_os_tile(const LvlK<T> &L, const Basis<T> &B, const Cx<T> *win, Cx<T> *wout, int j, int s, size_t ld,
+                    const zc *pin, int nbin, zc *pout, GState *gs, double tiny, const TileGeo &tg, int nrhs,
+                    hipStream_t st, const int *active);
+
 template <typename T>
 void launch_orthl(const Basis<T> &B, const Cx<T> *win, int j, int s, unsigned N, size_t ld, const zc *pin, int nbin,
                   zc *pout, GState *gs, double tiny, const Launch &g, const int *active);

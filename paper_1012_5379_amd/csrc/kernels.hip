@@ -910,6 +910,104 @@ __global__ __launch_bounds__(BLK) void k_os(LvlK<T> L, Basis<T> B, const Cx<T> *
     if (threadIdx.x < nv) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + c] = res[threadIdx.x];
 }
 
+// Fused pass j+1 on one 2-D tile (see launch_os_tile).  Phase 1: every point
+// of the tile and its one-point halo forms u_{j+1} = sj w_j - sum_i cu_i u_i
+// (zero outside the level) into shared memory, the tile's own points also to
+// global memory, keeping their u_i in registers.  Phase 2: the tile's points
+// apply the stencil to the shared copy, write w_{j+1} and sum <u_i, w_{j+1}>
+// (i <= j+1), ||u_{j+1}||^2 and, on the last step, ||w_{j+1}||^2.  A thread
+// owns the same points in both phases.
+template <typename T, int SB>
+__global__ __launch_bounds__(BLK) void k_os_tile(LvlK<T> L, Basis<T> B, const Cx<T> *win, Cx<T> *wout, int j, int s,
+                                                 size_t ld, const zc *__restrict__ pin, int nbin,
+                                                 zc *__restrict__ pout, GState *gsb, double tiny, TileGeo tg,
+                                                 int ntile, const int *active)
+{
+    __shared__ zc sh[(BLK / 64) * (SB + 1)];
+    __shared__ zc res[SB + 1];
+    __shared__ Cx<T> lu[TILE_MAXN];
+    const int rhs = blockIdx.y;
+    if (!active[rhs]) return;
+    GState *gs = gsb + rhs;
+    const GPrev<SB> pv = load_prev<SB>(gs, j);
+    reduce_parts<SB + 1>(pin + (size_t)rhs * NVAL * NBMAX, nbin, j + 2, sh, res);
+    Cx<T> cu[SB];
+    const double sjd = coef_step<T, SB>(res, j, s, tiny, pv, gs, blockIdx.x == 0 && threadIdx.x == 0, cu);
+    const T sj = (T)sjd;
+    const unsigned t = chunk_id(ntile);
+    const unsigned tyi = t / tg.ntx, txi = t - tyi * tg.ntx;
+    const int nx = (int)L.nx, ny = (int)L.ny;
+    const int x0 = (int)(txi * tg.tx), y0 = (int)(tyi * tg.ty);
+    const int HX = min(x0 + (int)tg.tx, nx) - x0 + 2, HY = min(y0 + (int)tg.ty, ny) - y0 + 2;
+    const int HN = HX * HY;
+    const size_t off = rhs * ld;
+    const Cx<T> *wi = win + off;
+    Cx<T> *un = pick(B, j + 1) + off;
+    Cx<T> *wo = wout + off;
+    Cx<T> uq[TILE_MAXE][SB - 1];
+#pragma unroll
+    for (int it = 0; it < TILE_MAXE; ++it) {
+        const int e = threadIdx.x + it * BLK;
+        if (e >= HN) break;
+        const int ey = e / HX, ex = e - ey * HX;
+        const int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
+        Cx<T> v = mkc<T>(0, 0);
+        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+            const size_t p = (size_t)gy * nx + gx;
+            v = sj * wi[p];
+#pragma unroll
+            for (int q = 0; q < SB - 1; ++q)
+                if (q <= j) {
+                    uq[it][q] = B.u[q][off + p];
+                    v = v - cu[q] * uq[it][q];
+                }
+            if (ex >= 1 && ex <= HX - 2 && ey >= 1 && ey <= HY - 2) un[p] = v;
+        }
+        lu[e] = v;
+    }
+    __syncthreads();
+    zc acc[SB + 1];
+#pragma unroll
+    for (int q = 0; q <= SB; ++q) acc[q] = mkc(0.0, 0.0);
+    const bool wn = norm_from_sums<T>() && j + 2 == s;
+    const Cx<T> *tx = L.tab[0], *ty = L.tab[1];
+#pragma unroll
+    for (int it = 0; it < TILE_MAXE; ++it) {
+        const int e = threadIdx.x + it * BLK;
+        if (e >= HN) break;
+        const int ey = e / HX, ex = e - ey * HX;
+        if (ex < 1 || ex > HX - 2 || ey < 1 || ey > HY - 2) continue;
+        const int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
+        const size_t p = (size_t)gy * nx + gx;
+        const Cx<T> uc = lu[e];
+        Cx<T> d = tx[nx + gx] + ty[ny + gy];
+        d.re -= L.phi[p];
+        Cx<T> a = d * uc;
+        a = cfma(tx[gx], lu[e - 1], a);
+        a = cfma(tx[2 * nx + gx], lu[e + 1], a);
+        a = cfma(ty[gy], lu[e - HX], a);
+        a = cfma(ty[2 * ny + gy], lu[e + HX], a);
+        wo[p] = a;
+        const zc wd = cvt<double>(a), ud = cvt<double>(uc);
+#pragma unroll
+        for (int q = 0; q < SB - 1; ++q)
+            if (q <= j) acc[q] = cjfma(cvt<double>(uq[it][q]), wd, acc[q]);
+#pragma unroll
+        for (int q = 1; q < SB; ++q) {
+            if (q == j + 1) acc[q] = cjfma(ud, wd, acc[q]);
+            if (q == j + 2) acc[q].re += cabs2(ud);
+        }
+        if (wn) {
+#pragma unroll
+            for (int q = 3; q <= SB; ++q)
+                if (q == j + 3) acc[q].re += cabs2(wd);
+        }
+    }
+    const int nv = j + 3 + (wn ? 1 : 0);
+    block_sum<SB + 1>(acc, nv, sh, res);
+    if (threadIdx.x < nv) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + t] = res[threadIdx.x];
+}
+
 // last pass: u_s and ||u_s||^2
 template <typename T, int SB>
 __global__ __launch_bounds__(BLK) void k_orthl(Basis<T> B, const Cx<T> *win, int j, int s, unsigned N, size_t ld,
@@ -2114,6 +2212,16 @@ void launch_os(const LvlK<T> &L, const Basis<T> &B, const Cx<T> *win, Cx<T> *wou
 }
 
 template <typename T>
+void launch_os_tile(const LvlK<T> &L, const Basis<T> &B, const Cx<T> *win, Cx<T> *wout, int j, int s, size_t ld,
+                    const zc *pin, int nbin, zc *pout, GState *gs, double tiny, const TileGeo &tg, int nrhs,
+                    hipStream_t st, const int *active)
+{
+    const int ntile = (int)(tg.ntx * tg.nty);
+    hipLaunchKernelGGL((k_os_tile<T, 4>), dim3(ntile, nrhs), dim3(BLK), 0, st, L, B, win, wout, j, s, ld, pin, nbin,
+                       pout, gs, tiny, tg, ntile, active);
+}
+
+template <typename T>
 void launch_orthl(const Basis<T> &B, const Cx<T> *win, int j, int s, unsigned N, size_t ld, const zc *pin, int nbin,
                   zc *pout, GState *gs, double tiny, const Launch &g, const int *active)
 {
@@ -2313,6 +2421,9 @@ INST_TD(float, 3)
                                 double, const Launch &, const int *);                                              \
     template void launch_upd_r<T>(Cx<T> *, int, Cx<T> *, const Basis<T> &, int, unsigned, size_t, const zc *, int, \
                                   GState *, double, const Launch &, const int *);                                  \
+    template void launch_os_tile<T>(const LvlK<T> &, const Basis<T> &, const Cx<T> *, Cx<T> *, int, int, size_t,   \
+                                    const zc *, int, zc *, GState *, double, const TileGeo &, int, hipStream_t,    \
+                                    const int *);                                                                  \
     template void launch_coarse<T>(const Cx<T> *, int, const Cx<T> *, Cx<T> *, size_t, int, hipStream_t,          \
                                    const int *);                                                                   \
     template void launch_vnorm<T>(const zc *, zc *, Cx<T> *, unsigned, size_t, const FState *, const Launch &,     \
