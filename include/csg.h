@@ -209,10 +209,18 @@ enum {
     CSG_PROF_OUTER_CGS2 = 9,    /* FGMRES: second-round dots                  */
     CSG_PROF_OUTER_NORM = 10,   /* FGMRES: v_1 = r / beta at a cycle start    */
     CSG_PROF_OUTER_PROJ2 = 11,  /* FGMRES: second projection, scale, cast     */
-    CSG_PROF_KINDS = 12
+    CSG_PROF_FUSED = 12,        /* finest-level fused Gram-Schmidt + stencil  */
+    CSG_PROF_KINDS = 13
 };
 int csg_profile(csg_operator *op, int kind, int cap);
 int csg_profile_read(csg_operator *op, double *ms, long *launches, double *bytes);
+
+/* 1 when uninstrumented FGMRES iterations replay captured HIP graphs (the
+ * default), 0 when they run as individual launches (graphs disabled by
+ * csg_params.graphs, or capture unavailable).  While a pass kind is being
+ * timed (csg_profile) iterations always run as individual launches: events
+ * recorded inside a graph cannot be timed on this HIP. */
+int csg_graphs_active(const csg_operator *op);
 
 #ifdef __cplusplus
 }

@@ -69,11 +69,12 @@ _SIGS = {
     "csg_solve_end": (ip, [vp, C.POINTER(csg_solve_info)]),
     "csg_profile": (ip, [vp, ip, ip]),
     "csg_profile_read": (ip, [vp, C.POINTER(C.c_double), C.POINTER(C.c_long), C.POINTER(C.c_double)]),
+    "csg_graphs_active": (ip, [vp]),
 }
 
 PROF_KINDS = {"vcycle": 1, "stencil_dots": 2, "orth": 3, "upd_restrict": 4, "prolong_resid": 5,
               "update": 6, "outer_h": 7, "outer_cgs1": 8, "outer_cgs2": 9, "outer_norm": 10,
-              "outer_proj2": 11}
+              "outer_proj2": 11, "fused": 12}
 
 
 def lib() -> C.CDLL:
@@ -223,3 +224,7 @@ def csg_profile_read(op):
     ms, n, by = C.c_double(0), C.c_long(0), C.c_double(0)
     check(lib().csg_profile_read(op, C.byref(ms), C.byref(n), C.byref(by)))
     return ms.value, n.value, by.value
+
+
+def csg_graphs_active(op) -> bool:
+    return check(lib().csg_graphs_active(op)) == 1

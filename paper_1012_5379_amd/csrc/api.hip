@@ -300,7 +300,7 @@ int arnoldi_passes(const csg_operator *op, int l, const Basis<T> &B, int nrhs, h
     }
     int nlast = lv.nb;   // partials written by the last pass
     for (int j = 0; j + 1 < s; ++j) {
-        ProfScope ps(op, l == 0 ? CSG_PROF_STENCIL_DOTS : -1, st, by.os(j, lv.N));
+        ProfScope ps(op, l == 0 ? CSG_PROF_FUSED : -1, st, by.os(j, lv.N));
         if (tl) {
             launch_os_tile<T>(L, B, W[j & 1], W[(j + 1) & 1], j, s, lv.ld, lv.part[j & 1], nlast,
                               lv.part[(j + 1) & 1], lv.gs, tiny, lv.tile, nrhs, st, active);
@@ -555,6 +555,17 @@ void iter_body(csg_solve *sv, int j, hipStream_t st)
                      op->p.cycle_prec ? (Cx<TZ> *)op->b0 : nullptr, g, mask);
 }
 
+// Destroys every cached graph.
+void drop_graphs(csg_operator *op)
+{
+    GraphCache *gc = op->gc;
+    if (!gc) return;
+    for (auto &kv : gc->it)
+        for (hipGraphExec_t g : kv.second)
+            if (g) hipGraphExecDestroy(g);
+    gc->it.clear();
+}
+
 // Replays the captured graph of column j (capturing it on first use); eager
 // launches when graphs are disabled or a pass is being instrumented.
 template <typename TZ, int DIM>
@@ -564,6 +575,8 @@ void enqueue_iter(csg_solve *sv)
     GraphCache *gc = op->gc;
     const int j = sv->j;
     if (!gc || !gc->enabled || op->prof) {
+        // eager: graphs disabled, or launches being timed (this HIP cannot time
+        // events recorded inside a graph)
         iter_body<TZ, DIM>(sv, j, sv->st);
         return;
     }
@@ -581,6 +594,7 @@ void enqueue_iter(csg_solve *sv)
         if (graph) hipGraphDestroy(graph);
         if (!ok) {
             hipGetLastError();
+            drop_graphs(op);
             gc->enabled = false;   // capture unsupported here: stay eager
             iter_body<TZ, DIM>(sv, j, sv->st);
             return;
@@ -913,8 +927,8 @@ int csg_profile(csg_operator *op, int kind, int cap)
 {
     if (!op) return fail(CSG_EINVAL, "null operator");
     if (kind < 0 || kind >= CSG_PROF_KINDS || cap < 0 || cap > (1 << 20)) return fail(CSG_EINVAL, "bad profile kind/cap");
+    hipDeviceSynchronize();
     if (op->prof) {
-        hipDeviceSynchronize();
         for (hipEvent_t e : op->prof->ev) hipEventDestroy(e);
         delete op->prof;
         op->prof = nullptr;
@@ -951,10 +965,17 @@ int csg_profile_read(csg_operator *op, double *ms, long *launches, double *bytes
         n = pr->n;
         by = pr->bytes;
     }
+
     if (ms) *ms = tot;
     if (launches) *launches = n;
     if (bytes) *bytes = by;
     return CSG_OK;
+}
+
+int csg_graphs_active(const csg_operator *op)
+{
+    if (!op) return fail(CSG_EINVAL, "null operator");
+    return op->gc && op->gc->enabled ? 1 : 0;
 }
 
 int csg_operator_destroy(csg_operator *op)
@@ -963,9 +984,7 @@ int csg_operator_destroy(csg_operator *op)
     if (op->prof) csg_profile(op, CSG_PROF_OFF, 0);
     if (op->gc) {
         hipDeviceSynchronize();
-        for (auto &kv : op->gc->it)
-            for (hipGraphExec_t g : kv.second)
-                if (g) hipGraphExecDestroy(g);
+        drop_graphs(op);
         if (op->gc->cap) hipStreamDestroy(op->gc->cap);
         delete op->gc;
     }
@@ -1217,8 +1236,13 @@ int helm_solve(const csg_operator *op, const void *chi, void *u, int nrhs, doubl
         if (done) break;
         st = csg_solve_step(sv);
     }
+    const std::string first = g_err;
     int rc = csg_solve_end(sv, info);
-    return st != CSG_OK ? st : rc;
+    if (st != CSG_OK) {
+        g_err = first;   // report the failure that stopped the loop
+        return st;
+    }
+    return rc;
 }
 
 }  // extern "C"

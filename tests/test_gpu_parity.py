@@ -231,3 +231,27 @@ def test_graph_replay_matches_eager(monkeypatch):
         outs.append((host(u), [i["iterations"] for i in infos]))
     assert outs[0][1] == outs[1][1] == outs[2][1]
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][0], outs[2][0])
+
+
+def test_instrumented_solve_times_every_launch():
+    """Timing one pass kind (eager launches with event pairs) times every
+    finest-level fused pass of every iteration and leaves the results
+    bit-identical to the graph-replayed uninstrumented solve."""
+    import torch
+    from paper_1012_5379_amd import binding as B
+    w = CASES["2d_wide"]()
+    chi = dev(w.chi[:1], torch.complex128)
+    op, orc = pair(w, max_rhs=1, cycle_prec=0, restart=12)
+    u0, rc0, inf0 = op.solve(chi, tol=1e-9, restart=12, maxit=400)
+    assert B.csg_graphs_active(op.op)
+    B.csg_profile(op.op, B.PROF_KINDS["fused"], 1 << 16)
+    u1, rc1, inf1 = op.solve(chi, tol=1e-9, restart=12, maxit=400)
+    ms, n, by = B.csg_profile_read(op.op)
+    B.csg_profile(op.op, 0, 0)
+    its = inf1[0]["iterations"]
+    note(f"  {n} timed launches over {its} iterations, {ms:.3f} ms")
+    assert rc0 == 0 and rc1 == 0 and inf0[0]["iterations"] == its
+    assert np.array_equal(host(u0), host(u1))
+    # s - 1 fused passes per sweep, two sweeps per V-cycle, one V-cycle per iteration
+    assert n == its * 2 * (w.s - 1)
+    assert ms > 0 and by > 0
