@@ -24,6 +24,28 @@ import time
 import numpy as np
 
 HBM_PEAK_GBPS = 8000.0
+HERE = os.path.dirname(os.path.abspath(__file__))
+PMC_SUMMARY = os.path.join(HERE, "profiles", "pmc_fused_c2_1024sq_fp64.txt")
+
+
+def counted_traffic(kind: str, workload: str):
+    """HBM bytes per launch of the finest-level fused pass from the committed
+    rocprofv3 counter summary, if it was taken on the current library sources."""
+    if kind != "fused" or workload != "c2" or not os.path.exists(PMC_SUMMARY):
+        return None
+    from paper_1012_5379_amd.trace_summary import source_hash
+    vals = {}
+    with open(PMC_SUMMARY) as f:
+        for line in f:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_sha256") != source_hash():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 METRIC = "solves/s & p99 latency at relres 1e-6; V-cycle GB/s vs HBM peak"
 
 
@@ -278,7 +300,7 @@ def main():
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": None,
+            "traffic": counted_traffic(dominant, args.workload),
             "launches": kn,
             "avg_launch_us": kms * 1e3 / max(1, kn),
             "alg_bytes_per_launch": kbytes / max(1, kn),

@@ -1,0 +1,129 @@
+"""Summaries of rocprofv3 output for one benchmark run of libcsg.
+
+    python -m paper_1012_5379_amd.trace_summary kernels TRACE_CSV
+    python -m paper_1012_5379_amd.trace_summary counters FETCH_CSV WRITE_CSV --copy-bytes N
+
+`kernels` reads a kernel trace (rocprofv3 --kernel-trace --output-format csv)
+and prints, per kernel and grid size, the dispatch count and the average, min
+and max duration, then the finest-level fused Arnoldi pass on its own.  That
+pass shares its kernel and grid size with the next level's, so its launches
+are told apart by position: every FGMRES iteration is one V-cycle followed by
+k_hdot, and the V-cycle opens and closes on the finest level, so its first two
+and last two fused launches are the finest level's (s = 3).
+
+`counters` reads two counter collections of the same command (rocprofv3
+--pmc FETCH_SIZE, then --pmc WRITE_SIZE; KiB per dispatch), scales each by
+what the counter reads for the run's plain device-to-device copy of
+--copy-bytes bytes (the largest __amd_rocclr_copyBuffer dispatch), and prints
+the HBM bytes per launch of the finest-level fused pass, with the hash of the
+library sources the counters belong to.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import hashlib
+import os
+import sys
+
+FUSED = "k_os_tile"
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+
+
+def source_hash() -> str:
+    """sha256 over the library's sources (kernel counters are stale once it changes)."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def _short(name: str) -> str:
+    return name.split("(")[0].replace("void ", "").replace("csg::", "").strip()
+
+
+def _rows(path):
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def finest_fused(names):
+    """Indices (into the time-ordered dispatch list) of the finest-level fused
+    passes: per V-cycle window (between the previous iteration's last pass and
+    k_hdot) the first two and the last two fused launches."""
+    out = []
+    start = 0
+    for i, nm in enumerate(names):
+        if nm.startswith("k_hdot"):
+            win = [k for k in range(start, i) if names[k].startswith(FUSED)]
+            if len(win) >= 4:
+                out += win[:2] + win[-2:]
+            start = i + 1
+    return out
+
+
+def kernels(trace: str) -> None:
+    rows = sorted(_rows(trace), key=lambda r: int(r["Start_Timestamp"]))
+    dur = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows]
+    names = [_short(r["Kernel_Name"]) for r in rows]
+    by = collections.defaultdict(list)
+    for r, nm, d in zip(rows, names, dur):
+        g = int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"])
+        by[(nm, g)].append(d)
+    tot = sum(dur)
+    print(f"{'kernel':44s} {'blocks':>6s} {'n':>7s} {'avg us':>9s} {'min us':>8s} {'max us':>8s} {'total %':>8s}")
+    for (nm, g), v in sorted(by.items(), key=lambda kv: -sum(kv[1])):
+        print(f"{nm[:44]:44s} {g:6d} {len(v):7d} {sum(v) / len(v):9.2f} {min(v):8.2f} {max(v):8.2f} "
+              f"{100 * sum(v) / tot:8.2f}")
+    idx = finest_fused(names)
+    if idx:
+        d = [dur[i] for i in idx]
+        print(f"\nfinest-level fused pass ({FUSED}, first two and last two fused launches of each V-cycle): "
+              f"n {len(d)}, avg {sum(d) / len(d):.2f} us, min {min(d):.2f} us, max {max(d):.2f} us")
+    print(f"dispatches {len(rows)}, kernel time {tot / 1e3:.2f} ms")
+
+
+def counters(fetch_csv: str, write_csv: str, copy_bytes: int) -> None:
+    out = {}
+    for key, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = sorted(_rows(path), key=lambda r: int(r["Dispatch_Id"]))
+        names = [_short(r["Kernel_Name"]) for r in rows]
+        vals = [float(r["Counter_Value"]) * 1024.0 for r in rows]
+        copies = [v for nm, v in zip(names, vals) if nm.startswith("__amd_rocclr_copyBuffer")]
+        ref = max(copies) if copies else 0.0
+        scale = copy_bytes / ref if ref > 0 else float("nan")
+        idx = finest_fused(names)
+        per = [vals[i] * scale for i in idx]
+        out[key] = (scale, sum(per) / len(per) if per else float("nan"), len(per), ref)
+    f, w = out["FETCH_SIZE"], out["WRITE_SIZE"]
+    print(f"calibration copy: {copy_bytes} bytes; FETCH_SIZE read {f[3]:.0f} bytes (scale {f[0]:.4f}), "
+          f"WRITE_SIZE read {w[3]:.0f} bytes (scale {w[0]:.4f})")
+    print(f"finest-level fused pass: {f[2]} launches")
+    print(f"fetch_bytes_per_launch: {f[1]:.0f}")
+    print(f"write_bytes_per_launch: {w[1]:.0f}")
+    print(f"traffic_bytes_per_launch: {f[1] + w[1]:.0f}")
+    print(f"source_sha256: {source_hash()}")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    k = sub.add_parser("kernels")
+    k.add_argument("trace")
+    c = sub.add_parser("counters")
+    c.add_argument("fetch")
+    c.add_argument("write")
+    c.add_argument("--copy-bytes", type=int, required=True)
+    a = ap.parse_args(argv)
+    if a.cmd == "kernels":
+        kernels(a.trace)
+    else:
+        counters(a.fetch, a.write, a.copy_bytes)
+
+
+if __name__ == "__main__":
+    sys.exit(main())
