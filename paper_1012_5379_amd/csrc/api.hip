@@ -545,6 +545,9 @@ void iter_body(csg_solve *sv, int j, hipStream_t st)
         ProfScope ps(op, CSG_PROF_OUTER_CGS1, st, R * N * 16.0 * (j + 3));
         launch_proj0(op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->opart, g, mask);
     }
+    // first round final unless it cancelled heavily; the second-round passes
+    // below return at once (mdot, FIN_CN) or only scale (proj1) when it is
+    launch_fin(FIN_P, op->opart, f.nb, j, op->fs, op->rep, sv->nrhs, st, mask);
     {
         ProfScope ps(op, CSG_PROF_OUTER_CGS2, st, R * N * 16.0 * (j + 2));
         launch_mdot(op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->opart, g, mask);

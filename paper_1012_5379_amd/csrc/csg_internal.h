@@ -52,8 +52,10 @@ struct FState {
     double nchi;       // ||chi||
     double hn;         // h_{j+1,j} of the current column
     double inv_hn;     // scale applied to form v_{j+1}
+    double w2;         // ||H z_j||^2 of the current column
     int kcols;         // columns of the current restart cycle used by the update
-    int pad[3];
+    int reorth;        // the current column takes the second Gram-Schmidt round
+    int pad[2];
 };
 
 // Host-visible per-RHS report (copied back after every outer iteration).

@@ -143,7 +143,7 @@ void launch_uupd(zc *u, const Cx<TZ> *Z, size_t zstride, unsigned N, size_t ld, 
                  const int *active);
 
 // finish kernels: one block per RHS
-enum FinMode { FIN_H = 0, FIN_CN = 1, FIN_BEGIN = 3, FIN_BETA = 4, FIN_LS = 5 };
+enum FinMode { FIN_H = 0, FIN_CN = 1, FIN_P = 2, FIN_BEGIN = 3, FIN_BETA = 4, FIN_LS = 5 };
 void launch_fin(int mode, const zc *pin, int nbin, int j, FState *fs, Report *rep, int nrhs, hipStream_t st,
                 const int *active);
 

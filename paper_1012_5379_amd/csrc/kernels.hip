@@ -1775,6 +1775,7 @@ __global__ __launch_bounds__(BLK) void k_hdot(LvlK<double> H, const Cx<TZ> *__re
     zc acc[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc[q] = mkc(0.0, 0.0);
+    zc wn[1] = {mkc(0.0, 0.0)};
     if (p0 < p1) {
         const unsigned last = p1 - 1;
         for (unsigned p = p0; p < p1; p += UH * BLK) {
@@ -1793,6 +1794,7 @@ __global__ __launch_bounds__(BLK) void k_hdot(LvlK<double> H, const Cx<TZ> *__re
             for (int k = 0; k < UH; ++k) {
                 if (p + k * BLK >= p1) break;
                 w[off + p + k * BLK] = wv[k];
+                wn[0].re += cabs2(wv[k]);
 #pragma unroll
                 for (int q = 0; q < 8; ++q)
                     if (q <= j) acc[q] = cjfma(vv[k][q], wv[k], acc[q]);
@@ -1806,6 +1808,8 @@ __global__ __launch_bounds__(BLK) void k_hdot(LvlK<double> H, const Cx<TZ> *__re
         dots8(w, V, vstride, g, j, off, p0, p1, acc);
         store_group(acc, g, j, po, c, sh, res);
     }
+    block_sum<1>(wn, 1, sh, res);
+    if (threadIdx.x == 0) po[(j + 1) * NBMAX + c] = res[0];
 }
 
 // x(p) = w(p) - sum_{q <= j} a_q v_q(p) for the U points of one batch
@@ -1862,8 +1866,9 @@ __global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__r
 }
 
 // Second projection and normalisation: v_{j+1} = (w - sum_i c_i v_i) / h_{j+1,j}
-// (c = corr, 1/h = inv_hn from the finish of the second round), with the
-// optional cycle-precision copy of v_{j+1} (the next V-cycle's input).
+// (c = corr, 1/h = inv_hn from the finish of the column), with the optional
+// cycle-precision copy of v_{j+1} (the next V-cycle's input).  Columns that
+// skip the second round are only scaled.
 template <typename TB>
 __global__ __launch_bounds__(BLK) void k_proj1(const zc *__restrict__ w, const zc *__restrict__ V, size_t vstride,
                                                int j, unsigned N, size_t ld, const FState *fsb, zc *__restrict__ vout,
@@ -1873,7 +1878,8 @@ __global__ __launch_bounds__(BLK) void k_proj1(const zc *__restrict__ w, const z
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
     const FState *fs = fsb + rhs;
-    if (threadIdx.x <= j) cc[threadIdx.x] = fs->corr[threadIdx.x];
+    const bool two = fs->reorth != 0;
+    if (two && threadIdx.x <= j) cc[threadIdx.x] = fs->corr[threadIdx.x];
     __syncthreads();
     const double sc = fs->inv_hn;
     const size_t off = rhs * ld;
@@ -1883,7 +1889,12 @@ __global__ __launch_bounds__(BLK) void k_proj1(const zc *__restrict__ w, const z
     const unsigned last = p1 - 1;
     for (unsigned p = p0; p < p1; p += UO * BLK) {
         zc x[UO];
-        proj_batch(w, V, vstride, j, off, p, last, cc, x);
+        if (two) {
+            proj_batch(w, V, vstride, j, off, p, last, cc, x);
+        } else {
+#pragma unroll
+            for (int k = 0; k < UO; ++k) x[k] = w[off + min(p + k * BLK, last)];
+        }
 #pragma unroll
         for (int k = 0; k < UO; ++k) {
             if (p + k * BLK >= p1) break;
@@ -1902,7 +1913,7 @@ __global__ __launch_bounds__(BLK) void k_mdot(const zc *__restrict__ w, const zc
     __shared__ zc sh[(BLK / 64) * 8];
     __shared__ zc res[8];
     const int rhs = blockIdx.y;
-    if (!active[rhs]) return;
+    if (!active[rhs] || !fsb[rhs].reorth) return;
     const size_t off = rhs * ld;
     const unsigned c = chunk_id(nb);
     const unsigned p0 = c * chunk + threadIdx.x, p1 = min(N, c * chunk + chunk);
@@ -2096,14 +2107,18 @@ __global__ __launch_bounds__(FT) void k_fin(int mode, const zc *__restrict__ pin
         for (int i = threadIdx.x; i < k; i += FT) fs->y[i] = gy[i];
         return;
     }
-    // values: FIN_H: 0..j; FIN_CN: 0..j+1; FIN_BEGIN: 0, 1; others: 0
-    const int nv = mode == FIN_H ? j + 1 : (mode == FIN_CN ? j + 2 : (mode == FIN_BEGIN ? 2 : 1));
+    // FIN_CN finishes a column only when it took the second round; FIN_P only
+    // when it did not (see below)
+    if (mode == FIN_CN && !fs->reorth) return;
+    // values: FIN_H: 0..j+1; FIN_CN: 0..j+1; FIN_P: j+1; FIN_BEGIN: 0, 1; others: 0
+    const int q0 = mode == FIN_P ? j + 1 : 0;
+    const int nv = (mode == FIN_H || mode == FIN_CN || mode == FIN_P) ? j + 2 : (mode == FIN_BEGIN ? 2 : 1);
     const int grp = threadIdx.x / FG;
-    for (int q = grp; q < nv; q += FT / FG) {
+    for (int q = q0 + grp; q < nv; q += FT / FG) {
         const zc v = group_parts(pp + q * NBMAX, nbin);
         if (threadIdx.x % FG == 0) val[q] = v;
     }
-    if (mode == FIN_CN) {
+    if (mode == FIN_CN || mode == FIN_P) {
         for (int q = threadIdx.x; q < j; q += FT) {
             cs_s[q] = fs->cs[q];
             sn_s[q] = fs->sn[q];
@@ -2111,6 +2126,26 @@ __global__ __launch_bounds__(FT) void k_fin(int mode, const zc *__restrict__ pin
         for (int q = threadIdx.x; q <= j; q += FT) col[q] = fs->hcol[q];
     }
     __syncthreads();
+    if (mode == FIN_P) {
+        // after the first projection w1 = w - V h (value j+1 = ||w1||^2): when
+        // ||w1|| >= ||w|| / 100 the first round lost at most ~100 eps of
+        // orthogonality and the column is final (h_{j+1,j} = ||w1||); otherwise the
+        // second round (k_mdot, FIN_CN, k_proj1) restores it
+        __shared__ int two;
+        if (threadIdx.x == 0) {
+            const double w1 = val[j + 1].re;
+            two = !(w1 >= 1e-4 * fs->w2);
+            fs->reorth = two;
+            if (!two) {
+                for (int q = 0; q <= j; ++q) fs->corr[q] = mkc(0.0, 0.0);
+                givens_column(fs, rep + rhs, j, sqrt(w1), col, cs_s, sn_s);
+            }
+        }
+        __syncthreads();
+        if (!two)
+            for (int q = threadIdx.x; q <= j + 1; q += FT) fs->R[q * M + j] = col[q];
+        return;
+    }
     if (mode == FIN_CN) {
         // second-round coefficients c (values 0..j) and ||w1||^2 of the first
         // projection (value j+1): h_{j+1,j}^2 = ||w1||^2 - ||c||^2, the norm of
@@ -2139,6 +2174,7 @@ __global__ __launch_bounds__(FT) void k_fin(int mode, const zc *__restrict__ pin
     switch (mode) {
     case FIN_H:
         for (int q = 0; q <= j; ++q) fs->hcol[q] = val[q];
+        fs->w2 = val[j + 1].re;
         return;
     default: {
         // FIN_BEGIN / FIN_BETA: start of a restart cycle
