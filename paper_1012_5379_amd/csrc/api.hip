@@ -521,9 +521,12 @@ void enqueue_begin(csg_solve *sv, bool with_chi_norm)
 }
 
 // One FGMRES iteration (section 5): z_j = V(v_j), w = H z_j, classical
-// Gram-Schmidt against v_0..v_j twice (the first projection also yields
-// ||w1||^2, so h_{j+1,j} follows from the second-round coefficients), Givens
-// update, and v_{j+1} written normalised by the second projection.
+// Gram-Schmidt against v_0..v_j with ||w||^2 summed alongside, so
+// h_{j+1,j}^2 = ||w||^2 - ||h||^2 is known before the projection.  When the
+// projection keeps at least 1% of ||w|| one round is final and the first
+// projection writes v_{j+1}; otherwise a second round (dots, finish with
+// h_{j+1,j} from ||w1||^2 - ||c||^2, second projection) restores orthogonality.
+// Givens update on the device either way.
 template <typename TZ, int DIM>
 void iter_body(csg_solve *sv, int j, hipStream_t st)
 {
@@ -542,12 +545,12 @@ void iter_body(csg_solve *sv, int j, hipStream_t st)
     }
     launch_fin(FIN_H, op->opart, f.nb, j, op->fs, op->rep, sv->nrhs, st, mask);
     {
-        ProfScope ps(op, CSG_PROF_OUTER_CGS1, st, R * N * 16.0 * (j + 3));
-        launch_proj0(op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->opart, g, mask);
+        // first projection: writes v_{j+1} when the first round is final (the
+        // second-round passes below then return at once)
+        ProfScope ps(op, CSG_PROF_OUTER_CGS1, st, R * N * (16.0 * (j + 3) + (op->p.cycle_prec ? 8.0 : 0.0)));
+        launch_proj0<TZ>(op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->opart, op->V + (j + 1) * vstride,
+                         op->p.cycle_prec ? (Cx<TZ> *)op->b0 : nullptr, g, mask);
     }
-    // first round final unless it cancelled heavily; the second-round passes
-    // below return at once (mdot, FIN_CN) or only scale (proj1) when it is
-    launch_fin(FIN_P, op->opart, f.nb, j, op->fs, op->rep, sv->nrhs, st, mask);
     {
         ProfScope ps(op, CSG_PROF_OUTER_CGS2, st, R * N * 16.0 * (j + 2));
         launch_mdot(op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->opart, g, mask);

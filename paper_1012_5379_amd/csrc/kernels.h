@@ -116,9 +116,11 @@ template <typename TZ, int DIM>
 void launch_hdot(const LvlK<double> &H, const Cx<TZ> *z, zc *w, const zc *V, size_t vstride, int j, size_t ld,
                  zc *pout, const Launch &g, const int *active);
 
-// first projection w -= V hcol in place; partial ||w||^2 as value j+1
+// first projection w - V hcol: kept in w with its partial norm^2 (value j+1)
+// when the column takes the second round, else written normalised as v_{j+1}
+template <typename TB>
 void launch_proj0(zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, const FState *fs, zc *pout,
-                  const Launch &g, const int *active);
+                  zc *vout, Cx<TB> *bcast, const Launch &g, const int *active);
 
 // v_{j+1} = (w - V corr) * inv_hn, optional cycle-precision copy
 template <typename TB>
@@ -143,7 +145,7 @@ void launch_uupd(zc *u, const Cx<TZ> *Z, size_t zstride, unsigned N, size_t ld, 
                  const int *active);
 
 // finish kernels: one block per RHS
-enum FinMode { FIN_H = 0, FIN_CN = 1, FIN_P = 2, FIN_BEGIN = 3, FIN_BETA = 4, FIN_LS = 5 };
+enum FinMode { FIN_H = 0, FIN_CN = 1, FIN_BEGIN = 3, FIN_BETA = 4, FIN_LS = 5 };
 void launch_fin(int mode, const zc *pin, int nbin, int j, FState *fs, Report *rep, int nrhs, hipStream_t st,
                 const int *active);
 

@@ -1829,12 +1829,15 @@ __device__ __forceinline__ void proj_batch(const zc *w, const zc *V, size_t vstr
     }
 }
 
-// First projection w <- w - sum_i h_i v_i (h = hcol), in place, with the
-// partial ||w||^2 of the result as value j+1 (values 0..j are left to the
-// second-round inner products).
+// First projection x = w - sum_i h_i v_i (h = hcol).  Columns that take the
+// second round keep x in w with the partial ||x||^2 as value j+1 (values 0..j
+// are left to the second-round inner products); the others are final and
+// write v_{j+1} = x / h_{j+1,j} and its optional cycle-precision copy.
+template <typename TB>
 __global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__restrict__ V, size_t vstride, int j,
                                                unsigned N, size_t ld, const FState *fsb, zc *__restrict__ pout,
-                                               unsigned chunk, int nb, const int *active)
+                                               zc *__restrict__ vout, Cx<TB> *__restrict__ bc, unsigned chunk,
+                                               int nb, const int *active)
 {
     __shared__ zc sh[BLK / 64];
     __shared__ zc res[1];
@@ -1843,6 +1846,8 @@ __global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__r
     if (!active[rhs]) return;
     const FState *fs = fsb + rhs;
     if (threadIdx.x <= j) cc[threadIdx.x] = fs->hcol[threadIdx.x];
+    const bool two = fs->reorth != 0;
+    const double sc = fs->inv_hn;
     __syncthreads();
     const size_t off = rhs * ld;
     zc acc[1] = {mkc(0.0, 0.0)};
@@ -1856,19 +1861,26 @@ __global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__r
 #pragma unroll
             for (int k = 0; k < UO; ++k) {
                 if (p + k * BLK >= p1) break;
-                w[off + p + k * BLK] = x[k];
-                acc[0].re += cabs2(x[k]);
+                if (two) {
+                    w[off + p + k * BLK] = x[k];
+                    acc[0].re += cabs2(x[k]);
+                } else {
+                    const zc v = sc * x[k];
+                    vout[off + p + k * BLK] = v;
+                    if (bc) bc[off + p + k * BLK] = cvt<TB>(v);
+                }
             }
         }
     }
+    if (!two) return;
     block_sum<1>(acc, 1, sh, res);
     if (threadIdx.x == 0) pout[((size_t)rhs * OVAL + j + 1) * NBMAX + c] = res[0];
 }
 
 // Second projection and normalisation: v_{j+1} = (w - sum_i c_i v_i) / h_{j+1,j}
 // (c = corr, 1/h = inv_hn from the finish of the column), with the optional
-// cycle-precision copy of v_{j+1} (the next V-cycle's input).  Columns that
-// skip the second round are only scaled.
+// cycle-precision copy of v_{j+1} (the next V-cycle's input); columns without
+// the second round return at once.
 template <typename TB>
 __global__ __launch_bounds__(BLK) void k_proj1(const zc *__restrict__ w, const zc *__restrict__ V, size_t vstride,
                                                int j, unsigned N, size_t ld, const FState *fsb, zc *__restrict__ vout,
@@ -1878,8 +1890,8 @@ __global__ __launch_bounds__(BLK) void k_proj1(const zc *__restrict__ w, const z
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
     const FState *fs = fsb + rhs;
-    const bool two = fs->reorth != 0;
-    if (two && threadIdx.x <= j) cc[threadIdx.x] = fs->corr[threadIdx.x];
+    if (!fs->reorth) return;   // v_{j+1} already written by the first projection
+    if (threadIdx.x <= j) cc[threadIdx.x] = fs->corr[threadIdx.x];
     __syncthreads();
     const double sc = fs->inv_hn;
     const size_t off = rhs * ld;
@@ -1889,12 +1901,7 @@ __global__ __launch_bounds__(BLK) void k_proj1(const zc *__restrict__ w, const z
     const unsigned last = p1 - 1;
     for (unsigned p = p0; p < p1; p += UO * BLK) {
         zc x[UO];
-        if (two) {
-            proj_batch(w, V, vstride, j, off, p, last, cc, x);
-        } else {
-#pragma unroll
-            for (int k = 0; k < UO; ++k) x[k] = w[off + min(p + k * BLK, last)];
-        }
+        proj_batch(w, V, vstride, j, off, p, last, cc, x);
 #pragma unroll
         for (int k = 0; k < UO; ++k) {
             if (p + k * BLK >= p1) break;
@@ -2107,39 +2114,45 @@ __global__ __launch_bounds__(FT) void k_fin(int mode, const zc *__restrict__ pin
         for (int i = threadIdx.x; i < k; i += FT) fs->y[i] = gy[i];
         return;
     }
-    // FIN_CN finishes a column only when it took the second round; FIN_P only
-    // when it did not (see below)
+    // FIN_CN finishes a column only when it took the second round
     if (mode == FIN_CN && !fs->reorth) return;
-    // values: FIN_H: 0..j+1; FIN_CN: 0..j+1; FIN_P: j+1; FIN_BEGIN: 0, 1; others: 0
-    const int q0 = mode == FIN_P ? j + 1 : 0;
-    const int nv = (mode == FIN_H || mode == FIN_CN || mode == FIN_P) ? j + 2 : (mode == FIN_BEGIN ? 2 : 1);
+    // values: FIN_H: 0..j+1; FIN_CN: 0..j+1; FIN_BEGIN: 0, 1; others: 0
+    const int nv = (mode == FIN_H || mode == FIN_CN) ? j + 2 : (mode == FIN_BEGIN ? 2 : 1);
     const int grp = threadIdx.x / FG;
-    for (int q = q0 + grp; q < nv; q += FT / FG) {
+    for (int q = grp; q < nv; q += FT / FG) {
         const zc v = group_parts(pp + q * NBMAX, nbin);
         if (threadIdx.x % FG == 0) val[q] = v;
     }
-    if (mode == FIN_CN || mode == FIN_P) {
+    if (mode == FIN_CN || mode == FIN_H) {
         for (int q = threadIdx.x; q < j; q += FT) {
             cs_s[q] = fs->cs[q];
             sn_s[q] = fs->sn[q];
         }
-        for (int q = threadIdx.x; q <= j; q += FT) col[q] = fs->hcol[q];
+        if (mode == FIN_CN)
+            for (int q = threadIdx.x; q <= j; q += FT) col[q] = fs->hcol[q];
     }
     __syncthreads();
-    if (mode == FIN_P) {
-        // after the first projection w1 = w - V h (value j+1 = ||w1||^2): when
-        // ||w1|| >= ||w|| / 100 the first round lost at most ~100 eps of
-        // orthogonality and the column is final (h_{j+1,j} = ||w1||); otherwise the
-        // second round (k_mdot, FIN_CN, k_proj1) restores it
+    if (mode == FIN_H) {
+        // first-round coefficients h (values 0..j) and ||w||^2 (value j+1) of
+        // w = H z_j.  w1 = w - V h has ||w1||^2 = ||w||^2 - ||h||^2 (V orthonormal).
+        // When ||w1|| >= ||w|| / 100 the single round lost at most ~100 eps of
+        // orthogonality: the column is final, h_{j+1,j} = ||w1|| and the first
+        // projection writes v_{j+1} directly.  Otherwise the second round
+        // (k_proj0 keeps w1, k_mdot, FIN_CN, k_proj1) restores orthogonality.
         __shared__ int two;
         if (threadIdx.x == 0) {
-            const double w1 = val[j + 1].re;
-            two = !(w1 >= 1e-4 * fs->w2);
-            fs->reorth = two;
-            if (!two) {
-                for (int q = 0; q <= j; ++q) fs->corr[q] = mkc(0.0, 0.0);
-                givens_column(fs, rep + rhs, j, sqrt(w1), col, cs_s, sn_s);
+            const double w2 = val[j + 1].re;
+            double h2 = 0.0;
+            for (int q = 0; q <= j; ++q) {
+                col[q] = val[q];
+                fs->hcol[q] = val[q];
+                h2 += cabs2(val[q]);
             }
+            fs->w2 = w2;
+            const double w1 = w2 - h2;
+            two = !(w1 >= 1e-4 * w2);
+            fs->reorth = two;
+            if (!two) givens_column(fs, rep + rhs, j, sqrt(w1), col, cs_s, sn_s);
         }
         __syncthreads();
         if (!two)
@@ -2172,10 +2185,6 @@ __global__ __launch_bounds__(FT) void k_fin(int mode, const zc *__restrict__ pin
     }
     if (threadIdx.x != 0) return;
     switch (mode) {
-    case FIN_H:
-        for (int q = 0; q <= j; ++q) fs->hcol[q] = val[q];
-        fs->w2 = val[j + 1].re;
-        return;
     default: {
         // FIN_BEGIN / FIN_BETA: start of a restart cycle
         const double beta = sqrt(val[0].re);
@@ -2352,10 +2361,12 @@ void launch_hdot(const LvlK<double> &H, const Cx<TZ> *z, zc *w, const zc *V, siz
                        g.nb, active);
 }
 
+template <typename TB>
 void launch_proj0(zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, const FState *fs, zc *pout,
-                  const Launch &g, const int *active)
+                  zc *vout, Cx<TB> *bcast, const Launch &g, const int *active)
 {
-    hipLaunchKernelGGL(k_proj0, grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, pout, g.chunk, g.nb, active);
+    hipLaunchKernelGGL((k_proj0<TB>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, pout, vout, bcast,
+                       g.chunk, g.nb, active);
 }
 
 template <typename TB>
@@ -2465,6 +2476,8 @@ INST_TD(float, 3)
     template void launch_vnorm<T>(const zc *, zc *, Cx<T> *, unsigned, size_t, const FState *, const Launch &,     \
                                   const int *);                                                                    \
     template void launch_proj1<T>(const zc *, const zc *, size_t, int, unsigned, size_t, const FState *, zc *,     \
+                                  Cx<T> *, const Launch &, const int *);                                           \
+    template void launch_proj0<T>(zc *, const zc *, size_t, int, unsigned, size_t, const FState *, zc *, zc *,     \
                                   Cx<T> *, const Launch &, const int *);                                           \
     template void launch_uupd<T>(zc *, const Cx<T> *, size_t, unsigned, size_t, const FState *, const Launch &,    \
                                  const int *);
