@@ -405,7 +405,7 @@ void vcycle_impl(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, h
         const Cx<T> *bt = lt == 0 ? b0 : (const Cx<T> *)op->lev[lt].b;
         Cx<T> *xt = lt == 0 ? x0 : (Cx<T> *)op->lev[lt].xb;
         launch_tail<T, DIM>((const TLev<T> *)op->tlev, lt, L, bt, xt, (const Cx<T> *)op->minvT, op->nc, op->p.s, nu1,
-                            nu2, tiny_of<T>(), nrhs, st, active);
+                            nu2, tiny_of<T>(), nrhs, op->tail_lds, st, active);
     }
     for (int l = lt - 1; l >= 0; --l) {
         const DevLevel &lv = op->lev[l];
@@ -857,6 +857,25 @@ int csg_operator_create(const csg_params *p, const double *phi_host, void *ws_de
         op->lt = op->L - 1;
         for (int l = 0; l < op->L; ++l)
             if ((long)op->lev[l].N <= tail_max) { op->lt = l; break; }
+        // the tail keeps its vectors in shared memory when they fit
+        op->tail_lds = 0;
+        bool lds_on = true;
+        if (const char *e = getenv("CSG_TAIL_LDS")) lds_on = atoi(e) != 0;
+        if (lds_on) {
+            unsigned Ns[CSG_MAX_LEVELS];
+            for (int l = 0; l < op->L; ++l) Ns[l] = op->lev[l].N;
+            const bool c64 = p->cycle_prec != 0, d3 = p->dim == 3;
+            const size_t need = c64 ? (d3 ? tail_lds_bytes<float, 3>(Ns, op->lt, op->L, p->s)
+                                          : tail_lds_bytes<float, 2>(Ns, op->lt, op->L, p->s))
+                                    : (d3 ? tail_lds_bytes<double, 3>(Ns, op->lt, op->L, p->s)
+                                          : tail_lds_bytes<double, 2>(Ns, op->lt, op->L, p->s));
+            const bool ok = need <= TAIL_LDS_MAX &&
+                            (c64 ? (d3 ? tail_lds_prepare<float, 3>(need, p->s) : tail_lds_prepare<float, 2>(need, p->s))
+                                 : (d3 ? tail_lds_prepare<double, 3>(need, p->s)
+                                       : tail_lds_prepare<double, 2>(need, p->s)));
+            if (ok) op->tail_lds = need;
+            hipGetLastError();
+        }
         std::vector<TLev<double>> tl(op->L);
         for (int l = 0; l < op->L; ++l) {
             const DevLevel &d = op->lev[l];

@@ -150,6 +150,7 @@ struct csg_operator {
     int nc;
     void *tlev;                       // device level descriptors of the coarse tail
     int lt;                           // first level handled by the coarse-tail kernel
+    size_t tail_lds;                  // shared-memory bytes of the tail's vectors (0: tail in global memory)
     long fuse_max;                    // levels up to this size use the fused Arnoldi passes
     bool tiles;                       // 2-D levels whose tiles fit use the LDS-staged fused pass
     // outer FGMRES storage

@@ -108,7 +108,16 @@ void launch_coarse(const Cx<T> *minvT, int n, const Cx<T> *b, Cx<T> *x, size_t l
 // output x at level lt).
 template <typename T, int DIM>
 void launch_tail(const TLev<T> *lev, int lt, int L, const Cx<T> *b_in, Cx<T> *x_out, const Cx<T> *minvT, int nc,
-                 int s, int nu1, int nu2, double tiny, int nrhs, hipStream_t st, const int *active);
+                 int s, int nu1, int nu2, double tiny, int nrhs, size_t lds, hipStream_t st, const int *active);
+
+// Shared-memory bytes of the tail's vectors from level lt down (N[l] unknowns
+// per level), and the one-time launch attribute that allows them (false: the
+// tail runs from global memory).
+template <typename T, int DIM>
+size_t tail_lds_bytes(const unsigned *N, int lt, int L, int s);
+template <typename T, int DIM>
+bool tail_lds_prepare(size_t bytes, int s);
+constexpr size_t TAIL_LDS_MAX = 156 * 1024;   // of the 160 KB per workgroup, the rest static
 
 // ---- outer FGMRES passes (FP64 arithmetic; TZ = cycle precision) ----------
 // w = H z and <v_i, w> (i <= j)

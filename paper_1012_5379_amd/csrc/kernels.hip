@@ -1596,7 +1596,38 @@ template <typename T, int SB>
 __device__ int tail_close(const GState *gs, int s, zc *Rs, zc *ys, zc *crs, zc *ax, zc *ar, int *ks, const zc *fold,
                           Cx<T> (&cx)[SB], Cx<T> (&cr)[SB])
 {
-    if (threadIdx.x == 0) {
+    if (SB <= 4 && threadIdx.x == 0) {
+        // register copy of Hbar (s <= 3), the same arithmetic as gmres_ls
+        constexpr int K = SB - 1;
+        zc H[SB][K];
+#pragma unroll
+        for (int r = 0; r < SB; ++r)
+#pragma unroll
+            for (int c = 0; c < K; ++c) H[r][c] = (c < s && r <= c + 1) ? gs->H[r * CSG_MAX_S + c] : mkc(0.0, 0.0);
+        const double beta0 = gs->beta0;
+        int k = gs->k;
+        if (k > s) k = s;
+        if (!(beta0 > 0.0)) k = 0;
+        zc yl[K];
+        ls_regs<SB>(H, beta0, k, yl);
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if (i < k) ax[i] = gs->sig[i] * yl[i];
+#pragma unroll
+        for (int i = 0; i < SB; ++i) {
+            zc acc = (i == 0) ? mkc(beta0, 0.0) : mkc(0.0, 0.0);
+#pragma unroll
+            for (int c = 0; c < K; ++c)
+                if (c < k && i <= c + 1) acc = acc - H[i][c] * yl[c];
+            if (i <= k) ar[i] = gs->sig[i] * acc;
+        }
+        if (norm_from_sums<T>() && k == s) {
+            const zc as = ar[s];
+            for (int i = 0; i < s; ++i) ar[i] = ar[i] - as * fold[i];
+            ar[s] = fold[s].re * as;
+        }
+        *ks = k;
+    } else if (threadIdx.x == 0) {
         const double hn = gs->H[s * CSG_MAX_S + (s - 1)].re;
         const int k = gmres_ls<SB>(gs, s, hn, Rs, ys, crs);
         for (int i = 0; i < k; ++i) ax[i] = gs->sig[i] * ys[i];
@@ -1612,6 +1643,129 @@ __device__ int tail_close(const GState *gs, int s, zc *Rs, zc *ys, zc *crs, zc *
     const int k = *ks;
     coefs_to_T<T, SB>(k, ax, ar, cx, cr);
     return k;
+}
+
+// Vectors of one level of the shared-memory tail: [b | x | u_0 .. | w_0 | w_1],
+// N elements each (the coarsest level uses b and x only).
+template <typename T>
+struct LdsLev {
+    Cx<T> *b, *x, *u[CSG_MAX_S + 1], *w[2];
+};
+
+// Elements of one tail level's block: b, x, the basis (u_0..u_{s-1}, and u_s
+// when the sweep forms it) and the two stencil outputs.
+template <typename T>
+__host__ __device__ __forceinline__ int tail_vectors(int s)
+{
+    return 2 + s + (norm_from_sums<T>() ? 0 : 1) + 2;
+}
+
+// The coarse tail with every level's vectors in shared memory: the top
+// level's b is copied in once, its x out once; tables, phi and the coarsest
+// inverse stay in global memory (read-only).  Same passes as k_tail, except
+// that the interpolated correction is applied in place and the residual that
+// opens the post-sweep is a separate pass (no second x buffer).
+template <typename T, int DIM, int SB>
+__global__ __launch_bounds__(TB) void k_tail_lds(const TLev<T> *__restrict__ lev, int lt, int L, const Cx<T> *b_in,
+                                                 Cx<T> *x_out, const Cx<T> *__restrict__ minvT, int nc, int s,
+                                                 int nu1, int nu2, double tiny, const int *active)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ GState gs;
+    __shared__ zc sh[TW * NVAL];
+    __shared__ zc res[NVAL];
+    __shared__ zc Rs[(CSG_MAX_S + 1) * CSG_MAX_S], ys[CSG_MAX_S], crs[CSG_MAX_S + 1], ax[CSG_MAX_S],
+        ar[CSG_MAX_S + 1];
+    __shared__ int ks;
+    __shared__ zc fold[CSG_MAX_S + 1];
+    const int rhs = blockIdx.x;
+    if (!active[rhs]) return;
+    const int t = threadIdx.x;
+    const int nv = tail_vectors<T>(s);
+    const int nbas = nv - 4;   // basis vectors kept
+    auto level = [&](int l) {
+        size_t o = 0;
+        for (int k = lt; k < l; ++k) o += (size_t)nv * lev[k].N;
+        Cx<T> *p = reinterpret_cast<Cx<T> *>(smem) + o;
+        const size_t N = lev[l].N;
+        LdsLev<T> v;
+        v.b = p;
+        v.x = p + N;
+        for (int q = 0; q <= CSG_MAX_S; ++q) v.u[q] = q < nbas ? p + (2 + q) * N : nullptr;
+        v.w[0] = p + (2 + nbas) * N;
+        v.w[1] = p + (3 + nbas) * N;
+        return v;
+    };
+    {
+        const LdsLev<T> top = level(lt);
+        const Cx<T> *src = b_in + rhs * lev[lt].ld;
+        for (unsigned p = t; p < lev[lt].N; p += TB) top.b[p] = src[p];
+        __syncthreads();
+    }
+    // down: pre-smoothing and restriction
+    for (int l = lt; l < L - 1; ++l) {
+        const LvlK<T> F = tlvl(lev[l]), C = tlvl(lev[l + 1]);
+        const LdsLev<T> f = level(l), c = level(l + 1);
+        if (nu1 == 0) {
+            body_restrict<T, DIM>(F, C, nullptr, f.b, c.b, t, C.N, TB);
+            __syncthreads();
+            continue;
+        }
+        Basis<T> B;
+        for (int q = 0; q <= CSG_MAX_S; ++q) B.u[q] = f.u[q];
+        if (norm_from_sums<T>()) B.u[s] = f.w[(s - 1) & 1];   // closing combines w_{s-1} in place of u_s
+        for (int k = 0; k < nu1; ++k) {
+            if (k == 0) {
+                B.u[0] = f.b;
+            } else {
+                body_resid<T, DIM>(F, f.x, f.b, f.u[0], t, F.N, TB);
+                __syncthreads();
+                B.u[0] = f.u[0];
+            }
+            tail_steps<T, DIM, SB>(F, B, f.w[0], f.w[1], 0, s, tiny, &gs, sh, res, fold);
+            Cx<T> cx[SB], cr[SB];
+            const int kk = tail_close<T, SB>(&gs, s, Rs, ys, crs, ax, ar, &ks, fold, cx, cr);
+            if (k == nu1 - 1)
+                body_upd_res<T, DIM, SB>(f.x, k > 0, B, kk, cx, cr, F, C, c.b, 0, t, C.N, TB);
+            else
+                body_upd<T, SB>(f.x, k > 0, B, kk, cx, 0, t, F.N, TB);
+            __syncthreads();
+        }
+    }
+    // coarsest level: exact solve (partials in the top level's idle scratch
+    // vectors, or past the coarsest block when those are too short)
+    {
+        const LdsLev<T> c = level(L - 1);
+        const bool inside = lt < L - 1 && (size_t)(nv - 2) * lev[lt].N >= TB;
+        Cx<T> *cpart = inside ? level(lt).u[0] : c.x + lev[L - 1].N;
+        body_coarse<T, TB>(minvT, nc, c.b, c.x, cpart);
+        __syncthreads();
+    }
+    // up: interpolated correction (in place) and post-smoothing
+    for (int l = L - 2; l >= lt; --l) {
+        const LvlK<T> F = tlvl(lev[l]), C = tlvl(lev[l + 1]);
+        const LdsLev<T> f = level(l), c = level(l + 1);
+        body_prolong<T, DIM>(F, C, c.x, nu1 > 0 ? f.x : nullptr, f.x, t, F.N, TB);
+        __syncthreads();
+        if (nu2 == 0) continue;
+        Basis<T> B;
+        for (int q = 0; q <= CSG_MAX_S; ++q) B.u[q] = f.u[q];
+        if (norm_from_sums<T>()) B.u[s] = f.w[(s - 1) & 1];
+        for (int k = 0; k < nu2; ++k) {
+            body_resid<T, DIM>(F, f.x, f.b, f.u[0], t, F.N, TB);
+            __syncthreads();
+            tail_steps<T, DIM, SB>(F, B, f.w[0], f.w[1], 0, s, tiny, &gs, sh, res, fold);
+            Cx<T> cx[SB], cr[SB];
+            const int kk = tail_close<T, SB>(&gs, s, Rs, ys, crs, ax, ar, &ks, fold, cx, cr);
+            body_upd<T, SB>(f.x, 1, B, kk, cx, 0, t, F.N, TB);
+            __syncthreads();
+        }
+    }
+    {
+        const LdsLev<T> top = level(lt);
+        Cx<T> *dst = x_out + rhs * lev[lt].ld;
+        for (unsigned p = t; p < lev[lt].N; p += TB) dst[p] = top.x[p];
+    }
 }
 
 template <typename T, int DIM, int SB>
@@ -2412,9 +2566,35 @@ void launch_fin(int mode, const zc *pin, int nbin, int j, FState *fs, Report *re
 }
 
 template <typename T, int DIM>
-void launch_tail(const TLev<T> *lev, int lt, int L, const Cx<T> *b_in, Cx<T> *x_out, const Cx<T> *minvT, int nc,
-                 int s, int nu1, int nu2, double tiny, int nrhs, hipStream_t st, const int *active)
+size_t tail_lds_bytes(const unsigned *N, int lt, int L, int s)
 {
+    size_t n = 0;
+    for (int l = lt; l < L - 1; ++l) n += (size_t)tail_vectors<T>(s) * N[l];
+    n += 2 * (size_t)N[L - 1];
+    if (lt == L - 1 || (size_t)(tail_vectors<T>(s) - 2) * N[lt] < TB) n += TB;   // coarse-solve partials
+    return n * sizeof(Cx<T>);
+}
+
+template <typename T, int DIM>
+bool tail_lds_prepare(size_t bytes, int s)
+{
+    const void *f = s <= 3 ? (const void *)k_tail_lds<T, DIM, 4> : (const void *)k_tail_lds<T, DIM, NVAL - 1>;
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess;
+}
+
+template <typename T, int DIM>
+void launch_tail(const TLev<T> *lev, int lt, int L, const Cx<T> *b_in, Cx<T> *x_out, const Cx<T> *minvT, int nc,
+                 int s, int nu1, int nu2, double tiny, int nrhs, size_t lds, hipStream_t st, const int *active)
+{
+    if (lds) {
+        if (s <= 3)
+            hipLaunchKernelGGL((k_tail_lds<T, DIM, 4>), dim3(nrhs), dim3(TB), lds, st, lev, lt, L, b_in, x_out, minvT,
+                               nc, s, nu1, nu2, tiny, active);
+        else
+            hipLaunchKernelGGL((k_tail_lds<T, DIM, NVAL - 1>), dim3(nrhs), dim3(TB), lds, st, lev, lt, L, b_in, x_out,
+                               minvT, nc, s, nu1, nu2, tiny, active);
+        return;
+    }
     if (s <= 3)
         hipLaunchKernelGGL((k_tail<T, DIM, 4>), dim3(nrhs), dim3(TB), 0, st, lev, lt, L, b_in, x_out, minvT, nc, s, nu1,
                            nu2, tiny, active);
@@ -2454,7 +2634,9 @@ void launch_copy_mask(const int *src, int *dst, int n, hipStream_t st)
     template void launch_hdot<T, D>(const LvlK<double> &, const Cx<T> *, zc *, const zc *, size_t, int, size_t,    \
                                     zc *, const Launch &, const int *);                                            \
     template void launch_tail<T, D>(const TLev<T> *, int, int, const Cx<T> *, Cx<T> *, const Cx<T> *, int, int,     \
-                                    int, int, double, int, hipStream_t, const int *);
+                                    int, int, double, int, size_t, hipStream_t, const int *);                      \
+    template size_t tail_lds_bytes<T, D>(const unsigned *, int, int, int);                                         \
+    template bool tail_lds_prepare<T, D>(size_t, int);
 
 INST_TD(double, 2)
 INST_TD(double, 3)
