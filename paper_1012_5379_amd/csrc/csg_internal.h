@@ -100,6 +100,7 @@ struct TileGeo {
     unsigned ntx, nty, tx, ty;
 };
 constexpr int TILE_MAXE = 10;                 // halo-tile points per thread
+constexpr int TILE_PRE = 2;                   // of them loaded before the pass's reduction
 constexpr int TILE_MAXN = TILE_MAXE * BLK;    // halo-tile points per block
 // Whether a tiling exists and its halo tile fits the shared-memory buffer.
 inline bool tile_fits(const TileGeo &t) { return t.ntx > 0 && (t.tx + 2) * (t.ty + 2) <= (unsigned)TILE_MAXN; }

@@ -930,10 +930,6 @@ __global__ __launch_bounds__(BLK) void k_os_tile(LvlK<T> L, Basis<T> B, const Cx
     if (!active[rhs]) return;
     GState *gs = gsb + rhs;
     const GPrev<SB> pv = load_prev<SB>(gs, j);
-    reduce_parts<SB + 1>(pin + (size_t)rhs * NVAL * NBMAX, nbin, j + 2, sh, res);
-    Cx<T> cu[SB];
-    const double sjd = coef_step<T, SB>(res, j, s, tiny, pv, gs, blockIdx.x == 0 && threadIdx.x == 0, cu);
-    const T sj = (T)sjd;
     const unsigned t = chunk_id(ntile);
     const unsigned tyi = t / tg.ntx, txi = t - tyi * tg.ntx;
     const int nx = (int)L.nx, ny = (int)L.ny;
@@ -944,7 +940,26 @@ __global__ __launch_bounds__(BLK) void k_os_tile(LvlK<T> L, Basis<T> B, const Cx
     const Cx<T> *wi = win + off;
     Cx<T> *un = pick(B, j + 1) + off;
     Cx<T> *wo = wout + off;
-    Cx<T> uq[TILE_MAXE][SB - 1];
+    // the first TILE_PRE halo-tile points of each thread are loaded before the
+    // partial-sum reduction, so their memory latency overlaps it
+    Cx<T> uq[TILE_MAXE][SB - 1], wq[TILE_PRE];
+#pragma unroll
+    for (int it = 0; it < TILE_PRE; ++it) {
+        const int e = threadIdx.x + it * BLK;
+        const int ey = e / HX, ex = e - ey * HX;
+        const int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
+        if (e < HN && gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+            const size_t p = (size_t)gy * nx + gx;
+            wq[it] = wi[p];
+#pragma unroll
+            for (int q = 0; q < SB - 1; ++q)
+                if (q <= j) uq[it][q] = B.u[q][off + p];
+        }
+    }
+    reduce_parts<SB + 1>(pin + (size_t)rhs * NVAL * NBMAX, nbin, j + 2, sh, res);
+    Cx<T> cu[SB];
+    const double sjd = coef_step<T, SB>(res, j, s, tiny, pv, gs, blockIdx.x == 0 && threadIdx.x == 0, cu);
+    const T sj = (T)sjd;
 #pragma unroll
     for (int it = 0; it < TILE_MAXE; ++it) {
         const int e = threadIdx.x + it * BLK;
@@ -954,13 +969,17 @@ __global__ __launch_bounds__(BLK) void k_os_tile(LvlK<T> L, Basis<T> B, const Cx
         Cx<T> v = mkc<T>(0, 0);
         if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
             const size_t p = (size_t)gy * nx + gx;
-            v = sj * wi[p];
+            if (it < TILE_PRE) {
+                v = sj * wq[it < TILE_PRE ? it : 0];
+            } else {
+                v = sj * wi[p];
+#pragma unroll
+                for (int q = 0; q < SB - 1; ++q)
+                    if (q <= j) uq[it][q] = B.u[q][off + p];
+            }
 #pragma unroll
             for (int q = 0; q < SB - 1; ++q)
-                if (q <= j) {
-                    uq[it][q] = B.u[q][off + p];
-                    v = v - cu[q] * uq[it][q];
-                }
+                if (q <= j) v = v - cu[q] * uq[it][q];
             if (ex >= 1 && ex <= HX - 2 && ey >= 1 && ey <= HY - 2) un[p] = v;
         }
         lu[e] = v;
