@@ -70,8 +70,33 @@ __device__ __forceinline__ Cx<T> apply_pt(const LvlK<T> &L, const Cx<TI> *__rest
     return acc;
 }
 
-// Wavefront (64 lanes) butterfly, then the BLK/64 wavefronts in order.  Every
-// lane ends with bit-identical sums (pairwise additions are commutative).
+// One DPP step on a double (both 32-bit halves moved alike; lanes without a
+// source or masked off contribute 0).
+template <int CTRL, int ROWS, int BANKS, bool BC>
+__device__ __forceinline__ double dpp64(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, BANKS, BC);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, BANKS, BC);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wavefront, valid in lane 63: running sums over
+// 4, 8 and 16 lanes by row shifts, then row 15 / row 31 broadcasts.  A fixed
+// order of additions, a few VALU cycles per step.
+__device__ __forceinline__ double wave_sum(double v)
+{
+    double s = v + dpp64<0x111, 0xF, 0xF, true>(v);   // row_shr:1
+    s = s + dpp64<0x112, 0xF, 0xF, true>(v);          // row_shr:2
+    s = s + dpp64<0x113, 0xF, 0xF, true>(v);          // row_shr:3
+    s = s + dpp64<0x114, 0xF, 0xE, false>(s);         // row_shr:4 into lanes 4-15 of a row
+    s = s + dpp64<0x118, 0xF, 0xC, false>(s);         // row_shr:8 into lanes 8-15 of a row
+    s = s + dpp64<0x142, 0xA, 0xF, false>(s);         // lane 15 of a row into rows 1 and 3
+    s = s + dpp64<0x143, 0xC, 0xF, false>(s);         // lane 31 into rows 2 and 3
+    return s;
+}
+
+// Wavefront sums (lane 63), then the BLK/64 wavefronts in order; every thread
+// reads the same totals from res.
 template <int NV>
 __device__ __forceinline__ void block_sum(zc (&v)[NV], int nv, zc *sh, zc *res)
 {
@@ -80,14 +105,11 @@ __device__ __forceinline__ void block_sum(zc (&v)[NV], int nv, zc *sh, zc *res)
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
         if (q < nv) {
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                v[q].re += __shfl_xor(v[q].re, off, 64);
-                v[q].im += __shfl_xor(v[q].im, off, 64);
-            }
+            v[q].re = wave_sum(v[q].re);
+            v[q].im = wave_sum(v[q].im);
         }
     }
-    if (lane == 0) {
+    if (lane == 63) {
 #pragma unroll
         for (int q = 0; q < NV; ++q)
             if (q < nv) sh[wv * NV + q] = v[q];
@@ -1510,14 +1532,11 @@ __device__ __forceinline__ void tail_sum(zc (&v)[NV], int nv, zc *sh, zc *res)
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
         if (q < nv) {
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                v[q].re += __shfl_xor(v[q].re, off, 64);
-                v[q].im += __shfl_xor(v[q].im, off, 64);
-            }
+            v[q].re = wave_sum(v[q].re);
+            v[q].im = wave_sum(v[q].im);
         }
     }
-    if (lane == 0) {
+    if (lane == 63) {
 #pragma unroll
         for (int q = 0; q < NV; ++q)
             if (q < nv) sh[wv * NV + q] = v[q];
