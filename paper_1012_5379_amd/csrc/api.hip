@@ -217,6 +217,8 @@ struct Bytes {
     double restrict_b(double N, double Nc) const { return R * z * (N + Nc); }
     double prc(bool xin, double N, double Nc) const { return R * z * ((xin ? N : 0) + Nc + 3 * N) + p * N; }
     double prolong(bool xin, double N, double Nc) const { return R * z * ((xin ? N : 0) + Nc + N); }
+    // interpolation + residual + pass 0: reads xin, ec, b, phi; writes x, r, w_0
+    double up(bool xin, double N, double Nc) const { return R * z * ((xin ? N : 0) + Nc + 4 * N) + p * N; }
     double coarse(double n) const { return n * n * z + R * 2 * n * z; }
 };
 
@@ -268,8 +270,19 @@ bool tiled(const csg_operator *op, int l)
     return DIM == 2 && op->tiles && op->p.s <= 3 && tile_fits(op->lev[l].tile);
 }
 
+// Whether the up path of level l runs as one tiled pass (interpolation,
+// residual and pass 0 of the post-sweep).
 template <typename T, int DIM>
-int arnoldi_passes(const csg_operator *op, int l, const Basis<T> &B, int nrhs, hipStream_t st, const int *active)
+bool up_tiled(const csg_operator *op, int l)
+{
+    return tiled<T, DIM>(op, l) && op->up_tiles && up_fits(op->lev[l].tile);
+}
+
+// `first` > 0: pass 0 already ran (fused into the up-path pass), leaving
+// `first` partials in part[0].
+template <typename T, int DIM>
+int arnoldi_passes(const csg_operator *op, int l, const Basis<T> &B, int nrhs, hipStream_t st, const int *active,
+                   int first = 0)
 {
     const DevLevel &lv = op->lev[l];
     const int s = op->p.s;
@@ -294,11 +307,12 @@ int arnoldi_passes(const csg_operator *op, int l, const Basis<T> &B, int nrhs, h
         return lv.nb;
     }
     const int ntile = tl ? (int)(lv.tile.ntx * lv.tile.nty) : lv.nb;
-    {
+    int nlast = first;   // partials written by the last pass
+    if (first == 0) {
         ProfScope ps(op, l == 0 ? CSG_PROF_STENCIL_DOTS : -1, st, by.st(0, lv.N));
         launch_st0<T, DIM>(L, B.u[0], W[0], sums && s == 1, lv.ld, lv.part[0], g, active);
+        nlast = lv.nb;
     }
-    int nlast = lv.nb;   // partials written by the last pass
     for (int j = 0; j + 1 < s; ++j) {
         ProfScope ps(op, l == 0 ? CSG_PROF_FUSED : -1, st, by.os(j, lv.N));
         if (tl) {
@@ -418,7 +432,16 @@ void vcycle_impl(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, h
             launch_prolong<T, DIM>(lvl<T>(op, l), lvl<T>(op, l + 1), (const Cx<T> *)cl.xb, xi, xo, lv.ld, cl.ld, g,
                                    active);
         } else {
-            {
+            const bool ut = up_tiled<T, DIM>(op, l) && xi != xo;
+            const int ntile = (int)(lv.tile.ntx * lv.tile.nty);
+            if (ut) {
+                // interpolated correction, residual and the post-sweep's pass 0 per tile
+                ProfScope ps(op, l == 0 ? CSG_PROF_PROLONG_RESID : -1, st,
+                             bytes_of(op, nrhs).up(xi != nullptr, lv.N, cl.N));
+                launch_up_tile<T>(lvl<T>(op, l), lvl<T>(op, l + 1), (const Cx<T> *)cl.xb, xi, xo, b,
+                                  (Cx<T> *)lv.r, (Cx<T> *)lv.w[0], lv.ld, cl.ld, sizeof(T) == 8 && op->p.s == 1,
+                                  lv.part[0], lv.tile, nrhs, st, active);
+            } else {
                 // interpolated correction, then the residual that opens the post-sweep
                 const Bytes by = bytes_of(op, nrhs);
                 ProfScope ps(op, l == 0 ? CSG_PROF_PROLONG_RESID : -1, st,
@@ -437,7 +460,7 @@ void vcycle_impl(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, h
                 for (int i = 0; i <= CSG_MAX_S; ++i) B.u[i] = (Cx<T> *)d.u[i];
                 if (k > 0) launch_resid<T, DIM>(Lk, xo, b, (Cx<T> *)d.r, d.ld, g, active);
                 B.u[0] = (Cx<T> *)d.r;
-                const int nclose = arnoldi_passes<T, DIM>(op, l, B, nrhs, st, active);
+                const int nclose = arnoldi_passes<T, DIM>(op, l, B, nrhs, st, active, ut && k == 0 ? ntile : 0);
                 B = closing_basis<T>(op, l, B);
                 ProfScope ps(op, l == 0 ? CSG_PROF_UPDATE : -1, st, bytes_of(op, nrhs).upd(s, true, d.N));
                 launch_upd<T>(xo, 1, B, s, d.N, d.ld, close_part<T, DIM>(op, l), nclose, d.gs, tiny, g, active);
@@ -854,6 +877,8 @@ int csg_operator_create(const csg_params *p, const double *phi_host, void *ws_de
         if (p->fuse_max) op->fuse_max = p->fuse_max < 0 ? 0 : p->fuse_max;
         op->tiles = true;
         if (const char *e = getenv("CSG_TILES")) op->tiles = atoi(e) != 0;
+        op->up_tiles = true;
+        if (const char *e = getenv("CSG_UP_TILES")) op->up_tiles = atoi(e) != 0;
         op->lt = op->L - 1;
         for (int l = 0; l < op->L; ++l)
             if ((long)op->lev[l].N <= tail_max) { op->lt = l; break; }

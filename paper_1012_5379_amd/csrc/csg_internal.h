@@ -104,6 +104,11 @@ constexpr int TILE_PRE = 2;                   // of them loaded before the pass'
 constexpr int TILE_MAXN = TILE_MAXE * BLK;    // halo-tile points per block
 // Whether a tiling exists and its halo tile fits the shared-memory buffer.
 inline bool tile_fits(const TileGeo &t) { return t.ntx > 0 && (t.tx + 2) * (t.ty + 2) <= (unsigned)TILE_MAXN; }
+// The up-path tile pass (interpolation, residual and pass 0 of the post-sweep)
+// stages the tile with a two-point halo.
+constexpr int UP_MAXE = 11;                   // two-point-halo tile points per thread
+constexpr int UP_MAXN = UP_MAXE * BLK;
+inline bool up_fits(const TileGeo &t) { return tile_fits(t) && (t.tx + 4) * (t.ty + 4) <= (unsigned)UP_MAXN; }
 
 struct DevLevel {
     unsigned nu[3];
@@ -154,6 +159,7 @@ struct csg_operator {
     size_t tail_lds;                  // shared-memory bytes of the tail's vectors (0: tail in global memory)
     long fuse_max;                    // levels up to this size use the fused Arnoldi passes
     bool tiles;                       // 2-D levels whose tiles fit use the LDS-staged fused pass
+    bool up_tiles;                    // ... and the LDS-staged interpolation + residual + pass 0
     // outer FGMRES storage
     csg::zc *V;                       // (m+1) x max_rhs x ld0
     void *Z;                          // m x max_rhs x ld0, cycle precision

@@ -66,6 +66,16 @@ void launch_os_tile(const LvlK<T> &L, const Basis<T> &B, const Cx<T> *win, Cx<T>
                     const zc *pin, int nbin, zc *pout, GState *gs, double tiny, const TileGeo &tg, int nrhs,
                     hipStream_t st, const int *active);
 
+// Interpolated correction, the residual that opens the post-sweep and that
+// sweep's pass 0 on 2-D tiles: xout = xin + P ec (xin may be null, never
+// xout), r = b - A xout, w = A r with <r, w>, ||r||^2 (and ||w||^2 when
+// wnorm) per tile into pout.  Same outputs as launch_prolong, launch_resid and
+// launch_st0 in turn, partials by tile.
+template <typename T>
+void launch_up_tile(const LvlK<T> &F, const LvlK<T> &C, const Cx<T> *ec, const Cx<T> *xin, Cx<T> *xout,
+                    const Cx<T> *b, Cx<T> *r, Cx<T> *w, size_t ldf, size_t ldc, bool wnorm, zc *pout,
+                    const TileGeo &tg, int nrhs, hipStream_t st, const int *active);
+
 template <typename T>
 void launch_orthl(const Basis<T> &B, const Cx<T> *win, int j, int s, unsigned N, size_t ld, const zc *pin, int nbin,
                   zc *pout, GState *gs, double tiny, const Launch &g, const int *active);

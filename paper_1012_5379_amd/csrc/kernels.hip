@@ -1049,6 +1049,111 @@ __global__ __launch_bounds__(BLK) void k_os_tile(LvlK<T> L, Basis<T> B, const Cx
     if (threadIdx.x < nv) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + t] = res[threadIdx.x];
 }
 
+// Up-path pass on one 2-D tile (see launch_up_tile).  Phase 1: x = xin + P ec
+// on the tile and a two-point halo into shared memory (zero outside the level;
+// the tile's own points also to xout).  Phase 2: r = b - A x on the tile and a
+// one-point halo, held in registers (the tile's points also to r), then moved
+// into the shared buffer once every thread is done reading x.  Phase 3: w_0 =
+// A r on the tile with <r, w_0>, ||r||^2 and (NA = 3) ||w_0||^2.  A thread owns
+// the same points in phases 2 and 3.
+template <typename T, int NA>
+__global__ __launch_bounds__(BLK) void k_up_tile(LvlK<T> F, LvlK<T> C, const Cx<T> *__restrict__ ec,
+                                                 const Cx<T> *__restrict__ xin, Cx<T> *__restrict__ xout,
+                                                 const Cx<T> *__restrict__ b, Cx<T> *__restrict__ r,
+                                                 Cx<T> *__restrict__ w, size_t ldf, size_t ldc,
+                                                 zc *__restrict__ pout, TileGeo tg, int ntile, const int *active)
+{
+    __shared__ zc sh[(BLK / 64) * NA];
+    __shared__ zc res[NA];
+    __shared__ Cx<T> lx[UP_MAXN];
+    const int rhs = blockIdx.y;
+    if (!active[rhs]) return;
+    const unsigned t = chunk_id(ntile);
+    const unsigned tyi = t / tg.ntx, txi = t - tyi * tg.ntx;
+    const int nx = (int)F.nx, ny = (int)F.ny;
+    const int x0 = (int)(txi * tg.tx), y0 = (int)(tyi * tg.ty);
+    const int TX = min(x0 + (int)tg.tx, nx) - x0, TY = min(y0 + (int)tg.ty, ny) - y0;
+    const int AX = TX + 4, AN = AX * (TY + 4);   // x: tile and two-point halo
+    const int RX = TX + 2, RN = RX * (TY + 2);   // r: tile and one-point halo
+    const size_t off = rhs * ldf;
+    const Cx<T> *e = ec + rhs * ldc;
+#pragma unroll
+    for (int it = 0; it < UP_MAXE; ++it) {
+        const int q = threadIdx.x + it * BLK;
+        if (q >= AN) break;
+        const int qy = q / AX, qx = q - qy * AX;
+        const int gx = x0 - 2 + qx, gy = y0 - 2 + qy;
+        Cx<T> v = mkc<T>(0, 0);
+        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+            const size_t p = (size_t)gy * nx + gx;
+            v = prolong_pt<T, 2>(e, gx, gy, 0, C.nx, C.ny, 1);
+            if (xin) v = v + xin[off + p];
+            if (qx >= 2 && qx < TX + 2 && qy >= 2 && qy < TY + 2) xout[off + p] = v;
+        }
+        lx[q] = v;
+    }
+    __syncthreads();
+    const Cx<T> *tx = F.tab[0], *ty = F.tab[1];
+    Cx<T> rq[TILE_MAXE];
+#pragma unroll
+    for (int it = 0; it < TILE_MAXE; ++it) {
+        const int q = threadIdx.x + it * BLK;
+        if (q >= RN) break;
+        const int qy = q / RX, qx = q - qy * RX;
+        const int gx = x0 - 1 + qx, gy = y0 - 1 + qy;
+        Cx<T> v = mkc<T>(0, 0);
+        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+            const size_t p = (size_t)gy * nx + gx;
+            const int a = (qy + 1) * AX + qx + 1;
+            Cx<T> d = tx[nx + gx] + ty[ny + gy];
+            d.re -= F.phi[p];
+            Cx<T> ax = d * lx[a];
+            ax = cfma(tx[gx], lx[a - 1], ax);
+            ax = cfma(tx[2 * nx + gx], lx[a + 1], ax);
+            ax = cfma(ty[gy], lx[a - AX], ax);
+            ax = cfma(ty[2 * ny + gy], lx[a + AX], ax);
+            v = b[off + p] - ax;
+            if (qx >= 1 && qx <= TX && qy >= 1 && qy <= TY) r[off + p] = v;
+        }
+        rq[it] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < TILE_MAXE; ++it) {
+        const int q = threadIdx.x + it * BLK;
+        if (q >= RN) break;
+        lx[q] = rq[it];
+    }
+    __syncthreads();
+    zc acc[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) acc[q] = mkc(0.0, 0.0);
+#pragma unroll
+    for (int it = 0; it < TILE_MAXE; ++it) {
+        const int q = threadIdx.x + it * BLK;
+        if (q >= RN) break;
+        const int qy = q / RX, qx = q - qy * RX;
+        if (qx < 1 || qx > TX || qy < 1 || qy > TY) continue;
+        const int gx = x0 - 1 + qx, gy = y0 - 1 + qy;
+        const size_t p = (size_t)gy * nx + gx;
+        const Cx<T> uc = rq[it];
+        Cx<T> d = tx[nx + gx] + ty[ny + gy];
+        d.re -= F.phi[p];
+        Cx<T> a = d * uc;
+        a = cfma(tx[gx], lx[q - 1], a);
+        a = cfma(tx[2 * nx + gx], lx[q + 1], a);
+        a = cfma(ty[gy], lx[q - RX], a);
+        a = cfma(ty[2 * ny + gy], lx[q + RX], a);
+        w[off + p] = a;
+        const zc wd = cvt<double>(a), ud = cvt<double>(uc);
+        acc[0] = cjfma(ud, wd, acc[0]);
+        acc[1].re += cabs2(ud);
+        if (NA > 2) acc[NA - 1].re += cabs2(wd);
+    }
+    block_sum<NA>(acc, NA, sh, res);
+    if (threadIdx.x < NA) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + t] = res[threadIdx.x];
+}
+
 // last pass: u_s and ||u_s||^2
 template <typename T, int SB>
 __global__ __launch_bounds__(BLK) void k_orthl(Basis<T> B, const Cx<T> *win, int j, int s, unsigned N, size_t ld,
@@ -2459,6 +2564,20 @@ void launch_os_tile(const LvlK<T> &L, const Basis<T> &B, const Cx<T> *win, Cx<T>
 }
 
 template <typename T>
+void launch_up_tile(const LvlK<T> &F, const LvlK<T> &C, const Cx<T> *ec, const Cx<T> *xin, Cx<T> *xout,
+                    const Cx<T> *b, Cx<T> *r, Cx<T> *w, size_t ldf, size_t ldc, bool wnorm, zc *pout,
+                    const TileGeo &tg, int nrhs, hipStream_t st, const int *active)
+{
+    const int ntile = (int)(tg.ntx * tg.nty);
+    if (wnorm)
+        hipLaunchKernelGGL((k_up_tile<T, 3>), dim3(ntile, nrhs), dim3(BLK), 0, st, F, C, ec, xin, xout, b, r, w, ldf,
+                           ldc, pout, tg, ntile, active);
+    else
+        hipLaunchKernelGGL((k_up_tile<T, 2>), dim3(ntile, nrhs), dim3(BLK), 0, st, F, C, ec, xin, xout, b, r, w, ldf,
+                           ldc, pout, tg, ntile, active);
+}
+
+template <typename T>
 void launch_orthl(const Basis<T> &B, const Cx<T> *win, int j, int s, unsigned N, size_t ld, const zc *pin, int nbin,
                   zc *pout, GState *gs, double tiny, const Launch &g, const int *active)
 {
@@ -2682,6 +2801,9 @@ INST_TD(float, 2)
 INST_TD(float, 3)
 
 #define INST_T(T)                                                                                                  \
+    template void launch_up_tile<T>(const LvlK<T> &, const LvlK<T> &, const Cx<T> *, const Cx<T> *, Cx<T> *,      \
+                                    const Cx<T> *, Cx<T> *, Cx<T> *, size_t, size_t, bool, zc *, const TileGeo &,  \
+                                    int, hipStream_t, const int *);                                                \
     template void launch_orthl<T>(const Basis<T> &, const Cx<T> *, int, int, unsigned, size_t, const zc *, int,    \
                                   zc *, GState *, double, const Launch &, const int *);                            \
     template void launch_upd<T>(Cx<T> *, int, const Basis<T> &, int, unsigned, size_t, const zc *, int, GState *, \
