@@ -217,6 +217,11 @@ struct Bytes {
     double restrict_b(double N, double Nc) const { return R * z * (N + Nc); }
     double prc(bool xin, double N, double Nc) const { return R * z * ((xin ? N : 0) + Nc + 3 * N) + p * N; }
     double prolong(bool xin, double N, double Nc) const { return R * z * ((xin ? N : 0) + Nc + N); }
+    // closing + restriction (+ the coarse pass 0): reads u_0..u_s (and x), writes x, bc (and w_0, phi_c read)
+    double down(int s, bool acc, double N, double Nc, bool st0) const
+    {
+        return R * z * ((s + 2 + (acc ? 1 : 0)) * N + Nc + (st0 ? Nc : 0)) + (st0 ? p * Nc : 0);
+    }
     // interpolation + residual + pass 0: reads xin, ec, b, phi; writes x, r, w_0
     double up(bool xin, double N, double Nc) const { return R * z * ((xin ? N : 0) + Nc + 4 * N) + p * N; }
     double coarse(double n) const { return n * n * z + R * 2 * n * z; }
@@ -355,12 +360,30 @@ Basis<T> closing_basis(const csg_operator *op, int l, Basis<T> B)
     return B;
 }
 
+// Whether the closing pass of level l's last pre-sweep runs fused with the
+// restriction on tiles of level l+1; with st0 also level l+1's pass 0.
+template <typename T, int DIM>
+bool down_tiled(const csg_operator *op, int l)
+{
+    if (DIM != 2 || !op->tiles || !op->down_tiles || op->p.s > 3 || l + 1 >= op->L) return false;
+    const DevLevel &f = op->lev[l], &c = op->lev[l + 1];
+    return down_fits(c.tile) && f.nu[0] <= 2 * c.nu[0] + 1 && f.nu[1] <= 2 * c.nu[1] + 1;
+}
+template <typename T, int DIM>
+bool down_st0(const csg_operator *op, int l)
+{
+    return l + 1 < op->lt && op->p.nu1 > 0 && tiled<T, DIM>(op, l + 1);
+}
+
 // One GMRES(s) sweep on level l: Arnoldi passes on u_0 (= b when x == 0, else
 // the residual in lv.r), then the closing pass: the plain update
 // (x (+)= V y) or, before the restriction, the update plus the Arnoldi residual.
+// `first`: pass 0 already ran (see arnoldi_passes).  Returns the `first` of
+// level l+1's first sweep: its partial count when the closing pass also ran
+// that sweep's pass 0, else 0.
 template <typename T, int DIM>
-void sweep(const csg_operator *op, int l, const Cx<T> *b, Cx<T> *x, bool from_zero, bool restrict_after, int nrhs,
-           hipStream_t st, const int *active)
+int sweep(const csg_operator *op, int l, const Cx<T> *b, Cx<T> *x, bool from_zero, bool restrict_after, int nrhs,
+          hipStream_t st, const int *active, int first = 0)
 {
     const DevLevel &lv = op->lev[l];
     const int s = op->p.s;
@@ -375,11 +398,22 @@ void sweep(const csg_operator *op, int l, const Cx<T> *b, Cx<T> *x, bool from_ze
         launch_resid<T, DIM>(L, x, b, (Cx<T> *)lv.r, lv.ld, g, active);
         B.u[0] = (Cx<T> *)lv.r;
     }
-    const int nclose = arnoldi_passes<T, DIM>(op, l, B, nrhs, st, active);
+    const int nclose = arnoldi_passes<T, DIM>(op, l, B, nrhs, st, active, first);
     B = closing_basis<T>(op, l, B);
     const Bytes by = bytes_of(op, nrhs);
     const int k0 = l == 0 ? 0 : -1;   // instrumented kinds exist for the finest level only
     zc *pclose = close_part<T, DIM>(op, l);
+    if (restrict_after && down_tiled<T, DIM>(op, l)) {
+        // closing update, restriction of the Arnoldi residual and (when level
+        // l+1 sweeps next) its pass 0, per coarse tile
+        const DevLevel &cl = op->lev[l + 1];
+        const bool st0 = down_st0<T, DIM>(op, l);
+        ProfScope ps(op, k0 ? -1 : CSG_PROF_UPD_RESTRICT, st, by.down(s, !from_zero, lv.N, cl.N, st0));
+        launch_down_tile<T>(x, from_zero ? 0 : 1, B, s, L, lvl<T>(op, l + 1), (Cx<T> *)cl.b, (Cx<T> *)cl.w[0],
+                            lv.ld, cl.ld, pclose, nclose, lv.gs, tiny, st0, sizeof(T) == 8 && s == 1, cl.part[0],
+                            cl.tile, nrhs, st, active);
+        return st0 ? (int)(cl.tile.ntx * cl.tile.nty) : 0;
+    }
     if (restrict_after) {
         // closing update writes x and the Arnoldi residual r; full weighting of r
         const DevLevel &cl = op->lev[l + 1];
@@ -393,6 +427,7 @@ void sweep(const csg_operator *op, int l, const Cx<T> *b, Cx<T> *x, bool from_ze
         ProfScope ps(op, k0 ? -1 : CSG_PROF_UPDATE, st, by.upd(s, !from_zero, lv.N));
         launch_upd<T>(x, from_zero ? 0 : 1, B, s, lv.N, lv.ld, pclose, nclose, lv.gs, tiny, g, active);
     }
+    return 0;
 }
 
 // x = V_{nu1,nu2}(0; b) on level l downwards (section 3.1).
@@ -402,6 +437,7 @@ void vcycle_impl(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, h
     const int L = op->L;
     const int lt = op->lt;
     const int nu1 = op->p.nu1, nu2 = op->p.nu2;
+    int first = 0;   // pass 0 of this level's first sweep already ran
     for (int l = 0; l < lt; ++l) {
         const DevLevel &lv = op->lev[l];
         const DevLevel &cl = op->lev[l + 1];
@@ -411,7 +447,10 @@ void vcycle_impl(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, h
             launch_restrict<T, DIM>(lvl<T>(op, l), lvl<T>(op, l + 1), nullptr, b, (Cx<T> *)cl.b, lv.ld, cl.ld,
                                     lch(op, l + 1, nrhs, st), active);
         } else {
-            for (int k = 0; k < nu1; ++k) sweep<T, DIM>(op, l, b, xa, k == 0, k == nu1 - 1, nrhs, st, active);
+            int next = 0;
+            for (int k = 0; k < nu1; ++k)
+                next = sweep<T, DIM>(op, l, b, xa, k == 0, k == nu1 - 1, nrhs, st, active, k == 0 ? first : 0);
+            first = next;
         }
     }
     {
@@ -879,6 +918,8 @@ int csg_operator_create(const csg_params *p, const double *phi_host, void *ws_de
         if (const char *e = getenv("CSG_TILES")) op->tiles = atoi(e) != 0;
         op->up_tiles = true;
         if (const char *e = getenv("CSG_UP_TILES")) op->up_tiles = atoi(e) != 0;
+        op->down_tiles = true;
+        if (const char *e = getenv("CSG_DOWN_TILES")) op->down_tiles = atoi(e) != 0;
         op->lt = op->L - 1;
         for (int l = 0; l < op->L; ++l)
             if ((long)op->lev[l].N <= tail_max) { op->lt = l; break; }

@@ -101,14 +101,36 @@ struct TileGeo {
 };
 constexpr int TILE_MAXE = 10;                 // halo-tile points per thread
 constexpr int TILE_PRE = 2;                   // of them loaded before the pass's reduction
+constexpr int TILE_PB = 4;                    // points per thread whose loads are issued together
 constexpr int TILE_MAXN = TILE_MAXE * BLK;    // halo-tile points per block
-// Whether a tiling exists and its halo tile fits the shared-memory buffer.
-inline bool tile_fits(const TileGeo &t) { return t.ntx > 0 && (t.tx + 2) * (t.ty + 2) <= (unsigned)TILE_MAXN; }
+constexpr int TAB_MAXD = 80;                  // tile columns / rows whose stencil tables are staged
+// Whether a tiling exists, its halo tile fits the shared-memory buffer and
+// the stencil tables of its columns and rows can be staged (one per thread).
+inline bool tile_fits(const TileGeo &t)
+{
+    return t.ntx > 0 && (t.tx + 2) * (t.ty + 2) <= (unsigned)TILE_MAXN && t.tx <= (unsigned)TAB_MAXD &&
+           t.ty <= (unsigned)TAB_MAXD && 3 * (t.tx + t.ty) <= (unsigned)BLK;
+}
 // The up-path tile pass (interpolation, residual and pass 0 of the post-sweep)
 // stages the tile with a two-point halo.
 constexpr int UP_MAXE = 11;                   // two-point-halo tile points per thread
 constexpr int UP_MAXN = UP_MAXE * BLK;
-inline bool up_fits(const TileGeo &t) { return tile_fits(t) && (t.tx + 4) * (t.ty + 4) <= (unsigned)UP_MAXN; }
+inline bool up_fits(const TileGeo &t)
+{
+    return tile_fits(t) && (t.tx + 4) * (t.ty + 4) <= (unsigned)UP_MAXN && t.tx + 2 <= (unsigned)TAB_MAXD &&
+           t.ty + 2 <= (unsigned)TAB_MAXD && 3 * (t.tx + t.ty + 4) <= (unsigned)BLK;
+}
+// The down-path tile pass (closing of the last pre-sweep, restriction and pass
+// 0 of the next level) runs on tiles of the coarse level: it stages the fine
+// points under the tile and its one-point halo, and the coarse tile with halo.
+constexpr int DN_MAXE = 4;                    // coarse halo-tile points per thread
+constexpr int DN_MAXB = DN_MAXE * BLK;
+inline bool down_fits(const TileGeo &tc)
+{
+    return tc.ntx > 0 && (int)(tc.ntx * tc.nty) <= NBMAX && (2 * tc.tx + 5) * (2 * tc.ty + 5) <= (unsigned)UP_MAXN &&
+           (tc.tx + 2) * (tc.ty + 2) <= (unsigned)DN_MAXB && tc.tx <= (unsigned)TAB_MAXD &&
+           tc.ty <= (unsigned)TAB_MAXD && 3 * (tc.tx + tc.ty) <= (unsigned)BLK;
+}
 
 struct DevLevel {
     unsigned nu[3];
@@ -160,6 +182,7 @@ struct csg_operator {
     long fuse_max;                    // levels up to this size use the fused Arnoldi passes
     bool tiles;                       // 2-D levels whose tiles fit use the LDS-staged fused pass
     bool up_tiles;                    // ... and the LDS-staged interpolation + residual + pass 0
+    bool down_tiles;                  // ... and the LDS-staged closing + restriction + next pass 0
     // outer FGMRES storage
     csg::zc *V;                       // (m+1) x max_rhs x ld0
     void *Z;                          // m x max_rhs x ld0, cycle precision

@@ -76,6 +76,20 @@ void launch_up_tile(const LvlK<T> &F, const LvlK<T> &C, const Cx<T> *ec, const C
                     const Cx<T> *b, Cx<T> *r, Cx<T> *w, size_t ldf, size_t ldc, bool wnorm, zc *pout,
                     const TileGeo &tg, int nrhs, hipStream_t st, const int *active);
 
+// Closing pass of the last pre-sweep on a 2-D level, the restriction and
+// (st0) pass 0 of the coarse level's first sweep, on tiles tc of the coarse
+// level: x (+)= sum cx_i u_i, bc = 2^-d P^T r with the Arnoldi residual
+// r = sum cr_i u_i, and with st0 wc = A_c bc with <bc, wc>, ||bc||^2 (and
+// ||wc||^2 when wnorm) per coarse tile into pout.  Same outputs as
+// launch_upd_r, launch_restrict and launch_st0 in turn (r itself is not
+// stored), partials by coarse tile.  Requires F.nx <= 2 C.nx + 1 and
+// F.ny <= 2 C.ny + 1 (every fine point lies under the coarse grid).
+template <typename T>
+void launch_down_tile(Cx<T> *x, int accumulate, const Basis<T> &B, int s, const LvlK<T> &F, const LvlK<T> &C,
+                      Cx<T> *bc, Cx<T> *wc, size_t ldf, size_t ldc, const zc *pin, int nbin, GState *gs,
+                      double tiny, bool st0, bool wnorm, zc *pout, const TileGeo &tc, int nrhs, hipStream_t st,
+                      const int *active);
+
 template <typename T>
 void launch_orthl(const Basis<T> &B, const Cx<T> *win, int j, int s, unsigned N, size_t ld, const zc *pin, int nbin,
                   zc *pout, GState *gs, double tiny, const Launch &g, const int *active);

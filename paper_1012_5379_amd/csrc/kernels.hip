@@ -125,17 +125,29 @@ __device__ __forceinline__ void block_sum(zc (&v)[NV], int nv, zc *sh, zc *res)
     __syncthreads();
 }
 
-// Sum the per-block partials of one RHS (layout [value][NBMAX]).
+// This thread's share of the per-block partials of one RHS (layout
+// [value][NBMAX]): one partial per thread, all NV rows loaded at once (rows >=
+// nv and blocks >= nb are read inside the buffer and dropped), so the
+// reduction waits for memory once.
+template <int NV>
+__device__ __forceinline__ void load_parts(const zc *part, int nb, int nv, zc (&v)[NV])
+{
+    static_assert(NBMAX <= BLK && NV <= NVAL, "partials layout");
+    const int b = min((int)threadIdx.x, NBMAX - 1);
+    const bool ok = (int)threadIdx.x < nb;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = part[q * NBMAX + b];
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+        if (!(ok && q < nv)) v[q] = mkc(0.0, 0.0);
+}
+
+// Sum the per-block partials of one RHS into res[0..nv-1].
 template <int NV>
 __device__ __forceinline__ void reduce_parts(const zc *part, int nb, int nv, zc *sh, zc *res)
 {
     zc v[NV];
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        v[q] = mkc(0.0, 0.0);
-        if (q < nv)
-            for (int b = threadIdx.x; b < nb; b += BLK) v[q] = v[q] + part[q * NBMAX + b];
-    }
+    load_parts<NV>(part, nb, nv, v);
     block_sum<NV>(v, nv, sh, res);
 }
 
@@ -542,6 +554,35 @@ __device__ __forceinline__ Cx<T> prolong_pt(const Cx<T> *__restrict__ ec, unsign
     return acc;
 }
 
+// prolong_pt in 2-D split into its loads and its sum, so that the loads of
+// several points can be issued before any of them is used.
+template <typename T>
+struct PLoads2 {
+    Cx<T> e[4];
+    float w[4];
+};
+template <typename T>
+__device__ __forceinline__ void prolong_load2(const Cx<T> *__restrict__ ec, unsigned i, unsigned j, unsigned ncx,
+                                              unsigned ncy, PLoads2<T> &pl)
+{
+    const PAx ax = paxis(i, ncx), ay = paxis(j, ncy);
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            pl.e[2 * b + a] = ec[ay.idx[b] * ncx + ax.idx[a]];
+            pl.w[2 * b + a] = ax.w[a] * ay.w[b];
+        }
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> prolong_sum2(const PLoads2<T> &pl)
+{
+    Cx<T> acc = mkc<T>(0, 0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc = acc + (T)pl.w[k] * pl.e[k];
+    return acc;
+}
+
 // Fine nodes 2c-1, 2c, 2c+1 of coarse node c = I+1 along one axis, as fine
 // unknown indices 2I, 2I+1, 2I+2 with weights 1/2, 1, 1/2; a node outside the
 // unknown range contributes nothing.  `own` marks the nodes whose x this
@@ -932,22 +973,30 @@ __global__ __launch_bounds__(BLK) void k_os(LvlK<T> L, Basis<T> B, const Cx<T> *
     if (threadIdx.x < nv) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + c] = res[threadIdx.x];
 }
 
-// Fused pass j+1 on one 2-D tile (see launch_os_tile).  Phase 1: every point
-// of the tile and its one-point halo forms u_{j+1} = sj w_j - sum_i cu_i u_i
-// (zero outside the level) into shared memory, the tile's own points also to
-// global memory, keeping their u_i in registers.  Phase 2: the tile's points
-// apply the stencil to the shared copy, write w_{j+1} and sum <u_i, w_{j+1}>
-// (i <= j+1), ||u_{j+1}||^2 and, on the last step, ||w_{j+1}||^2.  A thread
-// owns the same points in both phases.
-template <typename T, int SB>
-__global__ __launch_bounds__(BLK) void k_os_tile(LvlK<T> L, Basis<T> B, const Cx<T> *win, Cx<T> *wout, int j, int s,
+// Fused pass j+1 on one 2-D tile (see launch_os_tile), J = j.  Phase 1: every
+// point of the tile and its one-point halo forms u_{j+1} = sj w_j - sum_i cu_i
+// u_i (zero outside the level) into shared memory, the tile's own points also
+// to global memory, keeping their u_i and phi in registers.  Phase 2: the
+// tile's points apply the stencil to the shared copy, write w_{j+1} and sum
+// <u_i, w_{j+1}> (i <= j+1), ||u_{j+1}||^2 and, on the last step,
+// ||w_{j+1}||^2.  A thread owns the same points in both phases.  The loads of
+// the partials go first, then those of the tile's stencil tables (into shared
+// memory) and of the first TILE_PRE points, all before the partial-sum
+// reduction; phase 1 goes in batches of TILE_PB points per thread whose loads
+// are issued together (the address of an absent point clamped to the tile's
+// corner), so a batch waits for memory once.
+template <typename T, int SB, int J>
+__global__ __launch_bounds__(BLK) void k_os_tile(LvlK<T> L, Basis<T> B, const Cx<T> *win, Cx<T> *wout, int s,
                                                  size_t ld, const zc *__restrict__ pin, int nbin,
                                                  zc *__restrict__ pout, GState *gsb, double tiny, TileGeo tg,
                                                  int ntile, const int *active)
 {
+    static_assert(J + 3 <= SB, "basis and sum slots");
+    constexpr int j = J;
     __shared__ zc sh[(BLK / 64) * (SB + 1)];
     __shared__ zc res[SB + 1];
     __shared__ Cx<T> lu[TILE_MAXN];
+    __shared__ Cx<T> ltab[6 * TAB_MAXD];   // x lower, diag, upper; y lower, diag, upper
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
     GState *gs = gsb + rhs;
@@ -956,95 +1005,123 @@ __global__ __launch_bounds__(BLK) void k_os_tile(LvlK<T> L, Basis<T> B, const Cx
     const unsigned tyi = t / tg.ntx, txi = t - tyi * tg.ntx;
     const int nx = (int)L.nx, ny = (int)L.ny;
     const int x0 = (int)(txi * tg.tx), y0 = (int)(tyi * tg.ty);
-    const int HX = min(x0 + (int)tg.tx, nx) - x0 + 2, HY = min(y0 + (int)tg.ty, ny) - y0 + 2;
+    const int TX = min(x0 + (int)tg.tx, nx) - x0, TY = min(y0 + (int)tg.ty, ny) - y0;
+    const int HX = TX + 2, HY = TY + 2;
     const int HN = HX * HY;
     const size_t off = rhs * ld;
+    const size_t pc = (size_t)y0 * nx + x0;   // a point of the level every clamped address goes to
     const Cx<T> *wi = win + off;
     Cx<T> *un = pick(B, j + 1) + off;
     Cx<T> *wo = wout + off;
-    // the first TILE_PRE halo-tile points of each thread are loaded before the
-    // partial-sum reduction, so their memory latency overlaps it
-    Cx<T> uq[TILE_MAXE][SB - 1], wq[TILE_PRE];
-#pragma unroll
-    for (int it = 0; it < TILE_PRE; ++it) {
-        const int e = threadIdx.x + it * BLK;
+    // stencil tables of the tile's columns x0 .. x0+TX-1 and rows y0 .. y0+TY-1,
+    // one entry per thread, loaded ahead of the partials (so the reduction's
+    // wait covers it) and stored to shared memory after the reduction
+    int tslot = -1;
+    const Cx<T> *tsrc;
+    {
+        const int q = threadIdx.x;
+        const bool xs = q < 3 * TX;
+        const int qq = xs ? q : min(q - 3 * TX, 3 * TY - 1);
+        const int c = qq / 3, a = qq - 3 * c;
+        tsrc = (xs ? L.tab[0] + a * nx + x0 : L.tab[1] + a * ny + y0) + c;
+        if (q < 3 * TX + 3 * TY) tslot = (xs ? a : 3 + a) * TAB_MAXD + c;
+    }
+    // field by field: a whole-struct copy into shared memory later would keep
+    // the value in a per-thread shared-memory slot, written as soon as it lands
+    const T tre = tsrc->re, tim = tsrc->im;
+    zc pv_parts[SB + 1];
+    load_parts<SB + 1>(pin + (size_t)rhs * NVAL * NBMAX, nbin, j + 2, pv_parts);
+    // halo-tile point e: its index in the level (clamped when absent), whether present
+    auto locate = [&](int e, size_t &p) {
         const int ey = e / HX, ex = e - ey * HX;
         const int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
-        if (e < HN && gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-            const size_t p = (size_t)gy * nx + gx;
-            wq[it] = wi[p];
+        const bool ok = e < HN && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        p = ok ? (size_t)gy * nx + gx : pc;
+        return ok;
+    };
+    auto inner = [&](int e) {
+        const int ey = e / HX, ex = e - ey * HX;
+        return e < HN && ex >= 1 && ex <= HX - 2 && ey >= 1 && ey <= HY - 2;
+    };
+    // the first TILE_PRE points of each thread are loaded before the
+    // partial-sum reduction, so their memory latency overlaps it
+    Cx<T> uq[TILE_MAXE][J + 1], wq[TILE_PRE];
+    T phq[TILE_MAXE];
+    size_t pq[TILE_MAXE];
+    bool okq[TILE_MAXE];
 #pragma unroll
-            for (int q = 0; q < SB - 1; ++q)
-                if (q <= j) uq[it][q] = B.u[q][off + p];
-        }
+    for (int it = 0; it < TILE_PRE; ++it) {
+        okq[it] = locate(threadIdx.x + it * BLK, pq[it]);
+        wq[it] = wi[pq[it]];
+#pragma unroll
+        for (int q = 0; q <= J; ++q) uq[it][q] = B.u[q][off + pq[it]];
+        phq[it] = L.phi[pq[it]];
     }
-    reduce_parts<SB + 1>(pin + (size_t)rhs * NVAL * NBMAX, nbin, j + 2, sh, res);
+    block_sum<SB + 1>(pv_parts, j + 2, sh, res);
+    if (tslot >= 0) ltab[tslot] = mkc<T>(tre, tim);
     Cx<T> cu[SB];
     const double sjd = coef_step<T, SB>(res, j, s, tiny, pv, gs, blockIdx.x == 0 && threadIdx.x == 0, cu);
     const T sj = (T)sjd;
 #pragma unroll
-    for (int it = 0; it < TILE_MAXE; ++it) {
-        const int e = threadIdx.x + it * BLK;
-        if (e >= HN) break;
-        const int ey = e / HX, ex = e - ey * HX;
-        const int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
-        Cx<T> v = mkc<T>(0, 0);
-        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-            const size_t p = (size_t)gy * nx + gx;
+    for (int b0 = 0; b0 < TILE_MAXE; b0 += TILE_PB) {
+        if (b0 * BLK >= HN) break;   // the same for every thread of the block
+        Cx<T> wv[TILE_PB];
+#pragma unroll
+        for (int i = 0; i < TILE_PB; ++i) {
+            const int it = b0 + i;
+            if (it >= TILE_MAXE) break;
             if (it < TILE_PRE) {
-                v = sj * wq[it < TILE_PRE ? it : 0];
+                wv[i] = wq[it < TILE_PRE ? it : 0];
             } else {
-                v = sj * wi[p];
+                okq[it] = locate(threadIdx.x + it * BLK, pq[it]);
+                wv[i] = wi[pq[it]];
 #pragma unroll
-                for (int q = 0; q < SB - 1; ++q)
-                    if (q <= j) uq[it][q] = B.u[q][off + p];
+                for (int q = 0; q <= J; ++q) uq[it][q] = B.u[q][off + pq[it]];
+                phq[it] = L.phi[pq[it]];
             }
-#pragma unroll
-            for (int q = 0; q < SB - 1; ++q)
-                if (q <= j) v = v - cu[q] * uq[it][q];
-            if (ex >= 1 && ex <= HX - 2 && ey >= 1 && ey <= HY - 2) un[p] = v;
         }
-        lu[e] = v;
+#pragma unroll
+        for (int i = 0; i < TILE_PB; ++i) {
+            const int it = b0 + i;
+            if (it >= TILE_MAXE) break;
+            const int e = threadIdx.x + it * BLK;
+            Cx<T> v = sj * wv[i];
+#pragma unroll
+            for (int q = 0; q <= J; ++q) v = v - cu[q] * uq[it][q];
+            if (!okq[it]) v = mkc<T>(0, 0);
+            if (okq[it] && inner(e)) un[pq[it]] = v;
+            if (e < HN) lu[e] = v;
+        }
     }
     __syncthreads();
     zc acc[SB + 1];
 #pragma unroll
     for (int q = 0; q <= SB; ++q) acc[q] = mkc(0.0, 0.0);
-    const bool wn = norm_from_sums<T>() && j + 2 == s;
-    const Cx<T> *tx = L.tab[0], *ty = L.tab[1];
+    const bool wlast = norm_from_sums<T>() && j + 2 == s;   // last step of the sweep
 #pragma unroll
     for (int it = 0; it < TILE_MAXE; ++it) {
         const int e = threadIdx.x + it * BLK;
-        if (e >= HN) break;
+        if (it * BLK >= HN) break;   // the same for every thread of the block
+        if (!inner(e)) continue;
         const int ey = e / HX, ex = e - ey * HX;
-        if (ex < 1 || ex > HX - 2 || ey < 1 || ey > HY - 2) continue;
-        const int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
-        const size_t p = (size_t)gy * nx + gx;
+        const int c = ex - 1, r = ey - 1;
         const Cx<T> uc = lu[e];
-        Cx<T> d = tx[nx + gx] + ty[ny + gy];
-        d.re -= L.phi[p];
+        Cx<T> d = ltab[1 * TAB_MAXD + c] + ltab[4 * TAB_MAXD + r];
+        d.re -= phq[it];
         Cx<T> a = d * uc;
-        a = cfma(tx[gx], lu[e - 1], a);
-        a = cfma(tx[2 * nx + gx], lu[e + 1], a);
-        a = cfma(ty[gy], lu[e - HX], a);
-        a = cfma(ty[2 * ny + gy], lu[e + HX], a);
-        wo[p] = a;
+        a = cfma(ltab[0 * TAB_MAXD + c], lu[e - 1], a);
+        a = cfma(ltab[2 * TAB_MAXD + c], lu[e + 1], a);
+        a = cfma(ltab[3 * TAB_MAXD + r], lu[e - HX], a);
+        a = cfma(ltab[5 * TAB_MAXD + r], lu[e + HX], a);
+        wo[pq[it]] = a;
         const zc wd = cvt<double>(a), ud = cvt<double>(uc);
 #pragma unroll
-        for (int q = 0; q < SB - 1; ++q)
-            if (q <= j) acc[q] = cjfma(cvt<double>(uq[it][q]), wd, acc[q]);
-#pragma unroll
-        for (int q = 1; q < SB; ++q) {
-            if (q == j + 1) acc[q] = cjfma(ud, wd, acc[q]);
-            if (q == j + 2) acc[q].re += cabs2(ud);
-        }
-        if (wn) {
-#pragma unroll
-            for (int q = 3; q <= SB; ++q)
-                if (q == j + 3) acc[q].re += cabs2(wd);
-        }
+        for (int q = 0; q <= J; ++q) acc[q] = cjfma(cvt<double>(uq[it][q]), wd, acc[q]);
+        acc[j + 1] = cjfma(ud, wd, acc[j + 1]);
+        acc[j + 2].re += cabs2(ud);
+        if (wlast) acc[j + 3].re += cabs2(wd);
     }
-    const int nv = j + 3 + (wn ? 1 : 0);
+    const int nv = j + 3 + (wlast ? 1 : 0);
     block_sum<SB + 1>(acc, nv, sh, res);
     if (threadIdx.x < nv) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + t] = res[threadIdx.x];
 }
@@ -1055,7 +1132,11 @@ __global__ __launch_bounds__(BLK) void k_os_tile(LvlK<T> L, Basis<T> B, const Cx
 // one-point halo, held in registers (the tile's points also to r), then moved
 // into the shared buffer once every thread is done reading x.  Phase 3: w_0 =
 // A r on the tile with <r, w_0>, ||r||^2 and (NA = 3) ||w_0||^2.  A thread owns
-// the same points in phases 2 and 3.
+// the same points in phases 2 and 3 (phi loaded once).  The stencil tables of
+// the tile's columns and rows are staged in shared memory, and b and phi of
+// the first TILE_PB points of phase 2 are loaded with phase 1's first batch;
+// every phase goes in batches of TILE_PB points per thread whose loads are
+// issued together (absent points clamped to the tile's corner).
 template <typename T, int NA>
 __global__ __launch_bounds__(BLK) void k_up_tile(LvlK<T> F, LvlK<T> C, const Cx<T> *__restrict__ ec,
                                                  const Cx<T> *__restrict__ xin, Cx<T> *__restrict__ xout,
@@ -1066,6 +1147,7 @@ __global__ __launch_bounds__(BLK) void k_up_tile(LvlK<T> F, LvlK<T> C, const Cx<
     __shared__ zc sh[(BLK / 64) * NA];
     __shared__ zc res[NA];
     __shared__ Cx<T> lx[UP_MAXN];
+    __shared__ Cx<T> ltab[6 * TAB_MAXD];   // x lower, diag, upper; y lower, diag, upper
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
     const unsigned t = chunk_id(ntile);
@@ -1076,46 +1158,116 @@ __global__ __launch_bounds__(BLK) void k_up_tile(LvlK<T> F, LvlK<T> C, const Cx<
     const int AX = TX + 4, AN = AX * (TY + 4);   // x: tile and two-point halo
     const int RX = TX + 2, RN = RX * (TY + 2);   // r: tile and one-point halo
     const size_t off = rhs * ldf;
+    const size_t pc = (size_t)y0 * nx + x0;      // a point of the level every clamped address goes to
     const Cx<T> *e = ec + rhs * ldc;
-#pragma unroll
-    for (int it = 0; it < UP_MAXE; ++it) {
-        const int q = threadIdx.x + it * BLK;
-        if (q >= AN) break;
-        const int qy = q / AX, qx = q - qy * AX;
-        const int gx = x0 - 2 + qx, gy = y0 - 2 + qy;
-        Cx<T> v = mkc<T>(0, 0);
-        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-            const size_t p = (size_t)gy * nx + gx;
-            v = prolong_pt<T, 2>(e, gx, gy, 0, C.nx, C.ny, 1);
-            if (xin) v = v + xin[off + p];
-            if (qx >= 2 && qx < TX + 2 && qy >= 2 && qy < TY + 2) xout[off + p] = v;
-        }
-        lx[q] = v;
+    const Cx<T> *xi = xin ? xin + off : nullptr;
+    // stencil tables of the columns x0-1 .. x0+TX and rows y0-1 .. y0+TY (zero
+    // outside the level), one entry per thread, stored before phase 1's barrier
+    T tre, tim;
+    bool tzero;
+    int tslot = -1;
+    {
+        const int q = threadIdx.x;
+        const bool xs = q < 3 * RX;
+        const int qq = xs ? q : min(q - 3 * RX, 3 * (TY + 2) - 1);
+        const int c = qq / 3, a = qq - 3 * c;
+        const int g = (xs ? x0 : y0) - 1 + c, n = xs ? nx : ny;
+        const Cx<T> *tab = xs ? F.tab[0] : F.tab[1];
+        const Cx<T> *tp = tab + a * n + min(max(g, 0), n - 1);
+        tre = tp->re;
+        tim = tp->im;
+        tzero = g < 0 || g >= n;
+        if (q < 3 * RX + 3 * (TY + 2)) tslot = (xs ? a : 3 + a) * TAB_MAXD + c;
     }
-    __syncthreads();
-    const Cx<T> *tx = F.tab[0], *ty = F.tab[1];
-    Cx<T> rq[TILE_MAXE];
-#pragma unroll
-    for (int it = 0; it < TILE_MAXE; ++it) {
-        const int q = threadIdx.x + it * BLK;
-        if (q >= RN) break;
+    // phase-2 point q (tile and one-point halo): its index (clamped when absent), whether present
+    auto locate2 = [&](int q, size_t &p) {
         const int qy = q / RX, qx = q - qy * RX;
         const int gx = x0 - 1 + qx, gy = y0 - 1 + qy;
-        Cx<T> v = mkc<T>(0, 0);
-        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-            const size_t p = (size_t)gy * nx + gx;
-            const int a = (qy + 1) * AX + qx + 1;
-            Cx<T> d = tx[nx + gx] + ty[ny + gy];
-            d.re -= F.phi[p];
-            Cx<T> ax = d * lx[a];
-            ax = cfma(tx[gx], lx[a - 1], ax);
-            ax = cfma(tx[2 * nx + gx], lx[a + 1], ax);
-            ax = cfma(ty[gy], lx[a - AX], ax);
-            ax = cfma(ty[2 * ny + gy], lx[a + AX], ax);
-            v = b[off + p] - ax;
-            if (qx >= 1 && qx <= TX && qy >= 1 && qy <= TY) r[off + p] = v;
+        const bool ok = q < RN && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        p = ok ? (size_t)gy * nx + gx : pc;
+        return ok;
+    };
+    Cx<T> bq[TILE_MAXE];
+    T phq[TILE_MAXE];
+    size_t pq[TILE_MAXE];
+    bool okq[TILE_MAXE];
+#pragma unroll
+    for (int it = 0; it < TILE_PB; ++it) {
+        okq[it] = locate2(threadIdx.x + it * BLK, pq[it]);
+        bq[it] = b[off + pq[it]];
+        phq[it] = F.phi[pq[it]];
+    }
+#pragma unroll
+    for (int b0 = 0; b0 < UP_MAXE; b0 += TILE_PB) {
+        if (b0 * BLK >= AN) break;   // the same for every thread of the block
+        PLoads2<T> pl[TILE_PB];
+        Cx<T> xl[TILE_PB];
+        size_t pp[TILE_PB];
+        bool ok[TILE_PB], own[TILE_PB];
+#pragma unroll
+        for (int i = 0; i < TILE_PB; ++i) {
+            if (b0 + i >= UP_MAXE) break;
+            const int q = threadIdx.x + (b0 + i) * BLK;
+            const int qy = q / AX, qx = q - qy * AX;
+            int gx = x0 - 2 + qx, gy = y0 - 2 + qy;
+            ok[i] = q < AN && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+            own[i] = ok[i] && qx >= 2 && qx < TX + 2 && qy >= 2 && qy < TY + 2;
+            if (!ok[i]) gx = x0, gy = y0;
+            pp[i] = (size_t)gy * nx + gx;
+            prolong_load2<T>(e, gx, gy, C.nx, C.ny, pl[i]);
         }
-        rq[it] = v;
+        if (xi) {
+#pragma unroll
+            for (int i = 0; i < TILE_PB; ++i)
+                if (b0 + i < UP_MAXE) xl[i] = xi[pp[i]];
+        }
+#pragma unroll
+        for (int i = 0; i < TILE_PB; ++i) {
+            if (b0 + i >= UP_MAXE) break;
+            const int q = threadIdx.x + (b0 + i) * BLK;
+            Cx<T> v = prolong_sum2<T>(pl[i]);
+            if (xi) v = v + xl[i];
+            if (own[i]) xout[off + pp[i]] = v;
+            if (q < AN) lx[q] = ok[i] ? v : mkc<T>(0, 0);
+        }
+    }
+    asm volatile("" ::: "memory");   // the table store stays after phase 1's loads
+    if (tslot >= 0) ltab[tslot] = tzero ? mkc<T>(0, 0) : mkc<T>(tre, tim);
+    __syncthreads();
+    Cx<T> rq[TILE_MAXE];
+#pragma unroll
+    for (int b0 = 0; b0 < TILE_MAXE; b0 += TILE_PB) {
+        if (b0 * BLK >= RN) break;
+        if (b0 > 0) {
+#pragma unroll
+            for (int i = 0; i < TILE_PB; ++i) {
+                const int it = b0 + i;
+                if (it >= TILE_MAXE) break;
+                okq[it] = locate2(threadIdx.x + it * BLK, pq[it]);
+                bq[it] = b[off + pq[it]];
+                phq[it] = F.phi[pq[it]];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < TILE_PB; ++i) {
+            const int it = b0 + i;
+            if (it >= TILE_MAXE) break;
+            const int q = threadIdx.x + it * BLK;
+            const int qy = q / RX, qx = q - qy * RX;
+            const bool ok = okq[it];
+            const int a = ok ? (qy + 1) * AX + qx + 1 : 2 * AX + 2;
+            const int c = ok ? qx : 1, rr = ok ? qy : 1;
+            Cx<T> d = ltab[1 * TAB_MAXD + c] + ltab[4 * TAB_MAXD + rr];
+            d.re -= phq[it];
+            Cx<T> ax = d * lx[a];
+            ax = cfma(ltab[0 * TAB_MAXD + c], lx[a - 1], ax);
+            ax = cfma(ltab[2 * TAB_MAXD + c], lx[a + 1], ax);
+            ax = cfma(ltab[3 * TAB_MAXD + rr], lx[a - AX], ax);
+            ax = cfma(ltab[5 * TAB_MAXD + rr], lx[a + AX], ax);
+            const Cx<T> v = bq[it] - ax;
+            if (ok && qx >= 1 && qx <= TX && qy >= 1 && qy <= TY) r[off + pq[it]] = v;
+            rq[it] = ok ? v : mkc<T>(0, 0);
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -1130,21 +1282,19 @@ __global__ __launch_bounds__(BLK) void k_up_tile(LvlK<T> F, LvlK<T> C, const Cx<
     for (int q = 0; q < NA; ++q) acc[q] = mkc(0.0, 0.0);
 #pragma unroll
     for (int it = 0; it < TILE_MAXE; ++it) {
+        if (it * BLK >= RN) break;   // the same for every thread of the block
         const int q = threadIdx.x + it * BLK;
-        if (q >= RN) break;
         const int qy = q / RX, qx = q - qy * RX;
-        if (qx < 1 || qx > TX || qy < 1 || qy > TY) continue;
-        const int gx = x0 - 1 + qx, gy = y0 - 1 + qy;
-        const size_t p = (size_t)gy * nx + gx;
+        if (q >= RN || qx < 1 || qx > TX || qy < 1 || qy > TY) continue;
         const Cx<T> uc = rq[it];
-        Cx<T> d = tx[nx + gx] + ty[ny + gy];
-        d.re -= F.phi[p];
+        Cx<T> d = ltab[1 * TAB_MAXD + qx] + ltab[4 * TAB_MAXD + qy];
+        d.re -= phq[it];
         Cx<T> a = d * uc;
-        a = cfma(tx[gx], lx[q - 1], a);
-        a = cfma(tx[2 * nx + gx], lx[q + 1], a);
-        a = cfma(ty[gy], lx[q - RX], a);
-        a = cfma(ty[2 * ny + gy], lx[q + RX], a);
-        w[off + p] = a;
+        a = cfma(ltab[0 * TAB_MAXD + qx], lx[q - 1], a);
+        a = cfma(ltab[2 * TAB_MAXD + qx], lx[q + 1], a);
+        a = cfma(ltab[3 * TAB_MAXD + qy], lx[q - RX], a);
+        a = cfma(ltab[5 * TAB_MAXD + qy], lx[q + RX], a);
+        w[off + pq[it]] = a;
         const zc wd = cvt<double>(a), ud = cvt<double>(uc);
         acc[0] = cjfma(ud, wd, acc[0]);
         acc[1].re += cabs2(ud);
@@ -1274,7 +1424,7 @@ __device__ __forceinline__ void ls_regs(const zc (&H)[SB][SB - 1], double beta0,
 }
 
 template <typename T, int SB>
-__device__ void close_regs(const CloseIn<SB> &in, GState *gs, const zc *res, int s, double tiny, bool publish, zc *ax,
+__device__ __forceinline__ void close_regs(const CloseIn<SB> &in, GState *gs, const zc *res, int s, double tiny, bool publish, zc *ax,
                            zc *ar, int *ks)
 {
     constexpr int K = SB - 1;
@@ -1419,8 +1569,37 @@ __device__ void close_regs(const CloseIn<SB> &in, GState *gs, const zc *res, int
     }
 }
 
+// The closing prologue (s <= 3) in two halves, so that a pass can issue its
+// own loads in between: close_begin issues the loads of the sweep state
+// (thread 0) and of this thread's partials; close_end sums the partials and
+// solves the least squares (ax, ar and the returned k as close_sweep).
+template <int SB>
+struct CloseLoads {
+    CloseIn<SB> in;
+    zc v[SB + 1];
+};
 template <typename T, int SB>
-__device__ int close_sweep(const zc *pin, int nbin, GState *gs, int s, double tiny, zc *sh, zc *res, zc *ax, zc *ar)
+__device__ __forceinline__ void close_begin(const zc *pin, int nbin, const GState *gs, int s, CloseLoads<SB> &cl)
+{
+    static_assert(SB <= 4, "register form");
+    constexpr bool sums = norm_from_sums<T>();
+    if (threadIdx.x == 0) close_gather<SB>(gs, s, sums, cl.in);
+    load_parts<SB + 1>(pin, nbin, sums ? s + 2 : 1, cl.v);
+}
+template <typename T, int SB>
+__device__ __forceinline__ int close_end(CloseLoads<SB> &cl, GState *gs, int s, double tiny, zc *sh, zc *res,
+                                         zc *ax, zc *ar)
+{
+    __shared__ int ks;
+    constexpr bool sums = norm_from_sums<T>();
+    block_sum<SB + 1>(cl.v, sums ? s + 2 : 1, sh, res);
+    if (threadIdx.x == 0) close_regs<T, SB>(cl.in, gs, res, s, tiny, blockIdx.x == 0, ax, ar, &ks);
+    __syncthreads();
+    return ks;
+}
+
+template <typename T, int SB>
+__device__ __forceinline__ int close_sweep(const zc *pin, int nbin, GState *gs, int s, double tiny, zc *sh, zc *res, zc *ax, zc *ar)
 {
     __shared__ int ks;
     constexpr bool sums = norm_from_sums<T>();
@@ -1536,6 +1715,177 @@ __global__ __launch_bounds__(BLK) void k_upd_res(Cx<T> *x, int accumulate, Basis
     const unsigned p0 = c * chunk, p1 = min(C.N, p0 + chunk);
     body_upd_res<T, DIM, SB>(x + rhs * ldf, accumulate, B, k, cx, cr, F, C, bc + rhs * ldc, rhs * ldf, p0 + threadIdx.x,
                          p1, BLK);
+}
+
+// Down-path pass on one 2-D tile of the coarse level (see launch_down_tile).
+// Prologue: the sweep's closing coefficients (as k_upd_r), with the loads of
+// the first batch of phase 1, the coarse stencil tables of the tile (into
+// shared memory) and phi of phase 3 already issued.  Phase 1: per fine point
+// under the coarse tile and its one-point halo (fine nodes 2I .. 2I+2 of
+// coarse unknown I), the Arnoldi residual r = sum cr_i u_i into shared memory
+// (zero outside the fine level), and x (+)= sum cx_i u_i on the fine points the
+// tile owns: 2X0 .. 2(X0+TX)-1 per axis, up to the last fine point for the
+// tile at the far end.  Phase 1 goes in batches of TILE_PB points per thread
+// whose loads are issued together (absent points clamped to the tile's first
+// fine point).  Phase 2: bc = 2^-2 P^T r on the coarse tile and its halo into
+// shared memory (zero outside the coarse level), the tile's points also to bc.
+// Phase 3 (NA > 0): w_0 = A_c bc on the tile with <bc, w_0>, ||bc||^2 and
+// (NA = 3) ||w_0||^2.
+template <typename T, int SB, int NA>
+__global__ __launch_bounds__(BLK) void k_down_tile(Cx<T> *__restrict__ x, int accumulate, Basis<T> B, int s,
+                                                   LvlK<T> F, LvlK<T> C, Cx<T> *__restrict__ bc,
+                                                   Cx<T> *__restrict__ wc, size_t ldf, size_t ldc,
+                                                   const zc *__restrict__ pin, int nbin, GState *gsb, double tiny,
+                                                   zc *__restrict__ pout, TileGeo tg, int ntile, const int *active)
+{
+    __shared__ zc sh[(BLK / 64) * (SB + 1)];
+    __shared__ zc res[SB + 1];
+    __shared__ zc ax[CSG_MAX_S], ar[CSG_MAX_S + 1];
+    __shared__ Cx<T> lr[UP_MAXN];
+    __shared__ Cx<T> lb[DN_MAXB];
+    __shared__ Cx<T> ltab[6 * TAB_MAXD];   // coarse tables: x lower, diag, upper; y lower, diag, upper
+    const int rhs = blockIdx.y;
+    if (!active[rhs]) return;
+    const unsigned t = chunk_id(ntile);
+    const unsigned tyi = t / tg.ntx, txi = t - tyi * tg.ntx;
+    const int fnx = (int)F.nx, fny = (int)F.ny, cnx = (int)C.nx, cny = (int)C.ny;
+    const int X0 = (int)(txi * tg.tx), Y0 = (int)(tyi * tg.ty);
+    const int TX = min(X0 + (int)tg.tx, cnx) - X0, TY = min(Y0 + (int)tg.ty, cny) - Y0;
+    const int FX = 2 * TX + 5, FN = FX * (2 * TY + 5);
+    const int fx0 = 2 * X0 - 2, fy0 = 2 * Y0 - 2;
+    const int ox1 = (X0 + TX == cnx) ? fnx : 2 * (X0 + TX), oy1 = (Y0 + TY == cny) ? fny : 2 * (Y0 + TY);
+    const size_t offf = rhs * ldf, offc = rhs * ldc;
+    const int BX = TX + 2, BN = BX * (TY + 2);
+    CloseLoads<SB> cls;
+    close_begin<T, SB>(pin + (size_t)rhs * NVAL * NBMAX, nbin, gsb + rhs, s, cls);
+    // coarse tables of the tile's columns X0 .. X0+TX-1 and rows Y0 .. Y0+TY-1,
+    // one entry per thread (stored to shared memory after the prologue)
+    T tre = 0, tim = 0;
+    int tslot = -1;
+    if (NA > 0) {
+        const int q = threadIdx.x;
+        const bool xs = q < 3 * TX;
+        const int qq = xs ? q : min(q - 3 * TX, 3 * TY - 1);
+        const int c = qq / 3, a = qq - 3 * c;
+        const Cx<T> *tab = xs ? C.tab[0] + a * cnx + X0 : C.tab[1] + a * cny + Y0;
+        tre = tab[c].re;
+        tim = tab[c].im;
+        if (q < 3 * TX + 3 * TY) tslot = (xs ? a : 3 + a) * TAB_MAXD + c;
+    }
+    // phi of the coarse tile points of phase 3
+    T phq[DN_MAXE];
+    if (NA > 0) {
+#pragma unroll
+        for (int it = 0; it < DN_MAXE; ++it) {
+            const int q = threadIdx.x + it * BLK;
+            const int qy = q / BX, qx = q - qy * BX;
+            const bool in = q < BN && qx >= 1 && qx <= TX && qy >= 1 && qy <= TY;
+            phq[it] = C.phi[in ? (size_t)(Y0 - 1 + qy) * cnx + X0 - 1 + qx : (size_t)Y0 * cnx + X0];
+        }
+    }
+    Cx<T> u[TILE_PB][SB], xv[TILE_PB];
+    size_t pp[TILE_PB];
+    bool ok[TILE_PB], own[TILE_PB];
+    // loads of the batch of phase 1 starting at b0 (basis slots 0..s, all valid)
+    auto load_batch = [&](int b0) {
+#pragma unroll
+        for (int i = 0; i < TILE_PB; ++i) {
+            if (b0 + i >= UP_MAXE) break;
+            const int q = threadIdx.x + (b0 + i) * BLK;
+            const int qy = q / FX, qx = q - qy * FX;
+            int gx = fx0 + qx, gy = fy0 + qy;
+            ok[i] = q < FN && gx >= 0 && gx < fnx && gy >= 0 && gy < fny;
+            own[i] = ok[i] && gx >= 2 * X0 && gx < ox1 && gy >= 2 * Y0 && gy < oy1;
+            if (!ok[i]) gx = 2 * X0, gy = 2 * Y0;
+            pp[i] = offf + (size_t)gy * fnx + gx;
+#pragma unroll
+            for (int q2 = 0; q2 < SB; ++q2)
+                if (q2 <= s) u[i][q2] = B.u[q2][pp[i]];
+            xv[i] = mkc<T>(0, 0);
+        }
+        if (accumulate) {
+#pragma unroll
+            for (int i = 0; i < TILE_PB; ++i)
+                if (b0 + i < UP_MAXE) xv[i] = x[pp[i]];
+        }
+    };
+    load_batch(0);
+    const int k = close_end<T, SB>(cls, gsb + rhs, s, tiny, sh, res, ax, ar);
+    Cx<T> cx[SB], cr[SB];
+    coefs_to_T<T, SB>(k, ax, ar, cx, cr);
+    if (tslot >= 0) ltab[tslot] = mkc<T>(tre, tim);
+#pragma unroll
+    for (int b0 = 0; b0 < UP_MAXE; b0 += TILE_PB) {
+        if (b0 * BLK >= FN) break;   // the same for every thread of the block
+        if (b0 > 0) load_batch(b0);
+#pragma unroll
+        for (int i = 0; i < TILE_PB; ++i) {
+            if (b0 + i >= UP_MAXE) break;
+            const int q = threadIdx.x + (b0 + i) * BLK;
+            Cx<T> rr = mkc<T>(0, 0);
+#pragma unroll
+            for (int q2 = 0; q2 < SB; ++q2)
+                if (q2 <= k) {
+                    rr = cfma(cr[q2], u[i][q2], rr);
+                    if (q2 < k) xv[i] = cfma(cx[q2], u[i][q2], xv[i]);
+                }
+            if (own[i]) x[pp[i]] = xv[i];
+            if (q < FN) lr[q] = ok[i] ? rr : mkc<T>(0, 0);
+        }
+    }
+    __syncthreads();
+    Cx<T> bq[DN_MAXE];
+#pragma unroll
+    for (int it = 0; it < DN_MAXE; ++it) {
+        const int q = threadIdx.x + it * BLK;
+        if (q >= BN) break;
+        const int qy = q / BX, qx = q - qy * BX;
+        const int I = X0 - 1 + qx, J = Y0 - 1 + qy;
+        Cx<T> v = mkc<T>(0, 0);
+        if (I >= 0 && I < cnx && J >= 0 && J < cny) {
+            // fine nodes 2I + a, 2J + b sit at footprint offsets 2qx + a, 2qy + b
+            const int f0 = 2 * qy * FX + 2 * qx;
+            const int na = 2 * I + 2 < fnx ? 3 : (2 * I + 1 < fnx ? 2 : 1);
+            const int nbb = 2 * J + 2 < fny ? 3 : (2 * J + 1 < fny ? 2 : 1);
+            Cx<T> acc = mkc<T>(0, 0);
+            for (int b2 = 0; b2 < nbb; ++b2)
+                for (int a2 = 0; a2 < na; ++a2) acc = acc + (T)(rw(a2) * rw(b2)) * lr[f0 + b2 * FX + a2];
+            v = (T)0.25 * acc;
+            if (qx >= 1 && qx <= TX && qy >= 1 && qy <= TY) bc[offc + (size_t)J * cnx + I] = v;
+        }
+        bq[it] = v;
+        lb[q] = v;
+    }
+    if constexpr (NA > 0) {
+        __syncthreads();
+        zc acc[NA];
+#pragma unroll
+        for (int q = 0; q < NA; ++q) acc[q] = mkc(0.0, 0.0);
+#pragma unroll
+        for (int it = 0; it < DN_MAXE; ++it) {
+            const int q = threadIdx.x + it * BLK;
+            if (q >= BN) break;
+            const int qy = q / BX, qx = q - qy * BX;
+            if (qx < 1 || qx > TX || qy < 1 || qy > TY) continue;
+            const int c = qx - 1, r = qy - 1;
+            const size_t p = (size_t)(Y0 + r) * cnx + X0 + c;
+            const Cx<T> uc = bq[it];
+            Cx<T> d = ltab[1 * TAB_MAXD + c] + ltab[4 * TAB_MAXD + r];
+            d.re -= phq[it];
+            Cx<T> a = d * uc;
+            a = cfma(ltab[0 * TAB_MAXD + c], lb[q - 1], a);
+            a = cfma(ltab[2 * TAB_MAXD + c], lb[q + 1], a);
+            a = cfma(ltab[3 * TAB_MAXD + r], lb[q - BX], a);
+            a = cfma(ltab[5 * TAB_MAXD + r], lb[q + BX], a);
+            wc[offc + p] = a;
+            const zc wd = cvt<double>(a), ud = cvt<double>(uc);
+            acc[0] = cjfma(ud, wd, acc[0]);
+            acc[1].re += cabs2(ud);
+            if (NA > 2) acc[NA - 1].re += cabs2(wd);
+        }
+        block_sum<NA>(acc, NA, sh, res);
+        if (threadIdx.x < NA) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + t] = res[threadIdx.x];
+    }
 }
 
 template <typename T, int SB>
@@ -2559,8 +2909,31 @@ void launch_os_tile(const LvlK<T> &L, const Basis<T> &B, const Cx<T> *win, Cx<T>
                     hipStream_t st, const int *active)
 {
     const int ntile = (int)(tg.ntx * tg.nty);
-    hipLaunchKernelGGL((k_os_tile<T, 4>), dim3(ntile, nrhs), dim3(BLK), 0, st, L, B, win, wout, j, s, ld, pin, nbin,
-                       pout, gs, tiny, tg, ntile, active);
+    if (j == 0)
+        hipLaunchKernelGGL((k_os_tile<T, 4, 0>), dim3(ntile, nrhs), dim3(BLK), 0, st, L, B, win, wout, s, ld, pin,
+                           nbin, pout, gs, tiny, tg, ntile, active);
+    else
+        hipLaunchKernelGGL((k_os_tile<T, 4, 1>), dim3(ntile, nrhs), dim3(BLK), 0, st, L, B, win, wout, s, ld, pin,
+                           nbin, pout, gs, tiny, tg, ntile, active);
+}
+
+template <typename T>
+void launch_down_tile(Cx<T> *x, int accumulate, const Basis<T> &B, int s, const LvlK<T> &F, const LvlK<T> &C,
+                      Cx<T> *bc, Cx<T> *wc, size_t ldf, size_t ldc, const zc *pin, int nbin, GState *gs,
+                      double tiny, bool st0, bool wnorm, zc *pout, const TileGeo &tc, int nrhs, hipStream_t st,
+                      const int *active)
+{
+    const int ntile = (int)(tc.ntx * tc.nty);
+    const dim3 grd(ntile, nrhs);
+    if (!st0)
+        hipLaunchKernelGGL((k_down_tile<T, 4, 0>), grd, dim3(BLK), 0, st, x, accumulate, B, s, F, C, bc, wc, ldf, ldc,
+                           pin, nbin, gs, tiny, pout, tc, ntile, active);
+    else if (wnorm)
+        hipLaunchKernelGGL((k_down_tile<T, 4, 3>), grd, dim3(BLK), 0, st, x, accumulate, B, s, F, C, bc, wc, ldf, ldc,
+                           pin, nbin, gs, tiny, pout, tc, ntile, active);
+    else
+        hipLaunchKernelGGL((k_down_tile<T, 4, 2>), grd, dim3(BLK), 0, st, x, accumulate, B, s, F, C, bc, wc, ldf, ldc,
+                           pin, nbin, gs, tiny, pout, tc, ntile, active);
 }
 
 template <typename T>
@@ -2801,6 +3174,9 @@ INST_TD(float, 2)
 INST_TD(float, 3)
 
 #define INST_T(T)                                                                                                  \
+    template void launch_down_tile<T>(Cx<T> *, int, const Basis<T> &, int, const LvlK<T> &, const LvlK<T> &,       \
+                                      Cx<T> *, Cx<T> *, size_t, size_t, const zc *, int, GState *, double, bool,   \
+                                      bool, zc *, const TileGeo &, int, hipStream_t, const int *);                 \
     template void launch_up_tile<T>(const LvlK<T> &, const LvlK<T> &, const Cx<T> *, const Cx<T> *, Cx<T> *,      \
                                     const Cx<T> *, Cx<T> *, Cx<T> *, size_t, size_t, bool, zc *, const TileGeo &,  \
                                     int, hipStream_t, const int *);                                                \
