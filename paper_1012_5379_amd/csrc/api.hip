@@ -79,6 +79,22 @@ TileGeo tiling(unsigned nx, unsigned ny, int nb)
     return t;
 }
 
+// Tiling of the down-path pass onto a coarse level: small tiles whose fine
+// footprint each thread covers with one batch of loads, when they number at
+// most NBMAX; else the level's own tiling.
+TileGeo down_tiling(unsigned nx, unsigned ny, const TileGeo &dflt)
+{
+    constexpr unsigned D = 20;   // (2 D + 5)^2 <= TILE_PB * BLK
+    static_assert((2 * D + 5) * (2 * D + 5) <= (unsigned)(TILE_PB * BLK), "one batch per thread");
+    TileGeo t;
+    t.tx = std::min(D, nx);
+    t.ty = std::min(D, ny);
+    t.ntx = (nx + t.tx - 1) / t.tx;
+    t.nty = (ny + t.ty - 1) / t.ty;
+    if (down_fits(t)) return t;
+    return dflt;
+}
+
 // The layout of every buffer in the workspace; `op` may be a dry-run object.
 void carve(csg_operator &op, const int nint[CSG_MAX_LEVELS][3], Carver &cv)
 {
@@ -95,6 +111,7 @@ void carve(csg_operator &op, const int nint[CSG_MAX_LEVELS][3], Carver &cv)
         lv.ld = lv.N;
         geometry(lv.N, lv.nb, lv.chunk);
         lv.tile = p.dim == 2 ? tiling(lv.nu[0], lv.nu[1], lv.nb) : TileGeo{0, 0, 0, 0};
+        lv.dtile = p.dim == 2 ? down_tiling(lv.nu[0], lv.nu[1], lv.tile) : TileGeo{0, 0, 0, 0};
         for (int a = 0; a < p.dim; ++a) lv.tab[a] = cv.take(3 * (size_t)lv.nu[a] * cz);
         for (int a = p.dim; a < 3; ++a) lv.tab[a] = nullptr;
         lv.phi = cv.take(lv.N * cr);
@@ -367,7 +384,7 @@ bool down_tiled(const csg_operator *op, int l)
 {
     if (DIM != 2 || !op->tiles || !op->down_tiles || op->p.s > 3 || l + 1 >= op->L) return false;
     const DevLevel &f = op->lev[l], &c = op->lev[l + 1];
-    return down_fits(c.tile) && f.nu[0] <= 2 * c.nu[0] + 1 && f.nu[1] <= 2 * c.nu[1] + 1;
+    return down_fits(c.dtile) && f.nu[0] <= 2 * c.nu[0] + 1 && f.nu[1] <= 2 * c.nu[1] + 1;
 }
 template <typename T, int DIM>
 bool down_st0(const csg_operator *op, int l)
@@ -411,8 +428,8 @@ int sweep(const csg_operator *op, int l, const Cx<T> *b, Cx<T> *x, bool from_zer
         ProfScope ps(op, k0 ? -1 : CSG_PROF_UPD_RESTRICT, st, by.down(s, !from_zero, lv.N, cl.N, st0));
         launch_down_tile<T>(x, from_zero ? 0 : 1, B, s, L, lvl<T>(op, l + 1), (Cx<T> *)cl.b, (Cx<T> *)cl.w[0],
                             lv.ld, cl.ld, pclose, nclose, lv.gs, tiny, st0, sizeof(T) == 8 && s == 1, cl.part[0],
-                            cl.tile, nrhs, st, active);
-        return st0 ? (int)(cl.tile.ntx * cl.tile.nty) : 0;
+                            cl.dtile, nrhs, st, active);
+        return st0 ? (int)(cl.dtile.ntx * cl.dtile.nty) : 0;
     }
     if (restrict_after) {
         // closing update writes x and the Arnoldi residual r; full weighting of r

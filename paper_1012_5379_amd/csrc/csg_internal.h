@@ -146,6 +146,7 @@ struct DevLevel {
     int nb;                    // blocks of a reducing pass
     unsigned chunk;            // points per block of a reducing pass
     TileGeo tile;              // 2-D tiling of the LDS-staged fused pass (ntx = 0: none)
+    TileGeo dtile;             // tiling of the down-path pass that restricts onto this level
 };
 
 // Instantiated graphs of one FGMRES iteration (V-cycle + outer passes), per

@@ -2086,7 +2086,7 @@ __device__ void tail_steps(const LvlK<T> &L, const Basis<T> &B, Cx<T> *w0, Cx<T>
 // Least squares of the sweep (thread 0) -> coefficients for every thread; the
 // residual coefficients are those on {u_0..u_{s-1}, w_{s-1}} (u_s folded in).
 template <typename T, int SB>
-__device__ int tail_close(const GState *gs, int s, zc *Rs, zc *ys, zc *crs, zc *ax, zc *ar, int *ks, const zc *fold,
+__device__ __forceinline__ int tail_close(const GState *gs, int s, zc *Rs, zc *ys, zc *crs, zc *ax, zc *ar, int *ks, const zc *fold,
                           Cx<T> (&cx)[SB], Cx<T> (&cr)[SB])
 {
     if (SB <= 4 && threadIdx.x == 0) {
@@ -2136,6 +2136,203 @@ __device__ int tail_close(const GState *gs, int s, zc *Rs, zc *ys, zc *crs, zc *
     const int k = *ks;
     coefs_to_T<T, SB>(k, ax, ar, cx, cr);
     return k;
+}
+
+// --- register stencils of the shared-memory tail -----------------------------
+// The points a thread owns on a tail level are p = t + k TB, k < MP; their
+// stencils are loaded once per visit of the level: the diagonal (centre table
+// entries minus phi) and the neighbour weights in the order apply_pt adds
+// them, with the neighbours' indices (clamped to the point itself at the
+// level's edge, where the weight is zero).  Every stencil application of the
+// visit then reads only shared memory.
+template <typename T>
+constexpr int tail_mp()
+{
+    return sizeof(T) == 8 ? 3 : 5;
+}
+template <typename T, int DIM, int MP>
+struct TSten {
+    Cx<T> d[MP], c[MP][2 * DIM];
+    unsigned nb[MP][2 * DIM];
+};
+
+template <typename T, int DIM, int MP>
+__device__ __forceinline__ void tsten_load(const LvlK<T> &L, TSten<T, DIM, MP> &S)
+{
+#pragma unroll
+    for (int k = 0; k < MP; ++k) {
+        const unsigned p = min(threadIdx.x + k * TB, L.N - 1);
+        unsigned i, j, kk;
+        decomp<DIM>(p, L.nx, L.ny, i, j, kk);
+        const Cx<T> *tx = L.tab[0];
+        Cx<T> d = tx[L.nx + i];
+        if (DIM >= 2) d = d + L.tab[1][L.ny + j];
+        if (DIM == 3) d = d + L.tab[2][L.nz + kk];
+        d.re -= L.phi[p];
+        S.d[k] = d;
+        S.c[k][0] = tx[i];
+        S.nb[k][0] = i ? p - 1 : p;
+        S.c[k][1] = tx[2 * L.nx + i];
+        S.nb[k][1] = i + 1 < L.nx ? p + 1 : p;
+        if (DIM >= 2) {
+            S.c[k][2] = L.tab[1][j];
+            S.nb[k][2] = j ? p - L.nx : p;
+            S.c[k][3] = L.tab[1][2 * L.ny + j];
+            S.nb[k][3] = j + 1 < L.ny ? p + L.nx : p;
+        }
+        if (DIM == 3) {
+            const unsigned sz = L.nx * L.ny;
+            S.c[k][4] = L.tab[2][kk];
+            S.nb[k][4] = kk ? p - sz : p;
+            S.c[k][5] = L.tab[2][2 * L.nz + kk];
+            S.nb[k][5] = kk + 1 < L.nz ? p + sz : p;
+        }
+    }
+}
+
+// (A x)(p) for the thread's k-th point p, x in shared memory
+template <typename T, int DIM, int MP>
+__device__ __forceinline__ Cx<T> tsten_apply(const TSten<T, DIM, MP> &S, int k, const Cx<T> *x, unsigned p)
+{
+    Cx<T> a = S.d[k] * x[p];
+#pragma unroll
+    for (int m = 0; m < 2 * DIM; ++m) a = cfma(S.c[k][m], x[S.nb[k][m]], a);
+    return a;
+}
+
+// pass 0 (as body_st0)
+template <typename T, int DIM, int MP, int NA>
+__device__ __forceinline__ void tsten_st0(const TSten<T, DIM, MP> &S, const Cx<T> *u0, Cx<T> *w, unsigned N,
+                                          zc (&acc)[NA])
+{
+#pragma unroll
+    for (int k = 0; k < MP; ++k) {
+        const unsigned p = threadIdx.x + k * TB;
+        if (p >= N) break;
+        const Cx<T> wv = tsten_apply(S, k, u0, p);
+        w[p] = wv;
+        const zc wd = cvt<double>(wv), ud = cvt<double>(u0[p]);
+        acc[0] = cjfma(ud, wd, acc[0]);
+        acc[1].re += cabs2(ud);
+        if (NA > 2) acc[NA - 1].re += cabs2(wd);
+    }
+}
+
+// r = b - A x
+template <typename T, int DIM, int MP>
+__device__ __forceinline__ void tsten_resid(const TSten<T, DIM, MP> &S, const Cx<T> *x, const Cx<T> *b, Cx<T> *r,
+                                            unsigned N)
+{
+#pragma unroll
+    for (int k = 0; k < MP; ++k) {
+        const unsigned p = threadIdx.x + k * TB;
+        if (p >= N) break;
+        r[p] = b[p] - tsten_apply(S, k, x, p);
+    }
+}
+
+// pass j+1 (as body_os): u_{j+1} at the thread's points into B.u[j+1], then,
+// after a barrier, w_{j+1} = A u_{j+1} from there, with the same sums
+template <typename T, int DIM, int SB, int MP, int NA>
+__device__ __forceinline__ void tsten_os(const TSten<T, DIM, MP> &S, const Basis<T> &B, const Cx<T> *win,
+                                         Cx<T> *wout, int j, T sj, const Cx<T> (&cu)[SB], unsigned N,
+                                         zc (&acc)[NA], bool wn)
+{
+    Cx<T> *un = pick(B, j + 1);
+    Cx<T> uq[MP][SB - 1], uc[MP];
+#pragma unroll
+    for (int k = 0; k < MP; ++k) {
+        const unsigned p = min(threadIdx.x + k * TB, N - 1);
+        uc[k] = sj * win[p];
+#pragma unroll
+        for (int q = 0; q < SB - 1; ++q)
+            if (q <= j) {
+                uq[k][q] = B.u[q][p];
+                uc[k] = uc[k] - cu[q] * uq[k][q];
+            }
+        if (threadIdx.x + k * TB < N) un[p] = uc[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < MP; ++k) {
+        const unsigned p = threadIdx.x + k * TB;
+        if (p >= N) break;
+        const Cx<T> a = tsten_apply(S, k, un, p);
+        wout[p] = a;
+        const zc wd = cvt<double>(a), ud = cvt<double>(uc[k]);
+#pragma unroll
+        for (int q = 0; q < SB - 1; ++q)
+            if (q <= j) acc[q] = cjfma(cvt<double>(uq[k][q]), wd, acc[q]);
+#pragma unroll
+        for (int q = 1; q < SB; ++q) {
+            if (q == j + 1) acc[q] = cjfma(ud, wd, acc[q]);
+            if (q == j + 2) acc[q].re += cabs2(ud);
+        }
+        if (wn) {
+#pragma unroll
+            for (int q = 3; q < NA; ++q)
+                if (q == j + 3) acc[q].re += cabs2(wd);
+        }
+    }
+}
+
+// tail_steps on one shared-memory level with its register stencils
+template <typename T, int DIM, int SB, int MP>
+__device__ __forceinline__ void tsten_steps(const TSten<T, DIM, MP> &S, unsigned N, const Basis<T> &B, Cx<T> *w0, Cx<T> *w1, int s,
+                            double tiny, GState *gs, zc *sh, zc *res, zc *fold)
+{
+    if (norm_from_sums<T>() && s == 1) {
+        zc acc[3] = {mkc(0.0, 0.0), mkc(0.0, 0.0), mkc(0.0, 0.0)};
+        tsten_st0<T, DIM, MP, 3>(S, B.u[0], w0, N, acc);
+        tail_sum<3>(acc, 3, sh, res);
+    } else {
+        zc acc[2] = {mkc(0.0, 0.0), mkc(0.0, 0.0)};
+        tsten_st0<T, DIM, MP, 2>(S, B.u[0], w0, N, acc);
+        tail_sum<2>(acc, 2, sh, res);
+    }
+    for (int j = 0; j < s; ++j) {
+        Cx<T> cu[SB];
+        const double sj = coef_step<T, SB>(res, j, s, tiny, load_prev<SB>(gs, j), gs, threadIdx.x == 0, cu);
+        Cx<T> *win = (j & 1) ? w1 : w0;
+        Cx<T> *wout = (j & 1) ? w0 : w1;
+        if (j + 1 < s) {
+            zc acc[SB + 1];
+#pragma unroll
+            for (int q = 0; q <= SB; ++q) acc[q] = mkc(0.0, 0.0);
+            const bool wn = norm_from_sums<T>() && j + 2 == s;
+            tsten_os<T, DIM, SB, MP, SB + 1>(S, B, win, wout, j, (T)sj, cu, N, acc, wn);
+            tail_sum<SB + 1>(acc, j + 3 + (wn ? 1 : 0), sh, res);
+        } else if constexpr (!norm_from_sums<T>()) {
+            // explicit form: u_s and its norm
+            zc nr[1] = {mkc(0.0, 0.0)};
+            body_orthl<T, SB>(B, win, j, (T)sj, cu, 0, threadIdx.x, N, TB, nr[0].re);
+            tail_sum<1>(nr, 1, sh, res);
+            if (threadIdx.x == 0) {
+                const double hn = sqrt(res[0].re);
+                const bool brk = !(hn > tiny * gs->beta0);
+                gs->H[s * CSG_MAX_S + (s - 1)] = mkc(hn, 0.0);
+                gs->sig[s] = brk ? 0.0 : 1.0 / hn;
+            }
+            __syncthreads();
+        } else {
+            if (threadIdx.x == 0) {
+                // h_{s,s-1} (a difference at rounding level of ||A v_{s-1}||^2:
+                // A v_{s-1} lies in the basis span), the scale of u_s, the breakdown test
+                const double w2 = sj * sj * res[s + 1].re;
+                double h2 = w2;
+                for (int i = 0; i < s; ++i) h2 -= cabs2(gs->H[i * CSG_MAX_S + (s - 1)]);
+                const double hn = h2 > 1e-13 * w2 ? sqrt(h2) : 0.0;
+                const bool brk = !(hn > tiny * gs->beta0);
+                gs->H[s * CSG_MAX_S + (s - 1)] = mkc(hn, 0.0);
+                gs->sig[s] = brk ? 0.0 : 1.0 / hn;
+#pragma unroll
+                for (int i = 0; i < SB; ++i)
+                    if (i < s) fold[i] = cvt<double>(cu[i]);
+                fold[s] = mkc(sj, 0.0);
+            }
+            __syncthreads();
+        }
+    }
 }
 
 // Vectors of one level of the shared-memory tail: [b | x | u_0 .. | w_0 | w_1],
@@ -2195,10 +2392,13 @@ __global__ __launch_bounds__(TB) void k_tail_lds(const TLev<T> *__restrict__ lev
         for (unsigned p = t; p < lev[lt].N; p += TB) top.b[p] = src[p];
         __syncthreads();
     }
+    constexpr int MP = tail_mp<T>();
+    TSten<T, DIM, MP> S;
     // down: pre-smoothing and restriction
     for (int l = lt; l < L - 1; ++l) {
         const LvlK<T> F = tlvl(lev[l]), C = tlvl(lev[l + 1]);
         const LdsLev<T> f = level(l), c = level(l + 1);
+        if (nu1 > 0) tsten_load<T, DIM, MP>(F, S);
         if (nu1 == 0) {
             body_restrict<T, DIM>(F, C, nullptr, f.b, c.b, t, C.N, TB);
             __syncthreads();
@@ -2211,11 +2411,11 @@ __global__ __launch_bounds__(TB) void k_tail_lds(const TLev<T> *__restrict__ lev
             if (k == 0) {
                 B.u[0] = f.b;
             } else {
-                body_resid<T, DIM>(F, f.x, f.b, f.u[0], t, F.N, TB);
+                tsten_resid<T, DIM, MP>(S, f.x, f.b, f.u[0], F.N);
                 __syncthreads();
                 B.u[0] = f.u[0];
             }
-            tail_steps<T, DIM, SB>(F, B, f.w[0], f.w[1], 0, s, tiny, &gs, sh, res, fold);
+            tsten_steps<T, DIM, SB, MP>(S, F.N, B, f.w[0], f.w[1], s, tiny, &gs, sh, res, fold);
             Cx<T> cx[SB], cr[SB];
             const int kk = tail_close<T, SB>(&gs, s, Rs, ys, crs, ax, ar, &ks, fold, cx, cr);
             if (k == nu1 - 1)
@@ -2238,6 +2438,7 @@ __global__ __launch_bounds__(TB) void k_tail_lds(const TLev<T> *__restrict__ lev
     for (int l = L - 2; l >= lt; --l) {
         const LvlK<T> F = tlvl(lev[l]), C = tlvl(lev[l + 1]);
         const LdsLev<T> f = level(l), c = level(l + 1);
+        if (nu2 > 0) tsten_load<T, DIM, MP>(F, S);
         body_prolong<T, DIM>(F, C, c.x, nu1 > 0 ? f.x : nullptr, f.x, t, F.N, TB);
         __syncthreads();
         if (nu2 == 0) continue;
@@ -2245,9 +2446,9 @@ __global__ __launch_bounds__(TB) void k_tail_lds(const TLev<T> *__restrict__ lev
         for (int q = 0; q <= CSG_MAX_S; ++q) B.u[q] = f.u[q];
         if (norm_from_sums<T>()) B.u[s] = f.w[(s - 1) & 1];
         for (int k = 0; k < nu2; ++k) {
-            body_resid<T, DIM>(F, f.x, f.b, f.u[0], t, F.N, TB);
+            tsten_resid<T, DIM, MP>(S, f.x, f.b, f.u[0], F.N);
             __syncthreads();
-            tail_steps<T, DIM, SB>(F, B, f.w[0], f.w[1], 0, s, tiny, &gs, sh, res, fold);
+            tsten_steps<T, DIM, SB, MP>(S, F.N, B, f.w[0], f.w[1], s, tiny, &gs, sh, res, fold);
             Cx<T> cx[SB], cr[SB];
             const int kk = tail_close<T, SB>(&gs, s, Rs, ys, crs, ax, ar, &ks, fold, cx, cr);
             body_upd<T, SB>(f.x, 1, B, kk, cx, 0, t, F.N, TB);
@@ -3098,6 +3299,7 @@ void launch_fin(int mode, const zc *pin, int nbin, int j, FState *fs, Report *re
 template <typename T, int DIM>
 size_t tail_lds_bytes(const unsigned *N, int lt, int L, int s)
 {
+    if (N[lt] > (unsigned)(tail_mp<T>() * TB)) return ~(size_t)0;   // more points per thread than the register stencils
     size_t n = 0;
     for (int l = lt; l < L - 1; ++l) n += (size_t)tail_vectors<T>(s) * N[l];
     n += 2 * (size_t)N[L - 1];
