@@ -142,7 +142,6 @@ void carve(csg_operator &op, const int nint[CSG_MAX_LEVELS][3], Carver &cv)
     op.b0 = p.cycle_prec ? cv.take(n0 * cz) : nullptr;
     op.opart = (zc *)cv.take((size_t)R * OVAL * NBMAX * sizeof(zc));
     op.fs = (FState *)cv.take((size_t)R * sizeof(FState));
-    op.rep = (Report *)cv.take((size_t)R * sizeof(Report));
     op.active = (int *)cv.take((size_t)3 * R * sizeof(int));
     op.ones = op.active + 2 * R;
 }
@@ -570,8 +569,10 @@ struct csg_solve {
     int nrhs, m, maxit, use_x0;
     double tol;
     hipStream_t st;
-    enum { INIT, WAIT_BEGIN, CYCLE, WAIT_ITER, CYCLE_END, WAIT_END, FINISHED } phase;
-    int j;
+    enum { INIT, WAIT_BEGIN, CYCLE, CYCLE_END, WAIT_END, FINISHED } phase;
+    int j;            // columns of the current cycle whose reports the host has read
+    int jq;           // columns of the current cycle queued (j <= jq <= j + LOOKAHEAD)
+    bool halt;        // no RHS iterates any more in this cycle: queue no further column
     int rc;
     int it[CSG_MAX_RHS_HOST];
     int done[CSG_MAX_RHS_HOST], conv[CSG_MAX_RHS_HOST], act[CSG_MAX_RHS_HOST], restarts[CSG_MAX_RHS_HOST];
@@ -583,6 +584,9 @@ struct csg_solve {
 
 namespace {
 
+// Device address of report slot `slot` in pinned host memory.
+Report *report_slot(const csg_operator *op, int slot) { return op->rep_dev + (size_t)slot * op->p.max_rhs; }
+
 template <int DIM>
 void enqueue_begin(csg_solve *sv, bool with_chi_norm)
 {
@@ -591,7 +595,8 @@ void enqueue_begin(csg_solve *sv, bool with_chi_norm)
     const Launch g = lch(op, 0, sv->nrhs, sv->st);
     const int *mask = op->active + cyc_mask_offset(op);
     launch_tres<DIM>(lvlH(op), sv->chi, sv->u, op->V, f.ld, with_chi_norm ? 1 : 0, op->opart, g, mask);
-    launch_fin(with_chi_norm ? FIN_BEGIN : FIN_BETA, op->opart, f.nb, 0, op->fs, op->rep, sv->nrhs, sv->st, mask);
+    launch_fin(with_chi_norm ? FIN_BEGIN : FIN_BETA, op->opart, f.nb, 0, op->fs, report_slot(op, LOOKAHEAD), sv->nrhs,
+               sv->st, mask);
     ProfScope ps(op, CSG_PROF_OUTER_NORM, sv->st, sv->nrhs * f.N * (32.0 + (op->p.cycle_prec ? 8.0 : 0.0)));
     if (op->p.cycle_prec)
         launch_vnorm<float>(op->V, op->V, (cf *)op->b0, f.N, f.ld, op->fs, g, mask);
@@ -622,7 +627,7 @@ void iter_body(csg_solve *sv, int j, hipStream_t st)
         ProfScope ps(op, CSG_PROF_OUTER_H, st, R * N * (sizeof(Cx<TZ>) + 16.0 * (j + 2)) + 8.0 * N);
         launch_hdot<TZ, DIM>(lvlH(op), z, op->w, op->V, vstride, j, f.ld, op->opart, g, mask);
     }
-    launch_fin(FIN_H, op->opart, f.nb, j, op->fs, op->rep, sv->nrhs, st, mask);
+    launch_fin(FIN_H, op->opart, f.nb, j, op->fs, report_slot(op, j % LOOKAHEAD), sv->nrhs, st, mask, op->active);
     {
         // first projection: writes v_{j+1} when the first round is final (the
         // second-round passes below then return at once)
@@ -634,7 +639,7 @@ void iter_body(csg_solve *sv, int j, hipStream_t st)
         ProfScope ps(op, CSG_PROF_OUTER_CGS2, st, R * N * 16.0 * (j + 2));
         launch_mdot(op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->opart, g, mask);
     }
-    launch_fin(FIN_CN, op->opart, f.nb, j, op->fs, op->rep, sv->nrhs, st, mask);
+    launch_fin(FIN_CN, op->opart, f.nb, j, op->fs, report_slot(op, j % LOOKAHEAD), sv->nrhs, st, mask, op->active);
     ProfScope ps(op, CSG_PROF_OUTER_PROJ2, st, R * N * (16.0 * (j + 3) + (op->p.cycle_prec ? 8.0 : 0.0)));
     launch_proj1<TZ>(op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->V + (j + 1) * vstride,
                      op->p.cycle_prec ? (Cx<TZ> *)op->b0 : nullptr, g, mask);
@@ -654,11 +659,10 @@ void drop_graphs(csg_operator *op)
 // Replays the captured graph of column j (capturing it on first use); eager
 // launches when graphs are disabled or a pass is being instrumented.
 template <typename TZ, int DIM>
-void enqueue_iter(csg_solve *sv)
+void enqueue_iter(csg_solve *sv, int j)
 {
     csg_operator *op = sv->op;
     GraphCache *gc = op->gc;
-    const int j = sv->j;
     if (!gc || !gc->enabled || op->prof) {
         // eager: graphs disabled, or launches being timed (this HIP cannot time
         // events recorded inside a graph)
@@ -697,7 +701,7 @@ void enqueue_end(csg_solve *sv)
     const size_t vstride = (size_t)op->p.max_rhs * f.N;
     const Launch g = lch(op, 0, sv->nrhs, sv->st);
     const int *mask = op->active + cyc_mask_offset(op);
-    launch_fin(FIN_LS, op->opart, f.nb, 0, op->fs, op->rep, sv->nrhs, sv->st, mask);
+    launch_fin(FIN_LS, op->opart, f.nb, 0, op->fs, report_slot(op, LOOKAHEAD), sv->nrhs, sv->st, mask);
     launch_uupd<TZ>(sv->u, (const Cx<TZ> *)op->Z, vstride, f.N, f.ld, op->fs, g, mask);
     enqueue_begin<DIM>(sv, false);
 }
@@ -714,11 +718,22 @@ void upload_masks(csg_solve *sv)
     hipMemcpyAsync(op->active, sv->mask_host, 2 * R * sizeof(int), hipMemcpyHostToDevice, sv->st);
 }
 
-void enqueue_report(csg_solve *sv)
+// The event of report slot `slot` (column j of a cycle: j % LOOKAHEAD; cycle
+// begin / end: LOOKAHEAD), whose reports k_fin wrote to pinned host memory.
+void enqueue_report(csg_solve *sv, int slot) { hipEventRecord(sv->op->evq[slot], sv->st); }
+
+// The event of the report the host reads next, or null when none is queued.
+hipEvent_t pending_event(const csg_solve *sv)
 {
-    csg_operator *op = sv->op;
-    hipMemcpyAsync(op->rep_host, op->rep, sv->nrhs * sizeof(Report), hipMemcpyDeviceToHost, sv->st);
-    hipEventRecord(op->ev, sv->st);
+    switch (sv->phase) {
+    case csg_solve::WAIT_BEGIN:
+    case csg_solve::WAIT_END:
+        return sv->op->evq[LOOKAHEAD];
+    case csg_solve::CYCLE:
+        return sv->j < sv->jq ? sv->op->evq[sv->j % LOOKAHEAD] : nullptr;
+    default:
+        return nullptr;
+    }
 }
 
 int solve_step(csg_solve *sv)
@@ -729,22 +744,28 @@ int solve_step(csg_solve *sv)
     switch (sv->phase) {
     case csg_solve::INIT:
         upload_masks(sv);
+        launch_fs_params(op->fs, sv->tol, sv->maxit, sv->nrhs, sv->st);
         if (d3) enqueue_begin<3>(sv, true); else enqueue_begin<2>(sv, true);
-        enqueue_report(sv);
+        enqueue_report(sv, LOOKAHEAD);
         sv->phase = csg_solve::WAIT_BEGIN;
         break;
     case csg_solve::CYCLE:
-        upload_masks(sv);
-        if (mixed) { if (d3) enqueue_iter<float, 3>(sv); else enqueue_iter<float, 2>(sv); }
-        else { if (d3) enqueue_iter<double, 3>(sv); else enqueue_iter<double, 2>(sv); }
-        enqueue_report(sv);
-        sv->phase = csg_solve::WAIT_ITER;
+        // queue columns up to LOOKAHEAD ahead of the reports read; each RHS's
+        // iteration mask is cleared by the device when it stops.  Instrumented
+        // solves queue one at a time, so that no skipped column is timed.
+        if (sv->jq == 0) upload_masks(sv);
+        while (!sv->halt && sv->jq < sv->m && sv->jq - sv->j < (op->prof ? 1 : LOOKAHEAD)) {
+            if (mixed) { if (d3) enqueue_iter<float, 3>(sv, sv->jq); else enqueue_iter<float, 2>(sv, sv->jq); }
+            else { if (d3) enqueue_iter<double, 3>(sv, sv->jq); else enqueue_iter<double, 2>(sv, sv->jq); }
+            enqueue_report(sv, sv->jq % LOOKAHEAD);
+            sv->jq++;
+        }
         break;
     case csg_solve::CYCLE_END:
         upload_masks(sv);
         if (mixed) { if (d3) enqueue_end<float, 3>(sv); else enqueue_end<float, 2>(sv); }
         else { if (d3) enqueue_end<double, 3>(sv); else enqueue_end<double, 2>(sv); }
-        enqueue_report(sv);
+        enqueue_report(sv, LOOKAHEAD);
         sv->phase = csg_solve::WAIT_END;
         break;
     default:
@@ -757,7 +778,8 @@ int solve_step(csg_solve *sv)
 void solve_advance(csg_solve *sv)
 {
     csg_operator *op = sv->op;
-    const Report *rp = op->rep_host;
+    const int R = op->p.max_rhs;
+    const Report *rp = op->rep_host + (size_t)(sv->phase == csg_solve::CYCLE ? sv->j % LOOKAHEAD : LOOKAHEAD) * R;
     bool any = false;
     switch (sv->phase) {
     case csg_solve::WAIT_BEGIN:
@@ -781,10 +803,11 @@ void solve_advance(csg_solve *sv)
             sv->act[r] = 1;
             any = true;
         }
-        sv->j = 0;
+        sv->j = sv->jq = 0;
+        sv->halt = false;
         sv->phase = any ? csg_solve::CYCLE : csg_solve::FINISHED;
         break;
-    case csg_solve::WAIT_ITER: {
+    case csg_solve::CYCLE: {
         bool still = false;
         for (int r = 0; r < sv->nrhs; ++r) {
             if (sv->done[r] || !sv->act[r]) continue;
@@ -795,7 +818,8 @@ void solve_advance(csg_solve *sv)
             still = true;
         }
         sv->j++;
-        sv->phase = (still && sv->j < sv->m) ? csg_solve::CYCLE : csg_solve::CYCLE_END;
+        if (!still) sv->halt = true;   // the columns queued behind this one are no-ops
+        if (sv->j == sv->jq && (sv->halt || sv->j == sv->m)) sv->phase = csg_solve::CYCLE_END;
         break;
     }
     default:
@@ -1009,9 +1033,12 @@ int csg_operator_create(const csg_params *p, const double *phi_host, void *ws_de
         if (hipStreamSynchronize(s) != hipSuccess) rc = CSG_EDEVICE;
     }
     if (rc == CSG_OK) {
-        if (hipHostMalloc((void **)&op->rep_host, p->max_rhs * sizeof(Report), hipHostMallocDefault) != hipSuccess)
+        if (hipHostMalloc((void **)&op->rep_host, (LOOKAHEAD + 1) * (size_t)p->max_rhs * sizeof(Report),
+                          hipHostMallocDefault) != hipSuccess ||
+            hipHostGetDevicePointer((void **)&op->rep_dev, op->rep_host, 0) != hipSuccess)
             rc = CSG_EDEVICE;
-        if (hipEventCreateWithFlags(&op->ev, hipEventDisableTiming) != hipSuccess) rc = CSG_EDEVICE;
+        for (int q = 0; q <= LOOKAHEAD; ++q)
+            if (hipEventCreateWithFlags(&op->evq[q], hipEventDisableTiming) != hipSuccess) rc = CSG_EDEVICE;
         op->gc = new GraphCache;
         if (const char *e = getenv("CSG_GRAPHS")) op->gc->enabled = atoi(e) != 0;
         if (p->graphs) op->gc->enabled = p->graphs > 0;
@@ -1020,6 +1047,8 @@ int csg_operator_create(const csg_params *p, const double *phi_host, void *ws_de
     if (rc != CSG_OK) {
         hipError_t e = hipGetLastError();
         if (op->rep_host) hipHostFree(op->rep_host);
+        for (int q = 0; q <= LOOKAHEAD; ++q)
+            if (op->evq[q]) hipEventDestroy(op->evq[q]);
         if (op->gc) {
             if (op->gc->cap) hipStreamDestroy(op->gc->cap);
             delete op->gc;
@@ -1096,7 +1125,8 @@ int csg_operator_destroy(csg_operator *op)
         if (op->gc->cap) hipStreamDestroy(op->gc->cap);
         delete op->gc;
     }
-    if (op->ev) hipEventDestroy(op->ev);
+    for (int q = 0; q <= LOOKAHEAD; ++q)
+        if (op->evq[q]) hipEventDestroy(op->evq[q]);
     if (op->rep_host) hipHostFree(op->rep_host);
     delete op;
     return CSG_OK;
@@ -1289,9 +1319,9 @@ int csg_solve_poll(csg_solve *sv, int *done)
     if (!sv) return fail(CSG_EINVAL, "null solve");
     if (done) *done = sv->phase == csg_solve::FINISHED;
     if (sv->phase == csg_solve::FINISHED) return 1;
-    if (sv->phase != csg_solve::WAIT_BEGIN && sv->phase != csg_solve::WAIT_ITER && sv->phase != csg_solve::WAIT_END)
-        return 1;   // nothing in flight: the caller should step
-    hipError_t e = hipEventQuery(sv->op->ev);
+    hipEvent_t ev = pending_event(sv);
+    if (!ev) return 1;   // no report in flight: the caller should step
+    hipError_t e = hipEventQuery(ev);
     if (e == hipErrorNotReady) return 0;
     if (e != hipSuccess) return fail(CSG_EDEVICE, std::string("solve: ") + hipGetErrorString(e));
     solve_advance(sv);
@@ -1337,7 +1367,8 @@ int helm_solve(const csg_operator *op, const void *chi, void *u, int nrhs, doubl
     st = csg_solve_begin(op, chi, u, nrhs, tol, restart, maxit, use_initial_guess, stream, &sv);
     if (!sv) return st;
     while (st == CSG_OK && sv->phase != csg_solve::FINISHED) {
-        if (hipEventSynchronize(op->ev) != hipSuccess) { st = fail(CSG_EDEVICE, "event wait failed"); break; }
+        hipEvent_t ev = pending_event(sv);
+        if (ev && hipEventSynchronize(ev) != hipSuccess) { st = fail(CSG_EDEVICE, "event wait failed"); break; }
         int done = 0;
         int pr = csg_solve_poll(sv, &done);
         if (pr < 0) { st = pr; break; }

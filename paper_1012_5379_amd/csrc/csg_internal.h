@@ -53,10 +53,16 @@ struct FState {
     double hn;         // h_{j+1,j} of the current column
     double inv_hn;     // scale applied to form v_{j+1}
     double w2;         // ||H z_j||^2 of the current column
+    double tol;        // stopping tolerance of the solve
     int kcols;         // columns of the current restart cycle used by the update
     int reorth;        // the current column takes the second Gram-Schmidt round
-    int pad[2];
+    int it;            // outer iterations done by this RHS in the solve
+    int maxit;         // iteration limit of the solve
 };
+
+// Outer iterations a solve keeps queued ahead of the host's reading of their
+// reports: the device itself clears a RHS's iteration mask when it stops.
+constexpr int LOOKAHEAD = 3;
 
 // Host-visible per-RHS report (copied back after every outer iteration).
 struct Report {
@@ -191,11 +197,11 @@ struct csg_operator {
     void *b0;                         // cycle-precision copy of v_j (mixed mode)
     csg::zc *opart;                   // [max_rhs][OVAL][NBMAX]
     csg::FState *fs;                  // [max_rhs]
-    csg::Report *rep;                 // [max_rhs] device
     int *active;                      // [max_rhs] device mask of RHS still iterating
     int *ones;                        // [max_rhs] device all-ones mask
-    csg::Report *rep_host;            // pinned host mirror
-    hipEvent_t ev;
+    csg::Report *rep_host;            // pinned host reports: LOOKAHEAD + 1 slots of max_rhs, written by k_fin
+    csg::Report *rep_dev;             // the same memory as the device addresses it
+    hipEvent_t evq[csg::LOOKAHEAD + 1];   // one per report slot (the last: cycle begin / end)
     size_t ws_used;
     int busy;                         // a csg_solve is in flight
     csg::Prof *prof;                  // instrumentation, or null

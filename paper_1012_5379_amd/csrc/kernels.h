@@ -180,7 +180,10 @@ void launch_uupd(zc *u, const Cx<TZ> *Z, size_t zstride, unsigned N, size_t ld, 
 // finish kernels: one block per RHS
 enum FinMode { FIN_H = 0, FIN_CN = 1, FIN_BEGIN = 3, FIN_BETA = 4, FIN_LS = 5 };
 void launch_fin(int mode, const zc *pin, int nbin, int j, FState *fs, Report *rep, int nrhs, hipStream_t st,
-                const int *active);
+                const int *active, int *stop = nullptr);
+
+// Stopping parameters of a solve into every RHS's state (iteration count reset).
+void launch_fs_params(FState *fs, double tol, int maxit, int nrhs, hipStream_t st);
 
 void launch_copy_mask(const int *src, int *dst, int n, hipStream_t st);
 

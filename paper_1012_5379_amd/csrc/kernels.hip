@@ -2895,7 +2895,12 @@ __device__ __forceinline__ zc group_parts(const zc *pp, int nbin)
 // h_{j+1,j} = hn): apply the previous rotations (cs, sn staged in shared
 // memory), form the new one, update g and the estimate.  One thread; the
 // rotated column is left in col for the block to store.
-__device__ void givens_column(FState *fs, Report *rp, int j, double hn, zc *col, const double *cs_s, const zc *sn_s)
+// Also decides, as the host does on reading the report, whether the RHS stops
+// iterating (non-finite estimate, tolerance reached, breakdown, iteration
+// limit); stop (when given) is then cleared, so the iterations queued behind
+// this one skip it.
+__device__ void givens_column(FState *fs, Report *rp, int j, double hn, zc *col, const double *cs_s, const zc *sn_s,
+                              int *stop)
 {
     col[j + 1] = mkc(hn, 0.0);
     for (int q = 0; q < j; ++q) {
@@ -2922,13 +2927,15 @@ __device__ void givens_column(FState *fs, Report *rp, int j, double hn, zc *col,
     rp->est = est;
     rp->hn = hn;
     rp->finite = isfinite(est) && isfinite(hn);
+    fs->it += 1;
+    if (stop && (!rp->finite || est <= fs->tol || hn == 0.0 || fs->it >= fs->maxit)) *stop = 0;
 }
 
 // One block per RHS: finish an outer reduction and advance the small FGMRES
 // state (Hessenberg column, Givens rotations, residual estimate, LS solve).
 // The serial parts run on one thread over shared-memory copies of the state.
 __global__ __launch_bounds__(FT) void k_fin(int mode, const zc *__restrict__ pin, int nbin, int j, FState *fsb,
-                                            Report *rep, const int *active)
+                                            Report *rep, const int *active, int *stop)
 {
     constexpr int M = CSG_MAX_RESTART;
     __shared__ zc val[OVAL];
@@ -3000,7 +3007,7 @@ __global__ __launch_bounds__(FT) void k_fin(int mode, const zc *__restrict__ pin
             const double w1 = w2 - h2;
             two = !(w1 >= 1e-4 * w2);
             fs->reorth = two;
-            if (!two) givens_column(fs, rep + rhs, j, sqrt(w1), col, cs_s, sn_s);
+            if (!two) givens_column(fs, rep + rhs, j, sqrt(w1), col, cs_s, sn_s, stop ? stop + rhs : nullptr);
         }
         __syncthreads();
         if (!two)
@@ -3025,7 +3032,8 @@ __global__ __launch_bounds__(FT) void k_fin(int mode, const zc *__restrict__ pin
                 c2 += cabs2(val[q]);
             }
             const double w2 = val[j + 1].re, h2 = w2 - c2;
-            givens_column(fs, rep + rhs, j, h2 > 1e-13 * w2 ? sqrt(h2) : 0.0, col, cs_s, sn_s);
+            givens_column(fs, rep + rhs, j, h2 > 1e-13 * w2 ? sqrt(h2) : 0.0, col, cs_s, sn_s,
+                          stop ? stop + rhs : nullptr);
         }
         __syncthreads();
         for (int q = threadIdx.x; q <= j + 1; q += FT) fs->R[q * M + j] = col[q];
@@ -3291,9 +3299,24 @@ void launch_uupd(zc *u, const Cx<TZ> *Z, size_t zstride, unsigned N, size_t ld, 
 }
 
 void launch_fin(int mode, const zc *pin, int nbin, int j, FState *fs, Report *rep, int nrhs, hipStream_t st,
-                const int *active)
+                const int *active, int *stop)
 {
-    hipLaunchKernelGGL(k_fin, dim3(nrhs), dim3(FT), 0, st, mode, pin, nbin, j, fs, rep, active);
+    hipLaunchKernelGGL(k_fin, dim3(nrhs), dim3(FT), 0, st, mode, pin, nbin, j, fs, rep, active, stop);
+}
+
+__global__ void k_fs_params(FState *fs, double tol, int maxit, int nrhs)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < nrhs) {
+        fs[r].tol = tol;
+        fs[r].maxit = maxit;
+        fs[r].it = 0;
+    }
+}
+
+void launch_fs_params(FState *fs, double tol, int maxit, int nrhs, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fs_params, dim3((nrhs + 63) / 64), dim3(64), 0, st, fs, tol, maxit, nrhs);
 }
 
 template <typename T, int DIM>
