@@ -998,7 +998,9 @@ __global__ __launch_bounds__(BLK) void k_os_tile(LvlK<T> L, Basis<T> B, const Cx
     __shared__ Cx<T> lu[TILE_MAXN];
     __shared__ Cx<T> ltab[6 * TAB_MAXD];   // x lower, diag, upper; y lower, diag, upper
     const int rhs = blockIdx.y;
-    if (!active[rhs]) return;
+    // the mask is tested after the prologue's loads are issued (every read
+    // below is harmless for a RHS that no longer iterates)
+    const int act = active[rhs];
     GState *gs = gsb + rhs;
     const GPrev<SB> pv = load_prev<SB>(gs, j);
     const unsigned t = chunk_id(ntile);
@@ -1057,6 +1059,7 @@ __global__ __launch_bounds__(BLK) void k_os_tile(LvlK<T> L, Basis<T> B, const Cx
         for (int q = 0; q <= J; ++q) uq[it][q] = B.u[q][off + pq[it]];
         phq[it] = L.phi[pq[it]];
     }
+    if (!act) return;
     block_sum<SB + 1>(pv_parts, j + 2, sh, res);
     if (tslot >= 0) ltab[tslot] = mkc<T>(tre, tim);
     Cx<T> cu[SB];
@@ -1149,7 +1152,7 @@ __global__ __launch_bounds__(BLK) void k_up_tile(LvlK<T> F, LvlK<T> C, const Cx<
     __shared__ Cx<T> lx[UP_MAXN];
     __shared__ Cx<T> ltab[6 * TAB_MAXD];   // x lower, diag, upper; y lower, diag, upper
     const int rhs = blockIdx.y;
-    if (!active[rhs]) return;
+    const int act = active[rhs];   // tested before the first store (reads below are harmless)
     const unsigned t = chunk_id(ntile);
     const unsigned tyi = t / tg.ntx, txi = t - tyi * tg.ntx;
     const int nx = (int)F.nx, ny = (int)F.ny;
@@ -1221,6 +1224,7 @@ __global__ __launch_bounds__(BLK) void k_up_tile(LvlK<T> F, LvlK<T> C, const Cx<
             for (int i = 0; i < TILE_PB; ++i)
                 if (b0 + i < UP_MAXE) xl[i] = xi[pp[i]];
         }
+        if (b0 == 0 && !act) return;
 #pragma unroll
         for (int i = 0; i < TILE_PB; ++i) {
             if (b0 + i >= UP_MAXE) break;
@@ -1745,7 +1749,7 @@ __global__ __launch_bounds__(BLK) void k_down_tile(Cx<T> *__restrict__ x, int ac
     __shared__ Cx<T> lb[DN_MAXB];
     __shared__ Cx<T> ltab[6 * TAB_MAXD];   // coarse tables: x lower, diag, upper; y lower, diag, upper
     const int rhs = blockIdx.y;
-    if (!active[rhs]) return;
+    const int act = active[rhs];   // tested before the closing writes (reads below are harmless)
     const unsigned t = chunk_id(ntile);
     const unsigned tyi = t / tg.ntx, txi = t - tyi * tg.ntx;
     const int fnx = (int)F.nx, fny = (int)F.ny, cnx = (int)C.nx, cny = (int)C.ny;
@@ -1810,6 +1814,7 @@ __global__ __launch_bounds__(BLK) void k_down_tile(Cx<T> *__restrict__ x, int ac
         }
     };
     load_batch(0);
+    if (!act) return;
     const int k = close_end<T, SB>(cls, gsb + rhs, s, tiny, sh, res, ax, ar);
     Cx<T> cx[SB], cr[SB];
     coefs_to_T<T, SB>(k, ax, ar, cx, cr);
