@@ -331,8 +331,13 @@ int arnoldi_passes(const csg_operator *op, int l, const Basis<T> &B, int nrhs, h
     int nlast = first;   // partials written by the last pass
     if (first == 0) {
         ProfScope ps(op, l == 0 ? CSG_PROF_STENCIL_DOTS : -1, st, by.st(0, lv.N));
-        launch_st0<T, DIM>(L, B.u[0], W[0], sums && s == 1, lv.ld, lv.part[0], g, active);
-        nlast = lv.nb;
+        if (tl) {
+            launch_st0_tile<T>(L, B.u[0], W[0], lv.ld, sums && s == 1, lv.part[0], lv.tile, nrhs, st, active);
+            nlast = ntile;
+        } else {
+            launch_st0<T, DIM>(L, B.u[0], W[0], sums && s == 1, lv.ld, lv.part[0], g, active);
+            nlast = lv.nb;
+        }
     }
     for (int j = 0; j + 1 < s; ++j) {
         ProfScope ps(op, l == 0 ? CSG_PROF_FUSED : -1, st, by.os(j, lv.N));

@@ -76,6 +76,13 @@ void launch_up_tile(const LvlK<T> &F, const LvlK<T> &C, const Cx<T> *ec, const C
                     const Cx<T> *b, Cx<T> *r, Cx<T> *w, size_t ldf, size_t ldc, bool wnorm, zc *pout,
                     const TileGeo &tg, int nrhs, hipStream_t st, const int *active);
 
+// Pass 0 of a sweep on 2-D tiles: w = A u0 with <u0, w>, ||u0||^2 (and
+// ||w||^2 when wnorm) per tile into pout; same outputs as launch_st0,
+// partials by tile.
+template <typename T>
+void launch_st0_tile(const LvlK<T> &L, const Cx<T> *u0, Cx<T> *w, size_t ld, bool wnorm, zc *pout, const TileGeo &tg,
+                     int nrhs, hipStream_t st, const int *active);
+
 // Closing pass of the last pre-sweep on a 2-D level, the restriction and
 // (st0) pass 0 of the coarse level's first sweep, on tiles tc of the coarse
 // level: x (+)= sum cx_i u_i, bc = 2^-d P^T r with the Arnoldi residual

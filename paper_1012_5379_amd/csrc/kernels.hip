@@ -1129,6 +1129,100 @@ __global__ __launch_bounds__(BLK) void k_os_tile(LvlK<T> L, Basis<T> B, const Cx
     if (threadIdx.x < nv) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + t] = res[threadIdx.x];
 }
 
+// Pass 0 on one 2-D tile (see launch_st0_tile): u_0 on the tile and its
+// one-point halo into shared memory (zero outside the level), then w_0 = A u_0
+// on the tile's points with <u_0, w_0>, ||u_0||^2 and (NA = 3) ||w_0||^2.  The
+// loads go in batches of TILE_PB points per thread (phi kept for phase 2), the
+// tile's stencil tables are staged in shared memory, as in k_os_tile.
+template <typename T, int NA>
+__global__ __launch_bounds__(BLK) void k_st0_tile(LvlK<T> L, const Cx<T> *__restrict__ u0, Cx<T> *__restrict__ w,
+                                                  size_t ld, zc *__restrict__ pout, TileGeo tg, int ntile,
+                                                  const int *active)
+{
+    __shared__ zc sh[(BLK / 64) * NA];
+    __shared__ zc res[NA];
+    __shared__ Cx<T> lu[TILE_MAXN];
+    __shared__ Cx<T> ltab[6 * TAB_MAXD];
+    const int rhs = blockIdx.y;
+    const int act = active[rhs];   // tested before the first store (reads below are harmless)
+    const unsigned t = chunk_id(ntile);
+    const unsigned tyi = t / tg.ntx, txi = t - tyi * tg.ntx;
+    const int nx = (int)L.nx, ny = (int)L.ny;
+    const int x0 = (int)(txi * tg.tx), y0 = (int)(tyi * tg.ty);
+    const int TX = min(x0 + (int)tg.tx, nx) - x0, TY = min(y0 + (int)tg.ty, ny) - y0;
+    const int HX = TX + 2, HY = TY + 2, HN = HX * HY;
+    const size_t off = rhs * ld;
+    const size_t pc = (size_t)y0 * nx + x0;
+    const Cx<T> *ui = u0 + off;
+    int tslot = -1;
+    const Cx<T> *tsrc;
+    {
+        const int q = threadIdx.x;
+        const bool xs = q < 3 * TX;
+        const int qq = xs ? q : min(q - 3 * TX, 3 * TY - 1);
+        const int c = qq / 3, a = qq - 3 * c;
+        tsrc = (xs ? L.tab[0] + a * nx + x0 : L.tab[1] + a * ny + y0) + c;
+        if (q < 3 * TX + 3 * TY) tslot = (xs ? a : 3 + a) * TAB_MAXD + c;
+    }
+    const T tre = tsrc->re, tim = tsrc->im;
+    T phq[TILE_MAXE];
+    size_t pq[TILE_MAXE];
+#pragma unroll
+    for (int b0 = 0; b0 < TILE_MAXE; b0 += TILE_PB) {
+        if (b0 * BLK >= HN) break;   // the same for every thread of the block
+        Cx<T> v[TILE_PB];
+        bool ok[TILE_PB];
+#pragma unroll
+        for (int i = 0; i < TILE_PB; ++i) {
+            const int it = b0 + i;
+            if (it >= TILE_MAXE) break;
+            const int e = threadIdx.x + it * BLK;
+            const int ey = e / HX, ex = e - ey * HX;
+            const int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
+            ok[i] = e < HN && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+            pq[it] = ok[i] ? (size_t)gy * nx + gx : pc;
+            v[i] = ui[pq[it]];
+            phq[it] = L.phi[pq[it]];
+        }
+#pragma unroll
+        for (int i = 0; i < TILE_PB; ++i) {
+            const int it = b0 + i;
+            if (it >= TILE_MAXE) break;
+            const int e = threadIdx.x + it * BLK;
+            if (e < HN) lu[e] = ok[i] ? v[i] : mkc<T>(0, 0);
+        }
+    }
+    if (tslot >= 0) ltab[tslot] = mkc<T>(tre, tim);
+    if (!act) return;
+    __syncthreads();
+    zc acc[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) acc[q] = mkc(0.0, 0.0);
+#pragma unroll
+    for (int it = 0; it < TILE_MAXE; ++it) {
+        if (it * BLK >= HN) break;   // the same for every thread of the block
+        const int e = threadIdx.x + it * BLK;
+        const int ey = e / HX, ex = e - ey * HX;
+        if (e >= HN || ex < 1 || ex > HX - 2 || ey < 1 || ey > HY - 2) continue;
+        const int c = ex - 1, r = ey - 1;
+        const Cx<T> uc = lu[e];
+        Cx<T> d = ltab[1 * TAB_MAXD + c] + ltab[4 * TAB_MAXD + r];
+        d.re -= phq[it];
+        Cx<T> a = d * uc;
+        a = cfma(ltab[0 * TAB_MAXD + c], lu[e - 1], a);
+        a = cfma(ltab[2 * TAB_MAXD + c], lu[e + 1], a);
+        a = cfma(ltab[3 * TAB_MAXD + r], lu[e - HX], a);
+        a = cfma(ltab[5 * TAB_MAXD + r], lu[e + HX], a);
+        w[off + pq[it]] = a;
+        const zc wd = cvt<double>(a), ud = cvt<double>(uc);
+        acc[0] = cjfma(ud, wd, acc[0]);
+        acc[1].re += cabs2(ud);
+        if (NA > 2) acc[NA - 1].re += cabs2(wd);
+    }
+    block_sum<NA>(acc, NA, sh, res);
+    if (threadIdx.x < NA) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + t] = res[threadIdx.x];
+}
+
 // Up-path pass on one 2-D tile (see launch_up_tile).  Phase 1: x = xin + P ec
 // on the tile and a two-point halo into shared memory (zero outside the level;
 // the tile's own points also to xout).  Phase 2: r = b - A x on the tile and a
@@ -1682,7 +1776,11 @@ __device__ __forceinline__ void coefs_to_T(int k, const zc *ax, const zc *ar, Cx
     }
 }
 
-// x (+)= sum_i y_i sig_i u_i
+// x (+)= sum_i y_i sig_i u_i.  For s <= 3 the loads of the closing prologue
+// go first, then those of the thread's first TILE_PB points (every basis
+// vector the update can use, u_0..u_{s-1}, and x), then the mask test, so
+// that the least squares overlaps the first batch's memory latency; later
+// batches issue all their loads together.
 template <typename T, int SB>
 __global__ __launch_bounds__(BLK) void k_upd(Cx<T> *x, int accumulate, Basis<T> B, int s, unsigned N, size_t ld,
                                              const zc *__restrict__ pin, int nbin, GState *gsb, double tiny,
@@ -1692,13 +1790,56 @@ __global__ __launch_bounds__(BLK) void k_upd(Cx<T> *x, int accumulate, Basis<T> 
     __shared__ zc res[SB + 1];
     __shared__ zc ax[CSG_MAX_S], ar[CSG_MAX_S + 1];
     const int rhs = blockIdx.y;
-    if (!active[rhs]) return;
-    const int k = close_sweep<T, SB>(pin + (size_t)rhs * NVAL * NBMAX, nbin, gsb + rhs, s, tiny, sh, res, ax, ar);
-    Cx<T> cx[SB], cr[SB];
-    coefs_to_T<T, SB>(k, ax, ar, cx, cr);
-    const unsigned c = chunk_id(nb);
-    const unsigned p0 = c * chunk, p1 = min(N, p0 + chunk);
-    body_upd<T, SB>(x + rhs * ld, accumulate, B, k, cx, rhs * ld, p0 + threadIdx.x, p1, BLK);
+    if constexpr (SB <= 4) {
+        constexpr int PB = TILE_PB;
+        const int act = active[rhs];
+        CloseLoads<SB> cls;
+        close_begin<T, SB>(pin + (size_t)rhs * NVAL * NBMAX, nbin, gsb + rhs, s, cls);
+        const unsigned c = chunk_id(nb);
+        const unsigned p0 = c * chunk, p1 = min(N, p0 + chunk);
+        const size_t off = rhs * ld;
+        Cx<T> *xr = x + off;
+        Cx<T> u[PB][SB - 1], xv[PB];
+        auto load = [&](unsigned p) {
+#pragma unroll
+            for (int i = 0; i < PB; ++i) {
+                const unsigned pk = min(p + i * BLK, N - 1);
+#pragma unroll
+                for (int q = 0; q < SB - 1; ++q)
+                    if (q < s) u[i][q] = B.u[q][off + pk];
+                xv[i] = mkc<T>(0, 0);
+            }
+            if (accumulate) {
+#pragma unroll
+                for (int i = 0; i < PB; ++i) xv[i] = xr[min(p + i * BLK, N - 1)];
+            }
+        };
+        const unsigned pt = p0 + threadIdx.x;
+        load(pt);
+        if (!act) return;
+        const int k = close_end<T, SB>(cls, gsb + rhs, s, tiny, sh, res, ax, ar);
+        Cx<T> cx[SB], cr[SB];
+        coefs_to_T<T, SB>(k, ax, ar, cx, cr);
+        for (unsigned p = pt; p < p1; p += PB * BLK) {
+            if (p != pt) load(p);
+#pragma unroll
+            for (int i = 0; i < PB; ++i) {
+                Cx<T> v = xv[i];
+#pragma unroll
+                for (int q = 0; q < SB - 1; ++q)
+                    if (q < k) v = cfma(cx[q], u[i][q], v);
+                if (p + i * BLK < p1) xr[p + i * BLK] = v;
+            }
+        }
+    } else {
+        if (!active[rhs]) return;
+        const int k = close_sweep<T, SB>(pin + (size_t)rhs * NVAL * NBMAX, nbin, gsb + rhs, s, tiny, sh, res, ax, ar);
+        Cx<T> cx[SB], cr[SB];
+        coefs_to_T<T, SB>(k, ax, ar, cx, cr);
+        const unsigned c = chunk_id(nb);
+        const unsigned p0 = c * chunk, p1 = min(N, p0 + chunk);
+        body_upd<T, SB>(x + rhs * ld, accumulate, B, k, cx, rhs * ld, p0 + threadIdx.x, p1, BLK);
+    }
 }
 
 template <typename T, int DIM, int SB>
@@ -3132,6 +3273,19 @@ void launch_os_tile(const LvlK<T> &L, const Basis<T> &B, const Cx<T> *win, Cx<T>
 }
 
 template <typename T>
+void launch_st0_tile(const LvlK<T> &L, const Cx<T> *u0, Cx<T> *w, size_t ld, bool wnorm, zc *pout, const TileGeo &tg,
+                     int nrhs, hipStream_t st, const int *active)
+{
+    const int ntile = (int)(tg.ntx * tg.nty);
+    if (wnorm)
+        hipLaunchKernelGGL((k_st0_tile<T, 3>), dim3(ntile, nrhs), dim3(BLK), 0, st, L, u0, w, ld, pout, tg, ntile,
+                           active);
+    else
+        hipLaunchKernelGGL((k_st0_tile<T, 2>), dim3(ntile, nrhs), dim3(BLK), 0, st, L, u0, w, ld, pout, tg, ntile,
+                           active);
+}
+
+template <typename T>
 void launch_down_tile(Cx<T> *x, int accumulate, const Basis<T> &B, int s, const LvlK<T> &F, const LvlK<T> &C,
                       Cx<T> *bc, Cx<T> *wc, size_t ldf, size_t ldc, const zc *pin, int nbin, GState *gs,
                       double tiny, bool st0, bool wnorm, zc *pout, const TileGeo &tc, int nrhs, hipStream_t st,
@@ -3404,6 +3558,8 @@ INST_TD(float, 2)
 INST_TD(float, 3)
 
 #define INST_T(T)                                                                                                  \
+    template void launch_st0_tile<T>(const LvlK<T> &, const Cx<T> *, Cx<T> *, size_t, bool, zc *, const TileGeo &,  \
+                                     int, hipStream_t, const int *);                                               \
     template void launch_down_tile<T>(Cx<T> *, int, const Basis<T> &, int, const LvlK<T> &, const LvlK<T> &,       \
                                       Cx<T> *, Cx<T> *, size_t, size_t, const zc *, int, GState *, double, bool,   \
                                       bool, zc *, const TileGeo &, int, hipStream_t, const int *);                 \
