@@ -154,7 +154,16 @@ __device__ __forceinline__ void reduce_parts(const zc *part, int nb, int nv, zc 
 // Complex Givens rotation [c s; -conj(s) c] (c real) taking (a, b) to (r, 0).
 __device__ __forceinline__ void rot(zc a, zc b, double &c, zc &s)
 {
-    const double aa = sqrt(cabs2(a)), bb = sqrt(cabs2(b));
+    const double a2 = cabs2(a), b2 = cabs2(b), n2 = a2 + b2;
+    if (n2 > 1e-280 && n2 < 1e280 && a2 > 0.0) {
+        // c = |a| / nu, s = (a / |a|) conj(b) / nu with nu = sqrt(|a|^2 + |b|^2):
+        // one division on the dependent chain (squares far from under/overflow)
+        const double inv = 1.0 / (sqrt(a2) * sqrt(n2));
+        c = a2 * inv;
+        s = inv * (a * mkc(b.re, -b.im));
+        return;
+    }
+    const double aa = sqrt(a2), bb = sqrt(b2);
     if (bb == 0.0) { c = 1.0; s = mkc(0.0, 0.0); return; }
     if (aa == 0.0) { c = 0.0; s = mkc(b.re / bb, -b.im / bb); return; }
     const double nu = hypot(aa, bb);
