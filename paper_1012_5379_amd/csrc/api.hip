@@ -299,6 +299,15 @@ bool up_tiled(const csg_operator *op, int l)
     return tiled<T, DIM>(op, l) && op->up_tiles && up_fits(op->lev[l].tile);
 }
 
+// Whether level l's (l >= 1) last post-sweep closing update is applied by
+// level l-1's up-path pass instead of a pass of its own.
+template <typename T, int DIM>
+bool fuse_up(const csg_operator *op, int l)
+{
+    return l >= 1 && op->fuse_upd && op->p.s <= 3 && op->p.nu1 > 0 && up_tiled<T, DIM>(op, l - 1) &&
+           upc_fits(op->lev[l - 1].tile);
+}
+
 // `first` > 0: pass 0 already ran (fused into the up-path pass), leaving
 // `first` partials in part[0].
 template <typename T, int DIM>
@@ -481,6 +490,11 @@ void vcycle_impl(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, h
         launch_tail<T, DIM>((const TLev<T> *)op->tlev, lt, L, bt, xt, (const Cx<T> *)op->minvT, op->nc, op->p.s, nu1,
                             nu2, tiny_of<T>(), nrhs, op->tail_lds, st, active);
     }
+    // A level's post-sweep closing update is deferred to the next finer
+    // level's up-path pass when that pass is tiled (fuse_up): x_c then exists
+    // only on the tiles' coarse windows.
+    UpClose<T> pend{};
+    bool have_pend = false;
     for (int l = lt - 1; l >= 0; --l) {
         const DevLevel &lv = op->lev[l];
         const DevLevel &cl = op->lev[l + 1];
@@ -495,12 +509,14 @@ void vcycle_impl(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, h
             const bool ut = up_tiled<T, DIM>(op, l) && xi != xo;
             const int ntile = (int)(lv.tile.ntx * lv.tile.nty);
             if (ut) {
-                // interpolated correction, residual and the post-sweep's pass 0 per tile
+                // interpolated correction (after the coarse level's deferred
+                // closing update), residual and the post-sweep's pass 0 per tile
+                const Bytes by = bytes_of(op, nrhs);
                 ProfScope ps(op, l == 0 ? CSG_PROF_PROLONG_RESID : -1, st,
-                             bytes_of(op, nrhs).up(xi != nullptr, lv.N, cl.N));
+                             by.up(xi != nullptr, lv.N, cl.N) + (have_pend ? by.upd(op->p.s, true, cl.N) : 0.0));
                 launch_up_tile<T>(lvl<T>(op, l), lvl<T>(op, l + 1), (const Cx<T> *)cl.xb, xi, xo, b,
                                   (Cx<T> *)lv.r, (Cx<T> *)lv.w[0], lv.ld, cl.ld, sizeof(T) == 8 && op->p.s == 1,
-                                  lv.part[0], lv.tile, nrhs, st, active);
+                                  lv.part[0], lv.tile, nrhs, st, active, have_pend ? &pend : nullptr);
             } else {
                 // interpolated correction, then the residual that opens the post-sweep
                 const Bytes by = bytes_of(op, nrhs);
@@ -510,6 +526,7 @@ void vcycle_impl(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, h
                                        g, active);
                 launch_resid<T, DIM>(lvl<T>(op, l), xo, b, (Cx<T> *)lv.r, lv.ld, g, active);
             }
+            have_pend = false;
             for (int k = 0; k < nu2; ++k) {
                 // the first post-sweep starts from the residual already in lv.r
                 const DevLevel &d = op->lev[l];
@@ -522,6 +539,11 @@ void vcycle_impl(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, h
                 B.u[0] = (Cx<T> *)d.r;
                 const int nclose = arnoldi_passes<T, DIM>(op, l, B, nrhs, st, active, ut && k == 0 ? ntile : 0);
                 B = closing_basis<T>(op, l, B);
+                if (k + 1 == nu2 && fuse_up<T, DIM>(op, l)) {
+                    pend = UpClose<T>{B, xo, close_part<T, DIM>(op, l), nclose, d.gs, s, tiny};
+                    have_pend = true;
+                    continue;
+                }
                 ProfScope ps(op, l == 0 ? CSG_PROF_UPDATE : -1, st, bytes_of(op, nrhs).upd(s, true, d.N));
                 launch_upd<T>(xo, 1, B, s, d.N, d.ld, close_part<T, DIM>(op, l), nclose, d.gs, tiny, g, active);
             }
@@ -966,6 +988,8 @@ int csg_operator_create(const csg_params *p, const double *phi_host, void *ws_de
         if (const char *e = getenv("CSG_UP_TILES")) op->up_tiles = atoi(e) != 0;
         op->down_tiles = true;
         if (const char *e = getenv("CSG_DOWN_TILES")) op->down_tiles = atoi(e) != 0;
+        op->fuse_upd = true;
+        if (const char *e = getenv("CSG_FUSE_UPD")) op->fuse_upd = atoi(e) != 0;
         op->lt = op->L - 1;
         for (int l = 0; l < op->L; ++l)
             if ((long)op->lev[l].N <= tail_max) { op->lt = l; break; }

@@ -121,6 +121,11 @@ inline bool tile_fits(const TileGeo &t)
 // stages the tile with a two-point halo.
 constexpr int UP_MAXE = 11;                   // two-point-halo tile points per thread
 constexpr int UP_MAXN = UP_MAXE * BLK;
+// Coarse window of an up-path pass that applies the coarse closing update:
+// at most UPC_E points per thread.
+constexpr int UPC_E = 4;
+constexpr int UPC_MAXN = UPC_E * BLK;
+inline bool upc_fits(const TileGeo &t) { return (t.tx / 2 + 4) * (t.ty / 2 + 4) <= (unsigned)UPC_MAXN; }
 inline bool up_fits(const TileGeo &t)
 {
     return tile_fits(t) && (t.tx + 4) * (t.ty + 4) <= (unsigned)UP_MAXN && t.tx + 2 <= (unsigned)TAB_MAXD &&
@@ -190,6 +195,7 @@ struct csg_operator {
     bool tiles;                       // 2-D levels whose tiles fit use the LDS-staged fused pass
     bool up_tiles;                    // ... and the LDS-staged interpolation + residual + pass 0
     bool down_tiles;                  // ... and the LDS-staged closing + restriction + next pass 0
+    bool fuse_upd;                    // coarse post-sweep updates applied by the finer up-path pass
     // outer FGMRES storage
     csg::zc *V;                       // (m+1) x max_rhs x ld0
     void *Z;                          // m x max_rhs x ld0, cycle precision

@@ -71,10 +71,25 @@ void launch_os_tile(const LvlK<T> &L, const Basis<T> &B, const Cx<T> *win, Cx<T>
 // xout), r = b - A xout, w = A r with <r, w>, ||r||^2 (and ||w||^2 when
 // wnorm) per tile into pout.  Same outputs as launch_prolong, launch_resid and
 // launch_st0 in turn, partials by tile.
+// With fuse: ec is not read; the pass first applies the coarse level's
+// post-sweep closing update (x_c = fuse->xb + sum_{i<k} cx_i u_i, s <= 3) on
+// the coarse nodes its interpolation reads, so that update needs no pass of
+// its own and x_c is never stored.
+template <typename T>
+struct UpClose {
+    Basis<T> B;        // the coarse sweep's closing basis
+    const Cx<T> *xb;   // coarse x before the update
+    const zc *pin;     // partials of the coarse sweep's last pass
+    int nbin;
+    GState *gs;        // the coarse sweep's state [rhs]
+    int s;
+    double tiny;
+};
 template <typename T>
 void launch_up_tile(const LvlK<T> &F, const LvlK<T> &C, const Cx<T> *ec, const Cx<T> *xin, Cx<T> *xout,
                     const Cx<T> *b, Cx<T> *r, Cx<T> *w, size_t ldf, size_t ldc, bool wnorm, zc *pout,
-                    const TileGeo &tg, int nrhs, hipStream_t st, const int *active);
+                    const TileGeo &tg, int nrhs, hipStream_t st, const int *active,
+                    const UpClose<T> *fuse = nullptr);
 
 // Pass 0 of a sweep on 2-D tiles: w = A u0 with <u0, w>, ||u0||^2 (and
 // ||w||^2 when wnorm) per tile into pout; same outputs as launch_st0,

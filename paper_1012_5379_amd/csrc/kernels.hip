@@ -570,16 +570,20 @@ struct PLoads2 {
     Cx<T> e[4];
     float w[4];
 };
+// Coarse node (I, J) is read at ec[(J - oy) * ld + I - ox]: the whole coarse
+// level (ox = oy = 0, ld = ncx) or a staged window of it.
 template <typename T>
 __device__ __forceinline__ void prolong_load2(const Cx<T> *__restrict__ ec, unsigned i, unsigned j, unsigned ncx,
-                                              unsigned ncy, PLoads2<T> &pl)
+                                              unsigned ncy, PLoads2<T> &pl, unsigned ox = 0, unsigned oy = 0,
+                                              unsigned ld = 0)
 {
     const PAx ax = paxis(i, ncx), ay = paxis(j, ncy);
+    if (ld == 0) ld = ncx;
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
-            pl.e[2 * b + a] = ec[ay.idx[b] * ncx + ax.idx[a]];
+            pl.e[2 * b + a] = ec[(ay.idx[b] - oy) * ld + ax.idx[a] - ox];
             pl.w[2 * b + a] = ax.w[a] * ay.w[b];
         }
 }
@@ -1232,184 +1236,6 @@ __global__ __launch_bounds__(BLK) void k_st0_tile(LvlK<T> L, const Cx<T> *__rest
     if (threadIdx.x < NA) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + t] = res[threadIdx.x];
 }
 
-// Up-path pass on one 2-D tile (see launch_up_tile).  Phase 1: x = xin + P ec
-// on the tile and a two-point halo into shared memory (zero outside the level;
-// the tile's own points also to xout).  Phase 2: r = b - A x on the tile and a
-// one-point halo, held in registers (the tile's points also to r), then moved
-// into the shared buffer once every thread is done reading x.  Phase 3: w_0 =
-// A r on the tile with <r, w_0>, ||r||^2 and (NA = 3) ||w_0||^2.  A thread owns
-// the same points in phases 2 and 3 (phi loaded once).  The stencil tables of
-// the tile's columns and rows are staged in shared memory, and b and phi of
-// the first TILE_PB points of phase 2 are loaded with phase 1's first batch;
-// every phase goes in batches of TILE_PB points per thread whose loads are
-// issued together (absent points clamped to the tile's corner).
-template <typename T, int NA>
-__global__ __launch_bounds__(BLK) void k_up_tile(LvlK<T> F, LvlK<T> C, const Cx<T> *__restrict__ ec,
-                                                 const Cx<T> *__restrict__ xin, Cx<T> *__restrict__ xout,
-                                                 const Cx<T> *__restrict__ b, Cx<T> *__restrict__ r,
-                                                 Cx<T> *__restrict__ w, size_t ldf, size_t ldc,
-                                                 zc *__restrict__ pout, TileGeo tg, int ntile, const int *active)
-{
-    __shared__ zc sh[(BLK / 64) * NA];
-    __shared__ zc res[NA];
-    __shared__ Cx<T> lx[UP_MAXN];
-    __shared__ Cx<T> ltab[6 * TAB_MAXD];   // x lower, diag, upper; y lower, diag, upper
-    const int rhs = blockIdx.y;
-    const int act = active[rhs];   // tested before the first store (reads below are harmless)
-    const unsigned t = chunk_id(ntile);
-    const unsigned tyi = t / tg.ntx, txi = t - tyi * tg.ntx;
-    const int nx = (int)F.nx, ny = (int)F.ny;
-    const int x0 = (int)(txi * tg.tx), y0 = (int)(tyi * tg.ty);
-    const int TX = min(x0 + (int)tg.tx, nx) - x0, TY = min(y0 + (int)tg.ty, ny) - y0;
-    const int AX = TX + 4, AN = AX * (TY + 4);   // x: tile and two-point halo
-    const int RX = TX + 2, RN = RX * (TY + 2);   // r: tile and one-point halo
-    const size_t off = rhs * ldf;
-    const size_t pc = (size_t)y0 * nx + x0;      // a point of the level every clamped address goes to
-    const Cx<T> *e = ec + rhs * ldc;
-    const Cx<T> *xi = xin ? xin + off : nullptr;
-    // stencil tables of the columns x0-1 .. x0+TX and rows y0-1 .. y0+TY (zero
-    // outside the level), one entry per thread, stored before phase 1's barrier
-    T tre, tim;
-    bool tzero;
-    int tslot = -1;
-    {
-        const int q = threadIdx.x;
-        const bool xs = q < 3 * RX;
-        const int qq = xs ? q : min(q - 3 * RX, 3 * (TY + 2) - 1);
-        const int c = qq / 3, a = qq - 3 * c;
-        const int g = (xs ? x0 : y0) - 1 + c, n = xs ? nx : ny;
-        const Cx<T> *tab = xs ? F.tab[0] : F.tab[1];
-        const Cx<T> *tp = tab + a * n + min(max(g, 0), n - 1);
-        tre = tp->re;
-        tim = tp->im;
-        tzero = g < 0 || g >= n;
-        if (q < 3 * RX + 3 * (TY + 2)) tslot = (xs ? a : 3 + a) * TAB_MAXD + c;
-    }
-    // phase-2 point q (tile and one-point halo): its index (clamped when absent), whether present
-    auto locate2 = [&](int q, size_t &p) {
-        const int qy = q / RX, qx = q - qy * RX;
-        const int gx = x0 - 1 + qx, gy = y0 - 1 + qy;
-        const bool ok = q < RN && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-        p = ok ? (size_t)gy * nx + gx : pc;
-        return ok;
-    };
-    Cx<T> bq[TILE_MAXE];
-    T phq[TILE_MAXE];
-    size_t pq[TILE_MAXE];
-    bool okq[TILE_MAXE];
-#pragma unroll
-    for (int it = 0; it < TILE_PB; ++it) {
-        okq[it] = locate2(threadIdx.x + it * BLK, pq[it]);
-        bq[it] = b[off + pq[it]];
-        phq[it] = F.phi[pq[it]];
-    }
-#pragma unroll
-    for (int b0 = 0; b0 < UP_MAXE; b0 += TILE_PB) {
-        if (b0 * BLK >= AN) break;   // the same for every thread of the block
-        PLoads2<T> pl[TILE_PB];
-        Cx<T> xl[TILE_PB];
-        size_t pp[TILE_PB];
-        bool ok[TILE_PB], own[TILE_PB];
-#pragma unroll
-        for (int i = 0; i < TILE_PB; ++i) {
-            if (b0 + i >= UP_MAXE) break;
-            const int q = threadIdx.x + (b0 + i) * BLK;
-            const int qy = q / AX, qx = q - qy * AX;
-            int gx = x0 - 2 + qx, gy = y0 - 2 + qy;
-            ok[i] = q < AN && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-            own[i] = ok[i] && qx >= 2 && qx < TX + 2 && qy >= 2 && qy < TY + 2;
-            if (!ok[i]) gx = x0, gy = y0;
-            pp[i] = (size_t)gy * nx + gx;
-            prolong_load2<T>(e, gx, gy, C.nx, C.ny, pl[i]);
-        }
-        if (xi) {
-#pragma unroll
-            for (int i = 0; i < TILE_PB; ++i)
-                if (b0 + i < UP_MAXE) xl[i] = xi[pp[i]];
-        }
-        if (b0 == 0 && !act) return;
-#pragma unroll
-        for (int i = 0; i < TILE_PB; ++i) {
-            if (b0 + i >= UP_MAXE) break;
-            const int q = threadIdx.x + (b0 + i) * BLK;
-            Cx<T> v = prolong_sum2<T>(pl[i]);
-            if (xi) v = v + xl[i];
-            if (own[i]) xout[off + pp[i]] = v;
-            if (q < AN) lx[q] = ok[i] ? v : mkc<T>(0, 0);
-        }
-    }
-    asm volatile("" ::: "memory");   // the table store stays after phase 1's loads
-    if (tslot >= 0) ltab[tslot] = tzero ? mkc<T>(0, 0) : mkc<T>(tre, tim);
-    __syncthreads();
-    Cx<T> rq[TILE_MAXE];
-#pragma unroll
-    for (int b0 = 0; b0 < TILE_MAXE; b0 += TILE_PB) {
-        if (b0 * BLK >= RN) break;
-        if (b0 > 0) {
-#pragma unroll
-            for (int i = 0; i < TILE_PB; ++i) {
-                const int it = b0 + i;
-                if (it >= TILE_MAXE) break;
-                okq[it] = locate2(threadIdx.x + it * BLK, pq[it]);
-                bq[it] = b[off + pq[it]];
-                phq[it] = F.phi[pq[it]];
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < TILE_PB; ++i) {
-            const int it = b0 + i;
-            if (it >= TILE_MAXE) break;
-            const int q = threadIdx.x + it * BLK;
-            const int qy = q / RX, qx = q - qy * RX;
-            const bool ok = okq[it];
-            const int a = ok ? (qy + 1) * AX + qx + 1 : 2 * AX + 2;
-            const int c = ok ? qx : 1, rr = ok ? qy : 1;
-            Cx<T> d = ltab[1 * TAB_MAXD + c] + ltab[4 * TAB_MAXD + rr];
-            d.re -= phq[it];
-            Cx<T> ax = d * lx[a];
-            ax = cfma(ltab[0 * TAB_MAXD + c], lx[a - 1], ax);
-            ax = cfma(ltab[2 * TAB_MAXD + c], lx[a + 1], ax);
-            ax = cfma(ltab[3 * TAB_MAXD + rr], lx[a - AX], ax);
-            ax = cfma(ltab[5 * TAB_MAXD + rr], lx[a + AX], ax);
-            const Cx<T> v = bq[it] - ax;
-            if (ok && qx >= 1 && qx <= TX && qy >= 1 && qy <= TY) r[off + pq[it]] = v;
-            rq[it] = ok ? v : mkc<T>(0, 0);
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < TILE_MAXE; ++it) {
-        const int q = threadIdx.x + it * BLK;
-        if (q >= RN) break;
-        lx[q] = rq[it];
-    }
-    __syncthreads();
-    zc acc[NA];
-#pragma unroll
-    for (int q = 0; q < NA; ++q) acc[q] = mkc(0.0, 0.0);
-#pragma unroll
-    for (int it = 0; it < TILE_MAXE; ++it) {
-        if (it * BLK >= RN) break;   // the same for every thread of the block
-        const int q = threadIdx.x + it * BLK;
-        const int qy = q / RX, qx = q - qy * RX;
-        if (q >= RN || qx < 1 || qx > TX || qy < 1 || qy > TY) continue;
-        const Cx<T> uc = rq[it];
-        Cx<T> d = ltab[1 * TAB_MAXD + qx] + ltab[4 * TAB_MAXD + qy];
-        d.re -= phq[it];
-        Cx<T> a = d * uc;
-        a = cfma(ltab[0 * TAB_MAXD + qx], lx[q - 1], a);
-        a = cfma(ltab[2 * TAB_MAXD + qx], lx[q + 1], a);
-        a = cfma(ltab[3 * TAB_MAXD + qy], lx[q - RX], a);
-        a = cfma(ltab[5 * TAB_MAXD + qy], lx[q + RX], a);
-        w[off + pq[it]] = a;
-        const zc wd = cvt<double>(a), ud = cvt<double>(uc);
-        acc[0] = cjfma(ud, wd, acc[0]);
-        acc[1].re += cabs2(ud);
-        if (NA > 2) acc[NA - 1].re += cabs2(wd);
-    }
-    block_sum<NA>(acc, NA, sh, res);
-    if (threadIdx.x < NA) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + t] = res[threadIdx.x];
-}
 
 // last pass: u_s and ||u_s||^2
 template <typename T, int SB>
@@ -1869,6 +1695,234 @@ __global__ __launch_bounds__(BLK) void k_upd_res(Cx<T> *x, int accumulate, Basis
     const unsigned p0 = c * chunk, p1 = min(C.N, p0 + chunk);
     body_upd_res<T, DIM, SB>(x + rhs * ldf, accumulate, B, k, cx, cr, F, C, bc + rhs * ldc, rhs * ldf, p0 + threadIdx.x,
                          p1, BLK);
+}
+
+// Up-path pass on one 2-D tile (see launch_up_tile).  Phase 1: x = xin + P ec
+// on the tile and a two-point halo into shared memory (zero outside the level;
+// the tile's own points also to xout).  Phase 2: r = b - A x on the tile and a
+// one-point halo, held in registers (the tile's points also to r), then moved
+// into the shared buffer once every thread is done reading x.  Phase 3: w_0 =
+// A r on the tile with <r, w_0>, ||r||^2 and (NA = 3) ||w_0||^2.  A thread owns
+// the same points in phases 2 and 3 (phi loaded once).  The stencil tables of
+// the tile's columns and rows are staged in shared memory, and b and phi of
+// the first TILE_PB points of phase 2 are loaded with phase 1's first batch;
+// every phase goes in batches of TILE_PB points per thread whose loads are
+// issued together (absent points clamped to the tile's corner).
+template <typename T, int NA, bool FU>
+__global__ __launch_bounds__(BLK) void k_up_tile(LvlK<T> F, LvlK<T> C, const Cx<T> *__restrict__ ec,
+                                                 const Cx<T> *__restrict__ xin, Cx<T> *__restrict__ xout,
+                                                 const Cx<T> *__restrict__ b, Cx<T> *__restrict__ r,
+                                                 Cx<T> *__restrict__ w, size_t ldf, size_t ldc,
+                                                 zc *__restrict__ pout, TileGeo tg, int ntile, UpClose<T> uc,
+                                                 const int *active)
+{
+    constexpr int SB = 4;
+    __shared__ zc sh[(BLK / 64) * (NA > SB + 1 ? NA : SB + 1)];
+    __shared__ zc res[SB + 1];
+    __shared__ Cx<T> lx[UP_MAXN];
+    __shared__ Cx<T> ltab[6 * TAB_MAXD];   // x lower, diag, upper; y lower, diag, upper
+    __shared__ Cx<T> lc[FU ? UPC_MAXN : 1];   // the coarse correction on the tile's coarse window
+    __shared__ zc axc[CSG_MAX_S], arc[CSG_MAX_S + 1];
+    const int rhs = blockIdx.y;
+    const int act = active[rhs];   // tested before the first store (reads below are harmless)
+    const unsigned t = chunk_id(ntile);
+    const unsigned tyi = t / tg.ntx, txi = t - tyi * tg.ntx;
+    const int nx = (int)F.nx, ny = (int)F.ny;
+    const int x0 = (int)(txi * tg.tx), y0 = (int)(tyi * tg.ty);
+    const int TX = min(x0 + (int)tg.tx, nx) - x0, TY = min(y0 + (int)tg.ty, ny) - y0;
+    const int AX = TX + 4, AN = AX * (TY + 4);   // x: tile and two-point halo
+    const int RX = TX + 2, RN = RX * (TY + 2);   // r: tile and one-point halo
+    const size_t off = rhs * ldf;
+    const size_t pc = (size_t)y0 * nx + x0;      // a point of the level every clamped address goes to
+    const Cx<T> *e = ec + rhs * ldc;
+    const Cx<T> *xi = xin ? xin + off : nullptr;
+    // stencil tables of the columns x0-1 .. x0+TX and rows y0-1 .. y0+TY (zero
+    // outside the level), one entry per thread, stored before phase 1's barrier
+    T tre, tim;
+    bool tzero;
+    int tslot = -1;
+    {
+        const int q = threadIdx.x;
+        const bool xs = q < 3 * RX;
+        const int qq = xs ? q : min(q - 3 * RX, 3 * (TY + 2) - 1);
+        const int c = qq / 3, a = qq - 3 * c;
+        const int g = (xs ? x0 : y0) - 1 + c, n = xs ? nx : ny;
+        const Cx<T> *tab = xs ? F.tab[0] : F.tab[1];
+        const Cx<T> *tp = tab + a * n + min(max(g, 0), n - 1);
+        tre = tp->re;
+        tim = tp->im;
+        tzero = g < 0 || g >= n;
+        if (q < 3 * RX + 3 * (TY + 2)) tslot = (xs ? a : 3 + a) * TAB_MAXD + c;
+    }
+    // phase-2 point q (tile and one-point halo): its index (clamped when absent), whether present
+    auto locate2 = [&](int q, size_t &p) {
+        const int qy = q / RX, qx = q - qy * RX;
+        const int gx = x0 - 1 + qx, gy = y0 - 1 + qy;
+        const bool ok = q < RN && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        p = ok ? (size_t)gy * nx + gx : pc;
+        return ok;
+    };
+    // FU: the coarse sweep's closing update x_c + sum_{i<k} cx_i u_i, formed on
+    // the coarse nodes the tile's interpolation reads (its coarse window) and
+    // staged in shared memory; its prologue loads go first
+    CloseLoads<SB> cls;
+    unsigned cx0 = 0, cy0 = 0, CX = 1;
+    int CN = 0;
+    Cx<T> xbq[UPC_E], ucq[UPC_E][SB - 1];
+    if constexpr (FU) {
+        close_begin<T, SB>(uc.pin + (size_t)rhs * NVAL * NBMAX, uc.nbin, uc.gs + rhs, uc.s, cls);
+        cx0 = paxis((unsigned)max(x0 - 2, 0), C.nx).idx[0];
+        cy0 = paxis((unsigned)max(y0 - 2, 0), C.ny).idx[0];
+        CX = paxis((unsigned)min(x0 + TX + 1, nx - 1), C.nx).idx[1] - cx0 + 1;
+        const unsigned CY = paxis((unsigned)min(y0 + TY + 1, ny - 1), C.ny).idx[1] - cy0 + 1;
+        CN = (int)(CX * CY);
+        const size_t offc = rhs * ldc;
+#pragma unroll
+        for (int i = 0; i < UPC_E; ++i) {
+            const int q = min((int)threadIdx.x + i * BLK, CN - 1);
+            const unsigned qy = (unsigned)q / CX, qx = (unsigned)q - qy * CX;
+            const size_t P = offc + (size_t)(cy0 + qy) * C.nx + cx0 + qx;
+            xbq[i] = uc.xb[P];
+#pragma unroll
+            for (int q2 = 0; q2 < SB - 1; ++q2)
+                if (q2 < uc.s) ucq[i][q2] = uc.B.u[q2][P];
+        }
+    }
+    Cx<T> bq[TILE_MAXE];
+    T phq[TILE_MAXE];
+    size_t pq[TILE_MAXE];
+    bool okq[TILE_MAXE];
+#pragma unroll
+    for (int it = 0; it < TILE_PB; ++it) {
+        okq[it] = locate2(threadIdx.x + it * BLK, pq[it]);
+        bq[it] = b[off + pq[it]];
+        phq[it] = F.phi[pq[it]];
+    }
+    if constexpr (FU) {
+        if (!act) return;
+        const int k = close_end<T, SB>(cls, uc.gs + rhs, uc.s, uc.tiny, sh, res, axc, arc);
+        Cx<T> cxc[SB], crc[SB];
+        coefs_to_T<T, SB>(k, axc, arc, cxc, crc);
+#pragma unroll
+        for (int i = 0; i < UPC_E; ++i) {
+            const int q = threadIdx.x + i * BLK;
+            Cx<T> v = xbq[i];
+#pragma unroll
+            for (int q2 = 0; q2 < SB - 1; ++q2)
+                if (q2 < k) v = cfma(cxc[q2], ucq[i][q2], v);
+            if (q < CN) lc[q] = v;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int b0 = 0; b0 < UP_MAXE; b0 += TILE_PB) {
+        if (b0 * BLK >= AN) break;   // the same for every thread of the block
+        PLoads2<T> pl[TILE_PB];
+        Cx<T> xl[TILE_PB];
+        size_t pp[TILE_PB];
+        bool ok[TILE_PB], own[TILE_PB];
+#pragma unroll
+        for (int i = 0; i < TILE_PB; ++i) {
+            if (b0 + i >= UP_MAXE) break;
+            const int q = threadIdx.x + (b0 + i) * BLK;
+            const int qy = q / AX, qx = q - qy * AX;
+            int gx = x0 - 2 + qx, gy = y0 - 2 + qy;
+            ok[i] = q < AN && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+            own[i] = ok[i] && qx >= 2 && qx < TX + 2 && qy >= 2 && qy < TY + 2;
+            if (!ok[i]) gx = x0, gy = y0;
+            pp[i] = (size_t)gy * nx + gx;
+            if constexpr (FU)
+                prolong_load2<T>(lc, gx, gy, C.nx, C.ny, pl[i], cx0, cy0, CX);
+            else
+                prolong_load2<T>(e, gx, gy, C.nx, C.ny, pl[i]);
+        }
+        if (xi) {
+#pragma unroll
+            for (int i = 0; i < TILE_PB; ++i)
+                if (b0 + i < UP_MAXE) xl[i] = xi[pp[i]];
+        }
+        if (b0 == 0 && !act) return;
+#pragma unroll
+        for (int i = 0; i < TILE_PB; ++i) {
+            if (b0 + i >= UP_MAXE) break;
+            const int q = threadIdx.x + (b0 + i) * BLK;
+            Cx<T> v = prolong_sum2<T>(pl[i]);
+            if (xi) v = v + xl[i];
+            if (own[i]) xout[off + pp[i]] = v;
+            if (q < AN) lx[q] = ok[i] ? v : mkc<T>(0, 0);
+        }
+    }
+    asm volatile("" ::: "memory");   // the table store stays after phase 1's loads
+    if (tslot >= 0) ltab[tslot] = tzero ? mkc<T>(0, 0) : mkc<T>(tre, tim);
+    __syncthreads();
+    Cx<T> rq[TILE_MAXE];
+#pragma unroll
+    for (int b0 = 0; b0 < TILE_MAXE; b0 += TILE_PB) {
+        if (b0 * BLK >= RN) break;
+        if (b0 > 0) {
+#pragma unroll
+            for (int i = 0; i < TILE_PB; ++i) {
+                const int it = b0 + i;
+                if (it >= TILE_MAXE) break;
+                okq[it] = locate2(threadIdx.x + it * BLK, pq[it]);
+                bq[it] = b[off + pq[it]];
+                phq[it] = F.phi[pq[it]];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < TILE_PB; ++i) {
+            const int it = b0 + i;
+            if (it >= TILE_MAXE) break;
+            const int q = threadIdx.x + it * BLK;
+            const int qy = q / RX, qx = q - qy * RX;
+            const bool ok = okq[it];
+            const int a = ok ? (qy + 1) * AX + qx + 1 : 2 * AX + 2;
+            const int c = ok ? qx : 1, rr = ok ? qy : 1;
+            Cx<T> d = ltab[1 * TAB_MAXD + c] + ltab[4 * TAB_MAXD + rr];
+            d.re -= phq[it];
+            Cx<T> ax = d * lx[a];
+            ax = cfma(ltab[0 * TAB_MAXD + c], lx[a - 1], ax);
+            ax = cfma(ltab[2 * TAB_MAXD + c], lx[a + 1], ax);
+            ax = cfma(ltab[3 * TAB_MAXD + rr], lx[a - AX], ax);
+            ax = cfma(ltab[5 * TAB_MAXD + rr], lx[a + AX], ax);
+            const Cx<T> v = bq[it] - ax;
+            if (ok && qx >= 1 && qx <= TX && qy >= 1 && qy <= TY) r[off + pq[it]] = v;
+            rq[it] = ok ? v : mkc<T>(0, 0);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < TILE_MAXE; ++it) {
+        const int q = threadIdx.x + it * BLK;
+        if (q >= RN) break;
+        lx[q] = rq[it];
+    }
+    __syncthreads();
+    zc acc[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) acc[q] = mkc(0.0, 0.0);
+#pragma unroll
+    for (int it = 0; it < TILE_MAXE; ++it) {
+        if (it * BLK >= RN) break;   // the same for every thread of the block
+        const int q = threadIdx.x + it * BLK;
+        const int qy = q / RX, qx = q - qy * RX;
+        if (q >= RN || qx < 1 || qx > TX || qy < 1 || qy > TY) continue;
+        const Cx<T> uc = rq[it];
+        Cx<T> d = ltab[1 * TAB_MAXD + qx] + ltab[4 * TAB_MAXD + qy];
+        d.re -= phq[it];
+        Cx<T> a = d * uc;
+        a = cfma(ltab[0 * TAB_MAXD + qx], lx[q - 1], a);
+        a = cfma(ltab[2 * TAB_MAXD + qx], lx[q + 1], a);
+        a = cfma(ltab[3 * TAB_MAXD + qy], lx[q - RX], a);
+        a = cfma(ltab[5 * TAB_MAXD + qy], lx[q + RX], a);
+        w[off + pq[it]] = a;
+        const zc wd = cvt<double>(a), ud = cvt<double>(uc);
+        acc[0] = cjfma(ud, wd, acc[0]);
+        acc[1].re += cabs2(ud);
+        if (NA > 2) acc[NA - 1].re += cabs2(wd);
+    }
+    block_sum<NA>(acc, NA, sh, res);
+    if (threadIdx.x < NA) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + t] = res[threadIdx.x];
 }
 
 // Down-path pass on one 2-D tile of the coarse level (see launch_down_tile).
@@ -3316,15 +3370,26 @@ void launch_down_tile(Cx<T> *x, int accumulate, const Basis<T> &B, int s, const 
 template <typename T>
 void launch_up_tile(const LvlK<T> &F, const LvlK<T> &C, const Cx<T> *ec, const Cx<T> *xin, Cx<T> *xout,
                     const Cx<T> *b, Cx<T> *r, Cx<T> *w, size_t ldf, size_t ldc, bool wnorm, zc *pout,
-                    const TileGeo &tg, int nrhs, hipStream_t st, const int *active)
+                    const TileGeo &tg, int nrhs, hipStream_t st, const int *active, const UpClose<T> *fuse)
 {
     const int ntile = (int)(tg.ntx * tg.nty);
-    if (wnorm)
-        hipLaunchKernelGGL((k_up_tile<T, 3>), dim3(ntile, nrhs), dim3(BLK), 0, st, F, C, ec, xin, xout, b, r, w, ldf,
-                           ldc, pout, tg, ntile, active);
-    else
-        hipLaunchKernelGGL((k_up_tile<T, 2>), dim3(ntile, nrhs), dim3(BLK), 0, st, F, C, ec, xin, xout, b, r, w, ldf,
-                           ldc, pout, tg, ntile, active);
+    const dim3 grd(ntile, nrhs);
+    const UpClose<T> uc = fuse ? *fuse : UpClose<T>{};
+    if (fuse) {
+        if (wnorm)
+            hipLaunchKernelGGL((k_up_tile<T, 3, true>), grd, dim3(BLK), 0, st, F, C, ec, xin, xout, b, r, w, ldf, ldc,
+                               pout, tg, ntile, uc, active);
+        else
+            hipLaunchKernelGGL((k_up_tile<T, 2, true>), grd, dim3(BLK), 0, st, F, C, ec, xin, xout, b, r, w, ldf, ldc,
+                               pout, tg, ntile, uc, active);
+    } else {
+        if (wnorm)
+            hipLaunchKernelGGL((k_up_tile<T, 3, false>), grd, dim3(BLK), 0, st, F, C, ec, xin, xout, b, r, w, ldf,
+                               ldc, pout, tg, ntile, uc, active);
+        else
+            hipLaunchKernelGGL((k_up_tile<T, 2, false>), grd, dim3(BLK), 0, st, F, C, ec, xin, xout, b, r, w, ldf,
+                               ldc, pout, tg, ntile, uc, active);
+    }
 }
 
 template <typename T>
@@ -3574,7 +3639,7 @@ INST_TD(float, 3)
                                       bool, zc *, const TileGeo &, int, hipStream_t, const int *);                 \
     template void launch_up_tile<T>(const LvlK<T> &, const LvlK<T> &, const Cx<T> *, const Cx<T> *, Cx<T> *,      \
                                     const Cx<T> *, Cx<T> *, Cx<T> *, size_t, size_t, bool, zc *, const TileGeo &,  \
-                                    int, hipStream_t, const int *);                                                \
+                                    int, hipStream_t, const int *, const UpClose<T> *);                            \
     template void launch_orthl<T>(const Basis<T> &, const Cx<T> *, int, int, unsigned, size_t, const zc *, int,    \
                                   zc *, GState *, double, const Launch &, const int *);                            \
     template void launch_upd<T>(Cx<T> *, int, const Basis<T> &, int, unsigned, size_t, const zc *, int, GState *, \
