@@ -683,27 +683,29 @@ void drop_graphs(csg_operator *op)
     gc->it.clear();
 }
 
-// Replays the captured graph of column j (capturing it on first use); eager
-// launches when graphs are disabled or a pass is being instrumented.
+// Replays the captured graph of columns j .. j+g-1 (capturing it on first use;
+// groups start at multiples of GCOLS); eager launches when graphs are disabled
+// or a pass is being instrumented.
 template <typename TZ, int DIM>
-void enqueue_iter(csg_solve *sv, int j)
+void enqueue_iters(csg_solve *sv, int j, int g)
 {
     csg_operator *op = sv->op;
     GraphCache *gc = op->gc;
     if (!gc || !gc->enabled || op->prof) {
         // eager: graphs disabled, or launches being timed (this HIP cannot time
         // events recorded inside a graph)
-        iter_body<TZ, DIM>(sv, j, sv->st);
+        for (int c = j; c < j + g; ++c) iter_body<TZ, DIM>(sv, c, sv->st);
         return;
     }
-    std::vector<hipGraphExec_t> &v = gc->it[sv->nrhs];
+    // a graph holds the columns of its group, which depend on the cycle length m
+    std::vector<hipGraphExec_t> &v = gc->it[sv->nrhs * (CSG_MAX_RESTART + 1) + sv->m];
     if ((int)v.size() < op->p.restart) v.resize(op->p.restart, nullptr);
     if (!v[j]) {
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
         bool ok = hipStreamBeginCapture(gc->cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
         if (ok) {
-            iter_body<TZ, DIM>(sv, j, gc->cap);
+            for (int c = j; c < j + g; ++c) iter_body<TZ, DIM>(sv, c, gc->cap);
             ok = hipStreamEndCapture(gc->cap, &graph) == hipSuccess && graph;
         }
         ok = ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
@@ -712,7 +714,7 @@ void enqueue_iter(csg_solve *sv, int j)
             hipGetLastError();
             drop_graphs(op);
             gc->enabled = false;   // capture unsupported here: stay eager
-            iter_body<TZ, DIM>(sv, j, sv->st);
+            for (int c = j; c < j + g; ++c) iter_body<TZ, DIM>(sv, c, sv->st);
             return;
         }
         v[j] = exec;
@@ -777,15 +779,18 @@ int solve_step(csg_solve *sv)
         sv->phase = csg_solve::WAIT_BEGIN;
         break;
     case csg_solve::CYCLE:
-        // queue columns up to LOOKAHEAD ahead of the reports read; each RHS's
-        // iteration mask is cleared by the device when it stops.  Instrumented
-        // solves queue one at a time, so that no skipped column is timed.
+        // queue groups of GCOLS columns (one graph each) up to LOOKAHEAD columns
+        // ahead of the reports read; each RHS's iteration mask is cleared by
+        // the device when it stops.  Instrumented solves queue one column at a
+        // time, so that no skipped column is timed.
         if (sv->jq == 0) upload_masks(sv);
-        while (!sv->halt && sv->jq < sv->m && sv->jq - sv->j < (op->prof ? 1 : LOOKAHEAD)) {
-            if (mixed) { if (d3) enqueue_iter<float, 3>(sv, sv->jq); else enqueue_iter<float, 2>(sv, sv->jq); }
-            else { if (d3) enqueue_iter<double, 3>(sv, sv->jq); else enqueue_iter<double, 2>(sv, sv->jq); }
-            enqueue_report(sv, sv->jq % LOOKAHEAD);
-            sv->jq++;
+        for (;;) {
+            const int g = op->prof ? 1 : std::min(GCOLS, sv->m - sv->jq);
+            if (sv->halt || sv->jq >= sv->m || sv->jq + g - sv->j > (op->prof ? 1 : LOOKAHEAD)) break;
+            if (mixed) { if (d3) enqueue_iters<float, 3>(sv, sv->jq, g); else enqueue_iters<float, 2>(sv, sv->jq, g); }
+            else { if (d3) enqueue_iters<double, 3>(sv, sv->jq, g); else enqueue_iters<double, 2>(sv, sv->jq, g); }
+            for (int c = 0; c < g; ++c) enqueue_report(sv, (sv->jq + c) % LOOKAHEAD);
+            sv->jq += g;
         }
         break;
     case csg_solve::CYCLE_END:

@@ -61,8 +61,11 @@ struct FState {
 };
 
 // Outer iterations a solve keeps queued ahead of the host's reading of their
-// reports: the device itself clears a RHS's iteration mask when it stops.
-constexpr int LOOKAHEAD = 3;
+// reports (the device itself clears a RHS's iteration mask when it stops),
+// captured GCOLS columns to a graph (fewer graph boundaries, each of which
+// costs a launch gap on the device).
+constexpr int GCOLS = 3;
+constexpr int LOOKAHEAD = 2 * GCOLS;
 
 // Host-visible per-RHS report (copied back after every outer iteration).
 struct Report {
@@ -163,7 +166,7 @@ struct DevLevel {
 // Instantiated graphs of one FGMRES iteration (V-cycle + outer passes), per
 // right-hand-side count and Arnoldi column, captured on a private stream.
 struct GraphCache {
-    std::map<int, std::vector<hipGraphExec_t>> it;
+    std::map<int, std::vector<hipGraphExec_t>> it;   // by nrhs and cycle length: graphs by first column
     hipStream_t cap = nullptr;
     bool enabled = true;
 };

@@ -1798,6 +1798,20 @@ __global__ __launch_bounds__(BLK) void k_up_tile(LvlK<T> F, LvlK<T> C, const Cx<
         bq[it] = b[off + pq[it]];
         phq[it] = F.phi[pq[it]];
     }
+    // phase 1's first batch: coordinates and x_in loads ahead of the prologue
+    size_t pp0[TILE_PB];
+    bool ok0[TILE_PB], own0[TILE_PB];
+    Cx<T> xl0[TILE_PB];
+#pragma unroll
+    for (int i = 0; i < TILE_PB; ++i) {
+        const int q = threadIdx.x + i * BLK;
+        const int qy = q / AX, qx = q - qy * AX;
+        const int gx = x0 - 2 + qx, gy = y0 - 2 + qy;
+        ok0[i] = q < AN && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        own0[i] = ok0[i] && qx >= 2 && qx < TX + 2 && qy >= 2 && qy < TY + 2;
+        pp0[i] = ok0[i] ? (size_t)gy * nx + gx : pc;
+        if (xi) xl0[i] = xi[pp0[i]];
+    }
     if constexpr (FU) {
         if (!act) return;
         const int k = close_end<T, SB>(cls, uc.gs + rhs, uc.s, uc.tiny, sh, res, axc, arc);
@@ -1827,8 +1841,13 @@ __global__ __launch_bounds__(BLK) void k_up_tile(LvlK<T> F, LvlK<T> C, const Cx<
             const int q = threadIdx.x + (b0 + i) * BLK;
             const int qy = q / AX, qx = q - qy * AX;
             int gx = x0 - 2 + qx, gy = y0 - 2 + qy;
-            ok[i] = q < AN && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-            own[i] = ok[i] && qx >= 2 && qx < TX + 2 && qy >= 2 && qy < TY + 2;
+            if (b0 == 0) {
+                ok[i] = ok0[i];
+                own[i] = own0[i];
+            } else {
+                ok[i] = q < AN && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+                own[i] = ok[i] && qx >= 2 && qx < TX + 2 && qy >= 2 && qy < TY + 2;
+            }
             if (!ok[i]) gx = x0, gy = y0;
             pp[i] = (size_t)gy * nx + gx;
             if constexpr (FU)
@@ -1839,7 +1858,7 @@ __global__ __launch_bounds__(BLK) void k_up_tile(LvlK<T> F, LvlK<T> C, const Cx<
         if (xi) {
 #pragma unroll
             for (int i = 0; i < TILE_PB; ++i)
-                if (b0 + i < UP_MAXE) xl[i] = xi[pp[i]];
+                if (b0 + i < UP_MAXE) xl[i] = b0 == 0 ? xl0[i] : xi[pp[i]];
         }
         if (b0 == 0 && !act) return;
 #pragma unroll

@@ -216,6 +216,25 @@ def test_vcycle_any_tail_split(tail_max, monkeypatch):
         assert e <= TOL64
 
 
+@pytest.mark.parametrize("knob", ["CSG_TILES", "CSG_UP_TILES", "CSG_DOWN_TILES", "CSG_FUSE_UPD", "CSG_TAIL_LDS"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_vcycle_with_each_fused_path_off(knob, prec, monkeypatch):
+    """Every fused path (tiled Arnoldi passes, tiled up and down passes, the
+    coarse closing update applied by the finer up pass, the LDS tail) and the
+    unfused passes it replaces compute the same cycle: with each one switched
+    off the cycle still matches the oracle, on a ragged 2-D case whose levels
+    take both kinds of pass."""
+    monkeypatch.setenv(knob, "0")
+    w = CASES["2d_wide"]()
+    op, orc = pair(w, max_rhs=2, cycle_prec=prec)
+    b = np.stack([rvec(orc.shape(0), 200), rvec(orc.shape(0), 201)])
+    x = host(op.vcycle(dev(b, op.cdtype)))
+    for r in range(2):
+        e = rel(x[r], orc.vcycle(b[r]))
+        note(f"  {knob}=0 prec {prec} rhs {r}: {e:.2e}")
+        assert e <= (TOL64 if prec == 0 else TOL32["vcycle"])
+
+
 def test_graph_replay_matches_eager(monkeypatch):
     """FGMRES iterations replayed from captured graphs (with eager restart and
     report work in between) give bit-identical results to eager launches."""
@@ -231,6 +250,30 @@ def test_graph_replay_matches_eager(monkeypatch):
         outs.append((host(u), [i["iterations"] for i in infos]))
     assert outs[0][1] == outs[1][1] == outs[2][1]
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][0], outs[2][0])
+
+
+def test_graphs_follow_the_cycle_length(monkeypatch):
+    """Iterations are replayed from graphs of several columns; one operator
+    solving with two cycle lengths (whose last groups differ) gives the same
+    results as eager launches of each."""
+    import torch
+    w = CASES["2d_ragged"]()
+    chi = dev(w.chi[:1], torch.complex128)
+    monkeypatch.setenv("CSG_GRAPHS", "1")
+    op, _ = pair(w, max_rhs=1, cycle_prec=0, restart=12)
+    got = {}
+    for m in (12, 10, 12, 7):
+        u, rc, infos = op.solve(chi, tol=1e-9, restart=m, maxit=400)
+        assert rc == 0
+        got.setdefault(m, []).append((host(u), infos[0]["iterations"]))
+    monkeypatch.setenv("CSG_GRAPHS", "0")
+    ref, _ = pair(w, max_rhs=1, cycle_prec=0, restart=12)
+    for m, runs in got.items():
+        u, rc, infos = ref.solve(chi, tol=1e-9, restart=m, maxit=400)
+        note(f"  restart {m}: iterations {infos[0]['iterations']} (graphs {[r[1] for r in runs]})")
+        for ug, itg in runs:
+            assert itg == infos[0]["iterations"]
+            assert np.array_equal(ug, host(u))
 
 
 def test_instrumented_solve_times_every_launch():
