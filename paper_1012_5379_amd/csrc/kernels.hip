@@ -142,6 +142,35 @@ __device__ __forceinline__ void load_parts(const zc *part, int nb, int nv, zc (&
         if (!(ok && q < nv)) v[q] = mkc(0.0, 0.0);
 }
 
+// block_sum at the end of a pass: thread q < nv stores the total it formed
+// itself (res[q]), so the closing barrier is left out.
+template <int NV>
+__device__ __forceinline__ void block_sum_last(zc (&v)[NV], int nv, zc *sh, zc *res)
+{
+    constexpr int NW = BLK / 64;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        if (q < nv) {
+            v[q].re = wave_sum(v[q].re);
+            v[q].im = wave_sum(v[q].im);
+        }
+    }
+    if (lane == 63) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q)
+            if (q < nv) sh[wv * NV + q] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < nv) {
+        const int q = threadIdx.x;
+        zc a = sh[q];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) a = a + sh[w * NV + q];
+        res[q] = a;
+    }
+}
+
 // Sum the per-block partials of one RHS into res[0..nv-1].
 template <int NV>
 __device__ __forceinline__ void reduce_parts(const zc *part, int nb, int nv, zc *sh, zc *res)
@@ -935,7 +964,7 @@ __global__ __launch_bounds__(BLK) void k_st0(LvlK<T> L, const Cx<T> *u0, Cx<T> *
     const unsigned c = chunk_id(nb);
     const unsigned p0 = c * chunk, p1 = min(L.N, p0 + chunk);
     body_st0<T, DIM, NA>(L, u0 + rhs * ld, w + rhs * ld, p0 + threadIdx.x, p1, BLK, acc);
-    block_sum<NA>(acc, NA, sh, res);
+    block_sum_last<NA>(acc, NA, sh, res);
     if (threadIdx.x < NA) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + c] = res[threadIdx.x];
 }
 
@@ -955,7 +984,7 @@ __global__ __launch_bounds__(BLK) void k_stj(LvlK<T> L, Basis<T> B, Cx<T> *w, in
     const unsigned p0 = c * chunk, p1 = min(L.N, p0 + chunk);
     body_stj<T, DIM, SB>(L, B, w, j, rhs * ld, p0 + threadIdx.x, p1, BLK, acc, wn != 0);
     const int nv = j + 2 + (wn ? 1 : 0);
-    block_sum<SB + 1>(acc, nv, sh, res);
+    block_sum_last<SB + 1>(acc, nv, sh, res);
     if (threadIdx.x < nv) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + c] = res[threadIdx.x];
 }
 
@@ -982,7 +1011,7 @@ __global__ __launch_bounds__(BLK) void k_os(LvlK<T> L, Basis<T> B, const Cx<T> *
     const bool wn = norm_from_sums<T>() && j + 2 == s;   // last step of the sweep
     body_os<T, DIM, SB, SB + 1>(L, B, win, wout, j, (T)sj, cu, rhs * ld, p0 + threadIdx.x, p1, BLK, acc, wn);
     const int nv = j + 3 + (wn ? 1 : 0);
-    block_sum<SB + 1>(acc, nv, sh, res);
+    block_sum_last<SB + 1>(acc, nv, sh, res);
     if (threadIdx.x < nv) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + c] = res[threadIdx.x];
 }
 
@@ -1138,7 +1167,7 @@ __global__ __launch_bounds__(BLK) void k_os_tile(LvlK<T> L, Basis<T> B, const Cx
         if (wlast) acc[j + 3].re += cabs2(wd);
     }
     const int nv = j + 3 + (wlast ? 1 : 0);
-    block_sum<SB + 1>(acc, nv, sh, res);
+    block_sum_last<SB + 1>(acc, nv, sh, res);
     if (threadIdx.x < nv) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + t] = res[threadIdx.x];
 }
 
@@ -1232,7 +1261,7 @@ __global__ __launch_bounds__(BLK) void k_st0_tile(LvlK<T> L, const Cx<T> *__rest
         acc[1].re += cabs2(ud);
         if (NA > 2) acc[NA - 1].re += cabs2(wd);
     }
-    block_sum<NA>(acc, NA, sh, res);
+    block_sum_last<NA>(acc, NA, sh, res);
     if (threadIdx.x < NA) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + t] = res[threadIdx.x];
 }
 
@@ -1256,7 +1285,7 @@ __global__ __launch_bounds__(BLK) void k_orthl(Basis<T> B, const Cx<T> *win, int
     const unsigned c = chunk_id(nb);
     const unsigned p0 = c * chunk, p1 = min(N, p0 + chunk);
     body_orthl<T, SB>(B, win + rhs * ld, j, (T)sj, cu, rhs * ld, p0 + threadIdx.x, p1, BLK, acc[0].re);
-    block_sum<1>(acc, 1, sh, res);
+    block_sum_last<1>(acc, 1, sh, res);
     if (threadIdx.x == 0) pout[((size_t)rhs * NVAL) * NBMAX + c] = res[0];
 }
 
@@ -1940,7 +1969,7 @@ __global__ __launch_bounds__(BLK) void k_up_tile(LvlK<T> F, LvlK<T> C, const Cx<
         acc[1].re += cabs2(ud);
         if (NA > 2) acc[NA - 1].re += cabs2(wd);
     }
-    block_sum<NA>(acc, NA, sh, res);
+    block_sum_last<NA>(acc, NA, sh, res);
     if (threadIdx.x < NA) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + t] = res[threadIdx.x];
 }
 
@@ -2111,7 +2140,7 @@ __global__ __launch_bounds__(BLK) void k_down_tile(Cx<T> *__restrict__ x, int ac
             acc[1].re += cabs2(ud);
             if (NA > 2) acc[NA - 1].re += cabs2(wd);
         }
-        block_sum<NA>(acc, NA, sh, res);
+        block_sum_last<NA>(acc, NA, sh, res);
         if (threadIdx.x < NA) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + t] = res[threadIdx.x];
     }
 }
@@ -2949,7 +2978,7 @@ __global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__r
         }
     }
     if (!two) return;
-    block_sum<1>(acc, 1, sh, res);
+    block_sum_last<1>(acc, 1, sh, res);
     if (threadIdx.x == 0) pout[((size_t)rhs * OVAL + j + 1) * NBMAX + c] = res[0];
 }
 
@@ -3060,7 +3089,7 @@ __global__ __launch_bounds__(BLK) void k_tres(LvlK<double> H, const zc *__restri
         acc[1].re += cabs2(ch);
     }
     const int nv = with_chi ? 2 : 1;
-    block_sum<2>(acc, nv, sh, res);
+    block_sum_last<2>(acc, nv, sh, res);
     if (threadIdx.x < nv) pout[((size_t)rhs * OVAL + threadIdx.x) * NBMAX + c] = res[threadIdx.x];
 }
 
