@@ -1535,9 +1535,14 @@ __device__ __forceinline__ void close_regs(const CloseIn<SB> &in, GState *gs, co
 // own loads in between: close_begin issues the loads of the sweep state
 // (thread 0) and of this thread's partials; close_end sums the partials and
 // solves the least squares (ax, ar and the returned k as close_sweep).
+// The sweep state is copied with one vector load per thread (8 bytes each) and
+// staged in shared memory, so that no scalar load of it (each waited for in
+// turn) stands before the pass's other loads.
+constexpr int GS_WORDS = (int)(sizeof(GState) / sizeof(double));
+static_assert(sizeof(GState) % sizeof(double) == 0 && GS_WORDS <= BLK, "state copy");
 template <int SB>
 struct CloseLoads {
-    CloseIn<SB> in;
+    double gv;
     zc v[SB + 1];
 };
 template <typename T, int SB>
@@ -1545,7 +1550,7 @@ __device__ __forceinline__ void close_begin(const zc *pin, int nbin, const GStat
 {
     static_assert(SB <= 4, "register form");
     constexpr bool sums = norm_from_sums<T>();
-    if (threadIdx.x == 0) close_gather<SB>(gs, s, sums, cl.in);
+    cl.gv = reinterpret_cast<const double *>(gs)[min((int)threadIdx.x, GS_WORDS - 1)];
     load_parts<SB + 1>(pin, nbin, sums ? s + 2 : 1, cl.v);
 }
 template <typename T, int SB>
@@ -1553,9 +1558,15 @@ __device__ __forceinline__ int close_end(CloseLoads<SB> &cl, GState *gs, int s, 
                                          zc *ax, zc *ar)
 {
     __shared__ int ks;
+    __shared__ __align__(16) double lgs[GS_WORDS];
     constexpr bool sums = norm_from_sums<T>();
+    if (threadIdx.x < GS_WORDS) lgs[threadIdx.x] = cl.gv;
     block_sum<SB + 1>(cl.v, sums ? s + 2 : 1, sh, res);
-    if (threadIdx.x == 0) close_regs<T, SB>(cl.in, gs, res, s, tiny, blockIdx.x == 0, ax, ar, &ks);
+    if (threadIdx.x == 0) {
+        CloseIn<SB> in;
+        close_gather<SB>(reinterpret_cast<const GState *>(lgs), s, sums, in);
+        close_regs<T, SB>(in, gs, res, s, tiny, blockIdx.x == 0, ax, ar, &ks);
+    }
     __syncthreads();
     return ks;
 }
@@ -1664,18 +1675,19 @@ __global__ __launch_bounds__(BLK) void k_upd(Cx<T> *x, int accumulate, Basis<T> 
         const size_t off = rhs * ld;
         Cx<T> *xr = x + off;
         Cx<T> u[PB][SB - 1], xv[PB];
+        // every load unconditional (slots past s-1 read slot s-1 again; x read
+        // and dropped when not accumulating), so that the wait before the least
+        // squares leaves the first batch in flight
+        const Cx<T> *bu[SB - 1];
+#pragma unroll
+        for (int q = 0; q < SB - 1; ++q) bu[q] = B.u[min(q, s - 1)] + off;
         auto load = [&](unsigned p) {
 #pragma unroll
             for (int i = 0; i < PB; ++i) {
                 const unsigned pk = min(p + i * BLK, N - 1);
 #pragma unroll
-                for (int q = 0; q < SB - 1; ++q)
-                    if (q < s) u[i][q] = B.u[q][off + pk];
-                xv[i] = mkc<T>(0, 0);
-            }
-            if (accumulate) {
-#pragma unroll
-                for (int i = 0; i < PB; ++i) xv[i] = xr[min(p + i * BLK, N - 1)];
+                for (int q = 0; q < SB - 1; ++q) u[i][q] = bu[q][pk];
+                xv[i] = xr[pk];
             }
         };
         const unsigned pt = p0 + threadIdx.x;
@@ -1688,7 +1700,7 @@ __global__ __launch_bounds__(BLK) void k_upd(Cx<T> *x, int accumulate, Basis<T> 
             if (p != pt) load(p);
 #pragma unroll
             for (int i = 0; i < PB; ++i) {
-                Cx<T> v = xv[i];
+                Cx<T> v = accumulate ? xv[i] : mkc<T>(0, 0);
 #pragma unroll
                 for (int q = 0; q < SB - 1; ++q)
                     if (q < k) v = cfma(cx[q], u[i][q], v);
@@ -1813,8 +1825,7 @@ __global__ __launch_bounds__(BLK) void k_up_tile(LvlK<T> F, LvlK<T> C, const Cx<
             const size_t P = offc + (size_t)(cy0 + qy) * C.nx + cx0 + qx;
             xbq[i] = uc.xb[P];
 #pragma unroll
-            for (int q2 = 0; q2 < SB - 1; ++q2)
-                if (q2 < uc.s) ucq[i][q2] = uc.B.u[q2][P];
+            for (int q2 = 0; q2 < SB - 1; ++q2) ucq[i][q2] = uc.B.u[min(q2, uc.s - 1)][P];   // slots past s-1 unused
         }
     }
     Cx<T> bq[TILE_MAXE];
@@ -2042,8 +2053,15 @@ __global__ __launch_bounds__(BLK) void k_down_tile(Cx<T> *__restrict__ x, int ac
     Cx<T> u[TILE_PB][SB], xv[TILE_PB];
     size_t pp[TILE_PB];
     bool ok[TILE_PB], own[TILE_PB];
-    // loads of the batch of phase 1 starting at b0 (basis slots 0..s, all valid)
-    auto load_batch = [&](int b0) {
+    // basis slots 0..s; slots past s read slot s again (every load unconditional,
+    // so the wait before the least squares leaves this batch in flight)
+    const Cx<T> *bu[SB];
+#pragma unroll
+    for (int q2 = 0; q2 < SB; ++q2) bu[q2] = B.u[min(q2, s)];
+    Cx<T> *const xw = x;
+    // loads of the batch of phase 1 starting at b0 (x after the least squares
+    // for the first batch: a sweep from zero never reads it)
+    auto load_batch = [&](int b0, bool with_x) {
 #pragma unroll
         for (int i = 0; i < TILE_PB; ++i) {
             if (b0 + i >= UP_MAXE) break;
@@ -2055,26 +2073,29 @@ __global__ __launch_bounds__(BLK) void k_down_tile(Cx<T> *__restrict__ x, int ac
             if (!ok[i]) gx = 2 * X0, gy = 2 * Y0;
             pp[i] = offf + (size_t)gy * fnx + gx;
 #pragma unroll
-            for (int q2 = 0; q2 < SB; ++q2)
-                if (q2 <= s) u[i][q2] = B.u[q2][pp[i]];
+            for (int q2 = 0; q2 < SB; ++q2) u[i][q2] = bu[q2][pp[i]];
             xv[i] = mkc<T>(0, 0);
         }
-        if (accumulate) {
+        if (with_x && accumulate) {
 #pragma unroll
             for (int i = 0; i < TILE_PB; ++i)
-                if (b0 + i < UP_MAXE) xv[i] = x[pp[i]];
+                if (b0 + i < UP_MAXE) xv[i] = xw[pp[i]];
         }
     };
-    load_batch(0);
+    load_batch(0, false);
     if (!act) return;
     const int k = close_end<T, SB>(cls, gsb + rhs, s, tiny, sh, res, ax, ar);
+    if (accumulate) {
+#pragma unroll
+        for (int i = 0; i < TILE_PB; ++i) xv[i] = xw[pp[i]];
+    }
     Cx<T> cx[SB], cr[SB];
     coefs_to_T<T, SB>(k, ax, ar, cx, cr);
     if (tslot >= 0) ltab[tslot] = mkc<T>(tre, tim);
 #pragma unroll
     for (int b0 = 0; b0 < UP_MAXE; b0 += TILE_PB) {
         if (b0 * BLK >= FN) break;   // the same for every thread of the block
-        if (b0 > 0) load_batch(b0);
+        if (b0 > 0) load_batch(b0, true);
 #pragma unroll
         for (int i = 0; i < TILE_PB; ++i) {
             if (b0 + i >= UP_MAXE) break;
@@ -2086,7 +2107,7 @@ __global__ __launch_bounds__(BLK) void k_down_tile(Cx<T> *__restrict__ x, int ac
                     rr = cfma(cr[q2], u[i][q2], rr);
                     if (q2 < k) xv[i] = cfma(cx[q2], u[i][q2], xv[i]);
                 }
-            if (own[i]) x[pp[i]] = xv[i];
+            if (own[i]) xw[pp[i]] = xv[i];
             if (q < FN) lr[q] = ok[i] ? rr : mkc<T>(0, 0);
         }
     }
