@@ -206,7 +206,7 @@ enum {
     CSG_PROF_UPDATE = 6,        /* finest-level post-smoother update pass     */
     CSG_PROF_OUTER_H = 7,       /* FGMRES: w = H z + first-round dots         */
     CSG_PROF_OUTER_CGS1 = 8,    /* FGMRES: first projection + ||w1||^2        */
-    CSG_PROF_OUTER_CGS2 = 9,    /* FGMRES: second-round dots                  */
+    CSG_PROF_OUTER_CGS2 = 9,    /* (unused: the second-round dots run inside the first projection) */
     CSG_PROF_OUTER_NORM = 10,   /* FGMRES: v_1 = r / beta at a cycle start    */
     CSG_PROF_OUTER_PROJ2 = 11,  /* FGMRES: second projection, scale, cast     */
     CSG_PROF_FUSED = 12,        /* finest-level fused Gram-Schmidt + stencil  */

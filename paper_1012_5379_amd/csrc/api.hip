@@ -657,14 +657,11 @@ void iter_body(csg_solve *sv, int j, hipStream_t st)
     launch_fin(FIN_H, op->opart, f.nb, j, op->fs, report_slot(op, j % LOOKAHEAD), sv->nrhs, st, mask, op->active);
     {
         // first projection: writes v_{j+1} when the first round is final (the
-        // second-round passes below then return at once)
+        // second-round passes below then return at once); otherwise keeps w_1
+        // and forms the second round's inner products in the same launch
         ProfScope ps(op, CSG_PROF_OUTER_CGS1, st, R * N * (16.0 * (j + 3) + (op->p.cycle_prec ? 8.0 : 0.0)));
         launch_proj0<TZ>(op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->opart, op->V + (j + 1) * vstride,
                          op->p.cycle_prec ? (Cx<TZ> *)op->b0 : nullptr, g, mask);
-    }
-    {
-        ProfScope ps(op, CSG_PROF_OUTER_CGS2, st, R * N * 16.0 * (j + 2));
-        launch_mdot(op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->opart, g, mask);
     }
     launch_fin(FIN_CN, op->opart, f.nb, j, op->fs, report_slot(op, j % LOOKAHEAD), sv->nrhs, st, mask, op->active);
     ProfScope ps(op, CSG_PROF_OUTER_PROJ2, st, R * N * (16.0 * (j + 3) + (op->p.cycle_prec ? 8.0 : 0.0)));
@@ -773,7 +770,7 @@ int solve_step(csg_solve *sv)
     switch (sv->phase) {
     case csg_solve::INIT:
         upload_masks(sv);
-        launch_fs_params(op->fs, sv->tol, sv->maxit, sv->nrhs, sv->st);
+        launch_fs_params(op->fs, sv->tol, sv->maxit, op->force_cgs2 ? 1 : 0, sv->nrhs, sv->st);
         if (d3) enqueue_begin<3>(sv, true); else enqueue_begin<2>(sv, true);
         enqueue_report(sv, LOOKAHEAD);
         sv->phase = csg_solve::WAIT_BEGIN;
@@ -995,6 +992,8 @@ int csg_operator_create(const csg_params *p, const double *phi_host, void *ws_de
         if (const char *e = getenv("CSG_DOWN_TILES")) op->down_tiles = atoi(e) != 0;
         op->fuse_upd = true;
         if (const char *e = getenv("CSG_FUSE_UPD")) op->fuse_upd = atoi(e) != 0;
+        op->force_cgs2 = false;
+        if (const char *e = getenv("CSG_FORCE_CGS2")) op->force_cgs2 = atoi(e) != 0;
         op->lt = op->L - 1;
         for (int l = 0; l < op->L; ++l)
             if ((long)op->lev[l].N <= tail_max) { op->lt = l; break; }

@@ -58,6 +58,8 @@ struct FState {
     int reorth;        // the current column takes the second Gram-Schmidt round
     int it;            // outer iterations done by this RHS in the solve
     int maxit;         // iteration limit of the solve
+    int force2;        // every column takes the second Gram-Schmidt round (experiments, tests)
+    int pad;
 };
 
 // Outer iterations a solve keeps queued ahead of the host's reading of their
@@ -199,6 +201,7 @@ struct csg_operator {
     bool up_tiles;                    // ... and the LDS-staged interpolation + residual + pass 0
     bool down_tiles;                  // ... and the LDS-staged closing + restriction + next pass 0
     bool fuse_upd;                    // coarse post-sweep updates applied by the finer up-path pass
+    bool force_cgs2;                  // every outer column takes the second Gram-Schmidt round
     // outer FGMRES storage
     csg::zc *V;                       // (m+1) x max_rhs x ld0
     void *Z;                          // m x max_rhs x ld0, cycle precision

@@ -182,10 +182,6 @@ template <typename TB>
 void launch_proj1(const zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, const FState *fs, zc *vout,
                   Cx<TB> *bcast, const Launch &g, const int *active);
 
-// second-round <v_i, w>
-void launch_mdot(const zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, const FState *fs, zc *pout,
-                 const Launch &g, const int *active);
-
 // v = w * scale (scale = fs->inv_hn), optional cycle-precision copy (cast).
 template <typename TB>
 void launch_vnorm(const zc *w, zc *v, Cx<TB> *bcast, unsigned N, size_t ld, const FState *fs, const Launch &g,
@@ -204,8 +200,9 @@ enum FinMode { FIN_H = 0, FIN_CN = 1, FIN_BEGIN = 3, FIN_BETA = 4, FIN_LS = 5 };
 void launch_fin(int mode, const zc *pin, int nbin, int j, FState *fs, Report *rep, int nrhs, hipStream_t st,
                 const int *active, int *stop = nullptr);
 
-// Stopping parameters of a solve into every RHS's state (iteration count reset).
-void launch_fs_params(FState *fs, double tol, int maxit, int nrhs, hipStream_t st);
+// Stopping parameters of a solve into every RHS's state (iteration count
+// reset; force2: every column takes the second Gram-Schmidt round).
+void launch_fs_params(FState *fs, double tol, int maxit, int force2, int nrhs, hipStream_t st);
 
 void launch_copy_mask(const int *src, int *dst, int n, hipStream_t st);
 

@@ -2956,17 +2956,18 @@ __device__ __forceinline__ void proj_batch(const zc *w, const zc *V, size_t vstr
 }
 
 // First projection x = w - sum_i h_i v_i (h = hcol).  Columns that take the
-// second round keep x in w with the partial ||x||^2 as value j+1 (values 0..j
-// are left to the second-round inner products); the others are final and
-// write v_{j+1} = x / h_{j+1,j} and its optional cycle-precision copy.
+// second round keep x in w and write the partials of the second round's
+// inputs: <v_i, x> (values 0..j, a second pass over the block's chunk) and
+// ||x||^2 (value j+1); the others are final and write v_{j+1} = x / h_{j+1,j}
+// and its optional cycle-precision copy.
 template <typename TB>
 __global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__restrict__ V, size_t vstride, int j,
                                                unsigned N, size_t ld, const FState *fsb, zc *__restrict__ pout,
                                                zc *__restrict__ vout, Cx<TB> *__restrict__ bc, unsigned chunk,
                                                int nb, const int *active)
 {
-    __shared__ zc sh[BLK / 64];
-    __shared__ zc res[1];
+    __shared__ zc sh[(BLK / 64) * 8];
+    __shared__ zc res[8];
     __shared__ zc cc[OVAL];
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
@@ -2999,8 +3000,18 @@ __global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__r
         }
     }
     if (!two) return;
-    block_sum_last<1>(acc, 1, sh, res);
-    if (threadIdx.x == 0) pout[((size_t)rhs * OVAL + j + 1) * NBMAX + c] = res[0];
+    zc *po = pout + (size_t)rhs * OVAL * NBMAX;
+    block_sum<1>(acc, 1, sh, res);
+    if (threadIdx.x == 0) po[(j + 1) * NBMAX + c] = res[0];
+    // second-round inner products <v_i, w_1> (values 0..j) over the same chunk:
+    // each thread re-reads the w_1 points it has just written
+    for (int g = 0; 8 * g <= j; ++g) {
+        zc dots[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) dots[q] = mkc(0.0, 0.0);
+        dots8(w, V, vstride, g, j, off, p0, p1, dots);
+        store_group(dots, g, j, po, c, sh, res);
+    }
 }
 
 // Second projection and normalisation: v_{j+1} = (w - sum_i c_i v_i) / h_{j+1,j}
@@ -3035,28 +3046,6 @@ __global__ __launch_bounds__(BLK) void k_proj1(const zc *__restrict__ w, const z
             vout[off + p + k * BLK] = v;
             if (bc) bc[off + p + k * BLK] = cvt<TB>(v);
         }
-    }
-}
-
-// second-round inner products c_i = <v_i, w1>
-__global__ __launch_bounds__(BLK) void k_mdot(const zc *__restrict__ w, const zc *__restrict__ V, size_t vstride, int j,
-                                              unsigned N, size_t ld, const FState *fsb, zc *__restrict__ pout,
-                                              unsigned chunk, int nb, const int *active)
-{
-    __shared__ zc sh[(BLK / 64) * 8];
-    __shared__ zc res[8];
-    const int rhs = blockIdx.y;
-    if (!active[rhs] || !fsb[rhs].reorth) return;
-    const size_t off = rhs * ld;
-    const unsigned c = chunk_id(nb);
-    const unsigned p0 = c * chunk + threadIdx.x, p1 = min(N, c * chunk + chunk);
-    zc *po = pout + (size_t)rhs * OVAL * NBMAX;
-    for (int g = 0; 8 * g <= j; ++g) {
-        zc acc[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] = mkc(0.0, 0.0);
-        dots8(w, V, vstride, g, j, off, p0, p1, acc);
-        store_group(acc, g, j, po, c, sh, res);
     }
 }
 
@@ -3157,10 +3146,17 @@ constexpr int FG = 32;     // lanes that reduce one value
 // then a butterfly inside the lane group): deterministic, no block barrier.
 __device__ __forceinline__ zc group_parts(const zc *pp, int nbin)
 {
+    // every load of the lane issued at once (inside the row of NBMAX partials),
+    // then summed in the order of b
+    constexpr int K = NBMAX / FG;
     const int lane = threadIdx.x % FG;
+    zc t[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) t[k] = pp[min(lane + k * FG, NBMAX - 1)];
     zc v = mkc(0.0, 0.0);
-#pragma unroll 4
-    for (int b = lane; b < nbin; b += FG) v = v + pp[b];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (lane + k * FG < nbin) v = v + t[k];
 #pragma unroll
     for (int off = FG / 2; off > 0; off >>= 1) {
         v.re += __shfl_xor(v.re, off, FG);
@@ -3271,7 +3267,8 @@ __global__ __launch_bounds__(FT) void k_fin(int mode, const zc *__restrict__ pin
         // When ||w1|| >= ||w|| / 100 the single round lost at most ~100 eps of
         // orthogonality: the column is final, h_{j+1,j} = ||w1|| and the first
         // projection writes v_{j+1} directly.  Otherwise the second round
-        // (k_proj0 keeps w1, k_mdot, FIN_CN, k_proj1) restores orthogonality.
+        // (k_proj0 keeps w1 and forms its inner products, FIN_CN, k_proj1)
+        // restores orthogonality.
         __shared__ int two;
         if (threadIdx.x == 0) {
             const double w2 = val[j + 1].re;
@@ -3283,7 +3280,7 @@ __global__ __launch_bounds__(FT) void k_fin(int mode, const zc *__restrict__ pin
             }
             fs->w2 = w2;
             const double w1 = w2 - h2;
-            two = !(w1 >= 1e-4 * w2);
+            two = fs->force2 || !(w1 >= 1e-4 * w2);   // force2: every column, for tests
             fs->reorth = two;
             if (!two) givens_column(fs, rep + rhs, j, sqrt(w1), col, cs_s, sn_s, stop ? stop + rhs : nullptr);
         }
@@ -3572,12 +3569,6 @@ void launch_proj1(const zc *w, const zc *V, size_t vstride, int j, unsigned N, s
                        g.nb, active);
 }
 
-void launch_mdot(const zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, const FState *fs, zc *pout,
-                 const Launch &g, const int *active)
-{
-    hipLaunchKernelGGL(k_mdot, grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, pout, g.chunk, g.nb, active);
-}
-
 template <typename TB>
 void launch_vnorm(const zc *w, zc *v, Cx<TB> *bcast, unsigned N, size_t ld, const FState *fs, const Launch &g,
                   const int *active)
@@ -3606,19 +3597,20 @@ void launch_fin(int mode, const zc *pin, int nbin, int j, FState *fs, Report *re
     hipLaunchKernelGGL(k_fin, dim3(nrhs), dim3(FT), 0, st, mode, pin, nbin, j, fs, rep, active, stop);
 }
 
-__global__ void k_fs_params(FState *fs, double tol, int maxit, int nrhs)
+__global__ void k_fs_params(FState *fs, double tol, int maxit, int force2, int nrhs)
 {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r < nrhs) {
         fs[r].tol = tol;
         fs[r].maxit = maxit;
         fs[r].it = 0;
+        fs[r].force2 = force2;
     }
 }
 
-void launch_fs_params(FState *fs, double tol, int maxit, int nrhs, hipStream_t st)
+void launch_fs_params(FState *fs, double tol, int maxit, int force2, int nrhs, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_fs_params, dim3((nrhs + 63) / 64), dim3(64), 0, st, fs, tol, maxit, nrhs);
+    hipLaunchKernelGGL(k_fs_params, dim3((nrhs + 63) / 64), dim3(64), 0, st, fs, tol, maxit, force2, nrhs);
 }
 
 template <typename T, int DIM>

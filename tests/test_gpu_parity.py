@@ -235,6 +235,27 @@ def test_vcycle_with_each_fused_path_off(knob, prec, monkeypatch):
         assert e <= (TOL64 if prec == 0 else TOL32["vcycle"])
 
 
+def test_fgmres_second_round_every_column(monkeypatch):
+    """The outer second Gram-Schmidt round (taken only when the first round
+    cancels) forced on every column: the solve still matches the oracle's
+    iteration count and answer, and the selective solve to rounding."""
+    import torch
+    w = CASES["2d_ragged"]()
+    chi = dev(w.chi[:1], torch.complex128)
+    res = {}
+    for force in ("0", "1"):
+        monkeypatch.setenv("CSG_FORCE_CGS2", force)
+        op, orc = pair(w, max_rhs=1, cycle_prec=0, restart=12)
+        u, rc, infos = op.solve(chi, tol=1e-9, restart=12, maxit=400)
+        assert rc == 0
+        res[force] = (host(u)[0], infos[0]["iterations"])
+    uo, info = orc.fgmres(w.chi[0], tol=1e-9, restart=12, maxit=400)
+    note(f"  iterations: selective {res['0'][1]}, every column {res['1'][1]}, oracle {info.iterations}")
+    assert abs(res["1"][1] - info.iterations) <= 1
+    assert rel(res["1"][0], uo) <= 1e-8
+    assert rel(res["1"][0], res["0"][0]) <= 1e-8
+
+
 def test_graph_replay_matches_eager(monkeypatch):
     """FGMRES iterations replayed from captured graphs (with eager restart and
     report work in between) give bit-identical results to eager launches."""
