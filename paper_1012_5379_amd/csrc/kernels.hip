@@ -80,40 +80,123 @@ __device__ __forceinline__ double dpp64(double v)
     return __hiloint2double(hi, lo);
 }
 
-// Sum over the 64 lanes of a wavefront, valid in lane 63: running sums over
-// 4, 8 and 16 lanes by row shifts, then row 15 / row 31 broadcasts.  A fixed
-// order of additions, a few VALU cycles per step.
-__device__ __forceinline__ double wave_sum(double v)
+// Exchanges of a double between lane pairs of a wavefront.  permlane32/16
+// swaps (gfx950) trade the upper half of a with the lower half of b across
+// lanes L and L^32 (rows 1, 3 of a with rows 0, 2 of b across L and L^16), so
+// a + b afterwards holds, in lanes with that lane bit clear, the pair sum of a
+// and in the others the pair sum of b.
+__device__ __forceinline__ void swap32(double &a, double &b)
 {
-    double s = v + dpp64<0x111, 0xF, 0xF, true>(v);   // row_shr:1
-    s = s + dpp64<0x112, 0xF, 0xF, true>(v);          // row_shr:2
-    s = s + dpp64<0x113, 0xF, 0xF, true>(v);          // row_shr:3
-    s = s + dpp64<0x114, 0xF, 0xE, false>(s);         // row_shr:4 into lanes 4-15 of a row
-    s = s + dpp64<0x118, 0xF, 0xC, false>(s);         // row_shr:8 into lanes 8-15 of a row
-    s = s + dpp64<0x142, 0xA, 0xF, false>(s);         // lane 15 of a row into rows 1 and 3
-    s = s + dpp64<0x143, 0xC, 0xF, false>(s);         // lane 31 into rows 2 and 3
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
+    a = __hiloint2double(hi[0], lo[0]);
+    b = __hiloint2double(hi[1], lo[1]);
+}
+__device__ __forceinline__ void swap16(double &a, double &b)
+{
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false, false);
+    a = __hiloint2double(hi[0], lo[0]);
+    b = __hiloint2double(hi[1], lo[1]);
+}
+
+// Partner lanes of the in-row steps: L^15 (row mirror), L^7 (half-row
+// mirror), L^2 and L^1 (quad permutations); each differs from L in bit 3, 2,
+// 1, 0 respectively and agrees with it on every higher bit.
+template <int B>
+__device__ __forceinline__ double partner(double v)
+{
+    constexpr int CTRL = B == 3 ? 0x140 : B == 2 ? 0x141 : B == 1 ? 0x4E : 0xB1;
+    return dpp64<CTRL, 0xF, 0xF, false>(v);
+}
+
+// One halving step of the reduce-scatter at lane bit B: value k pairs with
+// value k + n/2; the lane keeps k when its bit B is clear, k + n/2 otherwise,
+// and adds the partner lane's copy of the value it keeps.
+template <int B, int N, int ND>
+__device__ __forceinline__ void halve(double (&d)[ND])
+{
+    constexpr int H = N / 2;
+    if constexpr (B >= 4) {
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+            if constexpr (B == 5) swap32(d[k], d[k + H]);
+            else swap16(d[k], d[k + H]);
+            d[k] = d[k] + d[k + H];
+        }
+    } else {
+        const bool up = (threadIdx.x >> B) & 1;
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+            const double keep = up ? d[k + H] : d[k], send = up ? d[k] : d[k + H];
+            d[k] = keep + partner<B>(send);
+        }
+    }
+}
+
+// Wavefront totals of d[0..ND-1] (ND a power of two, 2..64): a reduce-scatter
+// over lane bits 5, 4, ... (log2 ND steps, each exchanging half the values a
+// lane holds) and sums over the lower lane bits.  Every lane returns the total
+// of value lane >> (6 - log2 ND).  The additions follow a fixed order; the
+// cost is at most about 4 VALU operations per value (a scan of one value at a
+// time across the wavefront takes 21).
+template <int ND>
+__device__ __forceinline__ double wave_totals(double (&d)[ND])
+{
+    static_assert(ND >= 2 && ND <= 64 && (ND & (ND - 1)) == 0, "power of two");
+    halve<5, ND>(d);
+    if constexpr (ND >= 4) halve<4, ND / 2>(d);
+    if constexpr (ND >= 8) halve<3, ND / 4>(d);
+    if constexpr (ND >= 16) halve<2, ND / 8>(d);
+    if constexpr (ND >= 32) halve<1, ND / 16>(d);
+    if constexpr (ND >= 64) halve<0, ND / 32>(d);
+    double s = d[0];
+    if constexpr (ND < 4) {
+        double t = s;
+        swap16(s, t);
+        s = s + t;
+    }
+    if constexpr (ND < 8) s = s + partner<3>(s);
+    if constexpr (ND < 16) s = s + partner<2>(s);
+    if constexpr (ND < 32) s = s + partner<1>(s);
+    if constexpr (ND < 64) s = s + partner<0>(s);
     return s;
 }
 
-// Wavefront sums (lane 63), then the BLK/64 wavefronts in order; every thread
-// reads the same totals from res.
+constexpr int pow2_at_least(int n)
+{
+    int p = 2;
+    while (p < n) p *= 2;
+    return p;
+}
+
+// Wavefront totals of v[0..NV-1] into this wave's row of sh (row layout
+// [NV] complex, as re/im doubles): one lane per total writes it.
+template <int NV>
+__device__ __forceinline__ void wave_totals_to(const zc (&v)[NV], int nv, zc *sh, int wv)
+{
+    constexpr int ND = pow2_at_least(2 * NV);
+    constexpr int SH = ND == 2 ? 5 : ND == 4 ? 4 : ND == 8 ? 3 : ND == 16 ? 2 : ND == 32 ? 1 : 0;
+    double d[ND];
+#pragma unroll
+    for (int q = 0; q < ND / 2; ++q) {
+        const bool on = q < NV && q < nv;
+        const zc x = v[q < NV ? q : 0];
+        d[2 * q] = on ? x.re : 0.0;
+        d[2 * q + 1] = on ? x.im : 0.0;
+    }
+    const double t = wave_totals<ND>(d);
+    const int lane = threadIdx.x & 63, idx = lane >> SH;
+    if ((lane & ((1 << SH) - 1)) == 0 && idx < 2 * nv) reinterpret_cast<double *>(sh)[wv * 2 * NV + idx] = t;
+}
+
+// Wavefront totals, then the BLK/64 wavefronts in order; every thread reads
+// the same totals from res.
 template <int NV>
 __device__ __forceinline__ void block_sum(zc (&v)[NV], int nv, zc *sh, zc *res)
 {
     constexpr int NW = BLK / 64;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        if (q < nv) {
-            v[q].re = wave_sum(v[q].re);
-            v[q].im = wave_sum(v[q].im);
-        }
-    }
-    if (lane == 63) {
-#pragma unroll
-        for (int q = 0; q < NV; ++q)
-            if (q < nv) sh[wv * NV + q] = v[q];
-    }
+    wave_totals_to<NV>(v, nv, sh, threadIdx.x >> 6);
     __syncthreads();
     if (threadIdx.x < nv) {
         const int q = threadIdx.x;
@@ -148,19 +231,7 @@ template <int NV>
 __device__ __forceinline__ void block_sum_last(zc (&v)[NV], int nv, zc *sh, zc *res)
 {
     constexpr int NW = BLK / 64;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        if (q < nv) {
-            v[q].re = wave_sum(v[q].re);
-            v[q].im = wave_sum(v[q].im);
-        }
-    }
-    if (lane == 63) {
-#pragma unroll
-        for (int q = 0; q < NV; ++q)
-            if (q < nv) sh[wv * NV + q] = v[q];
-    }
+    wave_totals_to<NV>(v, nv, sh, threadIdx.x >> 6);
     __syncthreads();
     if (threadIdx.x < nv) {
         const int q = threadIdx.x;
@@ -2261,19 +2332,7 @@ constexpr int TW = TB / 64;
 template <int NV>
 __device__ __forceinline__ void tail_sum(zc (&v)[NV], int nv, zc *sh, zc *res)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        if (q < nv) {
-            v[q].re = wave_sum(v[q].re);
-            v[q].im = wave_sum(v[q].im);
-        }
-    }
-    if (lane == 63) {
-#pragma unroll
-        for (int q = 0; q < NV; ++q)
-            if (q < nv) sh[wv * NV + q] = v[q];
-    }
+    wave_totals_to<NV>(v, nv, sh, threadIdx.x >> 6);
     __syncthreads();
     if (threadIdx.x < nv) {
         const int q = threadIdx.x;
