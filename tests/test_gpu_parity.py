@@ -160,6 +160,21 @@ def test_fgmres_fp64_multi_rhs(name):
         assert e <= 1e-10
 
 
+def test_fgmres_bases_longer_than_32():
+    """FGMRES(40): bases of up to 40 vectors (five groups of 8 inner products
+    per column); iterations and solution match the oracle."""
+    import torch
+    w = CASES["2d_ragged"]()
+    op, orc = pair(w, max_rhs=1, cycle_prec=0, restart=40)
+    u, rc, infos = op.solve(dev(w.chi[:1], torch.complex128), tol=1e-10, restart=40, maxit=400)
+    uo, io = orc.fgmres(w.chi[0], tol=1e-10, restart=40, maxit=400)
+    e = rel(host(u)[0], uo)
+    note(f"  its gpu {infos[0]['iterations']} oracle {io.iterations} sol err {e:.2e}")
+    assert rc == 0 and io.iterations > 34
+    assert abs(infos[0]["iterations"] - io.iterations) <= 1
+    assert e <= 1e-10
+
+
 def test_fgmres_mixed_precision_reaches_tolerance():
     """complex64 cycle, complex128 outer: true FP64 relres <= 1e-6 and the
     solution error against the tightly converged FP64 oracle is stated."""
