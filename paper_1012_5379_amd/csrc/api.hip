@@ -141,6 +141,7 @@ void carve(csg_operator &op, const int nint[CSG_MAX_LEVELS][3], Carver &cv)
     op.w = (zc *)cv.take(n0 * sizeof(zc));
     op.b0 = p.cycle_prec ? cv.take(n0 * cz) : nullptr;
     op.opart = (zc *)cv.take((size_t)R * OVAL * NBMAX * sizeof(zc));
+    op.opart2 = (zc *)cv.take((size_t)R * OVAL * NBMAX * sizeof(zc));
     op.fs = (FState *)cv.take((size_t)R * sizeof(FState));
     op.active = (int *)cv.take((size_t)3 * R * sizeof(int));
     op.ones = op.active + 2 * R;
@@ -654,16 +655,17 @@ void iter_body(csg_solve *sv, int j, hipStream_t st)
         ProfScope ps(op, CSG_PROF_OUTER_H, st, R * N * (sizeof(Cx<TZ>) + 16.0 * (j + 2)) + 8.0 * N);
         launch_hdot<TZ, DIM>(lvlH(op), z, op->w, op->V, vstride, j, f.ld, op->opart, g, mask);
     }
-    launch_fin(FIN_H, op->opart, f.nb, j, op->fs, report_slot(op, j % LOOKAHEAD), sv->nrhs, st, mask, op->active);
     {
-        // first projection: writes v_{j+1} when the first round is final (the
-        // second-round passes below then return at once); otherwise keeps w_1
-        // and forms the second round's inner products in the same launch
+        // first round finished and applied: writes v_{j+1} (and advances the
+        // FGMRES state) when the first round is final, and the second-round
+        // passes below then return at once; otherwise keeps w_1 and forms the
+        // second round's inner products in the same launch
         ProfScope ps(op, CSG_PROF_OUTER_CGS1, st, R * N * (16.0 * (j + 3) + (op->p.cycle_prec ? 8.0 : 0.0)));
-        launch_proj0<TZ>(op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->opart, op->V + (j + 1) * vstride,
+        launch_proj0<TZ>(op->w, op->V, vstride, j, f.N, f.ld, op->fs, report_slot(op, j % LOOKAHEAD), op->active,
+                         op->opart, f.nb, op->opart2, op->V + (j + 1) * vstride,
                          op->p.cycle_prec ? (Cx<TZ> *)op->b0 : nullptr, g, mask);
     }
-    launch_fin(FIN_CN, op->opart, f.nb, j, op->fs, report_slot(op, j % LOOKAHEAD), sv->nrhs, st, mask, op->active);
+    launch_fin(FIN_CN, op->opart2, f.nb, j, op->fs, report_slot(op, j % LOOKAHEAD), sv->nrhs, st, mask, op->active);
     ProfScope ps(op, CSG_PROF_OUTER_PROJ2, st, R * N * (16.0 * (j + 3) + (op->p.cycle_prec ? 8.0 : 0.0)));
     launch_proj1<TZ>(op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->V + (j + 1) * vstride,
                      op->p.cycle_prec ? (Cx<TZ> *)op->b0 : nullptr, g, mask);

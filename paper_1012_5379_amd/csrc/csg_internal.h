@@ -208,6 +208,7 @@ struct csg_operator {
     csg::zc *w;                       // max_rhs x ld0
     void *b0;                         // cycle-precision copy of v_j (mixed mode)
     csg::zc *opart;                   // [max_rhs][OVAL][NBMAX]
+    csg::zc *opart2;                  // second-round partials of the first projection, same layout
     csg::FState *fs;                  // [max_rhs]
     int *active;                      // [max_rhs] device mask of RHS still iterating
     int *ones;                        // [max_rhs] device all-ones mask

@@ -3014,65 +3014,6 @@ __device__ __forceinline__ void proj_batch(const zc *w, const zc *V, size_t vstr
     }
 }
 
-// First projection x = w - sum_i h_i v_i (h = hcol).  Columns that take the
-// second round keep x in w and write the partials of the second round's
-// inputs: <v_i, x> (values 0..j, a second pass over the block's chunk) and
-// ||x||^2 (value j+1); the others are final and write v_{j+1} = x / h_{j+1,j}
-// and its optional cycle-precision copy.
-template <typename TB>
-__global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__restrict__ V, size_t vstride, int j,
-                                               unsigned N, size_t ld, const FState *fsb, zc *__restrict__ pout,
-                                               zc *__restrict__ vout, Cx<TB> *__restrict__ bc, unsigned chunk,
-                                               int nb, const int *active)
-{
-    __shared__ zc sh[(BLK / 64) * 8];
-    __shared__ zc res[8];
-    __shared__ zc cc[OVAL];
-    const int rhs = blockIdx.y;
-    if (!active[rhs]) return;
-    const FState *fs = fsb + rhs;
-    if (threadIdx.x <= j) cc[threadIdx.x] = fs->hcol[threadIdx.x];
-    const bool two = fs->reorth != 0;
-    const double sc = fs->inv_hn;
-    __syncthreads();
-    const size_t off = rhs * ld;
-    zc acc[1] = {mkc(0.0, 0.0)};
-    const unsigned c = chunk_id(nb);
-    const unsigned p0 = c * chunk + threadIdx.x, p1 = min(N, c * chunk + chunk);
-    if (p0 < p1) {
-        const unsigned last = p1 - 1;
-        for (unsigned p = p0; p < p1; p += UO * BLK) {
-            zc x[UO];
-            proj_batch(w, V, vstride, j, off, p, last, cc, x);
-#pragma unroll
-            for (int k = 0; k < UO; ++k) {
-                if (p + k * BLK >= p1) break;
-                if (two) {
-                    w[off + p + k * BLK] = x[k];
-                    acc[0].re += cabs2(x[k]);
-                } else {
-                    const zc v = sc * x[k];
-                    vout[off + p + k * BLK] = v;
-                    if (bc) bc[off + p + k * BLK] = cvt<TB>(v);
-                }
-            }
-        }
-    }
-    if (!two) return;
-    zc *po = pout + (size_t)rhs * OVAL * NBMAX;
-    block_sum<1>(acc, 1, sh, res);
-    if (threadIdx.x == 0) po[(j + 1) * NBMAX + c] = res[0];
-    // second-round inner products <v_i, w_1> (values 0..j) over the same chunk:
-    // each thread re-reads the w_1 points it has just written
-    for (int g = 0; 8 * g <= j; ++g) {
-        zc dots[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) dots[q] = mkc(0.0, 0.0);
-        dots8(w, V, vstride, g, j, off, p0, p1, dots);
-        store_group(dots, g, j, po, c, sh, res);
-    }
-}
-
 // Second projection and normalisation: v_{j+1} = (w - sum_i c_i v_i) / h_{j+1,j}
 // (c = corr, 1/h = inv_hn from the finish of the column), with the optional
 // cycle-precision copy of v_{j+1} (the next V-cycle's input); columns without
@@ -3304,14 +3245,14 @@ __global__ __launch_bounds__(FT) void k_fin(int mode, const zc *__restrict__ pin
     }
     // FIN_CN finishes a column only when it took the second round
     if (mode == FIN_CN && !fs->reorth) return;
-    // values: FIN_H: 0..j+1; FIN_CN: 0..j+1; FIN_BEGIN: 0, 1; others: 0
-    const int nv = (mode == FIN_H || mode == FIN_CN) ? j + 2 : (mode == FIN_BEGIN ? 2 : 1);
+    // values: FIN_CN: 0..j+1; FIN_BEGIN: 0, 1; others: 0
+    const int nv = mode == FIN_CN ? j + 2 : (mode == FIN_BEGIN ? 2 : 1);
     const int grp = threadIdx.x / FG;
     for (int q = grp; q < nv; q += FT / FG) {
         const zc v = group_parts(pp + q * NBMAX, nbin);
         if (threadIdx.x % FG == 0) val[q] = v;
     }
-    if (mode == FIN_CN || mode == FIN_H) {
+    if (mode == FIN_CN) {
         for (int q = threadIdx.x; q < j; q += FT) {
             cs_s[q] = fs->cs[q];
             sn_s[q] = fs->sn[q];
@@ -3320,34 +3261,6 @@ __global__ __launch_bounds__(FT) void k_fin(int mode, const zc *__restrict__ pin
             for (int q = threadIdx.x; q <= j; q += FT) col[q] = fs->hcol[q];
     }
     __syncthreads();
-    if (mode == FIN_H) {
-        // first-round coefficients h (values 0..j) and ||w||^2 (value j+1) of
-        // w = H z_j.  w1 = w - V h has ||w1||^2 = ||w||^2 - ||h||^2 (V orthonormal).
-        // When ||w1|| >= ||w|| / 100 the single round lost at most ~100 eps of
-        // orthogonality: the column is final, h_{j+1,j} = ||w1|| and the first
-        // projection writes v_{j+1} directly.  Otherwise the second round
-        // (k_proj0 keeps w1 and forms its inner products, FIN_CN, k_proj1)
-        // restores orthogonality.
-        __shared__ int two;
-        if (threadIdx.x == 0) {
-            const double w2 = val[j + 1].re;
-            double h2 = 0.0;
-            for (int q = 0; q <= j; ++q) {
-                col[q] = val[q];
-                fs->hcol[q] = val[q];
-                h2 += cabs2(val[q]);
-            }
-            fs->w2 = w2;
-            const double w1 = w2 - h2;
-            two = fs->force2 || !(w1 >= 1e-4 * w2);   // force2: every column, for tests
-            fs->reorth = two;
-            if (!two) givens_column(fs, rep + rhs, j, sqrt(w1), col, cs_s, sn_s, stop ? stop + rhs : nullptr);
-        }
-        __syncthreads();
-        if (!two)
-            for (int q = threadIdx.x; q <= j + 1; q += FT) fs->R[q * M + j] = col[q];
-        return;
-    }
     if (mode == FIN_CN) {
         // second-round coefficients c (values 0..j) and ||w1||^2 of the first
         // projection (value j+1): h_{j+1,j}^2 = ||w1||^2 - ||c||^2, the norm of
@@ -3604,6 +3517,122 @@ void launch_coarse(const Cx<T> *minvT, int n, const Cx<T> *b, Cx<T> *x, size_t l
     hipLaunchKernelGGL((k_coarse<T>), dim3(1, nrhs), dim3(BLK), 0, st, minvT, n, b, x, ld, active);
 }
 
+// First round of column j, finished and applied in one launch.  Every block
+// sums the inner products of k_hdot (h_i = <v_i, w>, i <= j, and ||w||^2) from
+// their partials, in the order the finish kernel uses, and takes the same
+// decision: with ||w1||^2 = ||w||^2 - ||h||^2 (w1 = w - V h, V orthonormal)
+// the column is final when ||w1|| >= ||w|| / 100 (at most ~100 eps of
+// orthogonality lost); then h_{j+1,j} = ||w1|| and the block writes its chunk
+// of v_{j+1} = w1 / h_{j+1,j} and its optional cycle-precision copy.
+// Otherwise it keeps w1 in w and writes the second round's partials into
+// pout (a buffer apart from pin, which other blocks may still be reading):
+// <v_i, w1> (values 0..j, a second pass over the block's chunk) and ||w1||^2
+// (value j+1).  Block 0 then advances the FGMRES state as the finish kernel
+// would: the column h, the flag of the second round and, for a final column,
+// the Givens step, the report and the stop test (stop clears the RHS in the
+// mask; blocks that read the mask after that skip their chunk of a v_{j+1}
+// that is never used).
+template <typename TB>
+__global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__restrict__ V, size_t vstride, int j,
+                                               unsigned N, size_t ld, FState *fsb, Report *rep, int *stop,
+                                               const zc *__restrict__ pin, int nbin, zc *__restrict__ pout,
+                                               zc *__restrict__ vout, Cx<TB> *__restrict__ bc, unsigned chunk,
+                                               int nb, const int *active)
+{
+    constexpr int M = CSG_MAX_RESTART;
+    __shared__ zc sh[(BLK / 64) * 8];
+    __shared__ zc res[8];
+    __shared__ zc cc[OVAL];
+    __shared__ double scs;
+    __shared__ int twos;
+    const int rhs = blockIdx.y;
+    if (!active[rhs]) return;
+    FState *fs = fsb + rhs;
+    {
+        const zc *pp = pin + (size_t)rhs * OVAL * NBMAX;
+        for (int q = threadIdx.x / FG; q <= j + 1; q += BLK / FG) {
+            const zc v = group_parts(pp + q * NBMAX, nbin);
+            if (threadIdx.x % FG == 0) cc[q] = v;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double w2 = cc[j + 1].re;
+        double h2 = 0.0;
+        for (int q = 0; q <= j; ++q) h2 += cabs2(cc[q]);
+        const double w1 = w2 - h2;
+        const int two = fs->force2 || !(w1 >= 1e-4 * w2);   // force2: every column, for tests
+        const double hn = sqrt(w1);
+        twos = two;
+        scs = hn > 0.0 ? 1.0 / hn : 0.0;
+    }
+    __syncthreads();
+    const bool two = twos != 0;
+    const double sc = scs;
+    const size_t off = rhs * ld;
+    zc acc[1] = {mkc(0.0, 0.0)};
+    const unsigned c = chunk_id(nb);
+    const unsigned p0 = c * chunk + threadIdx.x, p1 = min(N, c * chunk + chunk);
+    if (p0 < p1) {
+        const unsigned last = p1 - 1;
+        for (unsigned p = p0; p < p1; p += UO * BLK) {
+            zc x[UO];
+            proj_batch(w, V, vstride, j, off, p, last, cc, x);
+#pragma unroll
+            for (int k = 0; k < UO; ++k) {
+                if (p + k * BLK >= p1) break;
+                if (two) {
+                    w[off + p + k * BLK] = x[k];
+                    acc[0].re += cabs2(x[k]);
+                } else {
+                    const zc v = sc * x[k];
+                    vout[off + p + k * BLK] = v;
+                    if (bc) bc[off + p + k * BLK] = cvt<TB>(v);
+                }
+            }
+        }
+    }
+    if (two) {
+        zc *po = pout + (size_t)rhs * OVAL * NBMAX;
+        block_sum<1>(acc, 1, sh, res);
+        if (threadIdx.x == 0) po[(j + 1) * NBMAX + c] = res[0];
+        // second-round inner products <v_i, w_1> (values 0..j) over the same
+        // chunk: each thread re-reads the w_1 points it has just written
+        for (int g = 0; 8 * g <= j; ++g) {
+            zc dots[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) dots[q] = mkc(0.0, 0.0);
+            dots8(w, V, vstride, g, j, off, p0, p1, dots);
+            store_group(dots, g, j, po, c, sh, res);
+        }
+    }
+    if (blockIdx.x != 0) return;
+    // the FGMRES state (block 0)
+    __shared__ zc col[OVAL];
+    __shared__ double cs_s[M];
+    __shared__ zc sn_s[M];
+    for (int q = threadIdx.x; q < j; q += BLK) {
+        cs_s[q] = fs->cs[q];
+        sn_s[q] = fs->sn[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 0; q <= j; ++q) {
+            col[q] = cc[q];
+            fs->hcol[q] = cc[q];
+        }
+        const double w2 = cc[j + 1].re;
+        double h2 = 0.0;
+        for (int q = 0; q <= j; ++q) h2 += cabs2(cc[q]);
+        fs->w2 = w2;
+        fs->reorth = two;
+        if (!two) givens_column(fs, rep + rhs, j, sqrt(w2 - h2), col, cs_s, sn_s, stop ? stop + rhs : nullptr);
+    }
+    __syncthreads();
+    if (!two)
+        for (int q = threadIdx.x; q <= j + 1; q += BLK) fs->R[q * M + j] = col[q];
+}
+
 template <typename TZ, int DIM>
 void launch_hdot(const LvlK<double> &H, const Cx<TZ> *z, zc *w, const zc *V, size_t vstride, int j, size_t ld,
                  zc *pout, const Launch &g, const int *active)
@@ -3613,11 +3642,12 @@ void launch_hdot(const LvlK<double> &H, const Cx<TZ> *z, zc *w, const zc *V, siz
 }
 
 template <typename TB>
-void launch_proj0(zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, const FState *fs, zc *pout,
-                  zc *vout, Cx<TB> *bcast, const Launch &g, const int *active)
+void launch_proj0(zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, FState *fs, Report *rep,
+                  int *stop, const zc *pin, int nbin, zc *pout, zc *vout, Cx<TB> *bcast, const Launch &g,
+                  const int *active)
 {
-    hipLaunchKernelGGL((k_proj0<TB>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, pout, vout, bcast,
-                       g.chunk, g.nb, active);
+    hipLaunchKernelGGL((k_proj0<TB>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop, pin, nbin,
+                       pout, vout, bcast, g.chunk, g.nb, active);
 }
 
 template <typename TB>
@@ -3775,8 +3805,8 @@ INST_TD(float, 3)
                                   const int *);                                                                    \
     template void launch_proj1<T>(const zc *, const zc *, size_t, int, unsigned, size_t, const FState *, zc *,     \
                                   Cx<T> *, const Launch &, const int *);                                           \
-    template void launch_proj0<T>(zc *, const zc *, size_t, int, unsigned, size_t, const FState *, zc *, zc *,     \
-                                  Cx<T> *, const Launch &, const int *);                                           \
+    template void launch_proj0<T>(zc *, const zc *, size_t, int, unsigned, size_t, FState *, Report *, int *,      \
+                                  const zc *, int, zc *, zc *, Cx<T> *, const Launch &, const int *);              \
     template void launch_uupd<T>(zc *, const Cx<T> *, size_t, unsigned, size_t, const FState *, const Launch &,    \
                                  const int *);
 
