@@ -665,10 +665,10 @@ void iter_body(csg_solve *sv, int j, hipStream_t st)
                          op->opart, f.nb, op->opart2, op->V + (j + 1) * vstride,
                          op->p.cycle_prec ? (Cx<TZ> *)op->b0 : nullptr, g, mask);
     }
-    launch_fin(FIN_CN, op->opart2, f.nb, j, op->fs, report_slot(op, j % LOOKAHEAD), sv->nrhs, st, mask, op->active);
     ProfScope ps(op, CSG_PROF_OUTER_PROJ2, st, R * N * (16.0 * (j + 3) + (op->p.cycle_prec ? 8.0 : 0.0)));
-    launch_proj1<TZ>(op->w, op->V, vstride, j, f.N, f.ld, op->fs, op->V + (j + 1) * vstride,
-                     op->p.cycle_prec ? (Cx<TZ> *)op->b0 : nullptr, g, mask);
+    launch_proj1<TZ>(op->w, op->V, vstride, j, f.N, f.ld, op->fs, report_slot(op, j % LOOKAHEAD), op->active,
+                     op->opart2, f.nb, op->V + (j + 1) * vstride, op->p.cycle_prec ? (Cx<TZ> *)op->b0 : nullptr, g,
+                     mask);
 }
 
 // Destroys every cached graph.

@@ -181,10 +181,13 @@ void launch_proj0(zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t 
                   int *stop, const zc *pin, int nbin, zc *pout, zc *vout, Cx<TB> *bcast, const Launch &g,
                   const int *active);
 
-// v_{j+1} = (w - V corr) * inv_hn, optional cycle-precision copy
+// second round of column j (columns that take it): the second-round inner
+// products summed from their partials (pin) in every block, v_{j+1} = (w1 -
+// V c) / h_{j+1,j} with its optional cycle-precision copy; block 0 advances
+// the FGMRES state (report, stop test clearing stop[rhs])
 template <typename TB>
-void launch_proj1(const zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, const FState *fs, zc *vout,
-                  Cx<TB> *bcast, const Launch &g, const int *active);
+void launch_proj1(const zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, FState *fs, Report *rep,
+                  int *stop, const zc *pin, int nbin, zc *vout, Cx<TB> *bcast, const Launch &g, const int *active);
 
 // v = w * scale (scale = fs->inv_hn), optional cycle-precision copy (cast).
 template <typename TB>
@@ -200,7 +203,7 @@ void launch_uupd(zc *u, const Cx<TZ> *Z, size_t zstride, unsigned N, size_t ld, 
                  const int *active);
 
 // finish kernels: one block per RHS
-enum FinMode { FIN_CN = 1, FIN_BEGIN = 3, FIN_BETA = 4, FIN_LS = 5 };
+enum FinMode { FIN_BEGIN = 3, FIN_BETA = 4, FIN_LS = 5 };
 void launch_fin(int mode, const zc *pin, int nbin, int j, FState *fs, Report *rep, int nrhs, hipStream_t st,
                 const int *active, int *stop = nullptr);
 

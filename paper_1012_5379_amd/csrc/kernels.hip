@@ -3014,41 +3014,6 @@ __device__ __forceinline__ void proj_batch(const zc *w, const zc *V, size_t vstr
     }
 }
 
-// Second projection and normalisation: v_{j+1} = (w - sum_i c_i v_i) / h_{j+1,j}
-// (c = corr, 1/h = inv_hn from the finish of the column), with the optional
-// cycle-precision copy of v_{j+1} (the next V-cycle's input); columns without
-// the second round return at once.
-template <typename TB>
-__global__ __launch_bounds__(BLK) void k_proj1(const zc *__restrict__ w, const zc *__restrict__ V, size_t vstride,
-                                               int j, unsigned N, size_t ld, const FState *fsb, zc *__restrict__ vout,
-                                               Cx<TB> *__restrict__ bc, unsigned chunk, int nb, const int *active)
-{
-    __shared__ zc cc[OVAL];
-    const int rhs = blockIdx.y;
-    if (!active[rhs]) return;
-    const FState *fs = fsb + rhs;
-    if (!fs->reorth) return;   // v_{j+1} already written by the first projection
-    if (threadIdx.x <= j) cc[threadIdx.x] = fs->corr[threadIdx.x];
-    __syncthreads();
-    const double sc = fs->inv_hn;
-    const size_t off = rhs * ld;
-    const unsigned c = chunk_id(nb);
-    const unsigned p0 = c * chunk + threadIdx.x, p1 = min(N, c * chunk + chunk);
-    if (p0 >= p1) return;
-    const unsigned last = p1 - 1;
-    for (unsigned p = p0; p < p1; p += UO * BLK) {
-        zc x[UO];
-        proj_batch(w, V, vstride, j, off, p, last, cc, x);
-#pragma unroll
-        for (int k = 0; k < UO; ++k) {
-            if (p + k * BLK >= p1) break;
-            const zc v = sc * x[k];
-            vout[off + p + k * BLK] = v;
-            if (bc) bc[off + p + k * BLK] = cvt<TB>(v);
-        }
-    }
-}
-
 // v = w / h (scale from the FGMRES state), optional cycle-precision copy.
 template <typename TB>
 __global__ __launch_bounds__(BLK) void k_vnorm(const zc *w, zc *v, Cx<TB> *__restrict__ bc, unsigned N, size_t ld,
@@ -3212,10 +3177,7 @@ __global__ __launch_bounds__(FT) void k_fin(int mode, const zc *__restrict__ pin
                                             Report *rep, const int *active, int *stop)
 {
     constexpr int M = CSG_MAX_RESTART;
-    __shared__ zc val[OVAL];
-    __shared__ zc col[OVAL];
-    __shared__ double cs_s[M];
-    __shared__ zc sn_s[M];
+    __shared__ zc val[2];
     const int rhs = blockIdx.x;
     if (!active[rhs]) return;
     FState *fs = fsb + rhs;
@@ -3243,52 +3205,16 @@ __global__ __launch_bounds__(FT) void k_fin(int mode, const zc *__restrict__ pin
         for (int i = threadIdx.x; i < k; i += FT) fs->y[i] = gy[i];
         return;
     }
-    // FIN_CN finishes a column only when it took the second round
-    if (mode == FIN_CN && !fs->reorth) return;
-    // values: FIN_CN: 0..j+1; FIN_BEGIN: 0, 1; others: 0
-    const int nv = mode == FIN_CN ? j + 2 : (mode == FIN_BEGIN ? 2 : 1);
+    // values: FIN_BEGIN: 0, 1; FIN_BETA: 0
+    const int nv = mode == FIN_BEGIN ? 2 : 1;
     const int grp = threadIdx.x / FG;
     for (int q = grp; q < nv; q += FT / FG) {
         const zc v = group_parts(pp + q * NBMAX, nbin);
         if (threadIdx.x % FG == 0) val[q] = v;
     }
-    if (mode == FIN_CN) {
-        for (int q = threadIdx.x; q < j; q += FT) {
-            cs_s[q] = fs->cs[q];
-            sn_s[q] = fs->sn[q];
-        }
-        if (mode == FIN_CN)
-            for (int q = threadIdx.x; q <= j; q += FT) col[q] = fs->hcol[q];
-    }
     __syncthreads();
-    if (mode == FIN_CN) {
-        // second-round coefficients c (values 0..j) and ||w1||^2 of the first
-        // projection (value j+1): h_{j+1,j}^2 = ||w1||^2 - ||c||^2, the norm of
-        // w1 - V c for orthonormal V.  A difference at rounding level of
-        // ||w1||^2 means w1 lies in span(V): breakdown, h = 0.
-        for (int q = threadIdx.x; q <= j; q += FT) {
-            const zc h = col[q] + val[q];
-            fs->corr[q] = val[q];
-            fs->hcol[q] = h;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double c2 = 0.0;
-            for (int q = 0; q <= j; ++q) {
-                col[q] = col[q] + val[q];
-                c2 += cabs2(val[q]);
-            }
-            const double w2 = val[j + 1].re, h2 = w2 - c2;
-            givens_column(fs, rep + rhs, j, h2 > 1e-13 * w2 ? sqrt(h2) : 0.0, col, cs_s, sn_s,
-                          stop ? stop + rhs : nullptr);
-        }
-        __syncthreads();
-        for (int q = threadIdx.x; q <= j + 1; q += FT) fs->R[q * M + j] = col[q];
-        return;
-    }
     if (threadIdx.x != 0) return;
-    switch (mode) {
-    default: {
+    {
         // FIN_BEGIN / FIN_BETA: start of a restart cycle
         const double beta = sqrt(val[0].re);
         if (mode == FIN_BEGIN) fs->nchi = sqrt(val[1].re);
@@ -3301,7 +3227,6 @@ __global__ __launch_bounds__(FT) void k_fin(int mode, const zc *__restrict__ pin
         rep[rhs].est = est;
         rep[rhs].hn = fs->nchi;
         rep[rhs].finite = isfinite(est) && isfinite(fs->nchi);
-    }
     }
 }
 
@@ -3633,6 +3558,92 @@ __global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__r
         for (int q = threadIdx.x; q <= j + 1; q += BLK) fs->R[q * M + j] = col[q];
 }
 
+// Second round of column j, finished and applied in one launch (columns
+// whose first round was final return at once).  Every block sums the
+// second-round inner products c_i = <v_i, w1> (i <= j) and ||w1||^2 from their
+// partials, in the order the finish kernel uses; h_{j+1,j}^2 = ||w1||^2 -
+// ||c||^2 is the norm of w1 - V c for orthonormal V (a difference at rounding
+// level of ||w1||^2 means w1 lies in span(V): breakdown, h = 0), and the block
+// writes its chunk of v_{j+1} = (w1 - V c) / h_{j+1,j} with the optional
+// cycle-precision copy.  Block 0 then advances the FGMRES state: the column
+// h + c, the Givens step, the report and the stop test.
+template <typename TB>
+__global__ __launch_bounds__(BLK) void k_proj1(const zc *__restrict__ w, const zc *__restrict__ V, size_t vstride,
+                                               int j, unsigned N, size_t ld, FState *fsb, Report *rep, int *stop,
+                                               const zc *__restrict__ pin, int nbin, zc *__restrict__ vout,
+                                               Cx<TB> *__restrict__ bc, unsigned chunk, int nb, const int *active)
+{
+    constexpr int M = CSG_MAX_RESTART;
+    __shared__ zc cc[OVAL];
+    __shared__ double scs;
+    const int rhs = blockIdx.y;
+    if (!active[rhs]) return;
+    FState *fs = fsb + rhs;
+    if (!fs->reorth) return;   // v_{j+1} already written by the first projection
+    {
+        const zc *pp = pin + (size_t)rhs * OVAL * NBMAX;
+        for (int q = threadIdx.x / FG; q <= j + 1; q += BLK / FG) {
+            const zc v = group_parts(pp + q * NBMAX, nbin);
+            if (threadIdx.x % FG == 0) cc[q] = v;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double c2 = 0.0;
+        for (int q = 0; q <= j; ++q) c2 += cabs2(cc[q]);
+        const double w2 = cc[j + 1].re, h2 = w2 - c2;
+        const double hn = h2 > 1e-13 * w2 ? sqrt(h2) : 0.0;
+        scs = hn > 0.0 ? 1.0 / hn : 0.0;
+    }
+    __syncthreads();
+    const double sc = scs;
+    const size_t off = rhs * ld;
+    const unsigned c = chunk_id(nb);
+    const unsigned p0 = c * chunk + threadIdx.x, p1 = min(N, c * chunk + chunk);
+    if (p0 < p1) {
+        const unsigned last = p1 - 1;
+        for (unsigned p = p0; p < p1; p += UO * BLK) {
+            zc x[UO];
+            proj_batch(w, V, vstride, j, off, p, last, cc, x);
+#pragma unroll
+            for (int k = 0; k < UO; ++k) {
+                if (p + k * BLK >= p1) break;
+                const zc v = sc * x[k];
+                vout[off + p + k * BLK] = v;
+                if (bc) bc[off + p + k * BLK] = cvt<TB>(v);
+            }
+        }
+    }
+    if (blockIdx.x != 0) return;
+    // the FGMRES state (block 0)
+    __shared__ zc col[OVAL];
+    __shared__ double cs_s[M];
+    __shared__ zc sn_s[M];
+    for (int q = threadIdx.x; q < j; q += BLK) {
+        cs_s[q] = fs->cs[q];
+        sn_s[q] = fs->sn[q];
+    }
+    for (int q = threadIdx.x; q <= j; q += BLK) {
+        const zc h1 = fs->hcol[q];
+        col[q] = h1;
+        fs->corr[q] = cc[q];
+        fs->hcol[q] = h1 + cc[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double c2 = 0.0;
+        for (int q = 0; q <= j; ++q) {
+            col[q] = col[q] + cc[q];
+            c2 += cabs2(cc[q]);
+        }
+        const double w2 = cc[j + 1].re, h2 = w2 - c2;
+        givens_column(fs, rep + rhs, j, h2 > 1e-13 * w2 ? sqrt(h2) : 0.0, col, cs_s, sn_s,
+                      stop ? stop + rhs : nullptr);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q <= j + 1; q += BLK) fs->R[q * M + j] = col[q];
+}
+
 template <typename TZ, int DIM>
 void launch_hdot(const LvlK<double> &H, const Cx<TZ> *z, zc *w, const zc *V, size_t vstride, int j, size_t ld,
                  zc *pout, const Launch &g, const int *active)
@@ -3651,11 +3662,11 @@ void launch_proj0(zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t 
 }
 
 template <typename TB>
-void launch_proj1(const zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, const FState *fs, zc *vout,
-                  Cx<TB> *bcast, const Launch &g, const int *active)
+void launch_proj1(const zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, FState *fs, Report *rep,
+                  int *stop, const zc *pin, int nbin, zc *vout, Cx<TB> *bcast, const Launch &g, const int *active)
 {
-    hipLaunchKernelGGL((k_proj1<TB>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, vout, bcast, g.chunk,
-                       g.nb, active);
+    hipLaunchKernelGGL((k_proj1<TB>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop, pin, nbin,
+                       vout, bcast, g.chunk, g.nb, active);
 }
 
 template <typename TB>
@@ -3803,8 +3814,8 @@ INST_TD(float, 3)
                                    const int *);                                                                   \
     template void launch_vnorm<T>(const zc *, zc *, Cx<T> *, unsigned, size_t, const FState *, const Launch &,     \
                                   const int *);                                                                    \
-    template void launch_proj1<T>(const zc *, const zc *, size_t, int, unsigned, size_t, const FState *, zc *,     \
-                                  Cx<T> *, const Launch &, const int *);                                           \
+    template void launch_proj1<T>(const zc *, const zc *, size_t, int, unsigned, size_t, FState *, Report *,       \
+                                  int *, const zc *, int, zc *, Cx<T> *, const Launch &, const int *);             \
     template void launch_proj0<T>(zc *, const zc *, size_t, int, unsigned, size_t, FState *, Report *, int *,      \
                                   const zc *, int, zc *, zc *, Cx<T> *, const Launch &, const int *);              \
     template void launch_uupd<T>(zc *, const Cx<T> *, size_t, unsigned, size_t, const FState *, const Launch &,    \
