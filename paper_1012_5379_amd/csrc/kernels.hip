@@ -356,6 +356,18 @@ __device__ __forceinline__ Cx<T> *pick(const Basis<T> &B, int j)
     return r;
 }
 
+// B.u[j] = v with a run-time j, written as a select per slot: an indexed
+// store would place the whole pointer array in scratch memory, and pointers
+// read back from there lose their address space (shared-memory vectors are
+// then reached by flat accesses behind scratch loads).
+template <typename T>
+__device__ __forceinline__ void place(Basis<T> &B, int j, Cx<T> *v)
+{
+#pragma unroll
+    for (int q = 0; q <= CSG_MAX_S; ++q)
+        if (q == j) B.u[q] = v;
+}
+
 template <typename T, int DIM>
 __device__ __forceinline__ void body_apply(const LvlK<T> &L, const Cx<T> *x, Cx<T> *y, unsigned p0, unsigned p1,
                                            unsigned st)
@@ -2571,11 +2583,10 @@ __device__ __forceinline__ void tsten_resid(const TSten<T, DIM, MP> &S, const Cx
 // pass j+1 (as body_os): u_{j+1} at the thread's points into B.u[j+1], then,
 // after a barrier, w_{j+1} = A u_{j+1} from there, with the same sums
 template <typename T, int DIM, int SB, int MP, int NA>
-__device__ __forceinline__ void tsten_os(const TSten<T, DIM, MP> &S, const Basis<T> &B, const Cx<T> *win,
-                                         Cx<T> *wout, int j, T sj, const Cx<T> (&cu)[SB], unsigned N,
-                                         zc (&acc)[NA], bool wn)
+__device__ __forceinline__ void tsten_os(const TSten<T, DIM, MP> &S, const Basis<T> &B, Cx<T> *un,
+                                         const Cx<T> *win, Cx<T> *wout, int j, T sj, const Cx<T> (&cu)[SB],
+                                         unsigned N, zc (&acc)[NA], bool wn)
 {
-    Cx<T> *un = pick(B, j + 1);
     Cx<T> uq[MP][SB - 1], uc[MP];
 #pragma unroll
     for (int k = 0; k < MP; ++k) {
@@ -2615,7 +2626,8 @@ __device__ __forceinline__ void tsten_os(const TSten<T, DIM, MP> &S, const Basis
 
 // tail_steps on one shared-memory level with its register stencils
 template <typename T, int DIM, int SB, int MP>
-__device__ __forceinline__ void tsten_steps(const TSten<T, DIM, MP> &S, unsigned N, const Basis<T> &B, Cx<T> *w0, Cx<T> *w1, int s,
+__device__ __forceinline__ void tsten_steps(const TSten<T, DIM, MP> &S, unsigned N, const Basis<T> &B, Cx<T> *u1,
+                                            Cx<T> *w0, Cx<T> *w1, int s,
                             double tiny, GState *gs, zc *sh, zc *res, zc *fold)
 {
     if (norm_from_sums<T>() && s == 1) {
@@ -2637,7 +2649,10 @@ __device__ __forceinline__ void tsten_steps(const TSten<T, DIM, MP> &S, unsigned
 #pragma unroll
             for (int q = 0; q <= SB; ++q) acc[q] = mkc(0.0, 0.0);
             const bool wn = norm_from_sums<T>() && j + 2 == s;
-            tsten_os<T, DIM, SB, MP, SB + 1>(S, B, win, wout, j, (T)sj, cu, N, acc, wn);
+            // u_{j+1} at u1 + j N: an offset from a shared-memory base rather than
+            // a pick among the basis pointers (which the compiler turns into an
+            // indexed table in scratch memory, and flat accesses behind it)
+            tsten_os<T, DIM, SB, MP, SB + 1>(S, B, u1 + (size_t)j * N, win, wout, j, (T)sj, cu, N, acc, wn);
             tail_sum<SB + 1>(acc, j + 3 + (wn ? 1 : 0), sh, res);
         } else if constexpr (!norm_from_sums<T>()) {
             // explicit form: u_s and its norm
@@ -2743,7 +2758,7 @@ __global__ __launch_bounds__(TB) void k_tail_lds(const TLev<T> *__restrict__ lev
         }
         Basis<T> B;
         for (int q = 0; q <= CSG_MAX_S; ++q) B.u[q] = f.u[q];
-        if (norm_from_sums<T>()) B.u[s] = f.w[(s - 1) & 1];   // closing combines w_{s-1} in place of u_s
+        if (norm_from_sums<T>()) place(B, s, ((s - 1) & 1) ? f.w[1] : f.w[0]);   // closing combines w_{s-1} in place of u_s
         for (int k = 0; k < nu1; ++k) {
             if (k == 0) {
                 B.u[0] = f.b;
@@ -2752,7 +2767,7 @@ __global__ __launch_bounds__(TB) void k_tail_lds(const TLev<T> *__restrict__ lev
                 __syncthreads();
                 B.u[0] = f.u[0];
             }
-            tsten_steps<T, DIM, SB, MP>(S, F.N, B, f.w[0], f.w[1], s, tiny, &gs, sh, res, fold);
+            tsten_steps<T, DIM, SB, MP>(S, F.N, B, f.u[1], f.w[0], f.w[1], s, tiny, &gs, sh, res, fold);
             Cx<T> cx[SB], cr[SB];
             const int kk = tail_close<T, SB>(&gs, s, Rs, ys, crs, ax, ar, &ks, fold, cx, cr);
             if (k == nu1 - 1)
@@ -2781,11 +2796,11 @@ __global__ __launch_bounds__(TB) void k_tail_lds(const TLev<T> *__restrict__ lev
         if (nu2 == 0) continue;
         Basis<T> B;
         for (int q = 0; q <= CSG_MAX_S; ++q) B.u[q] = f.u[q];
-        if (norm_from_sums<T>()) B.u[s] = f.w[(s - 1) & 1];
+        if (norm_from_sums<T>()) place(B, s, ((s - 1) & 1) ? f.w[1] : f.w[0]);
         for (int k = 0; k < nu2; ++k) {
             tsten_resid<T, DIM, MP>(S, f.x, f.b, f.u[0], F.N);
             __syncthreads();
-            tsten_steps<T, DIM, SB, MP>(S, F.N, B, f.w[0], f.w[1], s, tiny, &gs, sh, res, fold);
+            tsten_steps<T, DIM, SB, MP>(S, F.N, B, f.u[1], f.w[0], f.w[1], s, tiny, &gs, sh, res, fold);
             Cx<T> cx[SB], cr[SB];
             const int kk = tail_close<T, SB>(&gs, s, Rs, ys, crs, ax, ar, &ks, fold, cx, cr);
             body_upd<T, SB>(f.x, 1, B, kk, cx, 0, t, F.N, TB);
@@ -2830,7 +2845,7 @@ __global__ __launch_bounds__(TB) void k_tail(const TLev<T> *__restrict__ lev, in
         }
         Basis<T> B;
         for (int q = 0; q <= CSG_MAX_S; ++q) B.u[q] = Fd.u[q];
-        if (norm_from_sums<T>()) B.u[s] = Fd.w[(s - 1) & 1];   // closing combines w_{s-1} in place of u_s
+        if (norm_from_sums<T>()) place(B, s, ((s - 1) & 1) ? Fd.w[1] : Fd.w[0]);   // closing combines w_{s-1} in place of u_s
         for (int k = 0; k < nu1; ++k) {
             if (k == 0) {
                 B.u[0] = const_cast<Cx<T> *>(b) - offf;
@@ -2878,7 +2893,7 @@ __global__ __launch_bounds__(TB) void k_tail(const TLev<T> *__restrict__ lev, in
         Basis<T> B;
         for (int q = 0; q <= CSG_MAX_S; ++q) B.u[q] = Fd.u[q];
         B.u[0] = Fd.r;
-        if (norm_from_sums<T>()) B.u[s] = Fd.w[(s - 1) & 1];
+        if (norm_from_sums<T>()) place(B, s, ((s - 1) & 1) ? Fd.w[1] : Fd.w[0]);
         for (int k = 0; k < nu2; ++k) {
             if (k > 0) {
                 body_resid<T, DIM>(F, x, b, Fd.r + offf, t, F.N, TB);
