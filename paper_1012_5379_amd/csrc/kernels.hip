@@ -2624,6 +2624,62 @@ __device__ __forceinline__ void tsten_os(const TSten<T, DIM, MP> &S, const Basis
     }
 }
 
+// Closing pass of the last pre-smoothing sweep on a shared-memory tail level,
+// then the restriction (as body_upd_res, in two phases): each thread forms
+// the Arnoldi residual r = sum_i cr_i u_i at its own fine points into rbuf
+// (a stencil output the closing does not read) and updates x there; after a
+// barrier, bc = 2^-d P^T r per coarse point from rbuf.  Every fine value is
+// formed once instead of once per coarse footprint that covers it; the sums
+// are the same, in the same order.
+template <typename T, int DIM, int SB, int MP>
+__device__ __forceinline__ void tail_upd_res(Cx<T> *xx, int accumulate, const Basis<T> &B, int k,
+                                             const Cx<T> (&cx)[SB], const Cx<T> (&cr)[SB], const LvlK<T> &F,
+                                             const LvlK<T> &C, Cx<T> *rbuf, Cx<T> *bb)
+{
+#pragma unroll
+    for (int kk = 0; kk < MP; ++kk) {
+        const unsigned p = threadIdx.x + kk * TB;
+        if (p >= F.N) break;
+        Cx<T> uv[SB];
+#pragma unroll
+        for (int q = 0; q < SB; ++q)
+            if (q <= k) uv[q] = B.u[q][p];
+        Cx<T> r = mkc<T>(0, 0);
+#pragma unroll
+        for (int q = 0; q < SB; ++q)
+            if (q <= k) r = cfma(cr[q], uv[q], r);
+        rbuf[p] = r;
+        Cx<T> v = accumulate ? xx[p] : mkc<T>(0, 0);
+#pragma unroll
+        for (int q = 0; q < SB - 1; ++q)
+            if (q < k) v = cfma(cx[q], uv[q], v);
+        xx[p] = v;
+    }
+    __syncthreads();
+    const T scale = (DIM == 2) ? (T)0.25 : (T)0.125;
+    for (unsigned pc = threadIdx.x; pc < C.N; pc += TB) {
+        unsigned I, J, K;
+        decomp<DIM>(pc, C.nx, C.ny, I, J, K);
+        const RAx rx = raxis(I, C.nx, F.nx);
+        const RAx ry = raxis(J, C.ny, F.ny);
+        const RAx rz = (DIM == 3) ? raxis(K, C.nz, F.nz) : RAx{0, 1, 1};
+        Cx<T> acc = mkc<T>(0, 0);
+#pragma unroll
+        for (int qz = 0; qz < (DIM == 3 ? 3 : 1); ++qz)
+#pragma unroll
+            for (int qy = 0; qy < 3; ++qy)
+#pragma unroll
+                for (int qx = 0; qx < 3; ++qx) {
+                    if (qz >= rz.n || qy >= ry.n || qx >= rx.n) continue;
+                    const unsigned fp = ((rz.lo + qz) * F.ny + (ry.lo + qy)) * F.nx + (rx.lo + qx);
+                    T wgt = (T)(rw(qx) * rw(qy));
+                    if (DIM == 3) wgt *= (T)rw(qz);
+                    acc = acc + wgt * rbuf[fp];
+                }
+        bb[pc] = scale * acc;
+    }
+}
+
 // tail_steps on one shared-memory level with its register stencils
 template <typename T, int DIM, int SB, int MP>
 __device__ __forceinline__ void tsten_steps(const TSten<T, DIM, MP> &S, unsigned N, const Basis<T> &B, Cx<T> *u1,
@@ -2771,7 +2827,7 @@ __global__ __launch_bounds__(TB) void k_tail_lds(const TLev<T> *__restrict__ lev
             Cx<T> cx[SB], cr[SB];
             const int kk = tail_close<T, SB>(&gs, s, Rs, ys, crs, ax, ar, &ks, fold, cx, cr);
             if (k == nu1 - 1)
-                body_upd_res<T, DIM, SB>(f.x, k > 0, B, kk, cx, cr, F, C, c.b, 0, t, C.N, TB);
+                tail_upd_res<T, DIM, SB, MP>(f.x, k > 0, B, kk, cx, cr, F, C, (s & 1) ? f.w[1] : f.w[0], c.b);
             else
                 body_upd<T, SB>(f.x, k > 0, B, kk, cx, 0, t, F.N, TB);
             __syncthreads();
