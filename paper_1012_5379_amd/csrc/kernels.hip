@@ -2846,7 +2846,8 @@ __global__ __launch_bounds__(TB) void k_tail_lds(const TLev<T> *__restrict__ lev
     for (int l = L - 2; l >= lt; --l) {
         const LvlK<T> F = tlvl(lev[l]), C = tlvl(lev[l + 1]);
         const LdsLev<T> f = level(l), c = level(l + 1);
-        if (nu2 > 0) tsten_load<T, DIM, MP>(F, S);
+        // the last pre-smoothed level's stencils are still in S
+        if (nu2 > 0 && !(l == L - 2 && nu1 > 0)) tsten_load<T, DIM, MP>(F, S);
         body_prolong<T, DIM>(F, C, c.x, nu1 > 0 ? f.x : nullptr, f.x, t, F.N, TB);
         __syncthreads();
         if (nu2 == 0) continue;
