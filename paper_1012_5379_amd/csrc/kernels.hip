@@ -2738,7 +2738,8 @@ __device__ __forceinline__ void tsten_steps(const TSten<T, DIM, MP> &S, unsigned
                     if (i < s) fold[i] = cvt<double>(cu[i]);
                 fold[s] = mkc(sj, 0.0);
             }
-            __syncthreads();
+            // no barrier: only thread 0 reads these, in the closing least
+            // squares that follows, whose own barrier publishes its results
         }
     }
 }
