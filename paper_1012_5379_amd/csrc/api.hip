@@ -747,7 +747,7 @@ void upload_masks(csg_solve *sv)
 }
 
 // The event of report slot `slot` (column j of a cycle: j % LOOKAHEAD; cycle
-// begin / end: LOOKAHEAD), whose reports k_fin wrote to pinned host memory.
+// begin / end: LOOKAHEAD), whose reports the projection passes (or, at a restart, k_fin) wrote to pinned host memory.
 void enqueue_report(csg_solve *sv, int slot) { hipEventRecord(sv->op->evq[slot], sv->st); }
 
 // The event of the report the host reads next, or null when none is queued.

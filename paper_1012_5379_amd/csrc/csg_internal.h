@@ -212,7 +212,7 @@ struct csg_operator {
     csg::FState *fs;                  // [max_rhs]
     int *active;                      // [max_rhs] device mask of RHS still iterating
     int *ones;                        // [max_rhs] device all-ones mask
-    csg::Report *rep_host;            // pinned host reports: LOOKAHEAD + 1 slots of max_rhs, written by k_fin
+    csg::Report *rep_host;            // pinned host reports: LOOKAHEAD + 1 slots of max_rhs, written by k_proj0/k_proj1 and k_fin
     csg::Report *rep_dev;             // the same memory as the device addresses it
     hipEvent_t evq[csg::LOOKAHEAD + 1];   // one per report slot (the last: cycle begin / end)
     size_t ws_used;

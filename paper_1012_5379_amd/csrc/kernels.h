@@ -174,8 +174,8 @@ void launch_hdot(const LvlK<double> &H, const Cx<TZ> *z, zc *w, const zc *V, siz
 // first round of column j: the inner products of k_hdot summed from their
 // partials (pin) in every block, w1 = w - V h kept in w with the second
 // round's partials (pout) when the column takes the second round, else
-// written normalised as v_{j+1}; block 0 advances the FGMRES state (report,
-// stop test clearing stop[rhs]) as the finish kernel does for a final column
+// written normalised as v_{j+1}; block 0 advances the FGMRES state (Givens
+// step, report, stop test clearing stop[rhs]) for a final column
 template <typename TB>
 void launch_proj0(zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, FState *fs, Report *rep,
                   int *stop, const zc *pin, int nbin, zc *pout, zc *vout, Cx<TB> *bcast, const Launch &g,
@@ -202,7 +202,7 @@ template <typename TZ>
 void launch_uupd(zc *u, const Cx<TZ> *Z, size_t zstride, unsigned N, size_t ld, const FState *fs, const Launch &g,
                  const int *active);
 
-// finish kernels: one block per RHS
+// finish kernel (start of a restart cycle, least squares): one block per RHS
 enum FinMode { FIN_BEGIN = 3, FIN_BETA = 4, FIN_LS = 5 };
 void launch_fin(int mode, const zc *pin, int nbin, int j, FState *fs, Report *rep, int nrhs, hipStream_t st,
                 const int *active, int *stop = nullptr);

@@ -3177,7 +3177,7 @@ __global__ __launch_bounds__(BLK) void k_uupd(zc *__restrict__ u, const Cx<TZ> *
     }
 }
 
-constexpr int FT = 1024;   // threads of the finish kernel
+constexpr int FT = 1024;   // threads of the finish kernel (restarts, least squares)
 constexpr int FG = 32;     // lanes that reduce one value
 
 // Sum of the partials of value q by FG consecutive lanes (independent loads,
@@ -3517,16 +3517,16 @@ void launch_coarse(const Cx<T> *minvT, int n, const Cx<T> *b, Cx<T> *x, size_t l
 
 // First round of column j, finished and applied in one launch.  Every block
 // sums the inner products of k_hdot (h_i = <v_i, w>, i <= j, and ||w||^2) from
-// their partials, in the order the finish kernel uses, and takes the same
-// decision: with ||w1||^2 = ||w||^2 - ||h||^2 (w1 = w - V h, V orthonormal)
+// their partials (group_parts: a fixed order, so every block gets the same
+// bits) and takes the same decision: with ||w1||^2 = ||w||^2 - ||h||^2 (w1 = w - V h, V orthonormal)
 // the column is final when ||w1|| >= ||w|| / 100 (at most ~100 eps of
 // orthogonality lost); then h_{j+1,j} = ||w1|| and the block writes its chunk
 // of v_{j+1} = w1 / h_{j+1,j} and its optional cycle-precision copy.
 // Otherwise it keeps w1 in w and writes the second round's partials into
 // pout (a buffer apart from pin, which other blocks may still be reading):
 // <v_i, w1> (values 0..j, a second pass over the block's chunk) and ||w1||^2
-// (value j+1).  Block 0 then advances the FGMRES state as the finish kernel
-// would: the column h, the flag of the second round and, for a final column,
+// (value j+1).  Block 0 then advances the FGMRES state: the column h, the
+// flag of the second round and, for a final column,
 // the Givens step, the report and the stop test (stop clears the RHS in the
 // mask; blocks that read the mask after that skip their chunk of a v_{j+1}
 // that is never used).
@@ -3634,7 +3634,7 @@ __global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__r
 // Second round of column j, finished and applied in one launch (columns
 // whose first round was final return at once).  Every block sums the
 // second-round inner products c_i = <v_i, w1> (i <= j) and ||w1||^2 from their
-// partials, in the order the finish kernel uses; h_{j+1,j}^2 = ||w1||^2 -
+// partials (group_parts, as in k_proj0); h_{j+1,j}^2 = ||w1||^2 -
 // ||c||^2 is the norm of w1 - V c for orthonormal V (a difference at rounding
 // level of ||w1||^2 means w1 lies in span(V): breakdown, h = 0), and the block
 // writes its chunk of v_{j+1} = (w1 - V c) / h_{j+1,j} with the optional
