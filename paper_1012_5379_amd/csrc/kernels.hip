@@ -1256,9 +1256,9 @@ __global__ __launch_bounds__(BLK) void k_os_tile(LvlK<T> L, Basis<T> B, const Cx
 
 // Pass 0 on one 2-D tile (see launch_st0_tile): u_0 on the tile and its
 // one-point halo into shared memory (zero outside the level), then w_0 = A u_0
-// on the tile's points with <u_0, w_0>, ||u_0||^2 and (NA = 3) ||w_0||^2.  The
-// loads go in batches of TILE_PB points per thread (phi kept for phase 2), the
-// tile's stencil tables are staged in shared memory, as in k_os_tile.
+// on the tile's points with <u_0, w_0>, ||u_0||^2 and (NA = 3) ||w_0||^2.  All
+// of a thread's loads are issued together (phi kept for phase 2), the tile's
+// stencil tables are staged in shared memory, as in k_os_tile.
 template <typename T, int NA>
 __global__ __launch_bounds__(BLK) void k_st0_tile(LvlK<T> L, const Cx<T> *__restrict__ u0, Cx<T> *__restrict__ w,
                                                   size_t ld, zc *__restrict__ pout, TileGeo tg, int ntile,
@@ -1292,13 +1292,16 @@ __global__ __launch_bounds__(BLK) void k_st0_tile(LvlK<T> L, const Cx<T> *__rest
     const T tre = tsrc->re, tim = tsrc->im;
     T phq[TILE_MAXE];
     size_t pq[TILE_MAXE];
+    // one batch: this pass holds a single vector per point, so all of a
+    // thread's points fit in registers and the tile waits for memory once
+    constexpr int PB = TILE_MAXE;
 #pragma unroll
-    for (int b0 = 0; b0 < TILE_MAXE; b0 += TILE_PB) {
+    for (int b0 = 0; b0 < TILE_MAXE; b0 += PB) {
         if (b0 * BLK >= HN) break;   // the same for every thread of the block
-        Cx<T> v[TILE_PB];
-        bool ok[TILE_PB];
+        Cx<T> v[PB];
+        bool ok[PB];
 #pragma unroll
-        for (int i = 0; i < TILE_PB; ++i) {
+        for (int i = 0; i < PB; ++i) {
             const int it = b0 + i;
             if (it >= TILE_MAXE) break;
             const int e = threadIdx.x + it * BLK;
@@ -1310,7 +1313,7 @@ __global__ __launch_bounds__(BLK) void k_st0_tile(LvlK<T> L, const Cx<T> *__rest
             phq[it] = L.phi[pq[it]];
         }
 #pragma unroll
-        for (int i = 0; i < TILE_PB; ++i) {
+        for (int i = 0; i < PB; ++i) {
             const int it = b0 + i;
             if (it >= TILE_MAXE) break;
             const int e = threadIdx.x + it * BLK;
