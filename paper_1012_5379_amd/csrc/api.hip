@@ -292,6 +292,15 @@ bool tiled(const csg_operator *op, int l)
     return DIM == 2 && op->tiles && op->p.s <= 3 && tile_fits(op->lev[l].tile);
 }
 
+// w = H z and its inner products on the finest level's tiles (the tiles of the
+// fused pass, which share the grid of H)
+template <int DIM>
+bool hdot_tiled(const csg_operator *op)
+{
+    const TileGeo &t = op->lev[0].tile;
+    return DIM == 2 && op->hdot_tiles && tile_fits(t) && (int)(t.ntx * t.nty) <= NBMAX;
+}
+
 // Whether the up path of level l runs as one tiled pass (interpolation,
 // residual and pass 0 of the post-sweep).
 template <typename T, int DIM>
@@ -653,7 +662,10 @@ void iter_body(csg_solve *sv, int j, hipStream_t st)
     const double N = f.N, R = sv->nrhs;
     {
         ProfScope ps(op, CSG_PROF_OUTER_H, st, R * N * (sizeof(Cx<TZ>) + 16.0 * (j + 2)) + 8.0 * N);
-        launch_hdot<TZ, DIM>(lvlH(op), z, op->w, op->V, vstride, j, f.ld, op->opart, g, mask);
+        if (hdot_tiled<DIM>(op))
+            launch_hdot_tile<TZ>(lvlH(op), z, op->w, op->V, vstride, j, f.ld, op->opart, f.tile, sv->nrhs, st, mask);
+        else
+            launch_hdot<TZ, DIM>(lvlH(op), z, op->w, op->V, vstride, j, f.ld, op->opart, g, mask);
     }
     {
         // first round finished and applied: writes v_{j+1} (and advances the
@@ -662,7 +674,7 @@ void iter_body(csg_solve *sv, int j, hipStream_t st)
         // second round's inner products in the same launch
         ProfScope ps(op, CSG_PROF_OUTER_CGS1, st, R * N * (16.0 * (j + 3) + (op->p.cycle_prec ? 8.0 : 0.0)));
         launch_proj0<TZ>(op->w, op->V, vstride, j, f.N, f.ld, op->fs, report_slot(op, j % LOOKAHEAD), op->active,
-                         op->opart, f.nb, op->opart2, op->V + (j + 1) * vstride,
+                         op->opart, hdot_tiled<DIM>(op) ? (int)(f.tile.ntx * f.tile.nty) : f.nb, op->opart2, op->V + (j + 1) * vstride,
                          op->p.cycle_prec ? (Cx<TZ> *)op->b0 : nullptr, g, mask);
     }
     ProfScope ps(op, CSG_PROF_OUTER_PROJ2, st, R * N * (16.0 * (j + 3) + (op->p.cycle_prec ? 8.0 : 0.0)));
@@ -988,6 +1000,8 @@ int csg_operator_create(const csg_params *p, const double *phi_host, void *ws_de
         if (p->fuse_max) op->fuse_max = p->fuse_max < 0 ? 0 : p->fuse_max;
         op->tiles = true;
         if (const char *e = getenv("CSG_TILES")) op->tiles = atoi(e) != 0;
+        op->hdot_tiles = true;
+        if (const char *e = getenv("CSG_HDOT_TILES")) op->hdot_tiles = atoi(e) != 0;
         op->up_tiles = true;
         if (const char *e = getenv("CSG_UP_TILES")) op->up_tiles = atoi(e) != 0;
         op->down_tiles = true;

@@ -198,6 +198,7 @@ struct csg_operator {
     size_t tail_lds;                  // shared-memory bytes of the tail's vectors (0: tail in global memory)
     long fuse_max;                    // levels up to this size use the fused Arnoldi passes
     bool tiles;                       // 2-D levels whose tiles fit use the LDS-staged fused pass
+    bool hdot_tiles;                  // w = H z and its inner products on the finest level's tiles
     bool up_tiles;                    // ... and the LDS-staged interpolation + residual + pass 0
     bool down_tiles;                  // ... and the LDS-staged closing + restriction + next pass 0
     bool fuse_upd;                    // coarse post-sweep updates applied by the finer up-path pass

@@ -171,6 +171,11 @@ template <typename TZ, int DIM>
 void launch_hdot(const LvlK<double> &H, const Cx<TZ> *z, zc *w, const zc *V, size_t vstride, int j, size_t ld,
                  zc *pout, const Launch &g, const int *active);
 
+// the same on the finest level's 2-D tiles (one partial per tile)
+template <typename TZ>
+void launch_hdot_tile(const LvlK<double> &H, const Cx<TZ> *z, zc *w, const zc *V, size_t vstride, int j, size_t ld,
+                      zc *pout, const TileGeo &tg, int nrhs, hipStream_t st, const int *active);
+
 // first round of column j: the inner products of k_hdot summed from their
 // partials (pin) in every block, w1 = w - V h kept in w with the second
 // round's partials (pout) when the column takes the second round, else

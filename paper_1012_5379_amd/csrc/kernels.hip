@@ -3073,6 +3073,132 @@ __global__ __launch_bounds__(BLK) void k_hdot(LvlK<double> H, const Cx<TZ> *__re
     if (threadIdx.x == 0) po[(j + 1) * NBMAX + c] = res[0];
 }
 
+// k_hdot on one 2-D tile of the finest level (same partials, one per tile):
+// z on the tile and its one-point halo is loaded in one batch (all of a
+// thread's points at once) into shared memory with the tile's tables of H;
+// the tile's points form w = H z from there, write it and ||w||^2, and keep
+// w in their own shared-memory slots for the inner products <v_i, w> (groups
+// of 8 basis vectors, four points per batch), so w is never read back from
+// memory.
+template <typename TZ>
+__global__ __launch_bounds__(BLK) void k_hdot_tile(LvlK<double> H, const Cx<TZ> *__restrict__ z,
+                                                   zc *__restrict__ w, const zc *__restrict__ V, size_t vstride,
+                                                   int j, size_t ld, zc *__restrict__ pout, TileGeo tg, int ntile,
+                                                   const int *active)
+{
+    __shared__ zc sh[(BLK / 64) * 8];
+    __shared__ zc res[8];
+    __shared__ zc lz[TILE_MAXN];
+    __shared__ zc ltab[6 * TAB_MAXD];   // x lower, diag, upper; y lower, diag, upper
+    const int rhs = blockIdx.y;
+    if (!active[rhs]) return;
+    const unsigned t = chunk_id(ntile);
+    const unsigned tyi = t / tg.ntx, txi = t - tyi * tg.ntx;
+    const int nx = (int)H.nx, ny = (int)H.ny;
+    const int x0 = (int)(txi * tg.tx), y0 = (int)(tyi * tg.ty);
+    const int TX = min(x0 + (int)tg.tx, nx) - x0, TY = min(y0 + (int)tg.ty, ny) - y0;
+    const int HX = TX + 2, HY = TY + 2, HN = HX * HY;
+    const size_t off = rhs * ld;
+    const size_t pc = (size_t)y0 * nx + x0;   // a point of the level every clamped address goes to
+    int tslot = -1;
+    const zc *tsrc;
+    {
+        const int q = threadIdx.x;
+        const bool xs = q < 3 * TX;
+        const int qq = xs ? q : min(q - 3 * TX, 3 * TY - 1);
+        const int c = qq / 3, a = qq - 3 * c;
+        tsrc = (xs ? H.tab[0] + a * nx + x0 : H.tab[1] + a * ny + y0) + c;
+        if (q < 3 * TX + 3 * TY) tslot = (xs ? a : 3 + a) * TAB_MAXD + c;
+    }
+    const double tre = tsrc->re, tim = tsrc->im;
+    auto inner = [&](int e) {
+        const int ey = e / HX, ex = e - ey * HX;
+        return e < HN && ex >= 1 && ex <= HX - 2 && ey >= 1 && ey <= HY - 2;
+    };
+    Cx<TZ> zq[TILE_MAXE];
+    double phq[TILE_MAXE];
+    size_t pq[TILE_MAXE];
+    bool okq[TILE_MAXE];
+#pragma unroll
+    for (int it = 0; it < TILE_MAXE; ++it) {
+        const int e = threadIdx.x + it * BLK;
+        const int ey = e / HX, ex = e - ey * HX;
+        const int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
+        okq[it] = e < HN && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        pq[it] = okq[it] ? (size_t)gy * nx + gx : pc;
+        zq[it] = z[off + pq[it]];
+        phq[it] = H.phi[pq[it]];
+    }
+#pragma unroll
+    for (int it = 0; it < TILE_MAXE; ++it) {
+        const int e = threadIdx.x + it * BLK;
+        if (e < HN) lz[e] = okq[it] ? cvt<double>(zq[it]) : mkc(0.0, 0.0);
+    }
+    if (tslot >= 0) ltab[tslot] = mkc(tre, tim);
+    __syncthreads();
+    zc wq[TILE_MAXE];
+    zc wn[1] = {mkc(0.0, 0.0)};
+#pragma unroll
+    for (int it = 0; it < TILE_MAXE; ++it) {
+        const int e = threadIdx.x + it * BLK;
+        wq[it] = mkc(0.0, 0.0);
+        if (!inner(e)) continue;
+        const int ey = e / HX, ex = e - ey * HX;
+        const int c = ex - 1, r = ey - 1;
+        zc d = ltab[1 * TAB_MAXD + c] + ltab[4 * TAB_MAXD + r];
+        d.re -= phq[it];
+        zc a = d * lz[e];
+        a = cfma(ltab[0 * TAB_MAXD + c], lz[e - 1], a);
+        a = cfma(ltab[2 * TAB_MAXD + c], lz[e + 1], a);
+        a = cfma(ltab[3 * TAB_MAXD + r], lz[e - HX], a);
+        a = cfma(ltab[5 * TAB_MAXD + r], lz[e + HX], a);
+        w[off + pq[it]] = a;
+        wq[it] = a;
+        wn[0].re += cabs2(a);
+    }
+    __syncthreads();   // every neighbour read of z is done
+#pragma unroll
+    for (int it = 0; it < TILE_MAXE; ++it) {
+        const int e = threadIdx.x + it * BLK;
+        if (inner(e)) lz[e] = wq[it];   // a thread reads back only its own slots
+    }
+    zc *po = pout + (size_t)rhs * OVAL * NBMAX;
+    constexpr int PB = 4;
+    for (int g = 0; 8 * g <= j; ++g) {
+        zc acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = mkc(0.0, 0.0);
+#pragma unroll
+        for (int b0 = 0; b0 < TILE_MAXE; b0 += PB) {
+            if (b0 * BLK >= HN) break;   // the same for every thread of the block
+            zc vv[PB][8], wv[PB];
+            bool in[PB];
+#pragma unroll
+            for (int i = 0; i < PB; ++i) {
+                const int it = b0 + i;
+                if (it >= TILE_MAXE) break;
+                const int e = threadIdx.x + it * BLK;
+                in[i] = inner(e);
+                wv[i] = in[i] ? lz[e] : mkc(0.0, 0.0);
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (8 * g + q <= j) vv[i][q] = V[(8 * g + q) * vstride + off + pq[it]];
+            }
+#pragma unroll
+            for (int i = 0; i < PB; ++i) {
+                if (b0 + i >= TILE_MAXE) break;
+                if (!in[i]) continue;
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (8 * g + q <= j) acc[q] = cjfma(vv[i][q], wv[i], acc[q]);
+            }
+        }
+        store_group(acc, g, j, po, t, sh, res);
+    }
+    block_sum<1>(wn, 1, sh, res);
+    if (threadIdx.x == 0) po[(j + 1) * NBMAX + t] = res[0];
+}
+
 // x(p) = w(p) - sum_{q <= j} a_q v_q(p) for the U points of one batch
 __device__ __forceinline__ void proj_batch(const zc *w, const zc *V, size_t vstride, int j, size_t off, unsigned p,
                                            unsigned last, const zc *cc, zc (&x)[UO])
@@ -3728,6 +3854,15 @@ void launch_hdot(const LvlK<double> &H, const Cx<TZ> *z, zc *w, const zc *V, siz
                        g.nb, active);
 }
 
+template <typename TZ>
+void launch_hdot_tile(const LvlK<double> &H, const Cx<TZ> *z, zc *w, const zc *V, size_t vstride, int j, size_t ld,
+                      zc *pout, const TileGeo &tg, int nrhs, hipStream_t st, const int *active)
+{
+    const int ntile = (int)(tg.ntx * tg.nty);
+    hipLaunchKernelGGL((k_hdot_tile<TZ>), dim3(ntile, nrhs), dim3(BLK), 0, st, H, z, w, V, vstride, j, ld, pout, tg,
+                       ntile, active);
+}
+
 template <typename TB>
 void launch_proj0(zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, FState *fs, Report *rep,
                   int *stop, const zc *pin, int nbin, zc *pout, zc *vout, Cx<TB> *bcast, const Launch &g,
@@ -3867,6 +4002,11 @@ INST_TD(double, 2)
 INST_TD(double, 3)
 INST_TD(float, 2)
 INST_TD(float, 3)
+
+template void launch_hdot_tile<double>(const LvlK<double> &, const Cx<double> *, zc *, const zc *, size_t, int,
+                                       size_t, zc *, const TileGeo &, int, hipStream_t, const int *);
+template void launch_hdot_tile<float>(const LvlK<double> &, const Cx<float> *, zc *, const zc *, size_t, int,
+                                      size_t, zc *, const TileGeo &, int, hipStream_t, const int *);
 
 #define INST_T(T)                                                                                                  \
     template void launch_st0_tile<T>(const LvlK<T> &, const Cx<T> *, Cx<T> *, size_t, bool, zc *, const TileGeo &,  \

@@ -250,6 +250,33 @@ def test_vcycle_with_each_fused_path_off(knob, prec, monkeypatch):
         assert e <= (TOL64 if prec == 0 else TOL32["vcycle"])
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("tiles", ["1", "0"])
+def test_fgmres_with_and_without_tiled_hdot(tiles, prec, monkeypatch):
+    """w = H z and its inner products on the finest level's tiles, or over the
+    plain chunked layout: two RHS, each matching its own oracle solve
+    (complex128 cycle: iterations +-1 and solution to 1e-10; complex64 cycle:
+    the true residual reaches the tolerance)."""
+    import torch
+    monkeypatch.setenv("CSG_HDOT_TILES", tiles)
+    w = CASES["2d_ragged"]()
+    chi = np.stack([w.chi[0], rvec(w.chi.shape[1:], 171)])
+    op, orc = pair(w, max_rhs=2, cycle_prec=prec)
+    u, rc, infos = op.solve(dev(chi, torch.complex128), tol=1e-8, restart=20, maxit=400)
+    u = host(u)
+    assert rc == 0
+    for r in range(2):
+        uo, io = orc.fgmres(chi[r], tol=1e-8, restart=20, maxit=400)
+        e = rel(u[r], uo)
+        note(f"  tiles {tiles} prec {prec} rhs {r}: its gpu {infos[r]['iterations']} oracle {io.iterations} "
+             f"sol err {e:.2e} relres {infos[r]['relres_true']:.2e}")
+        if prec == 0:
+            assert abs(infos[r]["iterations"] - io.iterations) <= 1
+            assert e <= 1e-10
+        else:
+            assert infos[r]["relres_true"] <= 1e-8
+
+
 def test_fgmres_second_round_every_column(monkeypatch):
     """The outer second Gram-Schmidt round (taken only when the first round
     cancels) forced on every column: the solve still matches the oracle's
