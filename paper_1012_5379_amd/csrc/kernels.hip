@@ -3073,6 +3073,41 @@ __global__ __launch_bounds__(BLK) void k_hdot(LvlK<double> H, const Cx<TZ> *__re
     if (threadIdx.x == 0) po[(j + 1) * NBMAX + c] = res[0];
 }
 
+// Inner products <v_{8g+q}, w> (q < QN, 8g+q <= j) over a thread's tile points,
+// w in its own shared-memory slots, PB points per batch of loads.
+template <int PB, int QN>
+__device__ __forceinline__ void tile_dots(const zc *lz, const zc *V, size_t vstride, size_t off,
+                                          const size_t (&pq)[TILE_MAXE], int HN, int HX, int HY, int g, int j,
+                                          zc (&acc)[8])
+{
+#pragma unroll
+    for (int b0 = 0; b0 < TILE_MAXE; b0 += PB) {
+        if (b0 * BLK >= HN) break;   // the same for every thread of the block
+        zc vv[PB][QN], wv[PB];
+        bool in[PB];
+#pragma unroll
+        for (int i = 0; i < PB; ++i) {
+            const int it = b0 + i;
+            if (it >= TILE_MAXE) break;
+            const int e = threadIdx.x + it * BLK;
+            const int ey = e / HX, ex = e - ey * HX;
+            in[i] = e < HN && ex >= 1 && ex <= HX - 2 && ey >= 1 && ey <= HY - 2;
+            wv[i] = in[i] ? lz[e] : mkc(0.0, 0.0);
+#pragma unroll
+            for (int q = 0; q < QN; ++q)
+                if (8 * g + q <= j) vv[i][q] = V[(8 * g + q) * vstride + off + pq[it]];
+        }
+#pragma unroll
+        for (int i = 0; i < PB; ++i) {
+            if (b0 + i >= TILE_MAXE) break;
+            if (!in[i]) continue;
+#pragma unroll
+            for (int q = 0; q < QN; ++q)
+                if (8 * g + q <= j) acc[q] = cjfma(vv[i][q], wv[i], acc[q]);
+        }
+    }
+}
+
 // k_hdot on one 2-D tile of the finest level (same partials, one per tile):
 // z on the tile and its one-point halo is loaded in one batch (all of a
 // thread's points at once) into shared memory with the tile's tables of H;
@@ -3163,36 +3198,16 @@ __global__ __launch_bounds__(BLK) void k_hdot_tile(LvlK<double> H, const Cx<TZ> 
         if (inner(e)) lz[e] = wq[it];   // a thread reads back only its own slots
     }
     zc *po = pout + (size_t)rhs * OVAL * NBMAX;
-    constexpr int PB = 4;
     for (int g = 0; 8 * g <= j; ++g) {
         zc acc[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) acc[q] = mkc(0.0, 0.0);
-#pragma unroll
-        for (int b0 = 0; b0 < TILE_MAXE; b0 += PB) {
-            if (b0 * BLK >= HN) break;   // the same for every thread of the block
-            zc vv[PB][8], wv[PB];
-            bool in[PB];
-#pragma unroll
-            for (int i = 0; i < PB; ++i) {
-                const int it = b0 + i;
-                if (it >= TILE_MAXE) break;
-                const int e = threadIdx.x + it * BLK;
-                in[i] = inner(e);
-                wv[i] = in[i] ? lz[e] : mkc(0.0, 0.0);
-#pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    if (8 * g + q <= j) vv[i][q] = V[(8 * g + q) * vstride + off + pq[it]];
-            }
-#pragma unroll
-            for (int i = 0; i < PB; ++i) {
-                if (b0 + i >= TILE_MAXE) break;
-                if (!in[i]) continue;
-#pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    if (8 * g + q <= j) acc[q] = cjfma(vv[i][q], wv[i], acc[q]);
-            }
-        }
+        // a group of at most two vectors loads all of a thread's points at
+        // once, larger ones four points per batch
+        if (j - 8 * g < 2)
+            tile_dots<TILE_MAXE, 2>(lz, V, vstride, off, pq, HN, HX, HY, g, j, acc);
+        else
+            tile_dots<4, 8>(lz, V, vstride, off, pq, HN, HX, HY, g, j, acc);
         store_group(acc, g, j, po, t, sh, res);
     }
     block_sum<1>(wn, 1, sh, res);
