@@ -1169,7 +1169,9 @@ int csg_operator_destroy(csg_operator *op)
     if (!op) return CSG_OK;
     if (op->prof) csg_profile(op, CSG_PROF_OFF, 0);
     if (op->gc) {
-        hipDeviceSynchronize();
+        // a solve's graphs finished when csg_solve_end synchronised its stream;
+        // captures run on the private stream only
+        if (op->gc->cap) hipStreamSynchronize(op->gc->cap);
         drop_graphs(op);
         if (op->gc->cap) hipStreamDestroy(op->gc->cap);
         delete op->gc;

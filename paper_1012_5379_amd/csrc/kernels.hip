@@ -3663,8 +3663,7 @@ void launch_coarse(const Cx<T> *minvT, int n, const Cx<T> *b, Cx<T> *x, size_t l
 // sums the inner products of k_hdot (h_i = <v_i, w>, i <= j, and ||w||^2) from
 // their partials (group_parts: a fixed order, so every block gets the same
 // bits) and takes the same decision: with ||w1||^2 = ||w||^2 - ||h||^2 (w1 = w - V h, V orthonormal)
-// the column is final when ||w1|| >= ||w|| / 100 (at most ~100 eps of
-// orthogonality lost); then h_{j+1,j} = ||w1|| and the block writes its chunk
+// the column is final when ||w1||^2 >= ||w||^2 / 2; then h_{j+1,j} = ||w1|| and the block writes its chunk
 // of v_{j+1} = w1 / h_{j+1,j} and its optional cycle-precision copy.
 // Otherwise it keeps w1 in w and writes the second round's partials into
 // pout (a buffer apart from pin, which other blocks may still be reading):
@@ -3703,7 +3702,11 @@ __global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__r
         double h2 = 0.0;
         for (int q = 0; q <= j; ++q) h2 += cabs2(cc[q]);
         const double w1 = w2 - h2;
-        const int two = fs->force2 || !(w1 >= 1e-4 * w2);   // force2: every column, for tests
+        // Daniel-Gragg-Kaufman-Stewart criterion: one round is final when it
+        // keeps at least 1/sqrt(2) of ||w||; a laxer bound lets the error of
+        // the single round (ratio ||h|| / ||w1|| times the basis's own loss of
+        // orthogonality) compound from column to column
+        const int two = fs->force2 || !(w1 >= 0.5 * w2);   // force2: every column, for tests
         const double hn = sqrt(w1);
         twos = two;
         scs = hn > 0.0 ? 1.0 / hn : 0.0;

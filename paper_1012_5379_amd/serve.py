@@ -55,7 +55,9 @@ class Request:
         return B.make_params(**dict(self.params, max_rhs=self.nrhs, restart=self.restart, graphs=-1))
 
     def workspace_bytes(self) -> int:
-        return B.csg_workspace_bytes(self.csg_params())
+        """Device bytes the request holds while admitted: the library's
+        workspace plus the complex128 chi and u vectors of every RHS."""
+        return B.csg_workspace_bytes(self.csg_params()) + 2 * self.chi.nbytes
 
     def key(self) -> str:
         h = hashlib.sha1(repr(sorted(self.params.items())).encode())
@@ -119,7 +121,7 @@ class Engine:
             ws, op, _ = cached
             return _Active(req, slot, ws, op, chi, u, stream)
         p = req.csg_params()
-        nb = B.csg_workspace_bytes(p)
+        nb = B.csg_workspace_bytes(p)   # the library's share of req.workspace_bytes()
         with torch.cuda.stream(stream):
             ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
         phi = np.ascontiguousarray(req.phi, dtype=np.float64)

@@ -49,3 +49,22 @@ def rel(a, b):
 
 def rvec(shape, item):
     return W.rand_cvec(shape, item=item)
+
+
+# Grids with odd interval counts, unequal layers and several blocks with a
+# ragged tail, in 2-D and 3-D (shared by the per-operation parity suites).
+def cases():
+    return {
+        "c1": lambda: W.c1(),
+        "2d_ragged": lambda: W.small(dim=2, n=101, mlo=7, mhi=4, beta=0.35, kh=0.45, item=1),
+        "2d_wide": lambda: W.small(dim=2, n=300, m=21, beta=0.4, kh=0.5, item=2),
+        "3d_ragged": lambda: W.small(dim=3, n=27, mlo=3, mhi=4, beta=0.4, kh=0.4, item=3),
+    }
+
+
+def tight_oracle(orc, chi, restart=30, maxit=4000):
+    """The oracle's answer at tol 1e-12: the reference a solve stopping at a
+    looser tolerance is measured against."""
+    u, info = orc.fgmres(chi, tol=1e-12, restart=restart, maxit=maxit)
+    assert info.converged
+    return u

@@ -9,20 +9,14 @@ import numpy as np
 import pytest
 
 from synth import workloads as W
-from tests.gpu_common import dev, host, note, pair, rel, rvec, torch_cuda
+from tests.gpu_common import cases, dev, host, note, pair, rel, rvec, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
-# C1 plus grids with odd interval counts, unequal layers and several blocks
-# with a ragged tail, in 2-D and 3-D.
-CASES = {
-    "c1": lambda: W.c1(),
-    "2d_ragged": lambda: W.small(dim=2, n=101, mlo=7, mhi=4, beta=0.35, kh=0.45, item=1),
-    "2d_wide": lambda: W.small(dim=2, n=300, m=21, beta=0.4, kh=0.5, item=2),
-    "3d_ragged": lambda: W.small(dim=3, n=27, mlo=3, mhi=4, beta=0.4, kh=0.4, item=3),
-}
+CASES = cases()
 TOL64 = 1e-12
-TOL32 = {"apply": 1e-5, "restrict": 1e-5, "prolong": 1e-6, "coarse": 1e-4, "smooth": 1e-4, "vcycle": 1e-3}
+# complex64 cycle: about ten times the largest error observed on these cases
+TOL32 = {"apply": 1e-6, "restrict": 3e-6, "prolong": 5e-7, "coarse": 6e-6, "smooth": 6e-6, "vcycle": 6e-6}
 
 
 @pytest.fixture(scope="module", params=list(CASES))
@@ -98,7 +92,7 @@ def test_gmres_sweep_every_level(case, prec):
             xo, k = orc.gmres_sweep(b[r], x0[r], l=l)
             e = rel(x[r], xo)
             note(f"  sweep level {l} rhs {r}: {e:.2e} (oracle steps {k})")
-            assert e <= (TOL64 * 10 if prec == 0 else TOL32["smooth"])
+            assert e <= (TOL64 if prec == 0 else TOL32["smooth"])
 
 
 @pytest.mark.parametrize("prec", [0, 1])

@@ -45,12 +45,19 @@ def test_alone_equals_mix():
 
 def test_admission_respects_budget():
     """A budget that holds only the largest request at a time still serves
-    every request, never exceeding the budget."""
+    every request, never exceeding the budget: neither by the engine's own
+    count nor by the device memory torch actually handed out."""
+    import torch
     reqs = _requests(6)
     need = max(r.workspace_bytes() for r in reqs)
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    base = torch.cuda.memory_allocated()
     done, eng = _serve(reqs, streams=4, budget=need)
+    peak = torch.cuda.max_memory_allocated() - base
     assert len(done) == 6 and all(r.status == 0 for r in done.values())
     assert eng.high_water <= need
+    assert peak <= need + (1 << 20)   # allocation granularity
 
 
 def test_oversized_request_rejected():
