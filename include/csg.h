@@ -145,6 +145,23 @@ int csg_vcycle(const csg_operator *op, const void *b_dev, void *x_dev, int nrhs,
 int csg_smooth(const csg_operator *op, int level, const void *b_dev, void *x_dev, int nrhs,
                void *stream);
 
+/* csg_smooth for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same sweep, same results, with its own vectors (residual, u_1..u_s, w_0,
+ * w_1), reduction partials and smoother states in a static device array of
+ * 128 MiB per GPU instead of the operator's workspace.  The call allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine); the array is
+ * created with the library's code object on each GPU it runs on and held until
+ * the process ends.  Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (other streams, other threads) race and must be
+ * serialised by the caller; partials and states are cleared on every call.
+ * Errors: CSG_ENOMEM when the sweep needs more than 128 MiB, i.e.
+ * (s + 3) * nrhs * unknowns(level) * (16 or 8 bytes) plus about 82 KB per
+ * RHS of partials and states; CSG_EDEVICE if the array's device address
+ * cannot be obtained; otherwise as csg_smooth. */
+int csg_smooth_static(const csg_operator *op, int level, const void *b_dev, void *x_dev, int nrhs,
+                      void *stream);
+
 /* bc = R (b - M_level x): residual restricted by full weighting R = 2^-d P^T
  * to level+1. */
 int csg_residual_restrict(const csg_operator *op, int level, const void *b_dev,

@@ -59,6 +59,7 @@ _SIGS = {
     "csg_stencil_apply": (ip, [vp, ip, ip, vp, vp, ip, vp]),
     "csg_vcycle": (ip, [vp, vp, vp, ip, vp]),
     "csg_smooth": (ip, [vp, ip, vp, vp, ip, vp]),
+    "csg_smooth_static": (ip, [vp, ip, vp, vp, ip, vp]),
     "csg_residual_restrict": (ip, [vp, ip, vp, vp, vp, ip, vp]),
     "csg_prolong_correct": (ip, [vp, ip, vp, vp, ip, vp]),
     "csg_coarse_solve": (ip, [vp, vp, vp, ip, vp]),
@@ -167,6 +168,10 @@ def csg_vcycle(op, b, x, nrhs, stream):
 
 def csg_smooth(op, level, b, x, nrhs, stream):
     return check(lib().csg_smooth(op, level, b, x, nrhs, stream))
+
+
+def csg_smooth_static(op, level, b, x, nrhs, stream):
+    return check(lib().csg_smooth_static(op, level, b, x, nrhs, stream))
 
 
 def csg_residual_restrict(op, level, b, x, bc, nrhs, stream):

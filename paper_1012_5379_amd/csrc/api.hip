@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "kernels.h"
@@ -28,6 +29,42 @@ int fail(int code, const std::string &msg)
         hipError_t e_ = (x);                                                                    \
         if (e_ != hipSuccess) return fail(CSG_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
     } while (0)
+
+// ---------------------------------------------------------------------------
+// Scratch of csg_smooth_static (callers that cannot allocate device memory):
+// one array per GPU, created with the code object and held until the process
+// ends.  Host code never passes `scratch` itself (in host code the name is a
+// stand-in, not a device address): it uses the address hipGetSymbolAddress
+// returned for the device, kept in scratch_dev.
+// ---------------------------------------------------------------------------
+constexpr size_t SCRATCH_BYTES = (size_t)128 << 20;
+static __device__ __align__(256) char scratch[SCRATCH_BYTES];
+
+constexpr int SCRATCH_MAX_DEV = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_dev[SCRATCH_MAX_DEV];   // device address of `scratch` per device (null: not looked up yet)
+
+// The current device's address of `scratch`, looked up once per device with
+// that device current; null (with the error in g_err) on failure.
+char *scratch_dev()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= SCRATCH_MAX_DEV) {
+        g_err = "no current HIP device for the static scratch";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            g_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return nullptr;
+        }
+        g_scratch_dev[dev] = (char *)ptr;
+    }
+    return g_scratch_dev[dev];
+}
 
 // Bump allocator over the caller's workspace (base == nullptr: size only).
 struct Carver {
@@ -929,6 +966,9 @@ int csg_operator_create(const csg_params *p, const double *phi_host, void *ws_de
     std::string err;
     st = build_hierarchy(*p, phi_host, hh, err);
     if (st) return fail(st, err);
+    // the static scratch's address on this device, once per device (a failure
+    // only disables csg_smooth_static, which reports it)
+    if (!scratch_dev()) g_err = "no error";
 
     csg_operator *op = new csg_operator;
     memset(op, 0, sizeof(*op));
@@ -1241,6 +1281,49 @@ int csg_smooth(const csg_operator *op, int level, const void *b, void *x, int nr
     } else {
         if (op->p.dim == 3) sweep<double, 3>(op, level, (const zc *)b, (zc *)x, false, false, nrhs, s, op->ones);
         else sweep<double, 2>(op, level, (const zc *)b, (zc *)x, false, false, nrhs, s, op->ones);
+    }
+    return last_launch_error();
+}
+
+int csg_smooth_static(const csg_operator *op, int level, const void *b, void *x, int nrhs, void *stream)
+{
+    int st = check_op(op, nrhs);
+    if (st) return st;
+    if (level < 0 || level >= op->L) return fail(CSG_EINVAL, "bad level");
+    if (nrhs == 0) return CSG_OK;
+    if (!b || !x) return fail(CSG_EINVAL, "null vector");
+    char *base = scratch_dev();
+    if (!base) return fail(CSG_EDEVICE, g_err);
+    // the sweep's own vectors (residual, u_1..u_s, w_0, w_1), reduction
+    // partials and smoother states, carved from the scratch as from a workspace
+    csg_operator tmp = *op;
+    tmp.prof = nullptr;
+    DevLevel &lv = tmp.lev[level];
+    Carver cv(base);
+    const size_t vb = (size_t)nrhs * lv.ld * op->csize;
+    lv.r = cv.take(vb);
+    for (int i = 1; i <= op->p.s; ++i) lv.u[i] = cv.take(vb);
+    lv.w[0] = cv.take(vb);
+    lv.w[1] = cv.take(vb);
+    const size_t cleared = cv.off;
+    const size_t pb = (size_t)nrhs * NVAL * NBMAX * sizeof(zc);
+    lv.part[0] = (zc *)cv.take(pb);
+    lv.part[1] = (zc *)cv.take(pb);
+    lv.gs = (GState *)cv.take((size_t)nrhs * sizeof(GState));
+    const size_t end = (cv.off + 255) & ~(size_t)255;
+    if (end > SCRATCH_BYTES)
+        return fail(CSG_ENOMEM, "csg_smooth_static: the sweep needs " + std::to_string(end) +
+                                    " bytes of scratch, more than the " + std::to_string(SCRATCH_BYTES) + " it has");
+    hipStream_t s = (hipStream_t)stream;
+    // partials and states start at zero on every call (the array keeps the last call's contents)
+    const size_t z0 = (cleared + 255) & ~(size_t)255;
+    launch_zero16(base + z0, end - z0, s);
+    if (op->p.cycle_prec) {
+        if (op->p.dim == 3) sweep<float, 3>(&tmp, level, (const cf *)b, (cf *)x, false, false, nrhs, s, op->ones);
+        else sweep<float, 2>(&tmp, level, (const cf *)b, (cf *)x, false, false, nrhs, s, op->ones);
+    } else {
+        if (op->p.dim == 3) sweep<double, 3>(&tmp, level, (const zc *)b, (zc *)x, false, false, nrhs, s, op->ones);
+        else sweep<double, 2>(&tmp, level, (const zc *)b, (zc *)x, false, false, nrhs, s, op->ones);
     }
     return last_launch_error();
 }

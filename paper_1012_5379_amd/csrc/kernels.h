@@ -218,4 +218,7 @@ void launch_fs_params(FState *fs, double tol, int maxit, int force2, int nrhs, h
 
 void launch_copy_mask(const int *src, int *dst, int n, hipStream_t st);
 
+// bytes (a multiple of 16, 16-byte aligned) of device memory set to zero
+void launch_zero16(void *p, size_t bytes, hipStream_t st);
+
 }  // namespace csg

@@ -8,6 +8,7 @@
 // blocks of the next pass re-reduce those partials in a fixed order, so results
 // are deterministic, no atomics are used and no pass waits on another block.
 // Inner products and norms accumulate in FP64 even when vectors are complex64.
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 
@@ -3984,6 +3985,22 @@ void launch_tail(const TLev<T> *lev, int lt, int L, const Cx<T> *b_in, Cx<T> *x_
 void launch_copy_mask(const int *src, int *dst, int n, hipStream_t st)
 {
     hipLaunchKernelGGL(k_copy_mask, dim3((n + 255) / 256), dim3(256), 0, st, src, dst, n);
+}
+
+// n 16-byte words set to zero with vector stores (a kernel, not a memset node,
+// so the clear also behaves inside captured graphs)
+__global__ void k_zero16(uint4 *p, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+void launch_zero16(void *p, size_t bytes, hipStream_t st)
+{
+    const size_t n = bytes / 16;
+    if (n == 0) return;
+    const unsigned nb = (unsigned)std::min<size_t>(1024, (n + 255) / 256);
+    hipLaunchKernelGGL(k_zero16, dim3(nb), dim3(256), 0, st, (uint4 *)p, n);
 }
 
 // ---------------------------------------------------------------------------
