@@ -10,6 +10,9 @@
 
 #include <float.h>
 #include <math.h>
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -331,6 +334,7 @@ static int validate(const ora_params *p)
     if (!(p->gamma > 0.0 && p->gamma < atan(1.0))) return -1; /* gamma < pi/4 */
     if (!(p->beta >= 0.0 && p->beta < p->gamma)) return -1;
     if (p->s < 1 || p->nu1 < 0 || p->nu2 < 0 || p->levels < 0 || p->levels > ORA_MAXL) return -1;
+    if (p->smoother < 0 || p->smoother > 1 || !(p->poly_k2 >= 0.0) || !isfinite(p->poly_k2)) return -1;
     for (int a = 0; a < p->dim; ++a) {
         if (p->n[a] < 1 || p->layer_lo[a] < 0 || p->layer_hi[a] < 0) return -1;
         if (p->n[a] + p->layer_lo[a] + p->layer_hi[a] < 2) return -1;
@@ -568,6 +572,181 @@ int ora_gmres_sweep(const ora_hier *hh, int l, int s, const cplx *b, cplx *x, in
 }
 
 /* ---------------------------------------------------------------------------
+ * Third-order polynomial smoother (section 4)
+ * ------------------------------------------------------------------------- */
+
+/* Vertices of the bounding triangle of Prop. 3.1 for spacing H:
+ * t0 = -k^2, t1 = -k^2 + 4d/(H e^{i beta})^2, t2 = -k^2 + 4d/(H e^{i gamma})^2. */
+static void poly_triangle(double k2, double H, int dim, double beta, double gamma, cplx t[3])
+{
+    cplx hb = H * cexp(I * beta), hg = H * cexp(I * gamma);
+    t[0] = -k2;
+    t[1] = -k2 + 4.0 * dim / (hb * hb);
+    t[2] = -k2 + 4.0 * dim / (hg * hg);
+}
+
+/* Solve the 3x3 system A x = b by Gaussian elimination with partial pivoting. */
+static void solve3(cplx A[3][3], const cplx b[3], cplx x[3])
+{
+    cplx M[3][4];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) M[r][c] = A[r][c];
+        M[r][3] = b[r];
+    }
+    for (int k = 0; k < 3; ++k) {
+        int pr = k;
+        for (int r = k + 1; r < 3; ++r) if (cabs(M[r][k]) > cabs(M[pr][k])) pr = r;
+        for (int c = 0; c < 4; ++c) { cplx t = M[k][c]; M[k][c] = M[pr][c]; M[pr][c] = t; }
+        for (int r = k + 1; r < 3; ++r) {
+            cplx f = M[r][k] / M[k][k];
+            for (int c = k; c < 4; ++c) M[r][c] -= f * M[k][c];
+        }
+    }
+    for (int r = 2; r >= 0; --r) {
+        cplx acc = M[r][3];
+        for (int c = r + 1; c < 3; ++c) acc -= M[r][c] * x[c];
+        x[r] = acc / M[r][r];
+    }
+}
+
+/* e and f of eq. coefficients_solution: the system of eq. coefficients_system
+ * (rows: p(0) = 1, p(t1) = 0, p(t2) = 0 written for c_1..c_3 around t0) solved
+ * for the right-hand sides (1,0,0) and (1,1,1). */
+static void poly_ef(const cplx t[3], cplx e[3], cplx f[3])
+{
+    cplx A[3][3];
+    const cplx x[3] = {-t[0], t[1] - t[0], t[2] - t[0]};
+    for (int r = 0; r < 3; ++r) {
+        A[r][0] = x[r];
+        A[r][1] = x[r] * x[r];
+        A[r][2] = x[r] * x[r] * x[r];
+    }
+    const cplx b100[3] = {1.0, 0.0, 0.0}, b111[3] = {1.0, 1.0, 1.0};
+    solve3(A, b100, e);
+    solve3(A, b111, f);
+}
+
+/* First- and second-order coefficients of |p|^2 along the edge t0 + rho w,
+ * w = e^{-2 i beta}, with c_0 = e^{i varphi}, c_j = e_j - e^{i varphi} f_j:
+ * |p|^2 = 1 + 2 rho Re(conj(c0) c1 w) + rho^2 (|c1|^2 + 2 Re(conj(c0) c2 w^2)) + O(rho^3). */
+static void poly_FS(const cplx e[3], const cplx f[3], double beta, double varphi, double *F, double *S)
+{
+    cplx w = cexp(-2.0 * I * beta), c0 = cexp(I * varphi);
+    cplx c1 = e[0] - c0 * f[0], c2 = e[1] - c0 * f[1];
+    *F = creal(conj(c0) * c1 * w);
+    *S = cabs(c1) * cabs(c1) + 2.0 * creal(conj(c0) * c2 * w * w);
+}
+
+int ora_poly_conditions(double k2, double H, int dim, double beta, double gamma, double varphi, double *F,
+                        double *S)
+{
+    if (!(H > 0.0) || dim < 1 || dim > 3 || !F || !S) return -1;
+    cplx t[3], e[3], f[3];
+    poly_triangle(k2, H, dim, beta, gamma, t);
+    poly_ef(t, e, f);
+    poly_FS(e, f, beta, varphi, F, S);
+    return 0;
+}
+
+/* The set {varphi : |a| cos(varphi - arg a) < g} as an arc: centre and half
+ * width in [0, pi]; *all / *none flag the whole circle / the empty set. */
+static void arc_below(cplx a, double g, double *centre, double *half, int *all, int *none)
+{
+    double m = cabs(a);
+    *all = *none = 0;
+    *centre = carg(a) + M_PI;
+    *half = 0.0;
+    if (m <= g) { *all = 1; *half = M_PI; return; }      /* cos < g/|a| with g/|a| >= 1 */
+    if (m <= -g) { *none = 1; return; }                  /* g/|a| <= -1 */
+    *half = M_PI - acos(g / m);
+}
+
+int ora_poly_level(const ora_hier *hh, int l, ora_poly *out)
+{
+    if (!hh || l < 0 || l >= hh->L || !out) return -1;
+    const ora_params *p = &hh->p;
+    double k2 = p->poly_k2;
+    if (k2 == 0.0) {
+        /* reading: the mean of phi over the finest unknowns (the paper's k is constant) */
+        const ora_level *F0 = &hh->lev[0];
+        double acc = 0.0;
+        for (long i = 0; i < F0->N; ++i) acc += F0->phi[i];
+        k2 = acc / (double)F0->N;
+    }
+    out->k2 = k2;
+    out->H = ldexp(p->h, l);
+    poly_triangle(k2, out->H, p->dim, p->beta, p->gamma, out->t);
+    poly_ef(out->t, out->e, out->f);
+    const cplx *e = out->e, *f = out->f;
+    /* F(varphi) = Re(e^{-i varphi} e1 w) - Re(f1 w) < 0 and
+     * S(varphi) = K + Re(e^{-i varphi} Z) < 0, with w = e^{-2i beta},
+     * K = |e1|^2 + |f1|^2 - 2 Re(f2 w^2), Z = 2 (e2 w^2 - e1 conj(f1)) */
+    const cplx w = cexp(-2.0 * I * p->beta);
+    double cA, rA, cB, rB;
+    int allA, noneA, allB, noneB;
+    arc_below(e[0] * w, creal(f[0] * w), &cA, &rA, &allA, &noneA);
+    const double K = cabs(e[0]) * cabs(e[0]) + cabs(f[0]) * cabs(f[0]) - 2.0 * creal(f[1] * w * w);
+    arc_below(2.0 * (e[1] * w * w - e[0] * conj(f[0])), -K, &cB, &rB, &allB, &noneB);
+    double varphi = 0.0;
+    int conds = 2;
+    if (!noneA && !noneB) {
+        if (allA && allB) { varphi = 0.0; conds = 0; }
+        else if (allA) { varphi = cB; conds = 0; }
+        else if (allB) { varphi = cA; conds = 0; }
+        else {
+            /* arc B around arc A's centre: offsets d - 2pi, d, d + 2pi; the
+             * longest overlap's midpoint */
+            double d = remainder(cB - cA, 2.0 * M_PI), best = 0.0, mid = 0.0;
+            for (int q = -1; q <= 1; ++q) {
+                double lo = fmax(-rA, d + 2.0 * M_PI * q - rB), hi = fmin(rA, d + 2.0 * M_PI * q + rB);
+                if (hi - lo > best) { best = hi - lo; mid = 0.5 * (lo + hi); }
+            }
+            if (best > 0.0) { varphi = cA + mid; conds = 0; }
+            else { varphi = cA; conds = 1; }
+        }
+    } else if (!noneA) {
+        varphi = allA ? 0.0 : cA;
+        conds = 1;
+    }
+    varphi = remainder(varphi, 2.0 * M_PI);
+    if (varphi < 0.0) varphi += 2.0 * M_PI;
+    out->varphi = varphi;
+    out->conds = conds;
+    const cplx c0 = cexp(I * varphi);
+    out->c[0] = c0;
+    for (int j = 0; j < 3; ++j) out->c[j + 1] = e[j] - c0 * f[j];
+    /* roots: t1 and t2 by construction; the third from the leading coefficient
+     * (p(t) = c3 (t - t1)(t - t2)(t - t3) and p(0) = 1) */
+    out->omega[0] = 1.0 / out->t[1];
+    out->omega[1] = 1.0 / out->t[2];
+    out->omega[2] = -out->c[3] * out->t[1] * out->t[2];
+    return 0;
+}
+
+int ora_poly_sweep(const ora_hier *hh, int l, const cplx *b, cplx *x, int x_is_zero)
+{
+    if (!hh || l < 0 || l >= hh->L) return -1;
+    ora_poly pl;
+    ora_poly_level(hh, l, &pl);
+    const long N = hh->lev[l].N;
+    cplx *r = cvec(N);
+    for (int i = 0; i < 3; ++i) {
+        /* x <- x + omega_i (b - M x): the error is multiplied by (1 - omega_i M) */
+        if (x_is_zero && i == 0) {
+            memcpy(r, b, sizeof(cplx) * (size_t)N);
+        } else {
+            applyM(hh, l, x, r);
+#pragma omp parallel for schedule(static)
+            for (long q = 0; q < N; ++q) r[q] = b[q] - r[q];
+        }
+        if (x_is_zero && i == 0) memset(x, 0, sizeof(cplx) * (size_t)N);
+        axpy(N, pl.omega[i], r, x);
+    }
+    free(r);
+    return 3;
+}
+
+/* ---------------------------------------------------------------------------
  * V(nu1, nu2)-cycle (section 3.1): nu1 GMRES(s) pre-sweeps from a zero guess,
  * restriction of the residual, recursion, interpolated correction, nu2
  * post-sweeps; exact solve on the coarsest level.
@@ -580,7 +759,11 @@ int ora_vcycle_level(const ora_hier *hh, int l, const cplx *b, cplx *x)
     if (l == hh->L - 1) return ora_coarse_solve(hh, b, x);
     memset(x, 0, sizeof(cplx) * (size_t)N);
     int zero = 1;
-    for (int k = 0; k < hh->p.nu1; ++k) { ora_gmres_sweep(hh, l, hh->p.s, b, x, zero); zero = 0; }
+    for (int k = 0; k < hh->p.nu1; ++k) {
+        if (hh->p.smoother == 1) ora_poly_sweep(hh, l, b, x, zero);
+        else ora_gmres_sweep(hh, l, hh->p.s, b, x, zero);
+        zero = 0;
+    }
     cplx *r = cvec(N);
     if (zero) {
         memcpy(r, b, sizeof(cplx) * (size_t)N);
@@ -594,7 +777,10 @@ int ora_vcycle_level(const ora_hier *hh, int l, const cplx *b, cplx *x)
     ora_restrict(hh, l, r, bc);
     ora_vcycle_level(hh, l + 1, bc, ec);
     ora_prolong_add(hh, l, ec, x);
-    for (int k = 0; k < hh->p.nu2; ++k) ora_gmres_sweep(hh, l, hh->p.s, b, x, 0);
+    for (int k = 0; k < hh->p.nu2; ++k) {
+        if (hh->p.smoother == 1) ora_poly_sweep(hh, l, b, x, 0);
+        else ora_gmres_sweep(hh, l, hh->p.s, b, x, 0);
+    }
     free(r); free(bc); free(ec);
     return 0;
 }

@@ -40,6 +40,8 @@ typedef struct ora_params {
     int levels;         /* multigrid levels; 0 = coarsen until <= 9 intervals per axis */
     int s;              /* GMRES(s) smoother length */
     int nu1, nu2;       /* pre- and post-smoothing sweeps */
+    int smoother;       /* 0 = GMRES(s) (section 3.1), 1 = third-order polynomial (section 4) */
+    double poly_k2;     /* k^2 of the polynomial's vertex t0 = -k^2; 0 = mean of phi on the finest level */
 } ora_params;
 
 typedef struct ora_info {
@@ -91,6 +93,34 @@ int ora_vcycle(const ora_hier *hh, const double complex *b, double complex *x);
 int ora_fgmres(const ora_hier *hh, const double complex *chi, double complex *u,
                double tol, int m, int maxit, int use_x0, ora_info *info,
                double *hist, int hist_len);
+
+/* Third-order polynomial smoother of section 4 on one level.  The bounding
+ * triangle of Prop. 3.1 has vertices t0 = -k^2, t1 = -k^2 + 4d/(H e^{i beta})^2,
+ * t2 = -k^2 + 4d/(H e^{i gamma})^2 with H = 2^l h the level's spacing.  p is
+ * fixed by p(0) = 1, p(t1) = p(t2) = 0, p(t0) = e^{i varphi} (eq.
+ * coefficients_system, coefficients_solution); varphi is the midpoint of the
+ * angles meeting both necessary stability conditions (first-order and
+ * second-order along the edge t0 t1), see ora_poly_conditions. */
+typedef struct ora_poly {
+    double k2;          /* k^2 of t0 */
+    double H;           /* the level's spacing 2^l h */
+    double complex t[3];      /* t0, t1, t2 */
+    double complex e[3], f[3];/* eq. coefficients_system solved for b = (1,0,0) and (1,1,1) */
+    double varphi;      /* p(t0) = e^{i varphi} */
+    double complex c[4];      /* p(t) = sum_j c_j (t - t0)^j */
+    double complex omega[3];  /* p(t) = (1 - omega_1 t)(1 - omega_2 t)(1 - omega_3 t) */
+    int conds;          /* 0: both conditions met; 1: only the first-order one; 2: neither */
+} ora_poly;
+int ora_poly_level(const ora_hier *hh, int l, ora_poly *out);
+/* Coefficients of |p(t0 + rho e^{-2i beta})|^2 = 1 + 2 rho F + rho^2 S + O(rho^3)
+ * along the top edge of the triangle for the polynomial of varphi: F < 0 is
+ * the first-order condition (eq. firstorder_varphi), S < 0 the second-order one
+ * (eq. secondorder_varphi).  k2, H, dim, beta, gamma define the triangle. */
+int ora_poly_conditions(double k2, double H, int dim, double beta, double gamma, double varphi,
+                        double *F, double *S);
+/* One polynomial smoothing sweep on M_l: x <- x + omega_i (b - M_l x) for
+ * i = 1, 2, 3, so the error is multiplied by p(M_l).  x_is_zero: x = 0 on entry. */
+int ora_poly_sweep(const ora_hier *hh, int l, const double complex *b, double complex *x, int x_is_zero);
 
 /* Deterministic Hermitian inner product sum conj(x) y in fixed 4096-element
  * chunks, summed in chunk order (independent of the thread count). */

@@ -38,11 +38,18 @@ class _Params(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("h", C.c_double),
                 ("layer_lo", C.c_int * 3), ("layer_hi", C.c_int * 3),
                 ("gamma", C.c_double), ("beta", C.c_double), ("levels", C.c_int),
-                ("s", C.c_int), ("nu1", C.c_int), ("nu2", C.c_int)]
+                ("s", C.c_int), ("nu1", C.c_int), ("nu2", C.c_int), ("smoother", C.c_int),
+                ("poly_k2", C.c_double)]
 
 
 class _Cplx(C.Structure):
     _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
+class _Poly(C.Structure):
+    _fields_ = [("k2", C.c_double), ("H", C.c_double), ("t", _Cplx * 3), ("e", _Cplx * 3),
+                ("f", _Cplx * 3), ("varphi", C.c_double), ("c", _Cplx * 4), ("omega", _Cplx * 3),
+                ("conds", C.c_int)]
 
 
 class _Info(C.Structure):
@@ -77,6 +84,10 @@ def lib():
         L.ora_vcycle_level.argtypes = [vp, ip, vp, vp]
         L.ora_vcycle.argtypes = [vp, vp, vp]
         L.ora_fgmres.argtypes = [vp, vp, vp, dp, ip, ip, ip, C.POINTER(_Info), vp, ip]
+        L.ora_poly_level.argtypes = [vp, ip, C.POINTER(_Poly)]
+        L.ora_poly_conditions.argtypes = [dp, dp, ip, dp, dp, dp, C.POINTER(C.c_double),
+                                          C.POINTER(C.c_double)]
+        L.ora_poly_sweep.argtypes = [vp, ip, vp, vp, ip]
         L.ora_threads.restype = C.c_int
         L.ora_threads.argtypes = []
         L.ora_dot.restype = _Cplx
@@ -99,6 +110,8 @@ class Params:
     s: int = 3
     nu1: int = 1
     nu2: int = 1
+    smoother: int = 0        # 0 = GMRES(s), 1 = third-order polynomial (section 4)
+    poly_k2: float = 0.0     # k^2 of the polynomial's vertex t0; 0 = mean of phi
 
     def c(self) -> _Params:
         p = _Params()
@@ -109,6 +122,7 @@ class Params:
             p.layer_hi[a] = int(self.layer_hi[a]) if a < len(self.layer_hi) else 0
         p.h, p.gamma, p.beta = float(self.h), float(self.gamma), float(self.beta)
         p.levels, p.s, p.nu1, p.nu2 = int(self.levels), int(self.s), int(self.nu1), int(self.nu2)
+        p.smoother, p.poly_k2 = int(self.smoother), float(self.poly_k2)
         return p
 
     def unknown_shape(self) -> tuple:
@@ -225,6 +239,23 @@ class Oracle:
         k = lib().ora_gmres_sweep(self._h, l, s, pb, x.ctypes.data, int(zero))
         return x, k
 
+    def poly(self, l: int) -> dict:
+        """The level's third-order polynomial smoother (section 4)."""
+        pl = _Poly()
+        if lib().ora_poly_level(self._h, l, C.byref(pl)):
+            raise ValueError("bad level")
+        cx = lambda a: np.array([complex(v.re, v.im) for v in a])
+        return dict(k2=pl.k2, H=pl.H, t=cx(pl.t), e=cx(pl.e), f=cx(pl.f), varphi=pl.varphi,
+                    c=cx(pl.c), omega=cx(pl.omega), conds=pl.conds)
+
+    def poly_sweep(self, b, x=None, l: int = 0):
+        """One polynomial smoothing sweep: x + q(M) (b - M x), error times p(M)."""
+        b, pb = _c(b.reshape(self.shape(l)), np.complex128)
+        zero = x is None
+        x = self._out(l) if zero else np.array(x, dtype=np.complex128, order="C").reshape(self.shape(l))
+        lib().ora_poly_sweep(self._h, l, pb, x.ctypes.data, int(zero))
+        return x
+
     def vcycle(self, b, l: int = 0) -> np.ndarray:
         b, pb = _c(b.reshape(self.shape(l)), np.complex128)
         x = self._out(l)
@@ -245,6 +276,15 @@ class Oracle:
         inf = Info(info.iterations, info.restarts, info.vcycles, bool(info.converged),
                    info.relres_true, info.relres_est, hist[: info.iterations].copy())
         return u, inf
+
+
+def poly_conditions(k2, H, dim, beta, gamma, varphi):
+    """(F, S): |p(t0 + rho e^{-2i beta})|^2 = 1 + 2 rho F + rho^2 S + O(rho^3)."""
+    F, S = C.c_double(0), C.c_double(0)
+    if lib().ora_poly_conditions(float(k2), float(H), int(dim), float(beta), float(gamma), float(varphi),
+                                 C.byref(F), C.byref(S)):
+        raise ValueError("bad arguments")
+    return F.value, S.value
 
 
 def dot(x: np.ndarray, y: np.ndarray) -> complex:
