@@ -83,6 +83,19 @@ typedef struct csg_params {
     int tail_max;
     int fuse_max;
     int graphs;
+    /* smoother of every non-coarsest level (section 4 compares the two):
+     *   0  GMRES(s) sweeps (section 3.1)
+     *   1  the third-order polynomial smoother of section 4: per level
+     *      p(t) = (1 - w1 t)(1 - w2 t)(1 - w3 t) with p(0) = 1, p(t1) = p(t2) = 0
+     *      and p(t0) = e^{i varphi} on the bounding triangle t0 = -k^2,
+     *      t1 = -k^2 + 4d/(2^l h e^{i beta})^2, t2 = -k^2 + 4d/(2^l h e^{i gamma})^2
+     *      (Prop. 3.1), varphi the midpoint of the angles meeting the first-
+     *      and second-order stability conditions (eq. firstorder_varphi,
+     *      eq. secondorder_varphi); one sweep = three Richardson steps
+     *      x += w_i (b - M x), no inner products
+     * poly_k2: k^2 of t0 (0 = the mean of phi over the finest unknowns). */
+    int smoother;
+    double poly_k2;
 } csg_params;
 
 typedef struct csg_operator csg_operator;
@@ -140,8 +153,9 @@ int csg_stencil_apply(const csg_operator *op, int which, int level, const void *
  * x_dev: nrhs finest-level vectors in the cycle precision; must not overlap. */
 int csg_vcycle(const csg_operator *op, const void *b_dev, void *x_dev, int nrhs, void *stream);
 
-/* One GMRES(s) sweep on M_level for M x = b, x updated in place (section 3.1:
- * a GMRES solve on the error stopped after s iterations). */
+/* One smoothing sweep on M_level for M x = b, x updated in place: GMRES(s)
+ * (section 3.1: a GMRES solve on the error stopped after s iterations) or,
+ * with csg_params.smoother = 1, the polynomial sweep of section 4. */
 int csg_smooth(const csg_operator *op, int level, const void *b_dev, void *x_dev, int nrhs,
                void *stream);
 
@@ -156,11 +170,18 @@ int csg_smooth(const csg_operator *op, int level, const void *b_dev, void *x_dev
  * overlap on one GPU (other streams, other threads) race and must be
  * serialised by the caller; partials and states are cleared on every call.
  * Errors: CSG_ENOMEM when the sweep needs more than 128 MiB, i.e.
- * (s + 3) * nrhs * unknowns(level) * (16 or 8 bytes) plus about 82 KB per
- * RHS of partials and states; CSG_EDEVICE if the array's device address
+ * (s + 3) * nrhs * unknowns(level) * (16 or 8 bytes) (s + 4 with the
+ * polynomial smoother) plus about 82 KB per RHS of partials and states; CSG_EDEVICE if the array's device address
  * cannot be obtained; otherwise as csg_smooth. */
 int csg_smooth_static(const csg_operator *op, int level, const void *b_dev, void *x_dev, int nrhs,
                       void *stream);
+
+/* The polynomial smoother of `level` (section 4; built for every level at
+ * create whatever csg_params.smoother says): varphi, the three Richardson
+ * weights omega[0..5] = (re, im) of w1, w2, w3 in the order the sweep applies
+ * them, and conds = 0 when varphi meets both necessary stability conditions,
+ * 1 when only the first-order one can be met, 2 when neither. */
+int csg_poly_info(const csg_operator *op, int level, double *varphi, double omega[6], int *conds);
 
 /* bc = R (b - M_level x): residual restricted by full weighting R = 2^-d P^T
  * to level+1. */

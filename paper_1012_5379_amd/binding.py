@@ -27,7 +27,8 @@ class csg_params(C.Structure):
                 ("layer_lo", C.c_int * 3), ("layer_hi", C.c_int * 3), ("gamma", C.c_double),
                 ("beta", C.c_double), ("levels", C.c_int), ("s", C.c_int), ("nu1", C.c_int),
                 ("nu2", C.c_int), ("cycle_prec", C.c_int), ("max_rhs", C.c_int), ("restart", C.c_int),
-                ("tail_max", C.c_int), ("fuse_max", C.c_int), ("graphs", C.c_int)]
+                ("tail_max", C.c_int), ("fuse_max", C.c_int), ("graphs", C.c_int),
+                ("smoother", C.c_int), ("poly_k2", C.c_double)]
 
 
 class csg_solve_info(C.Structure):
@@ -60,6 +61,7 @@ _SIGS = {
     "csg_vcycle": (ip, [vp, vp, vp, ip, vp]),
     "csg_smooth": (ip, [vp, ip, vp, vp, ip, vp]),
     "csg_smooth_static": (ip, [vp, ip, vp, vp, ip, vp]),
+    "csg_poly_info": (ip, [vp, ip, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int)]),
     "csg_residual_restrict": (ip, [vp, ip, vp, vp, vp, ip, vp]),
     "csg_prolong_correct": (ip, [vp, ip, vp, vp, ip, vp]),
     "csg_coarse_solve": (ip, [vp, vp, vp, ip, vp]),
@@ -108,7 +110,8 @@ def check(code: int) -> int:
 
 def make_params(dim=2, n=(64, 64, 0), h=1 / 64, layer_lo=(8, 8, 0), layer_hi=(8, 8, 0),
                 gamma=0.5235987755982988, beta=0.4, levels=0, s=3, nu1=1, nu2=1, cycle_prec=0,
-                max_rhs=1, restart=30, tail_max=0, fuse_max=0, graphs=0) -> csg_params:
+                max_rhs=1, restart=30, tail_max=0, fuse_max=0, graphs=0, smoother=0,
+                poly_k2=0.0) -> csg_params:
     p = csg_params()
     p.dim = int(dim)
     for a in range(3):
@@ -119,6 +122,7 @@ def make_params(dim=2, n=(64, 64, 0), h=1 / 64, layer_lo=(8, 8, 0), layer_hi=(8,
     p.levels, p.s, p.nu1, p.nu2 = int(levels), int(s), int(nu1), int(nu2)
     p.cycle_prec, p.max_rhs, p.restart = int(cycle_prec), int(max_rhs), int(restart)
     p.tail_max, p.fuse_max, p.graphs = int(tail_max), int(fuse_max), int(graphs)
+    p.smoother, p.poly_k2 = int(smoother), float(poly_k2)
     return p
 
 
@@ -172,6 +176,13 @@ def csg_smooth(op, level, b, x, nrhs, stream):
 
 def csg_smooth_static(op, level, b, x, nrhs, stream):
     return check(lib().csg_smooth_static(op, level, b, x, nrhs, stream))
+
+
+def csg_poly_info(op, level):
+    """(varphi, [w1, w2, w3] as complex, conds) of the level's polynomial smoother."""
+    vphi, om, conds = C.c_double(0), (C.c_double * 6)(), C.c_int(0)
+    check(lib().csg_poly_info(op, level, C.byref(vphi), om, C.byref(conds)))
+    return vphi.value, [complex(om[2 * i], om[2 * i + 1]) for i in range(3)], conds.value
 
 
 def csg_residual_restrict(op, level, b, x, bc, nrhs, stream):

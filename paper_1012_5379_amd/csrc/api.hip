@@ -293,6 +293,24 @@ Bytes bytes_of(const csg_operator *op, int nrhs)
 double vcycle_bytes(const csg_operator *op, int nrhs)
 {
     const Bytes b = bytes_of(op, nrhs);
+    if (op->p.smoother == 1) {
+        // polynomial smoother: a tiled 2-D sweep reads x, b, phi and writes x
+        // once (3z + p; 2z + p from zero), the untiled one does so per step
+        const bool tl = op->p.dim == 2 && op->poly_tiles;
+        const double sz = b.z * b.R, sp = b.p;
+        double tot = b.coarse(op->nc);
+        for (int l = 0; l + 1 < op->L; ++l) {
+            const double N = op->lev[l].N, Nc = op->lev[l + 1].N;
+            const double sweep0 = tl ? N * (2 * sz + sp) : N * (2 * sz + sp + 2 * (3 * sz + sp));
+            const double sweep1 = tl ? N * (3 * sz + sp) : 3 * N * (3 * sz + sp);
+            const int nu1 = op->p.nu1, nu2 = op->p.nu2;
+            if (nu1 > 0) tot += sweep0 + (nu1 - 1) * sweep1;
+            tot += N * ((nu1 > 0 ? 2 : 1) * sz + (nu1 > 0 ? sp : 0)) + Nc * sz;   // restriction (of the residual)
+            if (nu2 > 0) tot += nu2 * sweep1 + Nc * sz + (tl ? 0.0 : 2 * N * sz);   // interpolated start
+            else tot += b.prolong(nu1 > 0, N, Nc);
+        }
+        return tot;
+    }
     const int s = op->p.s, nu1 = op->p.nu1, nu2 = op->p.nu2;
     double tot = b.coarse(op->nc);
     for (int l = 0; l + 1 < op->L; ++l) {
@@ -598,9 +616,118 @@ void vcycle_impl(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, h
     }
 }
 
+// ---------------------------------------------------------------------------
+// Third-order polynomial smoother (section 4)
+// ---------------------------------------------------------------------------
+
+template <typename T>
+void poly_weights(const DevLevel &lv, Cx<T> (&w)[3])
+{
+    for (int i = 0; i < 3; ++i) w[i] = mkc<T>((T)lv.omega[i].real(), (T)lv.omega[i].imag());
+}
+
+// `sweeps` polynomial sweeps on level l from the start value xi + P ec (either
+// may be null: zero, no correction) into out, which aliases neither xi nor the
+// level's r, w[0], w[1] (its temporaries).  2-D levels run a whole sweep per
+// tiled launch (the tile kernel cannot update in place, so a chain of sweeps
+// alternates between out and r, ending in out); otherwise each sweep is three
+// Richardson passes through w[0] and w[1].
+template <typename T, int DIM>
+void poly_smooth(const csg_operator *op, int l, const Cx<T> *b, const Cx<T> *xi, const Cx<T> *ec, Cx<T> *out,
+                 int sweeps, int nrhs, hipStream_t st, const int *active)
+{
+    const DevLevel &lv = op->lev[l];
+    Cx<T> w[3];
+    poly_weights<T>(lv, w);
+    const LvlK<T> L = lvl<T>(op, l);
+    const LvlK<T> C = l + 1 < op->L ? lvl<T>(op, l + 1) : L;
+    const size_t ldc = l + 1 < op->L ? op->lev[l + 1].ld : 0;
+    Cx<T> *tmp = (Cx<T> *)lv.r;
+    if (DIM == 2 && op->poly_tiles) {
+        const Cx<T> *src = xi;
+        for (int k = 0; k < sweeps; ++k) {
+            Cx<T> *dst = ((sweeps - 1 - k) % 2 == 0) ? out : tmp;
+            launch_poly_tile<T>(L, C, k == 0 ? ec : nullptr, src, b, dst, w, lv.ld, ldc, nrhs, st, active);
+            src = dst;
+        }
+        return;
+    }
+    const Launch g = lch(op, l, nrhs, st);
+    const Cx<T> *src = xi;
+    if (ec) {
+        launch_prolong<T, DIM>(L, C, ec, xi, tmp, lv.ld, ldc, g, active);
+        src = tmp;
+    }
+    Cx<T> *W0 = (Cx<T> *)lv.w[0], *W1 = (Cx<T> *)lv.w[1];
+    for (int k = 0; k < sweeps; ++k) {
+        launch_rich<T, DIM>(L, src, b, W0, w[0], lv.ld, g, active);
+        launch_rich<T, DIM>(L, W0, b, W1, w[1], lv.ld, g, active);
+        launch_rich<T, DIM>(L, W1, b, out, w[2], lv.ld, g, active);
+        src = out;
+    }
+}
+
+// x = V_{nu1,nu2}(0; b) with the polynomial smoother on every non-coarsest
+// level: pre-sweeps from zero, restriction of the residual, recursion,
+// interpolated correction feeding the post-sweeps; dense coarsest solve.
+template <typename T, int DIM>
+void vcycle_poly(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, hipStream_t st, const int *active)
+{
+    const int L = op->L;
+    const int nu1 = op->p.nu1, nu2 = op->p.nu2;
+    for (int l = 0; l + 1 < L; ++l) {
+        const DevLevel &lv = op->lev[l];
+        const DevLevel &cl = op->lev[l + 1];
+        const Cx<T> *b = l == 0 ? b0 : (const Cx<T> *)lv.b;
+        Cx<T> *xa = nu1 > 0 ? (Cx<T> *)lv.xa : nullptr;
+        if (nu1 > 0) poly_smooth<T, DIM>(op, l, b, nullptr, nullptr, xa, nu1, nrhs, st, active);
+        launch_restrict<T, DIM>(lvl<T>(op, l), lvl<T>(op, l + 1), xa, b, (Cx<T> *)cl.b, lv.ld, cl.ld,
+                                lch(op, l + 1, nrhs, st), active);
+    }
+    const Cx<T> *bL = L == 1 ? b0 : (const Cx<T> *)op->lev[L - 1].b;
+    Cx<T> *xL = L == 1 ? x0 : (Cx<T> *)op->lev[L - 1].xb;
+    launch_coarse<T>((const Cx<T> *)op->minvT, op->nc, bL, xL, op->lev[L - 1].ld, nrhs, st, active);
+    for (int l = L - 2; l >= 0; --l) {
+        const DevLevel &lv = op->lev[l];
+        const DevLevel &cl = op->lev[l + 1];
+        const Cx<T> *b = l == 0 ? b0 : (const Cx<T> *)lv.b;
+        Cx<T> *xo = l == 0 ? x0 : (Cx<T> *)lv.xb;
+        const Cx<T> *xi = nu1 > 0 ? (const Cx<T> *)lv.xa : nullptr;
+        if (nu2 == 0)
+            launch_prolong<T, DIM>(lvl<T>(op, l), lvl<T>(op, l + 1), (const Cx<T> *)cl.xb, xi, xo, lv.ld, cl.ld,
+                                   lch(op, l, nrhs, st), active);
+        else
+            poly_smooth<T, DIM>(op, l, b, xi, (const Cx<T> *)cl.xb, xo, nu2, nrhs, st, active);
+    }
+}
+
+// One smoothing sweep of csg_smooth on level l (x in place): GMRES(s), or a
+// polynomial sweep into the level's xb, copied back (the polynomial kernels
+// never update in place).
+template <typename T, int DIM>
+void smooth_inplace(const csg_operator *op, int level, const Cx<T> *b, Cx<T> *x, int nrhs, hipStream_t st,
+                    const int *active)
+{
+    if (op->p.smoother != 1) {
+        sweep<T, DIM>(op, level, b, x, false, false, nrhs, st, active);
+        return;
+    }
+    const DevLevel &lv = op->lev[level];
+    Cx<T> *tmp = (Cx<T> *)lv.xb;
+    poly_smooth<T, DIM>(op, level, b, x, nullptr, tmp, 1, nrhs, st, active);
+    hipMemcpyAsync(x, tmp, (size_t)nrhs * lv.ld * sizeof(Cx<T>), hipMemcpyDeviceToDevice, st);
+}
+
 template <typename T>
 void vcycle_dispatch(const csg_operator *op, const void *b, void *x, int nrhs, hipStream_t st, const int *active)
 {
+    if (op->p.smoother == 1) {
+        if (op->p.dim == 2)
+            vcycle_poly<T, 2>(op, (const Cx<T> *)b, (Cx<T> *)x, nrhs, st, active);
+        else
+            vcycle_poly<T, 3>(op, (const Cx<T> *)b, (Cx<T> *)x, nrhs, st, active);
+        return;
+    }
     if (op->p.dim == 2)
         vcycle_impl<T, 2>(op, (const Cx<T> *)b, (Cx<T> *)x, nrhs, st, active);
     else
@@ -1050,6 +1177,13 @@ int csg_operator_create(const csg_params *p, const double *phi_host, void *ws_de
         if (const char *e = getenv("CSG_FUSE_UPD")) op->fuse_upd = atoi(e) != 0;
         op->force_cgs2 = false;
         if (const char *e = getenv("CSG_FORCE_CGS2")) op->force_cgs2 = atoi(e) != 0;
+        op->poly_tiles = true;
+        if (const char *e = getenv("CSG_POLY_TILES")) op->poly_tiles = atoi(e) != 0;
+        for (int l = 0; l < op->L; ++l) {
+            op->lev[l].varphi = hh.lev[l].varphi;
+            op->lev[l].conds = hh.lev[l].conds;
+            for (int i = 0; i < 3; ++i) op->lev[l].omega[i] = hh.lev[l].omega[i];
+        }
         op->lt = op->L - 1;
         for (int l = 0; l < op->L; ++l)
             if ((long)op->lev[l].N <= tail_max) { op->lt = l; break; }
@@ -1276,13 +1410,28 @@ int csg_smooth(const csg_operator *op, int level, const void *b, void *x, int nr
     if (!b || !x) return fail(CSG_EINVAL, "null vector");
     hipStream_t s = (hipStream_t)stream;
     if (op->p.cycle_prec) {
-        if (op->p.dim == 3) sweep<float, 3>(op, level, (const cf *)b, (cf *)x, false, false, nrhs, s, op->ones);
-        else sweep<float, 2>(op, level, (const cf *)b, (cf *)x, false, false, nrhs, s, op->ones);
+        if (op->p.dim == 3) smooth_inplace<float, 3>(op, level, (const cf *)b, (cf *)x, nrhs, s, op->ones);
+        else smooth_inplace<float, 2>(op, level, (const cf *)b, (cf *)x, nrhs, s, op->ones);
     } else {
-        if (op->p.dim == 3) sweep<double, 3>(op, level, (const zc *)b, (zc *)x, false, false, nrhs, s, op->ones);
-        else sweep<double, 2>(op, level, (const zc *)b, (zc *)x, false, false, nrhs, s, op->ones);
+        if (op->p.dim == 3) smooth_inplace<double, 3>(op, level, (const zc *)b, (zc *)x, nrhs, s, op->ones);
+        else smooth_inplace<double, 2>(op, level, (const zc *)b, (zc *)x, nrhs, s, op->ones);
     }
     return last_launch_error();
+}
+
+int csg_poly_info(const csg_operator *op, int level, double *varphi, double omega[6], int *conds)
+{
+    if (!op) return fail(CSG_EINVAL, "null operator");
+    if (level < 0 || level >= op->L) return fail(CSG_EINVAL, "bad level");
+    const DevLevel &lv = op->lev[level];
+    if (varphi) *varphi = lv.varphi;
+    if (omega)
+        for (int i = 0; i < 3; ++i) {
+            omega[2 * i] = lv.omega[i].real();
+            omega[2 * i + 1] = lv.omega[i].imag();
+        }
+    if (conds) *conds = lv.conds;
+    return CSG_OK;
 }
 
 int csg_smooth_static(const csg_operator *op, int level, const void *b, void *x, int nrhs, void *stream)
@@ -1305,6 +1454,7 @@ int csg_smooth_static(const csg_operator *op, int level, const void *b, void *x,
     for (int i = 1; i <= op->p.s; ++i) lv.u[i] = cv.take(vb);
     lv.w[0] = cv.take(vb);
     lv.w[1] = cv.take(vb);
+    if (op->p.smoother == 1) lv.xb = cv.take(vb);   // the polynomial sweep's result before the copy back
     const size_t cleared = cv.off;
     const size_t pb = (size_t)nrhs * NVAL * NBMAX * sizeof(zc);
     lv.part[0] = (zc *)cv.take(pb);
@@ -1319,11 +1469,11 @@ int csg_smooth_static(const csg_operator *op, int level, const void *b, void *x,
     const size_t z0 = (cleared + 255) & ~(size_t)255;
     launch_zero16(base + z0, end - z0, s);
     if (op->p.cycle_prec) {
-        if (op->p.dim == 3) sweep<float, 3>(&tmp, level, (const cf *)b, (cf *)x, false, false, nrhs, s, op->ones);
-        else sweep<float, 2>(&tmp, level, (const cf *)b, (cf *)x, false, false, nrhs, s, op->ones);
+        if (op->p.dim == 3) smooth_inplace<float, 3>(&tmp, level, (const cf *)b, (cf *)x, nrhs, s, op->ones);
+        else smooth_inplace<float, 2>(&tmp, level, (const cf *)b, (cf *)x, nrhs, s, op->ones);
     } else {
-        if (op->p.dim == 3) sweep<double, 3>(&tmp, level, (const zc *)b, (zc *)x, false, false, nrhs, s, op->ones);
-        else sweep<double, 2>(&tmp, level, (const zc *)b, (zc *)x, false, false, nrhs, s, op->ones);
+        if (op->p.dim == 3) smooth_inplace<double, 3>(&tmp, level, (const zc *)b, (zc *)x, nrhs, s, op->ones);
+        else smooth_inplace<double, 2>(&tmp, level, (const zc *)b, (zc *)x, nrhs, s, op->ones);
     }
     return last_launch_error();
 }

@@ -88,6 +88,10 @@ struct HostLevel {
     std::vector<cd> z[3];      // nested complex node coordinates of M's grid
     std::vector<cd> tab[3];    // Shortley-Weller rows of M: [west | centre | east]
     std::vector<double> phi;
+    // third-order polynomial smoother of this level (section 4)
+    double varphi = 0.0;
+    cd omega[3];
+    int conds = 2;
 };
 
 struct HostHier {
@@ -163,6 +167,9 @@ struct DevLevel {
     unsigned chunk;            // points per block of a reducing pass
     TileGeo tile;              // 2-D tiling of the LDS-staged fused pass (ntx = 0: none)
     TileGeo dtile;             // tiling of the down-path pass that restricts onto this level
+    double varphi;             // polynomial smoother: p(t0) = e^{i varphi}
+    cd omega[3];               // ... its Richardson weights, in the order they are applied
+    int conds;                 // ... which necessary stability conditions varphi meets
 };
 
 // Instantiated graphs of one FGMRES iteration (V-cycle + outer passes), per
@@ -203,6 +210,7 @@ struct csg_operator {
     bool down_tiles;                  // ... and the LDS-staged closing + restriction + next pass 0
     bool fuse_upd;                    // coarse post-sweep updates applied by the finer up-path pass
     bool force_cgs2;                  // every outer column takes the second Gram-Schmidt round
+    bool poly_tiles;                  // polynomial sweeps of 2-D levels run as one tiled launch
     // outer FGMRES storage
     csg::zc *V;                       // (m+1) x max_rhs x ld0
     void *Z;                          // m x max_rhs x ld0, cycle precision

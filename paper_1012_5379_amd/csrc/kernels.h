@@ -218,6 +218,20 @@ void launch_fs_params(FState *fs, double tol, int maxit, int force2, int nrhs, h
 
 void launch_copy_mask(const int *src, int *dst, int n, hipStream_t st);
 
+// ---- third-order polynomial smoother (section 4) ---------------------------
+// one Richardson step xout = xin + w (b - A xin) (xin null: zero; xout must
+// not alias xin)
+template <typename T, int DIM>
+void launch_rich(const LvlK<T> &L, const Cx<T> *xin, const Cx<T> *b, Cx<T> *xout, Cx<T> w, size_t ld, const Launch &g,
+                 const int *active);
+// a whole sweep (three steps with weights w[0..2]) on 32 x 32 tiles of a 2-D
+// level, from xin (null: zero) or, with ec, from xin + P ec; xout must not
+// alias xin
+template <typename T>
+void launch_poly_tile(const LvlK<T> &L, const LvlK<T> &C, const Cx<T> *ec, const Cx<T> *xin, const Cx<T> *b,
+                      Cx<T> *xout, const Cx<T> (&w)[3], size_t ld, size_t ldc, int nrhs, hipStream_t st,
+                      const int *active);
+
 // bytes (a multiple of 16, 16-byte aligned) of device memory set to zero
 void launch_zero16(void *p, size_t bytes, hipStream_t st);
 

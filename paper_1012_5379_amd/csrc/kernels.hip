@@ -3455,6 +3455,181 @@ __global__ void k_copy_mask(const int *src, int *dst, int n)
 }
 
 // ---------------------------------------------------------------------------
+// Third-order polynomial smoother (section 4): one sweep is three Richardson
+// steps x <- x + w_i (b - A x), so the error is multiplied by
+// p(A) = (1 - w1 A)(1 - w2 A)(1 - w3 A).  No inner products: nothing couples
+// distant points, which is what lets the three steps run on a tile at once.
+// ---------------------------------------------------------------------------
+
+// One step on the plain chunked layout: xout = xin + w (b - A xin), xin null
+// meaning zero (xout = w b); xout must not alias xin.
+template <typename T, int DIM>
+__global__ __launch_bounds__(BLK) void k_rich(LvlK<T> L, const Cx<T> *__restrict__ xin, const Cx<T> *__restrict__ b,
+                                              Cx<T> *__restrict__ xout, Cx<T> w, size_t ld, unsigned chunk, int nb,
+                                              const int *active)
+{
+    constexpr int U = Ubatch<T>::U;
+    const int rhs = blockIdx.y;
+    if (!active[rhs]) return;
+    const size_t off = rhs * ld;
+    const unsigned c = chunk_id(nb);
+    const unsigned p0 = c * chunk + threadIdx.x, p1 = min(L.N, c * chunk + chunk);
+    if (p0 >= p1) return;
+    const unsigned last = p1 - 1;
+    for (unsigned p = p0; p < p1; p += U * BLK) {
+        Cx<T> v[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const unsigned pk = min(p + k * BLK, last);
+            const Cx<T> bv = b[off + pk];
+            if (xin) {
+                unsigned i, jj, kk;
+                decomp<DIM>(pk, L.nx, L.ny, i, jj, kk);
+                v[k] = xin[off + pk] + w * (bv - apply_pt<T, DIM>(L, xin + off, i, jj, kk, pk));
+            } else {
+                v[k] = w * bv;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            if (p + k * BLK >= p1) break;
+            xout[off + p + k * BLK] = v[k];
+        }
+    }
+}
+
+// A whole sweep on one 2-D tile of PT x PT points: x is staged on the tile and
+// a three-point halo in shared memory (zero outside the level); step i
+// updates the points within 3 - i of the tile (each step's stencil reaches one
+// point further than the next step needs), so after three steps the tile's
+// points hold the sweep's result, with x, b and phi read from memory once per
+// staged point.  With ec, the start value is xin + P ec (the interpolated
+// coarse correction of the up path; xin may be null).  A thread owns the same
+// points of the two-point-halo region in every step and keeps their b, phi
+// and stencil rows in registers.  xout must not alias xin.
+constexpr int PT = 32;                      // tile side
+constexpr int PR = PT + 6;                  // staged region side
+constexpr int PN = (PT + 4) * (PT + 4);     // points updated by step 1
+constexpr int PE = (PN + BLK - 1) / BLK;    // of them per thread
+template <typename T, bool ZERO, bool PROL>
+__global__ __launch_bounds__(BLK) void k_poly_tile(LvlK<T> L, LvlK<T> C, const Cx<T> *__restrict__ ec,
+                                                   const Cx<T> *__restrict__ xin, const Cx<T> *__restrict__ b,
+                                                   Cx<T> *__restrict__ xout, Cx<T> w1, Cx<T> w2, Cx<T> w3,
+                                                   size_t ld, size_t ldc, unsigned ntx, const int *active)
+{
+    __shared__ Cx<T> X[2][PR * PR];
+    const int rhs = blockIdx.y;
+    if (!active[rhs]) return;
+    const size_t off = rhs * ld;
+    const int nx = (int)L.nx, ny = (int)L.ny;
+    const unsigned t = blockIdx.x, tyi = t / ntx, txi = t - tyi * ntx;
+    const int x0 = (int)txi * PT, y0 = (int)tyi * PT;
+    const int TX = min(PT, nx - x0), TY = min(PT, ny - y0);
+    const int RX = TX + 6, RY = TY + 6;
+    // stage the start value on the tile and its three-point halo
+    if (!ZERO) {
+        for (int e = threadIdx.x; e < RX * RY; e += BLK) {
+            const int ey = e / RX, ex = e - ey * RX;
+            const int gx = x0 - 3 + ex, gy = y0 - 3 + ey;
+            Cx<T> v = mkc<T>(0, 0);
+            if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+                const unsigned gp = (unsigned)gy * nx + gx;
+                if (xin) v = xin[off + gp];
+                if (PROL) v = v + prolong_pt<T, 2>(ec + rhs * ldc, (unsigned)gx, (unsigned)gy, 0u, C.nx, C.ny, 1u);
+            }
+            X[0][e] = v;
+        }
+    }
+    // owned points of the two-point-halo region: b, phi-shifted diagonal and
+    // the four off-diagonal weights
+    const int QX = TX + 4, QY = TY + 4;
+    Cx<T> bq[PE], dq[PE], wxq[PE], exq[PE], wyq[PE], eyq[PE];
+    int eq[PE], mq[PE];
+#pragma unroll
+    for (int k = 0; k < PE; ++k) {
+        const int q = threadIdx.x + k * BLK;
+        const int qy = q / QX, qx = q - qy * QX;
+        const int gx = x0 - 2 + qx, gy = y0 - 2 + qy;
+        const bool in = q < QX * QY && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        // distance of the point from the tile (0 on the tile), 9 when absent
+        const int m = max(max(max(-gx + x0, gx - (x0 + TX - 1)), max(-gy + y0, gy - (y0 + TY - 1))), 0);
+        mq[k] = in ? m : 9;
+        eq[k] = (qy + 1) * RX + qx + 1;
+        const int cx = in ? gx : 0, cy = in ? gy : 0;
+        const unsigned gp = (unsigned)cy * nx + cx;
+        bq[k] = b[off + gp];
+        Cx<T> d = L.tab[0][nx + cx] + L.tab[1][ny + cy];
+        d.re -= L.phi[gp];
+        dq[k] = d;
+        wxq[k] = L.tab[0][cx];
+        exq[k] = L.tab[0][2 * nx + cx];
+        wyq[k] = L.tab[1][cy];
+        eyq[k] = L.tab[1][2 * ny + cy];
+    }
+    if (ZERO) {
+        // the first step from x = 0 is x1 = w1 b: written straight into buffer 1,
+        // zero where absent
+        for (int e = threadIdx.x; e < RX * RY; e += BLK) X[1][e] = mkc<T>(0, 0);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PE; ++k)
+            if (mq[k] <= 2) X[1][eq[k]] = w1 * bq[k];
+    } else {
+        for (int e = threadIdx.x; e < RX * RY; e += BLK) X[1][e] = mkc<T>(0, 0);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PE; ++k) {
+            if (mq[k] > 2) continue;
+            const Cx<T> *S = X[0];
+            const int e = eq[k];
+            Cx<T> a = dq[k] * S[e];
+            a = cfma(wxq[k], S[e - 1], a);
+            a = cfma(exq[k], S[e + 1], a);
+            a = cfma(wyq[k], S[e - RX], a);
+            a = cfma(eyq[k], S[e + RX], a);
+            X[1][e] = S[e] + w1 * (bq[k] - a);
+        }
+    }
+    __syncthreads();
+    // step 2 into buffer 0 (points within one of the tile), step 3 from there
+    Cx<T> res[PE];
+#pragma unroll
+    for (int k = 0; k < PE; ++k) {
+        if (mq[k] > 1) continue;
+        const Cx<T> *S = X[1];
+        const int e = eq[k];
+        Cx<T> a = dq[k] * S[e];
+        a = cfma(wxq[k], S[e - 1], a);
+        a = cfma(exq[k], S[e + 1], a);
+        a = cfma(wyq[k], S[e - RX], a);
+        a = cfma(eyq[k], S[e + RX], a);
+        res[k] = S[e] + w2 * (bq[k] - a);
+    }
+    __syncthreads();   // every step-2 read of X[0]'s old contents is done
+    // buffer 0 now: zero outside the level and on the ring the steps never reach
+    for (int e = threadIdx.x; e < RX * RY; e += BLK) X[0][e] = mkc<T>(0, 0);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PE; ++k)
+        if (mq[k] <= 1) X[0][eq[k]] = res[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PE; ++k) {
+        if (mq[k] != 0) continue;
+        const Cx<T> *S = X[0];
+        const int e = eq[k];
+        Cx<T> a = dq[k] * S[e];
+        a = cfma(wxq[k], S[e - 1], a);
+        a = cfma(exq[k], S[e + 1], a);
+        a = cfma(wyq[k], S[e - RX], a);
+        a = cfma(eyq[k], S[e + RX], a);
+        const int q = threadIdx.x + k * BLK;
+        const int qy = q / QX, qx = q - qy * QX;
+        xout[off + (size_t)(y0 - 2 + qy) * nx + (x0 - 2 + qx)] = S[e] + w3 * (bq[k] - a);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 
@@ -3982,6 +4157,33 @@ void launch_tail(const TLev<T> *lev, int lt, int L, const Cx<T> *b_in, Cx<T> *x_
                            s, nu1, nu2, tiny, active);
 }
 
+template <typename T, int DIM>
+void launch_rich(const LvlK<T> &L, const Cx<T> *xin, const Cx<T> *b, Cx<T> *xout, Cx<T> w, size_t ld, const Launch &g,
+                 const int *active)
+{
+    hipLaunchKernelGGL((k_rich<T, DIM>), grid(g), dim3(BLK), 0, g.st, L, xin, b, xout, w, ld, g.chunk, g.nb, active);
+}
+
+unsigned poly_tiles(unsigned nx, unsigned ny) { return ((nx + PT - 1) / PT) * ((ny + PT - 1) / PT); }
+
+template <typename T>
+void launch_poly_tile(const LvlK<T> &L, const LvlK<T> &C, const Cx<T> *ec, const Cx<T> *xin, const Cx<T> *b,
+                      Cx<T> *xout, const Cx<T> (&w)[3], size_t ld, size_t ldc, int nrhs, hipStream_t st,
+                      const int *active)
+{
+    const unsigned ntx = (L.nx + PT - 1) / PT;
+    const dim3 gr(poly_tiles(L.nx, L.ny), nrhs);
+    if (ec)
+        hipLaunchKernelGGL((k_poly_tile<T, false, true>), gr, dim3(BLK), 0, st, L, C, ec, xin, b, xout, w[0], w[1], w[2],
+                           ld, ldc, ntx, active);
+    else if (xin)
+        hipLaunchKernelGGL((k_poly_tile<T, false, false>), gr, dim3(BLK), 0, st, L, C, ec, xin, b, xout, w[0], w[1],
+                           w[2], ld, ldc, ntx, active);
+    else
+        hipLaunchKernelGGL((k_poly_tile<T, true, false>), gr, dim3(BLK), 0, st, L, C, ec, xin, b, xout, w[0], w[1],
+                           w[2], ld, ldc, ntx, active);
+}
+
 void launch_copy_mask(const int *src, int *dst, int n, hipStream_t st)
 {
     hipLaunchKernelGGL(k_copy_mask, dim3((n + 255) / 256), dim3(256), 0, st, src, dst, n);
@@ -4009,6 +4211,8 @@ void launch_zero16(void *p, size_t bytes, hipStream_t st)
 
 #define INST_TD(T, D)                                                                                               \
     template void launch_apply<T, D>(const LvlK<T> &, const void *, void *, size_t, const Launch &, const int *);  \
+    template void launch_rich<T, D>(const LvlK<T> &, const Cx<T> *, const Cx<T> *, Cx<T> *, Cx<T>, size_t,         \
+                                    const Launch &, const int *);                                                  \
     template void launch_st0<T, D>(const LvlK<T> &, const Cx<T> *, Cx<T> *, int, size_t, zc *, const Launch &,     \
                                    const int *);                                                                   \
     template void launch_stj<T, D>(const LvlK<T> &, const Basis<T> &, Cx<T> *, int, int, size_t, zc *,             \
@@ -4070,7 +4274,10 @@ template void launch_hdot_tile<float>(const LvlK<double> &, const Cx<float> *, z
     template void launch_proj0<T>(zc *, const zc *, size_t, int, unsigned, size_t, FState *, Report *, int *,      \
                                   const zc *, int, zc *, zc *, Cx<T> *, const Launch &, const int *);              \
     template void launch_uupd<T>(zc *, const Cx<T> *, size_t, unsigned, size_t, const FState *, const Launch &,    \
-                                 const int *);
+                                 const int *);                                                                     \
+    template void launch_poly_tile<T>(const LvlK<T> &, const LvlK<T> &, const Cx<T> *, const Cx<T> *,            \
+                                      const Cx<T> *, Cx<T> *, const Cx<T>(&)[3], size_t, size_t, int, hipStream_t, \
+                                      const int *);
 
 INST_T(double)
 INST_T(float)

@@ -9,6 +9,7 @@
 // rediscretising on the coarser complex grid; here each coarse grid takes every
 // other node of the finer one (the last node always kept, so an odd interval
 // count leaves one single interval at the high end) and phi is injected.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -28,6 +29,8 @@ int plan_levels(const csg_params &p, int &L, int nint[CSG_MAX_LEVELS][3], std::s
     if (p.cycle_prec != 0 && p.cycle_prec != 1) { err = "cycle_prec must be 0 or 1"; return CSG_EINVAL; }
     if (p.max_rhs < 1 || p.max_rhs > CSG_MAX_RHS) { err = "max_rhs out of range 1..CSG_MAX_RHS"; return CSG_EINVAL; }
     if (p.restart < 1 || p.restart > CSG_MAX_RESTART) { err = "restart out of range"; return CSG_EINVAL; }
+    if (p.smoother != 0 && p.smoother != 1) { err = "smoother must be 0 (GMRES) or 1 (polynomial)"; return CSG_EINVAL; }
+    if (!(p.poly_k2 >= 0.0) || !std::isfinite(p.poly_k2)) { err = "poly_k2 must be finite and >= 0"; return CSG_EINVAL; }
     int cur[3] = {0, 0, 0};
     for (int a = 0; a < p.dim; ++a) {
         if (p.n[a] < 1 || p.layer_lo[a] < 0 || p.layer_hi[a] < 0) {
@@ -131,6 +134,98 @@ int invert(std::vector<cd> &A, int n, std::vector<cd> &inv)
     return 0;
 }
 
+// ---------------------------------------------------------------------------
+// Third-order polynomial smoother (section 4)
+// ---------------------------------------------------------------------------
+
+// Monomial coefficients (g0, g1, g2) of the quadratic through (x_r, y_r),
+// r = 0, 1, 2, from its Newton form.
+void quad_through(const cd x[3], const cd y[3], cd g[3])
+{
+    const cd d01 = (y[1] - y[0]) / (x[1] - x[0]);
+    const cd d12 = (y[2] - y[1]) / (x[2] - x[1]);
+    const cd d012 = (d12 - d01) / (x[2] - x[0]);
+    g[2] = d012;
+    g[1] = d01 - d012 * (x[0] + x[1]);
+    g[0] = y[0] - d01 * x[0] + d012 * x[0] * x[1];
+}
+
+// Angles v with |a| cos(v - arg a) < g, as [centre - half, centre + half];
+// returns 1 for every angle, 0 for an arc, -1 for none.
+int arc_of(cd a, double g, double &centre, double &half)
+{
+    const double m = std::abs(a);
+    centre = std::arg(a) + M_PI;
+    if (g >= m) { half = M_PI; return 1; }
+    if (-g >= m) { half = 0.0; return -1; }
+    half = M_PI - std::acos(g / m);
+    return 0;
+}
+
+// The level's polynomial: triangle t0 = -k^2, t1 = -k^2 + 4d/(H e^{i beta})^2,
+// t2 = -k^2 + 4d/(H e^{i gamma})^2 (Prop. 3.1, H = 2^l h).  Writing
+// p(t) = c0 + (t - t0) g(t - t0) with g quadratic, p(0) = 1 and p(t1) = p(t2)
+// = 0 fix g at the three nodes x = -t0, t1 - t0, t2 - t0 (eq.
+// coefficients_system): g(x_r) = b_r / x_r with b = (1 - c0, -c0, -c0), so
+// g = E - c0 F with E, F interpolating (1/x0, 0, 0) and (1/x0, 1/x1, 1/x2)
+// (eq. coefficients_solution: c_j = e_j - e^{i varphi} f_j).  Along the top
+// edge t0 + rho w, w = e^{-2i beta}, |p|^2 = 1 + 2 rho Fo + rho^2 So + ...:
+//   Fo(v) = Re(e^{-iv} E0 w) - Re(F0 w)                        (first order)
+//   So(v) = |E0|^2 + |F0|^2 - 2 Re(F1 w^2) + Re(e^{-iv} Z),
+//   Z = 2 (E1 w^2 - E0 conj(F0))                               (second order)
+// varphi is the midpoint of the angles where both are negative (or of those
+// where the first is, when no angle meets both).
+void poly_level(int dim, double beta, double gamma, double k2, double H, HostLevel &lv)
+{
+    const cd hb = std::polar(H, beta), hg = std::polar(H, gamma);
+    const cd t0 = -k2, t1 = t0 + 4.0 * dim / (hb * hb), t2 = t0 + 4.0 * dim / (hg * hg);
+    const cd x[3] = {-t0, t1 - t0, t2 - t0};
+    const cd ye[3] = {1.0 / x[0], 0.0, 0.0};
+    const cd yf[3] = {1.0 / x[0], 1.0 / x[1], 1.0 / x[2]};
+    cd E[3], F[3];
+    quad_through(x, ye, E);
+    quad_through(x, yf, F);
+    const cd w = std::polar(1.0, -2.0 * beta);
+    double cA, hA, cB, hB;
+    const int kA = arc_of(E[0] * w, (F[0] * w).real(), cA, hA);
+    const double K = std::norm(E[0]) + std::norm(F[0]) - 2.0 * (F[1] * w * w).real();
+    const int kB = arc_of(2.0 * (E[1] * w * w - E[0] * std::conj(F[0])), -K, cB, hB);
+    double v = 0.0;
+    int conds = 2;
+    if (kA >= 0 && kB >= 0) {
+        conds = 0;
+        if (kA == 1 && kB == 1) v = 0.0;
+        else if (kA == 1) v = cB;
+        else if (kB == 1) v = cA;
+        else {
+            // overlap of [-hA, hA] with arc B shifted about arc A's centre
+            const double d = std::remainder(cB - cA, 2.0 * M_PI);
+            double len = 0.0, mid = 0.0;
+            for (int q = -1; q <= 1; ++q) {
+                const double lo = std::max(-hA, d + q * 2.0 * M_PI - hB);
+                const double hi = std::min(hA, d + q * 2.0 * M_PI + hB);
+                if (hi - lo > len) { len = hi - lo; mid = 0.5 * (lo + hi); }
+            }
+            if (len > 0.0) v = cA + mid;
+            else { v = cA; conds = 1; }
+        }
+    } else if (kA >= 0) {
+        v = kA == 1 ? 0.0 : cA;
+        conds = 1;
+    }
+    v = std::remainder(v, 2.0 * M_PI);
+    if (v < 0.0) v += 2.0 * M_PI;
+    const cd c0 = std::polar(1.0, v);
+    const cd c3 = E[2] - c0 * F[2];
+    lv.varphi = v;
+    lv.conds = conds;
+    // roots 1/w: t1, t2 by construction, and the third from p(0) = 1 with
+    // leading coefficient c3: p(t) = c3 (t - t1)(t - t2)(t - t3)
+    lv.omega[0] = 1.0 / t1;
+    lv.omega[1] = 1.0 / t2;
+    lv.omega[2] = -c3 * t1 * t2;
+}
+
 }  // namespace
 
 int build_hierarchy(const csg_params &p, const double *phi, HostHier &hh, std::string &err)
@@ -185,6 +280,17 @@ int build_hierarchy(const csg_params &p, const double *phi, HostHier &hh, std::s
         std::vector<cd> zH;
         fine_nodes(p, a, 0.0, zH);
         sw_rows(zH, hh.tabH[a]);
+    }
+    {
+        // polynomial smoothers; k^2 of the vertex t0: given, else the mean of phi
+        double k2 = p.poly_k2;
+        if (k2 == 0.0) {
+            const HostLevel &F0 = hh.lev[0];
+            double acc = 0.0;
+            for (long q = 0; q < F0.N; ++q) acc += F0.phi[q];
+            k2 = acc / (double)F0.N;
+        }
+        for (int l = 0; l < L; ++l) poly_level(p.dim, p.beta, p.gamma, k2, std::ldexp(p.h, l), hh.lev[l]);
     }
     // dense coarsest matrix, assembled row by row from the tables
     const HostLevel &C = hh.lev[L - 1];
