@@ -171,8 +171,9 @@ int csg_smooth(const csg_operator *op, int level, const void *b_dev, void *x_dev
  * serialised by the caller; partials and states are cleared on every call.
  * Errors: CSG_ENOMEM when the sweep needs more than 128 MiB, i.e.
  * (s + 3) * nrhs * unknowns(level) * (16 or 8 bytes) (s + 4 with the
- * polynomial smoother) plus about 82 KB per RHS of partials and states; CSG_EDEVICE if the array's device address
- * cannot be obtained; otherwise as csg_smooth. */
+ * polynomial smoother) plus about 330 KB per RHS of partials and states;
+ * CSG_EDEVICE if the array's device address cannot be obtained; otherwise as
+ * csg_smooth. */
 int csg_smooth_static(const csg_operator *op, int level, const void *b_dev, void *x_dev, int nrhs,
                       void *stream);
 

@@ -85,7 +85,7 @@ void geometry(unsigned n, int &nb, unsigned &chunk)
 {
     long want = ((long)n + BLK - 1) / BLK;
     if (want < 1) want = 1;
-    nb = (int)std::min<long>(NBMAX, want);
+    nb = (int)std::min<long>(NBCH, want);
     if (nb >= 8) nb &= ~7;
     long per = ((long)n + nb - 1) / nb;
     chunk = (unsigned)(((per + BLK - 1) / BLK) * BLK);
@@ -93,8 +93,19 @@ void geometry(unsigned n, int &nb, unsigned &chunk)
 
 // Tiles of a 2-D level for the LDS-staged fused pass: as many as the chunked
 // passes have blocks (nb), tile rows in multiples of 8 when nb is, so the
-// XCD-aware block order hands each XCD a band of rows as in the chunked passes.
+// XCD-aware block order hands each XCD a band of rows as in the chunked passes;
+// where such tiles overflow the shared-memory buffer, 2, 4 ... times as many
+// (at most NBMAX partials per value).
+TileGeo tiling_n(unsigned nx, unsigned ny, int nb);
 TileGeo tiling(unsigned nx, unsigned ny, int nb)
+{
+    for (int k = nb; k >= 1 && k <= NBMAX; k *= 2) {
+        const TileGeo t = tiling_n(nx, ny, k);
+        if (t.ntx) return t;
+    }
+    return TileGeo{0, 0, 0, 0};
+}
+TileGeo tiling_n(unsigned nx, unsigned ny, int nb)
 {
     TileGeo t{0, 0, 0, 0};
     if (nb < 1) return t;
@@ -118,7 +129,7 @@ TileGeo tiling(unsigned nx, unsigned ny, int nb)
 
 // Tiling of the down-path pass onto a coarse level: small tiles whose fine
 // footprint each thread covers with one batch of loads, when they number at
-// most NBMAX; else the level's own tiling.
+// most NBCH; else the level's own tiling.
 TileGeo down_tiling(unsigned nx, unsigned ny, const TileGeo &dflt)
 {
     constexpr unsigned D = 20;   // (2 D + 5)^2 <= TILE_PB * BLK
@@ -128,7 +139,7 @@ TileGeo down_tiling(unsigned nx, unsigned ny, const TileGeo &dflt)
     t.ty = std::min(D, ny);
     t.ntx = (nx + t.tx - 1) / t.tx;
     t.nty = (ny + t.ty - 1) / t.ty;
-    if (down_fits(t)) return t;
+    if (down_fits(t) && (int)(t.ntx * t.nty) <= NBCH) return t;
     return dflt;
 }
 

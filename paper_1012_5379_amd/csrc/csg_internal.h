@@ -17,7 +17,8 @@ namespace csg {
 using cd = std::complex<double>;
 
 constexpr int BLK = 512;                    // threads per block of every level pass
-constexpr int NBMAX = 256;                  // max blocks of a reducing pass (partials per value)
+constexpr int NBMAX = 1024;                 // max blocks of a reducing pass (partials per value)
+constexpr int NBCH = 256;                   // blocks of a chunked (untiled) level pass
 constexpr int NVAL = CSG_MAX_S + 2;         // partial values per smoother pass
 constexpr int OVAL = CSG_MAX_RESTART + 1;   // partial values per outer pass
 constexpr int MAXC = 4096;                  // max coarsest unknowns

@@ -32,7 +32,7 @@ struct TLev {
 };
 
 struct Launch {
-    int nb;            // blocks along x (reducing passes: <= NBMAX)
+    int nb;            // blocks along x (chunked passes: <= NBCH)
     unsigned chunk;    // points per block
     int nrhs;
     hipStream_t st;

@@ -210,20 +210,26 @@ __device__ __forceinline__ void block_sum(zc (&v)[NV], int nv, zc *sh, zc *res)
 }
 
 // This thread's share of the per-block partials of one RHS (layout
-// [value][NBMAX]): one partial per thread, all NV rows loaded at once (rows >=
-// nv and blocks >= nb are read inside the buffer and dropped), so the
-// reduction waits for memory once.
+// [value][NBMAX]): partials b and b + BLK of every row, all loaded at once
+// (rows >= nv and blocks >= nb are read inside the buffer and dropped), so the
+// reduction waits for memory once; the second is added only when present.
 template <int NV>
 __device__ __forceinline__ void load_parts(const zc *part, int nb, int nv, zc (&v)[NV])
 {
-    static_assert(NBMAX <= BLK && NV <= NVAL, "partials layout");
-    const int b = min((int)threadIdx.x, NBMAX - 1);
-    const bool ok = (int)threadIdx.x < nb;
+    static_assert(NBMAX <= 2 * BLK && NV <= NVAL, "partials layout");
+    const int b = (int)threadIdx.x;
+    const bool ok = b < nb, ok2 = b + BLK < nb;
+    zc v2[NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) v[q] = part[q * NBMAX + b];
+    for (int q = 0; q < NV; ++q) {
+        v[q] = part[q * NBMAX + b];
+        v2[q] = part[q * NBMAX + min(b + BLK, NBMAX - 1)];
+    }
 #pragma unroll
-    for (int q = 0; q < NV; ++q)
+    for (int q = 0; q < NV; ++q) {
+        if (ok2) v[q] = v[q] + v2[q];
         if (!(ok && q < nv)) v[q] = mkc(0.0, 0.0);
+    }
 }
 
 // block_sum at the end of a pass: thread q < nv stores the total it formed
@@ -3329,17 +3335,19 @@ constexpr int FG = 32;     // lanes that reduce one value
 // then a butterfly inside the lane group): deterministic, no block barrier.
 __device__ __forceinline__ zc group_parts(const zc *pp, int nbin)
 {
-    // every load of the lane issued at once (inside the row of NBMAX partials),
-    // then summed in the order of b
-    constexpr int K = NBMAX / FG;
+    // the lane's loads issued eight at a time (inside the row of NBMAX
+    // partials), then summed in the order of b
+    constexpr int K = NBMAX / FG, KB = 8;
     const int lane = threadIdx.x % FG;
-    zc t[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) t[k] = pp[min(lane + k * FG, NBMAX - 1)];
     zc v = mkc(0.0, 0.0);
+    for (int k0 = 0; k0 < K && k0 * FG < nbin; k0 += KB) {
+        zc t[KB];
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-        if (lane + k * FG < nbin) v = v + t[k];
+        for (int k = 0; k < KB; ++k) t[k] = pp[min(lane + (k0 + k) * FG, NBMAX - 1)];
+#pragma unroll
+        for (int k = 0; k < KB; ++k)
+            if (lane + (k0 + k) * FG < nbin) v = v + t[k];
+    }
 #pragma unroll
     for (int off = FG / 2; off > 0; off >>= 1) {
         v.re += __shfl_xor(v.re, off, FG);
