@@ -143,6 +143,26 @@ TileGeo down_tiling(unsigned nx, unsigned ny, const TileGeo &dflt)
     return dflt;
 }
 
+// z-marching slabs of a 3-D level: columns of 32 x 16 points; enough runs of
+// planes that the launch has about 2048 blocks over max_rhs right-hand sides
+// (runs of at least 4 planes, at most NBMAX partials).
+SlabGeo slab_geo(unsigned nx, unsigned ny, unsigned nz, int max_rhs)
+{
+    SlabGeo g{0, 0, 0, 0, 0};
+    g.ntx = (nx + 31) / 32;
+    g.nty = (ny + 15) / 16;
+    const unsigned cols = g.ntx * g.nty;
+    if (cols == 0 || cols + 8 > (unsigned)NBMAX) return SlabGeo{0, 0, 0, 0, 0};
+    unsigned target = 2048u;
+    if (const char *e = getenv("CSG_SLAB_BLOCKS")) target = (unsigned)std::max(1, atoi(e));
+    unsigned want = (target + cols * max_rhs - 1) / (cols * max_rhs);
+    want = std::max(1u, std::min({want, (unsigned)(NBMAX - 8) / cols, std::max(1u, nz / 4)}));
+    g.zrun = (nz + want - 1) / want;
+    g.nzc = (nz + g.zrun - 1) / g.zrun;
+    g.npad = (g.ntx * g.nty * g.nzc + 7) / 8 * 8;
+    return g;
+}
+
 // The layout of every buffer in the workspace; `op` may be a dry-run object.
 void carve(csg_operator &op, const int nint[CSG_MAX_LEVELS][3], Carver &cv)
 {
@@ -160,6 +180,7 @@ void carve(csg_operator &op, const int nint[CSG_MAX_LEVELS][3], Carver &cv)
         geometry(lv.N, lv.nb, lv.chunk);
         lv.tile = p.dim == 2 ? tiling(lv.nu[0], lv.nu[1], lv.nb) : TileGeo{0, 0, 0, 0};
         lv.dtile = p.dim == 2 ? down_tiling(lv.nu[0], lv.nu[1], lv.tile) : TileGeo{0, 0, 0, 0};
+        lv.slab = p.dim == 3 ? slab_geo(lv.nu[0], lv.nu[1], lv.nu[2], R) : SlabGeo{0, 0, 0, 0};
         for (int a = 0; a < p.dim; ++a) lv.tab[a] = cv.take(3 * (size_t)lv.nu[a] * cz);
         for (int a = p.dim; a < 3; ++a) lv.tab[a] = nullptr;
         lv.phi = cv.take(lv.N * cr);
@@ -358,6 +379,13 @@ bool tiled(const csg_operator *op, int l)
     return DIM == 2 && op->tiles && op->p.s <= 3 && tile_fits(op->lev[l].tile);
 }
 
+// Whether level l's Arnoldi passes run on 3-D z-marching slabs.
+template <typename T, int DIM>
+bool slabbed(const csg_operator *op, int l)
+{
+    return DIM == 3 && op->p.s <= 3 && op->lev[l].slab.nzc > 0 && (long)op->lev[l].N >= op->slab_min;
+}
+
 // w = H z and its inner products on the finest level's tiles (the tiles of the
 // fused pass, which share the grid of H)
 template <int DIM>
@@ -399,6 +427,28 @@ int arnoldi_passes(const csg_operator *op, int l, const Basis<T> &B, int nrhs, h
     Cx<T> *W[2] = {(Cx<T> *)lv.w[0], (Cx<T> *)lv.w[1]};
     const bool sums = sizeof(T) == 8;   // FP64: h_{s,s-1} from the last pass's sums
     const bool tl = tiled<T, DIM>(op, l);
+    if (slabbed<T, DIM>(op, l)) {
+        // 3-D: pass 0 and the fused passes on z-marching slabs
+        const SlabGeo &sg = lv.slab;
+        const int nslab = (int)sg.npad;
+        {
+            ProfScope ps(op, l == 0 ? CSG_PROF_STENCIL_DOTS : -1, st, by.st(0, lv.N));
+            launch_slab<T>(L, B, nullptr, W[0], -1, s, lv.ld, nullptr, 0, lv.part[0], lv.gs, tiny, sums && s == 1, sg,
+                           nrhs, st, active);
+        }
+        for (int j = 0; j + 1 < s; ++j) {
+            ProfScope ps(op, l == 0 ? CSG_PROF_FUSED : -1, st, by.os(j, lv.N));
+            launch_slab<T>(L, B, W[j & 1], W[(j + 1) & 1], j, s, lv.ld, lv.part[j & 1], nslab, lv.part[(j + 1) & 1],
+                           lv.gs, tiny, sums && j + 2 == s, sg, nrhs, st, active);
+        }
+        if (!sums) {
+            ProfScope ps(op, l == 0 ? CSG_PROF_ORTH : -1, st, by.orth(s - 1, lv.N));
+            launch_orthl<T>(B, W[(s - 1) & 1], s - 1, s, lv.N, lv.ld, lv.part[(s - 1) & 1], nslab, lv.part[s & 1],
+                            lv.gs, tiny, g, active);
+            return lv.nb;
+        }
+        return nslab;
+    }
     if (!tl && lv.N > op->fuse_max) {
         // large level: stencil pass then Gram-Schmidt pass per step (fewer loads per point)
         for (int j = 0; j < s; ++j) {
@@ -452,7 +502,7 @@ zc *close_part(const csg_operator *op, int l)
 {
     const DevLevel &lv = op->lev[l];
     const int s = op->p.s;
-    const bool unfused = !tiled<T, DIM>(op, l) && lv.N > op->fuse_max;
+    const bool unfused = !tiled<T, DIM>(op, l) && !slabbed<T, DIM>(op, l) && lv.N > op->fuse_max;
     if (sizeof(T) == 8) return unfused ? lv.part[0] : lv.part[(s - 1) & 1];
     return unfused ? lv.part[1] : lv.part[s & 1];
 }
@@ -1190,6 +1240,11 @@ int csg_operator_create(const csg_params *p, const double *phi_host, void *ws_de
         if (const char *e = getenv("CSG_FORCE_CGS2")) op->force_cgs2 = atoi(e) != 0;
         op->poly_tiles = true;
         if (const char *e = getenv("CSG_POLY_TILES")) op->poly_tiles = atoi(e) != 0;
+        op->slab_min = 100000;
+        if (const char *e = getenv("CSG_SLAB_MIN")) op->slab_min = atol(e);
+        if (const char *e = getenv("CSG_SLABS"))
+            if (atoi(e) == 0) op->slab_min = -1;
+        if (op->slab_min < 0) op->slab_min = (long)1 << 62;
         for (int l = 0; l < op->L; ++l) {
             op->lev[l].varphi = hh.lev[l].varphi;
             op->lev[l].conds = hh.lev[l].conds;

@@ -115,6 +115,14 @@ int build_hierarchy(const csg_params &p, const double *phi, HostHier &hh, std::s
 struct TileGeo {
     unsigned ntx, nty, tx, ty;
 };
+// 3-D z-marching slabs of the Arnoldi passes: ntx x nty columns of 32 x 16
+// x-y points, each split into nzc runs of zrun planes (one partial per run);
+// launched as npad >= ntx * nty * nzc blocks, a multiple of 8 (the extra ones
+// only write zero partials) so every XCD receives a contiguous range of
+// columns and shares their halos in its L2.
+struct SlabGeo {
+    unsigned ntx, nty, nzc, zrun, npad;
+};
 constexpr int TILE_MAXE = 10;                 // halo-tile points per thread
 constexpr int TILE_PRE = 2;                   // of them loaded before the pass's reduction
 constexpr int TILE_PB = 4;                    // points per thread whose loads are issued together
@@ -168,6 +176,7 @@ struct DevLevel {
     unsigned chunk;            // points per block of a reducing pass
     TileGeo tile;              // 2-D tiling of the LDS-staged fused pass (ntx = 0: none)
     TileGeo dtile;             // tiling of the down-path pass that restricts onto this level
+    SlabGeo slab;              // 3-D slabs of the Arnoldi passes (nzc = 0: none)
     double varphi;             // polynomial smoother: p(t0) = e^{i varphi}
     cd omega[3];               // ... its Richardson weights, in the order they are applied
     int conds;                 // ... which necessary stability conditions varphi meets
@@ -212,6 +221,7 @@ struct csg_operator {
     bool fuse_upd;                    // coarse post-sweep updates applied by the finer up-path pass
     bool force_cgs2;                  // every outer column takes the second Gram-Schmidt round
     bool poly_tiles;                  // polynomial sweeps of 2-D levels run as one tiled launch
+    long slab_min;                    // 3-D levels from this size run the Arnoldi passes on z-marching slabs
     // outer FGMRES storage
     csg::zc *V;                       // (m+1) x max_rhs x ld0
     void *Z;                          // m x max_rhs x ld0, cycle precision

@@ -91,6 +91,14 @@ void launch_up_tile(const LvlK<T> &F, const LvlK<T> &C, const Cx<T> *ec, const C
                     const TileGeo &tg, int nrhs, hipStream_t st, const int *active,
                     const UpClose<T> *fuse = nullptr);
 
+// Arnoldi pass on 3-D z-marching slabs: j = -1 is pass 0 (w_0 = A u_0, like
+// launch_st0), j >= 0 the fused pass j+1 (like launch_os); s <= 3; one partial
+// per slab run.
+template <typename T>
+void launch_slab(const LvlK<T> &L, const Basis<T> &B, const Cx<T> *win, Cx<T> *wout, int j, int s, size_t ld,
+                 const zc *pin, int nbin, zc *pout, GState *gs, double tiny, bool wnorm, const SlabGeo &sg, int nrhs,
+                 hipStream_t st, const int *active);
+
 // Pass 0 of a sweep on 2-D tiles: w = A u0 with <u0, w>, ||u0||^2 (and
 // ||w||^2 when wnorm) per tile into pout; same outputs as launch_st0,
 // partials by tile.

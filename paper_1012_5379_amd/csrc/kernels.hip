@@ -1261,6 +1261,195 @@ __global__ __launch_bounds__(BLK) void k_os_tile(LvlK<T> L, Basis<T> B, const Cx
     if (threadIdx.x < nv) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + t] = res[threadIdx.x];
 }
 
+// ---------------------------------------------------------------------------
+// 3-D Arnoldi passes on z-marching slabs.  A block owns a column of
+// SX x SY points of the x-y plane over a run of planes; it forms the pass's
+// vector u (u_0 itself for pass 0, else u_{j+1} = sj w_j - sum cu_i u_i) on the
+// column's points and their one-point x-y halo, one plane at a time, into a
+// ring of three shared-memory planes, and applies the 7-point stencil to the
+// middle plane from there.  Every point of u is read (or formed) once per
+// block plus the halo (x-y ring, one plane above and below the run), instead
+// of once per stencil neighbour as in the chunked passes, whose z neighbours
+// lie a whole plane away.  Outputs match k_st0 (J = -1) and k_os (J = j):
+// w = A u, u_{j+1} stored for the run's own planes, and the partial sums
+// <u_i, w> (i < m), <u_m, w>, ||u_m||^2 (and ||w||^2 on the sweep's last
+// step), m = J + 1, one partial per block.
+// ---------------------------------------------------------------------------
+constexpr int SX = 32, SY = 16;             // slab column: SX * SY = BLK points per plane
+constexpr int SHX = SX + 2, SHY = SY + 2;   // with the x-y halo
+constexpr int SRING = 2 * SHX + 2 * SY;     // halo points of one plane
+static_assert(SX * SY == BLK && SRING <= BLK, "one column point and at most one halo point per thread");
+
+// The unit value at halo-plane position of ring index r (x-y halo of a TX x TY
+// column): (ex, ey) in [0, TX + 1] x [0, TY + 1].
+__device__ __forceinline__ void ring_pos(int r, int TX, int TY, int &ex, int &ey)
+{
+    const int W = TX + 2;
+    if (r < W) { ex = r; ey = 0; }
+    else if (r < 2 * W) { ex = r - W; ey = TY + 1; }
+    else if (r < 2 * W + TY) { ex = 0; ey = 1 + r - 2 * W; }
+    else { ex = TX + 1; ey = 1 + r - 2 * W - TY; }
+}
+
+template <typename T, int SB, int J>
+__global__ __launch_bounds__(BLK) void k_slab(LvlK<T> L, Basis<T> B, const Cx<T> *win, Cx<T> *wout, int s, size_t ld,
+                                              const zc *__restrict__ pin, int nbin, zc *__restrict__ pout,
+                                              GState *gsb, double tiny, unsigned ntx, unsigned nty, unsigned nzc,
+                                              unsigned zrun, int wnorm, int nslab, const int *active)
+{
+    constexpr int M = J + 1;                   // index of the pass's vector
+    constexpr int NU = J + 1;                  // older basis vectors read for the dots (J >= 0)
+    static_assert(M + 3 <= SB + 1, "sum slots");
+    __shared__ zc sh[(BLK / 64) * (SB + 1)];
+    __shared__ zc res[SB + 1];
+    __shared__ Cx<T> ring[3][SHX * SHY];
+    __shared__ Cx<T> ltab[3 * SX + 3 * SY];
+    const int rhs = blockIdx.y;
+    if (!active[rhs]) return;
+    const size_t off = rhs * ld;
+    // GMRES coefficients of this step from the previous pass's partials
+    Cx<T> cu[SB];
+    T sj = (T)1;
+    if (J >= 0) {
+        GState *gs = gsb + rhs;
+        const GPrev<SB> pv = load_prev<SB>(gs, J);
+        reduce_parts<SB + 1>(pin + (size_t)rhs * NVAL * NBMAX, nbin, J + 2, sh, res);
+        sj = (T)coef_step<T, SB>(res, J, s, tiny, pv, gs, blockIdx.x == 0 && threadIdx.x == 0, cu);
+    }
+    const unsigned slot = chunk_id(nslab);
+    const unsigned col = slot / nzc, zci = slot - col * nzc;
+    if (col >= ntx * nty) {
+        // padding block: zero partials
+        if ((int)threadIdx.x < M + 3) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + slot] = mkc(0.0, 0.0);
+        return;
+    }
+    const unsigned cyi = col / ntx, cxi = col - cyi * ntx;
+    const int nx = (int)L.nx, ny = (int)L.ny, nz = (int)L.nz;
+    const int x0 = (int)cxi * SX, y0 = (int)cyi * SY;
+    const int TX = min(SX, nx - x0), TY = min(SY, ny - y0);
+    const int z0 = (int)(zci * zrun), z1 = min(nz, z0 + (int)zrun);
+    // this thread's column point and (maybe) one halo point of every plane
+    const int tx = threadIdx.x % SX, ty = threadIdx.x / SX;
+    const bool own = tx < TX && ty < TY;
+    const int eo = (ty + 1) * SHX + tx + 1;
+    const unsigned po = (unsigned)(y0 + min(ty, TY - 1)) * nx + (x0 + min(tx, TX - 1));
+    int er = -1;
+    unsigned pr = 0;
+    bool rin = false;
+    if ((int)threadIdx.x < 2 * (TX + 2) + 2 * TY) {
+        int ex, ey;
+        ring_pos(threadIdx.x, TX, TY, ex, ey);
+        er = ey * SHX + ex;
+        const int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
+        rin = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        pr = rin ? (unsigned)gy * nx + gx : po;
+    }
+    // the column's x and y stencil rows
+    for (int q = threadIdx.x; q < 3 * (TX + TY); q += BLK) {
+        if (q < 3 * TX) {
+            const int a = q / TX, c = q - a * TX;
+            ltab[a * SX + c] = L.tab[0][a * nx + x0 + c];
+        } else {
+            const int qq = q - 3 * TX, a = qq / TY, c = qq - a * TY;
+            ltab[3 * SX + a * SY + c] = L.tab[1][a * ny + y0 + c];
+        }
+    }
+    const unsigned plane = (unsigned)nx * ny;
+    // the values a plane's u is formed from at one point (w_j and u_0..u_j,
+    // or u_0 itself), loaded one plane ahead of their use
+    struct Raw {
+        Cx<T> w;
+        Cx<T> u[NU > 0 ? NU : 1];
+    };
+    auto load = [&](int k, Raw &ro, Raw &rr, T &ph) {
+        const unsigned kp = (unsigned)max(0, min(k, nz - 1)) * plane;
+        if (J < 0) {
+            ro.w = B.u[0][off + kp + po];
+            rr.w = B.u[0][off + kp + pr];
+        } else {
+            ro.w = win[off + kp + po];
+            rr.w = win[off + kp + pr];
+#pragma unroll
+            for (int q = 0; q < NU; ++q) {
+                ro.u[q] = B.u[q][off + kp + po];
+                rr.u[q] = B.u[q][off + kp + pr];
+            }
+        }
+        ph = L.phi[kp + po];
+    };
+    auto combine = [&](const Raw &r) -> Cx<T> {
+        if (J < 0) return r.w;
+        Cx<T> v = sj * r.w;
+#pragma unroll
+        for (int q = 0; q < NU; ++q) v = v - cu[q] * r.u[q];
+        return v;
+    };
+    Cx<T> *un = J >= 0 ? B.u[M] + off : nullptr;
+    // plane k into ring slot k % 3 (zero outside the level); u_{j+1} of the
+    // run's own planes also to memory; returns the column point's u
+    auto stage = [&](int k, const Raw &ro, const Raw &rr) -> Cx<T> {
+        Cx<T> *R = ring[(k + 3) % 3];
+        const bool kin = k >= 0 && k < nz;
+        const Cx<T> uo = combine(ro);
+        if (er >= 0) R[er] = (kin && rin) ? combine(rr) : mkc<T>(0, 0);
+        R[eo] = (kin && own) ? uo : mkc<T>(0, 0);
+        if (J >= 0 && kin && own && k >= z0 && k < z1) un[(size_t)k * plane + po] = uo;
+        return uo;
+    };
+    zc acc[SB + 1];
+#pragma unroll
+    for (int q = 0; q <= SB; ++q) acc[q] = mkc(0.0, 0.0);
+    const bool wn = wnorm != 0;
+    Raw ro, rr, ro2, rr2;
+    T phc, phn, dph;
+    load(z0 - 1, ro, rr, dph);
+    stage(z0 - 1, ro, rr);
+    load(z0, ro, rr, phc);
+    Cx<T> uc = stage(z0, ro, rr);
+    Cx<T> ucq[NU > 0 ? NU : 1];
+#pragma unroll
+    for (int q = 0; q < NU; ++q) ucq[q] = ro.u[q];
+    load(z0 + 1, ro, rr, phn);
+    for (int k = z0; k < z1; ++k) {
+        const Cx<T> unx = stage(k + 1, ro, rr);
+        // the plane after next is in flight while this plane's stencil runs
+        T ph2 = phn;
+        if (k + 2 <= z1) load(k + 2, ro2, rr2, ph2);
+        __syncthreads();
+        if (own) {
+            const Cx<T> *Rm = ring[(k + 2) % 3], *R0 = ring[k % 3], *Rp = ring[(k + 1) % 3];
+            const Cx<T> *tz = L.tab[2];
+            Cx<T> d = ltab[SX + tx] + ltab[3 * SX + SY + ty] + tz[nz + k];
+            d.re -= phc;
+            Cx<T> a = d * R0[eo];
+            a = cfma(ltab[tx], R0[eo - 1], a);
+            a = cfma(ltab[2 * SX + tx], R0[eo + 1], a);
+            a = cfma(ltab[3 * SX + ty], R0[eo - SHX], a);
+            a = cfma(ltab[3 * SX + 2 * SY + ty], R0[eo + SHX], a);
+            a = cfma(tz[k], Rm[eo], a);
+            a = cfma(tz[2 * nz + k], Rp[eo], a);
+            wout[off + (size_t)k * plane + po] = a;
+            const zc wd = cvt<double>(a), ud = cvt<double>(uc);
+#pragma unroll
+            for (int q = 0; q < NU; ++q) acc[q] = cjfma(cvt<double>(ucq[q]), wd, acc[q]);
+            acc[M] = cjfma(ud, wd, acc[M]);
+            acc[M + 1].re += cabs2(ud);
+            if (wn) acc[M + 2].re += cabs2(wd);
+        }
+        __syncthreads();
+        uc = unx;
+        phc = phn;
+#pragma unroll
+        for (int q = 0; q < NU; ++q) ucq[q] = ro.u[q];
+        ro = ro2;
+        rr = rr2;
+        phn = ph2;
+    }
+    const int nv = M + 2 + (wn ? 1 : 0);
+    block_sum_last<SB + 1>(acc, nv, sh, res);
+    if ((int)threadIdx.x < nv) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + slot] = res[threadIdx.x];
+}
+
 // Pass 0 on one 2-D tile (see launch_st0_tile): u_0 on the tile and its
 // one-point halo into shared memory (zero outside the level), then w_0 = A u_0
 // on the tile's points with <u_0, w_0>, ||u_0||^2 and (NA = 3) ||w_0||^2.  All
@@ -3700,6 +3889,24 @@ void launch_os_tile(const LvlK<T> &L, const Basis<T> &B, const Cx<T> *win, Cx<T>
 }
 
 template <typename T>
+void launch_slab(const LvlK<T> &L, const Basis<T> &B, const Cx<T> *win, Cx<T> *wout, int j, int s, size_t ld,
+                 const zc *pin, int nbin, zc *pout, GState *gs, double tiny, bool wnorm, const SlabGeo &sg, int nrhs,
+                 hipStream_t st, const int *active)
+{
+    const int nslab = (int)sg.npad;
+    const dim3 gr(nslab, nrhs);
+    if (j < 0)
+        hipLaunchKernelGGL((k_slab<T, 4, -1>), gr, dim3(BLK), 0, st, L, B, win, wout, s, ld, pin, nbin, pout, gs, tiny,
+                           sg.ntx, sg.nty, sg.nzc, sg.zrun, wnorm ? 1 : 0, nslab, active);
+    else if (j == 0)
+        hipLaunchKernelGGL((k_slab<T, 4, 0>), gr, dim3(BLK), 0, st, L, B, win, wout, s, ld, pin, nbin, pout, gs, tiny,
+                           sg.ntx, sg.nty, sg.nzc, sg.zrun, wnorm ? 1 : 0, nslab, active);
+    else
+        hipLaunchKernelGGL((k_slab<T, 4, 1>), gr, dim3(BLK), 0, st, L, B, win, wout, s, ld, pin, nbin, pout, gs, tiny,
+                           sg.ntx, sg.nty, sg.nzc, sg.zrun, wnorm ? 1 : 0, nslab, active);
+}
+
+template <typename T>
 void launch_st0_tile(const LvlK<T> &L, const Cx<T> *u0, Cx<T> *w, size_t ld, bool wnorm, zc *pout, const TileGeo &tg,
                      int nrhs, hipStream_t st, const int *active)
 {
@@ -3857,7 +4064,7 @@ void launch_coarse(const Cx<T> *minvT, int n, const Cx<T> *b, Cx<T> *x, size_t l
 // the Givens step, the report and the stop test (stop clears the RHS in the
 // mask; blocks that read the mask after that skip their chunk of a v_{j+1}
 // that is never used).
-template <typename TB>
+template <typename TB, int JB>
 __global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__restrict__ V, size_t vstride, int j,
                                                unsigned N, size_t ld, FState *fsb, Report *rep, int *stop,
                                                const zc *__restrict__ pin, int nbin, zc *__restrict__ pout,
@@ -3902,7 +4109,48 @@ __global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__r
     zc acc[1] = {mkc(0.0, 0.0)};
     const unsigned c = chunk_id(nb);
     const unsigned p0 = c * chunk + threadIdx.x, p1 = min(N, c * chunk + chunk);
-    if (p0 < p1) {
+    if (JB > 0) {
+        // every basis value of a point held in registers: the first projection
+        // and, for a second round, its inner products <v_i, w_1> in one pass
+        // over V (j + 1 <= JB)
+        zc dots[JB > 0 ? JB : 1];
+#pragma unroll
+        for (int q = 0; q < JB; ++q) dots[q] = mkc(0.0, 0.0);
+        for (unsigned p = p0; p < p1; p += BLK) {
+            zc v[JB > 0 ? JB : 1];
+#pragma unroll
+            for (int q = 0; q < JB; ++q)
+                if (q <= j) v[q] = V[q * vstride + off + p];
+            zc x = w[off + p];
+#pragma unroll
+            for (int q = 0; q < JB; ++q)
+                if (q <= j) x = x - cc[q] * v[q];
+            if (two) {
+                w[off + p] = x;
+                acc[0].re += cabs2(x);
+#pragma unroll
+                for (int q = 0; q < JB; ++q)
+                    if (q <= j) dots[q] = cjfma(v[q], x, dots[q]);
+            } else {
+                const zc vn = sc * x;
+                vout[off + p] = vn;
+                if (bc) bc[off + p] = cvt<TB>(vn);
+            }
+        }
+        if (two) {
+            zc *po = pout + (size_t)rhs * OVAL * NBMAX;
+            block_sum<1>(acc, 1, sh, res);
+            if (threadIdx.x == 0) po[(j + 1) * NBMAX + c] = res[0];
+#pragma unroll
+            for (int g = 0; g < (JB + 7) / 8; ++g) {
+                if (8 * g > j) break;
+                zc d8[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) d8[q] = 8 * g + q < JB ? dots[8 * g + q < JB ? 8 * g + q : 0] : mkc(0.0, 0.0);
+                store_group(d8, g, j, po, c, sh, res);
+            }
+        }
+    } else if (p0 < p1) {
         const unsigned last = p1 - 1;
         for (unsigned p = p0; p < p1; p += UO * BLK) {
             zc x[UO];
@@ -3921,7 +4169,7 @@ __global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__r
             }
         }
     }
-    if (two) {
+    if (JB == 0 && two) {
         zc *po = pout + (size_t)rhs * OVAL * NBMAX;
         block_sum<1>(acc, 1, sh, res);
         if (threadIdx.x == 0) po[(j + 1) * NBMAX + c] = res[0];
@@ -4070,8 +4318,17 @@ void launch_proj0(zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t 
                   int *stop, const zc *pin, int nbin, zc *pout, zc *vout, Cx<TB> *bcast, const Launch &g,
                   const int *active)
 {
-    hipLaunchKernelGGL((k_proj0<TB>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop, pin, nbin,
-                       pout, vout, bcast, g.chunk, g.nb, active);
+    // columns of up to 16 basis vectors keep a point's whole basis in registers
+    // (more would spill)
+    if (j + 1 <= 8)
+        hipLaunchKernelGGL((k_proj0<TB, 8>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop, pin,
+                           nbin, pout, vout, bcast, g.chunk, g.nb, active);
+    else if (j + 1 <= 16)
+        hipLaunchKernelGGL((k_proj0<TB, 16>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop, pin,
+                           nbin, pout, vout, bcast, g.chunk, g.nb, active);
+    else
+        hipLaunchKernelGGL((k_proj0<TB, 0>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop, pin,
+                           nbin, pout, vout, bcast, g.chunk, g.nb, active);
 }
 
 template <typename TB>
@@ -4282,6 +4539,9 @@ template void launch_hdot_tile<float>(const LvlK<double> &, const Cx<float> *, z
     template void launch_proj0<T>(zc *, const zc *, size_t, int, unsigned, size_t, FState *, Report *, int *,      \
                                   const zc *, int, zc *, zc *, Cx<T> *, const Launch &, const int *);              \
     template void launch_uupd<T>(zc *, const Cx<T> *, size_t, unsigned, size_t, const FState *, const Launch &,    \
+                                 const int *);                                                                     \
+    template void launch_slab<T>(const LvlK<T> &, const Basis<T> &, const Cx<T> *, Cx<T> *, int, int, size_t,     \
+                                 const zc *, int, zc *, GState *, double, bool, const SlabGeo &, int, hipStream_t, \
                                  const int *);                                                                     \
     template void launch_poly_tile<T>(const LvlK<T> &, const LvlK<T> &, const Cx<T> *, const Cx<T> *,            \
                                       const Cx<T> *, Cx<T> *, const Cx<T>(&)[3], size_t, size_t, int, hipStream_t, \

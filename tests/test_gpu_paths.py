@@ -24,9 +24,12 @@ TOL32 = {"smooth": 6e-6, "vcycle": 6e-6}   # about ten times the largest error o
 # 2048^2, 128^3 and 192^3 grids), and the same with the fused untiled passes
 # (the mid-size 3-D levels)
 PATHS = {
-    "unfused": {"CSG_TILES": "0", "CSG_FUSE_MAX": "0", "CSG_TAIL_MAX": "0", "CSG_HDOT_TILES": "0"},
+    "unfused": {"CSG_TILES": "0", "CSG_FUSE_MAX": "0", "CSG_TAIL_MAX": "0", "CSG_HDOT_TILES": "0",
+                "CSG_SLABS": "0"},
     "fused_untiled": {"CSG_TILES": "0", "CSG_FUSE_MAX": "1000000000", "CSG_TAIL_MAX": "0",
-                      "CSG_HDOT_TILES": "0"},
+                      "CSG_HDOT_TILES": "0", "CSG_SLABS": "0"},
+    # every 3-D level on z-marching slabs (the large 3-D levels' path)
+    "slab": {"CSG_SLAB_MIN": "0", "CSG_TAIL_MAX": "0"},
 }
 CASES = {k: v for k, v in cases().items() if k in ("2d_wide", "3d_ragged")}
 
@@ -61,16 +64,17 @@ def test_sweep_and_vcycle(name, path, prec, monkeypatch):
         assert e <= (TOL64 if prec == 0 else TOL32["vcycle"])
 
 
+@pytest.mark.parametrize("path", ["unfused", "slab"])
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("name", list(CASES))
-def test_fgmres_unfused(name, prec, monkeypatch):
-    """The whole solve on the unfused, untiled passes: two RHS, complex128
+def test_fgmres_large_grid_paths(name, prec, path, monkeypatch):
+    """The whole solve on the unfused, untiled passes, and on 3-D slabs: two RHS, complex128
     cycle iterations +-1 and solution within 1e-10 of the oracle; complex64
     cycle true residual at the tolerance and solution error against the
     oracle's tightly converged answer within ten times the error any solve
     stopping at that tolerance has."""
     import torch
-    _env(monkeypatch, "unfused")
+    _env(monkeypatch, path)
     w = CASES[name]()
     chi = np.stack([w.chi[0], rvec(w.chi.shape[1:], 460)])
     op, orc = pair(w, max_rhs=2, cycle_prec=prec)
