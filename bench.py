@@ -2,16 +2,21 @@
 """Benchmark of the GMRES-smoothed CSG multigrid / FGMRES Helmholtz solve on one
 MI355X.
 
-One step = one complete solve of the 2-D 1024^2-interior problem with 32-cell
-ECS layers (phi = k0^2 (1 - 0.5 exp(-|x-c|^2/0.02)), kh = 0.5, Gaussian source
-of width 2h, beta = 0.4, 8 levels, V(1,1) with GMRES(3), FGMRES(30) to true
-relative residual 1e-6, all in complex128): every pass of the hot path (setup
-excluded, inputs resident in HBM) runs inside each step.
+Default workload (the largest single-GPU configuration, all in complex128):
+the 3-D 128^3-interior problem with 16-cell ECS layers (phi = k^2 (1 + 0.3 g),
+g a smooth random field with correlation length 8h, max kh = 0.5), 16
+unit point sources solved together, beta = 0.4, 6 levels, V(1,1) with
+GMRES(3), FGMRES(30) to true relative residual 1e-6.  One step = one complete
+solve of all 16 right-hand sides (every pass of the hot path, setup excluded,
+inputs resident in HBM); `value` counts right-hand sides solved per second.
+The same inputs are then solved with the V-cycle in complex64 (outer FGMRES in
+complex128), reported beside it as the mixed-precision gain.
 
 Printed JSON (one line): solves/s as `value`, p50/p99 solve latency, V-cycle
 GB/s, the roofline of the dominant pass (its algorithmic bytes per launch over
 its average launch time, both measured with HIP events on the solve's stream
-inside the timed region), and the CPU oracle timed on a bounded sample.
+inside the timed region), a measured device-to-device copy ceiling, and the
+CPU oracle timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -24,18 +29,22 @@ import time
 import numpy as np
 
 HBM_PEAK_GBPS = 8000.0
+MALL_BYTES = 256 << 20
 HERE = os.path.dirname(os.path.abspath(__file__))
-PMC_SUMMARY = os.path.join(HERE, "profiles", "pmc_fused_c2_1024sq_fp64.txt")
+PMC_SUMMARY = {"c2": "pmc_c2_1024sq_fp64.txt", "c4_fp64": "pmc_c4_128cube_16rhs_fp64.txt"}
 
 
 def counted_traffic(kind: str, workload: str):
-    """HBM bytes per launch of the finest-level fused pass from the committed
-    rocprofv3 counter summary, if it was taken on the current library sources."""
-    if kind != "fused" or workload != "c2" or not os.path.exists(PMC_SUMMARY):
+    """HBM bytes per launch of one pass kind from the committed rocprofv3
+    counter summary of this workload, if it was taken on the current library
+    sources (null otherwise)."""
+    name = PMC_SUMMARY.get(workload)
+    path = os.path.join(HERE, "profiles", name) if name else None
+    if not path or not os.path.exists(path):
         return None
     from paper_1012_5379_amd.trace_summary import source_hash
     vals = {}
-    with open(PMC_SUMMARY) as f:
+    with open(path) as f:
         for line in f:
             if ":" in line:
                 k, v = line.split(":", 1)
@@ -43,9 +52,31 @@ def counted_traffic(kind: str, workload: str):
     if vals.get("source_sha256") != source_hash():
         return None
     try:
-        return float(vals["traffic_bytes_per_launch"])
+        return float(vals[f"traffic_bytes_per_launch[{kind}]"])
     except (KeyError, ValueError):
         return None
+
+
+def copy_ceiling(torch, mib=2048, reps=5):
+    """Device-to-device copy rate (bytes read + written per second) of a plain
+    torch copy of `mib` MiB, timed with events: the streaming ceiling the
+    passes are compared with beside the nominal HBM peak."""
+    n = mib << 20
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 2.0 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbps
+
+
 METRIC = "solves/s & p99 latency at relres 1e-6; V-cycle GB/s vs HBM peak"
 
 
@@ -63,6 +94,8 @@ def _workload(name):
         return W.c4(), "3d_128cube_ecs16_16rhs_beta0.4_6lev_c64cycle"
     if name == "c4_fp64":
         return W.c4(cycle_prec=0), "3d_128cube_ecs16_16rhs_beta0.4_6lev_fp64"
+    if name == "c2_mixed":
+        return W.c2().with_(cycle_prec=1), "2d_1024sq_ecs32_kh0.5_gauss_beta0.4_8lev_c64cycle"
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -95,6 +128,12 @@ def cpu_baseline(w, its_per_solve, sample_its):
                    f"({dt:.1f} s, {per_it * 1e3:.1f} ms/iteration; setup {t_setup:.2f} s excluded), "
                    f"scaled to the {its_per_solve} iterations of a full solve of one right-hand side"),
     }
+
+
+def vcycle_working_set(level_sizes, nrhs, csize, s=3):
+    """Bytes the V-cycle touches: per non-coarsest level the cycle vectors
+    (b, x twice, r, u_1..u_s, w twice) of every RHS, plus phi."""
+    return sum(n * (nrhs * (s + 6) * csize + csize // 2) for n in level_sizes[:-1])
 
 
 def serve_bench(args):
@@ -173,9 +212,10 @@ def serve_bench(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c4_fp64")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the complex64-cycle solve of the same inputs")
     ap.add_argument("--cpu-sample-its", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-survey", action="store_true", help="skip the per-pass time survey")
@@ -231,6 +271,8 @@ def main():
 
     print(f"[bench] workload {wname}: levels {op.levels} dims {op.dims[0]}; setup {t_setup:.2f}s", file=sys.stderr,
           flush=True)
+    op_levels = [int(np.prod(d)) for d in op.dims[: op.levels]]
+    n_levels = op.levels
     for i in range(args.warmup):
         infos = solve()
         print(f"[bench] warmup {i}: {infos[0]['iterations']} its, relres {infos[0]['relres_true']:.2e}, "
@@ -277,6 +319,40 @@ def main():
     kms, kn, kbytes = B.csg_profile_read(op.op)
     B.csg_profile(op.op, 0, 0)
     its = infos[0]["iterations"]
+    relres = max(i["relres_true"] for i in infos)
+
+    # the same inputs with the V-cycle in complex64 (outer FGMRES complex128)
+    mixed = None
+    if not args.no_mixed and not w.cycle_prec:
+        del op
+        torch.cuda.empty_cache()
+        opm = Operator(dict(params, cycle_prec=1), w.phi)
+
+        def solve_m():
+            rc, inf = B.helm_solve(opm.op, chi.data_ptr(), u.data_ptr(), nrhs, w.tol, w.restart, w.maxit, 0, stream)
+            if rc != 0:
+                raise RuntimeError(f"complex64-cycle solve did not converge: {B.STATUS.get(rc, rc)}")
+            return inf
+
+        for _ in range(max(1, args.warmup)):
+            solve_m()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(args.steps):
+            inf = solve_m()
+        torch.cuda.synchronize()
+        el_m = time.perf_counter() - t2
+        mixed = {"value": args.steps * nrhs / el_m, "unit": "solves/s", "ms_per_step": el_m / args.steps * 1e3,
+                 "gain_over_fp64": (args.steps * nrhs / el_m) / (args.steps * nrhs / elapsed),
+                 "iterations_per_solve": inf[0]["iterations"],
+                 "relres_true_max": max(i["relres_true"] for i in inf),
+                 "cycle_dtype": "c64", "outer_dtype": "f64"}
+        print(f"[bench] complex64 cycle: {mixed['ms_per_step']:.1f} ms per step, {inf[0]['iterations']} its, "
+              f"gain {mixed['gain_over_fp64']:.3f}", file=sys.stderr, flush=True)
+        del opm
+    # (not in counter-calibration runs: their one plain copy must stay the largest)
+    ceiling = copy_ceiling(torch) if args.calibrate_copy <= 0 else 0.0
+    print(f"[bench] device copy ceiling {ceiling:.0f} GB/s", file=sys.stderr, flush=True)
 
     value = args.steps * nrhs / elapsed
     achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
@@ -294,11 +370,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if w.cycle_prec else "f64",
         "data": "synthetic",
-        "config": {"workload": wname, "unknowns": int(w.unknowns), "nrhs": nrhs, "levels": op.levels,
+        "config": {"workload": wname, "unknowns": int(w.unknowns), "nrhs": nrhs, "levels": n_levels,
                    "tol": w.tol, "restart": w.restart, "cycle": "V(1,1) GMRES(3)",
                    "outer_dtype": "f64", "parallelism": "single-gpu", "hip_graphs": graphs},
         "iterations_per_solve": its,
-        "relres_true": infos[0]["relres_true"],
+        "relres_true": relres,
         "p50_latency_ms": float(np.percentile(lat_ms, 50)),
         "p99_latency_ms": float(np.percentile(lat_ms, 99)),
         "roofline": {
@@ -314,13 +390,23 @@ def main():
             "alg_bytes_per_launch": kbytes / max(1, kn),
             "region": f"{args.steps} solves right after the timed region, same inputs, each {dominant} launch "
                       f"timed with a HIP event pair ({elapsed_instr / args.steps * 1e3:.1f} ms per solve there)",
+            "copy_ceiling": ceiling,
+            "frac_of_copy_ceiling": achieved / ceiling if ceiling > 0 else None,
         },
+        "copy_ceiling_GBps": ceiling,
     }
+    if mixed:
+        out["mixed_precision"] = mixed
     if "vcycle" in survey:
         v = survey["vcycle"]
         out["vcycle_GBps"] = v["GBps"]
         out["vcycle_ms"] = v["ms_per_solve"] / max(1, v["launches"])
         out["vcycle_frac_of_hbm_peak"] = v["GBps"] / HBM_PEAK_GBPS
+        # a working set inside the 256 MB Infinity Cache makes the rate an
+        # effective one, not an HBM fraction
+        ws = vcycle_working_set(op_levels, nrhs, 8 if w.cycle_prec else 16)
+        out["vcycle_working_set_MB"] = ws / 1e6
+        out["vcycle_rate_kind"] = "hbm" if ws > MALL_BYTES else "effective (Infinity-Cache resident working set)"
         out["pass_survey_ms_per_solve"] = {k: round(v["ms_per_solve"], 3) for k, v in survey.items()}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, its, args.cpu_sample_its)

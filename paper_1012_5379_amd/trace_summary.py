@@ -5,18 +5,19 @@
 
 `kernels` reads a kernel trace (rocprofv3 --kernel-trace --output-format csv)
 and prints, per kernel and grid size, the dispatch count and the average, min
-and max duration, then the finest-level fused Arnoldi pass on its own.  That
-pass shares its kernel and grid size with the next level's, so its launches
-are told apart by position: every FGMRES iteration is one V-cycle followed by
-k_hdot, and the V-cycle opens and closes on the finest level, so its first two
-and last two fused launches are the finest level's (s = 3).
+and max duration, then the pass kinds bench.py times on their own.  The 2-D
+finest-level fused pass shares its kernel and grid size with the next level's,
+so its launches are told apart by position: every FGMRES iteration is one
+V-cycle followed by k_hdot, and the V-cycle opens and closes on the finest
+level, so its first two and last two fused launches are the finest level's
+(s = 3); 3-D slab passes of the finest level have the largest grid.
 
 `counters` reads two counter collections of the same command (rocprofv3
 --pmc FETCH_SIZE, then --pmc WRITE_SIZE; KiB per dispatch), scales each by
 what the counter reads for the run's plain device-to-device copy of
 --copy-bytes bytes (the largest __amd_rocclr_copyBuffer dispatch), and prints
-the HBM bytes per launch of the finest-level fused pass, with the hash of the
-library sources the counters belong to.
+the HBM bytes per dispatch of every kernel and per launch of each pass kind,
+with the hash of the library sources the counters belong to.
 """
 from __future__ import annotations
 
@@ -79,33 +80,74 @@ def kernels(trace: str) -> None:
     for (nm, g), v in sorted(by.items(), key=lambda kv: -sum(kv[1])):
         print(f"{nm[:44]:44s} {g:6d} {len(v):7d} {sum(v) / len(v):9.2f} {min(v):8.2f} {max(v):8.2f} "
               f"{100 * sum(v) / tot:8.2f}")
-    idx = finest_fused(names)
-    if idx:
+    blocks = [_blocks(r) for r in rows]
+    for kind, idx in kind_launches(names, blocks).items():
         d = [dur[i] for i in idx]
-        print(f"\nfinest-level fused pass ({FUSED}, first two and last two fused launches of each V-cycle): "
-              f"n {len(d)}, avg {sum(d) / len(d):.2f} us, min {min(d):.2f} us, max {max(d):.2f} us")
+        print(f"\n{kind}: n {len(d)}, avg {sum(d) / len(d):.2f} us, min {min(d):.2f} us, max {max(d):.2f} us")
     print(f"dispatches {len(rows)}, kernel time {tot / 1e3:.2f} ms")
 
 
-def counters(fetch_csv: str, write_csv: str, copy_bytes: int) -> None:
+def _blocks(r) -> int:
+    """Workgroups of a dispatch (counter collections give the total grid)."""
+    if "Grid_Size" in r:
+        return int(r["Grid_Size"]) // int(r["Workgroup_Size"])
+    return (int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"])) * int(r.get("Grid_Size_Y", 1))
+
+
+def kind_launches(names, blocks):
+    """Dispatch indices of the pass kinds bench.py times: the finest level's
+    fused Arnoldi passes and pass 0 (2-D tiles: by position, see finest_fused;
+    3-D slabs: the largest grid of k_slab), and the three outer FGMRES passes."""
     out = {}
+    fused2 = finest_fused(names)
+    if fused2:
+        out["fused"] = fused2
+        out["stencil_dots"] = [i for i, nm in enumerate(names) if nm.startswith("k_st0_tile")]
+    slab = [i for i, nm in enumerate(names) if nm.startswith("k_slab")]
+    if slab:
+        top = max(blocks[i] for i in slab)
+        out["fused"] = [i for i in slab if blocks[i] == top and not names[i].endswith("-1>")]
+        out["stencil_dots"] = [i for i in slab if blocks[i] == top and names[i].endswith("-1>")]
+    out["outer_h"] = [i for i, nm in enumerate(names) if nm.startswith("k_hdot")]
+    out["outer_cgs1"] = [i for i, nm in enumerate(names) if nm.startswith("k_proj0")]
+    out["outer_proj2"] = [i for i, nm in enumerate(names) if nm.startswith("k_proj1")]
+    return {k: v for k, v in out.items() if v}
+
+
+def counters(fetch_csv: str, write_csv: str, copy_bytes: int) -> None:
+    per = {}
+    scales = {}
+    names = blocks = None
     for key, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         rows = sorted(_rows(path), key=lambda r: int(r["Dispatch_Id"]))
-        names = [_short(r["Kernel_Name"]) for r in rows]
+        nm = [_short(r["Kernel_Name"]) for r in rows]
         vals = [float(r["Counter_Value"]) * 1024.0 for r in rows]
-        copies = [v for nm, v in zip(names, vals) if nm.startswith("__amd_rocclr_copyBuffer")]
+        copies = [v for n, v in zip(nm, vals) if n.startswith("__amd_rocclr_copyBuffer")]
         ref = max(copies) if copies else 0.0
         scale = copy_bytes / ref if ref > 0 else float("nan")
-        idx = finest_fused(names)
-        per = [vals[i] * scale for i in idx]
-        out[key] = (scale, sum(per) / len(per) if per else float("nan"), len(per), ref)
-    f, w = out["FETCH_SIZE"], out["WRITE_SIZE"]
-    print(f"calibration copy: {copy_bytes} bytes; FETCH_SIZE read {f[3]:.0f} bytes (scale {f[0]:.4f}), "
-          f"WRITE_SIZE read {w[3]:.0f} bytes (scale {w[0]:.4f})")
-    print(f"finest-level fused pass: {f[2]} launches")
-    print(f"fetch_bytes_per_launch: {f[1]:.0f}")
-    print(f"write_bytes_per_launch: {w[1]:.0f}")
-    print(f"traffic_bytes_per_launch: {f[1] + w[1]:.0f}")
+        scales[key] = (scale, ref)
+        per[key] = [v * scale for v in vals]
+        names, blocks = nm, [_blocks(r) for r in rows]
+    f, w = scales["FETCH_SIZE"], scales["WRITE_SIZE"]
+    print(f"calibration copy: {copy_bytes} bytes; FETCH_SIZE read {f[1]:.0f} bytes (scale {f[0]:.4f}), "
+          f"WRITE_SIZE read {w[1]:.0f} bytes (scale {w[0]:.4f})")
+    print("\nper kernel and grid (workgroups), scaled bytes per dispatch:")
+    print(f"{'kernel':40s} {'blocks':>7s} {'n':>6s} {'fetch MB':>10s} {'write MB':>10s}")
+    agg = collections.defaultdict(list)
+    for i, (n, b) in enumerate(zip(names, blocks)):
+        agg[(n, b)].append(i)
+    tot = lambda ix, k: sum(per[k][i] for i in ix)
+    for (n, b), ix in sorted(agg.items(), key=lambda kv: -(tot(kv[1], "FETCH_SIZE") + tot(kv[1], "WRITE_SIZE")))[:30]:
+        print(f"{n[:40]:40s} {b:7d} {len(ix):6d} {tot(ix, 'FETCH_SIZE') / len(ix) / 1e6:10.1f} "
+              f"{tot(ix, 'WRITE_SIZE') / len(ix) / 1e6:10.1f}")
+    print("\nper pass kind (bench.py's names), bytes per launch:")
+    for kind, ix in kind_launches(names, blocks).items():
+        fe = tot(ix, "FETCH_SIZE") / len(ix)
+        wr = tot(ix, "WRITE_SIZE") / len(ix)
+        print(f"launches[{kind}]: {len(ix)}")
+        print(f"fetch_bytes_per_launch[{kind}]: {fe:.0f}")
+        print(f"write_bytes_per_launch[{kind}]: {wr:.0f}")
+        print(f"traffic_bytes_per_launch[{kind}]: {fe + wr:.0f}")
     print(f"source_sha256: {source_hash()}")
 
 
