@@ -227,6 +227,31 @@ int csg_solve_step(csg_solve *sv);
 int csg_solve_poll(csg_solve *sv, int *done);
 int csg_solve_end(csg_solve *sv, csg_solve_info *info);
 
+/* Batches: several problems of one size class in one operator, so their
+ * solves advance in the same launches (section 5's FGMRES and section 3.1's
+ * V-cycle, right-hand sides of every problem on the grid's second dimension).
+ * Problems share the grid shape (dim, n, layers, levels), s, nu1, nu2,
+ * cycle_prec, max_rhs (per problem), restart and the tuning fields; h, beta,
+ * gamma and phi may differ.  Only the GMRES(s) smoother is batched
+ * (smoother = 0).  The batched operator has nprob * max_rhs right-hand sides:
+ * problem q owns RHS q*max_rhs .. (q+1)*max_rhs - 1 of every vector (give
+ * unused ones a zero source: they finish at once with u = 0).  Every other
+ * entry point (stencil, V-cycle, helm_solve, csg_solve_*) works on it as on a
+ * single operator; results of each problem equal its solve alone.
+ *   csg_batch_workspace_bytes: exact workspace of nprob problems of class p
+ *   (CSG_EINVAL if nprob * max_rhs > CSG_MAX_RHS or smoother != 0).
+ *   csg_batch_create: p[q], phi_host[q] for q < nprob; errors as
+ *   csg_operator_create, CSG_EINVAL when the classes differ.
+ *   helm_step_batch: one step of a (batched) solve begun by csg_solve_begin:
+ *   waits for the oldest report in flight, applies the stop and restart
+ *   decisions of every problem's RHS and enqueues the next iterations (one
+ *   launch sequence for all problems); *done = 1 when every RHS has stopped
+ *   (then call csg_solve_end). */
+int csg_batch_workspace_bytes(const csg_params *p, int nprob, size_t *bytes);
+int csg_batch_create(const csg_params *const *p, int nprob, const double *const *phi_host, void *ws_dev,
+                     size_t ws_bytes, void *stream, csg_operator **out);
+int helm_step_batch(csg_solve *sv, int *done);
+
 /* Benchmark instrumentation (not needed to solve).  csg_profile(op, kind, cap)
  * makes the library record a pair of HIP events around every launch of one
  * pass kind, on the stream that launch uses, for up to `cap` launches, and sum

@@ -12,7 +12,7 @@ import numpy as np
 
 from . import binding as B
 
-__all__ = ["Operator", "B"]
+__all__ = ["Operator", "BatchOperator", "B"]
 
 
 def _torch():
@@ -131,3 +131,29 @@ class Operator:
         rc, infos = B.helm_solve(self.op, chi.data_ptr(), u.data_ptr(), chi.shape[0], float(tol), int(restart),
                                  int(maxit), use, self._stream())
         return u, rc, infos
+
+
+class BatchOperator(Operator):
+    """Problems of one size class in one operator (csg_batch_create): problem q
+    owns right-hand sides q*max_rhs .. (q+1)*max_rhs - 1 of every vector, and
+    every operation runs all problems in the same launches."""
+
+    def __init__(self, params_list: list, phis: list, device: str = "cuda"):
+        torch = _torch()
+        self.nprob = len(params_list)
+        self.params = dict(params_list[0])
+        ps = [B.make_params(**dict(p)) for p in params_list]
+        self.p = ps[0]
+        self.rpp = self.p.max_rhs
+        self.nbytes = B.csg_batch_workspace_bytes(self.p, self.nprob)
+        self.device = torch.device(device)
+        self.ws = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        self.levels, self.dims = B.csg_plan_levels(self.p)
+        self._phis = [np.ascontiguousarray(f, dtype=np.float64) for f in phis]
+        for f in self._phis:
+            if f.size != int(np.prod(self.dims[0])):
+                raise ValueError("phi must have one value per finest-level unknown")
+        self._ps = ps
+        self.op = B.csg_batch_create(ps, [f.ctypes.data for f in self._phis], self.ws.data_ptr(), self.nbytes,
+                                     self._stream())
+        self.cdtype = torch.complex64 if self.p.cycle_prec else torch.complex128

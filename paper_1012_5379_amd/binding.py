@@ -70,6 +70,9 @@ _SIGS = {
     "csg_solve_step": (ip, [vp]),
     "csg_solve_poll": (ip, [vp, C.POINTER(C.c_int)]),
     "csg_solve_end": (ip, [vp, C.POINTER(csg_solve_info)]),
+    "csg_batch_workspace_bytes": (ip, [C.POINTER(csg_params), ip, C.POINTER(C.c_size_t)]),
+    "csg_batch_create": (ip, [vp, ip, vp, vp, C.c_size_t, vp, C.POINTER(vp)]),
+    "helm_step_batch": (ip, [vp, C.POINTER(C.c_int)]),
     "csg_profile": (ip, [vp, ip, ip]),
     "csg_profile_read": (ip, [vp, C.POINTER(C.c_double), C.POINTER(C.c_long), C.POINTER(C.c_double)]),
     "csg_graphs_active": (ip, [vp]),
@@ -229,6 +232,28 @@ def csg_solve_end(sv, nrhs):
     if rc < 0 and rc != CSG_ENOCONV:
         check(rc)
     return rc, [infos[r].as_dict() for r in range(nrhs)]
+
+
+def csg_batch_workspace_bytes(p: csg_params, nprob: int) -> int:
+    n = C.c_size_t(0)
+    check(lib().csg_batch_workspace_bytes(C.byref(p), int(nprob), C.byref(n)))
+    return n.value
+
+
+def csg_batch_create(params: list, phi_ptrs: list, ws_ptr: int, ws_bytes: int, stream: int) -> int:
+    """params: csg_params per problem; phi_ptrs: host addresses of their phi."""
+    k = len(params)
+    parr = (C.POINTER(csg_params) * k)(*[C.pointer(p) for p in params])
+    farr = (C.c_void_p * k)(*phi_ptrs)
+    op = vp()
+    check(lib().csg_batch_create(parr, k, farr, ws_ptr, ws_bytes, stream, C.byref(op)))
+    return op.value
+
+
+def helm_step_batch(sv) -> bool:
+    done = C.c_int(0)
+    check(lib().helm_step_batch(sv, C.byref(done)))
+    return bool(done.value)
 
 
 def csg_profile(op, kind: int, cap: int) -> None:

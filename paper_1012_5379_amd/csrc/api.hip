@@ -181,9 +181,9 @@ void carve(csg_operator &op, const int nint[CSG_MAX_LEVELS][3], Carver &cv)
         lv.tile = p.dim == 2 ? tiling(lv.nu[0], lv.nu[1], lv.nb) : TileGeo{0, 0, 0, 0};
         lv.dtile = p.dim == 2 ? down_tiling(lv.nu[0], lv.nu[1], lv.tile) : TileGeo{0, 0, 0, 0};
         lv.slab = p.dim == 3 ? slab_geo(lv.nu[0], lv.nu[1], lv.nu[2], R) : SlabGeo{0, 0, 0, 0};
-        for (int a = 0; a < p.dim; ++a) lv.tab[a] = cv.take(3 * (size_t)lv.nu[a] * cz);
+        for (int a = 0; a < p.dim; ++a) lv.tab[a] = cv.take((size_t)op.nprob * 3 * lv.nu[a] * cz);
         for (int a = p.dim; a < 3; ++a) lv.tab[a] = nullptr;
-        lv.phi = cv.take(lv.N * cr);
+        lv.phi = cv.take((size_t)op.nprob * lv.N * cr);
         const size_t vb = (size_t)R * lv.N * cz;
         lv.b = cv.take(vb);
         lv.xa = cv.take(vb);
@@ -197,12 +197,12 @@ void carve(csg_operator &op, const int nint[CSG_MAX_LEVELS][3], Carver &cv)
         lv.gs = (GState *)cv.take((size_t)R * sizeof(GState));
     }
     const DevLevel &f = op.lev[0];
-    for (int a = 0; a < p.dim; ++a) op.tabH[a] = cv.take(3 * (size_t)f.nu[a] * sizeof(zc));
+    for (int a = 0; a < p.dim; ++a) op.tabH[a] = cv.take((size_t)op.nprob * 3 * f.nu[a] * sizeof(zc));
     for (int a = p.dim; a < 3; ++a) op.tabH[a] = nullptr;
-    op.phiH = (const double *)cv.take(f.N * sizeof(double));
+    op.phiH = (const double *)cv.take((size_t)op.nprob * f.N * sizeof(double));
     const DevLevel &c = op.lev[op.L - 1];
     op.nc = (int)c.N;
-    op.minvT = cv.take((size_t)op.nc * op.nc * cz);
+    op.minvT = cv.take((size_t)op.nprob * op.nc * op.nc * cz);
     op.tlev = cv.take((size_t)op.L * sizeof(TLev<double>));
     const size_t n0 = (size_t)R * f.N;
     op.V = (zc *)cv.take((size_t)(p.restart + 1) * n0 * sizeof(zc));
@@ -218,6 +218,15 @@ void carve(csg_operator &op, const int nint[CSG_MAX_LEVELS][3], Carver &cv)
 
 int cyc_mask_offset(const csg_operator *op) { return op->p.max_rhs; }
 
+// problem strides of a level's tables and phi (batched operators)
+template <typename T>
+void batch_strides(const csg_operator *op, const DevLevel &d, LvlK<T> &L)
+{
+    L.rpp = op->nprob > 1 ? (unsigned)op->rpp : 0u;
+    for (int a = 0; a < 3; ++a) L.tstride[a] = 3 * d.nu[a];
+    L.pstride = d.N;
+}
+
 template <typename T>
 LvlK<T> lvl(const csg_operator *op, int l)
 {
@@ -229,6 +238,7 @@ LvlK<T> lvl(const csg_operator *op, int l)
     L.ny = d.nu[1];
     L.nz = d.nu[2];
     L.N = d.N;
+    batch_strides<T>(op, d, L);
     return L;
 }
 
@@ -242,8 +252,13 @@ LvlK<double> lvlH(const csg_operator *op)
     L.ny = d.nu[1];
     L.nz = d.nu[2];
     L.N = d.N;
+    batch_strides<double>(op, d, L);
     return L;
 }
+
+// elements between the coarsest inverses of consecutive problems, and RHS per problem
+size_t minv_stride(const csg_operator *op) { return (size_t)op->nc * op->nc; }
+unsigned batch_rpp(const csg_operator *op) { return op->nprob > 1 ? (unsigned)op->rpp : 0u; }
 
 Launch lch(const csg_operator *op, int l, int nrhs, hipStream_t st)
 {
@@ -614,7 +629,7 @@ void vcycle_impl(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, h
         const Cx<T> *bt = lt == 0 ? b0 : (const Cx<T> *)op->lev[lt].b;
         Cx<T> *xt = lt == 0 ? x0 : (Cx<T> *)op->lev[lt].xb;
         launch_tail<T, DIM>((const TLev<T> *)op->tlev, lt, L, bt, xt, (const Cx<T> *)op->minvT, op->nc, op->p.s, nu1,
-                            nu2, tiny_of<T>(), nrhs, op->tail_lds, st, active);
+                            nu2, tiny_of<T>(), nrhs, op->tail_lds, st, active, minv_stride(op));
     }
     // A level's post-sweep closing update is deferred to the next finer
     // level's up-path pass when that pass is tiled (fuse_up): x_c then exists
@@ -747,7 +762,8 @@ void vcycle_poly(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, h
     }
     const Cx<T> *bL = L == 1 ? b0 : (const Cx<T> *)op->lev[L - 1].b;
     Cx<T> *xL = L == 1 ? x0 : (Cx<T> *)op->lev[L - 1].xb;
-    launch_coarse<T>((const Cx<T> *)op->minvT, op->nc, bL, xL, op->lev[L - 1].ld, nrhs, st, active);
+    launch_coarse<T>((const Cx<T> *)op->minvT, op->nc, bL, xL, op->lev[L - 1].ld, nrhs, st, active, minv_stride(op),
+                     batch_rpp(op));
     for (int l = L - 2; l >= 0; --l) {
         const DevLevel &lv = op->lev[l];
         const DevLevel &cl = op->lev[l + 1];
@@ -1120,9 +1136,29 @@ int csg_plan_levels(const csg_params *p, int *levels, int dims[][3])
     return CSG_OK;
 }
 
-int csg_workspace_bytes(const csg_params *p, size_t *bytes)
+}  // extern "C"
+
+namespace {
+
+// Fields a batch's problems must share (one size class): the grid shape,
+// level count, cycle and solver sizes; h, beta, gamma and phi may differ.
+bool same_class(const csg_params &a, const csg_params &b)
+{
+    bool eq = a.dim == b.dim && a.levels == b.levels && a.s == b.s && a.nu1 == b.nu1 && a.nu2 == b.nu2 &&
+              a.cycle_prec == b.cycle_prec && a.max_rhs == b.max_rhs && a.restart == b.restart &&
+              a.tail_max == b.tail_max && a.fuse_max == b.fuse_max && a.graphs == b.graphs &&
+              a.smoother == b.smoother;
+    for (int d = 0; d < a.dim; ++d)
+        eq = eq && a.n[d] == b.n[d] && a.layer_lo[d] == b.layer_lo[d] && a.layer_hi[d] == b.layer_hi[d];
+    return eq;
+}
+
+int batch_bytes(const csg_params *p, int nprob, size_t *bytes)
 {
     if (!p || !bytes) return fail(CSG_EINVAL, "null argument");
+    if (nprob < 1 || (long)nprob * p->max_rhs > CSG_MAX_RHS)
+        return fail(CSG_EINVAL, "nprob * max_rhs must be in 1..CSG_MAX_RHS");
+    if (nprob > 1 && p->smoother != 0) return fail(CSG_EINVAL, "batched operators take the GMRES(s) smoother");
     int nint[CSG_MAX_LEVELS][3];
     int L = 0;
     std::string err;
@@ -1131,6 +1167,9 @@ int csg_workspace_bytes(const csg_params *p, size_t *bytes)
     csg_operator dry;
     memset(&dry, 0, sizeof(dry));
     dry.p = *p;
+    dry.p.max_rhs = nprob * p->max_rhs;
+    dry.nprob = nprob;
+    dry.rpp = p->max_rhs;
     dry.L = L;
     dry.csize = p->cycle_prec ? 8 : 16;
     Carver cv(nullptr);
@@ -1139,21 +1178,56 @@ int csg_workspace_bytes(const csg_params *p, size_t *bytes)
     return CSG_OK;
 }
 
+int create_impl(const csg_params *const *ps, const double *const *phis, int P, void *ws_dev, size_t ws_bytes,
+                void *stream, csg_operator **out);
+
+}  // namespace
+
+extern "C" {
+
+int csg_workspace_bytes(const csg_params *p, size_t *bytes) { return batch_bytes(p, 1, bytes); }
+
+int csg_batch_workspace_bytes(const csg_params *p, int nprob, size_t *bytes) { return batch_bytes(p, nprob, bytes); }
+
 int csg_operator_create(const csg_params *p, const double *phi_host, void *ws_dev, size_t ws_bytes, void *stream,
                         csg_operator **out)
 {
     if (!p || !phi_host || !out) return fail(CSG_EINVAL, "null argument");
+    return create_impl(&p, &phi_host, 1, ws_dev, ws_bytes, stream, out);
+}
+
+int csg_batch_create(const csg_params *const *p, int nprob, const double *const *phi_host, void *ws_dev,
+                     size_t ws_bytes, void *stream, csg_operator **out)
+{
+    if (!p || !phi_host || !out || nprob < 1) return fail(CSG_EINVAL, "null argument or nprob < 1");
+    for (int q = 0; q < nprob; ++q) {
+        if (!p[q] || !phi_host[q]) return fail(CSG_EINVAL, "null params or phi");
+        if (!same_class(*p[0], *p[q])) return fail(CSG_EINVAL, "batched problems must share one size class");
+    }
+    return create_impl(p, phi_host, nprob, ws_dev, ws_bytes, stream, out);
+}
+
+}  // extern "C"
+
+namespace {
+
+int create_impl(const csg_params *const *ps, const double *const *phis, int P, void *ws_dev, size_t ws_bytes,
+                void *stream, csg_operator **out)
+{
+    const csg_params *p = ps[0];
     *out = nullptr;
     if (((uintptr_t)ws_dev & 255) != 0) return fail(CSG_EINVAL, "workspace must be 256-byte aligned");
     size_t need = 0;
-    int st = csg_workspace_bytes(p, &need);
+    int st = batch_bytes(p, P, &need);
     if (st) return st;
-    if (p->max_rhs > CSG_MAX_RHS_HOST) return fail(CSG_EINVAL, "max_rhs too large");
     if (!ws_dev || ws_bytes < need) return fail(CSG_ENOMEM, "workspace too small");
-    HostHier hh;
+    std::vector<HostHier> hhs(P);
     std::string err;
-    st = build_hierarchy(*p, phi_host, hh, err);
-    if (st) return fail(st, err);
+    for (int q = 0; q < P; ++q) {
+        st = build_hierarchy(*ps[q], phis[q], hhs[q], err);
+        if (st) return fail(st, P > 1 ? "problem " + std::to_string(q) + ": " + err : err);
+    }
+    const HostHier &hh = hhs[0];
     // the static scratch's address on this device, once per device (a failure
     // only disables csg_smooth_static, which reports it)
     if (!scratch_dev()) g_err = "no error";
@@ -1161,6 +1235,9 @@ int csg_operator_create(const csg_params *p, const double *phi_host, void *ws_de
     csg_operator *op = new csg_operator;
     memset(op, 0, sizeof(*op));
     op->p = *p;
+    op->p.max_rhs = P * p->max_rhs;
+    op->nprob = P;
+    op->rpp = p->max_rhs;
     op->L = hh.L;
     op->csize = p->cycle_prec ? 8 : 16;
     int nint[CSG_MAX_LEVELS][3];
@@ -1194,29 +1271,38 @@ int csg_operator_create(const csg_params *p, const double *phi_host, void *ws_de
     };
     int rc = CSG_OK;
     std::vector<std::vector<char>> keep;   // host staging kept alive until the sync below
+    const int R = op->p.max_rhs;   // every problem's right-hand sides
+    const size_t cz = op->csize;
     for (int l = 0; l < hh.L && rc == CSG_OK; ++l) {
-        const HostLevel &hl = hh.lev[l];
-        for (int a = 0; a < p->dim; ++a) {
-            if (put_tab(hl.tab[a], hl.nu[a], op->lev[l].tab[a], !mixed) != hipSuccess) rc = CSG_EDEVICE;
-            hipStreamSynchronize(s);
+        for (int q = 0; q < P; ++q) {
+            // problem q's tables and phi follow problem q-1's (strides of the kernels' LvlK)
+            const HostLevel &hl = hhs[q].lev[l];
+            for (int a = 0; a < p->dim; ++a) {
+                const char *dst = (const char *)op->lev[l].tab[a] + (size_t)q * 3 * hl.nu[a] * cz;
+                if (put_tab(hl.tab[a], hl.nu[a], dst, !mixed) != hipSuccess) rc = CSG_EDEVICE;
+                hipStreamSynchronize(s);
+            }
+            std::vector<char> ph(hl.N * (mixed ? 4 : 8));
+            for (long k = 0; k < hl.N; ++k) {
+                if (mixed) ((float *)ph.data())[k] = (float)hl.phi[k];
+                else ((double *)ph.data())[k] = hl.phi[k];
+            }
+            if (hipMemcpyAsync((char *)op->lev[l].phi + (size_t)q * ph.size(), ph.data(), ph.size(),
+                               hipMemcpyHostToDevice, s) != hipSuccess)
+                rc = CSG_EDEVICE;
+            keep.push_back(std::move(ph));
         }
-        std::vector<char> ph(hl.N * (mixed ? 4 : 8));
-        for (long q = 0; q < hl.N; ++q) {
-            if (mixed) ((float *)ph.data())[q] = (float)hl.phi[q];
-            else ((double *)ph.data())[q] = hl.phi[q];
-        }
-        if (hipMemcpyAsync((void *)op->lev[l].phi, ph.data(), ph.size(), hipMemcpyHostToDevice, s) != hipSuccess)
-            rc = CSG_EDEVICE;
-        keep.push_back(std::move(ph));
-        if (hipMemsetAsync(op->lev[l].gs, 0, p->max_rhs * sizeof(GState), s) != hipSuccess) rc = CSG_EDEVICE;
+        if (hipMemsetAsync(op->lev[l].gs, 0, R * sizeof(GState), s) != hipSuccess) rc = CSG_EDEVICE;
         for (int k = 0; k < 2; ++k)
-            if (hipMemsetAsync(op->lev[l].part[k], 0, (size_t)p->max_rhs * NVAL * NBMAX * sizeof(zc), s) != hipSuccess)
+            if (hipMemsetAsync(op->lev[l].part[k], 0, (size_t)R * NVAL * NBMAX * sizeof(zc), s) != hipSuccess)
                 rc = CSG_EDEVICE;
     }
-    for (int a = 0; a < p->dim && rc == CSG_OK; ++a) {
-        if (put_tab(hh.tabH[a], hh.lev[0].nu[a], op->tabH[a], true) != hipSuccess) rc = CSG_EDEVICE;
-        hipStreamSynchronize(s);
-    }
+    for (int q = 0; q < P; ++q)
+        for (int a = 0; a < p->dim && rc == CSG_OK; ++a) {
+            const char *dst = (const char *)op->tabH[a] + (size_t)q * 3 * hh.lev[0].nu[a] * sizeof(zc);
+            if (put_tab(hhs[q].tabH[a], hh.lev[0].nu[a], dst, true) != hipSuccess) rc = CSG_EDEVICE;
+            hipStreamSynchronize(s);
+        }
     {
         // the coarse tail starts at the first level small enough for one workgroup
         // execution tuning: parameter, else environment (experiments), else default
@@ -1290,6 +1376,9 @@ int csg_operator_create(const csg_params *p, const double *phi_host, void *ws_de
             t.nz = d.nu[2];
             t.N = d.N;
             t.ld = d.ld;
+            t.rpp = op->nprob > 1 ? (unsigned)op->rpp : 0u;
+            for (int a = 0; a < 3; ++a) t.tstride[a] = 3 * d.nu[a];
+            t.pstride = d.N;
         }
         // the descriptor holds only pointers and sizes: identical layout for both precisions
         if (rc == CSG_OK && hipMemcpyAsync(op->tlev, tl.data(), tl.size() * sizeof(TLev<double>),
@@ -1297,32 +1386,36 @@ int csg_operator_create(const csg_params *p, const double *phi_host, void *ws_de
             rc = CSG_EDEVICE;
         hipStreamSynchronize(s);
     }
-    if (rc == CSG_OK) {
-        if (hipMemcpyAsync((void *)op->phiH, hh.lev[0].phi.data(), hh.lev[0].N * sizeof(double),
-                           hipMemcpyHostToDevice, s) != hipSuccess)
+    for (int q = 0; q < P && rc == CSG_OK; ++q) {
+        const HostHier &hq = hhs[q];
+        if (hipMemcpyAsync((double *)op->phiH + (size_t)q * hh.lev[0].N, hq.lev[0].phi.data(),
+                           hh.lev[0].N * sizeof(double), hipMemcpyHostToDevice, s) != hipSuccess)
             rc = CSG_EDEVICE;
         std::vector<char> mi((size_t)op->nc * op->nc * op->csize);
-        for (size_t q = 0; q < (size_t)op->nc * op->nc; ++q) {
+        for (size_t k = 0; k < (size_t)op->nc * op->nc; ++k) {
             if (mixed) {
-                ((float *)mi.data())[2 * q] = (float)hh.minvT[q].real();
-                ((float *)mi.data())[2 * q + 1] = (float)hh.minvT[q].imag();
+                ((float *)mi.data())[2 * k] = (float)hq.minvT[k].real();
+                ((float *)mi.data())[2 * k + 1] = (float)hq.minvT[k].imag();
             } else {
-                ((double *)mi.data())[2 * q] = hh.minvT[q].real();
-                ((double *)mi.data())[2 * q + 1] = hh.minvT[q].imag();
+                ((double *)mi.data())[2 * k] = hq.minvT[k].real();
+                ((double *)mi.data())[2 * k + 1] = hq.minvT[k].imag();
             }
         }
-        if (hipMemcpyAsync((void *)op->minvT, mi.data(), mi.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+        if (hipMemcpyAsync((char *)op->minvT + (size_t)q * mi.size(), mi.data(), mi.size(), hipMemcpyHostToDevice,
+                           s) != hipSuccess)
             rc = CSG_EDEVICE;
         keep.push_back(std::move(mi));
-        std::vector<int> ones(3 * (size_t)p->max_rhs, 1);
+    }
+    if (rc == CSG_OK) {
+        std::vector<int> ones(3 * (size_t)R, 1);
         if (hipMemcpyAsync(op->active, ones.data(), ones.size() * sizeof(int), hipMemcpyHostToDevice, s) !=
             hipSuccess)
             rc = CSG_EDEVICE;
-        if (hipMemsetAsync(op->fs, 0, p->max_rhs * sizeof(FState), s) != hipSuccess) rc = CSG_EDEVICE;
+        if (hipMemsetAsync(op->fs, 0, R * sizeof(FState), s) != hipSuccess) rc = CSG_EDEVICE;
         if (hipStreamSynchronize(s) != hipSuccess) rc = CSG_EDEVICE;
     }
     if (rc == CSG_OK) {
-        if (hipHostMalloc((void **)&op->rep_host, (LOOKAHEAD + 1) * (size_t)p->max_rhs * sizeof(Report),
+        if (hipHostMalloc((void **)&op->rep_host, (LOOKAHEAD + 1) * (size_t)R * sizeof(Report),
                           hipHostMallocDefault) != hipSuccess ||
             hipHostGetDevicePointer((void **)&op->rep_dev, op->rep_host, 0) != hipSuccess)
             rc = CSG_EDEVICE;
@@ -1348,6 +1441,10 @@ int csg_operator_create(const csg_params *p, const double *phi_host, void *ws_de
     *out = op;
     return CSG_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int csg_profile(csg_operator *op, int kind, int cap)
 {
@@ -1608,10 +1705,10 @@ int csg_coarse_solve(const csg_operator *op, const void *b, void *x, int nrhs, v
     const size_t ld = op->lev[op->L - 1].ld;
     if (op->p.cycle_prec)
         launch_coarse<float>((const cf *)op->minvT, op->nc, (const cf *)b, (cf *)x, ld, nrhs, (hipStream_t)stream,
-                             op->ones);
+                             op->ones, minv_stride(op), batch_rpp(op));
     else
         launch_coarse<double>((const zc *)op->minvT, op->nc, (const zc *)b, (zc *)x, ld, nrhs, (hipStream_t)stream,
-                              op->ones);
+                              op->ones, minv_stride(op), batch_rpp(op));
     return last_launch_error();
 }
 
@@ -1705,6 +1802,24 @@ int csg_solve_end(csg_solve *sv, csg_solve_info *info)
     hipHostFree(sv->mask_host);
     delete sv;
     return rc;
+}
+
+int helm_step_batch(csg_solve *sv, int *done)
+{
+    if (!sv) return fail(CSG_EINVAL, "null solve");
+    int d = sv->phase == csg_solve::FINISHED;
+    if (!d) {
+        hipEvent_t ev = pending_event(sv);
+        if (ev && hipEventSynchronize(ev) != hipSuccess) return fail(CSG_EDEVICE, "event wait failed");
+        const int pr = csg_solve_poll(sv, &d);
+        if (pr < 0) return pr;
+        if (!d) {
+            const int st = csg_solve_step(sv);
+            if (st) return st;
+        }
+    }
+    if (done) *done = d;
+    return CSG_OK;
 }
 
 int helm_solve(const csg_operator *op, const void *chi, void *u, int nrhs, double tol, int restart, int maxit,

@@ -202,7 +202,9 @@ struct Prof {
 }  // namespace csg
 
 struct csg_operator {
-    csg_params p;
+    csg_params p;                     // (a batch: max_rhs is the total over its problems)
+    int nprob;                        // problems side by side (csg_batch_create), 1 otherwise
+    int rpp;                          // right-hand sides per problem (rhs r belongs to problem r / rpp)
     int L;
     int csize;                        // bytes of one cycle complex (8 or 16)
     csg::DevLevel lev[CSG_MAX_LEVELS];

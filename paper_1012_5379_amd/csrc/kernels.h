@@ -11,6 +11,25 @@ struct LvlK {
     const Cx<T> *tab[3];   // per axis [west | centre | east], boundary weights zeroed
     const T *phi;
     unsigned nx, ny, nz, N;
+    // A batch of problems of one size class (same grid, levels and cycle)
+    // side by side: right-hand side r belongs to problem r / rpp, whose
+    // tables and phi sit tstride[a] and pstride elements after the previous
+    // problem's (rpp = 0: one problem).
+    unsigned rpp;
+    unsigned tstride[3];
+    size_t pstride;
+    // the geometry as right-hand side rhs sees it
+    __host__ __device__ __forceinline__ LvlK at(int rhs) const
+    {
+        LvlK r = *this;
+        if (rpp) {
+            const unsigned q = (unsigned)rhs / rpp;
+            for (int a = 0; a < 3; ++a)
+                if (r.tab[a]) r.tab[a] += (size_t)q * tstride[a];
+            r.phi += q * pstride;
+        }
+        return r;
+    }
 };
 
 // Up to CSG_MAX_S+1 basis vector pointers (u_0..u_s) of one level.
@@ -29,6 +48,10 @@ struct TLev {
     Cx<T> *w[2];
     unsigned nx, ny, nz, N;
     size_t ld;
+    // batches (see LvlK): problem stride of the tables and phi, RHS per problem
+    unsigned rpp;
+    unsigned tstride[3];
+    size_t pstride;
 };
 
 struct Launch {
@@ -154,15 +177,17 @@ template <typename T, int DIM>
 void launch_prc(const LvlK<T> &F, const LvlK<T> &C, const Cx<T> *ec, const Cx<T> *xin, Cx<T> *xout,
                 const Cx<T> *b, Cx<T> *r, size_t ldf, size_t ldc, const Launch &g, const int *active);
 
+// mstride, rpp: batches (see LvlK): elements between the problems' inverses
 template <typename T>
 void launch_coarse(const Cx<T> *minvT, int n, const Cx<T> *b, Cx<T> *x, size_t ld, int nrhs, hipStream_t st,
-                   const int *active);
+                   const int *active, size_t mstride = 0, unsigned rpp = 0);
 
 // One workgroup per RHS runs levels lt..L-1 of the V-cycle (input b at level lt,
 // output x at level lt).
 template <typename T, int DIM>
 void launch_tail(const TLev<T> *lev, int lt, int L, const Cx<T> *b_in, Cx<T> *x_out, const Cx<T> *minvT, int nc,
-                 int s, int nu1, int nu2, double tiny, int nrhs, size_t lds, hipStream_t st, const int *active);
+                 int s, int nu1, int nu2, double tiny, int nrhs, size_t lds, hipStream_t st, const int *active,
+                 size_t mstride = 0);
 
 // Shared-memory bytes of the tail's vectors from level lt down (N[l] unknowns
 // per level), and the one-time launch attribute that allows them (false: the

@@ -1032,6 +1032,7 @@ __global__ __launch_bounds__(BLK) void k_apply(LvlK<T> L, const Cx<T> *__restric
                                                size_t ld, unsigned chunk, int nb, const int *active)
 {
     const int rhs = blockIdx.y;
+    L = L.at(rhs);
     if (!active[rhs]) return;
     const unsigned c = chunk_id(nb);
     const unsigned p0 = c * chunk, p1 = min(L.N, p0 + chunk);
@@ -1047,6 +1048,7 @@ __global__ __launch_bounds__(BLK) void k_st0(LvlK<T> L, const Cx<T> *u0, Cx<T> *
     __shared__ zc sh[(BLK / 64) * NA];
     __shared__ zc res[NA];
     const int rhs = blockIdx.y;
+    L = L.at(rhs);
     if (!active[rhs]) return;
     zc acc[NA];
 #pragma unroll
@@ -1066,6 +1068,7 @@ __global__ __launch_bounds__(BLK) void k_stj(LvlK<T> L, Basis<T> B, Cx<T> *w, in
     __shared__ zc sh[(BLK / 64) * (SB + 1)];
     __shared__ zc res[SB + 1];
     const int rhs = blockIdx.y;
+    L = L.at(rhs);
     if (!active[rhs]) return;
     zc acc[SB + 1];
 #pragma unroll
@@ -1087,6 +1090,7 @@ __global__ __launch_bounds__(BLK) void k_os(LvlK<T> L, Basis<T> B, const Cx<T> *
     __shared__ zc sh[(BLK / 64) * (SB + 1)];
     __shared__ zc res[SB + 1];
     const int rhs = blockIdx.y;
+    L = L.at(rhs);
     if (!active[rhs]) return;
     GState *gs = gsb + rhs;
     const GPrev<SB> pv = load_prev<SB>(gs, j);
@@ -1130,6 +1134,7 @@ __global__ __launch_bounds__(BLK) void k_os_tile(LvlK<T> L, Basis<T> B, const Cx
     __shared__ Cx<T> lu[TILE_MAXN];
     __shared__ Cx<T> ltab[6 * TAB_MAXD];   // x lower, diag, upper; y lower, diag, upper
     const int rhs = blockIdx.y;
+    L = L.at(rhs);
     // the mask is tested after the prologue's loads are issued (every read
     // below is harmless for a RHS that no longer iterates)
     const int act = active[rhs];
@@ -1305,6 +1310,7 @@ __global__ __launch_bounds__(BLK) void k_slab(LvlK<T> L, Basis<T> B, const Cx<T>
     __shared__ Cx<T> ring[3][SHX * SHY];
     __shared__ Cx<T> ltab[3 * SX + 3 * SY];
     const int rhs = blockIdx.y;
+    L = L.at(rhs);
     if (!active[rhs]) return;
     const size_t off = rhs * ld;
     // GMRES coefficients of this step from the previous pass's partials
@@ -1465,6 +1471,7 @@ __global__ __launch_bounds__(BLK) void k_st0_tile(LvlK<T> L, const Cx<T> *__rest
     __shared__ Cx<T> lu[TILE_MAXN];
     __shared__ Cx<T> ltab[6 * TAB_MAXD];
     const int rhs = blockIdx.y;
+    L = L.at(rhs);
     const int act = active[rhs];   // tested before the first store (reads below are harmless)
     const unsigned t = chunk_id(ntile);
     const unsigned tyi = t / tg.ntx, txi = t - tyi * tg.ntx;
@@ -2010,6 +2017,8 @@ __global__ __launch_bounds__(BLK) void k_upd_res(Cx<T> *x, int accumulate, Basis
     __shared__ zc res[SB + 1];
     __shared__ zc ax[CSG_MAX_S], ar[CSG_MAX_S + 1];
     const int rhs = blockIdx.y;
+    F = F.at(rhs);
+    C = C.at(rhs);
     if (!active[rhs]) return;
     const int k = close_sweep<T, SB>(pin + (size_t)rhs * NVAL * NBMAX, nbin, gsb + rhs, s, tiny, sh, res, ax, ar);
     Cx<T> cx[SB], cr[SB];
@@ -2047,6 +2056,8 @@ __global__ __launch_bounds__(BLK) void k_up_tile(LvlK<T> F, LvlK<T> C, const Cx<
     __shared__ Cx<T> lc[FU ? UPC_MAXN : 1];   // the coarse correction on the tile's coarse window
     __shared__ zc axc[CSG_MAX_S], arc[CSG_MAX_S + 1];
     const int rhs = blockIdx.y;
+    F = F.at(rhs);
+    C = C.at(rhs);
     const int act = active[rhs];   // tested before the first store (reads below are harmless)
     const unsigned t = chunk_id(ntile);
     const unsigned tyi = t / tg.ntx, txi = t - tyi * tg.ntx;
@@ -2294,6 +2305,8 @@ __global__ __launch_bounds__(BLK) void k_down_tile(Cx<T> *__restrict__ x, int ac
     __shared__ Cx<T> lb[DN_MAXB];
     __shared__ Cx<T> ltab[6 * TAB_MAXD];   // coarse tables: x lower, diag, upper; y lower, diag, upper
     const int rhs = blockIdx.y;
+    F = F.at(rhs);
+    C = C.at(rhs);
     const int act = active[rhs];   // tested before the closing writes (reads below are harmless)
     const unsigned t = chunk_id(ntile);
     const unsigned tyi = t / tg.ntx, txi = t - tyi * tg.ntx;
@@ -2472,6 +2485,7 @@ __global__ __launch_bounds__(BLK) void k_resid(LvlK<T> L, const Cx<T> *__restric
                                                const int *active)
 {
     const int rhs = blockIdx.y;
+    L = L.at(rhs);
     if (!active[rhs]) return;
     const size_t off = rhs * ld;
     const unsigned c = chunk_id(nb);
@@ -2485,6 +2499,8 @@ __global__ __launch_bounds__(BLK) void k_restrict(LvlK<T> F, LvlK<T> C, const Cx
                                                   size_t ldc, unsigned chunk, int nb, const int *active)
 {
     const int rhs = blockIdx.y;
+    F = F.at(rhs);
+    C = C.at(rhs);
     if (!active[rhs]) return;
     const size_t offf = rhs * ldf;
     const unsigned c = chunk_id(nb);
@@ -2498,6 +2514,8 @@ __global__ __launch_bounds__(BLK) void k_prolong(LvlK<T> F, LvlK<T> C, const Cx<
                                                  const int *active)
 {
     const int rhs = blockIdx.y;
+    F = F.at(rhs);
+    C = C.at(rhs);
     if (!active[rhs]) return;
     const size_t off = rhs * ldf;
     const unsigned c = chunk_id(nb);
@@ -2511,6 +2529,8 @@ __global__ __launch_bounds__(BLK) void k_prc(LvlK<T> F, LvlK<T> C, const Cx<T> *
                                              size_t ldc, unsigned chunk, int nb, const int *active)
 {
     const int rhs = blockIdx.y;
+    F = F.at(rhs);
+    C = C.at(rhs);
     if (!active[rhs]) return;
     const size_t off = rhs * ldf;
     const unsigned c = chunk_id(nb);
@@ -2521,11 +2541,13 @@ __global__ __launch_bounds__(BLK) void k_prc(LvlK<T> F, LvlK<T> C, const Cx<T> *
 
 template <typename T>
 __global__ __launch_bounds__(BLK) void k_coarse(const Cx<T> *__restrict__ minvT, int n, const Cx<T> *__restrict__ b,
-                                                Cx<T> *__restrict__ x, size_t ld, const int *active)
+                                                Cx<T> *__restrict__ x, size_t ld, size_t mstride, unsigned rpp,
+                                                const int *active)
 {
     __shared__ Cx<T> part[BLK];
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
+    if (rpp) minvT += (size_t)((unsigned)rhs / rpp) * mstride;
     body_coarse<T, BLK>(minvT, n, b + rhs * ld, x + rhs * ld, part);
 }
 
@@ -2555,16 +2577,21 @@ __device__ __forceinline__ void tail_sum(zc (&v)[NV], int nv, zc *sh, zc *res)
 }
 
 template <typename T>
-__device__ __forceinline__ LvlK<T> tlvl(const TLev<T> &d)
+__device__ __forceinline__ LvlK<T> tlvl(const TLev<T> &d, int rhs)
 {
     LvlK<T> L;
-    for (int a = 0; a < 3; ++a) L.tab[a] = d.tab[a];
+    for (int a = 0; a < 3; ++a) {
+        L.tab[a] = d.tab[a];
+        L.tstride[a] = d.tstride[a];
+    }
     L.phi = d.phi;
     L.nx = d.nx;
     L.ny = d.ny;
     L.nz = d.nz;
     L.N = d.N;
-    return L;
+    L.rpp = d.rpp;
+    L.pstride = d.pstride;
+    return L.at(rhs);
 }
 
 // Arnoldi passes of one sweep on the raw basis B (u_0 given), whole level;
@@ -2966,7 +2993,7 @@ __host__ __device__ __forceinline__ int tail_vectors(int s)
 template <typename T, int DIM, int SB>
 __global__ __launch_bounds__(TB) void k_tail_lds(const TLev<T> *__restrict__ lev, int lt, int L, const Cx<T> *b_in,
                                                  Cx<T> *x_out, const Cx<T> *__restrict__ minvT, int nc, int s,
-                                                 int nu1, int nu2, double tiny, const int *active)
+                                                 int nu1, int nu2, double tiny, size_t mstride, const int *active)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ GState gs;
@@ -2977,6 +3004,7 @@ __global__ __launch_bounds__(TB) void k_tail_lds(const TLev<T> *__restrict__ lev
     __shared__ int ks;
     __shared__ zc fold[CSG_MAX_S + 1];
     const int rhs = blockIdx.x;
+    if (lev[0].rpp) minvT += (size_t)((unsigned)rhs / lev[0].rpp) * mstride;
     if (!active[rhs]) return;
     const int t = threadIdx.x;
     const int nv = tail_vectors<T>(s);
@@ -3004,7 +3032,7 @@ __global__ __launch_bounds__(TB) void k_tail_lds(const TLev<T> *__restrict__ lev
     TSten<T, DIM, MP> S;
     // down: pre-smoothing and restriction
     for (int l = lt; l < L - 1; ++l) {
-        const LvlK<T> F = tlvl(lev[l]), C = tlvl(lev[l + 1]);
+        const LvlK<T> F = tlvl(lev[l], rhs), C = tlvl(lev[l + 1], rhs);
         const LdsLev<T> f = level(l), c = level(l + 1);
         if (nu1 > 0) tsten_load<T, DIM, MP>(F, S);
         if (nu1 == 0) {
@@ -3044,7 +3072,7 @@ __global__ __launch_bounds__(TB) void k_tail_lds(const TLev<T> *__restrict__ lev
     }
     // up: interpolated correction (in place) and post-smoothing
     for (int l = L - 2; l >= lt; --l) {
-        const LvlK<T> F = tlvl(lev[l]), C = tlvl(lev[l + 1]);
+        const LvlK<T> F = tlvl(lev[l], rhs), C = tlvl(lev[l + 1], rhs);
         const LdsLev<T> f = level(l), c = level(l + 1);
         // the last pre-smoothed level's stencils are still in S
         if (nu2 > 0 && !(l == L - 2 && nu1 > 0)) tsten_load<T, DIM, MP>(F, S);
@@ -3074,7 +3102,7 @@ __global__ __launch_bounds__(TB) void k_tail_lds(const TLev<T> *__restrict__ lev
 template <typename T, int DIM, int SB>
 __global__ __launch_bounds__(TB) void k_tail(const TLev<T> *__restrict__ lev, int lt, int L, const Cx<T> *b_in,
                                              Cx<T> *x_out, const Cx<T> *__restrict__ minvT, int nc, int s, int nu1,
-                                             int nu2, double tiny, const int *active)
+                                             int nu2, double tiny, size_t mstride, const int *active)
 {
     __shared__ GState gs;
     __shared__ zc sh[TW * NVAL];
@@ -3085,6 +3113,7 @@ __global__ __launch_bounds__(TB) void k_tail(const TLev<T> *__restrict__ lev, in
     __shared__ zc fold[CSG_MAX_S + 1];
     __shared__ Cx<T> cpart[TB];
     const int rhs = blockIdx.x;
+    if (lev[0].rpp) minvT += (size_t)((unsigned)rhs / lev[0].rpp) * mstride;
     if (!active[rhs]) return;
     const int t = threadIdx.x;
 
@@ -3092,7 +3121,7 @@ __global__ __launch_bounds__(TB) void k_tail(const TLev<T> *__restrict__ lev, in
     for (int l = lt; l < L - 1; ++l) {
         const TLev<T> &Fd = lev[l];
         const TLev<T> &Cd = lev[l + 1];
-        const LvlK<T> F = tlvl(Fd), C = tlvl(Cd);
+        const LvlK<T> F = tlvl(Fd, rhs), C = tlvl(Cd, rhs);
         const size_t offf = rhs * Fd.ld, offc = rhs * Cd.ld;
         const Cx<T> *b = (l == lt ? b_in : Fd.b) + offf;
         if (nu1 == 0) {
@@ -3134,7 +3163,7 @@ __global__ __launch_bounds__(TB) void k_tail(const TLev<T> *__restrict__ lev, in
     for (int l = L - 2; l >= lt; --l) {
         const TLev<T> &Fd = lev[l];
         const TLev<T> &Cd = lev[l + 1];
-        const LvlK<T> F = tlvl(Fd), C = tlvl(Cd);
+        const LvlK<T> F = tlvl(Fd, rhs), C = tlvl(Cd, rhs);
         const size_t offf = rhs * Fd.ld, offc = rhs * Cd.ld;
         const Cx<T> *b = (l == lt ? b_in : Fd.b) + offf;
         Cx<T> *x = (l == lt ? x_out : Fd.xb) + offf;
@@ -3224,6 +3253,7 @@ __global__ __launch_bounds__(BLK) void k_hdot(LvlK<double> H, const Cx<TZ> *__re
     __shared__ zc sh[(BLK / 64) * 8];
     __shared__ zc res[8];
     const int rhs = blockIdx.y;
+    H = H.at(rhs);
     if (!active[rhs]) return;
     const size_t off = rhs * ld;
     zc *po = pout + (size_t)rhs * OVAL * NBMAX;
@@ -3322,6 +3352,7 @@ __global__ __launch_bounds__(BLK) void k_hdot_tile(LvlK<double> H, const Cx<TZ> 
     __shared__ zc lz[TILE_MAXN];
     __shared__ zc ltab[6 * TAB_MAXD];   // x lower, diag, upper; y lower, diag, upper
     const int rhs = blockIdx.y;
+    H = H.at(rhs);
     if (!active[rhs]) return;
     const unsigned t = chunk_id(ntile);
     const unsigned tyi = t / tg.ntx, txi = t - tyi * tg.ntx;
@@ -3462,6 +3493,7 @@ __global__ __launch_bounds__(BLK) void k_tres(LvlK<double> H, const zc *__restri
     __shared__ zc sh[(BLK / 64) * 2];
     __shared__ zc res[2];
     const int rhs = blockIdx.y;
+    H = H.at(rhs);
     if (!active[rhs]) return;
     const size_t off = rhs * ld;
     zc acc[2] = {mkc(0.0, 0.0), mkc(0.0, 0.0)};
@@ -3667,6 +3699,7 @@ __global__ __launch_bounds__(BLK) void k_rich(LvlK<T> L, const Cx<T> *__restrict
 {
     constexpr int U = Ubatch<T>::U;
     const int rhs = blockIdx.y;
+    L = L.at(rhs);
     if (!active[rhs]) return;
     const size_t off = rhs * ld;
     const unsigned c = chunk_id(nb);
@@ -3716,6 +3749,8 @@ __global__ __launch_bounds__(BLK) void k_poly_tile(LvlK<T> L, LvlK<T> C, const C
 {
     __shared__ Cx<T> X[2][PR * PR];
     const int rhs = blockIdx.y;
+    L = L.at(rhs);
+    C = C.at(rhs);
     if (!active[rhs]) return;
     const size_t off = rhs * ld;
     const int nx = (int)L.nx, ny = (int)L.ny;
@@ -4045,9 +4080,9 @@ void launch_prc(const LvlK<T> &F, const LvlK<T> &C, const Cx<T> *ec, const Cx<T>
 
 template <typename T>
 void launch_coarse(const Cx<T> *minvT, int n, const Cx<T> *b, Cx<T> *x, size_t ld, int nrhs, hipStream_t st,
-                   const int *active)
+                   const int *active, size_t mstride, unsigned rpp)
 {
-    hipLaunchKernelGGL((k_coarse<T>), dim3(1, nrhs), dim3(BLK), 0, st, minvT, n, b, x, ld, active);
+    hipLaunchKernelGGL((k_coarse<T>), dim3(1, nrhs), dim3(BLK), 0, st, minvT, n, b, x, ld, mstride, rpp, active);
 }
 
 // First round of column j, finished and applied in one launch.  Every block
@@ -4403,23 +4438,24 @@ bool tail_lds_prepare(size_t bytes, int s)
 
 template <typename T, int DIM>
 void launch_tail(const TLev<T> *lev, int lt, int L, const Cx<T> *b_in, Cx<T> *x_out, const Cx<T> *minvT, int nc,
-                 int s, int nu1, int nu2, double tiny, int nrhs, size_t lds, hipStream_t st, const int *active)
+                 int s, int nu1, int nu2, double tiny, int nrhs, size_t lds, hipStream_t st, const int *active,
+                 size_t mstride)
 {
     if (lds) {
         if (s <= 3)
             hipLaunchKernelGGL((k_tail_lds<T, DIM, 4>), dim3(nrhs), dim3(TB), lds, st, lev, lt, L, b_in, x_out, minvT,
-                               nc, s, nu1, nu2, tiny, active);
+                               nc, s, nu1, nu2, tiny, mstride, active);
         else
             hipLaunchKernelGGL((k_tail_lds<T, DIM, NVAL - 1>), dim3(nrhs), dim3(TB), lds, st, lev, lt, L, b_in, x_out,
-                               minvT, nc, s, nu1, nu2, tiny, active);
+                               minvT, nc, s, nu1, nu2, tiny, mstride, active);
         return;
     }
     if (s <= 3)
         hipLaunchKernelGGL((k_tail<T, DIM, 4>), dim3(nrhs), dim3(TB), 0, st, lev, lt, L, b_in, x_out, minvT, nc, s, nu1,
-                           nu2, tiny, active);
+                           nu2, tiny, mstride, active);
     else
         hipLaunchKernelGGL((k_tail<T, DIM, NVAL - 1>), dim3(nrhs), dim3(TB), 0, st, lev, lt, L, b_in, x_out, minvT, nc,
-                           s, nu1, nu2, tiny, active);
+                           s, nu1, nu2, tiny, mstride, active);
 }
 
 template <typename T, int DIM>
@@ -4498,7 +4534,7 @@ void launch_zero16(void *p, size_t bytes, hipStream_t st)
     template void launch_hdot<T, D>(const LvlK<double> &, const Cx<T> *, zc *, const zc *, size_t, int, size_t,    \
                                     zc *, const Launch &, const int *);                                            \
     template void launch_tail<T, D>(const TLev<T> *, int, int, const Cx<T> *, Cx<T> *, const Cx<T> *, int, int,     \
-                                    int, int, double, int, size_t, hipStream_t, const int *);                      \
+                                    int, int, double, int, size_t, hipStream_t, const int *, size_t);              \
     template size_t tail_lds_bytes<T, D>(const unsigned *, int, int, int);                                         \
     template bool tail_lds_prepare<T, D>(size_t, int);
 
@@ -4531,7 +4567,7 @@ template void launch_hdot_tile<float>(const LvlK<double> &, const Cx<float> *, z
                                     const zc *, int, zc *, GState *, double, const TileGeo &, int, hipStream_t,    \
                                     const int *);                                                                  \
     template void launch_coarse<T>(const Cx<T> *, int, const Cx<T> *, Cx<T> *, size_t, int, hipStream_t,          \
-                                   const int *);                                                                   \
+                                   const int *, size_t, unsigned);                                                 \
     template void launch_vnorm<T>(const zc *, zc *, Cx<T> *, unsigned, size_t, const FState *, const Launch &,     \
                                   const int *);                                                                    \
     template void launch_proj1<T>(const zc *, const zc *, size_t, int, unsigned, size_t, FState *, Report *,       \
