@@ -144,18 +144,19 @@ TileGeo down_tiling(unsigned nx, unsigned ny, const TileGeo &dflt)
 }
 
 // z-marching slabs of a 3-D level: columns of 32 x 16 points; enough runs of
-// planes that the launch has about 2048 blocks over max_rhs right-hand sides
-// (runs of at least 4 planes, at most NBMAX partials).
-SlabGeo slab_geo(unsigned nx, unsigned ny, unsigned nz, int max_rhs)
+// planes for about 128 blocks per right-hand side (runs of at least 4 planes,
+// at most NBMAX partials).  The geometry depends on the level alone, so a
+// right-hand side's result is the same whatever else shares its launches.
+SlabGeo slab_geo(unsigned nx, unsigned ny, unsigned nz)
 {
     SlabGeo g{0, 0, 0, 0, 0};
     g.ntx = (nx + 31) / 32;
     g.nty = (ny + 15) / 16;
     const unsigned cols = g.ntx * g.nty;
     if (cols == 0 || cols + 8 > (unsigned)NBMAX) return SlabGeo{0, 0, 0, 0, 0};
-    unsigned target = 2048u;
+    unsigned target = 128u;
     if (const char *e = getenv("CSG_SLAB_BLOCKS")) target = (unsigned)std::max(1, atoi(e));
-    unsigned want = (target + cols * max_rhs - 1) / (cols * max_rhs);
+    unsigned want = (target + cols - 1) / cols;
     want = std::max(1u, std::min({want, (unsigned)(NBMAX - 8) / cols, std::max(1u, nz / 4)}));
     g.zrun = (nz + want - 1) / want;
     g.nzc = (nz + g.zrun - 1) / g.zrun;
@@ -180,7 +181,7 @@ void carve(csg_operator &op, const int nint[CSG_MAX_LEVELS][3], Carver &cv)
         geometry(lv.N, lv.nb, lv.chunk);
         lv.tile = p.dim == 2 ? tiling(lv.nu[0], lv.nu[1], lv.nb) : TileGeo{0, 0, 0, 0};
         lv.dtile = p.dim == 2 ? down_tiling(lv.nu[0], lv.nu[1], lv.tile) : TileGeo{0, 0, 0, 0};
-        lv.slab = p.dim == 3 ? slab_geo(lv.nu[0], lv.nu[1], lv.nu[2], R) : SlabGeo{0, 0, 0, 0};
+        lv.slab = p.dim == 3 ? slab_geo(lv.nu[0], lv.nu[1], lv.nu[2]) : SlabGeo{0, 0, 0, 0, 0};
         for (int a = 0; a < p.dim; ++a) lv.tab[a] = cv.take((size_t)op.nprob * 3 * lv.nu[a] * cz);
         for (int a = p.dim; a < 3; ++a) lv.tab[a] = nullptr;
         lv.phi = cv.take((size_t)op.nprob * lv.N * cr);

@@ -13,6 +13,12 @@ A retired request's hierarchy is kept in an LRU cache keyed by a hash of its
 parameters and phi, so a repeated problem skips setup; cached hierarchies are
 evicted, oldest first, when an admission needs their memory.
 
+Requests of one size class (same grid shape, levels, cycle, tolerance) that
+are queued together are batched into one operator (csg_batch_create): their
+hierarchies sit side by side in one workspace and every V-cycle and FGMRES
+iteration of all of them runs in the same launches; each request's answer is
+bit-identical to its solve alone.
+
 Every arithmetic step runs in libcsg's kernels; this module only schedules.
 """
 from __future__ import annotations
@@ -59,6 +65,13 @@ class Request:
         workspace plus the complex128 chi and u vectors of every RHS."""
         return B.csg_workspace_bytes(self.csg_params()) + 2 * self.chi.nbytes
 
+    def class_key(self) -> tuple:
+        """Requests with equal keys can share a batched operator."""
+        p = self.params
+        keep = ("dim", "n", "layer_lo", "layer_hi", "levels", "s", "nu1", "nu2", "cycle_prec")
+        return tuple((k, tuple(p[k]) if isinstance(p[k], (list, tuple)) else p[k]) for k in keep) + \
+            (("restart", self.restart), ("tol", self.tol), ("maxit", self.maxit))
+
     def key(self) -> str:
         h = hashlib.sha1(repr(sorted(self.params.items())).encode())
         h.update(repr((self.nrhs, self.restart)).encode())
@@ -67,18 +80,27 @@ class Request:
 
 
 class _Active:
-    def __init__(self, req, slot, ws, op, chi, u, stream):
-        self.req, self.slot, self.ws, self.op, self.chi, self.u, self.stream = req, slot, ws, op, chi, u, stream
+    """One operator on the device: a single request, or a batch of requests of
+    one size class (members[q] owns RHS q*R .. q*R + nrhs - 1)."""
+
+    def __init__(self, members, R, slot, ws, op, chi, u, stream):
+        self.members, self.R = members, R
+        self.req = members[0]
+        self.slot, self.ws, self.op, self.chi, self.u, self.stream = slot, ws, op, chi, u, stream
         self.sv = None
         self.nbytes = 0
         self.key = None
+
+    @property
+    def nrhs(self) -> int:
+        return self.R * len(self.members)
 
 
 class Engine:
     """Admit by HBM budget, overlap solves on `streams` HIP streams."""
 
     def __init__(self, hbm_budget: Optional[int] = None, streams: int = 4, device: str = "cuda",
-                 keep_solutions: bool = True, cache: bool = True):
+                 keep_solutions: bool = True, cache: bool = True, batch: int = 4):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -99,6 +121,8 @@ class Engine:
         self.use_cache = cache
         self.cache: "OrderedDict[str, tuple]" = OrderedDict()   # key -> (ws tensor, op, bytes)
         self.cache_hits = 0
+        self.max_batch = max(1, int(batch))
+        self.batches = 0          # batched operators built
         self.t0 = time.perf_counter()
 
     def now(self) -> float:
@@ -111,6 +135,16 @@ class Engine:
         self.queue.append(req)
 
     # -- admission -------------------------------------------------------------
+    @staticmethod
+    def _batch_params(members, R):
+        return [B.make_params(**dict(m.params, max_rhs=R, restart=m.restart, graphs=-1)) for m in members]
+
+    def _batch_bytes(self, members) -> int:
+        R = max(m.nrhs for m in members)
+        ps = self._batch_params(members, R)
+        grid = int(np.prod(members[0].chi.shape[1:]))
+        return B.csg_batch_workspace_bytes(ps[0], len(members)) + 2 * len(members) * R * grid * 16
+
     def _setup(self, req: Request, slot: int, cached=None):
         torch = self.torch
         stream = self.streams[slot]
@@ -119,14 +153,52 @@ class Engine:
             u = torch.empty_like(chi)
         if cached is not None:
             ws, op, _ = cached
-            return _Active(req, slot, ws, op, chi, u, stream)
+            return _Active([req], req.nrhs, slot, ws, op, chi, u, stream)
         p = req.csg_params()
         nb = B.csg_workspace_bytes(p)   # the library's share of req.workspace_bytes()
         with torch.cuda.stream(stream):
             ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
         phi = np.ascontiguousarray(req.phi, dtype=np.float64)
         op = B.csg_operator_create(p, phi.ctypes.data, ws.data_ptr(), nb, stream.cuda_stream)
-        return _Active(req, slot, ws, op, chi, u, stream)
+        return _Active([req], req.nrhs, slot, ws, op, chi, u, stream)
+
+    def _setup_batch(self, members, slot: int):
+        """One operator for several same-class requests: RHS of member q at
+        q*R .. q*R + nrhs - 1, the rest zero sources (they stop at once)."""
+        torch = self.torch
+        stream = self.streams[slot]
+        R = max(m.nrhs for m in members)
+        shape = members[0].chi.shape[1:]
+        host = np.zeros((len(members) * R,) + tuple(shape), dtype=np.complex128)
+        for q, m in enumerate(members):
+            host[q * R:q * R + m.nrhs] = m.chi
+        ps = self._batch_params(members, R)
+        nb = B.csg_batch_workspace_bytes(ps[0], len(members))
+        phis = [np.ascontiguousarray(m.phi, dtype=np.float64) for m in members]
+        with torch.cuda.stream(stream):
+            chi = torch.from_numpy(host).to(self.device, non_blocking=False)
+            u = torch.empty_like(chi)
+            ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        op = B.csg_batch_create(ps, [f.ctypes.data for f in phis], ws.data_ptr(), nb, stream.cuda_stream)
+        return _Active(list(members), R, slot, ws, op, chi, u, stream)
+
+    def _take_batch(self):
+        """The head of the queue and the queued requests of its size class
+        (at most max_batch problems and CSG_MAX_RHS right-hand sides), shrunk
+        until its bytes fit the budget; None if not even the head fits."""
+        head = self.queue[0]
+        members = [head]
+        if self.max_batch > 1:
+            cls = head.class_key()
+            for r in self.queue[1:]:
+                if len(members) >= self.max_batch:
+                    break
+                if r.class_key() == cls and (len(members) + 1) * max(r.nrhs, max(m.nrhs for m in members)) \
+                        <= B.CSG_MAX_RHS:
+                    members.append(r)
+        while len(members) > 1 and self.used + self._batch_bytes(members) > self.budget:
+            members.pop()
+        return members
 
     def _evict_one(self) -> bool:
         if not self.cache:
@@ -138,6 +210,20 @@ class Engine:
 
     def _admit(self) -> None:
         while self.queue and self.free_slots:
+            members = self._take_batch()
+            if len(members) > 1:
+                nb = self._batch_bytes(members)
+                self.used += nb
+                self.high_water = max(self.high_water, self.used)
+                for m in members:
+                    self.queue.remove(m)
+                slot = self.free_slots.pop(0)
+                now = self.now()
+                for m in members:
+                    m.t_admit = now
+                self.batches += 1
+                self.pending.append((self.pool.submit(self._setup_batch, members, slot), members[0], slot, nb, None))
+                continue
             req = self.queue[0]
             key = req.key() if self.use_cache else None
             cached = self.cache.pop(key, None) if key is not None else None
@@ -165,19 +251,31 @@ class Engine:
                 continue
             a = fut.result()
             a.nbytes, a.key = nb, key
-            req.t_ready = self.now()
-            a.sv = B.csg_solve_begin(a.op, a.chi.data_ptr(), a.u.data_ptr(), req.nrhs, req.tol, req.restart,
+            now = self.now()
+            for m in a.members:
+                m.t_ready = now
+            a.sv = B.csg_solve_begin(a.op, a.chi.data_ptr(), a.u.data_ptr(), a.nrhs, req.tol, req.restart,
                                      req.maxit, 0, a.stream.cuda_stream)
             self.active.append(a)
         self.pending = still
 
     # -- stepping --------------------------------------------------------------
     def _retire(self, a: _Active) -> None:
-        rc, infos = B.csg_solve_end(a.sv, a.req.nrhs)
-        a.req.status, a.req.infos = rc, infos
-        a.req.t_done = self.now()
-        if self.keep:
-            a.req.u = a.u.cpu().numpy()
+        rc, infos = B.csg_solve_end(a.sv, a.nrhs)
+        now = self.now()
+        u = a.u.cpu().numpy() if self.keep else None
+        for q, m in enumerate(a.members):
+            lo = q * a.R
+            m.infos = infos[lo:lo + m.nrhs]
+            if len(a.members) == 1:
+                m.status = rc
+            else:
+                m.status = 0 if all(i["converged"] for i in m.infos) else B.CSG_ENOCONV
+            m.t_done = now
+            if self.keep:
+                m.u = u[lo:lo + m.nrhs]
+            if m is not a.req:
+                self.done.append(m)
         if a.key is not None:
             self.cache[a.key] = (a.ws, a.op, a.nbytes)
         else:

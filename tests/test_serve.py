@@ -21,19 +21,22 @@ def _requests(n=10):
     return reqs
 
 
-def _serve(reqs, streams, budget=None):
+def _serve(reqs, streams, budget=None, batch=4, realtime=True):
     from paper_1012_5379_amd.serve import Engine
-    eng = Engine(hbm_budget=budget, streams=streams)
-    done = eng.run(reqs, realtime=True)
+    eng = Engine(hbm_budget=budget, streams=streams, batch=batch)
+    done = eng.run(reqs, realtime=realtime)
     eng.close()
     return {r.rid: r for r in done}, eng
 
 
 def test_alone_equals_mix():
-    """Each request solved alone (one stream, one at a time) and in the mix
-    (four streams, overlapping) gives bit-identical solutions and counts."""
-    alone, _ = _serve(_requests(), streams=1)
-    mixed, eng = _serve(_requests(), streams=4)
+    """Each request solved alone (one stream, one at a time, no batching) and
+    in the mix (four streams, every request queued at once, same-class
+    requests batched into shared operators) gives bit-identical solutions and
+    counts."""
+    alone, _ = _serve(_requests(), streams=1, batch=1)
+    mixed, eng = _serve(_requests(), streams=4, batch=4, realtime=False)
+    assert eng.batches >= 1
     assert set(alone) == set(mixed) and len(alone) == 10
     for rid in alone:
         a, m = alone[rid], mixed[rid]
@@ -41,6 +44,36 @@ def test_alone_equals_mix():
         assert [i["iterations"] for i in a.infos] == [i["iterations"] for i in m.infos]
         assert np.array_equal(a.u, m.u)
         assert all(i["relres_true"] <= 1e-7 for i in m.infos)
+
+
+def test_served_answers_match_the_oracle():
+    """Every served request (batched, overlapping) against the FP64 oracle:
+    complex128-cycle requests reach the oracle's answer at the same tolerance
+    (iterations +-1, solution within 1e-10); complex64-cycle requests reach the
+    tolerance by the oracle's own H, their solution within ten times the
+    error floor of a solve stopping there (or 1e-5) of the oracle's 1e-12
+    answer."""
+    from oracle.oracle import Oracle, Params
+    reqs = _requests()
+    done, _ = _serve(reqs, streams=4, batch=4, realtime=False)
+    for r in reqs:
+        d = done[r.rid]
+        p = {k: v for k, v in r.params.items() if k != "cycle_prec"}
+        orc = Oracle(Params(**p), r.phi)
+        for q in range(r.nrhs):
+            chi = r.chi[q]
+            uo, io = orc.fgmres(chi, tol=r.tol, restart=r.restart, maxit=r.maxit)
+            if r.params["cycle_prec"] == 0:
+                e = np.linalg.norm(d.u[q] - uo) / np.linalg.norm(uo)
+                assert abs(d.infos[q]["iterations"] - io.iterations) <= 1, (r.rid, q)
+                assert e <= 1e-10, (r.rid, q, e)
+            else:
+                rr = np.linalg.norm(chi - orc.apply(d.u[q], which=0, l=0)) / np.linalg.norm(chi)
+                ut, _ = orc.fgmres(chi, tol=1e-12, restart=r.restart, maxit=4000)
+                floor = np.linalg.norm(uo - ut) / np.linalg.norm(ut)
+                e = np.linalg.norm(d.u[q] - ut) / np.linalg.norm(ut)
+                assert rr <= r.tol, (r.rid, q, rr)
+                assert e <= max(1e-5, 10 * floor), (r.rid, q, e, floor)
 
 
 def test_admission_respects_budget():
@@ -75,7 +108,7 @@ def test_repeated_problem_reuses_hierarchy():
     from paper_1012_5379_amd.serve import request_from_workload
     w = W.small(dim=2, n=64, m=6, beta=0.35, kh=0.5, item=42, nrhs=2, cycle_prec=1).with_(tol=1e-7)
     reqs = [request_from_workload(w, rid=i, arrival=0.0) for i in range(2)]
-    done, eng = _serve(reqs, streams=1)
+    done, eng = _serve(reqs, streams=1, batch=1)
     assert eng.cache_hits == 1
     assert done[0].status == 0 and done[1].status == 0
     assert np.array_equal(done[0].u, done[1].u)
