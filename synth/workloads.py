@@ -21,7 +21,7 @@ import numpy as np
 SEED = 10125379
 
 __all__ = ["Workload", "rng", "axis_nodes_real", "c1", "c2", "c3", "c4", "c5_request",
-           "c5_stream", "small", "rand_cvec", "smooth_field", "SEED", "by_name"]
+           "c5_stream", "small", "rand_cvec", "smooth_field", "SEED", "by_name", "benchmark1", "benchmark3"]
 
 
 def rng(cfg_id: int, item: int = 0) -> np.random.Generator:
@@ -258,6 +258,52 @@ def small(dim: int = 2, n: int = 16, m: int = 4, beta: float = 0.4, kh: float = 
     return Workload(f"small_{dim}d_{'x'.join(map(str, nax))}_{item}", dim, nax, h, (mlo,) * dim,
                     (mhi,) * dim, gamma, beta, levels, phi, chi.astype(np.complex128), s=s,
                     nu1=nu1, nu2=nu2, cycle_prec=cycle_prec, meta=dict(cfg_id=100 + dim, item=item))
+
+
+# The paper's numerical experiments (section 5): theta_beta = 10.3132 degrees,
+# theta_gamma = pi/6, V(1,1) with GMRES(3), FGMRES to relative residual 1e-7,
+# kh <= 0.625.  The ECS layer width is not stated; m = n/4 cells per layer (the
+# width of the hierarchy figure of section 4) is the reading taken here.
+PAPER_BETA = 10.3132 * np.pi / 180.0
+BENCH1_GRID = {20: 32, 40: 64, 60: 128, 80: 128, 100: 256}
+BENCH3_GRID = {0.5: 64, 1.5: 128, 2.5: 256, 3.5: 512, 4.5: 512}
+
+
+def benchmark1(k: float, n: int | None = None) -> Workload:
+    """Benchmark 1 (constant k model): unit square, phi = k^2, unit point
+    source at (1/2, 1/2), ECS layers of n/4 cells on every side; the interior
+    grid of the paper's table for this k."""
+    n = BENCH1_GRID[int(k)] if n is None else n
+    m = n // 4
+    h = 1.0 / n
+    shape = (n + 2 * m - 1,) * 2
+    phi = np.full(shape, float(k) ** 2)
+    c = m + n // 2 - 1
+    chi = _point_source(shape, (c, c))[None]
+    return Workload(f"bench1_k{k:g}_{n}", 2, (n, n), h, (m, m), (m, m), np.pi / 6, PAPER_BETA, 0, phi, chi,
+                    tol=1e-7, restart=30, maxit=3000, meta=dict(cfg_id=11, k=k))
+
+
+def benchmark3(k: float, nu: float, n: int | None = None) -> Workload:
+    """Benchmark 3 (Gaussian model): the square (0, 50)^2 with
+    phi = nu (e^{-x^2} + e^{-y^2}) + k^2 and chi = 1 / (e^{x^2} + e^{y^2}),
+    homogeneous Dirichlet on the south and west edges (no layer there), ECS
+    layers of n/4 cells on the north and east edges; the interior grid of the
+    paper's tables for this k."""
+    n = BENCH3_GRID[float(k)] if n is None else n
+    m = n // 4
+    L = 50.0
+    h = L / n
+    # unknown nodes 1 .. n + m - 1 per axis; x = j h, phi constant beyond x = L
+    x = np.arange(1, n + m) * h
+    xc = np.minimum(x, L)
+    Y, X = np.meshgrid(xc, xc, indexing="ij")
+    phi = nu * (np.exp(-X ** 2) + np.exp(-Y ** 2)) + float(k) ** 2
+    Ys, Xs = np.meshgrid(x, x, indexing="ij")
+    with np.errstate(over="ignore"):
+        chi = (1.0 / (np.exp(Xs ** 2) + np.exp(Ys ** 2))).astype(np.complex128)[None]
+    return Workload(f"bench3_k{k:g}_nu{nu:g}_{n}", 2, (n, n), h, (0, 0), (m, m), np.pi / 6, PAPER_BETA, 0, phi, chi,
+                    tol=1e-7, restart=30, maxit=3000, meta=dict(cfg_id=13, k=k, nu=nu))
 
 
 def rand_cvec(shape, item: int = 0, cfg_id: int = 99) -> np.ndarray:
