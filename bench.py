@@ -136,75 +136,87 @@ def vcycle_working_set(level_sizes, nrhs, csize, s=3):
     return sum(n * (nrhs * (s + 6) * csize + csize // 2) for n in level_sizes[:-1])
 
 
-def serve_bench(args):
-    """Serving stream: seeded C5 requests (2-D 256^2..2048^2 and 3-D 64^3..192^3,
-    1-8 point sources, complex64 cycle).  A closed-loop pass (every request
-    queued at once) measures the saturated rate; an open-loop pass then replays
-    Poisson arrivals at `--load` times that rate.  Latency = arrival -> last RHS
-    done, setup included."""
+def serving(count, streams, load, batch=4):
+    """Serving stream: `count` seeded C5 requests (2-D 256^2..2048^2 and 3-D
+    64^3..192^3, 1-8 point sources, complex64 cycle; requests of one size
+    class queued together share one batched operator).  A closed-loop pass
+    (every request queued at once) measures the saturated rate; an open-loop
+    pass then replays Poisson arrivals at `load` times that rate.  Latency =
+    arrival -> last RHS done, setup included."""
     import torch
     from synth import workloads as W
     from paper_1012_5379_amd.serve import Engine, report, request_from_workload
 
-    count = args.requests
-    items = list(range(count))
     t0 = time.perf_counter()
-    base = [W.c5_request(i) for i in items]
+    base = [W.c5_request(i) for i in range(count)]
     print(f"[bench] c5: {count} requests generated in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
 
     def reqs(arrivals):
         return [request_from_workload(w, rid=i, arrival=float(a)) for i, (w, a) in enumerate(zip(base, arrivals))]
 
     # warm-up (kernels loaded, allocator primed): two small requests
-    eng = Engine(streams=args.streams, keep_solutions=False, cache=False)
+    eng = Engine(streams=streams, keep_solutions=False, cache=False, batch=batch)
     eng.run([request_from_workload(W.c5_request(10 ** 5 + i, dim=2, n=256), rid=i) for i in range(2)],
             realtime=False)
     eng.close()
 
-    eng = Engine(streams=args.streams, keep_solutions=False, cache=False)
+    eng = Engine(streams=streams, keep_solutions=False, cache=False, batch=batch)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = eng.run(reqs([0.0] * count), realtime=False)
     torch.cuda.synchronize()
     closed = report(done, time.perf_counter() - t0)
     closed["hbm_high_water_GB"] = eng.high_water / 1e9
+    closed["batched_operators"] = eng.batches
     eng.close()
     print(f"[bench] c5 closed loop: {json.dumps(closed)}", file=sys.stderr, flush=True)
 
-    rate = args.load * closed["requests_per_s"]
+    rate = load * closed["requests_per_s"]
     arr, _ = W.c5_stream(count, rate)
-    eng = Engine(streams=args.streams, keep_solutions=False, cache=False)
+    eng = Engine(streams=streams, keep_solutions=False, cache=False, batch=batch)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = eng.run(reqs(arr), realtime=True)
     torch.cuda.synchronize()
     opened = report(done, time.perf_counter() - t0)
     opened["hbm_high_water_GB"] = eng.high_water / 1e9
+    opened["batched_operators"] = eng.batches
     eng.close()
+    print(f"[bench] c5 open loop: {json.dumps(opened)}", file=sys.stderr, flush=True)
     classes = {}
     for w in base:
         k = f"{w.dim}d_{w.n[0]}"
         classes[k] = classes.get(k, 0) + 1
+    return {"workload": "c5_serving_stream_2d256-2048_3d64-192_1-8rhs_c64cycle", "requests": count,
+            "classes": classes, "streams": streams, "max_batch": batch, "tol": 1e-6,
+            "closed_loop": closed, "open_loop": dict(opened, offered_rate_rps=rate, load=load),
+            "p50_latency_ms": opened["p50_latency_ms"], "p99_latency_ms": opened["p99_latency_ms"]}
+
+
+def serve_bench(args):
+    """--workload c5: the serving stream as the headline line."""
+    sv = serving(args.requests, args.streams, args.load, args.batch)
+    closed = sv["closed_loop"]
     out = {
         "metric": METRIC,
         "value": closed["solves_per_s"],
         "unit": "solves/s",
         "n_gpus": 1,
-        "steps": count,
+        "steps": sv["requests"],
         "warmup": 2,
-        "ms_per_step": closed["seconds"] / count * 1e3,
+        "ms_per_step": closed["seconds"] / sv["requests"] * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "c5_serving_stream_2d256-2048_3d64-192_1-8rhs_c64cycle", "requests": count,
-                   "classes": classes, "streams": args.streams, "tol": 1e-6, "outer_dtype": "f64",
+        "config": {"workload": sv["workload"], "requests": sv["requests"], "classes": sv["classes"],
+                   "streams": sv["streams"], "max_batch": sv["max_batch"], "tol": 1e-6, "outer_dtype": "f64",
                    "parallelism": "single-gpu"},
         "closed_loop": closed,
-        "open_loop": dict(opened, offered_rate_rps=rate, load=args.load),
-        "p50_latency_ms": opened["p50_latency_ms"],
-        "p99_latency_ms": opened["p99_latency_ms"],
+        "open_loop": sv["open_loop"],
+        "p50_latency_ms": sv["p50_latency_ms"],
+        "p99_latency_ms": sv["p99_latency_ms"],
     }
     print(json.dumps(out), flush=True)
 
@@ -222,6 +234,10 @@ def main():
     ap.add_argument("--requests", type=int, default=24, help="c5: requests per pass")
     ap.add_argument("--streams", type=int, default=4, help="c5: concurrent solves")
     ap.add_argument("--load", type=float, default=0.75, help="c5: offered rate / saturated rate")
+    ap.add_argument("--batch", type=int, default=4, help="c5: problems of one size class per batched operator")
+    ap.add_argument("--serving-requests", type=int, default=12,
+                    help="requests of the bounded serving stream reported beside the headline (0: skip)")
+    ap.add_argument("--no-tuned", action="store_true", help="library default knobs instead of the tuned table")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="one device-to-device copy of MIB MiB before the solves (a plain copy of known size "
                          "for scaling hardware byte counters)")
@@ -248,8 +264,10 @@ def main():
     w, wname = _workload(args.workload)
     params = dict(w.params(), cycle_prec=w.cycle_prec, max_rhs=w.nrhs, restart=w.restart)
     t0 = time.perf_counter()
-    op = Operator(params, w.phi)
+    op = Operator(params, w.phi, tuned=not args.no_tuned)
     t_setup = time.perf_counter() - t0
+    knobs = {k: op.params[k] for k in ("slab_blocks", "tile_mult", "slab_min", "tail_max", "fuse_max")
+             if op.params.get(k)}
     chi = torch.from_numpy(w.chi).to("cuda")
     u = torch.empty_like(chi)
     if args.calibrate_copy > 0:
@@ -324,9 +342,9 @@ def main():
     # the same inputs with the V-cycle in complex64 (outer FGMRES complex128)
     mixed = None
     if not args.no_mixed and not w.cycle_prec:
-        del op
+        op = None
         torch.cuda.empty_cache()
-        opm = Operator(dict(params, cycle_prec=1), w.phi)
+        opm = Operator(dict(params, cycle_prec=1), w.phi, tuned=not args.no_tuned)
 
         def solve_m():
             rc, inf = B.helm_solve(opm.op, chi.data_ptr(), u.data_ptr(), nrhs, w.tol, w.restart, w.maxit, 0, stream)
@@ -372,7 +390,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wname, "unknowns": int(w.unknowns), "nrhs": nrhs, "levels": n_levels,
                    "tol": w.tol, "restart": w.restart, "cycle": "V(1,1) GMRES(3)",
-                   "outer_dtype": "f64", "parallelism": "single-gpu", "hip_graphs": graphs},
+                   "outer_dtype": "f64", "parallelism": "single-gpu", "hip_graphs": graphs,
+                   "tuned_knobs": knobs or "library defaults"},
         "iterations_per_solve": its,
         "relres_true": relres,
         "p50_latency_ms": float(np.percentile(lat_ms, 50)),
@@ -410,6 +429,11 @@ def main():
         out["pass_survey_ms_per_solve"] = {k: round(v["ms_per_solve"], 3) for k, v in survey.items()}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, its, args.cpu_sample_its)
+    if args.serving_requests > 0:
+        # a bounded serving stream beside the headline (its own workload: C5)
+        op = None
+        torch.cuda.empty_cache()
+        out["serving"] = serving(args.serving_requests, args.streams, args.load, args.batch)
     print(json.dumps(out), flush=True)
 
 

@@ -96,6 +96,18 @@ typedef struct csg_params {
      * poly_k2: k^2 of t0 (0 = the mean of phi over the finest unknowns). */
     int smoother;
     double poly_k2;
+    /* more execution tuning (0 = library default; results are unaffected
+     * beyond rounding), the knobs the autotuner searches:
+     *   slab_blocks  3-D levels: workgroups per right-hand side the z-marching
+     *                slab passes aim for (default 128; fewer runs of planes
+     *                re-read fewer halo planes, more fill more CUs), 1..4096
+     *   tile_mult    2-D levels: LDS tiles of the fused passes per chunked-pass
+     *                block, a power of two 1..64 (default 1)
+     *   slab_min     3-D levels with at least this many unknowns run the slab
+     *                passes (default 100000; -1: never) */
+    int slab_blocks;
+    int tile_mult;
+    int slab_min;
 } csg_params;
 
 typedef struct csg_operator csg_operator;

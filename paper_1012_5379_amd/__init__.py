@@ -23,9 +23,15 @@ def _torch():
 class Operator:
     """One CSG multigrid hierarchy + FGMRES state resident on the GPU."""
 
-    def __init__(self, params: dict, phi: np.ndarray, device: str = "cuda"):
+    def __init__(self, params: dict, phi: np.ndarray, device: str = "cuda", tuned: bool = False):
+        """tuned: take the execution knobs the caller left at 0 from the
+        autotuner's table (paper_1012_5379_amd/tuned.json) for this problem's
+        dimension, precision, smoother and size class."""
         torch = _torch()
         self.params = dict(params)
+        if tuned:
+            from . import tune
+            self.params = tune.apply(self.params)
         self.p = B.make_params(**self.params)
         self.nbytes = B.csg_workspace_bytes(self.p)
         self.device = torch.device(device)

@@ -147,7 +147,7 @@ TileGeo down_tiling(unsigned nx, unsigned ny, const TileGeo &dflt)
 // planes for about 128 blocks per right-hand side (runs of at least 4 planes,
 // at most NBMAX partials).  The geometry depends on the level alone, so a
 // right-hand side's result is the same whatever else shares its launches.
-SlabGeo slab_geo(unsigned nx, unsigned ny, unsigned nz)
+SlabGeo slab_geo(unsigned nx, unsigned ny, unsigned nz, int blocks)
 {
     SlabGeo g{0, 0, 0, 0, 0};
     g.ntx = (nx + 31) / 32;
@@ -156,6 +156,7 @@ SlabGeo slab_geo(unsigned nx, unsigned ny, unsigned nz)
     if (cols == 0 || cols + 8 > (unsigned)NBMAX) return SlabGeo{0, 0, 0, 0, 0};
     unsigned target = 128u;
     if (const char *e = getenv("CSG_SLAB_BLOCKS")) target = (unsigned)std::max(1, atoi(e));
+    if (blocks > 0) target = (unsigned)blocks;
     unsigned want = (target + cols - 1) / cols;
     want = std::max(1u, std::min({want, (unsigned)(NBMAX - 8) / cols, std::max(1u, nz / 4)}));
     g.zrun = (nz + want - 1) / want;
@@ -179,9 +180,9 @@ void carve(csg_operator &op, const int nint[CSG_MAX_LEVELS][3], Carver &cv)
         }
         lv.ld = lv.N;
         geometry(lv.N, lv.nb, lv.chunk);
-        lv.tile = p.dim == 2 ? tiling(lv.nu[0], lv.nu[1], lv.nb) : TileGeo{0, 0, 0, 0};
+        lv.tile = p.dim == 2 ? tiling(lv.nu[0], lv.nu[1], lv.nb * std::max(1, p.tile_mult)) : TileGeo{0, 0, 0, 0};
         lv.dtile = p.dim == 2 ? down_tiling(lv.nu[0], lv.nu[1], lv.tile) : TileGeo{0, 0, 0, 0};
-        lv.slab = p.dim == 3 ? slab_geo(lv.nu[0], lv.nu[1], lv.nu[2]) : SlabGeo{0, 0, 0, 0, 0};
+        lv.slab = p.dim == 3 ? slab_geo(lv.nu[0], lv.nu[1], lv.nu[2], p.slab_blocks) : SlabGeo{0, 0, 0, 0, 0};
         for (int a = 0; a < p.dim; ++a) lv.tab[a] = cv.take((size_t)op.nprob * 3 * lv.nu[a] * cz);
         for (int a = p.dim; a < 3; ++a) lv.tab[a] = nullptr;
         lv.phi = cv.take((size_t)op.nprob * lv.N * cr);
@@ -1148,7 +1149,8 @@ bool same_class(const csg_params &a, const csg_params &b)
     bool eq = a.dim == b.dim && a.levels == b.levels && a.s == b.s && a.nu1 == b.nu1 && a.nu2 == b.nu2 &&
               a.cycle_prec == b.cycle_prec && a.max_rhs == b.max_rhs && a.restart == b.restart &&
               a.tail_max == b.tail_max && a.fuse_max == b.fuse_max && a.graphs == b.graphs &&
-              a.smoother == b.smoother;
+              a.smoother == b.smoother && a.slab_blocks == b.slab_blocks && a.tile_mult == b.tile_mult &&
+              a.slab_min == b.slab_min;
     for (int d = 0; d < a.dim; ++d)
         eq = eq && a.n[d] == b.n[d] && a.layer_lo[d] == b.layer_lo[d] && a.layer_hi[d] == b.layer_hi[d];
     return eq;
@@ -1331,6 +1333,7 @@ int create_impl(const csg_params *const *ps, const double *const *phis, int P, v
         if (const char *e = getenv("CSG_SLAB_MIN")) op->slab_min = atol(e);
         if (const char *e = getenv("CSG_SLABS"))
             if (atoi(e) == 0) op->slab_min = -1;
+        if (p->slab_min) op->slab_min = p->slab_min;
         if (op->slab_min < 0) op->slab_min = (long)1 << 62;
         for (int l = 0; l < op->L; ++l) {
             op->lev[l].varphi = hh.lev[l].varphi;

@@ -31,6 +31,12 @@ int plan_levels(const csg_params &p, int &L, int nint[CSG_MAX_LEVELS][3], std::s
     if (p.restart < 1 || p.restart > CSG_MAX_RESTART) { err = "restart out of range"; return CSG_EINVAL; }
     if (p.smoother != 0 && p.smoother != 1) { err = "smoother must be 0 (GMRES) or 1 (polynomial)"; return CSG_EINVAL; }
     if (!(p.poly_k2 >= 0.0) || !std::isfinite(p.poly_k2)) { err = "poly_k2 must be finite and >= 0"; return CSG_EINVAL; }
+    if (p.slab_blocks < 0 || p.slab_blocks > 4096) { err = "slab_blocks out of range 0..4096"; return CSG_EINVAL; }
+    if (p.tile_mult < 0 || p.tile_mult > 64 || (p.tile_mult & (p.tile_mult - 1))) {
+        err = "tile_mult must be 0 or a power of two <= 64";
+        return CSG_EINVAL;
+    }
+    if (p.slab_min < -1) { err = "slab_min must be >= -1"; return CSG_EINVAL; }
     int cur[3] = {0, 0, 0};
     for (int a = 0; a < p.dim; ++a) {
         if (p.n[a] < 1 || p.layer_lo[a] < 0 || p.layer_hi[a] < 0) {
