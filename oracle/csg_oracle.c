@@ -30,6 +30,7 @@ typedef struct ora_level {
     cplx *zM[3];   /* node coordinates of the CSG grid (theta = beta) */
     cplx *swM[3];  /* Shortley-Weller coefficients of M: west | centre | east */
     double *phi;   /* injected phi */
+    cplx *gal;     /* Galerkin levels: 3^d-point stencil, [offset][unknown] */
 } ora_level;
 
 struct ora_hier {
@@ -125,11 +126,12 @@ static void axis_sw(int nint, const cplx *z, cplx *sw)
     }
 }
 
-/* d-dimensional operator as a Kronecker sum of the 1-D operators, minus phi
- * (eq. csg_dis with the sign of eq. helm and Lemma 2.1):
- *   (A u)_p = sum_a (w_a u_{p-e_a} + e_a u_{p+e_a}) + (sum_a c_a - phi_p) u_p,
+/* d-dimensional operator as a Kronecker sum of the 1-D operators, minus s phi
+ * (eq. csg_dis with the sign of eq. helm and Lemma 2.1; s = 1 but for the
+ * shifted preconditioner):
+ *   (A u)_p = sum_a (w_a u_{p-e_a} + e_a u_{p+e_a}) + (sum_a c_a - s phi_p) u_p,
  * with values beyond the unknown range equal to zero (Dirichlet). */
-static void apply_tables(const ora_level *lv, cplx *const sw[3], const cplx *x, cplx *y)
+static void apply_tables(const ora_level *lv, cplx *const sw[3], cplx s, const cplx *x, cplx *y)
 {
     const int n0 = lv->nu[0], n1 = lv->nu[1], n2 = lv->nu[2];
     const long s1 = n0, s2 = (long)n0 * n1;
@@ -138,7 +140,7 @@ static void apply_tables(const ora_level *lv, cplx *const sw[3], const cplx *x, 
         for (int j = 0; j < n1; ++j) {
             for (int i = 0; i < n0; ++i) {
                 long p = i + s1 * j + s2 * k;
-                cplx diag = -lv->phi[p];
+                cplx diag = -s * lv->phi[p];
                 cplx acc = 0.0;
                 /* axis 0 */
                 diag += sw[0][n0 + i];
@@ -160,9 +162,48 @@ static void apply_tables(const ora_level *lv, cplx *const sw[3], const cplx *x, 
     }
 }
 
+/* the factor s of phi in M */
+static cplx shift_of(const ora_params *p)
+{
+    if (p->shift_re == 0.0 && p->shift_im == 0.0) return 1.0;
+    return p->shift_re + I * p->shift_im;
+}
+
+/* offsets of a 3^d-point stencil: index sum_a (o_a + 1) 3^a over the used axes */
+static int stencil_points(int d)
+{
+    return d == 1 ? 3 : d == 2 ? 9 : 27;
+}
+
+/* y = A x for a stored 3^d-point stencil (Galerkin levels) */
+static void apply_stencil(const ora_level *lv, int d, const cplx *st, const cplx *x, cplx *y)
+{
+    const int n0 = lv->nu[0], n1 = lv->nu[1], n2 = lv->nu[2];
+    const long N = lv->N;
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < n2; ++k)
+        for (int j = 0; j < n1; ++j)
+            for (int i = 0; i < n0; ++i) {
+                const long p = i + (long)n0 * (j + (long)n1 * k);
+                cplx acc = 0.0;
+                for (int o2 = (d > 2 ? -1 : 0); o2 <= (d > 2 ? 1 : 0); ++o2)
+                    for (int o1 = (d > 1 ? -1 : 0); o1 <= (d > 1 ? 1 : 0); ++o1)
+                        for (int o0 = -1; o0 <= 1; ++o0) {
+                            const long kk = k + o2;
+                            const int jj = j + o1, ii = i + o0;
+                            if (ii < 0 || ii >= n0 || jj < 0 || jj >= n1 || kk < 0 || kk >= n2) continue;
+                            const int oi = (o0 + 1) + 3 * (o1 + 1) * (d > 1) + 9 * (o2 + 1) * (d > 2);
+                            acc += st[oi * N + p] * x[ii + (long)n0 * (jj + (long)n1 * kk)];
+                        }
+                y[p] = acc;
+            }
+}
+
 static void applyM(const ora_hier *hh, int l, const cplx *x, cplx *y)
 {
-    apply_tables(&hh->lev[l], (cplx *const *)hh->lev[l].swM, x, y);
+    const ora_level *lv = &hh->lev[l];
+    if (lv->gal) apply_stencil(lv, hh->p.dim, lv->gal, x, y);
+    else apply_tables(lv, (cplx *const *)lv->swM, shift_of(&hh->p), x, y);
 }
 
 /* ---------------------------------------------------------------------------
@@ -270,7 +311,7 @@ static int coarse_factor(ora_hier *hh)
     for (int c = 0; c < n; ++c) {
         memset(e, 0, sizeof(cplx) * (size_t)n);
         e[c] = 1.0;
-        apply_tables(C, (cplx *const *)C->swM, e, col);
+        applyM(hh, hh->L - 1, e, col);
         for (int r = 0; r < n; ++r) hh->lu[(long)r * n + c] = col[r];
     }
     free(e);
@@ -327,6 +368,66 @@ int ora_coarse_solve(const ora_hier *hh, const cplx *b, cplx *x)
  * complex grid; phi injected)
  * ------------------------------------------------------------------------- */
 
+/* Galerkin coarse operator of level l from level l - 1 (its Kronecker-sum
+ * tables or its own stencil): M_l = R M_{l-1} P.  Column J of M_l has its
+ * nonzeros at |K_a - J_a| <= 1 (P e_J spans fine unknowns 2J .. 2J+2 per axis,
+ * M_{l-1} widens that by one, R reaches back to coarse unknowns within one),
+ * so the columns whose indices agree mod 3 on every axis have disjoint
+ * supports: each of the 3^d colour classes is applied at once,
+ * y = R M_{l-1} P (sum of e_J over the class), and entry (K, K + o) is y_K for
+ * the class of K + o. */
+static void galerkin_level(ora_hier *hh, int l)
+{
+    ora_level *C = &hh->lev[l];
+    const ora_level *F = &hh->lev[l - 1];
+    const int d = hh->p.dim, np = stencil_points(d);
+    const long N = C->N;
+    C->gal = cvec(np * N);
+    cplx *xc = cvec(N), *y = cvec(N), *f = cvec(F->N), *g = cvec(F->N);
+    for (int col = 0; col < np; ++col) {
+        const int c0 = col % 3, c1 = (col / 3) % 3, c2 = col / 9;
+        for (long K = 0; K < C->nu[2]; ++K)
+            for (int J = 0; J < C->nu[1]; ++J)
+                for (int Ii = 0; Ii < C->nu[0]; ++Ii) {
+                    const int on = Ii % 3 == c0 && (d < 2 || J % 3 == c1) && (d < 3 || K % 3 == c2);
+                    xc[Ii + (long)C->nu[0] * (J + (long)C->nu[1] * K)] = on ? 1.0 : 0.0;
+                }
+        memset(f, 0, sizeof(cplx) * (size_t)F->N);
+        ora_prolong_add(hh, l - 1, xc, f);
+        applyM(hh, l - 1, f, g);
+        ora_restrict(hh, l - 1, g, y);
+        for (long K = 0; K < C->nu[2]; ++K)
+            for (int J = 0; J < C->nu[1]; ++J)
+                for (int Ii = 0; Ii < C->nu[0]; ++Ii) {
+                    const long p = Ii + (long)C->nu[0] * (J + (long)C->nu[1] * K);
+                    for (int o2 = (d > 2 ? -1 : 0); o2 <= (d > 2 ? 1 : 0); ++o2)
+                        for (int o1 = (d > 1 ? -1 : 0); o1 <= (d > 1 ? 1 : 0); ++o1)
+                            for (int o0 = -1; o0 <= 1; ++o0) {
+                                const long kk = K + o2;
+                                const int jj = J + o1, ii = Ii + o0;
+                                if (ii < 0 || ii >= C->nu[0] || jj < 0 || jj >= C->nu[1] || kk < 0 ||
+                                    kk >= C->nu[2])
+                                    continue;
+                                const int in = ii % 3 == c0 && (d < 2 || jj % 3 == c1) && (d < 3 || kk % 3 == c2);
+                                if (!in) continue;
+                                const int oi = (o0 + 1) + 3 * (o1 + 1) * (d > 1) + 9 * (o2 + 1) * (d > 2);
+                                C->gal[oi * N + p] = y[p];
+                            }
+                }
+    }
+    free(xc);
+    free(y);
+    free(f);
+    free(g);
+}
+
+int ora_galerkin_stencil(const ora_hier *hh, int l, cplx *out)
+{
+    if (!hh || l < 0 || l >= hh->L || !hh->lev[l].gal) return -1;
+    memcpy(out, hh->lev[l].gal, sizeof(cplx) * (size_t)stencil_points(hh->p.dim) * (size_t)hh->lev[l].N);
+    return 0;
+}
+
 static int validate(const ora_params *p)
 {
     if (p->dim < 1 || p->dim > 3) return -1;
@@ -335,6 +436,9 @@ static int validate(const ora_params *p)
     if (!(p->beta >= 0.0 && p->beta < p->gamma)) return -1;
     if (p->s < 1 || p->nu1 < 0 || p->nu2 < 0 || p->levels < 0 || p->levels > ORA_MAXL) return -1;
     if (p->smoother < 0 || p->smoother > 1 || !(p->poly_k2 >= 0.0) || !isfinite(p->poly_k2)) return -1;
+    if (!isfinite(p->shift_re) || !isfinite(p->shift_im) || p->coarse_op < 0 || p->coarse_op > 1) return -1;
+    /* the polynomial smoother's triangle is that of the rediscretised CSG operator */
+    if (p->smoother == 1 && (p->coarse_op != 0 || shift_of(p) != 1.0)) return -1;
     for (int a = 0; a < p->dim; ++a) {
         if (p->n[a] < 1 || p->layer_lo[a] < 0 || p->layer_hi[a] < 0) return -1;
         if (p->n[a] + p->layer_lo[a] + p->layer_hi[a] < 2) return -1;
@@ -412,6 +516,8 @@ ora_hier *ora_build(const ora_params *p, const double *phi, int *status)
         hh->swH[a] = cvec(3L * (nint[a] - 1));
         axis_sw(nint[a], hh->zH[a], hh->swH[a]);
     }
+    if (p->coarse_op == 1)
+        for (int l = 1; l < L; ++l) galerkin_level(hh, l);
     st = coarse_factor(hh);
     if (st) { ora_free(hh); if (status) *status = st; return NULL; }
     if (status) *status = 0;
@@ -424,6 +530,7 @@ void ora_free(ora_hier *hh)
     for (int l = 0; l < hh->L; ++l) {
         for (int a = 0; a < 3; ++a) { free(hh->lev[l].zM[a]); free(hh->lev[l].swM[a]); }
         free(hh->lev[l].phi);
+        free(hh->lev[l].gal);
     }
     for (int a = 0; a < 3; ++a) { free(hh->zH[a]); free(hh->swH[a]); }
     free(hh->lu);
@@ -468,7 +575,7 @@ int ora_apply(const ora_hier *hh, int which, int l, const cplx *x, cplx *y)
     if (!hh || l < 0 || l >= hh->L) return -1;
     if (which == 0) {
         if (l != 0) return -1;
-        apply_tables(&hh->lev[0], (cplx *const *)hh->swH, x, y);
+        apply_tables(&hh->lev[0], (cplx *const *)hh->swH, 1.0, x, y);
         return 0;
     }
     if (which != 1) return -1;

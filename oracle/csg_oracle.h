@@ -42,6 +42,14 @@ typedef struct ora_params {
     int nu1, nu2;       /* pre- and post-smoothing sweeps */
     int smoother;       /* 0 = GMRES(s) (section 3.1), 1 = third-order polynomial (section 4) */
     double poly_k2;     /* k^2 of the polynomial's vertex t0 = -k^2; 0 = mean of phi on the finest level */
+    /* complex factor s of phi in the preconditioner, M = L(theta = beta) - s phi
+     * on every level (0 + 0i means s = 1, the CSG preconditioner).  beta = 0 and
+     * s = 1 + i eps is the complex shifted Laplacian (section 1, section 2). */
+    double shift_re, shift_im;
+    /* coarse operators: 0 = rediscretisation on the coarser complex grid
+     * (section 3), 1 = Galerkin products M_{l+1} = R M_l P (section 5 remark on
+     * the bound states), stored as 3^d-point stencils */
+    int coarse_op;
 } ora_params;
 
 typedef struct ora_info {
@@ -121,6 +129,12 @@ int ora_poly_conditions(double k2, double H, int dim, double beta, double gamma,
 /* One polynomial smoothing sweep on M_l: x <- x + omega_i (b - M_l x) for
  * i = 1, 2, 3, so the error is multiplied by p(M_l).  x_is_zero: x = 0 on entry. */
 int ora_poly_sweep(const ora_hier *hh, int l, const double complex *b, double complex *x, int x_is_zero);
+
+/* Galerkin coarse operator of level l >= 1 (coarse_op = 1): 3^d coefficients
+ * per unknown, laid out [offset][unknown] with the offset index
+ * sum_a (o_a + 1) 3^a over the used axes, o_a in {-1, 0, 1} (entries whose
+ * neighbour lies outside the grid are 0). */
+int ora_galerkin_stencil(const ora_hier *hh, int l, double complex *out);
 
 /* Deterministic Hermitian inner product sum conj(x) y in fixed 4096-element
  * chunks, summed in chunk order (independent of the thread count). */

@@ -39,7 +39,8 @@ class _Params(C.Structure):
                 ("layer_lo", C.c_int * 3), ("layer_hi", C.c_int * 3),
                 ("gamma", C.c_double), ("beta", C.c_double), ("levels", C.c_int),
                 ("s", C.c_int), ("nu1", C.c_int), ("nu2", C.c_int), ("smoother", C.c_int),
-                ("poly_k2", C.c_double)]
+                ("poly_k2", C.c_double), ("shift_re", C.c_double), ("shift_im", C.c_double),
+                ("coarse_op", C.c_int)]
 
 
 class _Cplx(C.Structure):
@@ -88,6 +89,7 @@ def lib():
         L.ora_poly_conditions.argtypes = [dp, dp, ip, dp, dp, dp, C.POINTER(C.c_double),
                                           C.POINTER(C.c_double)]
         L.ora_poly_sweep.argtypes = [vp, ip, vp, vp, ip]
+        L.ora_galerkin_stencil.argtypes = [vp, ip, vp]
         L.ora_threads.restype = C.c_int
         L.ora_threads.argtypes = []
         L.ora_dot.restype = _Cplx
@@ -112,6 +114,8 @@ class Params:
     nu2: int = 1
     smoother: int = 0        # 0 = GMRES(s), 1 = third-order polynomial (section 4)
     poly_k2: float = 0.0     # k^2 of the polynomial's vertex t0; 0 = mean of phi
+    shift: complex = 0j      # factor s of phi in M = L(beta) - s phi; 0 means 1 (beta = 0, s = 1 + i eps: CSL)
+    coarse_op: int = 0       # 0 = rediscretisation (section 3), 1 = Galerkin R M P
 
     def c(self) -> _Params:
         p = _Params()
@@ -123,6 +127,8 @@ class Params:
         p.h, p.gamma, p.beta = float(self.h), float(self.gamma), float(self.beta)
         p.levels, p.s, p.nu1, p.nu2 = int(self.levels), int(self.s), int(self.nu1), int(self.nu2)
         p.smoother, p.poly_k2 = int(self.smoother), float(self.poly_k2)
+        p.shift_re, p.shift_im = float(complex(self.shift).real), float(complex(self.shift).imag)
+        p.coarse_op = int(self.coarse_op)
         return p
 
     def unknown_shape(self) -> tuple:
@@ -238,6 +244,15 @@ class Oracle:
         x = self._out(l) if zero else np.array(x, dtype=np.complex128, order="C").reshape(self.shape(l))
         k = lib().ora_gmres_sweep(self._h, l, s, pb, x.ctypes.data, int(zero))
         return x, k
+
+    def galerkin_stencil(self, l: int) -> np.ndarray:
+        """Level l's Galerkin operator (coarse_op = 1) as (3^d, *shape) coefficients,
+        offset index sum_a (o_a + 1) 3^a over the used axes (x first)."""
+        np_ = 3 ** self.params.dim
+        out = np.zeros((np_,) + self.shape(l), dtype=np.complex128)
+        if lib().ora_galerkin_stencil(self._h, l, out.ctypes.data):
+            raise ValueError("no Galerkin operator on this level")
+        return out
 
     def poly(self, l: int) -> dict:
         """The level's third-order polynomial smoother (section 4)."""
