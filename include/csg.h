@@ -108,6 +108,14 @@ typedef struct csg_params {
     int slab_blocks;
     int tile_mult;
     int slab_min;
+    /* complex factor s of phi in the preconditioner on every level,
+     * M = L(theta_beta) - s phi (0 + 0i means s = 1, the CSG preconditioner).
+     * beta = 0 and s = 1 + i eps is the complex shifted Laplacian the paper
+     * compares with (section 1, section 2: (1 + eps i) k^2); on a grid without
+     * ECS layers the CSG preconditioner equals e^{-2i beta} times the one with
+     * beta = 0 and s = e^{2i beta}.  H is never shifted.  Takes the GMRES(s)
+     * smoother (smoother = 0). */
+    double shift_re, shift_im;
 } csg_params;
 
 typedef struct csg_operator csg_operator;

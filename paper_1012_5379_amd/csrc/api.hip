@@ -241,6 +241,9 @@ LvlK<T> lvl(const csg_operator *op, int l)
     L.nz = d.nu[2];
     L.N = d.N;
     batch_strides<T>(op, d, L);
+    const cd sh = phi_shift(op->p);
+    L.sre = sh.real();
+    L.sim = sh.imag();
     return L;
 }
 
@@ -1150,7 +1153,7 @@ bool same_class(const csg_params &a, const csg_params &b)
               a.cycle_prec == b.cycle_prec && a.max_rhs == b.max_rhs && a.restart == b.restart &&
               a.tail_max == b.tail_max && a.fuse_max == b.fuse_max && a.graphs == b.graphs &&
               a.smoother == b.smoother && a.slab_blocks == b.slab_blocks && a.tile_mult == b.tile_mult &&
-              a.slab_min == b.slab_min;
+              a.slab_min == b.slab_min && phi_shift(a) == phi_shift(b);
     for (int d = 0; d < a.dim; ++d)
         eq = eq && a.n[d] == b.n[d] && a.layer_lo[d] == b.layer_lo[d] && a.layer_hi[d] == b.layer_hi[d];
     return eq;
@@ -1383,6 +1386,9 @@ int create_impl(const csg_params *const *ps, const double *const *phis, int P, v
             t.rpp = op->nprob > 1 ? (unsigned)op->rpp : 0u;
             for (int a = 0; a < 3; ++a) t.tstride[a] = 3 * d.nu[a];
             t.pstride = d.N;
+            const cd sh = phi_shift(op->p);
+            t.sre = sh.real();
+            t.sim = sh.imag();
         }
         // the descriptor holds only pointers and sizes: identical layout for both precisions
         if (rc == CSG_OK && hipMemcpyAsync(op->tlev, tl.data(), tl.size() * sizeof(TLev<double>),

@@ -104,6 +104,8 @@ struct HostHier {
 };
 
 int plan_levels(const csg_params &p, int &L, int nint[CSG_MAX_LEVELS][3], std::string &err);
+// the factor s of phi in the preconditioner (1 when the parameters leave it at 0)
+cd phi_shift(const csg_params &p);
 int build_hierarchy(const csg_params &p, const double *phi, HostHier &hh, std::string &err);
 
 // ---------------------------------------------------------------------------

@@ -18,6 +18,10 @@ struct LvlK {
     unsigned rpp;
     unsigned tstride[3];
     size_t pstride;
+    // complex factor s of phi in the operator's diagonal (sum of the axes'
+    // centre weights - s phi): 1 for H and the CSG preconditioner, 1 + i eps
+    // for the complex shifted Laplacian
+    double sre = 1.0, sim = 0.0;
     // the geometry as right-hand side rhs sees it
     __host__ __device__ __forceinline__ LvlK at(int rhs) const
     {
@@ -52,6 +56,7 @@ struct TLev {
     unsigned rpp;
     unsigned tstride[3];
     size_t pstride;
+    double sre = 1.0, sim = 0.0;   // factor of phi (see LvlK)
 };
 
 struct Launch {

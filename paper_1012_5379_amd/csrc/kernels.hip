@@ -42,6 +42,15 @@ __device__ __forceinline__ void decomp(unsigned p, unsigned nx, unsigned ny, uns
     }
 }
 
+// diagonal d -= s phi_p with the operator's factor s (exactly d.re -= phi_p
+// for s = 1)
+template <typename T>
+__device__ __forceinline__ void sub_phi(Cx<T> &d, const LvlK<T> &K, T ph)
+{
+    d.re -= (T)K.sre * ph;
+    d.im -= (T)K.sim * ph;
+}
+
 // (A x)_p for the Kronecker-sum operator: per axis west/centre/east weights,
 // diagonal minus phi.  Boundary weights are zero in the tables, so the clamped
 // neighbour index only keeps the load in range.
@@ -53,7 +62,7 @@ __device__ __forceinline__ Cx<T> apply_pt(const LvlK<T> &L, const Cx<TI> *__rest
     Cx<T> d = tx[L.nx + i];
     if (DIM >= 2) d = d + L.tab[1][L.ny + j];
     if (DIM == 3) d = d + L.tab[2][L.nz + k];
-    d.re -= L.phi[p];
+    sub_phi(d, L, L.phi[p]);
     Cx<T> acc = d * cvt<T>(x[p]);
     acc = cfma(tx[i], cvt<T>(x[i ? p - 1 : p]), acc);
     acc = cfma(tx[2 * L.nx + i], cvt<T>(x[i + 1 < L.nx ? p + 1 : p]), acc);
@@ -517,7 +526,7 @@ __device__ __forceinline__ void body_os(const LvlK<T> &L, const Basis<T> &B, con
         Cx<T> d = tx[L.nx + i];
         if (DIM >= 2) d = d + L.tab[1][L.ny + jj];
         if (DIM == 3) d = d + L.tab[2][L.nz + k];
-        d.re -= L.phi[p];
+        sub_phi(d, L, L.phi[p]);
         Cx<T> a = d * uc;
         if (i) a = cfma(tx[i], next_u<T, SB>(B, wi, j, sj, cu, off, p - 1), a);
         if (i + 1 < L.nx) a = cfma(tx[2 * L.nx + i], next_u<T, SB>(B, wi, j, sj, cu, off, p + 1), a);
@@ -881,7 +890,7 @@ __device__ __forceinline__ void prc_pt(const LvlK<T> &F, const LvlK<T> &C, const
     Cx<T> d = tx[F.nx + i];
     if (DIM >= 2) d = d + F.tab[1][F.ny + j];
     if (DIM == 3) d = d + F.tab[2][F.nz + k];
-    d.re -= F.phi[p];
+    sub_phi(d, F, F.phi[p]);
     xc = corrected<T, DIM>(xi, e, i, j, k, p, C);
     Cx<T> acc = d * xc;
     if (i) acc = cfma(tx[i], corrected<T, DIM>(xi, e, i - 1, j, k, p - 1, C), acc);
@@ -1247,7 +1256,7 @@ __global__ __launch_bounds__(BLK) void k_os_tile(LvlK<T> L, Basis<T> B, const Cx
         const int c = ex - 1, r = ey - 1;
         const Cx<T> uc = lu[e];
         Cx<T> d = ltab[1 * TAB_MAXD + c] + ltab[4 * TAB_MAXD + r];
-        d.re -= phq[it];
+        sub_phi(d, L, phq[it]);
         Cx<T> a = d * uc;
         a = cfma(ltab[0 * TAB_MAXD + c], lu[e - 1], a);
         a = cfma(ltab[2 * TAB_MAXD + c], lu[e + 1], a);
@@ -1426,7 +1435,7 @@ __global__ __launch_bounds__(BLK) void k_slab(LvlK<T> L, Basis<T> B, const Cx<T>
             const Cx<T> *Rm = ring[(k + 2) % 3], *R0 = ring[k % 3], *Rp = ring[(k + 1) % 3];
             const Cx<T> *tz = L.tab[2];
             Cx<T> d = ltab[SX + tx] + ltab[3 * SX + SY + ty] + tz[nz + k];
-            d.re -= phc;
+            sub_phi(d, L, phc);
             Cx<T> a = d * R0[eo];
             a = cfma(ltab[tx], R0[eo - 1], a);
             a = cfma(ltab[2 * SX + tx], R0[eo + 1], a);
@@ -1538,7 +1547,7 @@ __global__ __launch_bounds__(BLK) void k_st0_tile(LvlK<T> L, const Cx<T> *__rest
         const int c = ex - 1, r = ey - 1;
         const Cx<T> uc = lu[e];
         Cx<T> d = ltab[1 * TAB_MAXD + c] + ltab[4 * TAB_MAXD + r];
-        d.re -= phq[it];
+        sub_phi(d, L, phq[it]);
         Cx<T> a = d * uc;
         a = cfma(ltab[0 * TAB_MAXD + c], lu[e - 1], a);
         a = cfma(ltab[2 * TAB_MAXD + c], lu[e + 1], a);
@@ -2231,7 +2240,7 @@ __global__ __launch_bounds__(BLK) void k_up_tile(LvlK<T> F, LvlK<T> C, const Cx<
             const int a = ok ? (qy + 1) * AX + qx + 1 : 2 * AX + 2;
             const int c = ok ? qx : 1, rr = ok ? qy : 1;
             Cx<T> d = ltab[1 * TAB_MAXD + c] + ltab[4 * TAB_MAXD + rr];
-            d.re -= phq[it];
+            sub_phi(d, F, phq[it]);
             Cx<T> ax = d * lx[a];
             ax = cfma(ltab[0 * TAB_MAXD + c], lx[a - 1], ax);
             ax = cfma(ltab[2 * TAB_MAXD + c], lx[a + 1], ax);
@@ -2261,7 +2270,7 @@ __global__ __launch_bounds__(BLK) void k_up_tile(LvlK<T> F, LvlK<T> C, const Cx<
         if (q >= RN || qx < 1 || qx > TX || qy < 1 || qy > TY) continue;
         const Cx<T> uc = rq[it];
         Cx<T> d = ltab[1 * TAB_MAXD + qx] + ltab[4 * TAB_MAXD + qy];
-        d.re -= phq[it];
+        sub_phi(d, F, phq[it]);
         Cx<T> a = d * uc;
         a = cfma(ltab[0 * TAB_MAXD + qx], lx[q - 1], a);
         a = cfma(ltab[2 * TAB_MAXD + qx], lx[q + 1], a);
@@ -2444,7 +2453,7 @@ __global__ __launch_bounds__(BLK) void k_down_tile(Cx<T> *__restrict__ x, int ac
             const size_t p = (size_t)(Y0 + r) * cnx + X0 + c;
             const Cx<T> uc = bq[it];
             Cx<T> d = ltab[1 * TAB_MAXD + c] + ltab[4 * TAB_MAXD + r];
-            d.re -= phq[it];
+            sub_phi(d, C, phq[it]);
             Cx<T> a = d * uc;
             a = cfma(ltab[0 * TAB_MAXD + c], lb[q - 1], a);
             a = cfma(ltab[2 * TAB_MAXD + c], lb[q + 1], a);
@@ -2591,6 +2600,8 @@ __device__ __forceinline__ LvlK<T> tlvl(const TLev<T> &d, int rhs)
     L.N = d.N;
     L.rpp = d.rpp;
     L.pstride = d.pstride;
+    L.sre = d.sre;
+    L.sim = d.sim;
     return L.at(rhs);
 }
 
@@ -2743,7 +2754,7 @@ __device__ __forceinline__ void tsten_load(const LvlK<T> &L, TSten<T, DIM, MP> &
         Cx<T> d = tx[L.nx + i];
         if (DIM >= 2) d = d + L.tab[1][L.ny + j];
         if (DIM == 3) d = d + L.tab[2][L.nz + kk];
-        d.re -= L.phi[p];
+        sub_phi(d, L, L.phi[p]);
         S.d[k] = d;
         S.c[k][0] = tx[i];
         S.nb[k][0] = i ? p - 1 : p;
@@ -3791,7 +3802,7 @@ __global__ __launch_bounds__(BLK) void k_poly_tile(LvlK<T> L, LvlK<T> C, const C
         const unsigned gp = (unsigned)cy * nx + cx;
         bq[k] = b[off + gp];
         Cx<T> d = L.tab[0][nx + cx] + L.tab[1][ny + cy];
-        d.re -= L.phi[gp];
+        sub_phi(d, L, L.phi[gp]);
         dq[k] = d;
         wxq[k] = L.tab[0][cx];
         exq[k] = L.tab[0][2 * nx + cx];
@@ -4085,6 +4096,67 @@ void launch_coarse(const Cx<T> *minvT, int n, const Cx<T> *b, Cx<T> *x, size_t l
     hipLaunchKernelGGL((k_coarse<T>), dim3(1, nrhs), dim3(BLK), 0, st, minvT, n, b, x, ld, mstride, rpp, active);
 }
 
+// Shared start of the first-round kernels: sum the inner products of k_hdot
+// (h_i = <v_i, w>, i <= j, and ||w||^2) from the RHS's partials pp into cc
+// (group_parts: a fixed order, so every block gets the same bits) and take
+// the block-uniform decision: twos = 1 when a second round is needed, else
+// scs = 1 / ||w1|| for the final column.
+__device__ __forceinline__ void proj0_head(const FState *fs, int j, const zc *pp, int nbin, zc *cc, double &scs,
+                                           int &twos)
+{
+    for (int q = threadIdx.x / FG; q <= j + 1; q += BLK / FG) {
+        const zc v = group_parts(pp + q * NBMAX, nbin);
+        if (threadIdx.x % FG == 0) cc[q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double w2 = cc[j + 1].re;
+        double h2 = 0.0;
+        for (int q = 0; q <= j; ++q) h2 += cabs2(cc[q]);
+        const double w1 = w2 - h2;
+        // Daniel-Gragg-Kaufman-Stewart criterion: one round is final when it
+        // keeps at least 1/sqrt(2) of ||w||; a laxer bound lets the error of
+        // the single round (ratio ||h|| / ||w1|| times the basis's own loss of
+        // orthogonality) compound from column to column
+        const int two = fs->force2 || !(w1 >= 0.5 * w2);   // force2: every column, for tests
+        const double hn = sqrt(w1);
+        twos = two;
+        scs = hn > 0.0 ? 1.0 / hn : 0.0;
+    }
+    __syncthreads();
+}
+
+// Shared end of the first-round kernels (block 0): the FGMRES state advances
+// by the column h, the flag of the second round and, for a final column, the
+// Givens step, the report and the stop test.
+__device__ __forceinline__ void proj0_state(FState *fs, Report *rep, int *stop, int j, const zc *cc, bool two)
+{
+    constexpr int M = CSG_MAX_RESTART;
+    __shared__ zc col[OVAL];
+    __shared__ double cs_s[M];
+    __shared__ zc sn_s[M];
+    for (int q = threadIdx.x; q < j; q += BLK) {
+        cs_s[q] = fs->cs[q];
+        sn_s[q] = fs->sn[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 0; q <= j; ++q) {
+            col[q] = cc[q];
+            fs->hcol[q] = cc[q];
+        }
+        const double w2 = cc[j + 1].re;
+        double h2 = 0.0;
+        for (int q = 0; q <= j; ++q) h2 += cabs2(cc[q]);
+        fs->w2 = w2;
+        fs->reorth = two;
+        if (!two) givens_column(fs, rep, j, sqrt(w2 - h2), col, cs_s, sn_s, stop);
+    }
+    __syncthreads();
+    if (!two)
+        for (int q = threadIdx.x; q <= j + 1; q += BLK) fs->R[q * M + j] = col[q];
+}
+
 // First round of column j, finished and applied in one launch.  Every block
 // sums the inner products of k_hdot (h_i = <v_i, w>, i <= j, and ||w||^2) from
 // their partials (group_parts: a fixed order, so every block gets the same
@@ -4106,7 +4178,6 @@ __global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__r
                                                zc *__restrict__ vout, Cx<TB> *__restrict__ bc, unsigned chunk,
                                                int nb, const int *active)
 {
-    constexpr int M = CSG_MAX_RESTART;
     __shared__ zc sh[(BLK / 64) * 8];
     __shared__ zc res[8];
     __shared__ zc cc[OVAL];
@@ -4115,29 +4186,7 @@ __global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__r
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
     FState *fs = fsb + rhs;
-    {
-        const zc *pp = pin + (size_t)rhs * OVAL * NBMAX;
-        for (int q = threadIdx.x / FG; q <= j + 1; q += BLK / FG) {
-            const zc v = group_parts(pp + q * NBMAX, nbin);
-            if (threadIdx.x % FG == 0) cc[q] = v;
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const double w2 = cc[j + 1].re;
-        double h2 = 0.0;
-        for (int q = 0; q <= j; ++q) h2 += cabs2(cc[q]);
-        const double w1 = w2 - h2;
-        // Daniel-Gragg-Kaufman-Stewart criterion: one round is final when it
-        // keeps at least 1/sqrt(2) of ||w||; a laxer bound lets the error of
-        // the single round (ratio ||h|| / ||w1|| times the basis's own loss of
-        // orthogonality) compound from column to column
-        const int two = fs->force2 || !(w1 >= 0.5 * w2);   // force2: every column, for tests
-        const double hn = sqrt(w1);
-        twos = two;
-        scs = hn > 0.0 ? 1.0 / hn : 0.0;
-    }
-    __syncthreads();
+    proj0_head(fs, j, pin + (size_t)rhs * OVAL * NBMAX, nbin, cc, scs, twos);
     const bool two = twos != 0;
     const double sc = scs;
     const size_t off = rhs * ld;
@@ -4219,30 +4268,115 @@ __global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__r
         }
     }
     if (blockIdx.x != 0) return;
-    // the FGMRES state (block 0)
-    __shared__ zc col[OVAL];
-    __shared__ double cs_s[M];
-    __shared__ zc sn_s[M];
-    for (int q = threadIdx.x; q < j; q += BLK) {
-        cs_s[q] = fs->cs[q];
-        sn_s[q] = fs->sn[q];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int q = 0; q <= j; ++q) {
-            col[q] = cc[q];
-            fs->hcol[q] = cc[q];
+    proj0_state(fs, rep + rhs, stop ? stop + rhs : nullptr, j, cc, two);
+}
+
+// k_proj0 for columns of more than 16 basis vectors, reading V once: the
+// basis is split over the block's wavefronts (wavefront wv holds v_q for
+// q = wv, wv + NW, ..., QW of them at most) and every lane takes PU points per
+// step, so a point's basis values sit in the registers of NW lanes.  Each
+// wavefront forms its share of (V c)(p) in ascending q; the shares meet in
+// shared memory and every wavefront sums them in wavefront order, so all form
+// the same w1(p) = w(p) - sum; wavefront 0 stores it (or, for a final column,
+// v_{j+1} and its copy), and for a second round each wavefront accumulates the
+// inner products <v_q, w1> of its own vectors and wavefront 0 also ||w1||^2.
+// The shares are double-buffered, so one barrier per step suffices.
+template <typename TB, int QW, int PU>
+__global__ __launch_bounds__(BLK) void k_proj0w(zc *__restrict__ w, const zc *__restrict__ V, size_t vstride, int j,
+                                                unsigned N, size_t ld, FState *fsb, Report *rep, int *stop,
+                                                const zc *__restrict__ pin, int nbin, zc *__restrict__ pout,
+                                                zc *__restrict__ vout, Cx<TB> *__restrict__ bc, unsigned chunk,
+                                                int nb, const int *active)
+{
+    constexpr int NW = BLK / 64;
+    constexpr int NV = QW + 1;                    // QW inner products and ||w1||^2
+    constexpr int ND = pow2_at_least(2 * NV);
+    constexpr int SH = ND == 2 ? 5 : ND == 4 ? 4 : ND == 8 ? 3 : ND == 16 ? 2 : ND == 32 ? 1 : 0;
+    __shared__ zc cc[OVAL];
+    __shared__ double scs;
+    __shared__ int twos;
+    __shared__ zc share[2][NW][PU * 64];
+    __shared__ zc wsh[2][PU * 64];
+    const int rhs = blockIdx.y;
+    if (!active[rhs]) return;
+    FState *fs = fsb + rhs;
+    proj0_head(fs, j, pin + (size_t)rhs * OVAL * NBMAX, nbin, cc, scs, twos);
+    const bool two = twos != 0;
+    const double sc = scs;
+    const size_t off = rhs * ld;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nq = (j + NW - wv) / NW;            // vectors wv, wv + NW, ... <= j
+    const unsigned c = chunk_id(nb);
+    const unsigned b0 = c * chunk, b1 = min(N, b0 + chunk);
+    zc dots[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) dots[k] = mkc(0.0, 0.0);
+    int buf = 0;
+    for (unsigned pb = b0; pb < b1; pb += PU * 64, buf ^= 1) {
+        zc v[PU][QW];
+#pragma unroll
+        for (int u = 0; u < PU; ++u) {
+            const unsigned pc = min(pb + u * 64 + lane, b1 - 1);
+#pragma unroll
+            for (int k = 0; k < QW; ++k)
+                if (k < nq) v[u][k] = V[(wv + NW * k) * vstride + off + pc];
+            if (wv == NW - 1) wsh[buf][u * 64 + lane] = w[off + pc];
         }
-        const double w2 = cc[j + 1].re;
-        double h2 = 0.0;
-        for (int q = 0; q <= j; ++q) h2 += cabs2(cc[q]);
-        fs->w2 = w2;
-        fs->reorth = two;
-        if (!two) givens_column(fs, rep + rhs, j, sqrt(w2 - h2), col, cs_s, sn_s, stop ? stop + rhs : nullptr);
+#pragma unroll
+        for (int u = 0; u < PU; ++u) {
+            zc a = mkc(0.0, 0.0);
+#pragma unroll
+            for (int k = 0; k < QW; ++k)
+                if (k < nq) a = a + cc[wv + NW * k] * v[u][k];
+            share[buf][wv][u * 64 + lane] = a;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PU; ++u) {
+            const unsigned p = pb + u * 64 + lane;
+            zc a = share[buf][0][u * 64 + lane];
+#pragma unroll
+            for (int t = 1; t < NW; ++t) a = a + share[buf][t][u * 64 + lane];
+            const zc x = wsh[buf][u * 64 + lane] - a;
+            if (p < b1) {
+                if (two) {
+                    if (wv == 0) {
+                        w[off + p] = x;
+                        dots[QW].re += cabs2(x);
+                    }
+#pragma unroll
+                    for (int k = 0; k < QW; ++k)
+                        if (k < nq) dots[k] = cjfma(v[u][k], x, dots[k]);
+                } else if (wv == 0) {
+                    const zc vn = sc * x;
+                    vout[off + p] = vn;
+                    if (bc) bc[off + p] = cvt<TB>(vn);
+                }
+            }
+        }
     }
-    __syncthreads();
-    if (!two)
-        for (int q = threadIdx.x; q <= j + 1; q += BLK) fs->R[q * M + j] = col[q];
+    if (two) {
+        // wavefront totals straight into the partials: value wv + NW k from
+        // wavefront wv, ||w1||^2 (value j + 1) from wavefront 0
+        double d[ND];
+#pragma unroll
+        for (int k = 0; k < ND / 2; ++k) {
+            const zc x = dots[k < NV ? k : 0];
+            d[2 * k] = k < NV ? x.re : 0.0;
+            d[2 * k + 1] = k < NV ? x.im : 0.0;
+        }
+        const double t = wave_totals<ND>(d);
+        const int idx = lane >> SH, k = idx >> 1;
+        zc *po = pout + (size_t)rhs * OVAL * NBMAX;
+        if ((lane & ((1 << SH) - 1)) == 0 && k < NV) {
+            int q = -1;
+            if (k < QW && k < nq) q = wv + NW * k;
+            if (k == QW && wv == 0) q = j + 1;
+            if (q >= 0) reinterpret_cast<double *>(po + (size_t)q * NBMAX + c)[idx & 1] = t;
+        }
+    }
+    if (blockIdx.x != 0) return;
+    proj0_state(fs, rep + rhs, stop ? stop + rhs : nullptr, j, cc, two);
 }
 
 // Second round of column j, finished and applied in one launch (columns
@@ -4348,19 +4482,37 @@ void launch_hdot_tile(const LvlK<double> &H, const Cx<TZ> *z, zc *w, const zc *V
                        ntile, active);
 }
 
+// the wavefront-split first round for columns of 17..64 vectors (CSG_PROJ0W=0:
+// the two-pass k_proj0 instead, for comparisons)
+static bool wide_proj0()
+{
+    static const bool on = [] {
+        const char *e = getenv("CSG_PROJ0W");
+        return !(e && atoi(e) == 0);
+    }();
+    return on;
+}
+
 template <typename TB>
 void launch_proj0(zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, FState *fs, Report *rep,
                   int *stop, const zc *pin, int nbin, zc *pout, zc *vout, Cx<TB> *bcast, const Launch &g,
                   const int *active)
 {
-    // columns of up to 16 basis vectors keep a point's whole basis in registers
-    // (more would spill)
+    // columns of up to 16 basis vectors keep a point's whole basis in one
+    // lane's registers (more would spill); longer ones split it over the
+    // block's wavefronts
     if (j + 1 <= 8)
         hipLaunchKernelGGL((k_proj0<TB, 8>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop, pin,
                            nbin, pout, vout, bcast, g.chunk, g.nb, active);
     else if (j + 1 <= 16)
         hipLaunchKernelGGL((k_proj0<TB, 16>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop, pin,
                            nbin, pout, vout, bcast, g.chunk, g.nb, active);
+    else if (j + 1 <= 4 * (BLK / 64) && wide_proj0())
+        hipLaunchKernelGGL((k_proj0w<TB, 4, 2>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop,
+                           pin, nbin, pout, vout, bcast, g.chunk, g.nb, active);
+    else if (j + 1 <= 8 * (BLK / 64) && wide_proj0())
+        hipLaunchKernelGGL((k_proj0w<TB, 8, 1>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop,
+                           pin, nbin, pout, vout, bcast, g.chunk, g.nb, active);
     else
         hipLaunchKernelGGL((k_proj0<TB, 0>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop, pin,
                            nbin, pout, vout, bcast, g.chunk, g.nb, active);

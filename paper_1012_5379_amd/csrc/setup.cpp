@@ -17,6 +17,12 @@
 
 namespace csg {
 
+std::complex<double> phi_shift(const csg_params &p)
+{
+    if (p.shift_re == 0.0 && p.shift_im == 0.0) return 1.0;
+    return {p.shift_re, p.shift_im};
+}
+
 int plan_levels(const csg_params &p, int &L, int nint[CSG_MAX_LEVELS][3], std::string &err)
 {
     if (p.dim != 2 && p.dim != 3) { err = "dim must be 2 or 3"; return CSG_EINVAL; }
@@ -37,6 +43,11 @@ int plan_levels(const csg_params &p, int &L, int nint[CSG_MAX_LEVELS][3], std::s
         return CSG_EINVAL;
     }
     if (p.slab_min < -1) { err = "slab_min must be >= -1"; return CSG_EINVAL; }
+    if (!std::isfinite(p.shift_re) || !std::isfinite(p.shift_im)) { err = "shift must be finite"; return CSG_EINVAL; }
+    if (p.smoother == 1 && !(p.shift_re == 0.0 && p.shift_im == 0.0) && !(p.shift_re == 1.0 && p.shift_im == 0.0)) {
+        err = "the polynomial smoother takes the unshifted preconditioner (shift 1)";
+        return CSG_EINVAL;
+    }
     int cur[3] = {0, 0, 0};
     for (int a = 0; a < p.dim; ++a) {
         if (p.n[a] < 1 || p.layer_lo[a] < 0 || p.layer_hi[a] < 0) {
@@ -300,6 +311,7 @@ int build_hierarchy(const csg_params &p, const double *phi, HostHier &hh, std::s
     }
     // dense coarsest matrix, assembled row by row from the tables
     const HostLevel &C = hh.lev[L - 1];
+    const cd shift = phi_shift(p);
     const int n = (int)C.N;
     hh.nc = n;
     std::vector<cd> A((size_t)n * n, cd(0.0));
@@ -308,7 +320,7 @@ int build_hierarchy(const csg_params &p, const double *phi, HostHier &hh, std::s
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 const long r = i + (long)nx * (j + (long)ny * k);
-                cd diag = C.tab[0][nx + i] - C.phi[r];
+                cd diag = C.tab[0][nx + i] - shift * C.phi[r];
                 if (i > 0) A[r * n + r - 1] += C.tab[0][i];
                 if (i < nx - 1) A[r * n + r + 1] += C.tab[0][2 * nx + i];
                 if (p.dim > 1) {

@@ -4,9 +4,9 @@ theta_beta = 10.3132 degrees, tolerance 1e-7, kh <= 0.625): Benchmark 1
 Gaussian model: Dirichlet on the south and west edges, layers on the north
 and east), complex128 throughout, against the FP64 oracle on the same inputs
 (iterations +-1, solution within 1e-10, or as close as the oracle is to
-itself under a rounding-size perturbation where the problem is that
-sensitive).  The counts are printed beside the
-paper's tables (ballpark only: layer width and restart are unstated)."""
+itself under rounding-size perturbations where the problem is that
+sensitive).  The counts are printed beside the paper's tables (ballpark
+only: layer width and restart are unstated)."""
 import json
 import os
 
@@ -22,13 +22,13 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 def _check(w, restart, printed):
     """Iterations +-1 and solutions within 1e-10, unless the oracle itself is
-    that sensitive: where a relative perturbation of 1e-15 in the right-hand
-    side moves the oracle's own solution and iteration count (the bound
-    states of Benchmark 3 at nu > 2.73 put isolated eigenvalues of H close to
-    zero, section 5), the GPU must agree with the oracle as closely as the
-    oracle agrees with itself under that perturbation (10x margin, +1
-    iteration).  The GPU solution's true residual is recomputed with the
-    oracle's H either way."""
+    that sensitive: where relative perturbations of 1e-15 in the right-hand
+    side move the oracle's own solution and iteration count (the bound states
+    of Benchmark 3 at nu > 2.73 put isolated eigenvalues of H close to zero,
+    section 5), the GPU must agree with the oracle as closely as the oracle
+    agrees with itself over six such perturbations (10x margin on the
+    solution, their iteration spread + 1).  The GPU solution's true residual
+    is recomputed with the oracle's H either way."""
     import numpy as np
     import torch
     torch_cuda()
@@ -44,13 +44,17 @@ def _check(w, restart, printed):
     assert rc == 0 and io.converged
     assert res <= w.tol * (1 + 1e-6)
     e_tol, it_tol = 1e-10, 1
-    if e > e_tol:
-        noise = np.random.default_rng(12345).standard_normal(chi.shape)
-        up, ip = orc.fgmres(chi * (1 + 1e-15 * noise), tol=w.tol, restart=restart, maxit=3000)
-        e_self = rel(up, uo)
-        note(f"    oracle self-sensitivity: sol {e_self:.2e}, its {ip.iterations}")
+    if e > e_tol or abs(infos[0]["iterations"] - io.iterations) > it_tol:
+        # the oracle's own spread over six rounding-size perturbations
+        spread, e_self = 0, 0.0
+        for seed in range(6):
+            noise = np.random.default_rng(12345 + seed).standard_normal(chi.shape)
+            up, ip = orc.fgmres(chi * (1 + 1e-15 * noise), tol=w.tol, restart=restart, maxit=3000)
+            spread = max(spread, abs(ip.iterations - io.iterations))
+            e_self = max(e_self, rel(up, uo))
+        note(f"    oracle self-sensitivity: sol {e_self:.2e}, iterations +-{spread}")
         e_tol = max(e_tol, 10 * e_self)
-        it_tol += abs(ip.iterations - io.iterations)
+        it_tol += spread
     assert abs(infos[0]["iterations"] - io.iterations) <= it_tol
     assert e <= e_tol
 
