@@ -116,6 +116,13 @@ typedef struct csg_params {
      * beta = 0 and s = e^{2i beta}.  H is never shifted.  Takes the GMRES(s)
      * smoother (smoother = 0). */
     double shift_re, shift_im;
+    /* coarse operators: 0 = rediscretisation on the coarser complex grid
+     * (section 3.1), 1 = Galerkin products M_{l+1} = R M_l P with the
+     * transfers of csg_residual_restrict / csg_prolong_correct (the section 5
+     * remark reports similar convergence), stored as 9- or 27-point stencils.
+     * Galerkin operators run every level on the unfused multi-block passes
+     * (no LDS tiles, slabs or coarse tail) and take the GMRES(s) smoother. */
+    int coarse_op;
 } csg_params;
 
 typedef struct csg_operator csg_operator;

@@ -30,7 +30,7 @@ class csg_params(C.Structure):
                 ("tail_max", C.c_int), ("fuse_max", C.c_int), ("graphs", C.c_int),
                 ("smoother", C.c_int), ("poly_k2", C.c_double),
                 ("slab_blocks", C.c_int), ("tile_mult", C.c_int), ("slab_min", C.c_int),
-                ("shift_re", C.c_double), ("shift_im", C.c_double)]
+                ("shift_re", C.c_double), ("shift_im", C.c_double), ("coarse_op", C.c_int)]
 
 
 class csg_solve_info(C.Structure):
@@ -116,7 +116,7 @@ def check(code: int) -> int:
 def make_params(dim=2, n=(64, 64, 0), h=1 / 64, layer_lo=(8, 8, 0), layer_hi=(8, 8, 0),
                 gamma=0.5235987755982988, beta=0.4, levels=0, s=3, nu1=1, nu2=1, cycle_prec=0,
                 max_rhs=1, restart=30, tail_max=0, fuse_max=0, graphs=0, smoother=0,
-                poly_k2=0.0, slab_blocks=0, tile_mult=0, slab_min=0, shift=0j) -> csg_params:
+                poly_k2=0.0, slab_blocks=0, tile_mult=0, slab_min=0, shift=0j, coarse_op=0) -> csg_params:
     p = csg_params()
     p.dim = int(dim)
     for a in range(3):
@@ -130,6 +130,7 @@ def make_params(dim=2, n=(64, 64, 0), h=1 / 64, layer_lo=(8, 8, 0), layer_hi=(8,
     p.smoother, p.poly_k2 = int(smoother), float(poly_k2)
     p.slab_blocks, p.tile_mult, p.slab_min = int(slab_blocks), int(tile_mult), int(slab_min)
     p.shift_re, p.shift_im = float(complex(shift).real), float(complex(shift).imag)
+    p.coarse_op = int(coarse_op)
     return p
 
 

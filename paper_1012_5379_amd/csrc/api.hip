@@ -186,6 +186,7 @@ void carve(csg_operator &op, const int nint[CSG_MAX_LEVELS][3], Carver &cv)
         for (int a = 0; a < p.dim; ++a) lv.tab[a] = cv.take((size_t)op.nprob * 3 * lv.nu[a] * cz);
         for (int a = p.dim; a < 3; ++a) lv.tab[a] = nullptr;
         lv.phi = cv.take((size_t)op.nprob * lv.N * cr);
+        lv.gst = p.coarse_op == 1 && l > 0 ? cv.take((size_t)op.nprob * (p.dim == 2 ? 9 : 27) * lv.N * cz) : nullptr;
         const size_t vb = (size_t)R * lv.N * cz;
         lv.b = cv.take(vb);
         lv.xa = cv.take(vb);
@@ -244,6 +245,8 @@ LvlK<T> lvl(const csg_operator *op, int l)
     const cd sh = phi_shift(op->p);
     L.sre = sh.real();
     L.sim = sh.imag();
+    L.gst = (const Cx<T> *)d.gst;
+    L.gstride = (size_t)(op->p.dim == 2 ? 9 : 27) * d.N;
     return L;
 }
 
@@ -1153,7 +1156,7 @@ bool same_class(const csg_params &a, const csg_params &b)
               a.cycle_prec == b.cycle_prec && a.max_rhs == b.max_rhs && a.restart == b.restart &&
               a.tail_max == b.tail_max && a.fuse_max == b.fuse_max && a.graphs == b.graphs &&
               a.smoother == b.smoother && a.slab_blocks == b.slab_blocks && a.tile_mult == b.tile_mult &&
-              a.slab_min == b.slab_min && phi_shift(a) == phi_shift(b);
+              a.slab_min == b.slab_min && phi_shift(a) == phi_shift(b) && a.coarse_op == b.coarse_op;
     for (int d = 0; d < a.dim; ++d)
         eq = eq && a.n[d] == b.n[d] && a.layer_lo[d] == b.layer_lo[d] && a.layer_hi[d] == b.layer_hi[d];
     return eq;
@@ -1297,6 +1300,23 @@ int create_impl(const csg_params *const *ps, const double *const *phis, int P, v
                                hipMemcpyHostToDevice, s) != hipSuccess)
                 rc = CSG_EDEVICE;
             keep.push_back(std::move(ph));
+            if (op->lev[l].gst) {
+                // Galerkin stencil in the cycle precision, problem q after problem q-1
+                std::vector<char> gs(hl.gst.size() * cz);
+                for (size_t k = 0; k < hl.gst.size(); ++k) {
+                    if (mixed) {
+                        ((float *)gs.data())[2 * k] = (float)hl.gst[k].real();
+                        ((float *)gs.data())[2 * k + 1] = (float)hl.gst[k].imag();
+                    } else {
+                        ((double *)gs.data())[2 * k] = hl.gst[k].real();
+                        ((double *)gs.data())[2 * k + 1] = hl.gst[k].imag();
+                    }
+                }
+                if (hipMemcpyAsync((char *)op->lev[l].gst + (size_t)q * gs.size(), gs.data(), gs.size(),
+                                   hipMemcpyHostToDevice, s) != hipSuccess)
+                    rc = CSG_EDEVICE;
+                keep.push_back(std::move(gs));
+            }
         }
         if (hipMemsetAsync(op->lev[l].gs, 0, R * sizeof(GState), s) != hipSuccess) rc = CSG_EDEVICE;
         for (int k = 0; k < 2; ++k)
@@ -1338,6 +1358,13 @@ int create_impl(const csg_params *const *ps, const double *const *phis, int P, v
             if (atoi(e) == 0) op->slab_min = -1;
         if (p->slab_min) op->slab_min = p->slab_min;
         if (op->slab_min < 0) op->slab_min = (long)1 << 62;
+        if (p->coarse_op == 1) {
+            // Galerkin levels: only the multi-block passes take a stored stencil
+            op->tiles = false;
+            op->slab_min = (long)1 << 62;
+            op->fuse_max = 0;
+            tail_max = 0;
+        }
         for (int l = 0; l < op->L; ++l) {
             op->lev[l].varphi = hh.lev[l].varphi;
             op->lev[l].conds = hh.lev[l].conds;

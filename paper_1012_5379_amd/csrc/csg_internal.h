@@ -89,6 +89,10 @@ struct HostLevel {
     std::vector<cd> z[3];      // nested complex node coordinates of M's grid
     std::vector<cd> tab[3];    // Shortley-Weller rows of M: [west | centre | east]
     std::vector<double> phi;
+    // Galerkin coarse operator R M_{l-1} P (coarse_op = 1, levels >= 1): 3^d
+    // coefficients per unknown, [offset][unknown], offset index
+    // sum_a (o_a + 1) 3^a over the used axes; 0 towards neighbours outside the grid
+    std::vector<cd> gst;
     // third-order polynomial smoother of this level (section 4)
     double varphi = 0.0;
     cd omega[3];
@@ -169,6 +173,7 @@ struct DevLevel {
     size_t ld;                 // elements between consecutive RHS vectors
     const void *tab[3];        // cycle-precision complex tables (boundary weights zeroed)
     const void *phi;           // cycle-precision real phi
+    const void *gst;           // Galerkin levels: cycle-precision 3^d-point stencil per problem (else null)
     void *b, *xa, *xb, *r;     // cycle-precision vectors [max_rhs][ld]
     void *u[CSG_MAX_S + 1];    // u[1..s]; u[0] aliases b or r
     void *w[2];                // stencil outputs of the Arnoldi passes (ping-pong)

@@ -22,6 +22,11 @@ struct LvlK {
     // centre weights - s phi): 1 for H and the CSG preconditioner, 1 + i eps
     // for the complex shifted Laplacian
     double sre = 1.0, sim = 0.0;
+    // Galerkin levels: 3^d coefficients per point, [offset][point] (offset
+    // index sum_a (o_a + 1) 3^a), zero towards neighbours outside the grid;
+    // gstride elements between problems.  Null: the Kronecker-sum form above.
+    const Cx<T> *gst = nullptr;
+    size_t gstride = 0;
     // the geometry as right-hand side rhs sees it
     __host__ __device__ __forceinline__ LvlK at(int rhs) const
     {
@@ -31,6 +36,7 @@ struct LvlK {
             for (int a = 0; a < 3; ++a)
                 if (r.tab[a]) r.tab[a] += (size_t)q * tstride[a];
             r.phi += q * pstride;
+            if (r.gst) r.gst += q * gstride;
         }
         return r;
     }

@@ -51,13 +51,38 @@ __device__ __forceinline__ void sub_phi(Cx<T> &d, const LvlK<T> &K, T ph)
     d.im -= (T)K.sim * ph;
 }
 
+// (A x)_p for a Galerkin level's stored stencil (neighbours outside the grid
+// have coefficient 0; their loads are clamped to p).
+template <typename T, int DIM, typename TI>
+__device__ __forceinline__ Cx<T> apply_gal(const LvlK<T> &L, const Cx<TI> *__restrict__ x, unsigned i, unsigned j,
+                                           unsigned k, unsigned p)
+{
+    Cx<T> acc = mkc(T(0), T(0));
+    const unsigned sz = L.nx * L.ny;
+#pragma unroll
+    for (int oz = (DIM == 3 ? -1 : 0); oz <= (DIM == 3 ? 1 : 0); ++oz)
+#pragma unroll
+        for (int oy = -1; oy <= 1; ++oy)
+#pragma unroll
+            for (int ox = -1; ox <= 1; ++ox) {
+                const int oi = (ox + 1) + 3 * (oy + 1) + (DIM == 3 ? 9 * (oz + 1) : 0);
+                const bool in = (ox >= 0 || i > 0) && (ox <= 0 || i + 1 < L.nx) && (oy >= 0 || j > 0) &&
+                                (oy <= 0 || j + 1 < L.ny) && (oz >= 0 || k > 0) && (oz <= 0 || k + 1 < L.nz);
+                const unsigned q = in ? (unsigned)((int)p + ox + oy * (int)L.nx + oz * (int)sz) : p;
+                acc = cfma(L.gst[(size_t)oi * L.N + p], cvt<T>(x[q]), acc);
+            }
+    return acc;
+}
+
 // (A x)_p for the Kronecker-sum operator: per axis west/centre/east weights,
 // diagonal minus phi.  Boundary weights are zero in the tables, so the clamped
-// neighbour index only keeps the load in range.
+// neighbour index only keeps the load in range.  Galerkin levels take the
+// stored stencil instead.
 template <typename T, int DIM, typename TI>
 __device__ __forceinline__ Cx<T> apply_pt(const LvlK<T> &L, const Cx<TI> *__restrict__ x, unsigned i, unsigned j,
                                           unsigned k, unsigned p)
 {
+    if (L.gst) return apply_gal<T, DIM>(L, x, i, j, k, p);
     const Cx<T> *tx = L.tab[0];
     Cx<T> d = tx[L.nx + i];
     if (DIM >= 2) d = d + L.tab[1][L.ny + j];

@@ -44,6 +44,11 @@ int plan_levels(const csg_params &p, int &L, int nint[CSG_MAX_LEVELS][3], std::s
     }
     if (p.slab_min < -1) { err = "slab_min must be >= -1"; return CSG_EINVAL; }
     if (!std::isfinite(p.shift_re) || !std::isfinite(p.shift_im)) { err = "shift must be finite"; return CSG_EINVAL; }
+    if (p.coarse_op != 0 && p.coarse_op != 1) { err = "coarse_op must be 0 (rediscretised) or 1 (Galerkin)"; return CSG_EINVAL; }
+    if (p.smoother == 1 && p.coarse_op != 0) {
+        err = "the polynomial smoother takes rediscretised coarse operators";
+        return CSG_EINVAL;
+    }
     if (p.smoother == 1 && !(p.shift_re == 0.0 && p.shift_im == 0.0) && !(p.shift_re == 1.0 && p.shift_im == 0.0)) {
         err = "the polynomial smoother takes the unshifted preconditioner (shift 1)";
         return CSG_EINVAL;
@@ -245,6 +250,98 @@ void poly_level(int dim, double beta, double gamma, double k2, double H, HostLev
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Galerkin coarse operators (section 5 remark)
+
+namespace {
+
+// Entry (p, p + o) of level F's operator, o in {-1, 0, 1}^d (0 when p + o lies
+// outside the grid): the Kronecker-sum rows with s phi on the diagonal, or a
+// Galerkin level's stored stencil.
+cd op_entry(const HostLevel &F, int dim, cd shift, const int i[3], const int o[3])
+{
+    for (int a = 0; a < 3; ++a)
+        if (i[a] + o[a] < 0 || i[a] + o[a] >= F.nu[a]) return 0.0;
+    const long p = i[0] + (long)F.nu[0] * (i[1] + (long)F.nu[1] * i[2]);
+    if (!F.gst.empty()) {
+        int oi = 0, m = 1;
+        for (int a = 0; a < dim; ++a, m *= 3) oi += (o[a] + 1) * m;
+        return F.gst[(size_t)oi * F.N + p];
+    }
+    int moved = 0, ax = 0;
+    for (int a = 0; a < dim; ++a)
+        if (o[a]) { ++moved; ax = a; }
+    if (moved > 1) return 0.0;
+    if (moved == 0) {
+        cd d = -shift * F.phi[p];
+        for (int a = 0; a < dim; ++a) d += F.tab[a][F.nu[a] + i[a]];
+        return d;
+    }
+    const int n = F.nu[ax];
+    return o[ax] < 0 ? F.tab[ax][i[ax]] : F.tab[ax][2 * n + i[ax]];
+}
+
+// Linear interpolation weight of coarse unknown J at fine unknown f on one
+// axis: coarse unknown J is fine unknown 2J + 1 (weight 1), its fine
+// neighbours take 1/2.
+double lin_w(int f, int J)
+{
+    const int c = 2 * J + 1;
+    return f == c ? 1.0 : (f == c - 1 || f == c + 1) ? 0.5 : 0.0;
+}
+
+// C.gst = R M_F P, entry by entry: for coarse unknown K and each fine unknown i
+// that R_K weighs (2^{-d} times the interpolation weights), each fine neighbour
+// i' of i in M_F, and each coarse unknown J within one of K that P spreads onto
+// i', accumulate R_{K,i} (M_F)_{i,i'} P_{i',J} into offset J - K.
+void galerkin_level(const HostLevel &F, HostLevel &C, int dim, cd shift)
+{
+    const int np = dim == 2 ? 9 : 27;
+    C.gst.assign((size_t)np * C.N, cd(0.0));
+    const double rs = std::ldexp(1.0, -dim);
+    const int r1[3] = {1, dim > 1 ? 1 : 0, dim > 2 ? 1 : 0};   // offset range per axis
+    for (int K2 = 0; K2 < C.nu[2]; ++K2)
+        for (int K1 = 0; K1 < C.nu[1]; ++K1)
+            for (int K0 = 0; K0 < C.nu[0]; ++K0) {
+                const int K[3] = {K0, K1, K2};
+                const long pk = K0 + (long)C.nu[0] * (K1 + (long)C.nu[1] * K2);
+                int i[3], o[3], jj[3], ip[3];
+                for (i[2] = 2 * K[2] + 1 - r1[2]; i[2] <= 2 * K[2] + 1 + r1[2]; ++i[2])
+                    for (i[1] = 2 * K[1] + 1 - r1[1]; i[1] <= 2 * K[1] + 1 + r1[1]; ++i[1])
+                        for (i[0] = 2 * K[0] + 1 - 1; i[0] <= 2 * K[0] + 1 + 1; ++i[0]) {
+                            const int fi[3] = {i[0], dim > 1 ? i[1] : 0, dim > 2 ? i[2] : 0};
+                            bool in = true;
+                            double r = rs;
+                            for (int a = 0; a < dim; ++a) {
+                                in = in && fi[a] >= 0 && fi[a] < F.nu[a];
+                                r *= lin_w(fi[a], K[a]);
+                            }
+                            if (!in || r == 0.0) continue;
+                            for (o[2] = -r1[2]; o[2] <= r1[2]; ++o[2])
+                                for (o[1] = -r1[1]; o[1] <= r1[1]; ++o[1])
+                                    for (o[0] = -1; o[0] <= 1; ++o[0]) {
+                                        const cd aij = op_entry(F, dim, shift, fi, o);
+                                        if (aij == cd(0.0)) continue;
+                                        for (int a = 0; a < 3; ++a) ip[a] = fi[a] + o[a];
+                                        for (jj[2] = -r1[2]; jj[2] <= r1[2]; ++jj[2])
+                                            for (jj[1] = -r1[1]; jj[1] <= r1[1]; ++jj[1])
+                                                for (jj[0] = -1; jj[0] <= 1; ++jj[0]) {
+                                                    double w = 1.0;
+                                                    int oi = 0, m = 1;
+                                                    for (int a = 0; a < dim; ++a, m *= 3) {
+                                                        const int J = K[a] + jj[a];
+                                                        w *= (J >= 0 && J < C.nu[a]) ? lin_w(ip[a], J) : 0.0;
+                                                        oi += (jj[a] + 1) * m;
+                                                    }
+                                                    if (w != 0.0) C.gst[(size_t)oi * C.N + pk] += r * aij * w;
+                                                }
+                                    }
+                        }
+            }
+}
+
+}  // namespace
+
 int build_hierarchy(const csg_params &p, const double *phi, HostHier &hh, std::string &err)
 {
     int nint[CSG_MAX_LEVELS][3];
@@ -298,6 +395,8 @@ int build_hierarchy(const csg_params &p, const double *phi, HostHier &hh, std::s
         fine_nodes(p, a, 0.0, zH);
         sw_rows(zH, hh.tabH[a]);
     }
+    if (p.coarse_op == 1)
+        for (int l = 1; l < L; ++l) galerkin_level(hh.lev[l - 1], hh.lev[l], p.dim, phi_shift(p));
     {
         // polynomial smoothers; k^2 of the vertex t0: given, else the mean of phi
         double k2 = p.poly_k2;
@@ -316,7 +415,23 @@ int build_hierarchy(const csg_params &p, const double *phi, HostHier &hh, std::s
     hh.nc = n;
     std::vector<cd> A((size_t)n * n, cd(0.0));
     const int nx = C.nu[0], ny = C.nu[1], nz = C.nu[2];
-    for (int k = 0; k < nz; ++k)
+    if (!C.gst.empty()) {
+        // Galerkin: row r from the stored stencil
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    const int ii[3] = {i, j, k};
+                    const long r = i + (long)nx * (j + (long)ny * k);
+                    int o[3];
+                    for (o[2] = p.dim > 2 ? -1 : 0; o[2] <= (p.dim > 2 ? 1 : 0); ++o[2])
+                        for (o[1] = -1; o[1] <= 1; ++o[1])
+                            for (o[0] = -1; o[0] <= 1; ++o[0]) {
+                                const cd v = op_entry(C, p.dim, shift, ii, o);
+                                if (v != cd(0.0)) A[r * n + r + o[0] + (long)nx * (o[1] + (long)ny * o[2])] += v;
+                            }
+                }
+    }
+    for (int k = 0; k < nz && C.gst.empty(); ++k)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
                 const long r = i + (long)nx * (j + (long)ny * k);
