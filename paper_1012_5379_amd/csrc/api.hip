@@ -216,7 +216,7 @@ void carve(csg_operator &op, const int nint[CSG_MAX_LEVELS][3], Carver &cv)
     op.opart2 = (zc *)cv.take((size_t)R * OVAL * NBMAX * sizeof(zc));
     op.fs = (FState *)cv.take((size_t)R * sizeof(FState));
     op.active = (int *)cv.take((size_t)3 * R * sizeof(int));
-    op.ones = op.active + 2 * R;
+    op.ones = op.active ? op.active + 2 * R : nullptr;   // (no arithmetic on the dry run's null)
 }
 
 int cyc_mask_offset(const csg_operator *op) { return op->p.max_rhs; }
