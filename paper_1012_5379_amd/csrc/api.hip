@@ -893,9 +893,14 @@ void enqueue_begin(csg_solve *sv, bool with_chi_norm)
 // One FGMRES iteration (section 5): z_j = V(v_j), w = H z_j, classical
 // Gram-Schmidt against v_0..v_j with ||w||^2 summed alongside, so
 // h_{j+1,j}^2 = ||w||^2 - ||h||^2 is known before the projection.  When the
-// projection keeps at least 1% of ||w|| one round is final and the first
-// projection writes v_{j+1}; otherwise a second round (dots, finish with
-// h_{j+1,j} from ||w1||^2 - ||c||^2, second projection) restores orthogonality.
+// projection keeps at least 1/sqrt(2) of ||w|| one round is final and the
+// first projection writes v_{j+1}; otherwise a second round (its inner
+// products formed by the first projection, h_{j+1,j} from ||w1||^2 - ||c||^2)
+// restores orthogonality.  Lazy (default): the first projection writes the
+// first-round form v~_{j+1}, which the next V-cycle takes as its input, k_col
+// finishes the column, and the next first projection replaces v~_{j+1} by
+// v_{j+1} while it reads the basis anyway, so a second round costs no pass
+// over V of its own.  Otherwise k_proj1 applies the second round at once.
 // Givens update on the device either way.
 template <typename TZ, int DIM>
 void iter_body(csg_solve *sv, int j, hipStream_t st)
@@ -921,10 +926,18 @@ void iter_body(csg_solve *sv, int j, hipStream_t st)
         // FGMRES state) when the first round is final, and the second-round
         // passes below then return at once; otherwise keeps w_1 and forms the
         // second round's inner products in the same launch
-        ProfScope ps(op, CSG_PROF_OUTER_CGS1, st, R * N * (16.0 * (j + 3) + (op->p.cycle_prec ? 8.0 : 0.0)));
+        ProfScope ps(op, CSG_PROF_OUTER_CGS1, st,
+                     R * N * (16.0 * (j + 3) + (op->p.cycle_prec ? 8.0 : 0.0) + (op->lazy && j > 0 ? 16.0 : 0.0)));
         launch_proj0<TZ>(op->w, op->V, vstride, j, f.N, f.ld, op->fs, report_slot(op, j % LOOKAHEAD), op->active,
                          op->opart, hdot_tiled<DIM>(op) ? (int)(f.tile.ntx * f.tile.nty) : f.nb, op->opart2, op->V + (j + 1) * vstride,
-                         op->p.cycle_prec ? (Cx<TZ> *)op->b0 : nullptr, g, mask);
+                         op->p.cycle_prec ? (Cx<TZ> *)op->b0 : nullptr, op->V + j * vstride, op->lazy ? 1 : 0, g,
+                         mask);
+    }
+    if (op->lazy) {
+        // the column's finish (its second round's vector update waits for the next first projection)
+        ProfScope ps(op, CSG_PROF_OUTER_PROJ2, st, 0.0);
+        launch_col(j, op->fs, report_slot(op, j % LOOKAHEAD), op->active, op->opart2, f.nb, sv->nrhs, st, mask);
+        return;
     }
     ProfScope ps(op, CSG_PROF_OUTER_PROJ2, st, R * N * (16.0 * (j + 3) + (op->p.cycle_prec ? 8.0 : 0.0)));
     launch_proj1<TZ>(op->w, op->V, vstride, j, f.N, f.ld, op->fs, report_slot(op, j % LOOKAHEAD), op->active,
@@ -1350,6 +1363,12 @@ int create_impl(const csg_params *const *ps, const double *const *phis, int P, v
         if (const char *e = getenv("CSG_FUSE_UPD")) op->fuse_upd = atoi(e) != 0;
         op->force_cgs2 = false;
         if (const char *e = getenv("CSG_FORCE_CGS2")) op->force_cgs2 = atoi(e) != 0;
+        // deferred second rounds need the register or wavefront-split first
+        // projection (CSG_PROJ0W=0 selects the two-pass one for long columns)
+        op->lazy = true;
+        if (const char *e = getenv("CSG_LAZY")) op->lazy = atoi(e) != 0;
+        if (const char *e = getenv("CSG_PROJ0W"))
+            if (atoi(e) == 0) op->lazy = false;
         op->poly_tiles = true;
         if (const char *e = getenv("CSG_POLY_TILES")) op->poly_tiles = atoi(e) != 0;
         op->slab_min = 100000;

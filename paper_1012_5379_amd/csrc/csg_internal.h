@@ -47,7 +47,7 @@ struct FState {
     zc sn[CSG_MAX_RESTART];
     zc g[CSG_MAX_RESTART + 1];
     zc hcol[CSG_MAX_RESTART + 1];   // current column (first + second CGS round)
-    zc corr[CSG_MAX_RESTART + 1];   // second-round coefficients of the current column
+    zc corr[CSG_MAX_RESTART + 1];   // second-round coefficients of the current column (lazy: scaled by sc1)
     zc y[CSG_MAX_RESTART];
     double beta;       // norm of the current restart residual
     double nchi;       // ||chi||
@@ -61,6 +61,12 @@ struct FState {
     int maxit;         // iteration limit of the solve
     int force2;        // every column takes the second Gram-Schmidt round (experiments, tests)
     int pad;
+    // deferred second rounds: scale of the first-round form v~_{j+1} = sc1 w1,
+    // and, when pend, v_j = gpend (v~_j - sum_{i<j} corr_i v_i)
+    double sc1;
+    double gpend;
+    int pend;
+    int pad2;
 };
 
 // Outer iterations a solve keeps queued ahead of the host's reading of their
@@ -229,6 +235,7 @@ struct csg_operator {
     bool down_tiles;                  // ... and the LDS-staged closing + restriction + next pass 0
     bool fuse_upd;                    // coarse post-sweep updates applied by the finer up-path pass
     bool force_cgs2;                  // every outer column takes the second Gram-Schmidt round
+    bool lazy;                        // second rounds deferred into the next first projection
     bool poly_tiles;                  // polynomial sweeps of 2-D levels run as one tiled launch
     long slab_min;                    // 3-D levels from this size run the Arnoldi passes on z-marching slabs
     // outer FGMRES storage

@@ -227,8 +227,11 @@ void launch_hdot_tile(const LvlK<double> &H, const Cx<TZ> *z, zc *w, const zc *V
 // step, report, stop test clearing stop[rhs]) for a final column
 template <typename TB>
 void launch_proj0(zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, FState *fs, Report *rep,
-                  int *stop, const zc *pin, int nbin, zc *pout, zc *vout, Cx<TB> *bcast, const Launch &g,
-                  const int *active);
+                  int *stop, const zc *pin, int nbin, zc *pout, zc *vout, Cx<TB> *bcast, zc *vfix, int lazy,
+                  const Launch &g, const int *active);
+// finish of a column whose second Gram-Schmidt round is deferred (lazy)
+void launch_col(int j, FState *fs, Report *rep, int *stop, const zc *pin, int nbin, int nrhs, hipStream_t st,
+                const int *active);
 
 // second round of column j (columns that take it): the second-round inner
 // products summed from their partials (pin) in every block, v_{j+1} = (w1 -

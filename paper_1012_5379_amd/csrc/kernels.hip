@@ -4124,17 +4124,32 @@ void launch_coarse(const Cx<T> *minvT, int n, const Cx<T> *b, Cx<T> *x, size_t l
 // Shared start of the first-round kernels: sum the inner products of k_hdot
 // (h_i = <v_i, w>, i <= j, and ||w||^2) from the RHS's partials pp into cc
 // (group_parts: a fixed order, so every block gets the same bits) and take
-// the block-uniform decision: twos = 1 when a second round is needed, else
-// scs = 1 / ||w1|| for the final column.
-__device__ __forceinline__ void proj0_head(const FState *fs, int j, const zc *pp, int nbin, zc *cc, double &scs,
-                                           int &twos)
+// the block-uniform decision: twos = 1 when a second round is needed.
+// Deferred second rounds (lazy): when column j - 1 took a second round, v_j
+// holds its first-round form v~_j and the coefficients c~ and scale g of
+// v_j = g (v~_j - sum_{i<j} c~_i v_i) sit in the FGMRES state (pends = 1,
+// ccor, gps); <v_j, w> then follows from the inner products already formed.
+// scs scales the first round's result into v_{j+1} (final column) or into the
+// next first-round form v~_{j+1} (second round pending; any positive scale
+// serves, 1/||w1|| when the estimate ||w||^2 - ||h||^2 is usable).
+__device__ __forceinline__ void proj0_head(const FState *fs, int j, const zc *pp, int nbin, bool lazy, zc *cc,
+                                           zc *ccor, double &scs, double &gps, int &twos, int &pends)
 {
+    const bool pend = lazy && j > 0 && fs->pend;
     for (int q = threadIdx.x / FG; q <= j + 1; q += BLK / FG) {
         const zc v = group_parts(pp + q * NBMAX, nbin);
         if (threadIdx.x % FG == 0) cc[q] = v;
     }
+    if (pend)
+        for (int q = threadIdx.x; q < j; q += BLK) ccor[q] = fs->corr[q];
     __syncthreads();
     if (threadIdx.x == 0) {
+        const double gp = pend ? fs->gpend : 0.0;
+        if (pend) {
+            zc t = mkc(0.0, 0.0);
+            for (int q = 0; q < j; ++q) t = cjfma(ccor[q], cc[q], t);
+            cc[j] = gp * (cc[j] - t);
+        }
         const double w2 = cc[j + 1].re;
         double h2 = 0.0;
         for (int q = 0; q <= j; ++q) h2 += cabs2(cc[q]);
@@ -4144,9 +4159,13 @@ __device__ __forceinline__ void proj0_head(const FState *fs, int j, const zc *pp
         // the single round (ratio ||h|| / ||w1|| times the basis's own loss of
         // orthogonality) compound from column to column
         const int two = fs->force2 || !(w1 >= 0.5 * w2);   // force2: every column, for tests
-        const double hn = sqrt(w1);
+        double sc;
+        if (!two) sc = w1 > 0.0 ? 1.0 / sqrt(w1) : 0.0;
+        else sc = w1 > 1e-8 * w2 ? 1.0 / sqrt(w1) : (w2 > 0.0 ? 1.0 / sqrt(w2) : 0.0);
         twos = two;
-        scs = hn > 0.0 ? 1.0 / hn : 0.0;
+        scs = sc;
+        gps = gp;
+        pends = pend;
     }
     __syncthreads();
 }
@@ -4154,7 +4173,8 @@ __device__ __forceinline__ void proj0_head(const FState *fs, int j, const zc *pp
 // Shared end of the first-round kernels (block 0): the FGMRES state advances
 // by the column h, the flag of the second round and, for a final column, the
 // Givens step, the report and the stop test.
-__device__ __forceinline__ void proj0_state(FState *fs, Report *rep, int *stop, int j, const zc *cc, bool two)
+__device__ __forceinline__ void proj0_state(FState *fs, Report *rep, int *stop, int j, const zc *cc, bool two,
+                                            double sc)
 {
     constexpr int M = CSG_MAX_RESTART;
     __shared__ zc col[OVAL];
@@ -4175,6 +4195,7 @@ __device__ __forceinline__ void proj0_state(FState *fs, Report *rep, int *stop, 
         for (int q = 0; q <= j; ++q) h2 += cabs2(cc[q]);
         fs->w2 = w2;
         fs->reorth = two;
+        fs->sc1 = sc;
         if (!two) givens_column(fs, rep, j, sqrt(w2 - h2), col, cs_s, sn_s, stop);
     }
     __syncthreads();
@@ -4183,45 +4204,49 @@ __device__ __forceinline__ void proj0_state(FState *fs, Report *rep, int *stop, 
 }
 
 // First round of column j, finished and applied in one launch.  Every block
-// sums the inner products of k_hdot (h_i = <v_i, w>, i <= j, and ||w||^2) from
-// their partials (group_parts: a fixed order, so every block gets the same
-// bits) and takes the same decision: with ||w1||^2 = ||w||^2 - ||h||^2 (w1 = w - V h, V orthonormal)
-// the column is final when ||w1||^2 >= ||w||^2 / 2; then h_{j+1,j} = ||w1|| and the block writes its chunk
-// of v_{j+1} = w1 / h_{j+1,j} and its optional cycle-precision copy.
-// Otherwise it keeps w1 in w and writes the second round's partials into
+// sums the inner products of k_hdot (proj0_head) and takes the same decision:
+// with ||w1||^2 = ||w||^2 - ||h||^2 (w1 = w - V h, V orthonormal) the column is
+// final when ||w1||^2 >= ||w||^2 / 2; then h_{j+1,j} = ||w1|| and the block
+// writes its chunk of v_{j+1} = w1 / h_{j+1,j} and its optional
+// cycle-precision copy.  Otherwise it writes the second round's partials into
 // pout (a buffer apart from pin, which other blocks may still be reading):
-// <v_i, w1> (values 0..j, a second pass over the block's chunk) and ||w1||^2
-// (value j+1).  Block 0 then advances the FGMRES state: the column h, the
-// flag of the second round and, for a final column,
-// the Givens step, the report and the stop test (stop clears the RHS in the
-// mask; blocks that read the mask after that skip their chunk of a v_{j+1}
-// that is never used).
+// <v_i, w1> (values 0..j) and ||w1||^2 (value j + 1), and either keeps w1 in w
+// for k_proj1 or (lazy) writes the first-round form v~_{j+1} = scs w1 into
+// v_{j+1}'s place and the copy: the V-cycle takes v~_{j+1} (flexible GMRES
+// accepts any preconditioner input), k_col finishes the column, and the next
+// column's first projection, which reads the whole basis anyway, replaces
+// v~_{j+1} by v_{j+1} (vfix = v_j's place; pending form, see proj0_head).
+// Block 0 then advances the FGMRES state: the column h, the flag of the
+// second round and, for a final column, the Givens step, the report and the
+// stop test (stop clears the RHS in the mask; blocks that read the mask after
+// that skip their chunk of a v_{j+1} that is never used).
 template <typename TB, int JB>
 __global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__restrict__ V, size_t vstride, int j,
                                                unsigned N, size_t ld, FState *fsb, Report *rep, int *stop,
                                                const zc *__restrict__ pin, int nbin, zc *__restrict__ pout,
-                                               zc *__restrict__ vout, Cx<TB> *__restrict__ bc, unsigned chunk,
-                                               int nb, const int *active)
+                                               zc *__restrict__ vout, Cx<TB> *__restrict__ bc, zc *vfix, int lazy,
+                                               unsigned chunk, int nb, const int *active)
 {
     __shared__ zc sh[(BLK / 64) * 8];
     __shared__ zc res[8];
     __shared__ zc cc[OVAL];
-    __shared__ double scs;
-    __shared__ int twos;
+    __shared__ zc ccor[OVAL];
+    __shared__ double scs, gps;
+    __shared__ int twos, pends;
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
     FState *fs = fsb + rhs;
-    proj0_head(fs, j, pin + (size_t)rhs * OVAL * NBMAX, nbin, cc, scs, twos);
-    const bool two = twos != 0;
-    const double sc = scs;
+    proj0_head(fs, j, pin + (size_t)rhs * OVAL * NBMAX, nbin, lazy != 0 && JB > 0, cc, ccor, scs, gps, twos, pends);
+    const bool two = twos != 0, pend = pends != 0;
+    const double sc = scs, gp = gps;
     const size_t off = rhs * ld;
     zc acc[1] = {mkc(0.0, 0.0)};
     const unsigned c = chunk_id(nb);
     const unsigned p0 = c * chunk + threadIdx.x, p1 = min(N, c * chunk + chunk);
     if (JB > 0) {
-        // every basis value of a point held in registers: the first projection
-        // and, for a second round, its inner products <v_i, w_1> in one pass
-        // over V (j + 1 <= JB)
+        // every basis value of a point held in registers: the pending
+        // correction of v_j, the first projection and, for a second round, its
+        // inner products <v_i, w1> in one pass over V (j + 1 <= JB)
         zc dots[JB > 0 ? JB : 1];
 #pragma unroll
         for (int q = 0; q < JB; ++q) dots[q] = mkc(0.0, 0.0);
@@ -4229,13 +4254,31 @@ __global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__r
             zc v[JB > 0 ? JB : 1];
 #pragma unroll
             for (int q = 0; q < JB; ++q)
-                if (q <= j) v[q] = V[q * vstride + off + p];
+                if (q <= j) v[q] = pend && q == j ? vfix[off + p] : V[q * vstride + off + p];
+            if (pend) {
+                zc t = mkc(0.0, 0.0);
+#pragma unroll
+                for (int q = 0; q < JB; ++q)
+                    if (q < j) t = cfma(ccor[q], v[q], t);
+#pragma unroll
+                for (int q = 0; q < JB; ++q)
+                    if (q == j) {
+                        v[q] = gp * (v[q] - t);
+                        vfix[off + p] = v[q];
+                    }
+            }
             zc x = w[off + p];
 #pragma unroll
             for (int q = 0; q < JB; ++q)
                 if (q <= j) x = x - cc[q] * v[q];
             if (two) {
-                w[off + p] = x;
+                if (lazy) {
+                    const zc vn = sc * x;
+                    vout[off + p] = vn;
+                    if (bc) bc[off + p] = cvt<TB>(vn);
+                } else {
+                    w[off + p] = x;
+                }
                 acc[0].re += cabs2(x);
 #pragma unroll
                 for (int q = 0; q < JB; ++q)
@@ -4260,6 +4303,7 @@ __global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__r
             }
         }
     } else if (p0 < p1) {
+        // (not lazy: the host keeps k_proj1 for this path)
         const unsigned last = p1 - 1;
         for (unsigned p = p0; p < p1; p += UO * BLK) {
             zc x[UO];
@@ -4293,44 +4337,50 @@ __global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__r
         }
     }
     if (blockIdx.x != 0) return;
-    proj0_state(fs, rep + rhs, stop ? stop + rhs : nullptr, j, cc, two);
+    proj0_state(fs, rep + rhs, stop ? stop + rhs : nullptr, j, cc, two, sc);
 }
 
-// k_proj0 for columns of more than 16 basis vectors, reading V once: the
+// k_proj0 for columns of more than 8 basis vectors, reading V once: the
 // basis is split over the block's wavefronts (wavefront wv holds v_q for
 // q = wv, wv + NW, ..., QW of them at most) and every lane takes PU points per
 // step, so a point's basis values sit in the registers of NW lanes.  Each
-// wavefront forms its share of (V c)(p) in ascending q; the shares meet in
-// shared memory and every wavefront sums them in wavefront order, so all form
-// the same w1(p) = w(p) - sum; wavefront 0 stores it (or, for a final column,
-// v_{j+1} and its copy), and for a second round each wavefront accumulates the
-// inner products <v_q, w1> of its own vectors and wavefront 0 also ||w1||^2.
-// The shares are double-buffered, so one barrier per step suffices.
+// wavefront forms its shares of (V h)(p) and, for a pending v_j, of
+// (sum_{i<j} c~_i v_i)(p), in ascending q; the shares meet in shared memory
+// with w(p) and v~_j(p), and every wavefront sums them in wavefront order, so
+// all form the same v_j(p) and w1(p) = w(p) - sum.  Wavefront 0 stores w1 (or
+// v_{j+1}, v~_{j+1} and the copy), the wavefront holding v_j stores its
+// corrected form, and for a second round each wavefront accumulates the inner
+// products <v_q, w1> of its own vectors and wavefront 0 also ||w1||^2.  The
+// shares are double-buffered, so one barrier per step suffices.
 template <typename TB, int QW, int PU>
 __global__ __launch_bounds__(BLK) void k_proj0w(zc *__restrict__ w, const zc *__restrict__ V, size_t vstride, int j,
                                                 unsigned N, size_t ld, FState *fsb, Report *rep, int *stop,
                                                 const zc *__restrict__ pin, int nbin, zc *__restrict__ pout,
-                                                zc *__restrict__ vout, Cx<TB> *__restrict__ bc, unsigned chunk,
-                                                int nb, const int *active)
+                                                zc *__restrict__ vout, Cx<TB> *__restrict__ bc, zc *vfix, int lazy,
+                                                unsigned chunk, int nb, const int *active)
 {
     constexpr int NW = BLK / 64;
     constexpr int NV = QW + 1;                    // QW inner products and ||w1||^2
     constexpr int ND = pow2_at_least(2 * NV);
     constexpr int SH = ND == 2 ? 5 : ND == 4 ? 4 : ND == 8 ? 3 : ND == 16 ? 2 : ND == 32 ? 1 : 0;
     __shared__ zc cc[OVAL];
-    __shared__ double scs;
-    __shared__ int twos;
-    __shared__ zc share[2][NW][PU * 64];
+    __shared__ zc ccor[OVAL];
+    __shared__ double scs, gps;
+    __shared__ int twos, pends;
+    __shared__ zc shareH[2][NW][PU * 64];
+    __shared__ zc shareC[2][NW][PU * 64];
     __shared__ zc wsh[2][PU * 64];
+    __shared__ zc vsh[2][PU * 64];
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
     FState *fs = fsb + rhs;
-    proj0_head(fs, j, pin + (size_t)rhs * OVAL * NBMAX, nbin, cc, scs, twos);
-    const bool two = twos != 0;
-    const double sc = scs;
+    proj0_head(fs, j, pin + (size_t)rhs * OVAL * NBMAX, nbin, lazy != 0, cc, ccor, scs, gps, twos, pends);
+    const bool two = twos != 0, pend = pends != 0;
+    const double sc = scs, gp = gps;
     const size_t off = rhs * ld;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nq = (j + NW - wv) / NW;            // vectors wv, wv + NW, ... <= j
+    const int wj = j % NW, kj = j / NW;           // the wavefront and slot holding v_j
     const unsigned c = chunk_id(nb);
     const unsigned b0 = c * chunk, b1 = min(N, b0 + chunk);
     zc dots[NV];
@@ -4344,29 +4394,57 @@ __global__ __launch_bounds__(BLK) void k_proj0w(zc *__restrict__ w, const zc *__
             const unsigned pc = min(pb + u * 64 + lane, b1 - 1);
 #pragma unroll
             for (int k = 0; k < QW; ++k)
-                if (k < nq) v[u][k] = V[(wv + NW * k) * vstride + off + pc];
+                if (k < nq) v[u][k] = pend && wv == wj && k == kj ? vfix[off + pc] : V[(wv + NW * k) * vstride + off + pc];
             if (wv == NW - 1) wsh[buf][u * 64 + lane] = w[off + pc];
         }
 #pragma unroll
         for (int u = 0; u < PU; ++u) {
-            zc a = mkc(0.0, 0.0);
+            zc a = mkc(0.0, 0.0), t = mkc(0.0, 0.0);
 #pragma unroll
-            for (int k = 0; k < QW; ++k)
-                if (k < nq) a = a + cc[wv + NW * k] * v[u][k];
-            share[buf][wv][u * 64 + lane] = a;
+            for (int k = 0; k < QW; ++k) {
+                if (k >= nq) continue;
+                if (pend && wv == wj && k == kj) {
+                    vsh[buf][u * 64 + lane] = v[u][k];
+                    continue;
+                }
+                a = a + cc[wv + NW * k] * v[u][k];
+                if (pend && wv + NW * k < j) t = cfma(ccor[wv + NW * k], v[u][k], t);
+            }
+            shareH[buf][wv][u * 64 + lane] = a;
+            if (pend) shareC[buf][wv][u * 64 + lane] = t;
         }
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < PU; ++u) {
             const unsigned p = pb + u * 64 + lane;
-            zc a = share[buf][0][u * 64 + lane];
+            const int e = u * 64 + lane;
+            zc a = shareH[buf][0][e];
 #pragma unroll
-            for (int t = 1; t < NW; ++t) a = a + share[buf][t][u * 64 + lane];
-            const zc x = wsh[buf][u * 64 + lane] - a;
+            for (int t = 1; t < NW; ++t) a = a + shareH[buf][t][e];
+            zc x = wsh[buf][e] - a;
+            if (pend) {
+                zc cs = shareC[buf][0][e];
+#pragma unroll
+                for (int t = 1; t < NW; ++t) cs = cs + shareC[buf][t][e];
+                const zc vj = gp * (vsh[buf][e] - cs);
+                x = x - cc[j] * vj;
+                if (wv == wj) {
+#pragma unroll
+                    for (int k = 0; k < QW; ++k)
+                        if (k == kj) v[u][k] = vj;
+                    if (p < b1) vfix[off + p] = vj;
+                }
+            }
             if (p < b1) {
                 if (two) {
                     if (wv == 0) {
-                        w[off + p] = x;
+                        if (lazy) {
+                            const zc vn = sc * x;
+                            vout[off + p] = vn;
+                            if (bc) bc[off + p] = cvt<TB>(vn);
+                        } else {
+                            w[off + p] = x;
+                        }
                         dots[QW].re += cabs2(x);
                     }
 #pragma unroll
@@ -4401,7 +4479,59 @@ __global__ __launch_bounds__(BLK) void k_proj0w(zc *__restrict__ w, const zc *__
         }
     }
     if (blockIdx.x != 0) return;
-    proj0_state(fs, rep + rhs, stop ? stop + rhs : nullptr, j, cc, two);
+    proj0_state(fs, rep + rhs, stop ? stop + rhs : nullptr, j, cc, two, sc);
+}
+
+// Finish of column j when its second round is deferred (lazy): one block per
+// RHS sums the second round's inner products c_i = <v_i, w1> (i <= j) and
+// ||w1||^2 from k_proj0's partials, takes h_{j+1,j} = sqrt(||w1||^2 - ||c||^2)
+// (0 at a breakdown), keeps c~ = scs c and g = 1 / (scs h_{j+1,j}) for the next
+// first projection (v_{j+1} = g (v~_{j+1} - sum_i c~_i v_i)) and advances the
+// FGMRES state: the column h + c, the Givens step, the report and the stop
+// test, so a converged RHS takes no further V-cycle.  After a final column it
+// only clears the pending flag.
+__global__ __launch_bounds__(BLK) void k_col(int j, FState *fsb, Report *rep, int *stop, const zc *__restrict__ pin,
+                                             int nbin, const int *active)
+{
+    constexpr int M = CSG_MAX_RESTART;
+    __shared__ zc cc[OVAL];
+    __shared__ zc col[OVAL];
+    __shared__ double cs_s[M];
+    __shared__ zc sn_s[M];
+    const int rhs = blockIdx.y;
+    if (!active[rhs]) return;
+    FState *fs = fsb + rhs;
+    if (!fs->reorth) {
+        if (threadIdx.x == 0) fs->pend = 0;
+        return;
+    }
+    const zc *pp = pin + (size_t)rhs * OVAL * NBMAX;
+    for (int q = threadIdx.x / FG; q <= j + 1; q += BLK / FG) {
+        const zc v = group_parts(pp + q * NBMAX, nbin);
+        if (threadIdx.x % FG == 0) cc[q] = v;
+    }
+    for (int q = threadIdx.x; q < j; q += BLK) {
+        cs_s[q] = fs->cs[q];
+        sn_s[q] = fs->sn[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double sc = fs->sc1;
+        double c2 = 0.0;
+        for (int q = 0; q <= j; ++q) {
+            c2 += cabs2(cc[q]);
+            col[q] = fs->hcol[q] + cc[q];
+            fs->hcol[q] = col[q];
+            fs->corr[q] = sc * cc[q];
+        }
+        const double w2 = cc[j + 1].re, h2 = w2 - c2;
+        const double hn = h2 > 1e-13 * w2 ? sqrt(h2) : 0.0;
+        fs->gpend = hn > 0.0 && sc > 0.0 ? 1.0 / (sc * hn) : 0.0;
+        fs->pend = 1;
+        givens_column(fs, rep + rhs, j, hn, col, cs_s, sn_s, stop ? stop + rhs : nullptr);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q <= j + 1; q += BLK) fs->R[q * M + j] = col[q];
 }
 
 // Second round of column j, finished and applied in one launch (columns
@@ -4507,8 +4637,9 @@ void launch_hdot_tile(const LvlK<double> &H, const Cx<TZ> *z, zc *w, const zc *V
                        ntile, active);
 }
 
-// the wavefront-split first round for columns of 17..64 vectors (CSG_PROJ0W=0:
-// the two-pass k_proj0 instead, for comparisons)
+// the wavefront-split first round for columns of 9..64 vectors (CSG_PROJ0W=0:
+// the register kernel up to 16 vectors and the two-pass k_proj0 beyond, for
+// comparisons)
 static bool wide_proj0()
 {
     static const bool on = [] {
@@ -4520,27 +4651,36 @@ static bool wide_proj0()
 
 template <typename TB>
 void launch_proj0(zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, FState *fs, Report *rep,
-                  int *stop, const zc *pin, int nbin, zc *pout, zc *vout, Cx<TB> *bcast, const Launch &g,
-                  const int *active)
+                  int *stop, const zc *pin, int nbin, zc *pout, zc *vout, Cx<TB> *bcast, zc *vfix, int lazy,
+                  const Launch &g, const int *active)
 {
-    // columns of up to 16 basis vectors keep a point's whole basis in one
-    // lane's registers (more would spill); longer ones split it over the
-    // block's wavefronts
+    // columns of up to 8 basis vectors keep a point's whole basis in one
+    // lane's registers (16 with the pending correction would spill); longer
+    // ones split it over the block's wavefronts
     if (j + 1 <= 8)
         hipLaunchKernelGGL((k_proj0<TB, 8>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop, pin,
-                           nbin, pout, vout, bcast, g.chunk, g.nb, active);
-    else if (j + 1 <= 16)
+                           nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);
+    else if (j + 1 <= 16 && !wide_proj0())
         hipLaunchKernelGGL((k_proj0<TB, 16>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop, pin,
-                           nbin, pout, vout, bcast, g.chunk, g.nb, active);
+                           nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);
+    else if (j + 1 <= 2 * (BLK / 64))
+        hipLaunchKernelGGL((k_proj0w<TB, 2, 2>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop,
+                           pin, nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);
     else if (j + 1 <= 4 * (BLK / 64) && wide_proj0())
         hipLaunchKernelGGL((k_proj0w<TB, 4, 2>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop,
-                           pin, nbin, pout, vout, bcast, g.chunk, g.nb, active);
+                           pin, nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);
     else if (j + 1 <= 8 * (BLK / 64) && wide_proj0())
         hipLaunchKernelGGL((k_proj0w<TB, 8, 1>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop,
-                           pin, nbin, pout, vout, bcast, g.chunk, g.nb, active);
+                           pin, nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);
     else
         hipLaunchKernelGGL((k_proj0<TB, 0>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop, pin,
-                           nbin, pout, vout, bcast, g.chunk, g.nb, active);
+                           nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);
+}
+
+void launch_col(int j, FState *fs, Report *rep, int *stop, const zc *pin, int nbin, int nrhs, hipStream_t st,
+                const int *active)
+{
+    hipLaunchKernelGGL(k_col, dim3(1, nrhs), dim3(BLK), 0, st, j, fs, rep, stop, pin, nbin, active);
 }
 
 template <typename TB>
@@ -4750,7 +4890,7 @@ template void launch_hdot_tile<float>(const LvlK<double> &, const Cx<float> *, z
     template void launch_proj1<T>(const zc *, const zc *, size_t, int, unsigned, size_t, FState *, Report *,       \
                                   int *, const zc *, int, zc *, Cx<T> *, const Launch &, const int *);             \
     template void launch_proj0<T>(zc *, const zc *, size_t, int, unsigned, size_t, FState *, Report *, int *,      \
-                                  const zc *, int, zc *, zc *, Cx<T> *, const Launch &, const int *);              \
+                                  const zc *, int, zc *, zc *, Cx<T> *, zc *, int, const Launch &, const int *);   \
     template void launch_uupd<T>(zc *, const Cx<T> *, size_t, unsigned, size_t, const FState *, const Launch &,    \
                                  const int *);                                                                     \
     template void launch_slab<T>(const LvlK<T> &, const Basis<T> &, const Cx<T> *, Cx<T> *, int, int, size_t,     \

@@ -292,6 +292,39 @@ def test_fgmres_second_round_every_column(monkeypatch):
     assert rel(res["1"][0], res["0"][0]) <= 1e-8
 
 
+OUTER_MODES = {
+    "lazy": {},                                        # second rounds applied by the next first projection
+    "at_once": {"CSG_LAZY": "0"},                      # second rounds applied by k_proj1
+    "two_pass": {"CSG_PROJ0W": "0"},                   # register kernel to 16 vectors, two-pass beyond
+    "lazy_every_column": {"CSG_FORCE_CGS2": "1"},
+    "at_once_every_column": {"CSG_FORCE_CGS2": "1", "CSG_LAZY": "0"},
+}
+
+
+@pytest.mark.parametrize("mode", list(OUTER_MODES))
+@pytest.mark.parametrize("name", ["2d_ragged", "3d_ragged"])
+def test_fgmres_outer_orthogonalisation_modes(name, mode, monkeypatch):
+    """FGMRES(48) with two RHS (columns of 1..48 basis vectors: the register,
+    and every wavefront-split first projection) under each way of applying
+    the second Gram-Schmidt round: iterations +-1 and solution within 1e-10 of
+    the oracle."""
+    import torch
+    for k, v in OUTER_MODES[mode].items():
+        monkeypatch.setenv(k, v)
+    w = CASES[name]()
+    chi = np.stack([w.chi[0], rvec(w.chi.shape[1:], 480)])
+    op, orc = pair(w, max_rhs=2, cycle_prec=0, restart=48)
+    u, rc, infos = op.solve(dev(chi, torch.complex128), tol=1e-10, restart=48, maxit=600)
+    u = host(u)
+    assert rc == 0
+    for r in range(2):
+        uo, io = orc.fgmres(chi[r], tol=1e-10, restart=48, maxit=600)
+        e = rel(u[r], uo)
+        note(f"  {mode} rhs {r}: its gpu {infos[r]['iterations']} oracle {io.iterations} sol err {e:.2e}")
+        assert abs(infos[r]["iterations"] - io.iterations) <= 1
+        assert e <= 1e-10
+
+
 def test_graph_replay_matches_eager(monkeypatch):
     """FGMRES iterations replayed from captured graphs (with eager restart and
     report work in between) give bit-identical results to eager launches."""
