@@ -4121,6 +4121,19 @@ void launch_coarse(const Cx<T> *minvT, int n, const Cx<T> *b, Cx<T> *x, size_t l
     hipLaunchKernelGGL((k_coarse<T>), dim3(1, nrhs), dim3(BLK), 0, st, minvT, n, b, x, ld, mstride, rpp, active);
 }
 
+// A scalar zero the compiler cannot see through: added to the index of a
+// block-uniform coefficient in shared memory inside a point loop, it keeps
+// the coefficient a broadcast read at its point of use instead of a value
+// held in vector registers for the whole pass (the first projection's
+// coefficients, two per basis vector, would otherwise take 4 registers each
+// per lane and lower the kernel's occupancy or spill).
+__device__ __forceinline__ int opaque_zero()
+{
+    int z;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+    return z;
+}
+
 // Shared start of the first-round kernels: sum the inner products of k_hdot
 // (h_i = <v_i, w>, i <= j, and ||w||^2) from the RHS's partials pp into cc
 // (group_parts: a fixed order, so every block gets the same bits) and take
@@ -4131,9 +4144,10 @@ void launch_coarse(const Cx<T> *minvT, int n, const Cx<T> *b, Cx<T> *x, size_t l
 // ccor, gps); <v_j, w> then follows from the inner products already formed.
 // scs scales the first round's result into v_{j+1} (final column) or into the
 // next first-round form v~_{j+1} (second round pending; any positive scale
-// serves, 1/||w1|| when the estimate ||w||^2 - ||h||^2 is usable).
+// serves, 1/||w1|| when the estimate ||w||^2 - ||h||^2 is usable).  cx holds
+// the coefficients of the vectors as stored (v~_j in place of v_j).
 __device__ __forceinline__ void proj0_head(const FState *fs, int j, const zc *pp, int nbin, bool lazy, zc *cc,
-                                           zc *ccor, double &scs, double &gps, int &twos, int &pends)
+                                           zc *cx, zc *ccor, double &scs, double &gps, int &twos, int &pends)
 {
     const bool pend = lazy && j > 0 && fs->pend;
     for (int q = threadIdx.x / FG; q <= j + 1; q += BLK / FG) {
@@ -4166,6 +4180,14 @@ __device__ __forceinline__ void proj0_head(const FState *fs, int j, const zc *pp
         scs = sc;
         gps = gp;
         pends = pend;
+    }
+    __syncthreads();
+    // coefficients of the vectors as stored: w1 = w - sum_q cx_q u_q with u_j = v~_j
+    // when pending, i.e. cx_q = h_q - h_j g c~_q (q < j) and cx_j = h_j g
+    for (int q = threadIdx.x; q <= j; q += BLK) {
+        zc v = cc[q];
+        if (pend) v = q < j ? cc[q] - (gps * cc[j]) * ccor[q] : gps * cc[j];
+        cx[q] = v;
     }
     __syncthreads();
 }
@@ -4230,13 +4252,15 @@ __global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__r
     __shared__ zc sh[(BLK / 64) * 8];
     __shared__ zc res[8];
     __shared__ zc cc[OVAL];
+    __shared__ zc cx[OVAL];
     __shared__ zc ccor[OVAL];
     __shared__ double scs, gps;
     __shared__ int twos, pends;
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
     FState *fs = fsb + rhs;
-    proj0_head(fs, j, pin + (size_t)rhs * OVAL * NBMAX, nbin, lazy != 0 && JB > 0, cc, ccor, scs, gps, twos, pends);
+    proj0_head(fs, j, pin + (size_t)rhs * OVAL * NBMAX, nbin, lazy != 0 && JB > 0, cc, cx, ccor, scs, gps, twos,
+               pends);
     const bool two = twos != 0, pend = pends != 0;
     const double sc = scs, gp = gps;
     const size_t off = rhs * ld;
@@ -4255,11 +4279,17 @@ __global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__r
 #pragma unroll
             for (int q = 0; q < JB; ++q)
                 if (q <= j) v[q] = pend && q == j ? vfix[off + p] : V[q * vstride + off + p];
+            const int oz = opaque_zero();
+            zc x = w[off + p];
+#pragma unroll
+            for (int q = 0; q < JB; ++q)
+                if (q <= j) x = x - cx[q + oz] * v[q];
             if (pend) {
+                // v_j = g (v~_j - sum_{q<j} c~_q v_q), stored and used by the second round
                 zc t = mkc(0.0, 0.0);
 #pragma unroll
                 for (int q = 0; q < JB; ++q)
-                    if (q < j) t = cfma(ccor[q], v[q], t);
+                    if (q < j) t = cfma(ccor[q + oz], v[q], t);
 #pragma unroll
                 for (int q = 0; q < JB; ++q)
                     if (q == j) {
@@ -4267,10 +4297,6 @@ __global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__r
                         vfix[off + p] = v[q];
                     }
             }
-            zc x = w[off + p];
-#pragma unroll
-            for (int q = 0; q < JB; ++q)
-                if (q <= j) x = x - cc[q] * v[q];
             if (two) {
                 if (lazy) {
                     const zc vn = sc * x;
@@ -4340,18 +4366,19 @@ __global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__r
     proj0_state(fs, rep + rhs, stop ? stop + rhs : nullptr, j, cc, two, sc);
 }
 
-// k_proj0 for columns of more than 8 basis vectors, reading V once: the
+// k_proj0 for columns of more than 16 basis vectors, reading V once: the
 // basis is split over the block's wavefronts (wavefront wv holds v_q for
 // q = wv, wv + NW, ..., QW of them at most) and every lane takes PU points per
 // step, so a point's basis values sit in the registers of NW lanes.  Each
-// wavefront forms its shares of (V h)(p) and, for a pending v_j, of
-// (sum_{i<j} c~_i v_i)(p), in ascending q; the shares meet in shared memory
-// with w(p) and v~_j(p), and every wavefront sums them in wavefront order, so
-// all form the same v_j(p) and w1(p) = w(p) - sum.  Wavefront 0 stores w1 (or
-// v_{j+1}, v~_{j+1} and the copy), the wavefront holding v_j stores its
-// corrected form, and for a second round each wavefront accumulates the inner
-// products <v_q, w1> of its own vectors and wavefront 0 also ||w1||^2.  The
-// shares are double-buffered, so one barrier per step suffices.
+// wavefront forms its share of (sum_q cx_q u_q)(p) (the vectors as stored,
+// proj0_head) and, for a pending v_j, of (sum_{i<j} c~_i v_i)(p), in
+// ascending q; the shares meet in shared memory with w(p), and every
+// wavefront sums them in wavefront order, so all form the same
+// w1(p) = w(p) - sum.  The wavefront holding v~_j forms and stores
+// v_j = g (v~_j - sum); wavefront 0 stores w1 (or v_{j+1}, v~_{j+1} and the
+// copy), and for a second round each wavefront accumulates the inner products
+// <v_q, w1> of its own vectors and wavefront 0 also ||w1||^2.  The shares are
+// double-buffered, so one barrier per step suffices.
 template <typename TB, int QW, int PU>
 __global__ __launch_bounds__(BLK) void k_proj0w(zc *__restrict__ w, const zc *__restrict__ V, size_t vstride, int j,
                                                 unsigned N, size_t ld, FState *fsb, Report *rep, int *stop,
@@ -4364,17 +4391,17 @@ __global__ __launch_bounds__(BLK) void k_proj0w(zc *__restrict__ w, const zc *__
     constexpr int ND = pow2_at_least(2 * NV);
     constexpr int SH = ND == 2 ? 5 : ND == 4 ? 4 : ND == 8 ? 3 : ND == 16 ? 2 : ND == 32 ? 1 : 0;
     __shared__ zc cc[OVAL];
+    __shared__ zc cx[OVAL];
     __shared__ zc ccor[OVAL];
     __shared__ double scs, gps;
     __shared__ int twos, pends;
     __shared__ zc shareH[2][NW][PU * 64];
     __shared__ zc shareC[2][NW][PU * 64];
     __shared__ zc wsh[2][PU * 64];
-    __shared__ zc vsh[2][PU * 64];
     const int rhs = blockIdx.y;
     if (!active[rhs]) return;
     FState *fs = fsb + rhs;
-    proj0_head(fs, j, pin + (size_t)rhs * OVAL * NBMAX, nbin, lazy != 0, cc, ccor, scs, gps, twos, pends);
+    proj0_head(fs, j, pin + (size_t)rhs * OVAL * NBMAX, nbin, lazy != 0, cc, cx, ccor, scs, gps, twos, pends);
     const bool two = twos != 0, pend = pends != 0;
     const double sc = scs, gp = gps;
     const size_t off = rhs * ld;
@@ -4403,11 +4430,7 @@ __global__ __launch_bounds__(BLK) void k_proj0w(zc *__restrict__ w, const zc *__
 #pragma unroll
             for (int k = 0; k < QW; ++k) {
                 if (k >= nq) continue;
-                if (pend && wv == wj && k == kj) {
-                    vsh[buf][u * 64 + lane] = v[u][k];
-                    continue;
-                }
-                a = a + cc[wv + NW * k] * v[u][k];
+                a = a + cx[wv + NW * k] * v[u][k];
                 if (pend && wv + NW * k < j) t = cfma(ccor[wv + NW * k], v[u][k], t);
             }
             shareH[buf][wv][u * 64 + lane] = a;
@@ -4421,19 +4444,18 @@ __global__ __launch_bounds__(BLK) void k_proj0w(zc *__restrict__ w, const zc *__
             zc a = shareH[buf][0][e];
 #pragma unroll
             for (int t = 1; t < NW; ++t) a = a + shareH[buf][t][e];
-            zc x = wsh[buf][e] - a;
-            if (pend) {
+            const zc x = wsh[buf][e] - a;
+            if (pend && wv == wj) {
+                // the wavefront holding v~_j forms v_j = g (v~_j - sum_{q<j} c~_q v_q)
                 zc cs = shareC[buf][0][e];
 #pragma unroll
                 for (int t = 1; t < NW; ++t) cs = cs + shareC[buf][t][e];
-                const zc vj = gp * (vsh[buf][e] - cs);
-                x = x - cc[j] * vj;
-                if (wv == wj) {
 #pragma unroll
-                    for (int k = 0; k < QW; ++k)
-                        if (k == kj) v[u][k] = vj;
-                    if (p < b1) vfix[off + p] = vj;
-                }
+                for (int k = 0; k < QW; ++k)
+                    if (k == kj) {
+                        v[u][k] = gp * (v[u][k] - cs);
+                        if (p < b1) vfix[off + p] = v[u][k];
+                    }
             }
             if (p < b1) {
                 if (two) {
@@ -4637,9 +4659,8 @@ void launch_hdot_tile(const LvlK<double> &H, const Cx<TZ> *z, zc *w, const zc *V
                        ntile, active);
 }
 
-// the wavefront-split first round for columns of 9..64 vectors (CSG_PROJ0W=0:
-// the register kernel up to 16 vectors and the two-pass k_proj0 beyond, for
-// comparisons)
+// the wavefront-split first round for columns of 17..64 vectors (CSG_PROJ0W=0:
+// the two-pass k_proj0 instead, for comparisons)
 static bool wide_proj0()
 {
     static const bool on = [] {
@@ -4654,18 +4675,15 @@ void launch_proj0(zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t 
                   int *stop, const zc *pin, int nbin, zc *pout, zc *vout, Cx<TB> *bcast, zc *vfix, int lazy,
                   const Launch &g, const int *active)
 {
-    // columns of up to 8 basis vectors keep a point's whole basis in one
-    // lane's registers (16 with the pending correction would spill); longer
-    // ones split it over the block's wavefronts
+    // columns of up to 16 basis vectors keep a point's whole basis in one
+    // lane's registers (more would spill); longer ones split it over the
+    // block's wavefronts
     if (j + 1 <= 8)
         hipLaunchKernelGGL((k_proj0<TB, 8>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop, pin,
                            nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);
-    else if (j + 1 <= 16 && !wide_proj0())
+    else if (j + 1 <= 16)
         hipLaunchKernelGGL((k_proj0<TB, 16>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop, pin,
                            nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);
-    else if (j + 1 <= 2 * (BLK / 64))
-        hipLaunchKernelGGL((k_proj0w<TB, 2, 2>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop,
-                           pin, nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);
     else if (j + 1 <= 4 * (BLK / 64) && wide_proj0())
         hipLaunchKernelGGL((k_proj0w<TB, 4, 2>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop,
                            pin, nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);
