@@ -15,8 +15,9 @@ complex128), reported beside it as the mixed-precision gain.
 Printed JSON (one line): solves/s as `value`, p50/p99 solve latency, V-cycle
 GB/s, the roofline of the dominant pass (its algorithmic bytes per launch over
 its average launch time, both measured with HIP events on the solve's stream
-inside the timed region), a measured device-to-device copy ceiling, and the
-CPU oracle timed on a bounded sample.
+inside the timed region), a measured device-to-device copy ceiling, the CPU
+oracle timed on a bounded sample, a second configuration (the 2-D 2048^2
+three-layer model in complex128) and a bounded serving stream.
 """
 from __future__ import annotations
 
@@ -136,6 +137,43 @@ def vcycle_working_set(level_sizes, nrhs, csize, s=3):
     return sum(n * (nrhs * (s + 6) * csize + csize // 2) for n in level_sizes[:-1])
 
 
+def second_workload(name, steps, tuned):
+    """A second configuration beside the headline (default: the 2-D 2048^2
+    three-layer model all in complex128): solves/s over `steps` timed solves
+    after one warm-up solve, iteration count and true residual."""
+    import torch
+    from paper_1012_5379_amd import Operator
+    from paper_1012_5379_amd import binding as B
+    w, wname = _workload(name)
+    params = dict(w.params(), cycle_prec=w.cycle_prec, max_rhs=w.nrhs, restart=w.restart)
+    op = Operator(params, w.phi, tuned=tuned)
+    chi = torch.from_numpy(w.chi).to("cuda")
+    u = torch.empty_like(chi)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def solve():
+        rc, infos = B.helm_solve(op.op, chi.data_ptr(), u.data_ptr(), w.nrhs, w.tol, w.restart, w.maxit, 0, stream)
+        if rc != 0:
+            raise RuntimeError(f"{wname}: solve did not converge: {B.STATUS.get(rc, rc)}")
+        return infos
+
+    solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        infos = solve()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out = {"workload": wname, "value": steps * w.nrhs / el, "unit": "solves/s", "steps": steps,
+           "ms_per_step": el / steps * 1e3, "iterations_per_solve": infos[0]["iterations"],
+           "relres_true": max(i["relres_true"] for i in infos), "dtype": "f32" if w.cycle_prec else "f64"}
+    print(f"[bench] second workload {wname}: {out['ms_per_step']:.1f} ms per solve, {out['iterations_per_solve']} its",
+          file=sys.stderr, flush=True)
+    del op
+    torch.cuda.empty_cache()
+    return out
+
+
 def serving(count, streams, load, batch=4):
     """Serving stream: `count` seeded C5 requests (2-D 256^2..2048^2 and 3-D
     64^3..192^3, 1-8 point sources, complex64 cycle; requests of one size
@@ -238,6 +276,9 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=12,
                     help="requests of the bounded serving stream reported beside the headline (0: skip)")
     ap.add_argument("--no-tuned", action="store_true", help="library default knobs instead of the tuned table")
+    ap.add_argument("--second", default="c3_fp64",
+                    help="a second workload timed beside the headline ('' to skip): solves/s of a few solves")
+    ap.add_argument("--second-steps", type=int, default=2)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="one device-to-device copy of MIB MiB before the solves (a plain copy of known size "
                          "for scaling hardware byte counters)")
@@ -429,6 +470,10 @@ def main():
         out["pass_survey_ms_per_solve"] = {k: round(v["ms_per_solve"], 3) for k, v in survey.items()}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, its, args.cpu_sample_its)
+    if args.second and args.second != args.workload:
+        op = None
+        torch.cuda.empty_cache()
+        out["second_workload"] = second_workload(args.second, args.second_steps, not args.no_tuned)
     if args.serving_requests > 0:
         # a bounded serving stream beside the headline (its own workload: C5)
         op = None
