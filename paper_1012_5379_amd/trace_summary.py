@@ -2,6 +2,7 @@
 
     python -m paper_1012_5379_amd.trace_summary kernels TRACE_CSV
     python -m paper_1012_5379_amd.trace_summary counters FETCH_CSV WRITE_CSV --copy-bytes N
+    python -m paper_1012_5379_amd.trace_summary occupancy SQ_CSV
 
 `kernels` reads a kernel trace (rocprofv3 --kernel-trace --output-format csv)
 and prints, per kernel and grid size, the dispatch count and the average, min
@@ -18,6 +19,13 @@ what the counter reads for the run's plain device-to-device copy of
 --copy-bytes bytes (the largest __amd_rocclr_copyBuffer dispatch), and prints
 the HBM bytes per dispatch of every kernel and per launch of each pass kind,
 with the hash of the library sources the counters belong to.
+
+`occupancy` reads one collection of SQ counters (SQ_WAVES, SQ_WAVE_CYCLES,
+SQ_BUSY_CYCLES, SQ_WAIT_INST_ANY, SQ_INSTS_VALU, SQ_INSTS_VMEM_RD,
+SQ_INSTS_VMEM_WR, SQ_INSTS_LDS) and prints per kernel and grid the mean
+counts per dispatch, the wave-cycles per busy cycle (proportional to the mean
+number of resident waves: compare across kernels) and the share of wave time
+spent waiting on an outstanding instruction (mostly memory).
 """
 from __future__ import annotations
 
@@ -151,6 +159,26 @@ def counters(fetch_csv: str, write_csv: str, copy_bytes: int) -> None:
     print(f"source_sha256: {source_hash()}")
 
 
+def occupancy(sq_csv: str) -> None:
+    agg = collections.defaultdict(lambda: collections.defaultdict(float))
+    disp = collections.defaultdict(set)
+    for r in _rows(sq_csv):
+        key = (_short(r["Kernel_Name"]), _blocks(r))
+        agg[key][r["Counter_Name"]] += float(r["Counter_Value"])
+        disp[key].add(r["Dispatch_Id"])
+    print(f"{'kernel':36s} {'blocks':>6s} {'n':>5s} {'waves':>7s} {'VALU/wave':>10s} {'VMEM rd/wave':>12s} "
+          f"{'LDS/wave':>9s} {'wave-cyc/busy':>13s} {'wait share':>10s}")
+    for key in sorted(agg, key=lambda k: -agg[k]["SQ_BUSY_CYCLES"]):
+        a, n = agg[key], len(disp[key])
+        waves = a["SQ_WAVES"] / n
+        per = lambda c: a[c] / max(1.0, a["SQ_WAVES"])
+        occ = a["SQ_WAVE_CYCLES"] / a["SQ_BUSY_CYCLES"] if a["SQ_BUSY_CYCLES"] else 0.0
+        wait = a["SQ_WAIT_INST_ANY"] / a["SQ_WAVE_CYCLES"] if a["SQ_WAVE_CYCLES"] else 0.0
+        print(f"{key[0][:36]:36s} {key[1]:6d} {n:5d} {waves:7.0f} {per('SQ_INSTS_VALU'):10.0f} "
+              f"{per('SQ_INSTS_VMEM_RD'):12.0f} {per('SQ_INSTS_LDS'):9.0f} {occ:13.2f} {wait:10.3f}")
+    print(f"source_sha256: {source_hash()}")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -160,9 +188,13 @@ def main(argv=None):
     c.add_argument("fetch")
     c.add_argument("write")
     c.add_argument("--copy-bytes", type=int, required=True)
+    o = sub.add_parser("occupancy")
+    o.add_argument("sq")
     a = ap.parse_args(argv)
     if a.cmd == "kernels":
         kernels(a.trace)
+    elif a.cmd == "occupancy":
+        occupancy(a.sq)
     else:
         counters(a.fetch, a.write, a.copy_bytes)
 
