@@ -1,5 +1,7 @@
 // api.hip -- C ABI of libcsg: workspace layout, operator construction, the
 // V-cycle sequence (section 3.1) and the flexible GMRES driver (section 5).
+#include <dlfcn.h>
+
 #include <algorithm>
 #include <cfloat>
 #include <chrono>
@@ -284,6 +286,52 @@ double tiny_of() { return 10.0 * (sizeof(T) == 8 ? DBL_EPSILON : (double)FLT_EPS
 // ---------------------------------------------------------------------------
 // benchmark instrumentation: event pairs around the launches of one pass kind
 // ---------------------------------------------------------------------------
+// roctx ranges around the host's enqueue of every level visit of the V-cycle
+// and every outer pass (CSG_ROCTX=1), for rocprofv3 --marker-trace: with
+// eager launches (CSG_GRAPHS=0) each range holds the launches of its passes,
+// which trace_summary's `ranges` attributes kernel time to.  The marker
+// library is opened on first use, so libcsg has no link dependency on it.
+struct Roctx {
+    int (*push)(const char *) = nullptr;
+    int (*pop)() = nullptr;
+    bool on = false;
+};
+
+const Roctx &roctx()
+{
+    static const Roctx r = [] {
+        Roctx x;
+        const char *e = getenv("CSG_ROCTX");
+        if (!e || atoi(e) == 0) return x;
+        void *h = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_GLOBAL);
+        if (!h) h = dlopen("libroctx64.so.4", RTLD_NOW | RTLD_GLOBAL);
+        if (!h) return x;
+        x.push = reinterpret_cast<int (*)(const char *)>(dlsym(h, "roctxRangePushA"));
+        x.pop = reinterpret_cast<int (*)()>(dlsym(h, "roctxRangePop"));
+        x.on = x.push && x.pop;
+        return x;
+    }();
+    return r;
+}
+
+struct Range {
+    bool on;
+    explicit Range(const char *name, int a = -1) : on(roctx().on)
+    {
+        if (!on) return;
+        char buf[80];
+        if (a >= 0) snprintf(buf, sizeof buf, name, a);
+        else snprintf(buf, sizeof buf, "%s", name);
+        roctx().push(buf);
+    }
+    ~Range()
+    {
+        if (on) roctx().pop();
+    }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
+
 struct ProfScope {
     Prof *pr = nullptr;
     hipStream_t st = nullptr;
@@ -618,6 +666,7 @@ void vcycle_impl(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, h
     const int nu1 = op->p.nu1, nu2 = op->p.nu2;
     int first = 0;   // pass 0 of this level's first sweep already ran
     for (int l = 0; l < lt; ++l) {
+        const Range rg("V-cycle down L%d", l);
         const DevLevel &lv = op->lev[l];
         const DevLevel &cl = op->lev[l + 1];
         const Cx<T> *b = l == 0 ? b0 : (const Cx<T> *)lv.b;
@@ -634,6 +683,7 @@ void vcycle_impl(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, h
     }
     {
         // levels lt..L-1 (coarsest solve included) in one workgroup per RHS
+        const Range rg("V-cycle coarse tail from L%d", lt);
         const Cx<T> *bt = lt == 0 ? b0 : (const Cx<T> *)op->lev[lt].b;
         Cx<T> *xt = lt == 0 ? x0 : (Cx<T> *)op->lev[lt].xb;
         launch_tail<T, DIM>((const TLev<T> *)op->tlev, lt, L, bt, xt, (const Cx<T> *)op->minvT, op->nc, op->p.s, nu1,
@@ -645,6 +695,7 @@ void vcycle_impl(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, h
     UpClose<T> pend{};
     bool have_pend = false;
     for (int l = lt - 1; l >= 0; --l) {
+        const Range rg("V-cycle up L%d", l);
         const DevLevel &lv = op->lev[l];
         const DevLevel &cl = op->lev[l + 1];
         const Cx<T> *b = l == 0 ? b0 : (const Cx<T> *)lv.b;
@@ -821,6 +872,7 @@ void vcycle_dispatch(const csg_operator *op, const void *b, void *x, int nrhs, h
 
 void run_vcycle(const csg_operator *op, const void *b, void *x, int nrhs, hipStream_t st, const int *active)
 {
+    const Range rg("V-cycle");
     ProfScope ps(op, CSG_PROF_VCYCLE, st, vcycle_bytes(op, nrhs));
     if (op->p.cycle_prec)
         vcycle_dispatch<float>(op, b, x, nrhs, st, active);
@@ -912,9 +964,11 @@ void iter_body(csg_solve *sv, int j, hipStream_t st)
     const int *mask = op->active;
     const void *b = op->p.cycle_prec ? op->b0 : (const void *)(op->V + j * vstride);
     Cx<TZ> *z = (Cx<TZ> *)op->Z + j * vstride;
+    const Range rg("FGMRES column %d", j);
     run_vcycle(op, b, z, sv->nrhs, st, mask);
     const double N = f.N, R = sv->nrhs;
     {
+        const Range rh("outer w = H z");
         ProfScope ps(op, CSG_PROF_OUTER_H, st, R * N * (sizeof(Cx<TZ>) + 16.0 * (j + 2)) + 8.0 * N);
         if (hdot_tiled<DIM>(op))
             launch_hdot_tile<TZ>(lvlH(op), z, op->w, op->V, vstride, j, f.ld, op->opart, f.tile, sv->nrhs, st, mask);
@@ -926,6 +980,7 @@ void iter_body(csg_solve *sv, int j, hipStream_t st)
         // FGMRES state) when the first round is final, and the second-round
         // passes below then return at once; otherwise keeps w_1 and forms the
         // second round's inner products in the same launch
+        const Range rp("outer first projection");
         ProfScope ps(op, CSG_PROF_OUTER_CGS1, st,
                      R * N * (16.0 * (j + 3) + (op->p.cycle_prec ? 8.0 : 0.0) + (op->lazy && j > 0 ? 16.0 : 0.0)));
         launch_proj0<TZ>(op->w, op->V, vstride, j, f.N, f.ld, op->fs, report_slot(op, j % LOOKAHEAD), op->active,
@@ -935,10 +990,12 @@ void iter_body(csg_solve *sv, int j, hipStream_t st)
     }
     if (op->lazy) {
         // the column's finish (its second round's vector update waits for the next first projection)
+        const Range rc("outer column finish");
         ProfScope ps(op, CSG_PROF_OUTER_PROJ2, st, 0.0);
         launch_col(j, op->fs, report_slot(op, j % LOOKAHEAD), op->active, op->opart2, f.nb, sv->nrhs, st, mask);
         return;
     }
+    const Range r2("outer second projection");
     ProfScope ps(op, CSG_PROF_OUTER_PROJ2, st, R * N * (16.0 * (j + 3) + (op->p.cycle_prec ? 8.0 : 0.0)));
     launch_proj1<TZ>(op->w, op->V, vstride, j, f.N, f.ld, op->fs, report_slot(op, j % LOOKAHEAD), op->active,
                      op->opart2, f.nb, op->V + (j + 1) * vstride, op->p.cycle_prec ? (Cx<TZ> *)op->b0 : nullptr, g,

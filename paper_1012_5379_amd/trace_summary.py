@@ -3,6 +3,7 @@
     python -m paper_1012_5379_amd.trace_summary kernels TRACE_CSV
     python -m paper_1012_5379_amd.trace_summary counters FETCH_CSV WRITE_CSV --copy-bytes N
     python -m paper_1012_5379_amd.trace_summary occupancy SQ_CSV
+    python -m paper_1012_5379_amd.trace_summary ranges KERNEL_CSV HIP_API_CSV MARKER_CSV
 
 `kernels` reads a kernel trace (rocprofv3 --kernel-trace --output-format csv)
 and prints, per kernel and grid size, the dispatch count and the average, min
@@ -26,6 +27,12 @@ SQ_INSTS_VMEM_WR, SQ_INSTS_LDS) and prints per kernel and grid the mean
 counts per dispatch, the wave-cycles per busy cycle (proportional to the mean
 number of resident waves: compare across kernels) and the share of wave time
 spent waiting on an outstanding instruction (mostly memory).
+
+`ranges` attributes kernel time to the library's roctx ranges (CSG_ROCTX=1,
+eager launches: CSG_GRAPHS=0; rocprofv3 --kernel-trace --hip-trace
+--marker-trace): each dispatch is matched to its launch call by correlation
+id, the call to the innermost range open on its thread at that time, and the
+kernel time is summed per range (the outer column number dropped).
 """
 from __future__ import annotations
 
@@ -179,6 +186,54 @@ def occupancy(sq_csv: str) -> None:
     print(f"source_sha256: {source_hash()}")
 
 
+def _col(row, *names):
+    for n in names:
+        if n in row:
+            return row[n]
+    raise KeyError(names[0])
+
+
+def ranges(kernel_csv: str, hip_csv: str, marker_csv: str) -> None:
+    import bisect
+    import re
+    kern = {}
+    for r in _rows(kernel_csv):
+        kern[r["Correlation_Id"]] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+    calls = {}
+    for r in _rows(hip_csv):
+        if "Launch" in _col(r, "Function", "Operation"):
+            calls[r["Correlation_Id"]] = (r["Thread_Id"], int(r["Start_Timestamp"]))
+    by_thread = collections.defaultdict(list)
+    for r in _rows(marker_csv):
+        name = _col(r, "Function", "Message", "Operation")
+        by_thread[r["Thread_Id"]].append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), name))
+    for v in by_thread.values():
+        v.sort()
+    tot = collections.defaultdict(float)
+    unmatched = 0.0
+    for cid, us in kern.items():
+        c = calls.get(cid)
+        best = None
+        if c:
+            lst = by_thread.get(c[0], [])
+            i = bisect.bisect_right(lst, (c[1], float("inf"), ""))
+            # innermost open range: the latest-starting one that still covers the call
+            for k in range(i - 1, max(-1, i - 64), -1):
+                s0, e0, nm = lst[k]
+                if s0 <= c[1] <= e0:
+                    best = nm
+                    break
+        if best is None:
+            unmatched += us
+        else:
+            tot[re.sub(r"FGMRES column \d+", "FGMRES column", best)] += us
+    allt = sum(tot.values()) + unmatched
+    print(f"{'range':40s} {'kernel ms':>10s} {'share %':>8s}")
+    for nm, us in sorted(tot.items(), key=lambda kv: -kv[1]):
+        print(f"{nm[:40]:40s} {us / 1e3:10.2f} {100 * us / allt:8.2f}")
+    print(f"{'(outside any range)':40s} {unmatched / 1e3:10.2f} {100 * unmatched / allt:8.2f}")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -190,11 +245,17 @@ def main(argv=None):
     c.add_argument("--copy-bytes", type=int, required=True)
     o = sub.add_parser("occupancy")
     o.add_argument("sq")
+    g = sub.add_parser("ranges")
+    g.add_argument("kernel")
+    g.add_argument("hip")
+    g.add_argument("marker")
     a = ap.parse_args(argv)
     if a.cmd == "kernels":
         kernels(a.trace)
     elif a.cmd == "occupancy":
         occupancy(a.sq)
+    elif a.cmd == "ranges":
+        ranges(a.kernel, a.hip, a.marker)
     else:
         counters(a.fetch, a.write, a.copy_bytes)
 
