@@ -717,6 +717,12 @@ void vcycle_impl(const csg_operator *op, const Cx<T> *b0, Cx<T> *x0, int nrhs, h
                 launch_up_tile<T>(lvl<T>(op, l), lvl<T>(op, l + 1), (const Cx<T> *)cl.xb, xi, xo, b,
                                   (Cx<T> *)lv.r, (Cx<T> *)lv.w[0], lv.ld, cl.ld, sizeof(T) == 8 && op->p.s == 1,
                                   lv.part[0], lv.tile, nrhs, st, active, have_pend ? &pend : nullptr);
+            } else if (slabbed<T, DIM>(op, l) && op->slab_pr) {
+                // interpolated correction and the residual that opens the post-sweep in one slab pass
+                const Bytes by = bytes_of(op, nrhs);
+                ProfScope ps(op, l == 0 ? CSG_PROF_PROLONG_RESID : -1, st, by.prc(xi != nullptr, lv.N, cl.N));
+                launch_slab_pr<T>(lvl<T>(op, l), lvl<T>(op, l + 1), (const Cx<T> *)cl.xb, xi, xo, b, (Cx<T> *)lv.r,
+                                  lv.ld, cl.ld, lv.slab, nrhs, st, active);
             } else {
                 // interpolated correction, then the residual that opens the post-sweep
                 const Bytes by = bytes_of(op, nrhs);
@@ -1424,6 +1430,8 @@ int create_impl(const csg_params *const *ps, const double *const *phis, int P, v
         // projection (CSG_PROJ0W=0 selects the two-pass one for long columns)
         op->lazy = true;
         if (const char *e = getenv("CSG_LAZY")) op->lazy = atoi(e) != 0;
+        op->slab_pr = true;
+        if (const char *e = getenv("CSG_SLAB_PR")) op->slab_pr = atoi(e) != 0;
         if (const char *e = getenv("CSG_PROJ0W"))
             if (atoi(e) == 0) op->lazy = false;
         op->poly_tiles = true;

@@ -236,6 +236,7 @@ struct csg_operator {
     bool fuse_upd;                    // coarse post-sweep updates applied by the finer up-path pass
     bool force_cgs2;                  // every outer column takes the second Gram-Schmidt round
     bool lazy;                        // second rounds deferred into the next first projection
+    bool slab_pr;                     // 3-D slab levels: interpolation and residual in one slab pass
     bool poly_tiles;                  // polynomial sweeps of 2-D levels run as one tiled launch
     long slab_min;                    // 3-D levels from this size run the Arnoldi passes on z-marching slabs
     // outer FGMRES storage

@@ -132,6 +132,11 @@ template <typename T>
 void launch_slab(const LvlK<T> &L, const Basis<T> &B, const Cx<T> *win, Cx<T> *wout, int j, int s, size_t ld,
                  const zc *pin, int nbin, zc *pout, GState *gs, double tiny, bool wnorm, const SlabGeo &sg, int nrhs,
                  hipStream_t st, const int *active);
+// interpolated correction and the residual opening the post-sweep on the slabs of a 3-D level
+template <typename T>
+void launch_slab_pr(const LvlK<T> &F, const LvlK<T> &C, const Cx<T> *ec, const Cx<T> *xin, Cx<T> *xout,
+                    const Cx<T> *b, Cx<T> *r, size_t ldf, size_t ldc, const SlabGeo &sg, int nrhs, hipStream_t st,
+                    const int *active);
 
 // Pass 0 of a sweep on 2-D tiles: w = A u0 with <u0, w>, ||u0||^2 (and
 // ||w||^2 when wnorm) per tile into pout; same outputs as launch_st0,

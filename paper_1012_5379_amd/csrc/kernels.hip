@@ -3959,6 +3959,114 @@ void launch_os_tile(const LvlK<T> &L, const Basis<T> &B, const Cx<T> *win, Cx<T>
                            nbin, pout, gs, tiny, tg, ntile, active);
 }
 
+// Interpolated correction and the residual that opens the post-sweep on the
+// z-marching slabs of a 3-D level (the transfer-pass analogue of k_slab): for
+// each plane every thread forms x = P ec (+ xin) at its column point and at
+// one halo point of the 32 x 16 column into the three-plane shared-memory ring
+// (zero outside the level), stores x at its own points, and from the ring
+// planes around plane k forms r = b - A x there; b and phi of the next plane
+// are loaded while a plane's residual runs.  x never goes back to memory for
+// the residual's stencil, and the values equal k_prolong then k_resid bit for
+// bit (the same formulas in the same order).
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_slab_pr(LvlK<T> F, LvlK<T> C, const Cx<T> *__restrict__ ec,
+                                                 const Cx<T> *__restrict__ xin, Cx<T> *__restrict__ xout,
+                                                 const Cx<T> *__restrict__ b, Cx<T> *__restrict__ r, size_t ldf,
+                                                 size_t ldc, unsigned ntx, unsigned nty, unsigned nzc, unsigned zrun,
+                                                 int nslab, const int *active)
+{
+    __shared__ Cx<T> ring[3][SHX * SHY];
+    __shared__ Cx<T> ltab[3 * SX + 3 * SY];
+    const int rhs = blockIdx.y;
+    F = F.at(rhs);
+    C = C.at(rhs);
+    if (!active[rhs]) return;
+    const unsigned slot = chunk_id(nslab);
+    const unsigned col = slot / nzc, zci = slot - col * nzc;
+    if (col >= ntx * nty) return;   // padding block
+    const unsigned cyi = col / ntx, cxi = col - cyi * ntx;
+    const int nx = (int)F.nx, ny = (int)F.ny, nz = (int)F.nz;
+    const int x0 = (int)cxi * SX, y0 = (int)cyi * SY;
+    const int TX = min(SX, nx - x0), TY = min(SY, ny - y0);
+    const int z0 = (int)(zci * zrun), z1 = min(nz, z0 + (int)zrun);
+    const int tx = threadIdx.x % SX, ty = threadIdx.x / SX;
+    const bool own = tx < TX && ty < TY;
+    const int eo = (ty + 1) * SHX + tx + 1;
+    const int gxo = x0 + min(tx, TX - 1), gyo = y0 + min(ty, TY - 1);
+    const unsigned po = (unsigned)gyo * nx + gxo;
+    int er = -1, gxr = gxo, gyr = gyo;
+    unsigned pr = po;
+    bool rin = false;
+    if ((int)threadIdx.x < 2 * (TX + 2) + 2 * TY) {
+        int ex, ey;
+        ring_pos(threadIdx.x, TX, TY, ex, ey);
+        er = ey * SHX + ex;
+        const int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
+        rin = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        if (rin) {
+            pr = (unsigned)gy * nx + gx;
+            gxr = gx;
+            gyr = gy;
+        }
+    }
+    for (int q = threadIdx.x; q < 3 * (TX + TY); q += BLK) {
+        if (q < 3 * TX) {
+            const int a = q / TX, c = q - a * TX;
+            ltab[a * SX + c] = F.tab[0][a * nx + x0 + c];
+        } else {
+            const int qq = q - 3 * TX, a = qq / TY, c = qq - a * TY;
+            ltab[3 * SX + a * SY + c] = F.tab[1][a * ny + y0 + c];
+        }
+    }
+    const unsigned plane = (unsigned)nx * ny;
+    const Cx<T> *e = ec + rhs * ldc;
+    const Cx<T> *xi = xin ? xin + rhs * ldf : nullptr;
+    const size_t off = rhs * ldf;
+    // x at a point of plane k (as k_prolong forms it)
+    auto xat = [&](int k, int gx, int gy, unsigned pxy) -> Cx<T> {
+        Cx<T> v = prolong_pt<T, 3>(e, (unsigned)gx, (unsigned)gy, (unsigned)k, C.nx, C.ny, C.nz);
+        if (xi) v = v + xi[(size_t)k * plane + pxy];
+        return v;
+    };
+    // plane k into ring slot k % 3 (zero outside the level); x of the run's own planes to memory
+    auto stage = [&](int k) {
+        Cx<T> *R = ring[(k + 3) % 3];
+        const bool kin = k >= 0 && k < nz;
+        if (er >= 0) R[er] = (kin && rin) ? xat(k, gxr, gyr, pr) : mkc<T>(0, 0);
+        const Cx<T> xo = kin ? xat(k, gxo, gyo, po) : mkc<T>(0, 0);
+        R[eo] = (kin && own) ? xo : mkc<T>(0, 0);
+        if (kin && own && k >= z0 && k < z1) xout[off + (size_t)k * plane + po] = xo;
+    };
+    stage(z0 - 1);
+    stage(z0);
+    Cx<T> bc = b[off + (size_t)z0 * plane + po];
+    T phc = F.phi[(size_t)z0 * plane + po];
+    for (int k = z0; k < z1; ++k) {
+        stage(k + 1);
+        const int kn = min(k + 1, nz - 1);
+        const Cx<T> bn = b[off + (size_t)kn * plane + po];
+        const T phn = F.phi[(size_t)kn * plane + po];
+        __syncthreads();
+        if (own) {
+            const Cx<T> *Rm = ring[(k + 2) % 3], *R0 = ring[k % 3], *Rp = ring[(k + 1) % 3];
+            const Cx<T> *tz = F.tab[2];
+            Cx<T> d = ltab[SX + tx] + ltab[3 * SX + SY + ty] + tz[nz + k];
+            sub_phi(d, F, phc);
+            Cx<T> a = d * R0[eo];
+            a = cfma(ltab[tx], R0[eo - 1], a);
+            a = cfma(ltab[2 * SX + tx], R0[eo + 1], a);
+            a = cfma(ltab[3 * SX + ty], R0[eo - SHX], a);
+            a = cfma(ltab[3 * SX + 2 * SY + ty], R0[eo + SHX], a);
+            a = cfma(tz[k], Rm[eo], a);
+            a = cfma(tz[2 * nz + k], Rp[eo], a);
+            r[off + (size_t)k * plane + po] = bc - a;
+        }
+        __syncthreads();
+        bc = bn;
+        phc = phn;
+    }
+}
+
 template <typename T>
 void launch_slab(const LvlK<T> &L, const Basis<T> &B, const Cx<T> *win, Cx<T> *wout, int j, int s, size_t ld,
                  const zc *pin, int nbin, zc *pout, GState *gs, double tiny, bool wnorm, const SlabGeo &sg, int nrhs,
@@ -3975,6 +4083,16 @@ void launch_slab(const LvlK<T> &L, const Basis<T> &B, const Cx<T> *win, Cx<T> *w
     else
         hipLaunchKernelGGL((k_slab<T, 4, 1>), gr, dim3(BLK), 0, st, L, B, win, wout, s, ld, pin, nbin, pout, gs, tiny,
                            sg.ntx, sg.nty, sg.nzc, sg.zrun, wnorm ? 1 : 0, nslab, active);
+}
+
+template <typename T>
+void launch_slab_pr(const LvlK<T> &F, const LvlK<T> &C, const Cx<T> *ec, const Cx<T> *xin, Cx<T> *xout,
+                    const Cx<T> *b, Cx<T> *r, size_t ldf, size_t ldc, const SlabGeo &sg, int nrhs, hipStream_t st,
+                    const int *active)
+{
+    const int nslab = (int)sg.npad;
+    hipLaunchKernelGGL((k_slab_pr<T>), dim3(nslab, nrhs), dim3(BLK), 0, st, F, C, ec, xin, xout, b, r, ldf, ldc,
+                       sg.ntx, sg.nty, sg.nzc, sg.zrun, nslab, active);
 }
 
 template <typename T>
@@ -4914,6 +5032,9 @@ template void launch_hdot_tile<float>(const LvlK<double> &, const Cx<float> *, z
     template void launch_slab<T>(const LvlK<T> &, const Basis<T> &, const Cx<T> *, Cx<T> *, int, int, size_t,     \
                                  const zc *, int, zc *, GState *, double, bool, const SlabGeo &, int, hipStream_t, \
                                  const int *);                                                                     \
+    template void launch_slab_pr<T>(const LvlK<T> &, const LvlK<T> &, const Cx<T> *, const Cx<T> *, Cx<T> *,      \
+                                    const Cx<T> *, Cx<T> *, size_t, size_t, const SlabGeo &, int, hipStream_t,    \
+                                    const int *);                                                                  \
     template void launch_poly_tile<T>(const LvlK<T> &, const LvlK<T> &, const Cx<T> *, const Cx<T> *,            \
                                       const Cx<T> *, Cx<T> *, const Cx<T>(&)[3], size_t, size_t, int, hipStream_t, \
                                       const int *);
