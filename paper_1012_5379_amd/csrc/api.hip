@@ -641,7 +641,13 @@ int sweep(const csg_operator *op, int l, const Cx<T> *b, Cx<T> *x, bool from_zer
                             cl.dtile, nrhs, st, active);
         return st0 ? (int)(cl.dtile.ntx * cl.dtile.nty) : 0;
     }
-    if (restrict_after) {
+    if (restrict_after && slabbed<T, DIM>(op, l) && op->slab_down) {
+        // closing update and full weighting of the Arnoldi residual in one slab pass
+        const DevLevel &cl = op->lev[l + 1];
+        ProfScope ps(op, k0 ? -1 : CSG_PROF_UPD_RESTRICT, st, by.upd_res(s, !from_zero, lv.N, cl.N));
+        launch_slab_down<T>(x, from_zero ? 0 : 1, B, s, L, lvl<T>(op, l + 1), (Cx<T> *)cl.b, lv.ld, cl.ld, pclose,
+                            nclose, lv.gs, tiny, lv.slab, nrhs, st, active);
+    } else if (restrict_after) {
         // closing update writes x and the Arnoldi residual r; full weighting of r
         const DevLevel &cl = op->lev[l + 1];
         ProfScope ps(op, k0 ? -1 : CSG_PROF_UPD_RESTRICT, st,
@@ -1432,6 +1438,8 @@ int create_impl(const csg_params *const *ps, const double *const *phis, int P, v
         if (const char *e = getenv("CSG_LAZY")) op->lazy = atoi(e) != 0;
         op->slab_pr = true;
         if (const char *e = getenv("CSG_SLAB_PR")) op->slab_pr = atoi(e) != 0;
+        op->slab_down = true;
+        if (const char *e = getenv("CSG_SLAB_DOWN")) op->slab_down = atoi(e) != 0;
         if (const char *e = getenv("CSG_PROJ0W"))
             if (atoi(e) == 0) op->lazy = false;
         op->poly_tiles = true;

@@ -237,6 +237,7 @@ struct csg_operator {
     bool force_cgs2;                  // every outer column takes the second Gram-Schmidt round
     bool lazy;                        // second rounds deferred into the next first projection
     bool slab_pr;                     // 3-D slab levels: interpolation and residual in one slab pass
+    bool slab_down;                   // 3-D slab levels: closing update and restriction in one slab pass
     bool poly_tiles;                  // polynomial sweeps of 2-D levels run as one tiled launch
     long slab_min;                    // 3-D levels from this size run the Arnoldi passes on z-marching slabs
     // outer FGMRES storage

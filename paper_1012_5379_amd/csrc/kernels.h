@@ -132,6 +132,11 @@ template <typename T>
 void launch_slab(const LvlK<T> &L, const Basis<T> &B, const Cx<T> *win, Cx<T> *wout, int j, int s, size_t ld,
                  const zc *pin, int nbin, zc *pout, GState *gs, double tiny, bool wnorm, const SlabGeo &sg, int nrhs,
                  hipStream_t st, const int *active);
+// closing update of a pre-sweep and the restriction of its Arnoldi residual on the slabs of a 3-D level
+template <typename T>
+void launch_slab_down(Cx<T> *x, int accumulate, const Basis<T> &B, int s, const LvlK<T> &F, const LvlK<T> &C,
+                      Cx<T> *bc, size_t ldf, size_t ldc, const zc *pin, int nbin, GState *gs, double tiny,
+                      const SlabGeo &sg, int nrhs, hipStream_t st, const int *active);
 // interpolated correction and the residual opening the post-sweep on the slabs of a 3-D level
 template <typename T>
 void launch_slab_pr(const LvlK<T> &F, const LvlK<T> &C, const Cx<T> *ec, const Cx<T> *xin, Cx<T> *xout,

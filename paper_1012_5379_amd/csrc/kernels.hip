@@ -4067,6 +4067,114 @@ __global__ __launch_bounds__(BLK) void k_slab_pr(LvlK<T> F, LvlK<T> C, const Cx<
     }
 }
 
+// Closing pass of a pre-sweep fused with the restriction on the z-marching
+// slabs of a 3-D level: every block solves the sweep's small least squares
+// (close_sweep, as k_upd_r), then for each plane every thread forms the
+// Arnoldi residual r = sum_{i<=k} cr_i u_i at its column point and at one halo
+// point into the three-plane shared-memory ring, updates x (+)= sum_{i<k} cx_i
+// u_i at its own points, and after an odd plane the block forms the full
+// weighting of r for the coarse points centred on that plane and in its
+// column (16 x 8 of them).  r never goes to memory; the values equal k_upd_r
+// then k_restrict bit for bit (the same formulas in the same order).
+template <typename T, int SB>
+__global__ __launch_bounds__(BLK) void k_slab_down(Cx<T> *__restrict__ x, int accumulate, Basis<T> B, int s,
+                                                   LvlK<T> F, LvlK<T> C, Cx<T> *__restrict__ bc, size_t ldf,
+                                                   size_t ldc, const zc *__restrict__ pin, int nbin, GState *gsb,
+                                                   double tiny, unsigned ntx, unsigned nty, unsigned nzc,
+                                                   unsigned zrun, int nslab, const int *active)
+{
+    __shared__ zc sh[(BLK / 64) * (SB + 1)];
+    __shared__ zc res[SB + 1];
+    __shared__ zc ax[CSG_MAX_S], ar[CSG_MAX_S + 1];
+    __shared__ Cx<T> ring[3][SHX * SHY];
+    const int rhs = blockIdx.y;
+    F = F.at(rhs);
+    C = C.at(rhs);
+    if (!active[rhs]) return;
+    const int kb = close_sweep<T, SB>(pin + (size_t)rhs * NVAL * NBMAX, nbin, gsb + rhs, s, tiny, sh, res, ax, ar);
+    Cx<T> cx[SB], cr[SB];
+    coefs_to_T<T, SB>(kb, ax, ar, cx, cr);
+    const unsigned slot = chunk_id(nslab);
+    const unsigned col = slot / nzc, zci = slot - col * nzc;
+    if (col >= ntx * nty) return;   // padding block
+    const unsigned cyi = col / ntx, cxi = col - cyi * ntx;
+    const int nx = (int)F.nx, ny = (int)F.ny, nz = (int)F.nz;
+    const int x0 = (int)cxi * SX, y0 = (int)cyi * SY;
+    const int TX = min(SX, nx - x0), TY = min(SY, ny - y0);
+    const int z0 = (int)(zci * zrun), z1 = min(nz, z0 + (int)zrun);
+    const int tx = threadIdx.x % SX, ty = threadIdx.x / SX;
+    const bool own = tx < TX && ty < TY;
+    const int eo = (ty + 1) * SHX + tx + 1;
+    const unsigned po = (unsigned)(y0 + min(ty, TY - 1)) * nx + (x0 + min(tx, TX - 1));
+    int er = -1;
+    unsigned pr = po;
+    bool rin = false;
+    if ((int)threadIdx.x < 2 * (TX + 2) + 2 * TY) {
+        int ex, ey;
+        ring_pos(threadIdx.x, TX, TY, ex, ey);
+        er = ey * SHX + ex;
+        const int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
+        rin = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        if (rin) pr = (unsigned)gy * nx + gx;
+    }
+    const unsigned plane = (unsigned)nx * ny;
+    const size_t off = rhs * ldf;
+    // r at a point of plane z; with upd, also the update of x there
+    auto rat = [&](int z, unsigned pxy, bool upd) -> Cx<T> {
+        const size_t p = off + (size_t)z * plane + pxy;
+        Cx<T> uv[SB];
+#pragma unroll
+        for (int q = 0; q < SB; ++q)
+            if (q <= kb) uv[q] = B.u[q][p];
+        Cx<T> rr = mkc<T>(0, 0);
+#pragma unroll
+        for (int q = 0; q < SB; ++q)
+            if (q <= kb) rr = cfma(cr[q], uv[q], rr);
+        if (upd) {
+            Cx<T> v = accumulate ? x[p] : mkc<T>(0, 0);
+#pragma unroll
+            for (int q = 0; q < SB; ++q)
+                if (q < kb) v = cfma(cx[q], uv[q], v);
+            x[p] = v;
+        }
+        return rr;
+    };
+    auto stage = [&](int z) {
+        Cx<T> *R = ring[(z + 3) % 3];
+        const bool kin = z >= 0 && z < nz;
+        if (er >= 0) R[er] = (kin && rin) ? rat(z, pr, false) : mkc<T>(0, 0);
+        const Cx<T> ro = kin ? rat(z, po, own && z >= z0 && z < z1) : mkc<T>(0, 0);
+        R[eo] = (kin && own) ? ro : mkc<T>(0, 0);
+    };
+    // this thread's coarse point of a plane (16 x 8 per column), if any
+    const int lx = threadIdx.x % (SX / 2), ly = threadIdx.x / (SX / 2);
+    const int Kx = x0 / 2 + lx, Ky = y0 / 2 + ly;
+    const bool cown = ly < SY / 2 && 2 * Kx + 1 < x0 + TX && 2 * Ky + 1 < y0 + TY && Kx < (int)C.nx &&
+                      Ky < (int)C.ny;
+    const int ec0 = (2 * Ky + 1 - y0 + 1) * SHX + (2 * Kx + 1 - x0 + 1);   // ring index of the centre
+    const T scale = (T)0.125;
+    stage(z0 - 1);
+    stage(z0);
+    for (int z = z0; z < z1; ++z) {
+        stage(z + 1);
+        __syncthreads();
+        const int Kz = (z - 1) / 2;
+        if ((z & 1) && cown && Kz < (int)C.nz) {
+            const Cx<T> *Rq[3] = {ring[(z + 2) % 3], ring[z % 3], ring[(z + 1) % 3]};
+            Cx<T> acc = mkc<T>(0, 0);
+            for (int qz = 0; qz < 3; ++qz)
+                for (int qy = 0; qy < 3; ++qy)
+                    for (int qx = 0; qx < 3; ++qx) {
+                        T wgt = (T)(rw(qx) * rw(qy));
+                        wgt *= (T)rw(qz);
+                        acc = acc + wgt * Rq[qz][ec0 + (qy - 1) * SHX + (qx - 1)];
+                    }
+            bc[rhs * ldc + ((size_t)Kz * C.ny + Ky) * C.nx + Kx] = scale * acc;
+        }
+        __syncthreads();
+    }
+}
+
 template <typename T>
 void launch_slab(const LvlK<T> &L, const Basis<T> &B, const Cx<T> *win, Cx<T> *wout, int j, int s, size_t ld,
                  const zc *pin, int nbin, zc *pout, GState *gs, double tiny, bool wnorm, const SlabGeo &sg, int nrhs,
@@ -4083,6 +4191,16 @@ void launch_slab(const LvlK<T> &L, const Basis<T> &B, const Cx<T> *win, Cx<T> *w
     else
         hipLaunchKernelGGL((k_slab<T, 4, 1>), gr, dim3(BLK), 0, st, L, B, win, wout, s, ld, pin, nbin, pout, gs, tiny,
                            sg.ntx, sg.nty, sg.nzc, sg.zrun, wnorm ? 1 : 0, nslab, active);
+}
+
+template <typename T>
+void launch_slab_down(Cx<T> *x, int accumulate, const Basis<T> &B, int s, const LvlK<T> &F, const LvlK<T> &C,
+                      Cx<T> *bc, size_t ldf, size_t ldc, const zc *pin, int nbin, GState *gs, double tiny,
+                      const SlabGeo &sg, int nrhs, hipStream_t st, const int *active)
+{
+    const int nslab = (int)sg.npad;
+    hipLaunchKernelGGL((k_slab_down<T, 4>), dim3(nslab, nrhs), dim3(BLK), 0, st, x, accumulate, B, s, F, C, bc, ldf,
+                       ldc, pin, nbin, gs, tiny, sg.ntx, sg.nty, sg.nzc, sg.zrun, nslab, active);
 }
 
 template <typename T>
@@ -5032,6 +5150,9 @@ template void launch_hdot_tile<float>(const LvlK<double> &, const Cx<float> *, z
     template void launch_slab<T>(const LvlK<T> &, const Basis<T> &, const Cx<T> *, Cx<T> *, int, int, size_t,     \
                                  const zc *, int, zc *, GState *, double, bool, const SlabGeo &, int, hipStream_t, \
                                  const int *);                                                                     \
+    template void launch_slab_down<T>(Cx<T> *, int, const Basis<T> &, int, const LvlK<T> &, const LvlK<T> &,      \
+                                      Cx<T> *, size_t, size_t, const zc *, int, GState *, double, const SlabGeo &, \
+                                      int, hipStream_t, const int *);                                              \
     template void launch_slab_pr<T>(const LvlK<T> &, const LvlK<T> &, const Cx<T> *, const Cx<T> *, Cx<T> *,      \
                                     const Cx<T> *, Cx<T> *, size_t, size_t, const SlabGeo &, int, hipStream_t,    \
                                     const int *);                                                                  \
