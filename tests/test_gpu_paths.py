@@ -30,6 +30,8 @@ PATHS = {
                       "CSG_HDOT_TILES": "0", "CSG_SLABS": "0"},
     # every 3-D level on z-marching slabs (the large 3-D levels' path)
     "slab": {"CSG_SLAB_MIN": "0", "CSG_TAIL_MAX": "0"},
+    # slabs for the Arnoldi passes, the transfers as separate chunked passes
+    "slab_chunked_transfers": {"CSG_SLAB_MIN": "0", "CSG_TAIL_MAX": "0", "CSG_SLAB_PR": "0", "CSG_SLAB_DOWN": "0"},
 }
 CASES = {k: v for k, v in cases().items() if k in ("2d_wide", "3d_ragged")}
 
@@ -64,7 +66,7 @@ def test_sweep_and_vcycle(name, path, prec, monkeypatch):
         assert e <= (TOL64 if prec == 0 else TOL32["vcycle"])
 
 
-@pytest.mark.parametrize("path", ["unfused", "slab"])
+@pytest.mark.parametrize("path", ["unfused", "slab", "slab_chunked_transfers"])
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("name", list(CASES))
 def test_fgmres_large_grid_paths(name, prec, path, monkeypatch):
