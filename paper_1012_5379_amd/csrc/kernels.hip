@@ -4615,7 +4615,28 @@ __global__ __launch_bounds__(BLK) void k_proj0(zc *__restrict__ w, const zc *__r
 // copy), and for a second round each wavefront accumulates the inner products
 // <v_q, w1> of its own vectors and wavefront 0 also ||w1||^2.  The shares are
 // double-buffered, so one barrier per step suffices.
-template <typename TB, int QW, int PU>
+// one step's loads of the split first projection: this wavefront's basis
+// values v_{wv + NW k} (slot kfix from the corrected copy) at the step's
+// points, and in slot QW w there for the last wavefront
+template <int QW, int PU, int NW>
+__device__ __forceinline__ void proj0w_load(zc (&v)[PU][QW + 1], unsigned pb, unsigned b1, int lane, int wv, int nq,
+                                            int kfix, const zc *__restrict__ V, size_t vstride, const zc *vfix,
+                                            const zc *w, size_t off)
+{
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+        const unsigned pc = min(pb + u * 64 + lane, b1 - 1);
+#pragma unroll
+        for (int k = 0; k < QW; ++k)
+            if (k < nq) v[u][k] = k == kfix ? vfix[off + pc] : V[(wv + NW * k) * vstride + off + pc];
+        if (wv == NW - 1) {
+            const zc x = w[off + pc];
+            v[u][QW] = mkc(x.re, x.im);
+        }
+    }
+}
+
+template <typename TB, int QW, int PU, bool PF>
 __global__ __launch_bounds__(BLK) void k_proj0w(zc *__restrict__ w, const zc *__restrict__ V, size_t vstride, int j,
                                                 unsigned N, size_t ld, FState *fsb, Report *rep, int *stop,
                                                 const zc *__restrict__ pin, int nbin, zc *__restrict__ pout,
@@ -4649,9 +4670,24 @@ __global__ __launch_bounds__(BLK) void k_proj0w(zc *__restrict__ w, const zc *__
     zc dots[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) dots[k] = mkc(0.0, 0.0);
+    // PF: each step's loads are issued one step ahead, while the previous
+    // step finishes (launches of few workgroups, where no other workgroup
+    // hides their latency); the arithmetic and its order are the same
+    zc vq[PU][QW + 1];
+    const int kfix = pend && wv == wj ? kj : -1;
+    if (PF && b0 < b1) proj0w_load<QW, PU, NW>(vq, b0, b1, lane, wv, nq, kfix, V, vstride, vfix, w, off);
     int buf = 0;
     for (unsigned pb = b0; pb < b1; pb += PU * 64, buf ^= 1) {
         zc v[PU][QW];
+        if (PF) {
+#pragma unroll
+            for (int u = 0; u < PU; ++u) {
+#pragma unroll
+                for (int k = 0; k < QW; ++k)
+                    if (k < nq) v[u][k] = vq[u][k];
+                if (wv == NW - 1) wsh[buf][u * 64 + lane] = mkc(vq[u][QW].re, vq[u][QW].im);
+            }
+        } else {
 #pragma unroll
         for (int u = 0; u < PU; ++u) {
             const unsigned pc = min(pb + u * 64 + lane, b1 - 1);
@@ -4659,6 +4695,7 @@ __global__ __launch_bounds__(BLK) void k_proj0w(zc *__restrict__ w, const zc *__
             for (int k = 0; k < QW; ++k)
                 if (k < nq) v[u][k] = pend && wv == wj && k == kj ? vfix[off + pc] : V[(wv + NW * k) * vstride + off + pc];
             if (wv == NW - 1) wsh[buf][u * 64 + lane] = w[off + pc];
+        }
         }
 #pragma unroll
         for (int u = 0; u < PU; ++u) {
@@ -4673,6 +4710,8 @@ __global__ __launch_bounds__(BLK) void k_proj0w(zc *__restrict__ w, const zc *__
             if (pend) shareC[buf][wv][u * 64 + lane] = t;
         }
         __syncthreads();
+        if (PF && pb + PU * 64 < b1)
+            proj0w_load<QW, PU, NW>(vq, pb + PU * 64, b1, lane, wv, nq, kfix, V, vstride, vfix, w, off);
 #pragma unroll
         for (int u = 0; u < PU; ++u) {
             const unsigned p = pb + u * 64 + lane;
@@ -4913,19 +4952,27 @@ void launch_proj0(zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t 
 {
     // columns of up to 16 basis vectors keep a point's whole basis in one
     // lane's registers (more would spill); longer ones split it over the
-    // block's wavefronts
+    // block's wavefronts, loading a step ahead when the launch has few
+    // workgroups (about one per CU: one right-hand side)
+    const bool few = (long)g.nb * g.nrhs < 1024;
     if (j + 1 <= 8)
         hipLaunchKernelGGL((k_proj0<TB, 8>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop, pin,
                            nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);
     else if (j + 1 <= 16)
         hipLaunchKernelGGL((k_proj0<TB, 16>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop, pin,
                            nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);
+    else if (j + 1 <= 4 * (BLK / 64) && wide_proj0() && few)
+        hipLaunchKernelGGL((k_proj0w<TB, 4, 2, true>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep,
+                           stop, pin, nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);
     else if (j + 1 <= 4 * (BLK / 64) && wide_proj0())
-        hipLaunchKernelGGL((k_proj0w<TB, 4, 2>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop,
-                           pin, nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);
+        hipLaunchKernelGGL((k_proj0w<TB, 4, 2, false>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep,
+                           stop, pin, nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);
+    else if (j + 1 <= 8 * (BLK / 64) && wide_proj0() && few)
+        hipLaunchKernelGGL((k_proj0w<TB, 8, 1, true>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep,
+                           stop, pin, nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);
     else if (j + 1 <= 8 * (BLK / 64) && wide_proj0())
-        hipLaunchKernelGGL((k_proj0w<TB, 8, 1>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop,
-                           pin, nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);
+        hipLaunchKernelGGL((k_proj0w<TB, 8, 1, false>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep,
+                           stop, pin, nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);
     else
         hipLaunchKernelGGL((k_proj0<TB, 0>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop, pin,
                            nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);
