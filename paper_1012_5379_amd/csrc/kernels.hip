@@ -4671,8 +4671,8 @@ __global__ __launch_bounds__(BLK) void k_proj0w(zc *__restrict__ w, const zc *__
 #pragma unroll
     for (int k = 0; k < NV; ++k) dots[k] = mkc(0.0, 0.0);
     // PF: each step's loads are issued one step ahead, while the previous
-    // step finishes (launches of few workgroups, where no other workgroup
-    // hides their latency); the arithmetic and its order are the same
+    // step finishes (otherwise nothing is in flight across a step's barrier);
+    // the arithmetic and its order are the same
     zc vq[PU][QW + 1];
     const int kfix = pend && wv == wj ? kj : -1;
     if (PF && b0 < b1) proj0w_load<QW, PU, NW>(vq, b0, b1, lane, wv, nq, kfix, V, vstride, vfix, w, off);
@@ -4945,6 +4945,17 @@ static bool wide_proj0()
     return on;
 }
 
+// whether the split first projection loads a step ahead (CSG_PROJ0W_AHEAD=0:
+// loads at the top of each step, for comparisons)
+static bool proj0w_ahead()
+{
+    static const bool on = [] {
+        const char *e = getenv("CSG_PROJ0W_AHEAD");
+        return !(e && atoi(e) == 0);
+    }();
+    return on;
+}
+
 template <typename TB>
 void launch_proj0(zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t ld, FState *fs, Report *rep,
                   int *stop, const zc *pin, int nbin, zc *pout, zc *vout, Cx<TB> *bcast, zc *vfix, int lazy,
@@ -4952,22 +4963,24 @@ void launch_proj0(zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t 
 {
     // columns of up to 16 basis vectors keep a point's whole basis in one
     // lane's registers (more would spill); longer ones split it over the
-    // block's wavefronts, loading a step ahead when the launch has few
-    // workgroups (about one per CU: one right-hand side)
-    const bool few = (long)g.nb * g.nrhs < 1024;
+    // block's wavefronts, loading each step's values while the previous step
+    // finishes (without that, a block has no loads in flight across each
+    // step's barrier: a fifth more time in this pass on 16 right-hand sides
+    // of 128^3, 6 % more whole-solve time on one right-hand side of 1024^2)
+    const bool ahead = proj0w_ahead();
     if (j + 1 <= 8)
         hipLaunchKernelGGL((k_proj0<TB, 8>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop, pin,
                            nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);
     else if (j + 1 <= 16)
         hipLaunchKernelGGL((k_proj0<TB, 16>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop, pin,
                            nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);
-    else if (j + 1 <= 4 * (BLK / 64) && wide_proj0() && few)
+    else if (j + 1 <= 4 * (BLK / 64) && wide_proj0() && ahead)
         hipLaunchKernelGGL((k_proj0w<TB, 4, 2, true>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep,
                            stop, pin, nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);
     else if (j + 1 <= 4 * (BLK / 64) && wide_proj0())
         hipLaunchKernelGGL((k_proj0w<TB, 4, 2, false>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep,
                            stop, pin, nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);
-    else if (j + 1 <= 8 * (BLK / 64) && wide_proj0() && few)
+    else if (j + 1 <= 8 * (BLK / 64) && wide_proj0() && ahead)
         hipLaunchKernelGGL((k_proj0w<TB, 8, 1, true>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep,
                            stop, pin, nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);
     else if (j + 1 <= 8 * (BLK / 64) && wide_proj0())

@@ -298,6 +298,8 @@ OUTER_MODES = {
     "two_pass": {"CSG_PROJ0W": "0"},                   # register kernel to 16 vectors, two-pass beyond
     "lazy_every_column": {"CSG_FORCE_CGS2": "1"},
     "at_once_every_column": {"CSG_FORCE_CGS2": "1", "CSG_LAZY": "0"},
+    "proj0w_step_loads": {"CSG_PROJ0W_AHEAD": "0"},    # split first projection without loads a step ahead
+    "hdot_untiled": {"CSG_HDOT_TILES": "0"},           # 2-D: the chunked w = H z
 }
 
 
@@ -306,8 +308,8 @@ OUTER_MODES = {
 def test_fgmres_outer_orthogonalisation_modes(name, mode, monkeypatch):
     """FGMRES(48) with two RHS (columns of 1..48 basis vectors: the register,
     and every wavefront-split first projection) under each way of applying
-    the second Gram-Schmidt round: iterations +-1 and solution within 1e-10 of
-    the oracle."""
+    the second Gram-Schmidt round, and with the chunked w = H z in 2-D:
+    iterations +-1 and solution within 1e-10 of the oracle."""
     import torch
     for k, v in OUTER_MODES[mode].items():
         monkeypatch.setenv(k, v)
