@@ -466,6 +466,23 @@ bool hdot_tiled(const csg_operator *op)
     return DIM == 2 && op->hdot_tiles && tile_fits(t) && (int)(t.ntx * t.nty) <= NBMAX;
 }
 
+// the same on the finest level's slabs, when its Arnoldi passes take them
+template <int DIM>
+bool hdot_slabbed(const csg_operator *op)
+{
+    return DIM == 3 && op->hdot_tiles && slabbed<double, DIM>(op, 0);
+}
+
+// how many per-block partials w = H z leaves for the first projection
+template <int DIM>
+int hdot_parts(const csg_operator *op)
+{
+    const DevLevel &f = op->lev[0];
+    if (hdot_tiled<DIM>(op)) return (int)(f.tile.ntx * f.tile.nty);
+    if (hdot_slabbed<DIM>(op)) return (int)f.slab.npad;
+    return f.nb;
+}
+
 // Whether the up path of level l runs as one tiled pass (interpolation,
 // residual and pass 0 of the post-sweep).
 template <typename T, int DIM>
@@ -984,6 +1001,8 @@ void iter_body(csg_solve *sv, int j, hipStream_t st)
         ProfScope ps(op, CSG_PROF_OUTER_H, st, R * N * (sizeof(Cx<TZ>) + 16.0 * (j + 2)) + 8.0 * N);
         if (hdot_tiled<DIM>(op))
             launch_hdot_tile<TZ>(lvlH(op), z, op->w, op->V, vstride, j, f.ld, op->opart, f.tile, sv->nrhs, st, mask);
+        else if (hdot_slabbed<DIM>(op))
+            launch_slab_hdot<TZ>(lvlH(op), z, op->w, op->V, vstride, j, f.ld, op->opart, f.slab, sv->nrhs, st, mask);
         else
             launch_hdot<TZ, DIM>(lvlH(op), z, op->w, op->V, vstride, j, f.ld, op->opart, g, mask);
     }
@@ -996,7 +1015,7 @@ void iter_body(csg_solve *sv, int j, hipStream_t st)
         ProfScope ps(op, CSG_PROF_OUTER_CGS1, st,
                      R * N * (16.0 * (j + 3) + (op->p.cycle_prec ? 8.0 : 0.0) + (op->lazy && j > 0 ? 16.0 : 0.0)));
         launch_proj0<TZ>(op->w, op->V, vstride, j, f.N, f.ld, op->fs, report_slot(op, j % LOOKAHEAD), op->active,
-                         op->opart, hdot_tiled<DIM>(op) ? (int)(f.tile.ntx * f.tile.nty) : f.nb, op->opart2, op->V + (j + 1) * vstride,
+                         op->opart, hdot_parts<DIM>(op), op->opart2, op->V + (j + 1) * vstride,
                          op->p.cycle_prec ? (Cx<TZ> *)op->b0 : nullptr, op->V + j * vstride, op->lazy ? 1 : 0, g,
                          mask);
     }

@@ -225,6 +225,12 @@ template <typename TZ, int DIM>
 void launch_hdot(const LvlK<double> &H, const Cx<TZ> *z, zc *w, const zc *V, size_t vstride, int j, size_t ld,
                  zc *pout, const Launch &g, const int *active);
 
+// the same on the finest level's 3-D z-marching slabs (one partial per slab
+// block, sg.npad of them)
+template <typename TZ>
+void launch_slab_hdot(const LvlK<double> &H, const Cx<TZ> *z, zc *w, const zc *V, size_t vstride, int j, size_t ld,
+                      zc *pout, const SlabGeo &sg, int nrhs, hipStream_t st, const int *active);
+
 // the same on the finest level's 2-D tiles (one partial per tile)
 template <typename TZ>
 void launch_hdot_tile(const LvlK<double> &H, const Cx<TZ> *z, zc *w, const zc *V, size_t vstride, int j, size_t ld,

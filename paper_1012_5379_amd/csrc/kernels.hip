@@ -1490,6 +1490,133 @@ __global__ __launch_bounds__(BLK) void k_slab(LvlK<T> L, Basis<T> B, const Cx<T>
     if ((int)threadIdx.x < nv) pout[((size_t)rhs * NVAL + threadIdx.x) * NBMAX + slot] = res[threadIdx.x];
 }
 
+// w = H z on the z-marching slabs of the finest 3-D level, with the
+// first-round inner products <v_i, w> (i <= j) and ||w||^2 (the outer
+// analogue of k_slab, same column/run geometry): z of each plane is staged
+// into the ring (column points and their x-y halo, complex128), the 7-point
+// stencil of H is applied to the middle plane and w stored; the first group of
+// up to 8 basis vectors, loaded at the column point before the plane's
+// barrier, meets w in registers (later groups: k_hdot_groups).  One partial
+// per block; the padding blocks write zeros.
+template <typename TZ>
+__global__ __launch_bounds__(BLK) void k_slab_hdot(LvlK<double> H, const Cx<TZ> *__restrict__ z,
+                                                   zc *__restrict__ w, const zc *__restrict__ V, size_t vstride,
+                                                   int j, size_t ld, zc *__restrict__ pout, unsigned ntx,
+                                                   unsigned nty, unsigned nzc, unsigned zrun, int nslab,
+                                                   const int *active)
+{
+    __shared__ zc sh[(BLK / 64) * 9];
+    __shared__ zc res[9];
+    __shared__ zc ring[3][SHX * SHY];
+    __shared__ zc ltab[3 * SX + 3 * SY];
+    const int rhs = blockIdx.y;
+    H = H.at(rhs);
+    if (!active[rhs]) return;
+    const size_t off = rhs * ld;
+    zc *po = pout + (size_t)rhs * OVAL * NBMAX;
+    const unsigned slot = chunk_id(nslab);
+    const unsigned col = slot / nzc, zci = slot - col * nzc;
+    if (col >= ntx * nty) {
+        if ((int)threadIdx.x <= min(j, 7) || (int)threadIdx.x == j + 1)
+            po[(size_t)threadIdx.x * NBMAX + slot] = mkc(0.0, 0.0);
+        return;
+    }
+    const unsigned cyi = col / ntx, cxi = col - cyi * ntx;
+    const int nx = (int)H.nx, ny = (int)H.ny, nz = (int)H.nz;
+    const int x0 = (int)cxi * SX, y0 = (int)cyi * SY;
+    const int TX = min(SX, nx - x0), TY = min(SY, ny - y0);
+    const int z0 = (int)(zci * zrun), z1 = min(nz, z0 + (int)zrun);
+    const int tx = threadIdx.x % SX, ty = threadIdx.x / SX;
+    const bool own = tx < TX && ty < TY;
+    const int eo = (ty + 1) * SHX + tx + 1;
+    const unsigned pp = (unsigned)(y0 + min(ty, TY - 1)) * nx + (x0 + min(tx, TX - 1));
+    int er = -1;
+    unsigned pr = 0;
+    bool rin = false;
+    if ((int)threadIdx.x < 2 * (TX + 2) + 2 * TY) {
+        int ex, ey;
+        ring_pos(threadIdx.x, TX, TY, ex, ey);
+        er = ey * SHX + ex;
+        const int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
+        rin = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        pr = rin ? (unsigned)gy * nx + gx : pp;
+    }
+    for (int q = threadIdx.x; q < 3 * (TX + TY); q += BLK) {
+        if (q < 3 * TX) {
+            const int a = q / TX, c = q - a * TX;
+            ltab[a * SX + c] = H.tab[0][a * nx + x0 + c];
+        } else {
+            const int qq = q - 3 * TX, a = qq / TY, c = qq - a * TY;
+            ltab[3 * SX + a * SY + c] = H.tab[1][a * ny + y0 + c];
+        }
+    }
+    const unsigned plane = (unsigned)nx * ny;
+    const int g0 = min(j, 7);   // the first group: v_0 .. v_g0
+    // z of plane k at the column and halo points (clamped plane: the values
+    // outside the level are replaced by zeros when staged)
+    auto load_z = [&](int k, Cx<TZ> &zo, Cx<TZ> &zr) {
+        const unsigned kp = (unsigned)max(0, min(k, nz - 1)) * plane;
+        zo = z[off + kp + pp];
+        zr = z[off + kp + pr];
+    };
+    // the first group's basis values and phi at the column point of plane k
+    auto load_v = [&](int k, zc (&v)[8], double &ph) {
+        const unsigned kp = (unsigned)max(0, min(k, nz - 1)) * plane;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (q <= g0) v[q] = V[q * vstride + off + kp + pp];
+        ph = H.phi[kp + pp];
+    };
+    auto stage = [&](int k, const Cx<TZ> &zo, const Cx<TZ> &zr) {
+        zc *R = ring[(k + 3) % 3];
+        const bool kin = k >= 0 && k < nz;
+        if (er >= 0) R[er] = (kin && rin) ? cvt<double>(zr) : mkc(0.0, 0.0);
+        R[eo] = (kin && own) ? cvt<double>(zo) : mkc(0.0, 0.0);
+    };
+    zc acc[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) acc[q] = mkc(0.0, 0.0);
+    Cx<TZ> zo, zr;
+    load_z(z0 - 1, zo, zr);
+    stage(z0 - 1, zo, zr);
+    load_z(z0, zo, zr);
+    stage(z0, zo, zr);
+    load_z(z0 + 1, zo, zr);
+    for (int k = z0; k < z1; ++k) {
+        stage(k + 1, zo, zr);
+        // z of the plane after next, and this plane's basis values, are in
+        // flight across the barrier (values loaded a plane ahead would hold
+        // twice the registers and halve the resident workgroups)
+        if (k + 2 <= z1) load_z(k + 2, zo, zr);
+        zc vc[8];
+        double phc;
+        load_v(k, vc, phc);
+        __syncthreads();
+        if (own) {
+            const zc *Rm = ring[(k + 2) % 3], *R0 = ring[k % 3], *Rp = ring[(k + 1) % 3];
+            const zc *tz = H.tab[2];
+            zc d = ltab[SX + tx] + ltab[3 * SX + SY + ty] + tz[nz + k];
+            sub_phi(d, H, phc);
+            zc a = d * R0[eo];
+            a = cfma(ltab[tx], R0[eo - 1], a);
+            a = cfma(ltab[2 * SX + tx], R0[eo + 1], a);
+            a = cfma(ltab[3 * SX + ty], R0[eo - SHX], a);
+            a = cfma(ltab[3 * SX + 2 * SY + ty], R0[eo + SHX], a);
+            a = cfma(tz[k], Rm[eo], a);
+            a = cfma(tz[2 * nz + k], Rp[eo], a);
+            w[off + (size_t)k * plane + pp] = a;
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (q <= g0) acc[q] = cjfma(vc[q], a, acc[q]);
+            acc[8].re += cabs2(a);
+        }
+        __syncthreads();
+    }
+    block_sum_last<9>(acc, 9, sh, res);
+    if ((int)threadIdx.x <= g0) po[(size_t)threadIdx.x * NBMAX + slot] = res[threadIdx.x];
+    if (threadIdx.x == 8) po[(size_t)(j + 1) * NBMAX + slot] = res[8];
+}
+
 // Pass 0 on one 2-D tile (see launch_st0_tile): u_0 on the tile and its
 // one-point halo into shared memory (zero outside the level), then w_0 = A u_0
 // on the tile's points with <u_0, w_0>, ||u_0||^2 and (NA = 3) ||w_0||^2.  All
@@ -3335,6 +3462,32 @@ __global__ __launch_bounds__(BLK) void k_hdot(LvlK<double> H, const Cx<TZ> *__re
     if (threadIdx.x == 0) po[(j + 1) * NBMAX + c] = res[0];
 }
 
+// The later groups of 8 first-round inner products <v_{8g+q}, w> (8g+q <= j,
+// g >= 1) after k_slab_hdot: w re-read over chunks of points, one partial per
+// chunk in the partial slots of the slab blocks (as many chunks as slab
+// blocks).
+__global__ __launch_bounds__(BLK) void k_hdot_groups(const zc *__restrict__ w, const zc *__restrict__ V,
+                                                     size_t vstride, int j, unsigned N, size_t ld,
+                                                     zc *__restrict__ pout, unsigned chunk, int nb,
+                                                     const int *active)
+{
+    __shared__ zc sh[(BLK / 64) * 8];
+    __shared__ zc res[8];
+    const int rhs = blockIdx.y;
+    if (!active[rhs]) return;
+    const size_t off = rhs * ld;
+    zc *po = pout + (size_t)rhs * OVAL * NBMAX;
+    const unsigned c = chunk_id(nb);
+    const unsigned p0 = c * chunk + threadIdx.x, p1 = min(N, c * chunk + chunk);
+    for (int g = 1; 8 * g <= j; ++g) {
+        zc acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = mkc(0.0, 0.0);
+        dots8(w, V, vstride, g, j, off, p0, p1, acc);
+        store_group(acc, g, j, po, c, sh, res);
+    }
+}
+
 // Inner products <v_{8g+q}, w> (q < QN, 8g+q <= j) over a thread's tile points,
 // w in its own shared-memory slots, PB points per batch of loads.
 template <int PB, int QN>
@@ -4926,6 +5079,20 @@ void launch_hdot(const LvlK<double> &H, const Cx<TZ> *z, zc *w, const zc *V, siz
 }
 
 template <typename TZ>
+void launch_slab_hdot(const LvlK<double> &H, const Cx<TZ> *z, zc *w, const zc *V, size_t vstride, int j, size_t ld,
+                      zc *pout, const SlabGeo &sg, int nrhs, hipStream_t st, const int *active)
+{
+    const int nslab = (int)sg.npad;
+    hipLaunchKernelGGL((k_slab_hdot<TZ>), dim3(nslab, nrhs), dim3(BLK), 0, st, H, z, w, V, vstride, j, ld, pout,
+                       sg.ntx, sg.nty, sg.nzc, sg.zrun, nslab, active);
+    if (j >= 8) {
+        const unsigned chunk = (unsigned)((H.N + nslab - 1) / nslab);
+        hipLaunchKernelGGL(k_hdot_groups, dim3(nslab, nrhs), dim3(BLK), 0, st, w, V, vstride, j, H.N, ld, pout, chunk,
+                           nslab, active);
+    }
+}
+
+template <typename TZ>
 void launch_hdot_tile(const LvlK<double> &H, const Cx<TZ> *z, zc *w, const zc *V, size_t vstride, int j, size_t ld,
                       zc *pout, const TileGeo &tg, int nrhs, hipStream_t st, const int *active)
 {
@@ -5174,6 +5341,10 @@ INST_TD(double, 3)
 INST_TD(float, 2)
 INST_TD(float, 3)
 
+template void launch_slab_hdot<double>(const LvlK<double> &, const Cx<double> *, zc *, const zc *, size_t, int,
+                                       size_t, zc *, const SlabGeo &, int, hipStream_t, const int *);
+template void launch_slab_hdot<float>(const LvlK<double> &, const Cx<float> *, zc *, const zc *, size_t, int, size_t,
+                                      zc *, const SlabGeo &, int, hipStream_t, const int *);
 template void launch_hdot_tile<double>(const LvlK<double> &, const Cx<double> *, zc *, const zc *, size_t, int,
                                        size_t, zc *, const TileGeo &, int, hipStream_t, const int *);
 template void launch_hdot_tile<float>(const LvlK<double> &, const Cx<float> *, zc *, const zc *, size_t, int,

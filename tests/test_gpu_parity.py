@@ -300,6 +300,7 @@ OUTER_MODES = {
     "at_once_every_column": {"CSG_FORCE_CGS2": "1", "CSG_LAZY": "0"},
     "proj0w_step_loads": {"CSG_PROJ0W_AHEAD": "0"},    # split first projection without loads a step ahead
     "hdot_untiled": {"CSG_HDOT_TILES": "0"},           # 2-D: the chunked w = H z
+    "slabs": {"CSG_SLAB_MIN": "0"},                    # 3-D: w = H z (and the cycle) on slabs
 }
 
 
@@ -308,7 +309,8 @@ OUTER_MODES = {
 def test_fgmres_outer_orthogonalisation_modes(name, mode, monkeypatch):
     """FGMRES(48) with two RHS (columns of 1..48 basis vectors: the register,
     and every wavefront-split first projection) under each way of applying
-    the second Gram-Schmidt round, and with the chunked w = H z in 2-D:
+    the second Gram-Schmidt round, with the chunked w = H z in 2-D and the
+    slab one in 3-D:
     iterations +-1 and solution within 1e-10 of the oracle."""
     import torch
     for k, v in OUTER_MODES[mode].items():
