@@ -286,7 +286,8 @@ int helm_step_batch(csg_solve *sv, int *done);
  * each input vector read once, each output written once).  kind 0 disables it.
  * csg_profile_read waits for the last recorded event and returns the summed
  * kernel time (ms), the number of launches timed and the summed algorithmic
- * bytes.  Kinds: */
+ * bytes.  The events are timing-only (no system-scope fence), so recording
+ * them leaves the caches of the timed launches alone.  Kinds: */
 enum {
     CSG_PROF_OFF = 0,
     CSG_PROF_VCYCLE = 1,        /* one whole V-cycle (every level)            */

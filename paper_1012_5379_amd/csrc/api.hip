@@ -343,7 +343,8 @@ struct ProfScope {
         if (on) {
             st = s;
             hipEventRecord(pr->ev[2 * pr->n], s);
-            pr->bytes += bytes;
+            pr->bytes[pr->n] = bytes;
+            pr->col[pr->n] = pr->cur;
         }
     }
     ~ProfScope()
@@ -940,6 +941,7 @@ struct csg_solve {
     int j;            // columns of the current cycle whose reports the host has read
     int jq;           // columns of the current cycle queued (j <= jq <= j + LOOKAHEAD)
     bool halt;        // no RHS iterates any more in this cycle: queue no further column
+    long col0;        // profiling: number of the cycle's first column
     int rc;
     int it[CSG_MAX_RHS_HOST];
     int done[CSG_MAX_RHS_HOST], conv[CSG_MAX_RHS_HOST], act[CSG_MAX_RHS_HOST], restarts[CSG_MAX_RHS_HOST];
@@ -1055,7 +1057,11 @@ void enqueue_iters(csg_solve *sv, int j, int g)
     if (!gc || !gc->enabled || op->prof) {
         // eager: graphs disabled, or launches being timed (this HIP cannot time
         // events recorded inside a graph)
-        for (int c = j; c < j + g; ++c) iter_body<TZ, DIM>(sv, c, sv->st);
+        for (int c = j; c < j + g; ++c) {
+            if (op->prof) op->prof->cur = sv->col0 + c;
+            iter_body<TZ, DIM>(sv, c, sv->st);
+        }
+        if (op->prof) op->prof->cur = -1;
         return;
     }
     // a graph holds the columns of its group, which depend on the cycle length m
@@ -1142,12 +1148,14 @@ int solve_step(csg_solve *sv)
     case csg_solve::CYCLE:
         // queue groups of GCOLS columns (one graph each) up to LOOKAHEAD columns
         // ahead of the reports read; each RHS's iteration mask is cleared by
-        // the device when it stops.  Instrumented solves queue one column at a
-        // time, so that no skipped column is timed.
+        // the device when it stops.  Instrumented solves queue single columns
+        // as far ahead (the GPU never waits for the host, as in a plain
+        // solve); launches of columns queued after the halt are dropped from
+        // the timings.
         if (sv->jq == 0) upload_masks(sv);
         for (;;) {
             const int g = op->prof ? 1 : std::min(GCOLS, sv->m - sv->jq);
-            if (sv->halt || sv->jq >= sv->m || sv->jq + g - sv->j > (op->prof ? 1 : LOOKAHEAD)) break;
+            if (sv->halt || sv->jq >= sv->m || sv->jq + g - sv->j > LOOKAHEAD) break;
             if (mixed) { if (d3) enqueue_iters<float, 3>(sv, sv->jq, g); else enqueue_iters<float, 2>(sv, sv->jq, g); }
             else { if (d3) enqueue_iters<double, 3>(sv, sv->jq, g); else enqueue_iters<double, 2>(sv, sv->jq, g); }
             for (int c = 0; c < g; ++c) enqueue_report(sv, (sv->jq + c) % LOOKAHEAD);
@@ -1198,6 +1206,10 @@ void solve_advance(csg_solve *sv)
         }
         sv->j = sv->jq = 0;
         sv->halt = false;
+        if (op->prof) {
+            sv->col0 = op->prof->next;
+            op->prof->next += sv->m;
+        }
         sv->phase = any ? csg_solve::CYCLE : csg_solve::FINISHED;
         break;
     case csg_solve::CYCLE: {
@@ -1211,7 +1223,10 @@ void solve_advance(csg_solve *sv)
             still = true;
         }
         sv->j++;
-        if (!still) sv->halt = true;   // the columns queued behind this one are no-ops
+        if (!still) {
+            sv->halt = true;   // the columns queued behind this one are no-ops
+            if (op->prof && sv->jq > sv->j) op->prof->skipped.push_back({sv->col0 + sv->j, sv->col0 + sv->jq});
+        }
         if (sv->j == sv->jq && (sv->halt || sv->j == sv->m)) sv->phase = csg_solve::CYCLE_END;
         break;
     }
@@ -1609,8 +1624,12 @@ int csg_profile(csg_operator *op, int kind, int cap)
     pr->kind = kind;
     pr->cap = cap;
     pr->ev.resize(2 * (size_t)cap);
+    pr->bytes.assign((size_t)cap, 0.0);
+    pr->col.assign((size_t)cap, -1);
+    // timing-only events: no system-scope fence (cache write-back and
+    // invalidation) around the timed launches
     for (auto &e : pr->ev)
-        if (hipEventCreate(&e) != hipSuccess) {
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
             delete pr;
             return fail(CSG_EDEVICE, "event creation failed");
         }
@@ -1628,13 +1647,16 @@ int csg_profile_read(csg_operator *op, double *ms, long *launches, double *bytes
         Prof *pr = op->prof;
         if (hipEventSynchronize(pr->ev[2 * (pr->n - 1) + 1]) != hipSuccess) return fail(CSG_EDEVICE, "event wait");
         for (int i = 0; i < pr->n; ++i) {
+            bool skip = false;
+            for (const auto &r : pr->skipped) skip = skip || (pr->col[i] >= r.first && pr->col[i] < r.second);
+            if (skip) continue;
             float t = 0.f;
             if (hipEventElapsedTime(&t, pr->ev[2 * i], pr->ev[2 * i + 1]) != hipSuccess)
                 return fail(CSG_EDEVICE, "event elapsed time");
             tot += t;
+            by += pr->bytes[i];
+            ++n;
         }
-        n = pr->n;
-        by = pr->bytes;
     }
 
     if (ms) *ms = tot;

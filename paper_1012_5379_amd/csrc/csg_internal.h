@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "csg.h"
@@ -208,8 +209,12 @@ struct Prof {
     int kind = 0;
     int cap = 0;
     int n = 0;
-    double bytes = 0.0;
     std::vector<hipEvent_t> ev;   // 2 * cap events: start, stop
+    std::vector<double> bytes;    // per timed launch
+    std::vector<long> col;        // per timed launch: FGMRES column number (-1: outside columns)
+    long cur = -1;                // column being enqueued
+    long next = 0;                // first column number of the next cycle
+    std::vector<std::pair<long, long>> skipped;   // [first, last) columns queued after a halt
 };
 
 }  // namespace csg
