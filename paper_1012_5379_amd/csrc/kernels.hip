@@ -1401,18 +1401,21 @@ __global__ __launch_bounds__(BLK) void k_slab(LvlK<T> L, Basis<T> B, const Cx<T>
         Cx<T> w;
         Cx<T> u[NU > 0 ? NU : 1];
     };
+    // (only the threads holding a halo point load it: wavefronts 2..7 hold
+    // none and issue no halo loads)
     auto load = [&](int k, Raw &ro, Raw &rr, T &ph) {
         const unsigned kp = (unsigned)max(0, min(k, nz - 1)) * plane;
         if (J < 0) {
             ro.w = B.u[0][off + kp + po];
-            rr.w = B.u[0][off + kp + pr];
+            if (er >= 0) rr.w = B.u[0][off + kp + pr];
         } else {
             ro.w = win[off + kp + po];
-            rr.w = win[off + kp + pr];
 #pragma unroll
-            for (int q = 0; q < NU; ++q) {
-                ro.u[q] = B.u[q][off + kp + po];
-                rr.u[q] = B.u[q][off + kp + pr];
+            for (int q = 0; q < NU; ++q) ro.u[q] = B.u[q][off + kp + po];
+            if (er >= 0) {
+                rr.w = win[off + kp + pr];
+#pragma unroll
+                for (int q = 0; q < NU; ++q) rr.u[q] = B.u[q][off + kp + pr];
             }
         }
         ph = L.phi[kp + po];
@@ -1552,12 +1555,13 @@ __global__ __launch_bounds__(BLK) void k_slab_hdot(LvlK<double> H, const Cx<TZ> 
     }
     const unsigned plane = (unsigned)nx * ny;
     const int g0 = min(j, 7);   // the first group: v_0 .. v_g0
-    // z of plane k at the column and halo points (clamped plane: the values
-    // outside the level are replaced by zeros when staged)
+    // z of plane k at the column point and (threads holding one) the halo
+    // point (clamped plane: the values outside the level are replaced by zeros
+    // when staged)
     auto load_z = [&](int k, Cx<TZ> &zo, Cx<TZ> &zr) {
         const unsigned kp = (unsigned)max(0, min(k, nz - 1)) * plane;
         zo = z[off + kp + pp];
-        zr = z[off + kp + pr];
+        if (er >= 0) zr = z[off + kp + pr];
     };
     // the first group's basis values and phi at the column point of plane k
     auto load_v = [&](int k, zc (&v)[8], double &ph) {
