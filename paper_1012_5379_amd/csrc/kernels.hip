@@ -4117,14 +4117,20 @@ void launch_os_tile(const LvlK<T> &L, const Basis<T> &B, const Cx<T> *win, Cx<T>
 }
 
 // Interpolated correction and the residual that opens the post-sweep on the
-// z-marching slabs of a 3-D level (the transfer-pass analogue of k_slab): for
-// each plane every thread forms x = P ec (+ xin) at its column point and at
-// one halo point of the 32 x 16 column into the three-plane shared-memory ring
-// (zero outside the level), stores x at its own points, and from the ring
-// planes around plane k forms r = b - A x there; b and phi of the next plane
-// are loaded while a plane's residual runs.  x never goes back to memory for
-// the residual's stencil, and the values equal k_prolong then k_resid bit for
-// bit (the same formulas in the same order).
+// z-marching slabs of a 3-D level (the transfer-pass analogue of k_slab): the
+// coarse correction's window under the column (its x-y extent plus the
+// interpolation stencil) is staged into a three-plane shared-memory ring of
+// coarse planes, each loaded an iteration before it is first needed; for each
+// plane every thread forms x = P ec (+ xin) from there at its column point and
+// at one halo point of the 32 x 16 column into the three-plane ring of fine
+// planes (zero outside the level), stores x at its own points, and from the
+// ring planes around plane k forms r = b - A x there; xin of the plane after
+// next, b and phi of the next plane are loaded while a plane's residual runs.
+// x never goes back to memory for the residual's stencil, and the values
+// equal k_prolong then k_resid bit for bit (the same formulas in the same
+// order).
+constexpr int CWX = SX / 2 + 3, CWY = SY / 2 + 3;   // coarse window of a column, halo included
+static_assert(CWX * CWY <= BLK, "one coarse window point per thread");
 template <typename T>
 __global__ __launch_bounds__(BLK) void k_slab_pr(LvlK<T> F, LvlK<T> C, const Cx<T> *__restrict__ ec,
                                                  const Cx<T> *__restrict__ xin, Cx<T> *__restrict__ xout,
@@ -4133,6 +4139,7 @@ __global__ __launch_bounds__(BLK) void k_slab_pr(LvlK<T> F, LvlK<T> C, const Cx<
                                                  int nslab, const int *active)
 {
     __shared__ Cx<T> ring[3][SHX * SHY];
+    __shared__ Cx<T> cring[3][CWX * CWY];
     __shared__ Cx<T> ltab[3 * SX + 3 * SY];
     const int rhs = blockIdx.y;
     F = F.at(rhs);
@@ -4179,27 +4186,83 @@ __global__ __launch_bounds__(BLK) void k_slab_pr(LvlK<T> F, LvlK<T> C, const Cx<
     const Cx<T> *e = ec + rhs * ldc;
     const Cx<T> *xi = xin ? xin + rhs * ldf : nullptr;
     const size_t off = rhs * ldf;
-    // x at a point of plane k (as k_prolong forms it)
-    auto xat = [&](int k, int gx, int gy, unsigned pxy) -> Cx<T> {
-        Cx<T> v = prolong_pt<T, 3>(e, (unsigned)gx, (unsigned)gy, (unsigned)k, C.nx, C.ny, C.nz);
-        if (xi) v = v + xi[(size_t)k * plane + pxy];
+    // the coarse window: every coarse node the interpolation of a fine point
+    // of the column or its halo inside the level reads (paxis of the extreme
+    // fine coordinates), at most CWX x CWY of them
+    const unsigned ncx = C.nx, ncy = C.ny, ncz = C.nz;
+    const int gxa = max(x0 - 1, 0), gxb = min(x0 + TX, nx - 1);
+    const int gya = max(y0 - 1, 0), gyb = min(y0 + TY, ny - 1);
+    const unsigned cx0 = paxis((unsigned)gxa, ncx).idx[0], cx1 = paxis((unsigned)gxb, ncx).idx[1];
+    const unsigned cy0 = paxis((unsigned)gya, ncy).idx[0], cy1 = paxis((unsigned)gyb, ncy).idx[1];
+    const int cwx = (int)(cx1 - cx0) + 1, cwn = cwx * (int)(cy1 - cy0 + 1);
+    const int cq = (int)threadIdx.x;
+    const int cqy = cq / max(cwx, 1), cqx = cq - cqy * max(cwx, 1);
+    const size_t cpt = (size_t)(cy0 + cqy) * ncx + cx0 + cqx;   // this thread's window node (cq < cwn)
+    const int cslot = cqy * CWX + cqx;
+    // the last coarse plane fine plane k reads (paxis(k).idx[1])
+    auto chi = [&](int k) -> int { return (int)paxis((unsigned)max(0, min(k, nz - 1)), ncz).idx[1]; };
+    auto cload = [&](int K) -> Cx<T> {
+        return cq < cwn ? e[(size_t)K * ncx * ncy + cpt] : mkc<T>(0, 0);
+    };
+    auto cput = [&](int K, const Cx<T> &v) {
+        if (cq < cwn) cring[K % 3][cslot] = v;
+    };
+    // x at a point of plane k (as k_prolong forms it, the coarse values from
+    // the staged window)
+    auto xat = [&](int k, int gx, int gy, const Cx<T> &xa) -> Cx<T> {
+        const PAx ax = paxis((unsigned)gx, ncx), ay = paxis((unsigned)gy, ncy), az = paxis((unsigned)k, ncz);
+        Cx<T> v = mkc<T>(0, 0);
+#pragma unroll
+        for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+            for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+                    v = v + (T)(ax.w[a] * ay.w[bb] * az.w[cz]) *
+                                cring[az.idx[cz] % 3][(ay.idx[bb] - cy0) * CWX + ax.idx[a] - cx0];
+        if (xi) v = v + xa;
         return v;
     };
+    auto load_xa = [&](int k, Cx<T> &xo, Cx<T> &xr) {
+        if (!xi) return;
+        const size_t kp = (size_t)max(0, min(k, nz - 1)) * plane;
+        xo = xi[kp + po];
+        if (er >= 0) xr = xi[kp + pr];
+    };
     // plane k into ring slot k % 3 (zero outside the level); x of the run's own planes to memory
-    auto stage = [&](int k) {
+    auto stage = [&](int k, const Cx<T> &xao, const Cx<T> &xar) {
         Cx<T> *R = ring[(k + 3) % 3];
         const bool kin = k >= 0 && k < nz;
-        if (er >= 0) R[er] = (kin && rin) ? xat(k, gxr, gyr, pr) : mkc<T>(0, 0);
-        const Cx<T> xo = kin ? xat(k, gxo, gyo, po) : mkc<T>(0, 0);
+        if (er >= 0) R[er] = (kin && rin) ? xat(k, gxr, gyr, xar) : mkc<T>(0, 0);
+        const Cx<T> xo = kin ? xat(k, gxo, gyo, xao) : mkc<T>(0, 0);
         R[eo] = (kin && own) ? xo : mkc<T>(0, 0);
         if (kin && own && k >= z0 && k < z1) xout[off + (size_t)k * plane + po] = xo;
     };
-    stage(z0 - 1);
-    stage(z0);
+    // coarse planes read by the planes staged before the loop (at most three)
+    const int klo = max(z0 - 1, 0);
+    int cstaged = chi(z0 + 1);
+    for (int K = (int)paxis((unsigned)min(klo, nz - 1), ncz).idx[0]; K <= cstaged; ++K) cput(K, cload(K));
+    Cx<T> xao = mkc<T>(0, 0), xar = mkc<T>(0, 0);
+    load_xa(z0 - 1, xao, xar);
+    __syncthreads();
+    stage(z0 - 1, xao, xar);
+    load_xa(z0, xao, xar);
+    stage(z0, xao, xar);
+    load_xa(z0 + 1, xao, xar);
+    // the coarse plane the loop's first iteration stages for the one after it
+    int cnext = chi(z0 + 2);
+    Cx<T> cv = cnext > cstaged ? cload(cnext) : mkc<T>(0, 0);
     Cx<T> bc = b[off + (size_t)z0 * plane + po];
     T phc = F.phi[(size_t)z0 * plane + po];
     for (int k = z0; k < z1; ++k) {
-        stage(k + 1);
+        stage(k + 1, xao, xar);
+        if (cnext > cstaged) {
+            cput(cnext, cv);
+            cstaged = cnext;
+        }
+        load_xa(k + 2, xao, xar);
+        cnext = chi(k + 3);
+        if (cnext > cstaged) cv = cload(cnext);
         const int kn = min(k + 1, nz - 1);
         const Cx<T> bn = b[off + (size_t)kn * plane + po];
         const T phn = F.phi[(size_t)kn * plane + po];

@@ -100,3 +100,24 @@ def test_fgmres_large_grid_paths(name, prec, path, monkeypatch):
                  f"sol err {e:.2e} (floor {floor:.2e})")
             assert rr <= tol
             assert e <= max(1e-5, 10 * floor)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_slab_transfer_passes_bitwise(prec, monkeypatch):
+    """On slab levels the fused transfer passes (interpolation with the
+    residual that opens the post-sweep; the pre-sweep's closing update with
+    the restriction) give the V-cycle bit for bit the values of the chunked
+    passes they replace (the same formulas in the same order), two RHS."""
+    torch_cuda()
+    w = CASES["3d_ragged"]()
+    monkeypatch.setenv("CSG_SLAB_MIN", "0")
+    monkeypatch.setenv("CSG_TAIL_MAX", "0")
+    fused, orc = pair(w, max_rhs=2, cycle_prec=prec)
+    monkeypatch.setenv("CSG_SLAB_PR", "0")
+    monkeypatch.setenv("CSG_SLAB_DOWN", "0")
+    chunked, _ = pair(w, max_rhs=2, cycle_prec=prec)
+    b = np.stack([rvec(orc.shape(0), 470), rvec(orc.shape(0), 471)])
+    xf = host(fused.vcycle(dev(b, fused.cdtype)))
+    xc = host(chunked.vcycle(dev(b, chunked.cdtype)))
+    note(f"  prec {prec}: max |fused - chunked| {np.abs(xf - xc).max():.2e}")
+    assert np.array_equal(xf, xc)
