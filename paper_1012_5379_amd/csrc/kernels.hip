@@ -27,6 +27,19 @@ __device__ __forceinline__ unsigned chunk_id(int nb)
     return b;
 }
 
+// A scalar zero the compiler cannot see through: added to the index of a
+// block-uniform coefficient in shared memory inside a point loop, it keeps
+// the coefficient a broadcast read at its point of use instead of a value
+// held in vector registers for the whole pass (the first projection's
+// coefficients, two per basis vector, would otherwise take 4 registers each
+// per lane and lower the kernel's occupancy or spill).
+__device__ __forceinline__ int opaque_zero()
+{
+    int z;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+    return z;
+}
+
 template <int DIM>
 __device__ __forceinline__ void decomp(unsigned p, unsigned nx, unsigned ny, unsigned &i, unsigned &j, unsigned &k)
 {
@@ -4312,8 +4325,15 @@ __global__ __launch_bounds__(BLK) void k_slab_down(Cx<T> *__restrict__ x, int ac
     C = C.at(rhs);
     if (!active[rhs]) return;
     const int kb = close_sweep<T, SB>(pin + (size_t)rhs * NVAL * NBMAX, nbin, gsb + rhs, s, tiny, sh, res, ax, ar);
-    Cx<T> cx[SB], cr[SB];
-    coefs_to_T<T, SB>(kb, ax, ar, cx, cr);
+    // the update and residual coefficients in the cycle's precision, read
+    // from shared memory at their use (registers go to the loads in flight)
+    __shared__ Cx<T> scx[SB], scr[SB];
+    if ((int)threadIdx.x < SB) {
+        const int q = threadIdx.x;
+        if (q < kb) scx[q] = cvt<T>(ax[q]);
+        if (q <= kb) scr[q] = cvt<T>(ar[q]);
+    }
+    __syncthreads();
     const unsigned slot = chunk_id(nslab);
     const unsigned col = slot / nzc, zci = slot - col * nzc;
     if (col >= ntx * nty) return;   // padding block
@@ -4339,31 +4359,50 @@ __global__ __launch_bounds__(BLK) void k_slab_down(Cx<T> *__restrict__ x, int ac
     }
     const unsigned plane = (unsigned)nx * ny;
     const size_t off = rhs * ldf;
-    // r at a point of plane z; with upd, also the update of x there
-    auto rat = [&](int z, unsigned pxy, bool upd) -> Cx<T> {
-        const size_t p = off + (size_t)z * plane + pxy;
-        Cx<T> uv[SB];
+    // the values plane z's residual and update are formed from: u_0..u_kb at
+    // the column point (and x there on the run's own planes when the update
+    // accumulates) and at the halo point; loaded a plane ahead of their use
+    struct Raw {
+        Cx<T> u[SB];
+        Cx<T> x;
+    };
+    const bool upd_own = own;
+    auto load = [&](int z, Raw &o, Raw &h) {
+        const size_t zp = off + (size_t)max(0, min(z, nz - 1)) * plane;
 #pragma unroll
         for (int q = 0; q < SB; ++q)
-            if (q <= kb) uv[q] = B.u[q][p];
+            if (q <= kb) o.u[q] = B.u[q][zp + po];
+        if (accumulate && upd_own && z >= z0 && z < z1) o.x = x[zp + po];
+        if (er >= 0) {
+#pragma unroll
+            for (int q = 0; q < SB; ++q)
+                if (q <= kb) h.u[q] = B.u[q][zp + pr];
+        }
+    };
+    // r = sum_i cr_i u_i at a point
+    auto rsum = [&](const Raw &v) -> Cx<T> {
+        const int oz = opaque_zero();
         Cx<T> rr = mkc<T>(0, 0);
 #pragma unroll
         for (int q = 0; q < SB; ++q)
-            if (q <= kb) rr = cfma(cr[q], uv[q], rr);
-        if (upd) {
-            Cx<T> v = accumulate ? x[p] : mkc<T>(0, 0);
-#pragma unroll
-            for (int q = 0; q < SB; ++q)
-                if (q < kb) v = cfma(cx[q], uv[q], v);
-            x[p] = v;
-        }
+            if (q <= kb) rr = cfma(scr[q + oz], v.u[q], rr);
         return rr;
     };
-    auto stage = [&](int z) {
+    // plane z into ring slot z % 3 (zero outside the level); on the run's own
+    // planes also x (+)= sum_{i<kb} cx_i u_i at the column point
+    auto stage = [&](int z, const Raw &o, const Raw &h) {
         Cx<T> *R = ring[(z + 3) % 3];
         const bool kin = z >= 0 && z < nz;
-        if (er >= 0) R[er] = (kin && rin) ? rat(z, pr, false) : mkc<T>(0, 0);
-        const Cx<T> ro = kin ? rat(z, po, own && z >= z0 && z < z1) : mkc<T>(0, 0);
+        if (er >= 0) R[er] = (kin && rin) ? rsum(h) : mkc<T>(0, 0);
+        const Cx<T> ro = kin ? rsum(o) : mkc<T>(0, 0);
+        if (kin && upd_own && z >= z0 && z < z1) {
+            const int oz = opaque_zero();
+            Cx<T> v = accumulate ? o.x : mkc<T>(0, 0);
+#pragma unroll
+            for (int q = 0; q < SB; ++q)
+                if (q < kb) v = cfma(scx[q + oz], o.u[q], v);
+            x[off + (size_t)z * plane + po] = v;
+        }
         R[eo] = (kin && own) ? ro : mkc<T>(0, 0);
     };
     // this thread's coarse point of a plane (16 x 8 per column), if any
@@ -4373,10 +4412,16 @@ __global__ __launch_bounds__(BLK) void k_slab_down(Cx<T> *__restrict__ x, int ac
                       Ky < (int)C.ny;
     const int ec0 = (2 * Ky + 1 - y0 + 1) * SHX + (2 * Kx + 1 - x0 + 1);   // ring index of the centre
     const T scale = (T)0.125;
-    stage(z0 - 1);
-    stage(z0);
+    Raw o, h;
+    load(z0 - 1, o, h);
+    stage(z0 - 1, o, h);
+    load(z0, o, h);
+    stage(z0, o, h);
+    load(z0 + 1, o, h);
     for (int z = z0; z < z1; ++z) {
-        stage(z + 1);
+        stage(z + 1, o, h);
+        // the plane after next is in flight across the restriction
+        if (z + 2 <= z1) load(z + 2, o, h);
         __syncthreads();
         const int Kz = (z - 1) / 2;
         if ((z & 1) && cown && Kz < (int)C.nz) {
@@ -4575,19 +4620,6 @@ void launch_coarse(const Cx<T> *minvT, int n, const Cx<T> *b, Cx<T> *x, size_t l
                    const int *active, size_t mstride, unsigned rpp)
 {
     hipLaunchKernelGGL((k_coarse<T>), dim3(1, nrhs), dim3(BLK), 0, st, minvT, n, b, x, ld, mstride, rpp, active);
-}
-
-// A scalar zero the compiler cannot see through: added to the index of a
-// block-uniform coefficient in shared memory inside a point loop, it keeps
-// the coefficient a broadcast read at its point of use instead of a value
-// held in vector registers for the whole pass (the first projection's
-// coefficients, two per basis vector, would otherwise take 4 registers each
-// per lane and lower the kernel's occupancy or spill).
-__device__ __forceinline__ int opaque_zero()
-{
-    int z;
-    asm volatile("s_mov_b32 %0, 0" : "=s"(z));
-    return z;
 }
 
 // Shared start of the first-round kernels: sum the inner products of k_hdot
