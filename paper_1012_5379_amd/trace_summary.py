@@ -7,7 +7,8 @@
 
 `kernels` reads a kernel trace (rocprofv3 --kernel-trace --output-format csv)
 and prints, per kernel and grid size, the dispatch count and the average, min
-and max duration, then the pass kinds bench.py times on their own.  The 2-D
+and max duration (and over the launches that did work, see `working`), then
+the pass kinds bench.py times on their own.  The 2-D
 finest-level fused pass shares its kernel and grid size with the next level's,
 so its launches are told apart by position: every FGMRES iteration is one
 V-cycle followed by k_hdot, and the V-cycle opens and closes on the finest
@@ -91,15 +92,31 @@ def kernels(trace: str) -> None:
         g = int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"])
         by[(nm, g)].append(d)
     tot = sum(dur)
-    print(f"{'kernel':44s} {'blocks':>6s} {'n':>7s} {'avg us':>9s} {'min us':>8s} {'max us':>8s} {'total %':>8s}")
+    print(f"{'kernel':44s} {'blocks':>6s} {'n':>7s} {'avg us':>9s} {'min us':>8s} {'max us':>8s} {'total %':>8s} "
+          f"{'work n':>7s} {'work avg us':>11s}")
     for (nm, g), v in sorted(by.items(), key=lambda kv: -sum(kv[1])):
+        w = working(v)
         print(f"{nm[:44]:44s} {g:6d} {len(v):7d} {sum(v) / len(v):9.2f} {min(v):8.2f} {max(v):8.2f} "
-              f"{100 * sum(v) / tot:8.2f}")
+              f"{100 * sum(v) / tot:8.2f} {len(w):7d} {sum(w) / max(1, len(w)):11.2f}")
     blocks = [_blocks(r) for r in rows]
     for kind, idx in kind_launches(names, blocks).items():
         d = [dur[i] for i in idx]
-        print(f"\n{kind}: n {len(d)}, avg {sum(d) / len(d):.2f} us, min {min(d):.2f} us, max {max(d):.2f} us")
+        w = working(d)
+        print(f"\n{kind}: n {len(d)}, avg {sum(d) / len(d):.2f} us, min {min(d):.2f} us, max {max(d):.2f} us; "
+              f"working launches {len(w)}, avg {sum(w) / max(1, len(w)):.2f} us")
     print(f"dispatches {len(rows)}, kernel time {tot / 1e3:.2f} ms")
+
+
+def working(d):
+    """The launches that did work: a solve queues FGMRES columns ahead of the
+    convergence reports, and the columns queued after every right-hand side
+    has stopped run as no-op launches of a few microseconds (all blocks return
+    at once); bench.py drops them from its timings too.  Launches shorter than
+    a third of the median of the same kernel and grid are taken for those."""
+    if not d:
+        return []
+    m = sorted(d)[len(d) // 2]
+    return [x for x in d if x >= m / 3]
 
 
 def _blocks(r) -> int:
@@ -118,12 +135,14 @@ def kind_launches(names, blocks):
     if fused2:
         out["fused"] = fused2
         out["stencil_dots"] = [i for i, nm in enumerate(names) if nm.startswith("k_st0_tile")]
-    slab = [i for i, nm in enumerate(names) if nm.startswith("k_slab")]
+    slab = [i for i, nm in enumerate(names) if nm.startswith("k_slab<")]
     if slab:
         top = max(blocks[i] for i in slab)
         out["fused"] = [i for i in slab if blocks[i] == top and not names[i].endswith("-1>")]
         out["stencil_dots"] = [i for i in slab if blocks[i] == top and names[i].endswith("-1>")]
-    out["outer_h"] = [i for i, nm in enumerate(names) if nm.startswith("k_hdot")]
+    # w = H z: one kernel per column, or (3-D slabs, columns of more than 8
+    # vectors) k_slab_hdot followed by k_hdot_groups
+    out["outer_h"] = [i for i, nm in enumerate(names) if nm.startswith(("k_hdot", "k_slab_hdot"))]
     out["outer_cgs1"] = [i for i, nm in enumerate(names) if nm.startswith("k_proj0")]
     out["outer_proj2"] = [i for i, nm in enumerate(names) if nm.startswith("k_proj1")]
     return {k: v for k, v in out.items() if v}
@@ -155,8 +174,11 @@ def counters(fetch_csv: str, write_csv: str, copy_bytes: int) -> None:
     for (n, b), ix in sorted(agg.items(), key=lambda kv: -(tot(kv[1], "FETCH_SIZE") + tot(kv[1], "WRITE_SIZE")))[:30]:
         print(f"{n[:40]:40s} {b:7d} {len(ix):6d} {tot(ix, 'FETCH_SIZE') / len(ix) / 1e6:10.1f} "
               f"{tot(ix, 'WRITE_SIZE') / len(ix) / 1e6:10.1f}")
-    print("\nper pass kind (bench.py's names), bytes per launch:")
+    print("\nper pass kind (bench.py's names), bytes per launch that did work (see `working`):")
     for kind, ix in kind_launches(names, blocks).items():
+        tb = [per["FETCH_SIZE"][i] + per["WRITE_SIZE"][i] for i in ix]
+        m = sorted(tb)[len(tb) // 2]
+        ix = [i for i, t in zip(ix, tb) if t >= m / 3]
         fe = tot(ix, "FETCH_SIZE") / len(ix)
         wr = tot(ix, "WRITE_SIZE") / len(ix)
         print(f"launches[{kind}]: {len(ix)}")
