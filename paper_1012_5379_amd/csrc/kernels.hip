@@ -2648,13 +2648,64 @@ __global__ __launch_bounds__(BLK) void k_upd_r(Cx<T> *x, int accumulate, Cx<T> *
     __shared__ zc res[SB + 1];
     __shared__ zc ax[CSG_MAX_S], ar[CSG_MAX_S + 1];
     const int rhs = blockIdx.y;
-    if (!active[rhs]) return;
-    const int k = close_sweep<T, SB>(pin + (size_t)rhs * NVAL * NBMAX, nbin, gsb + rhs, s, tiny, sh, res, ax, ar);
-    Cx<T> cx[SB], cr[SB];
-    coefs_to_T<T, SB>(k, ax, ar, cx, cr);
-    const unsigned c = chunk_id(nb);
-    const unsigned p0 = c * chunk, p1 = min(N, p0 + chunk);
-    body_upd_r<T, SB>(x + rhs * ld, accumulate, r + rhs * ld, B, k, cx, cr, rhs * ld, p0 + threadIdx.x, p1, BLK);
+    if constexpr (SB <= 4) {
+        // as k_upd: the first batch of points (u_0..u_s and x) is loaded
+        // before the least squares, which runs while the loads are in flight
+        constexpr int PB = TILE_PB;
+        const int act = active[rhs];
+        CloseLoads<SB> cls;
+        close_begin<T, SB>(pin + (size_t)rhs * NVAL * NBMAX, nbin, gsb + rhs, s, cls);
+        const unsigned c = chunk_id(nb);
+        const unsigned p0 = c * chunk, p1 = min(N, p0 + chunk);
+        const size_t off = rhs * ld;
+        Cx<T> *xr = x + off, *rr = r + off;
+        Cx<T> u[PB][SB], xv[PB];
+        // every load unconditional (slots past s read slot s again; x read
+        // and dropped when not accumulating)
+        const Cx<T> *bu[SB];
+#pragma unroll
+        for (int q = 0; q < SB; ++q) bu[q] = B.u[min(q, s)] + off;
+        auto load = [&](unsigned p) {
+#pragma unroll
+            for (int i = 0; i < PB; ++i) {
+                const unsigned pk = min(p + i * BLK, N - 1);
+#pragma unroll
+                for (int q = 0; q < SB; ++q) u[i][q] = bu[q][pk];
+                xv[i] = xr[pk];
+            }
+        };
+        const unsigned pt = p0 + threadIdx.x;
+        load(pt);
+        if (!act) return;
+        const int k = close_end<T, SB>(cls, gsb + rhs, s, tiny, sh, res, ax, ar);
+        Cx<T> cx[SB], cr[SB];
+        coefs_to_T<T, SB>(k, ax, ar, cx, cr);
+        for (unsigned p = pt; p < p1; p += PB * BLK) {
+            if (p != pt) load(p);
+#pragma unroll
+            for (int i = 0; i < PB; ++i) {
+                Cx<T> v = accumulate ? xv[i] : mkc<T>(0, 0), rv = mkc<T>(0, 0);
+#pragma unroll
+                for (int q = 0; q < SB; ++q)
+                    if (q <= k) {
+                        rv = cfma(cr[q], u[i][q], rv);
+                        if (q < k) v = cfma(cx[q], u[i][q], v);
+                    }
+                if (p + i * BLK < p1) {
+                    xr[p + i * BLK] = v;
+                    rr[p + i * BLK] = rv;
+                }
+            }
+        }
+    } else {
+        if (!active[rhs]) return;
+        const int k = close_sweep<T, SB>(pin + (size_t)rhs * NVAL * NBMAX, nbin, gsb + rhs, s, tiny, sh, res, ax, ar);
+        Cx<T> cx[SB], cr[SB];
+        coefs_to_T<T, SB>(k, ax, ar, cx, cr);
+        const unsigned c = chunk_id(nb);
+        const unsigned p0 = c * chunk, p1 = min(N, p0 + chunk);
+        body_upd_r<T, SB>(x + rhs * ld, accumulate, r + rhs * ld, B, k, cx, cr, rhs * ld, p0 + threadIdx.x, p1, BLK);
+    }
 }
 
 template <typename T, int DIM>
