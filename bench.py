@@ -192,7 +192,7 @@ def second_workload(name, steps, tuned):
     return out
 
 
-def serving(count, streams, load, batch=4):
+def serving(count, streams, load, batch=4, graphs=False):
     """Serving stream: `count` seeded C5 requests (2-D 256^2..2048^2 and 3-D
     64^3..192^3, 1-8 point sources, complex64 cycle; requests of one size
     class queued together share one batched operator).  A closed-loop pass
@@ -211,12 +211,12 @@ def serving(count, streams, load, batch=4):
         return [request_from_workload(w, rid=i, arrival=float(a)) for i, (w, a) in enumerate(zip(base, arrivals))]
 
     # warm-up (kernels loaded, allocator primed): two small requests
-    eng = Engine(streams=streams, keep_solutions=False, cache=False, batch=batch)
+    eng = Engine(streams=streams, keep_solutions=False, cache=False, batch=batch, graphs=graphs)
     eng.run([request_from_workload(W.c5_request(10 ** 5 + i, dim=2, n=256), rid=i) for i in range(2)],
             realtime=False)
     eng.close()
 
-    eng = Engine(streams=streams, keep_solutions=False, cache=False, batch=batch)
+    eng = Engine(streams=streams, keep_solutions=False, cache=False, batch=batch, graphs=graphs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = eng.run(reqs([0.0] * count), realtime=False)
@@ -229,7 +229,7 @@ def serving(count, streams, load, batch=4):
 
     rate = load * closed["requests_per_s"]
     arr, _ = W.c5_stream(count, rate)
-    eng = Engine(streams=streams, keep_solutions=False, cache=False, batch=batch)
+    eng = Engine(streams=streams, keep_solutions=False, cache=False, batch=batch, graphs=graphs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = eng.run(reqs(arr), realtime=True)

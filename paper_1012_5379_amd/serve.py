@@ -57,8 +57,8 @@ class Request:
     def nrhs(self) -> int:
         return int(self.chi.shape[0])
 
-    def csg_params(self):
-        return B.make_params(**dict(self.params, max_rhs=self.nrhs, restart=self.restart, graphs=-1))
+    def csg_params(self, graphs: int = -1):
+        return B.make_params(**dict(self.params, max_rhs=self.nrhs, restart=self.restart, graphs=graphs))
 
     def workspace_bytes(self) -> int:
         """Device bytes the request holds while admitted: the library's
@@ -100,9 +100,12 @@ class Engine:
     """Admit by HBM budget, overlap solves on `streams` HIP streams."""
 
     def __init__(self, hbm_budget: Optional[int] = None, streams: int = 4, device: str = "cuda",
-                 keep_solutions: bool = True, cache: bool = True, batch: int = 4):
+                 keep_solutions: bool = True, cache: bool = True, batch: int = 4, graphs: bool = False):
         import torch
         self.torch = torch
+        # FGMRES iterations replayed from captured HIP graphs (capture on an
+        # operator's first solve) or launched one kernel at a time
+        self.graphs = 1 if graphs else -1
         self.device = torch.device(device)
         if hbm_budget is None:
             free, _ = torch.cuda.mem_get_info(self.device)
@@ -135,9 +138,8 @@ class Engine:
         self.queue.append(req)
 
     # -- admission -------------------------------------------------------------
-    @staticmethod
-    def _batch_params(members, R):
-        return [B.make_params(**dict(m.params, max_rhs=R, restart=m.restart, graphs=-1)) for m in members]
+    def _batch_params(self, members, R):
+        return [B.make_params(**dict(m.params, max_rhs=R, restart=m.restart, graphs=self.graphs)) for m in members]
 
     def _batch_bytes(self, members) -> int:
         R = max(m.nrhs for m in members)
@@ -154,7 +156,7 @@ class Engine:
         if cached is not None:
             ws, op, _ = cached
             return _Active([req], req.nrhs, slot, ws, op, chi, u, stream)
-        p = req.csg_params()
+        p = req.csg_params(self.graphs)
         nb = B.csg_workspace_bytes(p)   # the library's share of req.workspace_bytes()
         with torch.cuda.stream(stream):
             ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
