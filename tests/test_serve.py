@@ -21,9 +21,9 @@ def _requests(n=10):
     return reqs
 
 
-def _serve(reqs, streams, budget=None, batch=4, realtime=True):
+def _serve(reqs, streams, budget=None, batch=4, realtime=True, graphs=False):
     from paper_1012_5379_amd.serve import Engine
-    eng = Engine(hbm_budget=budget, streams=streams, batch=batch)
+    eng = Engine(hbm_budget=budget, streams=streams, batch=batch, graphs=graphs)
     done = eng.run(reqs, realtime=realtime)
     eng.close()
     return {r.rid: r for r in done}, eng
@@ -44,6 +44,19 @@ def test_alone_equals_mix():
         assert [i["iterations"] for i in a.infos] == [i["iterations"] for i in m.infos]
         assert np.array_equal(a.u, m.u)
         assert all(i["relres_true"] <= 1e-7 for i in m.infos)
+
+
+def test_graph_replay_equals_eager():
+    """Served operators replaying captured graphs (four streams, batching on)
+    give the eager engine's solutions and counts bit for bit."""
+    eager, _ = _serve(_requests(), streams=4, batch=4, realtime=False)
+    graphs, _ = _serve(_requests(), streams=4, batch=4, realtime=False, graphs=True)
+    assert set(eager) == set(graphs)
+    for rid in eager:
+        a, g = eager[rid], graphs[rid]
+        assert a.status == 0 and g.status == 0
+        assert [i["iterations"] for i in a.infos] == [i["iterations"] for i in g.infos]
+        assert np.array_equal(a.u, g.u)
 
 
 def test_served_answers_match_the_oracle():
