@@ -4939,8 +4939,10 @@ __device__ __forceinline__ void proj0w_load(zc (&v)[PU][QW + 1], unsigned pb, un
     }
 }
 
+// (four vectors per wavefront, one group per step: registers capped for two
+// workgroups per CU, which the form fits without spilling)
 template <typename TB, int QW, int PU, bool PF>
-__global__ __launch_bounds__(BLK) void k_proj0w(zc *__restrict__ w, const zc *__restrict__ V, size_t vstride, int j,
+__global__ __launch_bounds__(BLK, QW * PU <= 4 ? 4 : 2) void k_proj0w(zc *__restrict__ w, const zc *__restrict__ V, size_t vstride, int j,
                                                 unsigned N, size_t ld, FState *fsb, Report *rep, int *stop,
                                                 const zc *__restrict__ pin, int nbin, zc *__restrict__ pout,
                                                 zc *__restrict__ vout, Cx<TB> *__restrict__ bc, zc *vfix, int lazy,
@@ -5262,6 +5264,17 @@ static bool wide_proj0()
     return on;
 }
 
+// CSG_PROJ0W_GROUPS=1: steps of one group of points whatever the launch size
+// (for tests on small grids)
+static bool proj0w_one_group()
+{
+    static const bool on = [] {
+        const char *e = getenv("CSG_PROJ0W_GROUPS");
+        return e && atoi(e) == 1;
+    }();
+    return on;
+}
+
 // whether the split first projection loads a step ahead (CSG_PROJ0W_AHEAD=0:
 // loads at the top of each step, for comparisons)
 static bool proj0w_ahead()
@@ -5283,14 +5296,22 @@ void launch_proj0(zc *w, const zc *V, size_t vstride, int j, unsigned N, size_t 
     // block's wavefronts, loading each step's values while the previous step
     // finishes (without that, a block has no loads in flight across each
     // step's barrier: a fifth more time in this pass on 16 right-hand sides
-    // of 128^3, 6 % more whole-solve time on one right-hand side of 1024^2)
+    // of 128^3, 6 % more whole-solve time on one right-hand side of 1024^2).
+    // Launches of many workgroups take steps of one group of 64 points, whose
+    // registers leave room for two workgroups per CU (6 % less time in this
+    // pass on 16 right-hand sides of 128^3); with about one workgroup per CU
+    // (one right-hand side) steps of two groups keep more loads in flight.
     const bool ahead = proj0w_ahead();
+    const bool few = (long)g.nb * g.nrhs < 1024 && !proj0w_one_group();
     if (j + 1 <= 8)
         hipLaunchKernelGGL((k_proj0<TB, 8>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop, pin,
                            nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);
     else if (j + 1 <= 16)
         hipLaunchKernelGGL((k_proj0<TB, 16>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep, stop, pin,
                            nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);
+    else if (j + 1 <= 4 * (BLK / 64) && wide_proj0() && ahead && !few)
+        hipLaunchKernelGGL((k_proj0w<TB, 4, 1, true>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep,
+                           stop, pin, nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);
     else if (j + 1 <= 4 * (BLK / 64) && wide_proj0() && ahead)
         hipLaunchKernelGGL((k_proj0w<TB, 4, 2, true>), grid(g), dim3(BLK), 0, g.st, w, V, vstride, j, N, ld, fs, rep,
                            stop, pin, nbin, pout, vout, bcast, vfix, lazy, g.chunk, g.nb, active);

@@ -299,6 +299,7 @@ OUTER_MODES = {
     "lazy_every_column": {"CSG_FORCE_CGS2": "1"},
     "at_once_every_column": {"CSG_FORCE_CGS2": "1", "CSG_LAZY": "0"},
     "proj0w_step_loads": {"CSG_PROJ0W_AHEAD": "0"},    # split first projection without loads a step ahead
+    "proj0w_one_group": {"CSG_PROJ0W_GROUPS": "1"},    # its one-group steps (launches of many workgroups)
     "hdot_untiled": {"CSG_HDOT_TILES": "0"},           # 2-D: the chunked w = H z
     "slabs": {"CSG_SLAB_MIN": "0"},                    # 3-D: w = H z (and the cycle) on slabs
 }
