@@ -304,7 +304,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this solver build runs every solve on a single MI355X "
+        print("bench.py measures one GPU only: the solver runs every solve on a single MI355X "
               "(requests and right-hand sides would shard across GPUs without exchange); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
