@@ -434,6 +434,7 @@ def main():
     value = args.steps * nrhs / elapsed
     achieved = kbytes / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
     lat_ms = np.array(lat) * 1e3
+    traffic = counted_traffic(dominant, args.workload)
     out = {
         "metric": METRIC,
         "value": value,
@@ -462,7 +463,7 @@ def main():
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": counted_traffic(dominant, args.workload),
+            "traffic": traffic,
             "launches": kn,
             "avg_launch_us": kms * 1e3 / max(1, kn),
             "alg_bytes_per_launch": kbytes / max(1, kn),
@@ -470,6 +471,11 @@ def main():
                       f"timed with a HIP event pair ({elapsed_instr / args.steps * 1e3:.1f} ms per solve there)",
             "copy_ceiling": ceiling,
             "frac_of_copy_ceiling": achieved / ceiling if ceiling > 0 else None,
+            # the counted HBM bytes over the same launch time: how close the
+            # pass streams to the HBM limit, halo re-reads included
+            "traffic_GBps": (traffic / (kms * 1e-3 / max(1, kn)) / 1e9) if traffic and kms > 0 else None,
+            "traffic_frac": (traffic / (kms * 1e-3 / max(1, kn)) / 1e9 / HBM_PEAK_GBPS)
+                            if traffic and kms > 0 else None,
         },
         "copy_ceiling_GBps": ceiling,
     }
