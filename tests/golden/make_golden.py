@@ -8,11 +8,15 @@ GPU tests compare against (the oracle is too slow to run inside them):
                   and to 1e-12 (the reference answer a solve stopping at 1e-6
                   is measured against, and the distance of the 1e-6 answer
                   from it: the error floor of any solve stopping there)
+  c4_oracle.json  synth.workloads.c4(cycle_prec=0): 3-D 128^3 + 16 layers,
+                  beta = 0.4, 6 levels, FGMRES(30) to 1e-6, complex128; the
+                  first and the last of its 16 point sources (entries rhs0,
+                  rhs15), 8192 sampled entries each
 
 Each file holds the iteration counts and true residuals, the solution norm, a
 seeded sample of solution entries and the inner products of the solution with
 a few seeded random vectors.  Calls only oracle/ and synth/; run from the repo
-root:  python tests/golden/make_golden.py c2|c3
+root:  python tests/golden/make_golden.py c2|c3|c4
 """
 import json
 import os
@@ -31,9 +35,9 @@ NSAMPLE = 16384
 NPROJ = 4
 
 
-def sample_index(size, cfg_id):
+def sample_index(size, cfg_id, n=NSAMPLE):
     g = np.random.default_rng([W.SEED, cfg_id, 777])
-    return np.sort(g.choice(size, size=min(NSAMPLE, size), replace=False))
+    return np.sort(g.choice(size, size=min(n, size), replace=False))
 
 
 def probes(shape, cfg_id):
@@ -69,8 +73,22 @@ def main(name):
         w, cfg, tight = W.c3(cycle_prec=0), 3, True
         what = ("oracle FGMRES(30) solves of synth.workloads.c3(cycle_prec=0), tol 1e-6 and 1e-12, "
                 "complex128")
+    elif name == "c4":
+        w, cfg = W.c4(cycle_prec=0), 4
+        o = Oracle(Params(**w.params()), w.phi)
+        idx = sample_index(w.unknowns, cfg, 8192)
+        prb = probes(w.grid_shape, cfg)
+        out = dict(what="oracle FGMRES(30) solves of synth.workloads.c4(cycle_prec=0), right-hand sides 0 and 15, "
+                        "tol 1e-6, complex128", nsample=len(idx), sample_index=idx.tolist(),
+                   probe_items=[900 + q for q in range(NPROJ)], probe_cfg_id=cfg)
+        for r in (0, 15):
+            u, info = solve(o, w.chi[r], 1e-6, 3000)
+            out[f"rhs{r}"] = dict(info, **describe(u, idx, prb))
+        with open(os.path.join(ROOT, "tests", "golden", "c4_oracle.json"), "w") as f:
+            json.dump(out, f)
+        return
     else:
-        raise SystemExit("usage: make_golden.py c2|c3")
+        raise SystemExit("usage: make_golden.py c2|c3|c4")
     o = Oracle(Params(**w.params()), w.phi)
     idx = sample_index(w.unknowns, cfg)
     prb = probes(w.grid_shape, cfg)

@@ -144,6 +144,35 @@ def test_c3_mixed_precision_against_the_oracle():
     assert es <= max(1e-5, 3 * floor)
 
 
+def test_c4_fp64_headline_solve_matches_oracle_answer():
+    """The headline benchmark's solve as bench.py runs it: 128^3 + 16 layers,
+    all 16 point sources in one launch sequence, complex128 throughout, tuned
+    knobs.  The first and the last right-hand side: iterations within 1 of the
+    oracle's, true FP64 residual <= 1e-6 (recomputed by the oracle's H), the
+    solution within 1e-10 of the oracle's stored answer on 8192 sampled entries
+    and in its inner products with four seeded random vectors."""
+    import torch
+    from paper_1012_5379_amd import Operator
+    from oracle.oracle import Oracle, Params
+    g = _golden("c4")
+    w = W.c4(cycle_prec=0)
+    op = Operator(dict(w.params(), cycle_prec=0, max_rhs=w.nrhs, restart=w.restart), w.phi, tuned=True)
+    orc = Oracle(Params(**w.params()), w.phi)
+    u, rc, infos = op.solve(dev(w.chi, torch.complex128), tol=1e-6, restart=30, maxit=3000)
+    u = host(u)
+    assert rc == 0 and all(i["converged"] for i in infos)
+    for r in (0, 15):
+        e = g[f"rhs{r}"]
+        rr = _relres(orc, u[r], w.chi[r])
+        es, ep = _against_golden(u[r], g, e)
+        note(f"  rhs {r}: gpu its {infos[r]['iterations']} oracle {e['iterations']} relres {rr:.3e} "
+             f"sample err {es:.2e} probe err {ep:.2e}")
+        assert abs(infos[r]["iterations"] - e["iterations"]) <= 1
+        assert rr <= 1e-6
+        assert abs(np.linalg.norm(u[r]) - e["u_norm"]) <= 1e-10 * e["u_norm"]
+        assert es <= 1e-10 and ep <= 1e-10
+
+
 def test_c4_3d_sixteen_rhs_full_size():
     """128^3 + 16 layers, 16 point sources in one launch sequence, complex64
     cycle: every RHS converges (true residual by the oracle's H), and the first
