@@ -11,7 +11,8 @@ GPU tests compare against (the oracle is too slow to run inside them):
   c4_oracle.json  synth.workloads.c4(cycle_prec=0): 3-D 128^3 + 16 layers,
                   beta = 0.4, 6 levels, FGMRES(30) to 1e-6, complex128; the
                   first and the last of its 16 point sources (entries rhs0,
-                  rhs15), 8192 sampled entries each
+                  rhs15), 8192 sampled entries each, and the first again to
+                  1e-12 (tight0) with the error floor of a 1e-6 solve (floor0)
 
 Each file holds the iteration counts and true residuals, the solution norm, a
 seeded sample of solution entries and the inner products of the solution with
@@ -84,6 +85,13 @@ def main(name):
         for r in (0, 15):
             u, info = solve(o, w.chi[r], 1e-6, 3000)
             out[f"rhs{r}"] = dict(info, **describe(u, idx, prb))
+            if r == 0:
+                # the reference a complex64-cycle solve stopping at 1e-6 is
+                # measured against, and the error floor of any such solve
+                ut, it = solve(o, w.chi[0], 1e-12, 20000)
+                out["tight0"] = dict(it, **describe(ut, idx, prb))
+                out["floor0"] = float(np.linalg.norm(u - ut) / np.linalg.norm(ut))
+                print(f"  floor |u(1e-6) - u(1e-12)| / |u(1e-12)| = {out['floor0']:.3e}", flush=True)
         with open(os.path.join(ROOT, "tests", "golden", "c4_oracle.json"), "w") as f:
             json.dump(out, f)
         return

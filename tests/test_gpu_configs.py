@@ -175,8 +175,10 @@ def test_c4_fp64_headline_solve_matches_oracle_answer():
 
 def test_c4_3d_sixteen_rhs_full_size():
     """128^3 + 16 layers, 16 point sources in one launch sequence, complex64
-    cycle: every RHS converges (true residual by the oracle's H), and the first
-    two match separate single-RHS solves of the same operator."""
+    cycle: every RHS converges (true residual by the oracle's H), the first
+    one's solution lies within ten times the error floor of a 1e-6 solve (or
+    1e-5) of the oracle's 1e-12 answer, and it matches a separate single-RHS
+    solve of the same operator."""
     import torch
     w = W.c4()
     op, orc = pair(w, max_rhs=16, cycle_prec=1)
@@ -189,6 +191,11 @@ def test_c4_3d_sixteen_rhs_full_size():
         rr = _relres(orc, u[r], w.chi[r])
         note(f"  rhs {r}: relres {rr:.2e}")
         assert rr <= 1e-6
+    g = _golden("c4")
+    es, ep = _against_golden(u[0], g, g["tight0"])
+    note(f"  rhs 0 against the oracle's 1e-12 answer: sample err {es:.2e} probe err {ep:.2e} "
+         f"(floor of a 1e-6 solve {g['floor0']:.2e})")
+    assert es <= max(1e-5, 10 * g["floor0"]) and ep <= max(1e-5, 10 * g["floor0"])
     # batching does not change a RHS's result beyond rounding
     u1, rc1, inf1 = op.solve(dev(w.chi[:1], torch.complex128), tol=1e-6, restart=30, maxit=3000)
     assert rc1 == 0 and inf1[0]["iterations"] == infos[0]["iterations"]
