@@ -393,3 +393,24 @@ def test_instrumented_solve_times_every_launch():
     # s - 1 fused passes per sweep, two sweeps per V-cycle, one V-cycle per iteration
     assert n == its * 2 * (w.s - 1)
     assert ms > 0 and by > 0
+
+
+def test_instrumented_solve_with_rhs_stopping_apart():
+    """Two RHS that stop at different iterations: the columns a launch runs
+    while either RHS still iterates are timed, the columns queued after both
+    have stopped are not, and the answers equal the plain solve's."""
+    import torch
+    from paper_1012_5379_amd import binding as B
+    w = CASES["2d_wide"]()
+    chi = np.stack([w.chi[0], 1e-3 * rvec(w.chi.shape[1:], 482)])
+    op, orc = pair(w, max_rhs=2, cycle_prec=0, restart=12)
+    u0, rc0, inf0 = op.solve(dev(chi, torch.complex128), tol=1e-9, restart=12, maxit=400)
+    B.csg_profile(op.op, B.PROF_KINDS["fused"], 1 << 16)
+    u1, rc1, inf1 = op.solve(dev(chi, torch.complex128), tol=1e-9, restart=12, maxit=400)
+    ms, n, by = B.csg_profile_read(op.op)
+    B.csg_profile(op.op, 0, 0)
+    its = [i["iterations"] for i in inf1]
+    note(f"  iterations {its}, {n} timed launches")
+    assert rc0 == 0 and rc1 == 0 and [i["iterations"] for i in inf0] == its
+    assert np.array_equal(host(u0), host(u1))
+    assert n == max(its) * 2 * (w.s - 1)
